@@ -1,0 +1,212 @@
+"""Gradient oracle.  Test infrastructure.
+
+The right-hand side of the C oracle written once more with plain torch CPU
+float64 operations over an explicit list of ordered pairs, so that reverse-mode
+automatic differentiation supplies the exact vector-Jacobian product
+J^T y of the method's definition (no hand derivation).  The same formulas and
+readings as ``sph_oracle.c`` (see its header for the passages):
+
+  kernel (section 3.1.1), liquid equation of state (section 2.5.1), von Mises
+  limiter f_Y = min(Y0^2/(3 J2), 1) (section 2.6), density sum, continuity,
+  momentum with artificial viscosity (section 3.1.2, 3.1.3), standard velocity
+  gradient (section 3.1.6), Hooke's law with Jaumann terms R S - S R (section 2.4).
+
+Also the kick-drift-kick leapfrog used to drive the adjoint (the paper's own
+integrators are the predictor-corrector and RK3 of section 3.4; the leapfrog
+is the driver of the gradient workloads):
+
+  F_0 = F(x_0, U_0),   U = (v, rho, S)
+  U_{n+1/2} = U_n + dt/2 F_n          (S then limited by f_Y)
+  x_{n+1}   = x_n + dt v_{n+1/2}
+  F_{n+1}   = F(x_{n+1}, U_{n+1/2})
+  U_{n+1}   = U_{n+1/2} + dt/2 F_{n+1}  (S then limited by f_Y)
+
+Partner sets are recomputed by brute force (the C oracle) at every
+evaluation; they are index sets and carry no derivative (every term of the
+right-hand side vanishes with its first derivative at the support radius).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from . import native
+
+SIGMA3 = 8.0 / math.pi
+DT = torch.float64
+
+
+def pairs_of(pos: torch.Tensor, h: float):
+    """Ordered pairs (i target, j partner) by brute force on the detached positions."""
+    row_ptr, col = native.neighbours(pos.detach().cpu().numpy(), h)
+    counts = np.diff(row_ptr)
+    i = torch.from_numpy(np.repeat(np.arange(counts.shape[0], dtype=np.int64), counts))
+    j = torch.from_numpy(col.astype(np.int64))
+    return i, j
+
+
+def _mat(S6: torch.Tensor) -> torch.Tensor:
+    """(6, n) -> (3, 3, n) symmetric."""
+    xx, yy, zz, xy, xz, yz = S6
+    return torch.stack([torch.stack([xx, xy, xz]), torch.stack([xy, yy, yz]),
+                        torch.stack([xz, yz, zz])])
+
+
+def _six(M: torch.Tensor) -> torch.Tensor:
+    return torch.stack([M[0, 0], M[1, 1], M[2, 2], M[0, 1], M[0, 2], M[1, 2]])
+
+
+def yield_factor(S6: torch.Tensor, Y0) -> torch.Tensor:
+    """f_Y = min(Y0^2 / (3 J2), 1), J2 = S:S/2 over the nine entries (section 2.6)."""
+    J2 = 0.5 * (_mat(S6) ** 2).sum(dim=(0, 1))
+    over = 3.0 * J2 > Y0 * Y0
+    J2s = torch.where(over, J2, torch.ones_like(J2))
+    return torch.where(over, Y0 * Y0 / (3.0 * J2s), torch.ones_like(J2))
+
+
+def limit(S6: torch.Tensor, Y0) -> torch.Tensor:
+    return yield_factor(S6, Y0) * S6
+
+
+def rhs(pos, vel, rho, S6, m, par, mu=None, Y0=None, pairs=None):
+    """Right-hand side of every particle.  ``par`` = {h, rho0, c, mu, Y0, alpha,
+    beta, eps_v, rho_cut}; ``mu``/``Y0`` may be tensors (differentiable)
+    overriding par[3]/par[4].  Returns dict acc (3, n), drho, dS (6, n), rho_sum, L (3, 3, n)."""
+    h, rho0, c = float(par[0]), float(par[1]), float(par[2])
+    alpha, beta, eps_v, rho_cut = float(par[5]), float(par[6]), float(par[7]), float(par[8])
+    mu = float(par[3]) if mu is None else mu
+    Y0 = float(par[4]) if Y0 is None else Y0
+    n = rho.shape[0]
+    if pairs is None:
+        pairs = pairs_of(pos, h)
+    i, j = pairs
+
+    # prepass: pressure, limiter, stress
+    p = c * c * (rho - rho0)
+    if rho_cut > 0:
+        p = torch.where(rho / rho0 < rho_cut, torch.zeros_like(p), p)
+    f = yield_factor(S6, Y0)
+    St = _mat(f * S6)
+    eye = torch.eye(3, dtype=DT).unsqueeze(-1)
+    sig = St - p * eye
+    T = sig / (rho * rho)
+
+    # pair terms
+    rv = pos[:, i] - pos[:, j]
+    r2 = (rv * rv).sum(0)
+    r = torch.sqrt(r2)
+    q = r / h
+    inner = q < 0.5
+    u = 1.0 - q
+    W = SIGMA3 / h ** 3 * torch.where(inner, 6 * q ** 3 - 6 * q ** 2 + 1, 2 * u ** 3)
+    dW = 6 * SIGMA3 / h ** 4 * torch.where(inner, 3 * q ** 2 - 2 * q, -(u * u))
+    gW = dW / r * rv  # d W_ab / d x_a
+
+    mj = m[j]
+    rho_sum = m * (SIGMA3 / h ** 3) + torch.zeros(n, dtype=DT).index_add(0, i, mj * W)
+    V = m / rho
+    dv = vel[:, i] - vel[:, j]  # v_a - v_b
+    cont = torch.zeros(n, dtype=DT).index_add(0, i, V[j] * (dv * gW).sum(0))
+    drho = rho * cont
+    Lp = -(V[j] * dv).unsqueeze(1) * gW.unsqueeze(0)  # (3, 3, P): (v_b - v_a)^a d_b W
+    L = torch.zeros(3, 3, n, dtype=DT).index_add(2, i, Lp)
+    w = (dv * rv).sum(0)
+    nu = h * w / (r2 + eps_v * h * h)
+    Pi = torch.where(w < 0, (-alpha * c * nu + beta * nu * nu) / (0.5 * (rho[i] + rho[j])),
+                     torch.zeros_like(w))
+    B = T[:, :, i] + T[:, :, j] - Pi * eye
+    accp = mj * (B * gW.unsqueeze(0)).sum(1)
+    acc = torch.zeros(3, n, dtype=DT).index_add(1, i, accp)
+
+    # postpass: Hooke + Jaumann
+    Lt = L.transpose(0, 1)
+    ed = 0.5 * (L + Lt)
+    R = 0.5 * (L - Lt)
+    tr = ed[0, 0] + ed[1, 1] + ed[2, 2]
+    rot = torch.einsum("agn,gbn->abn", R, St) - torch.einsum("agn,gbn->abn", St, R)
+    dSm = 2.0 * mu * (ed - tr / 3.0 * eye) + rot
+    return dict(acc=acc, drho=drho, dS=_six(dSm), rho_sum=rho_sum, L=L)
+
+
+def as_tensors(w):
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64))
+    return t(w.pos), t(w.vel), t(w.rho), t(w.S), t(w.m), w.param_vector()
+
+
+def rhs_vjp(w, cot: dict, pairs=None):
+    """J^T y of one right-hand side: cotangents ``cot`` with keys acc (3, n), drho (n),
+    dS (6, n), rho_sum (n).  Returns gradients pos, vel, rho, S (6, n), mu, Y0."""
+    pos, vel, rho, S, m, par = as_tensors(w)
+    mu = torch.tensor(float(par[3]), dtype=DT, requires_grad=True)
+    Y0 = torch.tensor(float(par[4]), dtype=DT, requires_grad=True)
+    for t in (pos, vel, rho, S):
+        t.requires_grad_(True)
+    out = rhs(pos, vel, rho, S, m, par, mu=mu, Y0=Y0, pairs=pairs)
+    y = 0.0
+    for k in ("acc", "drho", "dS", "rho_sum"):
+        y = y + (out[k] * torch.from_numpy(np.asarray(cot[k], dtype=np.float64))).sum()
+    g = torch.autograd.grad(y, [pos, vel, rho, S, mu, Y0], allow_unused=True)
+    names = ["pos", "vel", "rho", "S", "mu", "Y0"]
+    return {k: (v.detach().numpy() if v is not None else None) for k, v in zip(names, g)}
+
+
+def leapfrog(pos, vel, rho, S6, m, par, steps: int, dt: float, mu=None, Y0=None):
+    """Kick-drift-kick trajectory; returns the final (pos, vel, rho, S)."""
+    Y0v = float(par[4]) if Y0 is None else Y0
+    F = rhs(pos, vel, rho, S6, m, par, mu=mu, Y0=Y0)
+    x, v, r, S = pos, vel, rho, S6
+    for _ in range(steps):
+        v = v + 0.5 * dt * F["acc"]
+        r = r + 0.5 * dt * F["drho"]
+        S = limit(S + 0.5 * dt * F["dS"], Y0v)
+        x = x + dt * v
+        F = rhs(x, v, r, S, m, par, mu=mu, Y0=Y0)
+        v = v + 0.5 * dt * F["acc"]
+        r = r + 0.5 * dt * F["drho"]
+        S = limit(S + 0.5 * dt * F["dS"], Y0v)
+    return x, v, r, S
+
+
+def leapfrog_grad(w, steps: int, dt: float, objective: str = "ke", direction=None):
+    """Gradients of a final-state objective with respect to (v0, mu, Y0).
+
+    objective 'ke': J = sum_a m_a |v_a|^2 / 2;  'px'/'py'/'pz': J = sum_a m_a v_a^k;
+    'dot': J = <direction, v_final> with ``direction`` (3, n).
+    Returns dict J, v0 (3, n), mu, Y0.
+    """
+    pos, vel, rho, S, m, par = as_tensors(w)
+    vel.requires_grad_(True)
+    mu = torch.tensor(float(par[3]), dtype=DT, requires_grad=True)
+    Y0 = torch.tensor(float(par[4]), dtype=DT, requires_grad=True)
+    _, vT, _, _ = leapfrog(pos, vel, rho, S, m, par, steps, dt, mu=mu, Y0=Y0)
+    J = objective_value(vT, m, objective, direction)
+    g = torch.autograd.grad(J, [vel, mu, Y0], allow_unused=True)
+    z = lambda t, like: (t.detach().numpy() if t is not None else np.zeros_like(like))
+    return dict(J=float(J.detach()), v0=z(g[0], w.vel), mu=float(g[1]) if g[1] is not None else 0.0,
+                Y0=float(g[2]) if g[2] is not None else 0.0)
+
+
+def objective_value(vT, m, objective: str, direction=None):
+    if objective == "ke":
+        return 0.5 * (m * (vT * vT).sum(0)).sum()
+    if objective in ("px", "py", "pz"):
+        k = "xyz".index(objective[1])
+        return (m * vT[k]).sum()
+    if objective == "dot":
+        return (torch.from_numpy(np.asarray(direction, dtype=np.float64)) * vT).sum()
+    raise ValueError(objective)
+
+
+def leapfrog_value(w, steps: int, dt: float, objective: str = "ke", direction=None,
+                   vel=None, mu=None, Y0=None) -> float:
+    """Objective of the final state without gradients (for finite differences)."""
+    pos, vel0, rho, S, m, par = as_tensors(w)
+    if vel is not None:
+        vel0 = torch.from_numpy(np.ascontiguousarray(vel, dtype=np.float64))
+    with torch.no_grad():
+        _, vT, _, _ = leapfrog(pos, vel0, rho, S, m, par, steps, dt,
+                               mu=None if mu is None else float(mu),
+                               Y0=None if Y0 is None else float(Y0))
+        return float(objective_value(vT, m, objective, direction))

@@ -1,0 +1,151 @@
+"""ctypes front end of the C oracle (``sph_oracle.c``).  Test infrastructure.
+
+Arrays are numpy float64 structure-of-arrays: pos/vel (3, n), S (6, n),
+rho/m (n,).  ``par`` is the parameter vector {h, rho0, c, mu, Y0, alpha,
+beta, eps_v, rho_cut}.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+_d = C.c_double
+_i64 = C.c_int64
+_pd = C.POINTER(C.c_double)
+_pi64 = C.POINTER(C.c_int64)
+_pi32 = C.POINTER(C.c_int32)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = C.CDLL(_build.LIB)
+        L.orc_threads.restype = C.c_int
+        L.orc_kernel.argtypes = [_d, _d, _pd, _pd]
+        L.orc_count_neighbours.argtypes = [_i64, _pd, _d, _pi64, _i64, _pi64]
+        L.orc_count_neighbours.restype = _i64
+        L.orc_fill_neighbours.argtypes = [_i64, _pd, _d, _pi64, _i64, _pi64, _pi32]
+        L.orc_ball.argtypes = [_i64, _pd, _pd, _d, _pi64, _i64]
+        L.orc_ball.restype = _i64
+        L.orc_prepass.argtypes = [_i64, _pd, _pd, _pd, _pd, _pd, _pd]
+        L.orc_rhs.argtypes = [_i64, _pd, _pd, _pd, _pd, _pd, _pd, _pi64, _i64, _pi64, _pi32,
+                              _pd, _pd, _pd, _pd, _pd]
+        _lib = L
+    return _lib
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_pd)
+
+
+def _i64a(a):
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    return a, a.ctypes.data_as(_pi64)
+
+
+def threads() -> int:
+    """OpenMP threads the oracle uses (OMP_NUM_THREADS or the core count)."""
+    return int(lib().orc_threads())
+
+
+def kernel(r: float, h: float):
+    """(W, dW/dr) of the cubic B-spline with support radius h."""
+    W, dW = C.c_double(), C.c_double()
+    lib().orc_kernel(float(r), float(h), C.byref(W), C.byref(dW))
+    return W.value, dW.value
+
+
+def neighbours(pos, h: float, targets=None):
+    """Brute-force partner sets: (row_ptr int64 [nt+1], col int32 [nnz]), each row ascending."""
+    pos, ppos = _f64(pos)
+    n = pos.shape[1]
+    if targets is None:
+        nt, ptg, tg = n, None, None
+    else:
+        tg, ptg = _i64a(targets)
+        nt = tg.shape[0]
+    counts = np.zeros(nt, dtype=np.int64)
+    lib().orc_count_neighbours(n, ppos, float(h), ptg, nt, counts.ctypes.data_as(_pi64))
+    row_ptr = np.zeros(nt + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    col = np.zeros(int(row_ptr[-1]), dtype=np.int32)
+    lib().orc_fill_neighbours(n, ppos, float(h), ptg, nt, row_ptr.ctypes.data_as(_pi64),
+                              col.ctypes.data_as(_pi32))
+    return row_ptr, col
+
+
+def ball(pos, centre, radius: float) -> np.ndarray:
+    """Ascending indices of particles strictly within ``radius`` of ``centre``."""
+    pos, ppos = _f64(pos)
+    n = pos.shape[1]
+    c, pc = _f64(np.asarray(centre, dtype=np.float64).reshape(3))
+    cnt = lib().orc_ball(n, ppos, pc, float(radius), None, 0)
+    out = np.zeros(max(cnt, 1), dtype=np.int64)
+    lib().orc_ball(n, ppos, pc, float(radius), out.ctypes.data_as(_pi64), cnt)
+    return out[:cnt]
+
+
+def prepass(rho, S, par):
+    rho, prho = _f64(rho)
+    S, pS = _f64(S)
+    par, ppar = _f64(par)
+    n = rho.shape[0]
+    p = np.zeros(n)
+    f = np.zeros(n)
+    sig = np.zeros((6, n))
+    lib().orc_prepass(n, prho, pS, ppar, p.ctypes.data_as(_pd), f.ctypes.data_as(_pd),
+                      sig.ctypes.data_as(_pd))
+    return dict(p=p, fy=f, sigma=sig)
+
+
+def rhs(pos, vel, rho, S, m, par, targets=None, csr=None, want_L: bool = True):
+    """Right-hand side for ``targets`` (all particles when None).
+
+    ``csr`` = (row_ptr, col) partner lists of the targets; computed by brute
+    force when omitted.  Returns dict acc (3, nt), drho (nt), dS (6, nt),
+    rho_sum (nt) and L (9, nt).
+    """
+    pos, ppos = _f64(pos)
+    vel, pvel = _f64(vel)
+    rho, prho = _f64(rho)
+    S, pS = _f64(S)
+    m, pm = _f64(m)
+    par, ppar = _f64(par)
+    n = rho.shape[0]
+    if csr is None:
+        csr = neighbours(pos, par[0], targets)
+    row_ptr, col = csr
+    row_ptr, prow = _i64a(row_ptr)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    if targets is None:
+        nt, ptg = n, None
+    else:
+        tg, ptg = _i64a(targets)
+        nt = tg.shape[0]
+    assert row_ptr.shape[0] == nt + 1
+    acc = np.zeros((3, nt))
+    drho = np.zeros(nt)
+    dS = np.zeros((6, nt))
+    rs = np.zeros(nt)
+    L = np.zeros((9, nt)) if want_L else None
+    lib().orc_rhs(n, ppos, pvel, prho, pS, pm, ppar, ptg, nt, prow, col.ctypes.data_as(_pi32),
+                  acc.ctypes.data_as(_pd), drho.ctypes.data_as(_pd), dS.ctypes.data_as(_pd),
+                  rs.ctypes.data_as(_pd), L.ctypes.data_as(_pd) if want_L else None)
+    out = dict(acc=acc, drho=drho, dS=dS, rho_sum=rs)
+    if want_L:
+        out["L"] = L
+    return out
+
+
+def rhs_workload(w, targets=None, csr=None, want_L: bool = True):
+    """``rhs`` on a ``workloads.Workload``."""
+    return rhs(w.pos, w.vel, w.rho, w.S, w.m, w.param_vector(), targets, csr, want_L)

@@ -1,0 +1,379 @@
+/*
+ * Plain FP64 CPU oracle for the SPH solid-body right-hand side of
+ * Schaefer et al. (2016), "A smooth particle hydrodynamics code to model
+ * collisions between solid, self-gravitating objects" (arXiv:1604.03290).
+ *
+ * TEST INFRASTRUCTURE.  Only the test-suite, the package smoke check and the
+ * CPU-baseline leg of the benchmark load this library.  It shares no source,
+ * header, table or constant with the HIP library, and the HIP library never
+ * calls it.
+ *
+ * Every quantity is evaluated as the paper writes it, in double precision,
+ * one target at a time, summing over partners in ascending index order; no
+ * blocking, fusion or reordering.  Build with -ffp-contract=off so that every
+ * operation is rounded on its own (no fused multiply-add).
+ *
+ *   partners      section 3.5.2 (neighbour search): b != a, distance below h
+ *   kernel        section 3.1.1 (kernel function): cubic B-spline, support h, D = 3
+ *   pressure      section 2.5.1 (liquid equation of state), optional cut-off
+ *   limiter       section 2.6 (plastic material equations), von Mises f_Y
+ *   density sum   eq. (density_by_kernel_sum), section 3.1.2
+ *   continuity    eq. (continuity_equation_sph), section 3.1.2
+ *   momentum      eqs. (accel) and (accel_artvisc), artificial viscosity (section 3.1.3)
+ *   gradient      section 3.1.6, standard SPH velocity derivative (uncorrected)
+ *   stress rate   eqs. (stresstensor_evolution), (strain_rate_tensor), (rotation_terms),
+ *                 section 2.4
+ *
+ * Readings of ambiguous passages (each is also listed in the design notes):
+ *   - h is the kernel's support radius, as in the kernel definition; the same
+ *     h enters nu_ab (averaged smoothing length, constant h) and eps_v h^2.
+ *   - the gradient in the momentum equation is taken with respect to x_a, and
+ *     the artificial viscosity enters the bracket as -Pi*_ab (an additional
+ *     pressure), so that pressure and viscosity both repel.
+ *   - the Jaumann rotation terms are R S - S R with
+ *     R = (dv^a/dx^b - dv^b/dx^a)/2, which rotates a stress carried by a
+ *     rigidly spinning body with it.
+ *   - f_Y = min(Y0^2 / (3 J2), 1) applied to the input S; the rotation terms
+ *     use the limited stress.
+ *   - mean sound speed: the linear equation of state has one sound speed c.
+ *   - the density sum includes the particle's own term m_a W(0).
+ *
+ * Layout: structure of arrays.  pos and vel are (3, n) row-major (x row, y row,
+ * z row); S is (6, n) in the order xx, yy, zz, xy, xz, yz; outputs follow the
+ * same layout with the target count nt in place of n; L is (9, nt) row-major
+ * over (alpha, beta) with L^{alpha beta} = dv^alpha / dx^beta.
+ * par = {h, rho0, c, mu, Y0, alpha, beta, eps_v, rho_cut}.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { P_H, P_RHO0, P_C, P_MU, P_Y0, P_ALPHA, P_BETA, P_EPSV, P_RHOCUT };
+
+static const double PI_ = 3.14159265358979323846;
+
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ---------------------------------------------------------------- kernel --
+ * Cubic B-spline (section 3.1.1, kernel function), D = 3, s = 8/pi:
+ *   W  = s/h^3 (6q^3 - 6q^2 + 1)       0 <= q < 1/2
+ *      = s/h^3  2 (1 - q)^3            1/2 <= q <= 1
+ *      = 0                             q > 1
+ *   dW/dr = 6 s / h^4 (3q^2 - 2q)      0 <= q < 1/2
+ *         = 6 s / h^4 (-(1 - q)^2)     1/2 <= q <= 1
+ *         = 0                          q > 1,      q = r / h.           */
+void orc_kernel(double r, double h, double *W, double *dWdr)
+{
+    const double s = 8.0 / PI_;
+    const double q = r / h;
+    const double h3 = h * h * h;
+    if (q < 0.5) {
+        *W = s / h3 * (6.0 * q * q * q - 6.0 * q * q + 1.0);
+        *dWdr = 6.0 * s / (h3 * h) * (3.0 * q * q - 2.0 * q);
+    } else if (q <= 1.0) {
+        const double u = 1.0 - q;
+        *W = s / h3 * 2.0 * u * u * u;
+        *dWdr = 6.0 * s / (h3 * h) * (-(u * u));
+    } else {
+        *W = 0.0;
+        *dWdr = 0.0;
+    }
+}
+
+/* ------------------------------------------------------------ partners --
+ * Section 3.5.2 (neighbour search): b is an interaction partner of a when b != a
+ * and their distance is smaller than h.  The squared distance is formed as
+ * ((dx*dx + dy*dy) + dz*dz) with dx = x_b - x_a, each operation rounded, and
+ * compared strictly with h*h.                                             */
+static int is_partner(const double *x, const double *y, const double *z,
+                      int64_t a, int64_t b, double h2)
+{
+    if (a == b)
+        return 0;
+    const double dx = x[b] - x[a];
+    const double dy = y[b] - y[a];
+    const double dz = z[b] - z[a];
+    const double d2 = dx * dx + dy * dy + dz * dz;
+    return d2 < h2;
+}
+
+/* counts[t] = number of partners of particle targets[t] (all particles when
+ * targets == NULL); returns the total.  Brute force over all n.            */
+int64_t orc_count_neighbours(int64_t n, const double *pos, double h,
+                             const int64_t *targets, int64_t nt, int64_t *counts)
+{
+    const double *x = pos, *y = pos + n, *z = pos + 2 * n;
+    const double h2 = h * h;
+    if (!targets)
+        nt = n;
+    int64_t total = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : total)
+    for (int64_t t = 0; t < nt; ++t) {
+        const int64_t a = targets ? targets[t] : t;
+        int64_t c = 0;
+        for (int64_t b = 0; b < n; ++b)
+            c += is_partner(x, y, z, a, b, h2);
+        counts[t] = c;
+        total += c;
+    }
+    return total;
+}
+
+/* Partner indices of each target in ascending order into col[row_ptr[t] ..]. */
+void orc_fill_neighbours(int64_t n, const double *pos, double h,
+                         const int64_t *targets, int64_t nt,
+                         const int64_t *row_ptr, int32_t *col)
+{
+    const double *x = pos, *y = pos + n, *z = pos + 2 * n;
+    const double h2 = h * h;
+    if (!targets)
+        nt = n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < nt; ++t) {
+        const int64_t a = targets ? targets[t] : t;
+        int64_t k = row_ptr[t];
+        for (int64_t b = 0; b < n; ++b)
+            if (is_partner(x, y, z, a, b, h2))
+                col[k++] = (int32_t)b;
+    }
+}
+
+/* Indices (ascending) of all particles whose squared distance to centre is
+ * below radius^2.  Returns the count; writes at most cap indices.          */
+int64_t orc_ball(int64_t n, const double *pos, const double *centre, double radius,
+                 int64_t *out, int64_t cap)
+{
+    const double *x = pos, *y = pos + n, *z = pos + 2 * n;
+    const double r2 = radius * radius;
+    int64_t k = 0;
+    for (int64_t b = 0; b < n; ++b) {
+        const double dx = x[b] - centre[0];
+        const double dy = y[b] - centre[1];
+        const double dz = z[b] - centre[2];
+        if (dx * dx + dy * dy + dz * dz < r2) {
+            if (k < cap)
+                out[k] = b;
+            ++k;
+        }
+    }
+    return k;
+}
+
+/* ------------------------------------------------------------- prepass --
+ * Per particle:
+ *   p      = c^2 (rho - rho0), set to 0 when rho_cut > 0 and rho/rho0 < rho_cut
+ *            (section 2.5.1, liquid equation of state and its tension cut-off)
+ *   J2     = S^{ab} S^{ab} / 2 over all nine entries (section 2.6)
+ *   f_Y    = min(Y0^2 / (3 J2), 1)                 (section 2.6)
+ *   sigma  = -p delta + f_Y S                      (section 2.2)
+ * Outputs p (n), fy (n), sigma (6, n).                                     */
+static void to_matrix(const double *s6, int64_t n, int64_t i, double M[3][3])
+{
+    M[0][0] = s6[0 * n + i];
+    M[1][1] = s6[1 * n + i];
+    M[2][2] = s6[2 * n + i];
+    M[0][1] = M[1][0] = s6[3 * n + i];
+    M[0][2] = M[2][0] = s6[4 * n + i];
+    M[1][2] = M[2][1] = s6[5 * n + i];
+}
+
+static void one_prepass(int64_t n, int64_t i, const double *rho, const double *S,
+                        const double *par, double *p_out, double *f_out, double sig[3][3])
+{
+    const double c = par[P_C], rho0 = par[P_RHO0], Y0 = par[P_Y0];
+    double p = c * c * (rho[i] - rho0);
+    if (par[P_RHOCUT] > 0.0 && rho[i] / rho0 < par[P_RHOCUT])
+        p = 0.0;
+    double Sm[3][3];
+    to_matrix(S, n, i, Sm);
+    double J2 = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            J2 += Sm[a][b] * Sm[a][b];
+    J2 *= 0.5;
+    double f = 1.0;
+    if (3.0 * J2 > Y0 * Y0)
+        f = Y0 * Y0 / (3.0 * J2);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            sig[a][b] = f * Sm[a][b] - (a == b ? p : 0.0);
+    *p_out = p;
+    *f_out = f;
+}
+
+void orc_prepass(int64_t n, const double *rho, const double *S, const double *par,
+                 double *p, double *fy, double *sigma)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double sig[3][3];
+        one_prepass(n, i, rho, S, par, &p[i], &fy[i], sig);
+        sigma[0 * n + i] = sig[0][0];
+        sigma[1 * n + i] = sig[1][1];
+        sigma[2 * n + i] = sig[2][2];
+        sigma[3 * n + i] = sig[0][1];
+        sigma[4 * n + i] = sig[0][2];
+        sigma[5 * n + i] = sig[1][2];
+    }
+}
+
+/* ----------------------------------------------------------------- RHS --
+ * For each target a = targets[t] (t = 0..nt-1; all particles when targets is
+ * NULL) over its partners b = col[row_ptr[t] .. row_ptr[t+1]) in the given
+ * (ascending) order.  With r_ab = x_a - x_b, r = |r_ab| and
+ * grad_a W_ab = (dW/dr)(r) r_ab / r (zero when r = 0):
+ *
+ *   rho_sum_a = m_a W(0) + sum_b m_b W_ab                      (density sum)
+ *   drho_a    = rho_a sum_b (m_b/rho_b) (v_a - v_b) . grad_a W_ab   (continuity)
+ *   L_a^{ab}  = sum_b (m_b/rho_b) (v_b - v_a)^alpha d W_ab / d x_a^beta
+ *   w_ab      = (v_a - v_b) . (x_a - x_b)
+ *   nu_ab     = h w_ab / (|r_ab|^2 + eps_v h^2)
+ *   Pi*_ab    = (-alpha c nu_ab + beta nu_ab^2) / ((rho_a + rho_b)/2) if w_ab < 0, else 0
+ *   a_a^alpha = sum_b m_b [sigma_a/rho_a^2 + sigma_b/rho_b^2 - Pi*_ab I]^{alpha beta}
+ *                    d W_ab / d x_a^beta
+ *   edot = (L + L^T)/2,  R = (L - L^T)/2,  S~ = f_Y S
+ *   dS_a = 2 mu (edot - tr(edot) I / 3) + R S~ - S~ R
+ *
+ * Outputs (per target): acc (3, nt), drho (nt), dS (6, nt), rho_sum (nt),
+ * and L (9, nt) when L != NULL.                                           */
+void orc_rhs(int64_t n, const double *pos, const double *vel, const double *rho,
+             const double *S, const double *m, const double *par,
+             const int64_t *targets, int64_t nt, const int64_t *row_ptr, const int32_t *col,
+             double *acc, double *drho, double *dS, double *rho_sum, double *Lout)
+{
+    const double h = par[P_H], c = par[P_C], mu = par[P_MU];
+    const double alpha = par[P_ALPHA], beta = par[P_BETA], eps_v = par[P_EPSV];
+    const double *x = pos, *y = pos + n, *z = pos + 2 * n;
+    const double *vx = vel, *vy = vel + n, *vz = vel + 2 * n;
+    if (!targets)
+        nt = n;
+
+    /* per-particle stress (prepass) for every particle */
+    double *p = (double *)malloc(sizeof(double) * (size_t)n);
+    double *fy = (double *)malloc(sizeof(double) * (size_t)n);
+    double *sg = (double *)malloc(sizeof(double) * 6 * (size_t)n);
+    orc_prepass(n, rho, S, par, p, fy, sg);
+
+    double W0, dW0;
+    orc_kernel(0.0, h, &W0, &dW0);
+
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < nt; ++t) {
+        const int64_t a = targets ? targets[t] : t;
+        const double xa[3] = {x[a], y[a], z[a]};
+        const double va[3] = {vx[a], vy[a], vz[a]};
+        const double ra = rho[a];
+        double siga[3][3];
+        to_matrix(sg, n, a, siga);
+
+        double rs = m[a] * W0;
+        double cont = 0.0;
+        double ac[3] = {0.0, 0.0, 0.0};
+        double L[3][3] = {{0.0}};
+
+        for (int64_t k = row_ptr[t]; k < row_ptr[t + 1]; ++k) {
+            const int64_t b = col[k];
+            const double xb[3] = {x[b], y[b], z[b]};
+            const double vb[3] = {vx[b], vy[b], vz[b]};
+            const double rb = rho[b];
+            double sigb[3][3];
+            to_matrix(sg, n, b, sigb);
+
+            double rv[3], r2 = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                rv[d] = xa[d] - xb[d];
+                r2 += rv[d] * rv[d];
+            }
+            const double r = sqrt(r2);
+            double W, dW;
+            orc_kernel(r, h, &W, &dW);
+            double gW[3] = {0.0, 0.0, 0.0};
+            if (r > 0.0)
+                for (int d = 0; d < 3; ++d)
+                    gW[d] = dW * rv[d] / r;
+
+            /* density sum */
+            rs += m[b] * W;
+
+            /* continuity and velocity gradient */
+            const double Vb = m[b] / rb;
+            for (int al = 0; al < 3; ++al)
+                cont += Vb * (va[al] - vb[al]) * gW[al];
+            for (int al = 0; al < 3; ++al)
+                for (int be = 0; be < 3; ++be)
+                    L[al][be] += Vb * (vb[al] - va[al]) * gW[be];
+
+            /* artificial viscosity */
+            double wab = 0.0;
+            for (int d = 0; d < 3; ++d)
+                wab += (va[d] - vb[d]) * rv[d];
+            double Pi = 0.0;
+            if (wab < 0.0) {
+                const double nu = h * wab / (r2 + eps_v * h * h);
+                Pi = (-alpha * c * nu + beta * nu * nu) / (0.5 * (ra + rb));
+            }
+
+            /* momentum */
+            for (int al = 0; al < 3; ++al) {
+                double s = 0.0;
+                for (int be = 0; be < 3; ++be) {
+                    const double B = siga[al][be] / (ra * ra) + sigb[al][be] / (rb * rb)
+                                     - (al == be ? Pi : 0.0);
+                    s += B * gW[be];
+                }
+                ac[al] += m[b] * s;
+            }
+        }
+
+        /* stress rate: Hooke term plus Jaumann rotation terms on the limited S */
+        double St[3][3];
+        to_matrix(S, n, a, St);
+        for (int al = 0; al < 3; ++al)
+            for (int be = 0; be < 3; ++be)
+                St[al][be] *= fy[a];
+        double ed[3][3], R[3][3];
+        for (int al = 0; al < 3; ++al)
+            for (int be = 0; be < 3; ++be) {
+                ed[al][be] = 0.5 * (L[al][be] + L[be][al]);
+                R[al][be] = 0.5 * (L[al][be] - L[be][al]);
+            }
+        const double tr = ed[0][0] + ed[1][1] + ed[2][2];
+        double dSm[3][3];
+        for (int al = 0; al < 3; ++al)
+            for (int be = 0; be < 3; ++be) {
+                double rot = 0.0;
+                for (int g = 0; g < 3; ++g)
+                    rot += R[al][g] * St[g][be] - St[al][g] * R[g][be];
+                dSm[al][be] = 2.0 * mu * (ed[al][be] - (al == be ? tr / 3.0 : 0.0)) + rot;
+            }
+
+        for (int d = 0; d < 3; ++d)
+            acc[d * nt + t] = ac[d];
+        drho[t] = ra * cont;
+        dS[0 * nt + t] = dSm[0][0];
+        dS[1 * nt + t] = dSm[1][1];
+        dS[2 * nt + t] = dSm[2][2];
+        dS[3 * nt + t] = dSm[0][1];
+        dS[4 * nt + t] = dSm[0][2];
+        dS[5 * nt + t] = dSm[1][2];
+        rho_sum[t] = rs;
+        if (Lout)
+            for (int al = 0; al < 3; ++al)
+                for (int be = 0; be < 3; ++be)
+                    Lout[(al * 3 + be) * nt + t] = L[al][be];
+    }
+    free(p);
+    free(fy);
+    free(sg);
+}

@@ -1,0 +1,111 @@
+"""Pins of the gradient oracle (reverse-mode AD of the torch transcription).
+
+  * the torch right-hand side equals the C oracle (two independent codings)
+  * one right-hand side: <J^T y, u> equals central finite differences of the
+    *C* oracle along random directions of every input (positions, velocities,
+    density, stress) and of mu and Y0
+  * leapfrog objectives: finite differences in mu, Y0 and v0 directions
+  * closed forms: final momentum = initial momentum (pairwise antisymmetric
+    forces) so d P / d v0_a = m_a I and d P / d(mu, Y0) = 0; with Y0 beyond any
+    stress the limiter never acts and d KE / d Y0 = 0 exactly
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import autodiff as AD
+from oracle import native
+
+
+def small(seed=11, n_side=6, **over):
+    w = W.cube(n_side, 0.1, seed=seed, **over)
+    rng = np.random.default_rng(seed + 1)
+    w.m = w.m * rng.uniform(0.7, 1.3, size=w.n)
+    return w
+
+
+def test_torch_transcription_matches_c_oracle():
+    w = small(alpha=1.0, beta=1.0)
+    ref = native.rhs_workload(w)
+    out = AD.rhs(*AD.as_tensors(w))
+    for k in ("acc", "drho", "dS", "rho_sum"):
+        a, b = ref[k], out[k].numpy()
+        assert np.abs(a - b).max() <= 1e-14 * np.abs(a).max(), k
+    assert np.abs(ref["L"] - out["L"].reshape(9, -1).numpy()).max() <= 1e-14 * np.abs(ref["L"]).max()
+
+
+def _objective(w, y, **kw):
+    o = native.rhs_workload(w, want_L=False)
+    return sum(float((o[k] * y[k]).sum()) for k in y)
+
+
+@pytest.mark.parametrize("which", ["pos", "vel", "rho", "S", "mu", "Y0"])
+def test_rhs_vjp_matches_finite_differences(which):
+    w = small(alpha=1.0, beta=1.0)
+    ref = native.rhs_workload(w, want_L=False)
+    rng = np.random.default_rng(5)
+    y = {k: rng.normal(size=ref[k].shape) / np.abs(ref[k]).max() for k in ref}
+    g = AD.rhs_vjp(w, y)
+    pv = w.param_vector()
+    scale = dict(pos=w.dx, vel=0.01 * 5000, rho=2700.0 * 0.01, S=6.75e7, mu=pv[3], Y0=pv[4])[which]
+    if which in ("mu", "Y0"):
+        u = 1.0
+        ad = g[which] * u
+    else:
+        u = rng.normal(size=getattr(w, which).shape)
+        ad = float((g[which] * u).sum())
+    eps = 1e-6 * scale
+    vals = []
+    for sgn in (+1, -1):
+        w2 = w.copy()
+        if which == "mu":
+            w2.params["mu"] = pv[3] + sgn * eps
+        elif which == "Y0":
+            w2.params["Y0"] = pv[4] + sgn * eps
+        else:
+            setattr(w2, which, getattr(w, which) + sgn * eps * u)
+        vals.append(_objective(w2, y))
+    fd = (vals[0] - vals[1]) / (2 * eps)
+    assert abs(fd - ad) <= 2e-6 * max(abs(ad), 1e-300) + 1e-9, (fd, ad)
+
+
+def test_leapfrog_gradients_match_finite_differences():
+    w = small(seed=21, n_side=5)
+    steps, dt = 4, 0.2 * w.dx / 5000.0
+    g = AD.leapfrog_grad(w, steps, dt, "ke")
+    pv = w.param_vector()
+    for name, idx in (("mu", 3), ("Y0", 4)):
+        e = 1e-6 * pv[idx]
+        kw = lambda s: {name: pv[idx] + s * e}
+        fd = (AD.leapfrog_value(w, steps, dt, **kw(+1)) - AD.leapfrog_value(w, steps, dt, **kw(-1))) / (2 * e)
+        assert abs(fd - g[name]) <= 1e-5 * abs(g[name]), (name, fd, g[name])
+    d = np.random.default_rng(3).normal(size=w.vel.shape)
+    e = 1e-6 * 50.0
+    fd = (AD.leapfrog_value(w, steps, dt, vel=w.vel + e * d)
+          - AD.leapfrog_value(w, steps, dt, vel=w.vel - e * d)) / (2 * e)
+    ad = float((g["v0"] * d).sum())
+    assert abs(fd - ad) <= 1e-6 * abs(ad)
+
+
+@pytest.mark.parametrize("axis", ["px", "py", "pz"])
+def test_momentum_objective_closed_form(axis):
+    w = small(seed=31, n_side=5)
+    steps, dt = 4, 0.2 * w.dx / 5000.0
+    g = AD.leapfrog_grad(w, steps, dt, axis)
+    k = "xyz".index(axis[1])
+    expect = np.zeros_like(w.vel)
+    expect[k] = w.m
+    assert np.abs(g["v0"] - expect).max() <= 1e-10 * w.m.max()
+    gk = AD.leapfrog_grad(w, steps, dt, "ke")
+    # d P / d mu vanishes: compare with the size of the same derivative of KE / |v|
+    vs = np.abs(w.vel).max()
+    assert abs(g["mu"]) * vs <= 1e-8 * abs(gk["mu"])
+    assert abs(g["Y0"]) * vs <= 1e-8 * abs(gk["Y0"])
+
+
+def test_unlimited_yield_stress_has_zero_gradient():
+    w = small(seed=41, n_side=5, Y0=1e30)
+    g = AD.leapfrog_grad(w, 3, 0.2 * w.dx / 5000.0, "ke")
+    assert g["Y0"] == 0.0
+    assert g["mu"] != 0.0
