@@ -1,0 +1,266 @@
+/*
+ * sph.h - C ABI of libsph, the MI355X (gfx950) implementation of the SPH
+ * solid-body right-hand side of Schaefer et al. (2016), "A smooth particle
+ * hydrodynamics code to model collisions between solid, self-gravitating
+ * objects" (arXiv:1604.03290).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every array pointer is a DEVICE pointer owned by the caller (for example
+ *    the data pointer of a contiguous torch tensor).  The library allocates no
+ *    device memory and keeps no state between calls; scratch space is passed in
+ *    as a caller-owned workspace whose size sph_workspace_bytes() returns.
+ *  - Particle data are structure-of-arrays in double precision, one array per
+ *    component, as in the paper's implementation section (section 3.5):
+ *    positions x, y, z; velocities vx, vy, vz; density rho; mass m; deviatoric
+ *    stress S in six arrays (xx, yy, zz, xy, xz, yz; S is symmetric).  The index
+ *    of a particle in these arrays is its "user index".
+ *  - Work is enqueued on the caller's HIP stream (a hipStream_t passed as
+ *    void*, NULL = the null stream) and is asynchronous unless stated.  The
+ *    int return value is the status of the host-side validation and of the
+ *    launches: SPH_OK or a negative sph_status code.  sph_last_error() gives a
+ *    message for the last failure on the calling thread.
+ *  - Conditions that only the device can see (non-finite input, a particle that
+ *    moved further than the grid's skin allows, non-positive density) raise a
+ *    flag inside the workspace; sph_workspace_status() synchronises the stream
+ *    and returns it.  Each entry point clears the flag of the workspace it is
+ *    given when it starts.
+ *  - h is the paper's smoothing length: the support radius of the cubic
+ *    B-spline (section 3.1.1).  Particles a != b interact when their squared
+ *    distance, formed as ((dx*dx + dy*dy) + dz*dz) with dx = x_b - x_a and every
+ *    operation rounded to double, is strictly below h*h (section 3.5.2).
+ */
+#ifndef SPH_MI355X_H
+#define SPH_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum sph_status {
+    SPH_OK = 0,
+    SPH_ERR_INVALID_ARG = -1,   /* null pointer, n <= 0, h <= 0, non-finite parameter, ... */
+    SPH_ERR_CAPACITY = -2,      /* an output array is too small; the required size is returned */
+    SPH_ERR_WORKSPACE = -3,     /* workspace smaller than sph_workspace_bytes() */
+    SPH_ERR_HIP = -4,           /* a HIP runtime call or launch failed */
+    SPH_ERR_DOMAIN = -5,        /* device flag: non-finite position or non-positive density */
+    SPH_ERR_NOT_IMPLEMENTED = -6,
+    SPH_ERR_STALE_GRID = -7     /* device flag: a particle left its cell by more than skin/2 */
+};
+
+enum sph_precision {
+    SPH_FP64 = 0,       /* every operation in double precision */
+    SPH_FP32_COMP = 1   /* pair terms in single precision with Kahan-compensated single-
+                           precision sums per particle; partner test, equation of state,
+                           limiter and stress rate in double precision */
+};
+
+enum sph_op {
+    SPH_OP_BUILD = 0,
+    SPH_OP_NEIGHBOURS = 1,
+    SPH_OP_RHS = 2,
+    SPH_OP_ADJOINT = 3,
+    SPH_OP_LEAPFROG = 4,
+    SPH_OP_LEAPFROG_ADJOINT = 5
+};
+
+/* Uniform grid of cubic cells ("helping grid", section 3.5.2) produced by
+ * sph_build_cells.  Cells are numbered c = ix + dims[0] * (iy + dims[1] * iz);
+ * particles outside the box [lo, lo + dims * cell) are binned into the nearest
+ * boundary cell, which keeps every partner reachable.  The grid stays valid for
+ * later positions as long as no particle has moved by more than skin / 2 since
+ * the build (checked by sph_rhs / sph_rhs_adjoint / sph_neighbours). */
+typedef struct {
+    int64_t n;            /* particles binned */
+    int32_t dims[3];      /* cells per axis */
+    int64_t ncells;       /* dims[0] * dims[1] * dims[2] */
+    double lo[3];         /* lower corner of cell (0,0,0) */
+    double cell;          /* cell edge length */
+    double h;             /* largest support radius the grid serves */
+    double skin;          /* displacement allowance: 2 x the tolerated movement */
+    int32_t *perm;        /* device [n]: sorted slot -> user index; slots ordered by
+                             (cell, user index) */
+    int32_t *cell_start;  /* device [ncells + 1]: first slot of each cell; last = n */
+    int32_t *cell_of;     /* device [n]: cell of each slot */
+} sph_grid;
+
+/* Particle state (inputs), all device arrays of length n, user order. */
+typedef struct {
+    int64_t n;
+    const double *x, *y, *z;
+    const double *vx, *vy, *vz;
+    const double *rho;
+    const double *sxx, *syy, *szz, *sxy, *sxz, *syz;
+    const double *m;
+} sph_state;
+
+/* Material and numerical constants (SI units).  h: support radius; rho0, c:
+ * linear equation of state p = c^2 (rho - rho0) (section 2.5.1); mu: shear
+ * modulus; Y0: von Mises yield stress (section 2.6); alpha, beta, eps_v:
+ * artificial viscosity (section 3.1.3); rho_cut: pressure is set to zero where
+ * rho / rho0 < rho_cut (tension cut-off of section 2.5.1; 0 disables it). */
+typedef struct {
+    double h, rho0, c, mu, Y0, alpha, beta, eps_v, rho_cut;
+} sph_params;
+
+/* Time derivatives (outputs) in user order.  rho_sum may be NULL. */
+typedef struct {
+    double *ax, *ay, *az;
+    double *drho;
+    double *dsxx, *dsyy, *dszz, *dsxy, *dsxz, *dsyz;
+    double *rho_sum;
+} sph_deriv;
+
+/* Cotangents of the derivatives (inputs of the adjoint), user order.  A NULL
+ * pointer means a zero cotangent. */
+typedef struct {
+    const double *ax, *ay, *az;
+    const double *drho;
+    const double *dsxx, *dsyy, *dszz, *dsxy, *dsxz, *dsyz;
+    const double *rho_sum;
+} sph_deriv_cot;
+
+/* Writable per-particle fields (no mass): used for gradients with respect to
+ * the state (outputs of the adjoints; per stored component of S, an
+ * off-diagonal entry standing for both of its matrix positions) and for the
+ * final state of a trajectory.  Outputs are overwritten. */
+typedef struct {
+    double *x, *y, *z;
+    double *vx, *vy, *vz;
+    double *rho;
+    double *sxx, *syy, *szz, *sxy, *sxz, *syz;
+} sph_fields;
+
+typedef sph_fields sph_state_grad;
+
+/* Read-only per-particle fields (cotangents of a final state).  NULL = zero. */
+typedef struct {
+    const double *x, *y, *z;
+    const double *vx, *vy, *vz;
+    const double *rho;
+    const double *sxx, *syy, *szz, *sxy, *sxz, *syz;
+} sph_cfields;
+
+/* Library version string. */
+const char *sph_version(void);
+
+/* Message describing the last failing call on this thread ("" if none). */
+const char *sph_last_error(void);
+
+/* Scratch bytes needed by an operation (enum sph_op) for n particles and
+ * ncells cells (ncells is ignored by SPH_OP_RHS and SPH_OP_ADJOINT). */
+size_t sph_workspace_bytes(int op, int64_t n, int64_t ncells);
+
+/* Host-only: grid geometry for the box [lo, hi] at support radius h, skin and
+ * cells_per_h (1 or 2): cell = (h + skin) (1 + 2^-40) / cells_per_h,
+ * dims = max(1, ceil((hi - lo) / cell)).  Lets the caller size cell_start. */
+int sph_grid_geometry(const double lo[3], const double hi[3], double h, double skin,
+                      int cells_per_h, int32_t dims_out[3], int64_t *ncells_out,
+                      double *cell_out);
+
+/* Cell list of the particles (the paper's helping grid of section 3.5.2):
+ * bins every particle into the grid given by sph_grid_geometry(lo, hi, h,
+ * skin, cells_per_h), counting-sorts the slots by cell (one digit of radix
+ * ncells) and orders each cell by user index, so the result is deterministic.
+ *   x, y, z     device [n] positions (user order)
+ *   perm        device [n] out; cell_of device [n] out
+ *   cell_start  device [ncells_cap + 1] out
+ *   grid_out    host struct, filled in (pointers are the caller's arrays)
+ * Errors: INVALID_ARG (null pointer, n <= 0, n >= 2^31, h <= 0, skin < 0,
+ * lo >= hi, cells_per_h not 1 or 2), CAPACITY (ncells > ncells_cap; grid_out->
+ * ncells holds the required count), WORKSPACE.  Device flag DOMAIN for
+ * non-finite positions. */
+int sph_build_cells(const double *x, const double *y, const double *z, int64_t n,
+                    const double lo[3], const double hi[3], double h, double skin,
+                    int cells_per_h, int32_t *perm, int32_t *cell_start,
+                    int64_t ncells_cap, int32_t *cell_of, sph_grid *grid_out,
+                    void *ws, size_t ws_bytes, void *stream);
+
+/* Interaction partner lists (the paper's interactionsList of section 3.5.2)
+ * at the current positions: row a of the CSR holds the user indices b of all
+ * partners of user particle a, ascending, self excluded.
+ *   row_ptr   device [n + 1] int64 out
+ *   col       device [col_cap] int32 out
+ *   nnz_out   host, receives the number of ordered pairs
+ * Synchronises the stream once (to learn nnz).  Errors: INVALID_ARG (h > grid
+ * h), CAPACITY (nnz > col_cap: nothing is written to col, *nnz_out holds the
+ * requirement), WORKSPACE, STALE_GRID, DOMAIN. */
+int sph_neighbours(const sph_grid *grid, const double *x, const double *y, const double *z,
+                   double h, int64_t *row_ptr, int32_t *col, int64_t col_cap,
+                   int64_t *nnz_out, void *ws, size_t ws_bytes, void *stream);
+
+/* Right-hand side for every particle, with the partner set re-derived from
+ * the grid at the current positions:
+ *   prepass   p = c^2 (rho - rho0) (section 2.5.1); f_Y = min(Y0^2 / (3 J2), 1),
+ *             J2 = S:S / 2 (section 2.6); sigma = -p I + f_Y S (section 2.2)
+ *   pairs     rho_sum_a = m_a W(0) + sum_b m_b W_ab  (eq. density_by_kernel_sum)
+ *             L_a = sum_b (m_b/rho_b) (v_b - v_a) (x) grad_a W_ab  (section 3.1.6)
+ *             a_a = sum_b m_b [sigma_a/rho_a^2 + sigma_b/rho_b^2 - Pi*_ab I] grad_a W_ab
+ *             with the artificial viscosity Pi*_ab of section 3.1.3 (only for
+ *             approaching pairs) and the B-spline of section 3.1.1
+ *   postpass  drho_a = -rho_a tr L_a (eq. continuity_equation_sph);
+ *             dS_a = 2 mu (edot - tr(edot) I / 3) + R S~ - S~ R with edot, R the
+ *             symmetric and antisymmetric parts of L and S~ = f_Y S (section 2.4)
+ * precision: enum sph_precision.  Outputs are overwritten (user order).
+ * Errors: INVALID_ARG (state->n != grid->n, h > grid->h, non-finite or
+ * non-positive h, c, rho0, negative mu or Y0, ...), WORKSPACE.  Device flags
+ * STALE_GRID, DOMAIN. */
+int sph_rhs(const sph_grid *grid, const sph_state *state, const sph_params *params,
+            int precision, const sph_deriv *out, void *ws, size_t ws_bytes, void *stream);
+
+/* Vector-Jacobian product of sph_rhs in double precision: given
+ * cotangents of (a, drho, dS, rho_sum) returns the gradients with respect to
+ * positions, velocities, densities and stresses (masses are constants) and,
+ * in dparams (device double[2], overwritten), with respect to mu and Y0.  The
+ * partner set is the one sph_rhs uses at the same positions; every pair term
+ * vanishes with its first derivative at distance h, so the product is exact.
+ * Gather form: each particle sums its own terms from its partners' data; no
+ * atomics, reproducible bit for bit.  Errors as sph_rhs. */
+int sph_rhs_adjoint(const sph_grid *grid, const sph_state *state, const sph_params *params,
+                    const sph_deriv_cot *cot, const sph_state_grad *grad, double *dparams,
+                    void *ws, size_t ws_bytes, void *stream);
+
+/* Kick-drift-kick leapfrog that drives the gradient workloads (the paper's
+ * own integrators are those of section 3.4).  With U = (v, rho, S) and
+ * F = sph_rhs in double precision on the given (frozen) grid:
+ *   F_0 = F(x_0, U_0); for n = 0 .. steps-1:
+ *     U_{n+1/2} = U_n + dt/2 F_n,  then S <- f_Y(S) S
+ *     x_{n+1}   = x_n + dt v_{n+1/2}
+ *     F_{n+1}   = F(x_{n+1}, U_{n+1/2})
+ *     U_{n+1}   = U_{n+1/2} + dt/2 F_{n+1},  then S <- f_Y(S) S
+ *   s0           initial state (device arrays, user order)
+ *   s_final      final state out (may alias the arrays of s0)
+ *   checkpoints  device, sph_checkpoint_bytes(n, steps) bytes, or NULL; holds
+ *                (x, v, rho, S, F) at the start of every step and at the end,
+ *                as needed by sph_leapfrog_adjoint
+ * The grid must have been built with a skin covering the trajectory's largest
+ * displacement (device flag STALE_GRID otherwise).  Errors: as sph_rhs. */
+int sph_leapfrog(const sph_grid *grid, const sph_state *s0, const sph_params *params,
+                 double dt, int steps, const sph_fields *s_final, double *checkpoints,
+                 void *ws, size_t ws_bytes, void *stream);
+
+/* Reverse sweep of sph_leapfrog (the adjoint applied through the trajectory):
+ * given the checkpoints of a forward run and the cotangent of the final state,
+ * writes the gradient with respect to the initial state into grad0 and
+ * (overwriting) dparams[0] = d/d mu, dparams[1] = d/d Y0 (device double[2]).
+ * Deterministic.  Errors: as sph_rhs_adjoint. */
+int sph_leapfrog_adjoint(const sph_grid *grid, const sph_state *s0, const sph_params *params,
+                         double dt, int steps, const double *checkpoints,
+                         const sph_cfields *cot_final, const sph_fields *grad0,
+                         double *dparams, void *ws, size_t ws_bytes, void *stream);
+
+/* Bytes of the checkpoint buffer of sph_leapfrog for n particles and steps steps. */
+size_t sph_checkpoint_bytes(int64_t n, int steps);
+
+/* Synchronise the stream and return the device flag of a workspace (SPH_OK or
+ * a negative status).  Errors: INVALID_ARG, HIP. */
+int sph_workspace_status(const void *ws, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPH_MI355X_H */

@@ -1,0 +1,241 @@
+"""Torch-facing wrappers of the C ABI (same names as the C entry points).
+
+All tensors live on the GPU in float64 (indices int32/int64), contiguous,
+structure-of-arrays: positions and velocities (3, n), stress (6, n) in the
+order xx, yy, zz, xy, xz, yz, density and mass (n,).  Calls are enqueued on
+torch's current stream.  These functions only marshal arguments; the work is
+done by libsph's kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+F64 = torch.float64
+PARAM_ORDER = ("h", "rho0", "c", "mu", "Y0", "alpha", "beta", "eps_v", "rho_cut")
+DERIV_KEYS = ("acc", "drho", "dS", "rho_sum")
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _dev(t: torch.Tensor, dtype=F64) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError("tensors must be on the GPU")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous {dtype} tensor")
+    return t
+
+
+@dataclass
+class ParticleState:
+    pos: torch.Tensor  # (3, n)
+    vel: torch.Tensor  # (3, n)
+    rho: torch.Tensor  # (n,)
+    S: torch.Tensor    # (6, n)
+    m: torch.Tensor    # (n,)
+
+    @property
+    def n(self) -> int:
+        return int(self.rho.shape[0])
+
+    @classmethod
+    def from_arrays(cls, pos, vel, rho, S, m, device="cuda"):
+        t = lambda a: torch.as_tensor(a, dtype=F64).to(device).contiguous()
+        return cls(t(pos), t(vel), t(rho), t(S), t(m))
+
+    def clone(self) -> "ParticleState":
+        return ParticleState(self.pos.clone(), self.vel.clone(), self.rho.clone(), self.S.clone(),
+                             self.m.clone())
+
+    def c_state(self) -> L.State:
+        for t in (self.pos, self.vel, self.rho, self.S, self.m):
+            _dev(t)
+        n = self.n
+        assert self.pos.shape == (3, n) and self.vel.shape == (3, n) and self.S.shape == (6, n)
+        p, v, s = self.pos, self.vel, self.S
+        return L.State(n, p[0].data_ptr(), p[1].data_ptr(), p[2].data_ptr(), v[0].data_ptr(),
+                       v[1].data_ptr(), v[2].data_ptr(), self.rho.data_ptr(), s[0].data_ptr(),
+                       s[1].data_ptr(), s[2].data_ptr(), s[3].data_ptr(), s[4].data_ptr(),
+                       s[5].data_ptr(), self.m.data_ptr())
+
+
+def params_struct(params) -> L.Params:
+    if isinstance(params, dict):
+        vals = [float(params[k]) for k in PARAM_ORDER]
+    else:
+        vals = [float(v) for v in params]
+    return L.Params(*vals)
+
+
+def workspace(op: int, n: int, ncells: int = 0, device="cuda") -> torch.Tensor:
+    """Caller-owned scratch buffer for one operation."""
+    return torch.empty(L.workspace_bytes(op, n, ncells), dtype=torch.uint8, device=device)
+
+
+def workspace_status(ws: torch.Tensor) -> int:
+    """Synchronises and returns the workspace's device flag (0 = fine)."""
+    rc = L.lib().sph_workspace_status(_ptr(ws), _stream())
+    return int(rc)
+
+
+class CellGrid:
+    """Device cell list (keeps the tensors behind the C struct alive)."""
+
+    def __init__(self, perm, cell_start, cell_of, cstruct: L.Grid):
+        self.perm, self.cell_start, self.cell_of, self.c = perm, cell_start, cell_of, cstruct
+        self.ws = None
+
+    @property
+    def n(self):
+        return int(self.c.n)
+
+    @property
+    def dims(self):
+        return tuple(self.c.dims)
+
+    @property
+    def h(self):
+        return float(self.c.h)
+
+
+def default_box(pos: torch.Tensor, h: float, skin: float = 0.0):
+    lo = pos.min(dim=1).values.double().cpu().numpy() - (h + skin)
+    hi = pos.max(dim=1).values.double().cpu().numpy() + (h + skin)
+    return lo, hi
+
+
+def sph_build_cells(pos: torch.Tensor, h: float, skin: float = 0.0, cells_per_h: int = 1,
+                    box=None, ws: torch.Tensor | None = None) -> CellGrid:
+    """Bin particles into the cell grid (C: sph_build_cells)."""
+    _dev(pos)
+    n = int(pos.shape[1])
+    lo, hi = default_box(pos, h, skin) if box is None else box
+    dims, ncells, cell = L.grid_geometry(lo, hi, h, skin, cells_per_h)
+    dev = pos.device
+    perm = torch.empty(n, dtype=torch.int32, device=dev)
+    cell_of = torch.empty(n, dtype=torch.int32, device=dev)
+    cell_start = torch.empty(ncells + 1, dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = workspace(L.SPH_OP_BUILD, n, ncells, dev)
+    g = L.Grid()
+    lo_a = (C.c_double * 3)(*[float(v) for v in lo])
+    hi_a = (C.c_double * 3)(*[float(v) for v in hi])
+    L.check(L.lib().sph_build_cells(_ptr(pos[0]), _ptr(pos[1]), _ptr(pos[2]), n, lo_a, hi_a,
+                                    float(h), float(skin), int(cells_per_h), _ptr(perm),
+                                    _ptr(cell_start), ncells, _ptr(cell_of), C.byref(g), _ptr(ws),
+                                    ws.numel(), _stream()))
+    grid = CellGrid(perm, cell_start, cell_of, g)
+    grid.ws = ws
+    return grid
+
+
+def sph_neighbours(grid: CellGrid, pos: torch.Tensor, h: float, col_cap: int | None = None,
+                   ws: torch.Tensor | None = None):
+    """Partner lists as CSR (row_ptr int64 [n+1], col int32 [nnz]), rows ascending
+    (C: sph_neighbours).  Synchronises once."""
+    _dev(pos)
+    n = grid.n
+    dev = pos.device
+    row_ptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    if ws is None:
+        ws = workspace(L.SPH_OP_NEIGHBOURS, n, 0, dev)
+    nnz = C.c_int64()
+    if col_cap is None:
+        # first pass learns nnz (capacity 0), second fills
+        rc = L.lib().sph_neighbours(C.byref(grid.c), _ptr(pos[0]), _ptr(pos[1]), _ptr(pos[2]),
+                                    float(h), _ptr(row_ptr), C.c_void_p(0), 0, C.byref(nnz),
+                                    _ptr(ws), ws.numel(), _stream())
+        if rc not in (L.SPH_OK, L.SPH_ERR_CAPACITY):
+            L.check(rc)
+        col_cap = int(nnz.value)
+    col = torch.empty(max(col_cap, 1), dtype=torch.int32, device=dev)
+    L.check(L.lib().sph_neighbours(C.byref(grid.c), _ptr(pos[0]), _ptr(pos[1]), _ptr(pos[2]),
+                                   float(h), _ptr(row_ptr), _ptr(col), col_cap, C.byref(nnz),
+                                   _ptr(ws), ws.numel(), _stream()))
+    return row_ptr, col[: int(nnz.value)]
+
+
+def new_deriv(n: int, device="cuda"):
+    return dict(acc=torch.empty(3, n, dtype=F64, device=device),
+                drho=torch.empty(n, dtype=F64, device=device),
+                dS=torch.empty(6, n, dtype=F64, device=device),
+                rho_sum=torch.empty(n, dtype=F64, device=device))
+
+
+def deriv_struct(d: dict, cls=L.Deriv):
+    a, s = d["acc"], d["dS"]
+    for t in (a, s, d["drho"]):
+        _dev(t)
+    rs = d.get("rho_sum")
+    return cls(a[0].data_ptr(), a[1].data_ptr(), a[2].data_ptr(), d["drho"].data_ptr(),
+               s[0].data_ptr(), s[1].data_ptr(), s[2].data_ptr(), s[3].data_ptr(),
+               s[4].data_ptr(), s[5].data_ptr(), rs.data_ptr() if rs is not None else None)
+
+
+def fields_struct(pos, vel, rho, S, cls=L.Fields):
+    return cls(pos[0].data_ptr(), pos[1].data_ptr(), pos[2].data_ptr(), vel[0].data_ptr(),
+               vel[1].data_ptr(), vel[2].data_ptr(), rho.data_ptr(), S[0].data_ptr(),
+               S[1].data_ptr(), S[2].data_ptr(), S[3].data_ptr(), S[4].data_ptr(),
+               S[5].data_ptr())
+
+
+def precision_code(precision) -> int:
+    if precision in (L.SPH_FP64, "fp64", "f64"):
+        return L.SPH_FP64
+    if precision in (L.SPH_FP32_COMP, "fp32comp", "fp32_comp", "f32c"):
+        return L.SPH_FP32_COMP
+    raise ValueError(precision)
+
+
+def sph_rhs(grid: CellGrid, state: ParticleState, params, precision="fp64", out=None,
+            ws: torch.Tensor | None = None) -> dict:
+    """Right-hand side (C: sph_rhs): dict acc (3, n), drho (n), dS (6, n), rho_sum (n)."""
+    n = state.n
+    if out is None:
+        out = new_deriv(n, state.rho.device)
+    if ws is None:
+        ws = workspace(L.SPH_OP_RHS, n, 0, state.rho.device)
+    cs = state.c_state()
+    d = deriv_struct(out)
+    L.check(L.lib().sph_rhs(C.byref(grid.c), C.byref(cs), C.byref(params_struct(params)),
+                            precision_code(precision), C.byref(d), _ptr(ws), ws.numel(),
+                            _stream()))
+    out["_ws"] = ws
+    return out
+
+
+def sph_rhs_adjoint(grid: CellGrid, state: ParticleState, params, cot: dict,
+                    ws: torch.Tensor | None = None) -> dict:
+    """Vector-Jacobian product of sph_rhs (C: sph_rhs_adjoint).  ``cot`` has keys of
+    sph_rhs's outputs (missing = zero).  Returns gradients pos, vel, rho, S, mu, Y0."""
+    n = state.n
+    dev = state.rho.device
+    z3 = lambda k, shape: _dev(cot[k]) if cot.get(k) is not None else None
+    acc, drho, dS, rs = (z3("acc", None), z3("drho", None), z3("dS", None), z3("rho_sum", None))
+    p = lambda t, i=None: (t[i].data_ptr() if i is not None else t.data_ptr()) if t is not None else None
+    dc = L.DerivCot(p(acc, 0), p(acc, 1), p(acc, 2), p(drho), p(dS, 0), p(dS, 1), p(dS, 2),
+                    p(dS, 3), p(dS, 4), p(dS, 5), p(rs))
+    g = dict(pos=torch.empty(3, n, dtype=F64, device=dev), vel=torch.empty(3, n, dtype=F64, device=dev),
+             rho=torch.empty(n, dtype=F64, device=dev), S=torch.empty(6, n, dtype=F64, device=dev))
+    dparams = torch.empty(2, dtype=F64, device=dev)
+    if ws is None:
+        ws = workspace(L.SPH_OP_ADJOINT, n, 0, dev)
+    cs = state.c_state()
+    fs = fields_struct(g["pos"], g["vel"], g["rho"], g["S"])
+    L.check(L.lib().sph_rhs_adjoint(C.byref(grid.c), C.byref(cs), C.byref(params_struct(params)),
+                                    C.byref(dc), C.byref(fs), _ptr(dparams), _ptr(ws), ws.numel(),
+                                    _stream()))
+    g["mu"] = dparams[0]
+    g["Y0"] = dparams[1]
+    g["_ws"] = ws
+    return g

@@ -1,0 +1,168 @@
+// Internal helpers shared by the HIP sources of libsph (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstddef>
+#include <cstdint>
+
+#include "sph.h"
+
+namespace sph {
+
+// ------------------------------------------------------------------ errors --
+int fail(int code, const char *fmt, ...);
+void clear_error();
+
+#define SPH_HIP_TRY(expr)                                                              \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return ::sph::fail(SPH_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_));   \
+    } while (0)
+
+#define SPH_LAUNCHED() SPH_HIP_TRY(hipGetLastError())
+
+constexpr int kBlock = 256;
+
+inline unsigned blocks_for(int64_t n, int per_block = kBlock) {
+    return (unsigned)((n + per_block - 1) / per_block);
+}
+
+// --------------------------------------------------------------- workspace --
+// Every workspace starts with a 256-byte header whose first int32 is the device
+// status flag; the rest is carved in 256-byte aligned pieces.  The same carving
+// code computes sizes (base == nullptr) and pointers.
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+struct Carve {
+    char *base;
+    size_t used = kAlign;  // header
+    explicit Carve(void *b) : base((char *)b) {}
+    template <class T>
+    T *take(size_t count) {
+        T *r = base ? (T *)(base + used) : nullptr;
+        used += align_up(count * sizeof(T));
+        return r;
+    }
+    int32_t *status() const { return (int32_t *)base; }
+};
+
+__device__ inline void raise_flag(int32_t *status, int32_t code) { atomicCAS(status, 0, code); }
+
+// Clears the status word (a kernel, not a memset, so the call sequence can be
+// captured in a graph).
+int clear_status(void *ws, hipStream_t s);
+
+// --------------------------------------------------------------------- grid --
+struct GridDev {
+    int32_t nx, ny, nz;
+    double lox, loy, loz;
+    double cell, inv_cell;
+    double delta;  // tolerated movement since binning: skin / 2
+    const int32_t *__restrict__ perm;
+    const int32_t *__restrict__ cell_start;
+    const int32_t *__restrict__ cell_of;
+};
+
+inline GridDev grid_dev(const sph_grid *g) {
+    GridDev d;
+    d.nx = g->dims[0];
+    d.ny = g->dims[1];
+    d.nz = g->dims[2];
+    d.lox = g->lo[0];
+    d.loy = g->lo[1];
+    d.loz = g->lo[2];
+    d.cell = g->cell;
+    d.inv_cell = 1.0 / g->cell;
+    d.delta = 0.5 * g->skin;
+    d.perm = g->perm;
+    d.cell_start = g->cell_start;
+    d.cell_of = g->cell_of;
+    return d;
+}
+
+int check_grid(const sph_grid *g);
+
+__device__ inline int cell_index(double p, double lo, double inv_cell, int ncell) {
+    double t = floor((p - lo) * inv_cell);
+    t = fmin(fmax(t, 0.0), (double)(ncell - 1));  // NaN -> 0
+    return (int)t;
+}
+
+// Distance from p to the slab of cell i along one axis; the first and last
+// cells extend to infinity (they also hold the particles binned from outside
+// the box).
+__device__ inline double slab_gap(double p, double lo, double cell, int i, int ncell) {
+    const double a = lo + cell * i;
+    const double b = a + cell;
+    double g = 0.0;
+    if (i > 0 && p < a) g = a - p;
+    if (i < ncell - 1 && p > b) g = p - b;
+    return g;
+}
+
+// Squared distance of the partner test, every operation rounded on its own.
+__device__ inline double dist2_exact(double xa, double ya, double za, double xb, double yb,
+                                     double zb) {
+#pragma clang fp contract(off)
+    const double dx = xb - xa;
+    const double dy = yb - ya;
+    const double dz = zb - za;
+    return (dx * dx + dy * dy) + dz * dz;
+}
+
+// Visits the slot ranges [s0, s1) of every cell row whose box comes within
+// `reach` of p (rows in y-z, a contiguous run of cells along x per row).
+// A partner b of a target at p (|x_b - p| < h) lies within delta of its cell's
+// box, so reach = (h + delta)(1 + 1e-9) visits every partner.
+template <class F>
+__device__ inline void for_each_row(const GridDev &g, double px, double py, double pz,
+                                    double reach, F &&f) {
+    const double r2 = reach * reach;
+    const int z0 = cell_index(pz - reach, g.loz, g.inv_cell, g.nz);
+    const int z1 = cell_index(pz + reach, g.loz, g.inv_cell, g.nz);
+    const int y0 = cell_index(py - reach, g.loy, g.inv_cell, g.ny);
+    const int y1 = cell_index(py + reach, g.loy, g.inv_cell, g.ny);
+    for (int iz = z0; iz <= z1; ++iz) {
+        const double gz = slab_gap(pz, g.loz, g.cell, iz, g.nz);
+        const double gz2 = gz * gz;
+        if (gz2 >= r2) continue;
+        for (int iy = y0; iy <= y1; ++iy) {
+            const double gy = slab_gap(py, g.loy, g.cell, iy, g.ny);
+            const double d2 = gz2 + gy * gy;
+            if (d2 >= r2) continue;
+            const double w = sqrt(r2 - d2) * (1.0 + 1e-9);
+            const int x0 = cell_index(px - w, g.lox, g.inv_cell, g.nx);
+            const int x1 = cell_index(px + w, g.lox, g.inv_cell, g.nx);
+            const int row = (iz * g.ny + iy) * g.nx;
+            f(g.cell_start[row + x0], g.cell_start[row + x1 + 1]);
+        }
+    }
+}
+
+// Slot -> box check: the current position of slot s must lie within delta of
+// the box of the cell it was binned into.
+__device__ inline bool within_cell(const GridDev &g, int s, double x, double y, double z) {
+    const int c = g.cell_of[s];
+    const int ix = c % g.nx;
+    const int iy = (c / g.nx) % g.ny;
+    const int iz = c / (g.nx * g.ny);
+    const double lim = g.delta * (1.0 - 1e-9);
+    return slab_gap(x, g.lox, g.cell, ix, g.nx) <= lim &&
+           slab_gap(y, g.loy, g.cell, iy, g.ny) <= lim &&
+           slab_gap(z, g.loz, g.cell, iz, g.nz) <= lim;
+}
+
+// ------------------------------------------------------------ B-spline, 3-D --
+// Section 3.1.1: W = s/h^3 w(q), dW/dr = 6s/h^4 g(q), q = r/h, s = 8/pi.
+constexpr double kSigma3 = 2.5464790894703255;  // 8 / pi
+
+// exclusive scans (scan.hip)
+int exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *tmp, hipStream_t s);
+int exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t s);
+size_t scan_tmp_elems(int64_t n);
+
+}  // namespace sph
