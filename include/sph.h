@@ -255,6 +255,15 @@ int sph_leapfrog_adjoint(const sph_grid *grid, const sph_state *s0, const sph_pa
 /* Bytes of the checkpoint buffer of sph_leapfrog for n particles and steps steps. */
 size_t sph_checkpoint_bytes(int64_t n, int steps);
 
+/* Diagnostics.  When enabled, the library brackets its hot kernels with HIP
+ * events recorded on the caller's stream ("pairs_fp64", "pairs_fp32comp",
+ * "adjoint_pairs", ...).  sph_timing_read synchronises on the recorded events
+ * and returns the summed duration in milliseconds and the number of launches
+ * since the last reset.  Off by default.  Errors: INVALID_ARG, HIP. */
+int sph_timing_enable(int on);
+int sph_timing_read(const char *kernel, double *total_ms, int64_t *launches);
+int sph_timing_reset(void);
+
 /* Synchronise the stream and return the device flag of a workspace (SPH_OK or
  * a negative status).  Errors: INVALID_ARG, HIP. */
 int sph_workspace_status(const void *ws, void *stream);

@@ -12,6 +12,8 @@ from .api import (  # noqa: F401
     CellGrid,
     ParticleState,
     sph_build_cells,
+    sph_leapfrog,
+    sph_leapfrog_adjoint,
     sph_neighbours,
     sph_rhs,
     sph_rhs_adjoint,
@@ -24,3 +26,5 @@ build_cells = sph_build_cells
 neighbours = sph_neighbours
 rhs = sph_rhs
 rhs_adjoint = sph_rhs_adjoint
+leapfrog = sph_leapfrog
+leapfrog_adjoint = sph_leapfrog_adjoint

@@ -116,6 +116,8 @@ def lib():
         L.sph_leapfrog_adjoint.argtypes = [P(Grid), P(State), P(Params), C.c_double, C.c_int, _pd,
                                            P(CFields), P(Fields), _pd, _pd, C.c_size_t, _vp]
         L.sph_workspace_status.argtypes = [_pd, _vp]
+        L.sph_timing_enable.argtypes = [C.c_int]
+        L.sph_timing_read.argtypes = [C.c_char_p, P(C.c_double), P(C.c_int64)]
         _lib = L
     return _lib
 
@@ -147,3 +149,19 @@ def grid_geometry(lo, hi, h: float, skin: float = 0.0, cells_per_h: int = 1):
     check(lib().sph_grid_geometry(lo_a, hi_a, float(h), float(skin), int(cells_per_h), dims,
                                   C.byref(ncells), C.byref(cell)))
     return tuple(dims), int(ncells.value), float(cell.value)
+
+
+def timing_enable(on: bool = True):
+    check(lib().sph_timing_enable(1 if on else 0))
+
+
+def timing_reset():
+    check(lib().sph_timing_reset())
+
+
+def timing_read(kernel: str):
+    """(total milliseconds, launches) of a bracketed kernel since the last reset."""
+    ms = C.c_double()
+    cnt = C.c_int64()
+    check(lib().sph_timing_read(kernel.encode(), C.byref(ms), C.byref(cnt)))
+    return float(ms.value), int(cnt.value)

@@ -239,3 +239,62 @@ def sph_rhs_adjoint(grid: CellGrid, state: ParticleState, params, cot: dict,
     g["Y0"] = dparams[1]
     g["_ws"] = ws
     return g
+
+
+def _fields(n, dev):
+    return dict(pos=torch.empty(3, n, dtype=F64, device=dev), vel=torch.empty(3, n, dtype=F64, device=dev),
+                rho=torch.empty(n, dtype=F64, device=dev), S=torch.empty(6, n, dtype=F64, device=dev))
+
+
+def sph_leapfrog(grid: CellGrid, state: ParticleState, params, dt: float, steps: int,
+                 checkpoints: bool | torch.Tensor = True, out: ParticleState | None = None,
+                 ws: torch.Tensor | None = None):
+    """Kick-drift-kick trajectory of ``steps`` steps on the (frozen) grid (C: sph_leapfrog).
+    Returns (final ParticleState, checkpoint tensor or None)."""
+    n = state.n
+    dev = state.rho.device
+    if out is None:
+        out = ParticleState(torch.empty_like(state.pos), torch.empty_like(state.vel),
+                            torch.empty_like(state.rho), torch.empty_like(state.S), state.m)
+    if checkpoints is True:
+        ck = torch.empty(L.checkpoint_bytes(n, steps) // 8, dtype=F64, device=dev)
+    elif checkpoints is False or checkpoints is None:
+        ck = None
+    else:
+        ck = checkpoints
+    if ws is None:
+        ws = workspace(L.SPH_OP_LEAPFROG, n, 0, dev)
+    cs = state.c_state()
+    fs = fields_struct(out.pos, out.vel, out.rho, out.S)
+    L.check(L.lib().sph_leapfrog(C.byref(grid.c), C.byref(cs), C.byref(params_struct(params)),
+                                 float(dt), int(steps), C.byref(fs), _ptr(ck), _ptr(ws), ws.numel(),
+                                 _stream()))
+    out._ws = ws
+    return out, ck
+
+
+def sph_leapfrog_adjoint(grid: CellGrid, state0: ParticleState, params, dt: float, steps: int,
+                         checkpoints: torch.Tensor, cot_final: dict, ws: torch.Tensor | None = None,
+                         grad: dict | None = None) -> dict:
+    """Gradient of <cot_final, final state> with respect to the initial state and (mu, Y0)
+    (C: sph_leapfrog_adjoint).  ``cot_final`` keys pos, vel, rho, S (missing = zero)."""
+    n = state0.n
+    dev = state0.rho.device
+    g = _fields(n, dev) if grad is None else grad
+    dparams = torch.empty(2, dtype=F64, device=dev)
+    if ws is None:
+        ws = workspace(L.SPH_OP_LEAPFROG_ADJOINT, n, 0, dev)
+    t = lambda k: _dev(cot_final[k]) if cot_final.get(k) is not None else None
+    cp, cv, cr, cS = t("pos"), t("vel"), t("rho"), t("S")
+    p = lambda x, i=None: (x[i].data_ptr() if i is not None else x.data_ptr()) if x is not None else None
+    cf = L.CFields(p(cp, 0), p(cp, 1), p(cp, 2), p(cv, 0), p(cv, 1), p(cv, 2), p(cr),
+                   p(cS, 0), p(cS, 1), p(cS, 2), p(cS, 3), p(cS, 4), p(cS, 5))
+    cs = state0.c_state()
+    fs = fields_struct(g["pos"], g["vel"], g["rho"], g["S"])
+    L.check(L.lib().sph_leapfrog_adjoint(C.byref(grid.c), C.byref(cs), C.byref(params_struct(params)),
+                                         float(dt), int(steps), _ptr(checkpoints), C.byref(cf),
+                                         C.byref(fs), _ptr(dparams), _ptr(ws), ws.numel(), _stream()))
+    g["mu"] = dparams[0]
+    g["Y0"] = dparams[1]
+    g["_ws"] = ws
+    return g

@@ -1,32 +1,419 @@
-// Vector-Jacobian product of the right-hand side (placeholder until the
-// gather-form kernels land).
+// Vector-Jacobian product of the right-hand side (double precision).
+//
+// Forward quantities are recomputed from the state: the prepass records
+// (T = sigma / rho^2, V = m / rho, slot order) and every particle's velocity
+// gradient L.  Then, in the reverse order of the forward passes:
+//
+//  post     per particle a, from the cotangents of drho = -rho tr L and
+//           dS = 2 mu dev(sym L) + R S~ - S~ R (section 2.4), with G the
+//           symmetric matrix of the dS cotangent (off-diagonal = half the stored
+//           component's cotangent):
+//             Lbar = -rho drho_bar I + 2 mu dev(G) + (G S~ - S~ G)
+//             mu_bar += 2 <dev G, L>,  rho_bar += -tr(L) drho_bar,
+//             S~_bar += G R - R G
+//  pairs    gather form: particle c loops over its partners b once and takes
+//           the derivative of every term it appears in, as target (sums of c)
+//           and as partner (sums of b).  With r = x_c - x_b, u = v_b - v_c,
+//           g = grad_c W_cb = F(r) r, A = m_b abar_c - m_c abar_b and
+//           M = V_b Lbar_c + V_c Lbar_b:
+//             gbar  = M^T u + (T_c + T_b - Pi I) A,   Pibar = -A . g
+//             xbar_c += (rsbar_c m_b + rsbar_b m_c) g + F gbar + G (r.gbar) r
+//                       - wbar u + 2 r2bar r
+//             vbar_c += -M g + wbar r
+//             Tbar_c += sym(A (x) g),  Vbar_c += u^T Lbar_b g,
+//             rhobar_c += -Pibar Pi / (rho_c + rho_b)
+//           where G = F'(r)/r and wbar, r2bar follow from Pibar through
+//           nu = h w / (r^2 + eps h^2), w = (v_c - v_b).r (approaching pairs).
+//           No atomics: every particle writes only its own gradient.
+//  pre      per particle: through T = (f_Y S - p I)/rho^2, V = m/rho, the
+//           pressure (section 2.5.1) and the limiter f_Y = min(Y0^2/(3 J2), 1)
+//           (section 2.6) to rho_bar, S_bar and Y0_bar.
+//
+// mu_bar and Y0_bar are reduced per block with a fixed tree and then by one
+// block in a fixed order, so results are reproducible bit for bit.
 #include "common.hpp"
+#include "rhs_common.hpp"
+#include "timing.hpp"
 
 namespace sph {
-size_t adjoint_ws_bytes(int64_t n) { Carve c(nullptr); c.take<double>(n); return c.used; }
-size_t leapfrog_ws_bytes(int64_t n) { Carve c(nullptr); c.take<double>(n); return c.used; }
-size_t leapfrog_adjoint_ws_bytes(int64_t n) { Carve c(nullptr); c.take<double>(n); return c.used; }
+
+struct AdjRec {
+    double *L[9];      // forward velocity gradient (slot order)
+    double *Lb[9];     // its cotangent
+    double *ab[3];     // acceleration cotangent (slot order)
+    double *rsb;       // rho_sum cotangent
+    double *rhob;      // partial density cotangent from the post stage
+    double *Stb[6];    // partial cotangent of f_Y S from the rotation terms (stored components)
+    double *part_mu;   // per-block partial sums
+    double *part_y0;
+};
+
+inline AdjRec carve_adj(Carve &c, int64_t n) {
+    AdjRec r;
+    for (int i = 0; i < 9; ++i) r.L[i] = c.take<double>(n);
+    for (int i = 0; i < 9; ++i) r.Lb[i] = c.take<double>(n);
+    for (int i = 0; i < 3; ++i) r.ab[i] = c.take<double>(n);
+    r.rsb = c.take<double>(n);
+    r.rhob = c.take<double>(n);
+    for (int i = 0; i < 6; ++i) r.Stb[i] = c.take<double>(n);
+    r.part_mu = c.take<double>(blocks_for(n));
+    r.part_y0 = c.take<double>(blocks_for(n));
+    return r;
+}
+
+namespace {
+
+__device__ inline double ld(const double *p, int i) { return p ? p[i] : 0.0; }
+
+__device__ inline void put(double *p, int i, double v, int acc) {
+    if (acc)
+        p[i] += v;
+    else
+        p[i] = v;
+}
+
+// forward velocity gradient of every slot
+__global__ __launch_bounds__(kBlock) void k_adj_L(GridDev g, int64_t n, Consts k, Rec64 rec,
+                                                  AdjRec ad) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const double xa = rec.x[s], ya = rec.y[s], za = rec.z[s];
+    const double vxa = rec.vx[s], vya = rec.vy[s], vza = rec.vz[s];
+    double L[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for_each_row(g, xa, ya, za, k.reach, [&](int s0, int s1) {
+        for (int t = s0; t < s1; ++t) {
+            const double d2 = dist2_exact(xa, ya, za, rec.x[t], rec.y[t], rec.z[t]);
+            if (!(d2 < k.h2) || t == s) continue;
+            const double r = sqrt(d2);
+            const double q = r * k.inv_h;
+            double f;
+            if (q < 0.5) {
+                f = 3.0 * q - 2.0;
+            } else {
+                const double u = 1.0 - q;
+                f = -u * u / q;
+            }
+            const double F = k.Fn * f;
+            const double gx = F * (xa - rec.x[t]), gy = F * (ya - rec.y[t]), gz = F * (za - rec.z[t]);
+            const double V = rec.V[t];
+            const double tx = V * (rec.vx[t] - vxa), ty = V * (rec.vy[t] - vya), tz = V * (rec.vz[t] - vza);
+            L[0] += tx * gx; L[1] += tx * gy; L[2] += tx * gz;
+            L[3] += ty * gx; L[4] += ty * gy; L[5] += ty * gz;
+            L[6] += tz * gx; L[7] += tz * gy; L[8] += tz * gz;
+        }
+    });
+#pragma unroll
+    for (int i = 0; i < 9; ++i) ad.L[i][s] = L[i];
+}
+
+// post stage (see the file header)
+__global__ __launch_bounds__(kBlock) void k_adj_post(GridDev g, int64_t n, Consts k, Rec64 rec,
+                                                     StateDev st, CotDev cot, AdjRec ad) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double mu_part = 0.0;
+    if (s < n) {
+        const int a = g.perm[s];
+        double L[3][3];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) L[i / 3][i % 3] = ad.L[i][s];
+        const double rho = rec.rho[s];
+        double S[6] = {st.sxx[a], st.syy[a], st.szz[a], st.sxy[a], st.sxz[a], st.syz[a]};
+        const double f = yield_factor(k, S);
+        const double St[3][3] = {{f * S[0], f * S[3], f * S[4]},
+                                 {f * S[3], f * S[1], f * S[5]},
+                                 {f * S[4], f * S[5], f * S[2]}};
+        double c6[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) c6[i] = ld(cot.ds[i], a);
+        const double G[3][3] = {{c6[0], 0.5 * c6[3], 0.5 * c6[4]},
+                                {0.5 * c6[3], c6[1], 0.5 * c6[5]},
+                                {0.5 * c6[4], 0.5 * c6[5], c6[2]}};
+        const double rdot = ld(cot.drho, a);
+        const double trG = G[0][0] + G[1][1] + G[2][2];
+        double R[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) R[i][j] = 0.5 * (L[i][j] - L[j][i]);
+        double mu_b = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const double D = G[i][j] - (i == j ? trG / 3.0 : 0.0);
+                double P = 0.0;  // (G S~ - S~ G)_ij
+#pragma unroll
+                for (int m = 0; m < 3; ++m) P += G[i][m] * St[m][j] - St[i][m] * G[m][j];
+                const double Lb = (i == j ? -rho * rdot : 0.0) + 2.0 * k.mu * D + P;
+                ad.Lb[3 * i + j][s] = Lb;
+                mu_b += 2.0 * D * L[i][j];
+            }
+        mu_part = mu_b;
+        ad.rhob[s] = -(L[0][0] + L[1][1] + L[2][2]) * rdot;
+        double Sb[3][3];  // G R - R G
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                double v = 0.0;
+#pragma unroll
+                for (int m = 0; m < 3; ++m) v += G[i][m] * R[m][j] - R[i][m] * G[m][j];
+                Sb[i][j] = v;
+            }
+        ad.Stb[0][s] = Sb[0][0];
+        ad.Stb[1][s] = Sb[1][1];
+        ad.Stb[2][s] = Sb[2][2];
+        ad.Stb[3][s] = Sb[0][1] + Sb[1][0];
+        ad.Stb[4][s] = Sb[0][2] + Sb[2][0];
+        ad.Stb[5][s] = Sb[1][2] + Sb[2][1];
+        ad.ab[0][s] = ld(cot.ax, a);
+        ad.ab[1][s] = ld(cot.ay, a);
+        ad.ab[2][s] = ld(cot.az, a);
+        ad.rsb[s] = ld(cot.rho_sum, a);
+    }
+    const double tot = block_sum(mu_part);
+    if (threadIdx.x == 0) ad.part_mu[blockIdx.x] = tot;
+}
+
+struct AdjAcc {
+    double gx = 0, gy = 0, gz = 0, gvx = 0, gvy = 0, gvz = 0, grho = 0, gV = 0;
+    double gT[6] = {0, 0, 0, 0, 0, 0};
+};
+
+// pair stage + pre stage (see the file header)
+__global__ __launch_bounds__(kBlock) void k_adj_pairs(GridDev g, int64_t n, Consts k, Rec64 rec,
+                                                      StateDev st, AdjRec ad, GradDev out) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double y0_part = 0.0;
+    if (s < n) {
+        const double xc = rec.x[s], yc = rec.y[s], zc = rec.z[s];
+        const double vxc = rec.vx[s], vyc = rec.vy[s], vzc = rec.vz[s];
+        const double rc = rec.rho[s], mc = rec.m[s], Vc = rec.V[s];
+        double Tc[6], Lbc[9];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) Tc[i] = rec.t[i][s];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) Lbc[i] = ad.Lb[i][s];
+        const double abx = ad.ab[0][s], aby = ad.ab[1][s], abz = ad.ab[2][s];
+        const double rsc = ad.rsb[s];
+        const double Gn = k.Fn * k.inv_h * k.inv_h;
+        AdjAcc acc;
+        for_each_row(g, xc, yc, zc, k.reach, [&](int s0, int s1) {
+            for (int t = s0; t < s1; ++t) {
+                const double d2 = dist2_exact(xc, yc, zc, rec.x[t], rec.y[t], rec.z[t]);
+                if (!(d2 < k.h2) || t == s) continue;
+                const double rx = xc - rec.x[t], ry = yc - rec.y[t], rz = zc - rec.z[t];
+                const double ux = rec.vx[t] - vxc, uy = rec.vy[t] - vyc, uz = rec.vz[t] - vzc;
+                const double rb = rec.rho[t], mb = rec.m[t], Vb = rec.V[t];
+                const double r = sqrt(d2);
+                const double q = r * k.inv_h;
+                double f, G;
+                if (q < 0.5) {
+                    f = 3.0 * q - 2.0;
+                    G = q > 0.0 ? 3.0 * Gn / q : 0.0;
+                } else {
+                    const double u1 = 1.0 - q;
+                    f = -u1 * u1 / q;
+                    G = Gn * (1.0 - q * q) / (q * q * q);
+                }
+                const double F = k.Fn * f;
+                const double gx = F * rx, gy = F * ry, gz = F * rz;
+                const double Ax = mb * abx - mc * ad.ab[0][t];
+                const double Ay = mb * aby - mc * ad.ab[1][t];
+                const double Az = mb * abz - mc * ad.ab[2][t];
+                double Lbb[9], M[9];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    Lbb[i] = ad.Lb[i][t];
+                    M[i] = Vb * Lbc[i] + Vc * Lbb[i];
+                }
+                const double w = -(ux * rx + uy * ry + uz * rz);
+                double Pi = 0.0, nu = 0.0, D = 1.0, coef = 0.0;
+                if (w < 0.0) {
+                    D = d2 + k.epsh2;
+                    nu = k.h * w / D;
+                    coef = 2.0 / (rc + rb);
+                    Pi = (-k.alpha_c * nu + k.beta * nu * nu) * coef;
+                }
+                const double B0 = Tc[0] + rec.t[0][t] - Pi, B1 = Tc[1] + rec.t[1][t] - Pi;
+                const double B2 = Tc[2] + rec.t[2][t] - Pi, B3 = Tc[3] + rec.t[3][t];
+                const double B4 = Tc[4] + rec.t[4][t], B5 = Tc[5] + rec.t[5][t];
+                const double gbx = M[0] * ux + M[3] * uy + M[6] * uz + B0 * Ax + B3 * Ay + B4 * Az;
+                const double gby = M[1] * ux + M[4] * uy + M[7] * uz + B3 * Ax + B1 * Ay + B5 * Az;
+                const double gbz = M[2] * ux + M[5] * uy + M[8] * uz + B4 * Ax + B5 * Ay + B2 * Az;
+                const double Pib = -(Ax * gx + Ay * gy + Az * gz);
+                double wb = 0.0, r2b = 0.0;
+                if (w < 0.0) {
+                    const double nub = Pib * (-k.alpha_c + 2.0 * k.beta * nu) * coef;
+                    wb = nub * k.h / D;
+                    r2b = -nub * nu / D;
+                    acc.grho += -Pib * Pi / (rc + rb);
+                }
+                const double rsw = rsc * mb + ad.rsb[t] * mc;
+                const double rg = rx * gbx + ry * gby + rz * gbz;
+                acc.gx += rsw * gx + F * gbx + G * rg * rx - wb * ux + 2.0 * r2b * rx;
+                acc.gy += rsw * gy + F * gby + G * rg * ry - wb * uy + 2.0 * r2b * ry;
+                acc.gz += rsw * gz + F * gbz + G * rg * rz - wb * uz + 2.0 * r2b * rz;
+                acc.gvx += -(M[0] * gx + M[1] * gy + M[2] * gz) + wb * rx;
+                acc.gvy += -(M[3] * gx + M[4] * gy + M[5] * gz) + wb * ry;
+                acc.gvz += -(M[6] * gx + M[7] * gy + M[8] * gz) + wb * rz;
+                acc.gT[0] += Ax * gx;
+                acc.gT[1] += Ay * gy;
+                acc.gT[2] += Az * gz;
+                acc.gT[3] += Ax * gy + Ay * gx;
+                acc.gT[4] += Ax * gz + Az * gx;
+                acc.gT[5] += Ay * gz + Az * gy;
+                acc.gV += ux * (Lbb[0] * gx + Lbb[1] * gy + Lbb[2] * gz) +
+                          uy * (Lbb[3] * gx + Lbb[4] * gy + Lbb[5] * gz) +
+                          uz * (Lbb[6] * gx + Lbb[7] * gy + Lbb[8] * gz);
+            }
+        });
+        // pre stage: T = (f S - p I) / rho^2, V = m / rho, pressure, limiter
+        const int a = g.perm[s];
+        double S[6] = {st.sxx[a], st.syy[a], st.szz[a], st.sxy[a], st.sxz[a], st.syz[a]};
+        const double j2 = j2_of(S);
+        const bool limited = 3.0 * j2 > k.Y0sq;
+        const double f = limited ? k.Y0sq / (3.0 * j2) : 1.0;
+        const double ir2 = 1.0 / (rc * rc);
+        double grho = ad.rhob[s] + acc.grho - acc.gV * Vc / rc;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) grho += acc.gT[i] * (-2.0 * Tc[i] / rc);
+        const bool cut = k.rho_cut > 0.0 && rc / k.rho0 < k.rho_cut;
+        if (!cut) grho += k.c2 * (-(acc.gT[0] + acc.gT[1] + acc.gT[2]) * ir2);
+        double Stb[6], fb = 0.0;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            Stb[i] = acc.gT[i] * ir2 + ad.Stb[i][s];
+            fb += Stb[i] * S[i];
+        }
+        double gS[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) gS[i] = f * Stb[i];
+        if (limited) {
+            const double Jb = -fb * f / j2;
+#pragma unroll
+            for (int i = 0; i < 6; ++i) gS[i] += Jb * (i < 3 ? S[i] : 2.0 * S[i]);
+            y0_part = fb * 2.0 * f / k.Y0;
+        }
+        const int A = out.accumulate;
+        put(out.x, a, acc.gx, A);
+        put(out.y, a, acc.gy, A);
+        put(out.z, a, acc.gz, A);
+        put(out.vx, a, acc.gvx, A);
+        put(out.vy, a, acc.gvy, A);
+        put(out.vz, a, acc.gvz, A);
+        put(out.rho, a, grho, A);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) put(out.s[i], a, gS[i], A);
+    }
+    const double tot = block_sum(y0_part);
+    if (threadIdx.x == 0) ad.part_y0[blockIdx.x] = tot;
+}
+
+}  // namespace
+
+namespace {
+// one block: dparams[i] (+)= sum of part_i in a fixed order (a null part is skipped)
+__global__ __launch_bounds__(kBlock) void k_reduce_params(const double *__restrict__ p0,
+                                                          const double *__restrict__ p1,
+                                                          int64_t m, double *dparams, int accumulate) {
+    double a = 0.0, b = 0.0;
+    for (int64_t i = threadIdx.x; i < m; i += kBlock) {
+        if (p0) a += p0[i];
+        if (p1) b += p1[i];
+    }
+    a = block_sum(a);
+    b = block_sum(b);
+    if (threadIdx.x == 0) {
+        if (accumulate) {
+            if (p0) dparams[0] += a;
+            if (p1) dparams[1] += b;
+        } else {
+            dparams[0] = a;
+            dparams[1] = b;
+        }
+    }
+}
+
+}  // namespace
+
+int reduce_params_launch(const double *p0, const double *p1, int64_t m, double *dparams,
+                         int accumulate, hipStream_t s) {
+    k_reduce_params<<<1, kBlock, 0, s>>>(p0, p1, m, dparams, accumulate);
+    SPH_LAUNCHED();
+    return SPH_OK;
+}
+
+size_t adjoint_ws_bytes(int64_t n) {
+    Carve c(nullptr);
+    carve_rec64(c, n);
+    carve_adj(c, n);
+    return c.used;
+}
+
+CotDev cot_dev(const sph_deriv_cot *c) {
+    return CotDev{c->ax, c->ay, c->az, c->drho, {c->dsxx, c->dsyy, c->dszz, c->dsxy, c->dsxz, c->dsyz},
+                  c->rho_sum};
+}
+
+GradDev grad_dev(const sph_fields *g, int accumulate) {
+    return GradDev{g->x, g->y, g->z, g->vx, g->vy, g->vz, g->rho,
+                   {g->sxx, g->syy, g->szz, g->sxy, g->sxz, g->syz}, accumulate};
+}
+
+// Adjoint of one right-hand side on a carved workspace; gradients written or
+// accumulated (accumulate != 0) into grad; dparams written or accumulated.
+int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_params *params,
+                       const CotDev &cot, const GradDev &grad, double *dparams, int accumulate_params,
+                       Carve &c, hipStream_t s) {
+    const int64_t n = grid->n;
+    GridDev g = grid_dev(grid);
+    Consts k = make_consts(*params, g.delta);
+    Rec64 rec = carve_rec64(c, n);
+    AdjRec ad = carve_adj(c, n);
+    StateDev st = state_dev(state);
+    int rc = prepass_launch(g, st, n, k, rec, c.status(), s);
+    if (rc) return rc;
+    k_adj_L<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, ad);
+    SPH_LAUNCHED();
+    k_adj_post<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, cot, ad);
+    SPH_LAUNCHED();
+    {
+        TimedRegion t("adjoint_pairs", s);
+        k_adj_pairs<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, ad, grad);
+        SPH_LAUNCHED();
+    }
+    return reduce_params_launch(ad.part_mu, ad.part_y0, blocks_for(n), dparams, accumulate_params, s);
+}
+
+int check_grad(const sph_fields *g) {
+    if (!g) return fail(SPH_ERR_INVALID_ARG, "gradient struct is NULL");
+    const double *p[] = {g->x, g->y, g->z, g->vx, g->vy, g->vz, g->rho,
+                         g->sxx, g->syy, g->szz, g->sxy, g->sxz, g->syz};
+    for (const double *q : p)
+        if (!q) return fail(SPH_ERR_INVALID_ARG, "gradient array is NULL");
+    return SPH_OK;
+}
+
 }  // namespace sph
 
 using namespace sph;
 
-extern "C" int sph_rhs_adjoint(const sph_grid *, const sph_state *, const sph_params *,
-                               const sph_deriv_cot *, const sph_state_grad *, double *, void *,
-                               size_t, void *) {
-    return fail(SPH_ERR_NOT_IMPLEMENTED, "sph_rhs_adjoint is not implemented yet");
-}
-
-extern "C" int sph_leapfrog(const sph_grid *, const sph_state *, const sph_params *, double, int,
-                            const sph_fields *, double *, void *, size_t, void *) {
-    return fail(SPH_ERR_NOT_IMPLEMENTED, "sph_leapfrog is not implemented yet");
-}
-
-extern "C" int sph_leapfrog_adjoint(const sph_grid *, const sph_state *, const sph_params *, double,
-                                    int, const double *, const sph_cfields *, const sph_fields *,
-                                    double *, void *, size_t, void *) {
-    return fail(SPH_ERR_NOT_IMPLEMENTED, "sph_leapfrog_adjoint is not implemented yet");
-}
-
-extern "C" size_t sph_checkpoint_bytes(int64_t n, int steps) {
-    return (size_t)(steps + 1) * 23u * (size_t)(n > 0 ? n : 0) * sizeof(double);
+extern "C" int sph_rhs_adjoint(const sph_grid *grid, const sph_state *state,
+                               const sph_params *params, const sph_deriv_cot *cot,
+                               const sph_state_grad *grad, double *dparams, void *ws,
+                               size_t ws_bytes, void *stream) {
+    clear_error();
+    int rc;
+    if ((rc = check_grid(grid)) || (rc = check_state(grid, state)) ||
+        (rc = check_params(grid, params)) || (rc = check_grad(grad)))
+        return rc;
+    if (!cot) return fail(SPH_ERR_INVALID_ARG, "cotangent struct is NULL");
+    if (!dparams || !ws) return fail(SPH_ERR_INVALID_ARG, "null pointer");
+    const size_t need = adjoint_ws_bytes(grid->n);
+    if (ws_bytes < need) return fail(SPH_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = clear_status(ws, s))) return rc;
+    Carve c(ws);
+    return rhs_adjoint_launch(grid, state, params, cot_dev(cot), grad_dev(grad, 0), dparams, 0, c, s);
 }

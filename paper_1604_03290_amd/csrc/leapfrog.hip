@@ -1,0 +1,393 @@
+// Kick-drift-kick leapfrog on a frozen grid and its reverse sweep.
+//
+//   F_0 = F(x_0, U_0),  U = (v, rho, S)
+//   for n = 0 .. K-1:
+//     U'      = U_n + dt/2 F_n,   S' <- f_Y(S') S'         (kick)
+//     x_{n+1} = x_n + dt v'                               (drift)
+//     F_{n+1} = F(x_{n+1}, U')
+//     U_{n+1} = U' + dt/2 F_{n+1}, S <- f_Y(S) S          (kick)
+//
+// f_Y = min(Y0^2 / (3 J2), 1) is the von Mises factor of section 2.6.  The
+// checkpoint of step k holds (x_k, v_k, rho_k, S_k, F_k), 23 arrays of n
+// doubles.  The reverse sweep walks the steps backwards, recomputing U' from
+// the checkpoint, and applies in turn the adjoints of the second kick, of the
+// right-hand side at (x_{n+1}, U'), of the drift and of the first kick.
+#include "common.hpp"
+#include "rhs_common.hpp"
+
+namespace sph {
+namespace {
+
+constexpr int kArrays = 23;  // x3 v3 rho S6 | a3 drho dS6
+
+struct Fields13 {
+    double *p[13];  // x y z vx vy vz rho sxx syy szz sxy sxz syz
+};
+
+struct Deriv10 {
+    double *p[10];  // ax ay az drho dsxx .. dsyz
+};
+
+__device__ inline void limit6(double S[6], double Y0sq) {
+    const double j3 = 3.0 * j2_of(S);
+    if (j3 > Y0sq) {
+        const double f = Y0sq / j3;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) S[i] *= f;
+    }
+}
+
+// U (in) -> U' (out): v += h a, rho += h drho, S = f_Y(S + h dS)(S + h dS)
+__global__ __launch_bounds__(kBlock) void k_kick(Fields13 in, Deriv10 d, Fields13 out, int64_t n,
+                                                 double h, double Y0sq) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out.p[3 + c][i] = in.p[3 + c][i] + h * d.p[c][i];
+    out.p[6][i] = in.p[6][i] + h * d.p[3][i];
+    double S[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) S[c] = in.p[7 + c][i] + h * d.p[4 + c][i];
+    limit6(S, Y0sq);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) out.p[7 + c][i] = S[c];
+}
+
+__global__ __launch_bounds__(kBlock) void k_drift(Fields13 f, int64_t n, double dt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) f.p[c][i] += dt * f.p[3 + c][i];
+}
+
+// copy (state, derivative) into a checkpoint slab of kArrays * n doubles
+__global__ __launch_bounds__(kBlock) void k_store(Fields13 f, Deriv10 d, int64_t n, double *slab) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+#pragma unroll
+    for (int c = 0; c < 13; ++c) slab[c * n + i] = f.p[c][i];
+#pragma unroll
+    for (int c = 0; c < 10; ++c) slab[(13 + c) * n + i] = d.p[c][i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill(double *p, int64_t n, double v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Adjoint of the kick U_out = kick(U_in, F): given S_in, dS and the cotangent of
+// U_out in gU (updated in place to the cotangent of U_in), writes or adds the
+// cotangent of F into gF and leaves the Y0 contribution in per-block partials.
+struct Ptr12 {
+    const double *p[12];  // S_in (6) then dS (6)
+};
+
+__global__ __launch_bounds__(kBlock) void k_kick_adj(Ptr12 Sin_dS, Fields13 gU,
+                                                     Deriv10 gF, int64_t n, double h, double Y0,
+                                                     int accumulate, double *part_y0) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double y0p = 0.0;
+    if (i < n) {
+        double S[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) S[c] = Sin_dS.p[c][i] + h * Sin_dS.p[6 + c][i];
+        double Sb[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) Sb[c] = gU.p[7 + c][i];
+        const double j2 = j2_of(S);
+        const double Y0sq = Y0 * Y0;
+        double out[6];
+        if (3.0 * j2 > Y0sq) {
+            const double f = Y0sq / (3.0 * j2);
+            double fb = 0.0;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) fb += Sb[c] * S[c];
+            const double Jb = -fb * f / j2;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) out[c] = f * Sb[c] + Jb * (c < 3 ? S[c] : 2.0 * S[c]);
+            y0p = fb * 2.0 * f / Y0;
+        } else {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) out[c] = Sb[c];
+        }
+#pragma unroll
+        for (int c = 0; c < 6; ++c) gU.p[7 + c][i] = out[c];
+        double v[10];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c] = h * gU.p[3 + c][i];
+        v[3] = h * gU.p[6][i];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[4 + c] = h * out[c];
+#pragma unroll
+        for (int c = 0; c < 10; ++c) {
+            if (accumulate)
+                gF.p[c][i] += v[c];
+            else
+                gF.p[c][i] = v[c];
+        }
+    }
+    const double tot = block_sum(y0p);
+    if (threadIdx.x == 0) part_y0[blockIdx.x] = tot;
+}
+
+// adjoint of the drift: vbar += dt xbar
+__global__ __launch_bounds__(kBlock) void k_drift_adj(Fields13 gU, int64_t n, double dt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gU.p[3 + c][i] += dt * gU.p[c][i];
+}
+
+Fields13 fields_of(const sph_fields *f) {
+    return Fields13{{f->x, f->y, f->z, f->vx, f->vy, f->vz, f->rho, f->sxx, f->syy, f->szz, f->sxy,
+                     f->sxz, f->syz}};
+}
+
+Fields13 slab_fields(double *slab, int64_t n) {
+    Fields13 f;
+    for (int c = 0; c < 13; ++c) f.p[c] = slab + c * n;
+    return f;
+}
+
+Deriv10 slab_deriv(double *slab, int64_t n) {
+    Deriv10 d;
+    for (int c = 0; c < 10; ++c) d.p[c] = slab + (13 + c) * n;
+    return d;
+}
+
+Deriv10 carve_deriv(Carve &c, int64_t n) {
+    Deriv10 d;
+    for (int i = 0; i < 10; ++i) d.p[i] = c.take<double>(n);
+    return d;
+}
+
+Fields13 carve_fields(Carve &c, int64_t n) {
+    Fields13 f;
+    for (int i = 0; i < 13; ++i) f.p[i] = c.take<double>(n);
+    return f;
+}
+
+sph_deriv deriv_struct(const Deriv10 &d) {
+    sph_deriv o;
+    o.ax = d.p[0];
+    o.ay = d.p[1];
+    o.az = d.p[2];
+    o.drho = d.p[3];
+    o.dsxx = d.p[4];
+    o.dsyy = d.p[5];
+    o.dszz = d.p[6];
+    o.dsxy = d.p[7];
+    o.dsxz = d.p[8];
+    o.dsyz = d.p[9];
+    o.rho_sum = nullptr;
+    return o;
+}
+
+sph_state state_struct(const Fields13 &f, const double *m, int64_t n) {
+    sph_state s;
+    s.n = n;
+    s.x = f.p[0];
+    s.y = f.p[1];
+    s.z = f.p[2];
+    s.vx = f.p[3];
+    s.vy = f.p[4];
+    s.vz = f.p[5];
+    s.rho = f.p[6];
+    s.sxx = f.p[7];
+    s.syy = f.p[8];
+    s.szz = f.p[9];
+    s.sxy = f.p[10];
+    s.sxz = f.p[11];
+    s.syz = f.p[12];
+    s.m = m;
+    return s;
+}
+
+int copy_fields(const sph_state *src, const Fields13 &dst, int64_t n, hipStream_t s) {
+    const double *p[13] = {src->x,   src->y,   src->z,   src->vx,  src->vy,  src->vz, src->rho,
+                           src->sxx, src->syy, src->szz, src->sxy, src->sxz, src->syz};
+    for (int c = 0; c < 13; ++c)
+        if (p[c] != dst.p[c])
+            SPH_HIP_TRY(hipMemcpyAsync(dst.p[c], p[c], n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return SPH_OK;
+}
+
+int check_lf(const sph_grid *grid, const sph_state *s0, const sph_params *params, double dt,
+             int steps) {
+    int rc;
+    if ((rc = check_grid(grid)) || (rc = check_state(grid, s0)) || (rc = check_params(grid, params)))
+        return rc;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SPH_ERR_INVALID_ARG, "dt must be positive");
+    if (steps < 1) return fail(SPH_ERR_INVALID_ARG, "steps must be >= 1");
+    return SPH_OK;
+}
+
+}  // namespace
+
+size_t leapfrog_ws_bytes(int64_t n) {
+    Carve c(nullptr);
+    carve_deriv(c, n);
+    c.used += rhs_ws_bytes(n);
+    return c.used;
+}
+
+size_t leapfrog_adjoint_ws_bytes(int64_t n) {
+    Carve c(nullptr);
+    carve_fields(c, n);  // cotangent of the state
+    carve_fields(c, n);  // U' (only v, rho, S used; x points at the next checkpoint)
+    carve_deriv(c, n);   // cotangent of F_{n+1}
+    carve_deriv(c, n);   // cotangent of F_n
+    c.take<double>(blocks_for(n));
+    c.used += adjoint_ws_bytes(n);
+    return c.used;
+}
+
+}  // namespace sph
+
+using namespace sph;
+
+extern "C" size_t sph_checkpoint_bytes(int64_t n, int steps) {
+    if (n <= 0 || steps < 0) return 0;
+    return (size_t)(steps + 1) * kArrays * (size_t)n * sizeof(double);
+}
+
+extern "C" int sph_leapfrog(const sph_grid *grid, const sph_state *s0, const sph_params *params,
+                            double dt, int steps, const sph_fields *s_final, double *checkpoints,
+                            void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    int rc;
+    if ((rc = check_lf(grid, s0, params, dt, steps)) || (rc = check_grad(s_final))) return rc;
+    if (!ws) return fail(SPH_ERR_INVALID_ARG, "workspace is NULL");
+    const int64_t n = grid->n;
+    const size_t need = leapfrog_ws_bytes(n);
+    if (ws_bytes < need) return fail(SPH_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = clear_status(ws, s))) return rc;
+    Carve c(ws);
+    Deriv10 F = carve_deriv(c, n);
+    Carve rc_ws(ws);  // the right-hand side shares the status word, carves after F
+    rc_ws.used = c.used;
+    const Fields13 U = fields_of(s_final);
+    if ((rc = copy_fields(s0, U, n, s))) return rc;
+    const sph_state st = state_struct(U, s0->m, n);
+    const sph_deriv d = deriv_struct(F);
+    const double half = 0.5 * dt;
+    const unsigned nb = blocks_for(n);
+    auto rhs = [&]() {
+        Carve w = rc_ws;
+        return rhs_launch(grid, &st, params, SPH_FP64, &d, w, s);
+    };
+    if ((rc = rhs())) return rc;
+    for (int k = 0; k < steps; ++k) {
+        if (checkpoints) {
+            k_store<<<nb, kBlock, 0, s>>>(U, F, n, checkpoints + (size_t)k * kArrays * n);
+            SPH_LAUNCHED();
+        }
+        k_kick<<<nb, kBlock, 0, s>>>(U, F, U, n, half, params->Y0 * params->Y0);
+        SPH_LAUNCHED();
+        k_drift<<<nb, kBlock, 0, s>>>(U, n, dt);
+        SPH_LAUNCHED();
+        if ((rc = rhs())) return rc;
+        k_kick<<<nb, kBlock, 0, s>>>(U, F, U, n, half, params->Y0 * params->Y0);
+        SPH_LAUNCHED();
+    }
+    if (checkpoints) {
+        k_store<<<nb, kBlock, 0, s>>>(U, F, n, checkpoints + (size_t)steps * kArrays * n);
+        SPH_LAUNCHED();
+    }
+    return SPH_OK;
+}
+
+extern "C" int sph_leapfrog_adjoint(const sph_grid *grid, const sph_state *s0,
+                                    const sph_params *params, double dt, int steps,
+                                    const double *checkpoints, const sph_cfields *cot_final,
+                                    const sph_fields *grad0, double *dparams, void *ws,
+                                    size_t ws_bytes, void *stream) {
+    clear_error();
+    int rc;
+    if ((rc = check_lf(grid, s0, params, dt, steps)) || (rc = check_grad(grad0))) return rc;
+    if (!checkpoints || !cot_final || !dparams || !ws)
+        return fail(SPH_ERR_INVALID_ARG, "null pointer");
+    const int64_t n = grid->n;
+    const size_t need = leapfrog_adjoint_ws_bytes(n);
+    if (ws_bytes < need) return fail(SPH_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = clear_status(ws, s))) return rc;
+    Carve c(ws);
+    const Fields13 gU = fields_of(grad0);  // cotangent of the current state, in place
+    Fields13 Up = carve_fields(c, n);
+    Deriv10 gF1 = carve_deriv(c, n);
+    Deriv10 gF0 = carve_deriv(c, n);
+    double *part = c.take<double>(blocks_for(n));
+    Carve adj_ws(ws);
+    adj_ws.used = c.used;
+    const unsigned nb = blocks_for(n);
+    const double half = 0.5 * dt;
+    double *ck = const_cast<double *>(checkpoints);
+    const double Y0 = params->Y0;
+
+    // cotangent of the final state
+    const double *cf[13] = {cot_final->x,   cot_final->y,   cot_final->z,   cot_final->vx,
+                            cot_final->vy,  cot_final->vz,  cot_final->rho, cot_final->sxx,
+                            cot_final->syy, cot_final->szz, cot_final->sxy, cot_final->sxz,
+                            cot_final->syz};
+    for (int i = 0; i < 13; ++i) {
+        if (cf[i]) {
+            SPH_HIP_TRY(hipMemcpyAsync(gU.p[i], cf[i], n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        } else {
+            k_fill<<<nb, kBlock, 0, s>>>(gU.p[i], n, 0.0);
+            SPH_LAUNCHED();
+        }
+    }
+    k_fill<<<1, 2, 0, s>>>(dparams, 2, 0.0);
+    SPH_LAUNCHED();
+
+    const GradDev acc = grad_dev(grad0, 1);
+    auto adjoint_at = [&](const sph_state &st, const Deriv10 &gF) {
+        CotDev cot{gF.p[0], gF.p[1], gF.p[2], gF.p[3],
+                   {gF.p[4], gF.p[5], gF.p[6], gF.p[7], gF.p[8], gF.p[9]}, nullptr};
+        Carve w = adj_ws;
+        return rhs_adjoint_launch(grid, &st, params, cot, acc, dparams, 1, w, s);
+    };
+    auto kick_adj = [&](const Fields13 &Uin, const Deriv10 &F, const Deriv10 &gF, int accumulate) {
+        Ptr12 t;
+        for (int c6 = 0; c6 < 6; ++c6) {
+            t.p[c6] = Uin.p[7 + c6];
+            t.p[6 + c6] = F.p[4 + c6];
+        }
+        k_kick_adj<<<nb, kBlock, 0, s>>>(t, gU, gF, n, half, Y0, accumulate, part);
+        SPH_LAUNCHED();
+        return reduce_params_launch(nullptr, part, nb, dparams, 1, s);
+    };
+
+    for (int k = steps - 1; k >= 0; --k) {
+        double *slab_k = ck + (size_t)k * kArrays * n;
+        double *slab_k1 = ck + (size_t)(k + 1) * kArrays * n;
+        const Fields13 Uk = slab_fields(slab_k, n);
+        const Deriv10 Fk = slab_deriv(slab_k, n);
+        const Fields13 Uk1 = slab_fields(slab_k1, n);
+        const Deriv10 Fk1 = slab_deriv(slab_k1, n);
+        // U' = kick(U_k, F_k); its positions are x_{k+1}
+        k_kick<<<nb, kBlock, 0, s>>>(Uk, Fk, Up, n, half, Y0 * Y0);
+        SPH_LAUNCHED();
+        Fields13 Upx = Up;
+        for (int c3 = 0; c3 < 3; ++c3) Upx.p[c3] = Uk1.p[c3];
+        // second kick U_{k+1} = kick(U', F_{k+1}): cotangent of U' and of F_{k+1}
+        // (F_{k+1} already holds the first kick of step k+1 unless k+1 = steps)
+        if ((rc = kick_adj(Up, Fk1, gF1, k + 1 < steps ? 1 : 0))) return rc;
+        // right-hand side F_{k+1} = F(x_{k+1}, U')
+        const sph_state st1 = state_struct(Upx, s0->m, n);
+        if ((rc = adjoint_at(st1, gF1))) return rc;
+        // drift x_{k+1} = x_k + dt v'
+        k_drift_adj<<<nb, kBlock, 0, s>>>(gU, n, dt);
+        SPH_LAUNCHED();
+        // first kick U' = kick(U_k, F_k): cotangent of U_k, fresh cotangent of F_k
+        if ((rc = kick_adj(Uk, Fk, gF0, 0))) return rc;
+        Deriv10 tmp = gF1;
+        gF1 = gF0;
+        gF0 = tmp;
+    }
+    // F_0 = F(x_0, U_0)
+    const sph_state st0 = state_struct(slab_fields(ck, n), s0->m, n);
+    return adjoint_at(st0, gF1);
+}

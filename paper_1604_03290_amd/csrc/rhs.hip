@@ -18,6 +18,7 @@
 // (W'/r)(x_a - x_b) stays finite as r -> 0.
 #include "common.hpp"
 #include "rhs_common.hpp"
+#include "timing.hpp"
 
 namespace sph {
 namespace {
@@ -127,6 +128,13 @@ __global__ __launch_bounds__(kBlock) void k_pairs32(GridDev g, int64_t n, Consts
 
 }  // namespace
 
+int prepass_launch(const GridDev &g, const StateDev &st, int64_t n, const Consts &k,
+                   const Rec64 &rec, int32_t *status, hipStream_t s) {
+    k_prepass<<<blocks_for(n), kBlock, 0, s>>>(g, st, n, k, rec, status);
+    SPH_LAUNCHED();
+    return SPH_OK;
+}
+
 size_t rhs_ws_bytes(int64_t n) {
     Carve c(nullptr);
     carve_rec64(c, n);
@@ -177,14 +185,16 @@ int rhs_launch(const sph_grid *grid, const sph_state *state, const sph_params *p
     Rec32 r32 = carve_rec32(c, n);
     StateDev st = state_dev(state);
     OutDev od = out_dev(out);
-    k_prepass<<<blocks_for(n), kBlock, 0, s>>>(g, st, n, k, rec, c.status());
-    SPH_LAUNCHED();
+    int rc = prepass_launch(g, st, n, k, rec, c.status(), s);
+    if (rc) return rc;
     if (precision == SPH_FP64) {
+        TimedRegion t("pairs_fp64", s);
         k_pairs64<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, od);
         SPH_LAUNCHED();
     } else {
         k_narrow<<<blocks_for(n), kBlock, 0, s>>>(rec, n, r32);
         SPH_LAUNCHED();
+        TimedRegion t("pairs_fp32comp", s);
         k_pairs32<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, r32, st, od);
         SPH_LAUNCHED();
     }

@@ -250,4 +250,53 @@ __device__ inline void postpass(const Consts &k, int a, double rho, const double
     if (o.rho_sum) o.rho_sum[a] = rs;
 }
 
+// Cotangents of the right-hand side's outputs (user order; null = zero).
+struct CotDev {
+    const double *ax, *ay, *az, *drho, *ds[6], *rho_sum;
+};
+
+// Gradient destination (user order), overwritten or accumulated.
+struct GradDev {
+    double *x, *y, *z, *vx, *vy, *vz, *rho, *s[6];
+    int accumulate;
+};
+
+// adjoint.hip
+CotDev cot_dev(const sph_deriv_cot *c);
+GradDev grad_dev(const sph_fields *g, int accumulate);
+int check_grad(const sph_fields *g);
+size_t adjoint_ws_bytes(int64_t n);
+int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_params *params,
+                       const CotDev &cot, const GradDev &grad, double *dparams, int accumulate_params,
+                       Carve &c, hipStream_t s);
+// dparams[0] (+)= sum of p0, dparams[1] (+)= sum of p1 (null parts skipped),
+// fixed summation order
+int reduce_params_launch(const double *p0, const double *p1, int64_t m, double *dparams,
+                         int accumulate, hipStream_t s);
+
+// host-side helpers shared by the entry points (rhs.hip)
+int prepass_launch(const GridDev &g, const StateDev &st, int64_t n, const Consts &k,
+                   const Rec64 &rec, int32_t *status, hipStream_t s);
+int check_state(const sph_grid *grid, const sph_state *st);
+int check_params(const sph_grid *grid, const sph_params *pr);
+int check_deriv(const sph_deriv *o);
+int rhs_launch(const sph_grid *grid, const sph_state *state, const sph_params *params,
+               int precision, const sph_deriv *out, Carve &c, hipStream_t s);
+size_t rhs_ws_bytes(int64_t n);
+
+// Deterministic sum over a 256-thread block (fixed tree); every thread must call it.
+__device__ inline double block_sum(double v) {
+    __shared__ double lds[kBlock];
+    const int t = threadIdx.x;
+    lds[t] = v;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if (t < off) lds[t] += lds[t + off];
+        __syncthreads();
+    }
+    const double r = lds[0];
+    __syncthreads();
+    return r;
+}
+
 }  // namespace sph
