@@ -40,6 +40,8 @@ PEAK_HBM_GBS = 8000.0
 # density sum, velocity gradient, artificial viscosity (on approaching pairs),
 # stress bracket and acceleration.
 FLOPS_PER_PAIR_RHS = 91.0
+# ... and of the adjoint's pair pass (both roles of the pair, see the design notes)
+FLOPS_PER_PAIR_ADJ = 203.0
 
 
 def parse():
@@ -123,23 +125,37 @@ def main():
     ws_rhs = P.workspace(L.SPH_OP_RHS, n)
     out = P.api.new_deriv(n)
 
+    ws_lf = P.workspace(L.SPH_OP_LEAPFROG, n)
+    ws_lfa = P.workspace(L.SPH_OP_LEAPFROG_ADJOINT, n)
+    ws_adj = P.workspace(L.SPH_OP_ADJOINT, n)
+    ck = torch.empty(L.checkpoint_bytes(n, steps_lf) // 8, dtype=torch.float64, device=dev)
+    fin = P.ParticleState(torch.empty_like(st.pos), torch.empty_like(st.vel), torch.empty_like(st.rho),
+                          torch.empty_like(st.S), st.m)
+    cot = {"vel": torch.empty_like(st.vel)}
+    grad = P.api._fields(n, dev)
+
     grid = P.sph_build_cells(st.pos, w.h, skin=skin, box=(lo, hi), ws=ws_build)
     row_ptr, col = P.sph_neighbours(grid, st.pos, w.h, ws=ws_nb)
-    nnz = int(row_ptr[-1].item())
-    col_cap = int(col.numel())
+    nnz0 = int(row_ptr[-1].item())
+    col_cap = int(col.numel()) + n  # room for pairs formed during the trajectory
 
     def step():
         g = P.sph_build_cells(st.pos, w.h, skin=skin, box=(lo, hi), ws=ws_build)
         P.sph_neighbours(g, st.pos, w.h, col_cap=col_cap, ws=ws_nb)
-        for _ in range(steps_lf + 1):
-            P.sph_rhs(g, st, w.params, "fp64", out=out, ws=ws_rhs)
-
-    pairs_per_step = (steps_lf + 1) * nnz
-    step_desc = (f"cell build + partner lists + {steps_lf + 1} FP64 right-hand sides on the frozen grid")
+        P.sph_leapfrog(g, st, w.params, w.dt, steps_lf, checkpoints=ck, out=fin, ws=ws_lf)
+        torch.mul(fin.vel, fin.m, out=cot["vel"])  # d KE / d v_final
+        P.sph_leapfrog_adjoint(g, st, w.params, w.dt, steps_lf, ck, cot, ws=ws_lfa, grad=grad)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    rp_end, _ = P.sph_neighbours(grid, fin.pos, w.h, ws=ws_nb)
+    nnz1 = int(rp_end[-1].item())
+    nnz = 0.5 * (nnz0 + nnz1)
+    pairs_per_step = 2 * (steps_lf + 1) * nnz
+    step_desc = (f"cell build + partner lists + {steps_lf}-step leapfrog ({steps_lf + 1} FP64 right-hand "
+                 f"sides) + reverse sweep ({steps_lf + 1} adjoints) for d KE / d (v0, mu, Y0)")
+
     L.timing_reset()
     L.timing_enable(True)
     torch.cuda.synchronize()
@@ -154,26 +170,44 @@ def main():
     wall = time.perf_counter() - t0
     L.timing_enable(False)
     ms_step = e0.elapsed_time(e1) / args.steps
-    pair_ms, pair_launches = L.timing_read("pairs_fp64")
-    rc = P.workspace_status(ws_rhs)
-    if rc != 0:
-        raise RuntimeError(f"device flag {rc}")
+    kern = {k: L.timing_read(k) for k in ("pairs_fp64", "adjoint_pairs")}
+    for wsx in (ws_lf, ws_lfa):
+        rc = P.workspace_status(wsx)
+        if rc != 0:
+            raise RuntimeError(f"device flag {rc}")
 
-    # per-form rates on the same input (median of reps)
+    # per-form rates on the initial state (median of reps)
     g = P.sph_build_cells(st.pos, w.h, skin=skin, box=(lo, hi), ws=ws_build)
     forms = {}
+    outs = {}
     for form in ("fp64", "fp32comp"):
-        ms = median_ms(lambda: P.sph_rhs(g, st, w.params, form, out=out, ws=ws_rhs), args.form_reps, torch)
-        forms[f"rhs_{form}"] = {"ms": ms, "pairs_per_s": nnz / (ms * 1e-3)}
+        o = P.api.new_deriv(n)
+        ms = median_ms(lambda: P.sph_rhs(g, st, w.params, form, out=o, ws=ws_rhs), args.form_reps, torch)
+        forms[f"rhs_{form}"] = {"ms": ms, "pairs_per_s": nnz0 / (ms * 1e-3)}
+        outs[form] = o
+    fields = {"acc": 3, "drho": 1, "dS": 6, "rho_sum": 1}
+    errs = {}
+    for k in fields:
+        ref = outs["fp64"][k]
+        errs[k] = float((outs["fp32comp"][k] - ref).abs().max() / ref.abs().max())
+    forms["rhs_fp32comp"]["normwise_error_vs_fp64"] = errs
     forms["fp32comp_speedup_vs_fp64"] = forms["rhs_fp64"]["ms"] / forms["rhs_fp32comp"]["ms"]
+    cg = {k: torch.randn_like(outs["fp64"][k]) for k in fields}
+    ms = median_ms(lambda: P.sph_rhs_adjoint(g, st, w.params, cg, ws=ws_adj), args.form_reps, torch)
+    forms["adjoint_fp64"] = {"ms": ms, "pairs_per_s": nnz0 / (ms * 1e-3)}
 
-    avg_pair_ms = pair_ms / max(pair_launches, 1)
-    achieved_tflops = FLOPS_PER_PAIR_RHS * nnz / (avg_pair_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": "k_pairs64 (FP64 right-hand side pair sums)",
-                "achieved": achieved_tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved_tflops / PEAK_FP64_TFLOPS, "traffic": None,
-                "avg_launch_ms": avg_pair_ms, "launches": pair_launches,
-                "flops_per_pair": FLOPS_PER_PAIR_RHS}
+    # dominant kernel of the step
+    dom = max(kern, key=lambda k: kern[k][0])
+    tot_ms, launches = kern[dom]
+    avg_ms = tot_ms / max(launches, 1)
+    fpp = {"pairs_fp64": FLOPS_PER_PAIR_RHS, "adjoint_pairs": FLOPS_PER_PAIR_ADJ}[dom]
+    achieved = fpp * nnz / (avg_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": {"pairs_fp64": "k_pairs64", "adjoint_pairs": "k_adj_pairs"}[dom],
+                "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                "avg_launch_ms": avg_ms, "launches": launches, "flops_per_pair": fpp,
+                "share_of_step": tot_ms / args.steps / ms_step,
+                "other": {k: {"avg_launch_ms": v[0] / max(v[1], 1), "launches": v[1]} for k, v in kern.items()}}
 
     result = {
         "metric": METRIC, "value": pairs_per_step / (ms_step * 1e-3), "unit": UNIT, "n_gpus": 1,
@@ -181,6 +215,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "particles": n, "ordered_pairs_per_rhs": nnz,
+                   "ordered_pairs_start_end": [nnz0, nnz1], "skin_over_dx": 0.25,
                    "h_over_dx": 2.4, "leapfrog_steps": steps_lf, "step": step_desc,
                    "grid_dims": list(dims)},
         "roofline": roofline,
