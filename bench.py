@@ -35,13 +35,12 @@ UNIT = "pair interactions/s"
 PEAK_FP64_TFLOPS = 78.6  # MI355X vector FP64
 PEAK_HBM_GBS = 8000.0
 
-# Algorithmic FP64 operations per ordered pair of the right-hand side (see the
-# design notes for the count): distance, square root, kernel, gradient,
-# density sum, velocity gradient, artificial viscosity (on approaching pairs),
-# stress bracket and acceleration.
-FLOPS_PER_PAIR_RHS = 91.0
-# ... and of the adjoint's pair pass (both roles of the pair, see the design notes)
-FLOPS_PER_PAIR_ADJ = 203.0
+# Algorithmic FP64 operations per ordered pair (FMA = 2, square root and division = 1):
+# right-hand side = distance, square root, kernel, gradient, density sum, velocity
+# gradient, stress bracket, acceleration (83) + the artificial viscosity on approaching
+# pairs (10); adjoint pair pass = both roles of the pair (222) + viscosity terms (23).
+FLOPS_RHS, FLOPS_RHS_APPROACH = 83.0, 10.0
+FLOPS_ADJ, FLOPS_ADJ_APPROACH = 222.0, 23.0
 
 
 def parse():
@@ -137,6 +136,12 @@ def main():
     grid = P.sph_build_cells(st.pos, w.h, skin=skin, box=(lo, hi), ws=ws_build)
     row_ptr, col = P.sph_neighbours(grid, st.pos, w.h, ws=ws_nb)
     nnz0 = int(row_ptr[-1].item())
+    # fraction of ordered pairs that approach (w_ab < 0): they also evaluate Pi
+    rows = torch.repeat_interleave(torch.arange(n, device=dev), row_ptr[1:] - row_ptr[:-1])
+    cl = col.long()
+    wab = ((st.vel[:, rows] - st.vel[:, cl]) * (st.pos[:, rows] - st.pos[:, cl])).sum(0)
+    f_app = float((wab < 0).double().mean())
+    del rows, cl, wab
     col_cap = int(col.numel()) + n  # room for pairs formed during the trajectory
 
     def step():
@@ -200,7 +205,8 @@ def main():
     dom = max(kern, key=lambda k: kern[k][0])
     tot_ms, launches = kern[dom]
     avg_ms = tot_ms / max(launches, 1)
-    fpp = {"pairs_fp64": FLOPS_PER_PAIR_RHS, "adjoint_pairs": FLOPS_PER_PAIR_ADJ}[dom]
+    fpp = {"pairs_fp64": FLOPS_RHS + FLOPS_RHS_APPROACH * f_app,
+           "adjoint_pairs": FLOPS_ADJ + FLOPS_ADJ_APPROACH * f_app}[dom]
     achieved = fpp * nnz / (avg_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": {"pairs_fp64": "k_pairs64", "adjoint_pairs": "k_adj_pairs"}[dom],
                 "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
@@ -216,6 +222,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "particles": n, "ordered_pairs_per_rhs": nnz,
                    "ordered_pairs_start_end": [nnz0, nnz1], "skin_over_dx": 0.25,
+                   "approaching_pair_fraction": f_app,
                    "h_over_dx": 2.4, "leapfrog_steps": steps_lf, "step": step_desc,
                    "grid_dims": list(dims)},
         "roofline": roofline,
