@@ -41,6 +41,7 @@ PEAK_HBM_GBS = 8000.0
 # pairs (10); adjoint pair pass = both roles of the pair (222) + viscosity terms (23).
 FLOPS_RHS, FLOPS_RHS_APPROACH = 83.0, 10.0
 FLOPS_ADJ, FLOPS_ADJ_APPROACH = 222.0, 23.0
+FLOPS_ADJ_L = 45.0  # the adjoint's recomputation of the velocity gradient
 
 
 def parse():
@@ -144,8 +145,12 @@ def main():
     del rows, cl, wab
     col_cap = int(col.numel()) + n  # room for pairs formed during the trajectory
 
+    ws_pairs = P.workspace(L.SPH_OP_PAIRS, n)
+    pl_cap = P.sph_build_pairs(grid, st.pos, ws=ws_pairs)
+
     def step():
         g = P.sph_build_cells(st.pos, w.h, skin=skin, box=(lo, hi), ws=ws_build)
+        P.sph_build_pairs(g, st.pos, capacity=pl_cap, ws=ws_pairs)
         P.sph_neighbours(g, st.pos, w.h, col_cap=col_cap, ws=ws_nb)
         P.sph_leapfrog(g, st, w.params, w.dt, steps_lf, checkpoints=ck, out=fin, ws=ws_lf)
         torch.mul(fin.vel, fin.m, out=cot["vel"])  # d KE / d v_final
@@ -158,8 +163,8 @@ def main():
     nnz1 = int(rp_end[-1].item())
     nnz = 0.5 * (nnz0 + nnz1)
     pairs_per_step = 2 * (steps_lf + 1) * nnz
-    step_desc = (f"cell build + partner lists + {steps_lf}-step leapfrog ({steps_lf + 1} FP64 right-hand "
-                 f"sides) + reverse sweep ({steps_lf + 1} adjoints) for d KE / d (v0, mu, Y0)")
+    step_desc = (f"cell build + frozen pair list + partner CSR + {steps_lf}-step leapfrog ({steps_lf + 1} "
+                 f"FP64 right-hand sides) + reverse sweep ({steps_lf + 1} adjoints) for d KE / d (v0, mu, Y0)")
 
     L.timing_reset()
     L.timing_enable(True)
@@ -175,15 +180,26 @@ def main():
     wall = time.perf_counter() - t0
     L.timing_enable(False)
     ms_step = e0.elapsed_time(e1) / args.steps
-    kern = {k: L.timing_read(k) for k in ("pairs_fp64", "adjoint_pairs")}
+    kern = {k: L.timing_read(k) for k in ("pairs_fp64", "adjoint_pairs", "adjoint_L")}
     for wsx in (ws_lf, ws_lfa):
         rc = P.workspace_status(wsx)
         if rc != 0:
             raise RuntimeError(f"device flag {rc}")
 
-    # per-form rates on the initial state (median of reps)
+    # per-form rates on the initial state (median of reps); the right-hand side and the
+    # adjoint read the frozen pair list, the "cells" form sweeps the cell rows instead
     g = P.sph_build_cells(st.pos, w.h, skin=skin, box=(lo, hi), ws=ws_build)
-    forms = {}
+    forms = {"build_cells": {"ms": median_ms(
+        lambda: P.sph_build_cells(st.pos, w.h, skin=skin, box=(lo, hi), ws=ws_build), args.form_reps, torch)}}
+    forms["build_pairs"] = {"ms": median_ms(
+        lambda: P.sph_build_pairs(g, st.pos, capacity=pl_cap, ws=ws_pairs), args.form_reps, torch),
+        "entries": pl_cap}
+    forms["neighbours_csr"] = {"ms": median_ms(
+        lambda: P.sph_neighbours(g, st.pos, w.h, col_cap=col_cap, ws=ws_nb), args.form_reps, torch)}
+    gc = P.sph_build_cells(st.pos, w.h, skin=skin, box=(lo, hi))
+    oc = P.api.new_deriv(n)
+    ms = median_ms(lambda: P.sph_rhs(gc, st, w.params, "fp64", out=oc, ws=ws_rhs), args.form_reps, torch)
+    forms["rhs_fp64_cell_sweep"] = {"ms": ms, "pairs_per_s": nnz0 / (ms * 1e-3)}
     outs = {}
     for form in ("fp64", "fp32comp"):
         o = P.api.new_deriv(n)
@@ -206,9 +222,11 @@ def main():
     tot_ms, launches = kern[dom]
     avg_ms = tot_ms / max(launches, 1)
     fpp = {"pairs_fp64": FLOPS_RHS + FLOPS_RHS_APPROACH * f_app,
-           "adjoint_pairs": FLOPS_ADJ + FLOPS_ADJ_APPROACH * f_app}[dom]
+           "adjoint_pairs": FLOPS_ADJ + FLOPS_ADJ_APPROACH * f_app,
+           "adjoint_L": FLOPS_ADJ_L}[dom]
     achieved = fpp * nnz / (avg_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": {"pairs_fp64": "k_pairs64", "adjoint_pairs": "k_adj_pairs"}[dom],
+    roofline = {"bound": "alu",
+                "kernel": {"pairs_fp64": "k_pairs64", "adjoint_pairs": "k_adj_pairs", "adjoint_L": "k_adj_L"}[dom],
                 "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
                 "avg_launch_ms": avg_ms, "launches": launches, "flops_per_pair": fpp,

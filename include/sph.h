@@ -64,8 +64,25 @@ enum sph_op {
     SPH_OP_RHS = 2,
     SPH_OP_ADJOINT = 3,
     SPH_OP_LEAPFROG = 4,
-    SPH_OP_LEAPFROG_ADJOINT = 5
+    SPH_OP_LEAPFROG_ADJOINT = 5,
+    SPH_OP_PAIRS = 6
 };
+
+/* Frozen candidate-pair list built by sph_build_pairs (the interaction list of
+ * section 3.5.2 widened by the grid's skin): for every slot s, the slots whose
+ * distance was below h + skin at build time.  Slots are grouped by 64; inside
+ * group B the j-th candidate of slot s = 64 B + l is slot[block_start[B] + 64 j
+ * + l] for j < count[s].  All arrays are device arrays owned by the caller. */
+typedef struct {
+    int64_t n;             /* slots */
+    double radius;         /* h + skin at build time */
+    double skin;           /* tolerated movement since the build: skin / 2 */
+    int32_t *count;        /* [n] candidates per slot */
+    int64_t *block_start;  /* [ceil(n / 64) + 1] first entry of each group; last = total */
+    int32_t *slot;         /* [capacity] candidate slots, interleaved by 64 */
+    int64_t capacity;
+    double *x0;            /* [3 n] slot-ordered positions at build time (x, y, z per slot) */
+} sph_pairs;
 
 /* Uniform grid of cubic cells ("helping grid", section 3.5.2) produced by
  * sph_build_cells.  Cells are numbered c = ix + dims[0] * (iy + dims[1] * iz);
@@ -85,6 +102,9 @@ typedef struct {
                              (cell, user index) */
     int32_t *cell_start;  /* device [ncells + 1]: first slot of each cell; last = n */
     int32_t *cell_of;     /* device [n]: cell of each slot */
+    const sph_pairs *pairs; /* host pointer, NULL until sph_build_pairs; when set, the
+                             right-hand side, adjoint and leapfrog take candidates from
+                             the list instead of sweeping the cells */
 } sph_grid;
 
 /* Particle state (inputs), all device arrays of length n, user order. */
@@ -178,6 +198,25 @@ int sph_build_cells(const double *x, const double *y, const double *z, int64_t n
                     int cells_per_h, int32_t *perm, int32_t *cell_start,
                     int64_t ncells_cap, int32_t *cell_of, sph_grid *grid_out,
                     void *ws, size_t ws_bytes, void *stream);
+
+/* Frozen candidate-pair list for the grid's slots at the current positions
+ * (the paper's interaction list of section 3.5.2, widened by the grid's skin so
+ * it can be reused while particles move): count pass, per-group sizes and scan,
+ * then fill.  Synchronises the stream once to learn the size.
+ *   out         host struct filled in; grid->pairs is set to out (keep it alive)
+ *   count       device [n]; block_start device [ceil(n/64) + 1]
+ *   slot        device [capacity] (may be NULL when capacity is 0)
+ *   x0          device [3 n] positions at build time (slot order)
+ *   needed      host, receives the number of entries (padding included)
+ * Later calls flag SPH_ERR_STALE_GRID when a particle has moved by more than
+ * skin / 2 since this build.  Errors: INVALID_ARG, CAPACITY (needed >
+ * capacity; nothing is filled and grid->pairs is unchanged), WORKSPACE
+ * (sph_workspace_bytes(SPH_OP_PAIRS, n, 0)), STALE_GRID (grid older than the
+ * positions by more than its skin). */
+int sph_build_pairs(sph_grid *grid, const double *x, const double *y, const double *z,
+                    sph_pairs *out, int32_t *count, int64_t *block_start, int32_t *slot,
+                    int64_t capacity, double *x0, int64_t *needed, void *ws, size_t ws_bytes,
+                    void *stream);
 
 /* Interaction partner lists (the paper's interactionsList of section 3.5.2)
  * at the current positions: row a of the CSR holds the user indices b of all

@@ -12,6 +12,7 @@ from .api import (  # noqa: F401
     CellGrid,
     ParticleState,
     sph_build_cells,
+    sph_build_pairs,
     sph_leapfrog,
     sph_leapfrog_adjoint,
     sph_neighbours,
@@ -23,6 +24,7 @@ from .api import (  # noqa: F401
 from ._lib import SPH_FP32_COMP, SPH_FP64, SphError  # noqa: F401
 
 build_cells = sph_build_cells
+build_pairs = sph_build_pairs
 neighbours = sph_neighbours
 rhs = sph_rhs
 rhs_adjoint = sph_rhs_adjoint

@@ -29,7 +29,7 @@ SPH_FP64 = 0
 SPH_FP32_COMP = 1
 
 SPH_OP_BUILD, SPH_OP_NEIGHBOURS, SPH_OP_RHS, SPH_OP_ADJOINT = 0, 1, 2, 3
-SPH_OP_LEAPFROG, SPH_OP_LEAPFROG_ADJOINT = 4, 5
+SPH_OP_LEAPFROG, SPH_OP_LEAPFROG_ADJOINT, SPH_OP_PAIRS = 4, 5, 6
 
 _NAMES = {0: "SPH_OK", -1: "SPH_ERR_INVALID_ARG", -2: "SPH_ERR_CAPACITY", -3: "SPH_ERR_WORKSPACE",
           -4: "SPH_ERR_HIP", -5: "SPH_ERR_DOMAIN", -6: "SPH_ERR_NOT_IMPLEMENTED",
@@ -45,10 +45,16 @@ class SphError(RuntimeError):
         self.code = code
 
 
+class Pairs(C.Structure):
+    _fields_ = [("n", C.c_int64), ("radius", C.c_double), ("skin", C.c_double), ("count", _vp),
+                ("block_start", _vp), ("slot", _vp), ("capacity", C.c_int64), ("x0", _vp)]
+
+
 class Grid(C.Structure):
     _fields_ = [("n", C.c_int64), ("dims", C.c_int32 * 3), ("ncells", C.c_int64),
                 ("lo", C.c_double * 3), ("cell", C.c_double), ("h", C.c_double),
-                ("skin", C.c_double), ("perm", _vp), ("cell_start", _vp), ("cell_of", _vp)]
+                ("skin", C.c_double), ("perm", _vp), ("cell_start", _vp), ("cell_of", _vp),
+                ("pairs", _vp)]
 
 
 class State(C.Structure):
@@ -105,6 +111,8 @@ def lib():
         L.sph_build_cells.argtypes = [_pd, _pd, _pd, C.c_int64, P(C.c_double), P(C.c_double),
                                       C.c_double, C.c_double, C.c_int, _pd, _pd, C.c_int64, _pd,
                                       P(Grid), _pd, C.c_size_t, _vp]
+        L.sph_build_pairs.argtypes = [P(Grid), _pd, _pd, _pd, P(Pairs), _pd, _pd, _pd, C.c_int64,
+                                      _pd, P(C.c_int64), _pd, C.c_size_t, _vp]
         L.sph_neighbours.argtypes = [P(Grid), _pd, _pd, _pd, C.c_double, _pd, _pd, C.c_int64,
                                      P(C.c_int64), _pd, C.c_size_t, _vp]
         L.sph_rhs.argtypes = [P(Grid), P(State), P(Params), C.c_int, P(Deriv), _pd, C.c_size_t,

@@ -89,11 +89,17 @@ def workspace_status(ws: torch.Tensor) -> int:
 
 
 class CellGrid:
-    """Device cell list (keeps the tensors behind the C struct alive)."""
+    """Device cell list (keeps the tensors behind the C struct alive), optionally with a
+    frozen candidate-pair list attached by sph_build_pairs."""
 
     def __init__(self, perm, cell_start, cell_of, cstruct: L.Grid):
         self.perm, self.cell_start, self.cell_of, self.c = perm, cell_start, cell_of, cstruct
         self.ws = None
+        self.pairs = None  # (L.Pairs, count, block_start, slot, x0) when attached
+
+    @property
+    def has_pairs(self) -> bool:
+        return self.pairs is not None
 
     @property
     def n(self):
@@ -115,8 +121,9 @@ def default_box(pos: torch.Tensor, h: float, skin: float = 0.0):
 
 
 def sph_build_cells(pos: torch.Tensor, h: float, skin: float = 0.0, cells_per_h: int = 1,
-                    box=None, ws: torch.Tensor | None = None) -> CellGrid:
-    """Bin particles into the cell grid (C: sph_build_cells)."""
+                    box=None, ws: torch.Tensor | None = None, pairs: bool = False) -> CellGrid:
+    """Bin particles into the cell grid (C: sph_build_cells); with ``pairs`` also attach
+    the frozen candidate-pair list (C: sph_build_pairs)."""
     _dev(pos)
     n = int(pos.shape[1])
     lo, hi = default_box(pos, h, skin) if box is None else box
@@ -136,7 +143,41 @@ def sph_build_cells(pos: torch.Tensor, h: float, skin: float = 0.0, cells_per_h:
                                     ws.numel(), _stream()))
     grid = CellGrid(perm, cell_start, cell_of, g)
     grid.ws = ws
+    if pairs:
+        sph_build_pairs(grid, pos)
     return grid
+
+
+def sph_build_pairs(grid: CellGrid, pos: torch.Tensor, capacity: int | None = None,
+                    ws: torch.Tensor | None = None) -> int:
+    """Attach a frozen candidate-pair list (radius h + skin of the grid) built at ``pos``
+    (C: sph_build_pairs).  Returns the number of list entries.  Synchronises once."""
+    _dev(pos)
+    n = grid.n
+    dev = pos.device
+    nb = (n + 63) // 64
+    count = torch.empty(n, dtype=torch.int32, device=dev)
+    block_start = torch.empty(nb + 1, dtype=torch.int64, device=dev)
+    x0 = torch.empty(3 * n, dtype=F64, device=dev)
+    if ws is None:
+        ws = workspace(L.SPH_OP_PAIRS, n, 0, dev)
+    needed = C.c_int64()
+    out = L.Pairs()
+    if capacity is None:
+        rc = L.lib().sph_build_pairs(C.byref(grid.c), _ptr(pos[0]), _ptr(pos[1]), _ptr(pos[2]),
+                                     C.byref(out), _ptr(count), _ptr(block_start), C.c_void_p(0), 0,
+                                     _ptr(x0), C.byref(needed), _ptr(ws), ws.numel(), _stream())
+        if rc not in (L.SPH_OK, L.SPH_ERR_CAPACITY):
+            L.check(rc)
+        capacity = int(needed.value)
+    slot = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+    L.check(L.lib().sph_build_pairs(C.byref(grid.c), _ptr(pos[0]), _ptr(pos[1]), _ptr(pos[2]),
+                                    C.byref(out), _ptr(count), _ptr(block_start), _ptr(slot),
+                                    capacity, _ptr(x0), C.byref(needed), _ptr(ws), ws.numel(),
+                                    _stream()))
+    grid.pairs = (out, count, block_start, slot, x0)
+    grid.c.pairs = C.cast(C.pointer(out), C.c_void_p)
+    return int(needed.value)
 
 
 def sph_neighbours(grid: CellGrid, pos: torch.Tensor, h: float, col_cap: int | None = None,

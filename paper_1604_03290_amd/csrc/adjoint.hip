@@ -37,11 +37,13 @@
 
 namespace sph {
 
+// Adjoint operand records, one 128-byte record per slot:
+//   Lbar(9) | abar(3) | rho_sum bar | - - -
+constexpr int kAdj = 16;
+
 struct AdjRec {
     double *L[9];      // forward velocity gradient (slot order)
-    double *Lb[9];     // its cotangent
-    double *ab[3];     // acceleration cotangent (slot order)
-    double *rsb;       // rho_sum cotangent
+    double *arec;      // adjoint records [n][kAdj]
     double *rhob;      // partial density cotangent from the post stage
     double *Stb[6];    // partial cotangent of f_Y S from the rotation terms (stored components)
     double *part_mu;   // per-block partial sums
@@ -51,9 +53,7 @@ struct AdjRec {
 inline AdjRec carve_adj(Carve &c, int64_t n) {
     AdjRec r;
     for (int i = 0; i < 9; ++i) r.L[i] = c.take<double>(n);
-    for (int i = 0; i < 9; ++i) r.Lb[i] = c.take<double>(n);
-    for (int i = 0; i < 3; ++i) r.ab[i] = c.take<double>(n);
-    r.rsb = c.take<double>(n);
+    r.arec = c.take<double>((size_t)n * kAdj);
     r.rhob = c.take<double>(n);
     for (int i = 0; i < 6; ++i) r.Stb[i] = c.take<double>(n);
     r.part_mu = c.take<double>(blocks_for(n));
@@ -73,42 +73,37 @@ __device__ inline void put(double *p, int i, double v, int acc) {
 }
 
 // forward velocity gradient of every slot
-__global__ __launch_bounds__(kBlock) void k_adj_L(GridDev g, int64_t n, Consts k, Rec64 rec,
-                                                  AdjRec ad) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kBlock) void k_adj_L(GridDev g, int64_t n, Consts k,
+                                                  const double *__restrict__ rec, AdjRec ad) {
+    const int64_t s = xcd_block(gridDim.x) * kBlock + threadIdx.x;
     if (s >= n) return;
-    const double xa = rec.x[s], ya = rec.y[s], za = rec.z[s];
-    const double vxa = rec.vx[s], vya = rec.vy[s], vza = rec.vz[s];
+    const double2 *ra = rec2(rec, s);
+    const double2 p0 = ra[0], p1 = ra[1], p2 = ra[2];
+    const double xa = p0.x, ya = p0.y, za = p1.x, vxa = p1.y, vya = p2.x, vza = p2.y;
     double L[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for_each_row(g, xa, ya, za, k.reach, [&](int s0, int s1) {
-        for (int t = s0; t < s1; ++t) {
-            const double d2 = dist2_exact(xa, ya, za, rec.x[t], rec.y[t], rec.z[t]);
-            if (!(d2 < k.h2) || t == s) continue;
-            const double r = sqrt(d2);
-            const double q = r * k.inv_h;
-            double f;
-            if (q < 0.5) {
-                f = 3.0 * q - 2.0;
-            } else {
-                const double u = 1.0 - q;
-                f = -u * u / q;
-            }
-            const double F = k.Fn * f;
-            const double gx = F * (xa - rec.x[t]), gy = F * (ya - rec.y[t]), gz = F * (za - rec.z[t]);
-            const double V = rec.V[t];
-            const double tx = V * (rec.vx[t] - vxa), ty = V * (rec.vy[t] - vya), tz = V * (rec.vz[t] - vza);
-            L[0] += tx * gx; L[1] += tx * gy; L[2] += tx * gz;
-            L[3] += ty * gx; L[4] += ty * gy; L[5] += ty * gz;
-            L[6] += tz * gx; L[7] += tz * gy; L[8] += tz * gz;
-        }
+    for_each_candidate(g, s, xa, ya, za, k.reach, [&](int t) {
+        const double2 *rb = rec2(rec, t);
+        const double2 b0 = rb[0], b1 = rb[1];
+        const double d2 = dist2_exact(xa, ya, za, b0.x, b0.y, b1.x);
+        if (!(d2 < k.h2)) return;
+        const double2 b2 = rb[2], b7 = rb[7];
+        const KernelPieces kp = kernel_pieces(k, d2, rsqrt64(d2));
+        const double F = k.Fn * kp.f;
+        const double gx = F * (xa - b0.x), gy = F * (ya - b0.y), gz = F * (za - b1.x);
+        const double V = b7.x;
+        const double tx = V * (b1.y - vxa), ty = V * (b2.x - vya), tz = V * (b2.y - vza);
+        L[0] = fma(tx, gx, L[0]); L[1] = fma(tx, gy, L[1]); L[2] = fma(tx, gz, L[2]);
+        L[3] = fma(ty, gx, L[3]); L[4] = fma(ty, gy, L[4]); L[5] = fma(ty, gz, L[5]);
+        L[6] = fma(tz, gx, L[6]); L[7] = fma(tz, gy, L[7]); L[8] = fma(tz, gz, L[8]);
     });
 #pragma unroll
     for (int i = 0; i < 9; ++i) ad.L[i][s] = L[i];
 }
 
 // post stage (see the file header)
-__global__ __launch_bounds__(kBlock) void k_adj_post(GridDev g, int64_t n, Consts k, Rec64 rec,
-                                                     StateDev st, CotDev cot, AdjRec ad) {
+__global__ __launch_bounds__(kBlock) void k_adj_post(GridDev g, int64_t n, Consts k,
+                                                     const double *__restrict__ rec, StateDev st,
+                                                     CotDev cot, AdjRec ad) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double mu_part = 0.0;
     if (s < n) {
@@ -116,7 +111,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_post(GridDev g, int64_t n, Const
         double L[3][3];
 #pragma unroll
         for (int i = 0; i < 9; ++i) L[i / 3][i % 3] = ad.L[i][s];
-        const double rho = rec.rho[s];
+        const double rho = rec[s * kRec + 6];
         double S[6] = {st.sxx[a], st.syy[a], st.szz[a], st.sxy[a], st.sxz[a], st.syz[a]};
         const double f = yield_factor(k, S);
         const double St[3][3] = {{f * S[0], f * S[3], f * S[4]},
@@ -135,6 +130,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_post(GridDev g, int64_t n, Const
         for (int i = 0; i < 3; ++i)
 #pragma unroll
             for (int j = 0; j < 3; ++j) R[i][j] = 0.5 * (L[i][j] - L[j][i]);
+        double Lb[9];
         double mu_b = 0.0;
 #pragma unroll
         for (int i = 0; i < 3; ++i)
@@ -144,8 +140,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_post(GridDev g, int64_t n, Const
                 double P = 0.0;  // (G S~ - S~ G)_ij
 #pragma unroll
                 for (int m = 0; m < 3; ++m) P += G[i][m] * St[m][j] - St[i][m] * G[m][j];
-                const double Lb = (i == j ? -rho * rdot : 0.0) + 2.0 * k.mu * D + P;
-                ad.Lb[3 * i + j][s] = Lb;
+                Lb[3 * i + j] = (i == j ? -rho * rdot : 0.0) + 2.0 * k.mu * D + P;
                 mu_b += 2.0 * D * L[i][j];
             }
         mu_part = mu_b;
@@ -166,10 +161,15 @@ __global__ __launch_bounds__(kBlock) void k_adj_post(GridDev g, int64_t n, Const
         ad.Stb[3][s] = Sb[0][1] + Sb[1][0];
         ad.Stb[4][s] = Sb[0][2] + Sb[2][0];
         ad.Stb[5][s] = Sb[1][2] + Sb[2][1];
-        ad.ab[0][s] = ld(cot.ax, a);
-        ad.ab[1][s] = ld(cot.ay, a);
-        ad.ab[2][s] = ld(cot.az, a);
-        ad.rsb[s] = ld(cot.rho_sum, a);
+        double2 *o = reinterpret_cast<double2 *>(ad.arec + s * kAdj);
+        o[0] = make_double2(Lb[0], Lb[1]);
+        o[1] = make_double2(Lb[2], Lb[3]);
+        o[2] = make_double2(Lb[4], Lb[5]);
+        o[3] = make_double2(Lb[6], Lb[7]);
+        o[4] = make_double2(Lb[8], ld(cot.ax, a));
+        o[5] = make_double2(ld(cot.ay, a), ld(cot.az, a));
+        o[6] = make_double2(ld(cot.rho_sum, a), 0.0);
+        o[7] = make_double2(0.0, 0.0);
     }
     const double tot = block_sum(mu_part);
     if (threadIdx.x == 0) ad.part_mu[blockIdx.x] = tot;
@@ -181,92 +181,87 @@ struct AdjAcc {
 };
 
 // pair stage + pre stage (see the file header)
-__global__ __launch_bounds__(kBlock) void k_adj_pairs(GridDev g, int64_t n, Consts k, Rec64 rec,
-                                                      StateDev st, AdjRec ad, GradDev out) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kBlock) void k_adj_pairs(GridDev g, int64_t n, Consts k,
+                                                      const double *__restrict__ rec, StateDev st,
+                                                      AdjRec ad, GradDev out) {
+    const int64_t s = xcd_block(gridDim.x) * kBlock + threadIdx.x;
     double y0_part = 0.0;
     if (s < n) {
-        const double xc = rec.x[s], yc = rec.y[s], zc = rec.z[s];
-        const double vxc = rec.vx[s], vyc = rec.vy[s], vzc = rec.vz[s];
-        const double rc = rec.rho[s], mc = rec.m[s], Vc = rec.V[s];
-        double Tc[6], Lbc[9];
-#pragma unroll
-        for (int i = 0; i < 6; ++i) Tc[i] = rec.t[i][s];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) Lbc[i] = ad.Lb[i][s];
-        const double abx = ad.ab[0][s], aby = ad.ab[1][s], abz = ad.ab[2][s];
-        const double rsc = ad.rsb[s];
+        const double2 *ra = rec2(rec, s);
+        const double2 p0 = ra[0], p1 = ra[1], p2 = ra[2], p3 = ra[3], p4 = ra[4], p5 = ra[5],
+                      p6 = ra[6], p7 = ra[7];
+        const double xc = p0.x, yc = p0.y, zc = p1.x, vxc = p1.y, vyc = p2.x, vzc = p2.y;
+        const double rc = p3.x, mc = p3.y, Vc = p7.x;
+        const double Tc[6] = {p4.x, p4.y, p5.x, p5.y, p6.x, p6.y};
+        const double2 *qa = reinterpret_cast<const double2 *>(ad.arec + s * kAdj);
+        const double2 q0 = qa[0], q1 = qa[1], q2 = qa[2], q3 = qa[3], q4 = qa[4], q5 = qa[5],
+                      q6 = qa[6];
+        const double Lbc[9] = {q0.x, q0.y, q1.x, q1.y, q2.x, q2.y, q3.x, q3.y, q4.x};
+        const double abx = q4.y, aby = q5.x, abz = q5.y, rsc = q6.x;
         const double Gn = k.Fn * k.inv_h * k.inv_h;
         AdjAcc acc;
-        for_each_row(g, xc, yc, zc, k.reach, [&](int s0, int s1) {
-            for (int t = s0; t < s1; ++t) {
-                const double d2 = dist2_exact(xc, yc, zc, rec.x[t], rec.y[t], rec.z[t]);
-                if (!(d2 < k.h2) || t == s) continue;
-                const double rx = xc - rec.x[t], ry = yc - rec.y[t], rz = zc - rec.z[t];
-                const double ux = rec.vx[t] - vxc, uy = rec.vy[t] - vyc, uz = rec.vz[t] - vzc;
-                const double rb = rec.rho[t], mb = rec.m[t], Vb = rec.V[t];
-                const double r = sqrt(d2);
-                const double q = r * k.inv_h;
-                double f, G;
-                if (q < 0.5) {
-                    f = 3.0 * q - 2.0;
-                    G = q > 0.0 ? 3.0 * Gn / q : 0.0;
-                } else {
-                    const double u1 = 1.0 - q;
-                    f = -u1 * u1 / q;
-                    G = Gn * (1.0 - q * q) / (q * q * q);
-                }
-                const double F = k.Fn * f;
-                const double gx = F * rx, gy = F * ry, gz = F * rz;
-                const double Ax = mb * abx - mc * ad.ab[0][t];
-                const double Ay = mb * aby - mc * ad.ab[1][t];
-                const double Az = mb * abz - mc * ad.ab[2][t];
-                double Lbb[9], M[9];
+        for_each_candidate(g, s, xc, yc, zc, k.reach, [&](int t) {
+            const double2 *rb = rec2(rec, t);
+            const double2 b0 = rb[0], b1 = rb[1];
+            const double d2 = dist2_exact(xc, yc, zc, b0.x, b0.y, b1.x);
+            if (!(d2 < k.h2)) return;
+            const double2 b2 = rb[2], b3 = rb[3], b4 = rb[4], b5 = rb[5], b6 = rb[6], b7 = rb[7];
+            const double2 *qb = reinterpret_cast<const double2 *>(ad.arec + (int64_t)t * kAdj);
+            const double2 e0 = qb[0], e1 = qb[1], e2 = qb[2], e3 = qb[3], e4 = qb[4], e5 = qb[5],
+                          e6 = qb[6];
+            const double Lbb[9] = {e0.x, e0.y, e1.x, e1.y, e2.x, e2.y, e3.x, e3.y, e4.x};
+            const double rx = xc - b0.x, ry = yc - b0.y, rz = zc - b1.x;
+            const double ux = b1.y - vxc, uy = b2.x - vyc, uz = b2.y - vzc;
+            const double rb_ = b3.x, mb = b3.y, Vb = b7.x;
+            const double ir = rsqrt64(d2);
+            const KernelPieces kp = kernel_pieces(k, d2, ir);
+            // G = F'(r) / r:  3 Gn / q inside, Gn (1 - q^2) / q^3 outside (0 at r = 0)
+            const double iq = k.h * ir;
+            const double Gi = 3.0 * Gn * iq;
+            const double Go = Gn * (1.0 - kp.q * kp.q) * iq * iq * iq;
+            const double G = d2 > 0.0 ? (kp.inner ? Gi : Go) : 0.0;
+            const double F = k.Fn * kp.f;
+            const double gx = F * rx, gy = F * ry, gz = F * rz;
+            const double Ax = mb * abx - mc * e4.y;
+            const double Ay = mb * aby - mc * e5.x;
+            const double Az = mb * abz - mc * e5.y;
+            double M[9];
 #pragma unroll
-                for (int i = 0; i < 9; ++i) {
-                    Lbb[i] = ad.Lb[i][t];
-                    M[i] = Vb * Lbc[i] + Vc * Lbb[i];
-                }
-                const double w = -(ux * rx + uy * ry + uz * rz);
-                double Pi = 0.0, nu = 0.0, D = 1.0, coef = 0.0;
-                if (w < 0.0) {
-                    D = d2 + k.epsh2;
-                    nu = k.h * w / D;
-                    coef = 2.0 / (rc + rb);
-                    Pi = (-k.alpha_c * nu + k.beta * nu * nu) * coef;
-                }
-                const double B0 = Tc[0] + rec.t[0][t] - Pi, B1 = Tc[1] + rec.t[1][t] - Pi;
-                const double B2 = Tc[2] + rec.t[2][t] - Pi, B3 = Tc[3] + rec.t[3][t];
-                const double B4 = Tc[4] + rec.t[4][t], B5 = Tc[5] + rec.t[5][t];
-                const double gbx = M[0] * ux + M[3] * uy + M[6] * uz + B0 * Ax + B3 * Ay + B4 * Az;
-                const double gby = M[1] * ux + M[4] * uy + M[7] * uz + B3 * Ax + B1 * Ay + B5 * Az;
-                const double gbz = M[2] * ux + M[5] * uy + M[8] * uz + B4 * Ax + B5 * Ay + B2 * Az;
-                const double Pib = -(Ax * gx + Ay * gy + Az * gz);
-                double wb = 0.0, r2b = 0.0;
-                if (w < 0.0) {
-                    const double nub = Pib * (-k.alpha_c + 2.0 * k.beta * nu) * coef;
-                    wb = nub * k.h / D;
-                    r2b = -nub * nu / D;
-                    acc.grho += -Pib * Pi / (rc + rb);
-                }
-                const double rsw = rsc * mb + ad.rsb[t] * mc;
-                const double rg = rx * gbx + ry * gby + rz * gbz;
-                acc.gx += rsw * gx + F * gbx + G * rg * rx - wb * ux + 2.0 * r2b * rx;
-                acc.gy += rsw * gy + F * gby + G * rg * ry - wb * uy + 2.0 * r2b * ry;
-                acc.gz += rsw * gz + F * gbz + G * rg * rz - wb * uz + 2.0 * r2b * rz;
-                acc.gvx += -(M[0] * gx + M[1] * gy + M[2] * gz) + wb * rx;
-                acc.gvy += -(M[3] * gx + M[4] * gy + M[5] * gz) + wb * ry;
-                acc.gvz += -(M[6] * gx + M[7] * gy + M[8] * gz) + wb * rz;
-                acc.gT[0] += Ax * gx;
-                acc.gT[1] += Ay * gy;
-                acc.gT[2] += Az * gz;
-                acc.gT[3] += Ax * gy + Ay * gx;
-                acc.gT[4] += Ax * gz + Az * gx;
-                acc.gT[5] += Ay * gz + Az * gy;
-                acc.gV += ux * (Lbb[0] * gx + Lbb[1] * gy + Lbb[2] * gz) +
-                          uy * (Lbb[3] * gx + Lbb[4] * gy + Lbb[5] * gz) +
-                          uz * (Lbb[6] * gx + Lbb[7] * gy + Lbb[8] * gz);
+            for (int i = 0; i < 9; ++i) M[i] = Vb * Lbc[i] + Vc * Lbb[i];
+            const double w = -(ux * rx + uy * ry + uz * rz);
+            const Visc vs = viscosity(k, d2, w, rc, rb_);
+            const double Pi = vs.Pi;
+            const double B0 = Tc[0] + b4.x - Pi, B1 = Tc[1] + b4.y - Pi;
+            const double B2 = Tc[2] + b5.x - Pi, B3 = Tc[3] + b5.y;
+            const double B4 = Tc[4] + b6.x, B5 = Tc[5] + b6.y;
+            const double gbx = M[0] * ux + M[3] * uy + M[6] * uz + B0 * Ax + B3 * Ay + B4 * Az;
+            const double gby = M[1] * ux + M[4] * uy + M[7] * uz + B3 * Ax + B1 * Ay + B5 * Az;
+            const double gbz = M[2] * ux + M[5] * uy + M[8] * uz + B4 * Ax + B5 * Ay + B2 * Az;
+            const double Pib = -(Ax * gx + Ay * gy + Az * gz);
+            double wb = 0.0, r2b = 0.0;
+            if (w < 0.0) {
+                const double nub = Pib * (-k.alpha_c + 2.0 * k.beta * vs.nu) * vs.coef;
+                wb = nub * k.h * vs.invD;
+                r2b = -nub * vs.nu * vs.invD;
+                acc.grho -= Pib * Pi * 0.5 * vs.coef;  // Pi / (rho_c + rho_b)
             }
+            const double rsw = rsc * mb + e6.x * mc;
+            const double rg = rx * gbx + ry * gby + rz * gbz;
+            acc.gx += rsw * gx + F * gbx + G * rg * rx - wb * ux + 2.0 * r2b * rx;
+            acc.gy += rsw * gy + F * gby + G * rg * ry - wb * uy + 2.0 * r2b * ry;
+            acc.gz += rsw * gz + F * gbz + G * rg * rz - wb * uz + 2.0 * r2b * rz;
+            acc.gvx += -(M[0] * gx + M[1] * gy + M[2] * gz) + wb * rx;
+            acc.gvy += -(M[3] * gx + M[4] * gy + M[5] * gz) + wb * ry;
+            acc.gvz += -(M[6] * gx + M[7] * gy + M[8] * gz) + wb * rz;
+            acc.gT[0] += Ax * gx;
+            acc.gT[1] += Ay * gy;
+            acc.gT[2] += Az * gz;
+            acc.gT[3] += Ax * gy + Ay * gx;
+            acc.gT[4] += Ax * gz + Az * gx;
+            acc.gT[5] += Ay * gz + Az * gy;
+            acc.gV += ux * (Lbb[0] * gx + Lbb[1] * gy + Lbb[2] * gz) +
+                      uy * (Lbb[3] * gx + Lbb[4] * gy + Lbb[5] * gz) +
+                      uz * (Lbb[6] * gx + Lbb[7] * gy + Lbb[8] * gz);
         });
         // pre stage: T = (f S - p I) / rho^2, V = m / rho, pressure, limiter
         const int a = g.perm[s];
@@ -346,7 +341,7 @@ int reduce_params_launch(const double *p0, const double *p1, int64_t m, double *
 
 size_t adjoint_ws_bytes(int64_t n) {
     Carve c(nullptr);
-    carve_rec64(c, n);
+    c.take<double>((size_t)n * kRec);
     carve_adj(c, n);
     return c.used;
 }
@@ -369,13 +364,16 @@ int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_p
     const int64_t n = grid->n;
     GridDev g = grid_dev(grid);
     Consts k = make_consts(*params, g.delta);
-    Rec64 rec = carve_rec64(c, n);
+    double *rec = c.take<double>((size_t)n * kRec);
     AdjRec ad = carve_adj(c, n);
     StateDev st = state_dev(state);
     int rc = prepass_launch(g, st, n, k, rec, c.status(), s);
     if (rc) return rc;
-    k_adj_L<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, ad);
-    SPH_LAUNCHED();
+    {
+        TimedRegion t("adjoint_L", s);
+        k_adj_L<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, ad);
+        SPH_LAUNCHED();
+    }
     k_adj_post<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, cot, ad);
     SPH_LAUNCHED();
     {

@@ -25,6 +25,7 @@ size_t rhs_ws_bytes(int64_t n);
 size_t adjoint_ws_bytes(int64_t n);
 size_t leapfrog_ws_bytes(int64_t n);
 size_t leapfrog_adjoint_ws_bytes(int64_t n);
+size_t pairs_ws_bytes(int64_t n);
 
 }  // namespace sph
 
@@ -44,6 +45,7 @@ extern "C" size_t sph_workspace_bytes(int op, int64_t n, int64_t ncells) {
         case SPH_OP_ADJOINT: return adjoint_ws_bytes(n);
         case SPH_OP_LEAPFROG: return leapfrog_ws_bytes(n);
         case SPH_OP_LEAPFROG_ADJOINT: return leapfrog_adjoint_ws_bytes(n);
+        case SPH_OP_PAIRS: return pairs_ws_bytes(n);
         default: return 0;
     }
 }

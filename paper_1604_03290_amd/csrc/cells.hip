@@ -153,6 +153,7 @@ extern "C" int sph_build_cells(const double *x, const double *y, const double *z
     grid_out->perm = perm;
     grid_out->cell_start = cell_start;
     grid_out->cell_of = cell_of;
+    grid_out->pairs = nullptr;
     if (ncells > ncells_cap)
         return fail(SPH_ERR_CAPACITY, "grid needs %lld cells, capacity %lld", (long long)ncells,
                     (long long)ncells_cap);

@@ -65,6 +65,12 @@ struct GridDev {
     const int32_t *__restrict__ perm;
     const int32_t *__restrict__ cell_start;
     const int32_t *__restrict__ cell_of;
+    // frozen candidate-pair list (null count = none)
+    const int32_t *__restrict__ pl_count;
+    const int64_t *__restrict__ pl_block;
+    const int32_t *__restrict__ pl_slot;
+    const double *__restrict__ pl_x0;
+    double pl_delta;  // tolerated movement since the list was built
 };
 
 inline GridDev grid_dev(const sph_grid *g) {
@@ -81,6 +87,11 @@ inline GridDev grid_dev(const sph_grid *g) {
     d.perm = g->perm;
     d.cell_start = g->cell_start;
     d.cell_of = g->cell_of;
+    d.pl_count = g->pairs ? g->pairs->count : nullptr;
+    d.pl_block = g->pairs ? g->pairs->block_start : nullptr;
+    d.pl_slot = g->pairs ? g->pairs->slot : nullptr;
+    d.pl_x0 = g->pairs ? g->pairs->x0 : nullptr;
+    d.pl_delta = g->pairs ? 0.5 * g->pairs->skin : 0.0;
     return d;
 }
 
@@ -114,6 +125,21 @@ __device__ inline double dist2_exact(double xa, double ya, double za, double xb,
     return (dx * dx + dy * dy) + dz * dz;
 }
 
+// Slot of logical workgroup for a 1-D launch of nblocks workgroups: the
+// dispatcher deals workgroups to the 8 XCDs round robin; this remap gives each
+// XCD one contiguous range of slots (neighbouring cells share its L2).
+__device__ inline int64_t xcd_block(int64_t nblocks) {
+    const int64_t i = blockIdx.x;
+    const int64_t x = i & 7, q = nblocks >> 3, r = nblocks & 7;
+    return x * q + (x < r ? x : r) + (i >> 3);
+}
+
+// Calls f(t) for every candidate slot t != s of slot s: from the pair list when
+// the grid has one, otherwise by sweeping the cell rows within reach.
+template <class F>
+__device__ inline void for_each_candidate(const GridDev &g, int64_t s, double xa, double ya,
+                                          double za, double reach, F &&f);
+
 // Visits the slot ranges [s0, s1) of every cell row whose box comes within
 // `reach` of p (rows in y-z, a contiguous run of cells along x per row).
 // A partner b of a target at p (|x_b - p| < h) lies within delta of its cell's
@@ -143,9 +169,15 @@ __device__ inline void for_each_row(const GridDev &g, double px, double py, doub
     }
 }
 
-// Slot -> box check: the current position of slot s must lie within delta of
-// the box of the cell it was binned into.
+// Staleness check of slot s at its current position: with a pair list, the
+// particle must lie within the list's skin / 2 of its position when the list
+// was built; otherwise within delta of the box of the cell it was binned into.
 __device__ inline bool within_cell(const GridDev &g, int s, double x, double y, double z) {
+    if (g.pl_count) {
+        const double dx = x - g.pl_x0[3 * s], dy = y - g.pl_x0[3 * s + 1], dz = z - g.pl_x0[3 * s + 2];
+        const double lim = g.pl_delta * (1.0 - 1e-9);
+        return dx * dx + dy * dy + dz * dz <= lim * lim;
+    }
     const int c = g.cell_of[s];
     const int ix = c % g.nx;
     const int iy = (c / g.nx) % g.ny;
@@ -154,6 +186,21 @@ __device__ inline bool within_cell(const GridDev &g, int s, double x, double y, 
     return slab_gap(x, g.lox, g.cell, ix, g.nx) <= lim &&
            slab_gap(y, g.loy, g.cell, iy, g.ny) <= lim &&
            slab_gap(z, g.loz, g.cell, iz, g.nz) <= lim;
+}
+
+template <class F>
+__device__ inline void for_each_candidate(const GridDev &g, int64_t s, double xa, double ya,
+                                          double za, double reach, F &&f) {
+    if (g.pl_count) {
+        const int c = g.pl_count[s];
+        const int32_t *p = g.pl_slot + g.pl_block[s >> 6] + (s & 63);
+        for (int j = 0; j < c; ++j) f(p[(int64_t)j << 6]);
+    } else {
+        for_each_row(g, xa, ya, za, reach, [&](int s0, int s1) {
+            for (int t = s0; t < s1; ++t)
+                if (t != s) f(t);
+        });
+    }
 }
 
 // ------------------------------------------------------------ B-spline, 3-D --

@@ -25,7 +25,8 @@ namespace {
 
 // --------------------------------------------------------------- prepass --
 __global__ __launch_bounds__(kBlock) void k_prepass(GridDev g, StateDev st, int64_t n, Consts k,
-                                                    Rec64 rec, int32_t *__restrict__ status) {
+                                                    double *__restrict__ rec,
+                                                    int32_t *__restrict__ status) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int a = g.perm[s];
@@ -37,99 +38,91 @@ __global__ __launch_bounds__(kBlock) void k_prepass(GridDev g, StateDev st, int6
     const double p = pressure(k, rho);
     const double f = yield_factor(k, S);
     const double ir2 = 1.0 / (rho * rho);
-    rec.x[s] = x;
-    rec.y[s] = y;
-    rec.z[s] = z;
-    rec.vx[s] = st.vx[a];
-    rec.vy[s] = st.vy[a];
-    rec.vz[s] = st.vz[a];
-    rec.rho[s] = rho;
-    rec.t[0][s] = (f * S[0] - p) * ir2;
-    rec.t[1][s] = (f * S[1] - p) * ir2;
-    rec.t[2][s] = (f * S[2] - p) * ir2;
-    rec.t[3][s] = f * S[3] * ir2;
-    rec.t[4][s] = f * S[4] * ir2;
-    rec.t[5][s] = f * S[5] * ir2;
     const double m = st.m[a];
-    rec.m[s] = m;
-    rec.V[s] = m / rho;
+    double2 *r = reinterpret_cast<double2 *>(rec + s * kRec);
+    r[0] = make_double2(x, y);
+    r[1] = make_double2(z, st.vx[a]);
+    r[2] = make_double2(st.vy[a], st.vz[a]);
+    r[3] = make_double2(rho, m);
+    r[4] = make_double2((f * S[0] - p) * ir2, (f * S[1] - p) * ir2);
+    r[5] = make_double2((f * S[2] - p) * ir2, f * S[3] * ir2);
+    r[6] = make_double2(f * S[4] * ir2, f * S[5] * ir2);
+    r[7] = make_double2(m / rho, 0.0);
 }
 
 // FP32 copies of the pair operands (positions stay FP64 for the exact test)
-__global__ __launch_bounds__(kBlock) void k_narrow(Rec64 rec, int64_t n, Rec32 r32) {
+__global__ __launch_bounds__(kBlock) void k_narrow(const double *__restrict__ rec, int64_t n,
+                                                   float *__restrict__ r32) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
-    r32.vx[s] = (float)rec.vx[s];
-    r32.vy[s] = (float)rec.vy[s];
-    r32.vz[s] = (float)rec.vz[s];
-    r32.rho[s] = (float)rec.rho[s];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) r32.t[c][s] = (float)rec.t[c][s];
-    r32.m[s] = (float)rec.m[s];
-    r32.V[s] = (float)rec.V[s];
+    const double *r = rec + s * kRec;
+    float4 *o = reinterpret_cast<float4 *>(r32 + s * kRec32);
+    o[0] = make_float4((float)r[3], (float)r[4], (float)r[5], (float)r[6]);
+    o[1] = make_float4((float)r[7], (float)r[14], (float)r[8], (float)r[9]);
+    o[2] = make_float4((float)r[10], (float)r[11], (float)r[12], (float)r[13]);
 }
 
 // ---------------------------------------------------------- pairs, FP64 --
-__global__ __launch_bounds__(kBlock) void k_pairs64(GridDev g, int64_t n, Consts k, Rec64 rec,
-                                                    StateDev st, OutDev out) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kBlock) void k_pairs64(GridDev g, int64_t n, Consts k,
+                                                    const double *__restrict__ rec, StateDev st,
+                                                    OutDev out) {
+    const int64_t s = xcd_block(gridDim.x) * kBlock + threadIdx.x;
     if (s >= n) return;
-    const double xa = rec.x[s], ya = rec.y[s], za = rec.z[s];
-    const double vxa = rec.vx[s], vya = rec.vy[s], vza = rec.vz[s];
-    const double ra = rec.rho[s];
-    const double ta0 = rec.t[0][s], ta1 = rec.t[1][s], ta2 = rec.t[2][s];
-    const double ta3 = rec.t[3][s], ta4 = rec.t[4][s], ta5 = rec.t[5][s];
+    const double2 *ra = rec2(rec, s);
+    const double2 p0 = ra[0], p1 = ra[1], p2 = ra[2], p3 = ra[3], p4 = ra[4], p5 = ra[5], p6 = ra[6];
+    const double xa = p0.x, ya = p0.y, za = p1.x, vxa = p1.y, vya = p2.x, vza = p2.y;
+    const double rho_a = p3.x;
     Acc64 acc;
-    acc.rs = rec.m[s] * k.Wn;  // own term m_a W(0)
-    for_each_row(g, xa, ya, za, k.reach, [&](int s0, int s1) {
-        for (int t = s0; t < s1; ++t) {
-            const double xb = rec.x[t], yb = rec.y[t], zb = rec.z[t];
-            const double d2 = dist2_exact(xa, ya, za, xb, yb, zb);
-            if (!(d2 < k.h2) || t == s) continue;
-            pair64(k, d2, xa - xb, ya - yb, za - zb, rec.vx[t] - vxa, rec.vy[t] - vya,
-                   rec.vz[t] - vza, ra, rec.rho[t], ta0 + rec.t[0][t], ta1 + rec.t[1][t],
-                   ta2 + rec.t[2][t], ta3 + rec.t[3][t], ta4 + rec.t[4][t], ta5 + rec.t[5][t],
-                   rec.m[t], rec.V[t], acc);
-        }
+    acc.rs = p3.y * k.Wn;  // own term m_a W(0)
+    for_each_candidate(g, s, xa, ya, za, k.reach, [&](int t) {
+        const double2 *rb = rec2(rec, t);
+        const double2 b0 = rb[0], b1 = rb[1];
+        const double d2 = dist2_exact(xa, ya, za, b0.x, b0.y, b1.x);
+        if (!(d2 < k.h2)) return;
+        const double2 b2 = rb[2], b3 = rb[3], b4 = rb[4], b5 = rb[5], b6 = rb[6], b7 = rb[7];
+        pair64(k, d2, xa - b0.x, ya - b0.y, za - b1.x, b1.y - vxa, b2.x - vya, b2.y - vza, rho_a,
+               b3.x, p4.x + b4.x, p4.y + b4.y, p5.x + b5.x, p5.y + b5.y, p6.x + b6.x, p6.y + b6.y,
+               b3.y, b7.x, acc);
     });
-    postpass(k, g.perm[s], ra, acc.L, acc.ax, acc.ay, acc.az, acc.rs, st, out);
+    postpass(k, g.perm[s], rho_a, acc.L, acc.ax, acc.ay, acc.az, acc.rs, st, out);
 }
 
 // ----------------------------------------- pairs, FP32 + Kahan sums --
-__global__ __launch_bounds__(kBlock) void k_pairs32(GridDev g, int64_t n, Consts k, Rec64 rec,
-                                                    Rec32 r32, StateDev st, OutDev out) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kBlock) void k_pairs32(GridDev g, int64_t n, Consts k,
+                                                    const double *__restrict__ rec,
+                                                    const float *__restrict__ r32, StateDev st,
+                                                    OutDev out) {
+    const int64_t s = xcd_block(gridDim.x) * kBlock + threadIdx.x;
     if (s >= n) return;
-    const double xa = rec.x[s], ya = rec.y[s], za = rec.z[s];
-    const float vxa = r32.vx[s], vya = r32.vy[s], vza = r32.vz[s];
-    const float ra = r32.rho[s];
-    const float ta0 = r32.t[0][s], ta1 = r32.t[1][s], ta2 = r32.t[2][s];
-    const float ta3 = r32.t[3][s], ta4 = r32.t[4][s], ta5 = r32.t[5][s];
+    const double2 *ra = rec2(rec, s);
+    const double2 p0 = ra[0], p1 = ra[1], p3 = ra[3];
+    const double xa = p0.x, ya = p0.y, za = p1.x;
+    const float4 *fa = rec4(r32, s);
+    const float4 o0 = fa[0], o1 = fa[1], o2 = fa[2];
     const Consts32 kf = narrow(k);
     Acc32 acc;
-    for_each_row(g, xa, ya, za, k.reach, [&](int s0, int s1) {
-        for (int t = s0; t < s1; ++t) {
-            const double xb = rec.x[t], yb = rec.y[t], zb = rec.z[t];
-            const double d2 = dist2_exact(xa, ya, za, xb, yb, zb);
-            if (!(d2 < k.h2) || t == s) continue;
-            pair32(kf, (float)d2, (float)(xa - xb), (float)(ya - yb), (float)(za - zb),
-                   r32.vx[t] - vxa, r32.vy[t] - vya, r32.vz[t] - vza, ra, r32.rho[t],
-                   ta0 + r32.t[0][t], ta1 + r32.t[1][t], ta2 + r32.t[2][t], ta3 + r32.t[3][t],
-                   ta4 + r32.t[4][t], ta5 + r32.t[5][t], r32.m[t], r32.V[t], acc);
-        }
+    for_each_candidate(g, s, xa, ya, za, k.reach, [&](int t) {
+        const double2 *rb = rec2(rec, t);
+        const double2 b0 = rb[0], b1 = rb[1];
+        const double d2 = dist2_exact(xa, ya, za, b0.x, b0.y, b1.x);
+        if (!(d2 < k.h2)) return;
+        const float4 *fb = rec4(r32, t);
+        const float4 c0 = fb[0], c1 = fb[1], c2 = fb[2];
+        pair32(kf, (float)d2, (float)(xa - b0.x), (float)(ya - b0.y), (float)(za - b1.x),
+               c0.x - o0.x, c0.y - o0.y, c0.z - o0.z, o0.w, c0.w, o1.z + c1.z, o1.w + c1.w,
+               o2.x + c2.x, o2.y + c2.y, o2.z + c2.z, o2.w + c2.w, c1.x, c1.y, acc);
     });
     double L[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) L[c] = acc.L[c].value();
-    const double rs = rec.m[s] * k.Wn + acc.rs.value();
-    postpass(k, g.perm[s], rec.rho[s], L, acc.ax.value(), acc.ay.value(), acc.az.value(), rs, st,
-             out);
+    const double rs = p3.y * k.Wn + acc.rs.value();
+    postpass(k, g.perm[s], p3.x, L, acc.ax.value(), acc.ay.value(), acc.az.value(), rs, st, out);
 }
 
 }  // namespace
 
-int prepass_launch(const GridDev &g, const StateDev &st, int64_t n, const Consts &k,
-                   const Rec64 &rec, int32_t *status, hipStream_t s) {
+int prepass_launch(const GridDev &g, const StateDev &st, int64_t n, const Consts &k, double *rec,
+                   int32_t *status, hipStream_t s) {
     k_prepass<<<blocks_for(n), kBlock, 0, s>>>(g, st, n, k, rec, status);
     SPH_LAUNCHED();
     return SPH_OK;
@@ -137,8 +130,8 @@ int prepass_launch(const GridDev &g, const StateDev &st, int64_t n, const Consts
 
 size_t rhs_ws_bytes(int64_t n) {
     Carve c(nullptr);
-    carve_rec64(c, n);
-    carve_rec32(c, n);
+    c.take<double>((size_t)n * kRec);
+    c.take<float>((size_t)n * kRec32);
     return c.used;
 }
 
@@ -181,8 +174,8 @@ int rhs_launch(const sph_grid *grid, const sph_state *state, const sph_params *p
     const int64_t n = grid->n;
     GridDev g = grid_dev(grid);
     Consts k = make_consts(*params, g.delta);
-    Rec64 rec = carve_rec64(c, n);
-    Rec32 r32 = carve_rec32(c, n);
+    double *rec = c.take<double>((size_t)n * kRec);
+    float *r32 = c.take<float>((size_t)n * kRec32);
     StateDev st = state_dev(state);
     OutDev od = out_dev(out);
     int rc = prepass_launch(g, st, n, k, rec, c.status(), s);

@@ -62,41 +62,21 @@ inline OutDev out_dev(const sph_deriv *o) {
                   o->dszz, o->dsxy, o->dsxz, o->dsyz, o->rho_sum};
 }
 
-// Slot-ordered operands of the pair sums: position, velocity, density,
-// T = sigma / rho^2 (xx, yy, zz, xy, xz, yz), mass, V = m / rho.
-struct Rec64 {
-    double *x, *y, *z, *vx, *vy, *vz, *rho, *t[6], *m, *V;
-};
+// Slot-ordered operand records, one 128-byte record per slot so that a partner
+// is gathered with eight 16-byte loads:
+//   x y z vx | vy vz rho m | T0 T1 T2 T3 | T4 T5 V -
+// with T = sigma / rho^2 (xx, yy, zz, xy, xz, yz) and V = m / rho.
+constexpr int kRec = 16;
+// FP32 copy of the non-position operands, 48 bytes per slot:
+//   vx vy vz rho | m V T0 T1 | T2 T3 T4 T5
+constexpr int kRec32 = 12;
 
-struct Rec32 {
-    float *vx, *vy, *vz, *rho, *t[6], *m, *V;
-};
-
-inline Rec64 carve_rec64(Carve &c, int64_t n) {
-    Rec64 r;
-    r.x = c.take<double>(n);
-    r.y = c.take<double>(n);
-    r.z = c.take<double>(n);
-    r.vx = c.take<double>(n);
-    r.vy = c.take<double>(n);
-    r.vz = c.take<double>(n);
-    r.rho = c.take<double>(n);
-    for (int i = 0; i < 6; ++i) r.t[i] = c.take<double>(n);
-    r.m = c.take<double>(n);
-    r.V = c.take<double>(n);
-    return r;
+__device__ inline const double2 *rec2(const double *rec, int64_t s) {
+    return reinterpret_cast<const double2 *>(rec + s * kRec);
 }
 
-inline Rec32 carve_rec32(Carve &c, int64_t n) {
-    Rec32 r;
-    r.vx = c.take<float>(n);
-    r.vy = c.take<float>(n);
-    r.vz = c.take<float>(n);
-    r.rho = c.take<float>(n);
-    for (int i = 0; i < 6; ++i) r.t[i] = c.take<float>(n);
-    r.m = c.take<float>(n);
-    r.V = c.take<float>(n);
-    return r;
+__device__ inline const float4 *rec4(const float *r32, int64_t s) {
+    return reinterpret_cast<const float4 *>(r32 + s * kRec32);
 }
 
 // Liquid equation of state with the optional tension cut-off (section 2.5.1).
@@ -117,6 +97,67 @@ __device__ inline double yield_factor(const Consts &k, const double S[6]) {
     return j3 > k.Y0sq ? k.Y0sq / j3 : 1.0;
 }
 
+// 1/sqrt(x): hardware estimate refined by two Newton steps y <- y (3 - x y^2) / 2
+// (full double precision); +inf at 0.
+__device__ inline double rsqrt64(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    y = y * fma(-hx, y * y, 1.5);
+    y = y * fma(-hx, y * y, 1.5);
+    return y;
+}
+
+// 1/x: hardware estimate refined by two Newton steps y <- y (2 - x y).
+__device__ inline double rcp64(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+
+// Kernel pieces at distance r (section 3.1.1), branch free: w(q) with
+// W = Wn w, and f(q) with W'(r)/r = Fn f; ir = 1/r (+inf at r = 0, where the
+// inner piece is selected).
+struct KernelPieces {
+    double q, w, f;
+    bool inner;
+};
+
+__device__ inline KernelPieces kernel_pieces(const Consts &k, double d2, double ir) {
+    KernelPieces p;
+    p.q = d2 > 0.0 ? d2 * ir * k.inv_h : 0.0;
+    const double q = p.q;
+    const double u = 1.0 - q, u2 = u * u;
+    const double w_in = fma(q * q, fma(6.0, q, -6.0), 1.0);
+    const double f_in = fma(3.0, q, -2.0);
+    const double w_out = 2.0 * u2 * u;
+    const double f_out = -u2 * (k.h * ir);  // -(1-q)^2 / q
+    p.inner = q < 0.5;
+    p.w = p.inner ? w_in : w_out;
+    p.f = p.inner ? f_in : f_out;
+    return p;
+}
+
+// Artificial viscosity Pi*_ab (section 3.1.3) for w = (v_a - v_b).(x_a - x_b):
+// nu = h w / (r^2 + eps h^2), Pi = (-alpha c nu + beta nu^2) / ((rho_a + rho_b)/2)
+// when w < 0, else 0.  One reciprocal serves both divisions.
+struct Visc {
+    double Pi, nu, invD, coef;
+};
+
+__device__ inline Visc viscosity(const Consts &k, double d2, double w, double ra, double rb) {
+    Visc v;
+    const double D = d2 + k.epsh2, S = ra + rb;
+    const double inv = rcp64(D * S);
+    v.invD = S * inv;        // 1 / D
+    v.coef = 2.0 * D * inv;  // 2 / (rho_a + rho_b)
+    v.nu = k.h * w * v.invD;
+    const double Pi = (-k.alpha_c * v.nu + k.beta * v.nu * v.nu) * v.coef;
+    v.Pi = w < 0.0 ? Pi : 0.0;
+    return v;
+}
+
 struct Acc64 {
     double rs = 0.0;
     double L[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -129,40 +170,27 @@ __device__ inline void pair64(const Consts &k, double d2, double rx, double ry, 
                               double dvx, double dvy, double dvz, double ra, double rb,
                               double Bxx, double Byy, double Bzz, double Bxy, double Bxz,
                               double Byz, double mb, double Vb, Acc64 &a) {
-    const double r = sqrt(d2);
-    const double q = r * k.inv_h;
-    double w, f;
-    if (q < 0.5) {
-        w = 1.0 + q * q * (6.0 * q - 6.0);
-        f = 3.0 * q - 2.0;
-    } else {
-        const double u = 1.0 - q;
-        w = 2.0 * u * u * u;
-        f = -u * u / q;
-    }
-    const double F = k.Fn * f;
+    const double ir = rsqrt64(d2);
+    const KernelPieces kp = kernel_pieces(k, d2, ir);
+    const double F = k.Fn * kp.f;
     const double gx = F * rx, gy = F * ry, gz = F * rz;
-    a.rs += mb * (k.Wn * w);
+    a.rs = fma(mb, k.Wn * kp.w, a.rs);
     const double tx = Vb * dvx, ty = Vb * dvy, tz = Vb * dvz;
-    a.L[0] += tx * gx;
-    a.L[1] += tx * gy;
-    a.L[2] += tx * gz;
-    a.L[3] += ty * gx;
-    a.L[4] += ty * gy;
-    a.L[5] += ty * gz;
-    a.L[6] += tz * gx;
-    a.L[7] += tz * gy;
-    a.L[8] += tz * gz;
+    a.L[0] = fma(tx, gx, a.L[0]);
+    a.L[1] = fma(tx, gy, a.L[1]);
+    a.L[2] = fma(tx, gz, a.L[2]);
+    a.L[3] = fma(ty, gx, a.L[3]);
+    a.L[4] = fma(ty, gy, a.L[4]);
+    a.L[5] = fma(ty, gz, a.L[5]);
+    a.L[6] = fma(tz, gx, a.L[6]);
+    a.L[7] = fma(tz, gy, a.L[7]);
+    a.L[8] = fma(tz, gz, a.L[8]);
     const double wab = -(dvx * rx + dvy * ry + dvz * rz);
-    double Pi = 0.0;
-    if (wab < 0.0) {
-        const double nu = k.h * wab / (d2 + k.epsh2);
-        Pi = (-k.alpha_c * nu + k.beta * nu * nu) * 2.0 / (ra + rb);
-    }
+    const double Pi = viscosity(k, d2, wab, ra, rb).Pi;
     const double bxx = Bxx - Pi, byy = Byy - Pi, bzz = Bzz - Pi;
-    a.ax += mb * (bxx * gx + Bxy * gy + Bxz * gz);
-    a.ay += mb * (Bxy * gx + byy * gy + Byz * gz);
-    a.az += mb * (Bxz * gx + Byz * gy + bzz * gz);
+    a.ax = fma(mb, bxx * gx + Bxy * gy + Bxz * gz, a.ax);
+    a.ay = fma(mb, Bxy * gx + byy * gy + Byz * gz, a.ay);
+    a.az = fma(mb, Bxz * gx + Byz * gy + bzz * gz, a.az);
 }
 
 // Kahan-compensated single-precision sum (Kahan 1965): c carries the low-order
@@ -186,17 +214,12 @@ __device__ inline void pair32(const Consts32 &k, float d2, float rx, float ry, f
                               float dvy, float dvz, float ra, float rb, float Bxx, float Byy,
                               float Bzz, float Bxy, float Bxz, float Byz, float mb, float Vb,
                               Acc32 &a) {
-    const float r = sqrtf(d2);
-    const float q = r * k.inv_h;
-    float w, f;
-    if (q < 0.5f) {
-        w = 1.0f + q * q * (6.0f * q - 6.0f);
-        f = 3.0f * q - 2.0f;
-    } else {
-        const float u = 1.0f - q;
-        w = 2.0f * u * u * u;
-        f = -u * u / q;
-    }
+    const float ir = __builtin_amdgcn_rsqf(d2);
+    const float q = d2 > 0.0f ? d2 * ir * k.inv_h : 0.0f;
+    const float u = 1.0f - q, u2 = u * u;
+    const bool inner = q < 0.5f;
+    const float w = inner ? fmaf(q * q, fmaf(6.0f, q, -6.0f), 1.0f) : 2.0f * u2 * u;
+    const float f = inner ? fmaf(3.0f, q, -2.0f) : -u2 * (k.h * ir);
     const float F = k.Fn * f;
     const float gx = F * rx, gy = F * ry, gz = F * rz;
     a.rs.add(mb * (k.Wn * w));
@@ -211,11 +234,10 @@ __device__ inline void pair32(const Consts32 &k, float d2, float rx, float ry, f
     a.L[7].add(tz * gy);
     a.L[8].add(tz * gz);
     const float wab = -(dvx * rx + dvy * ry + dvz * rz);
-    float Pi = 0.0f;
-    if (wab < 0.0f) {
-        const float nu = k.h * wab / (d2 + k.epsh2);
-        Pi = (-k.alpha_c * nu + k.beta * nu * nu) * 2.0f / (ra + rb);
-    }
+    const float D = d2 + k.epsh2, S = ra + rb;
+    const float inv = __builtin_amdgcn_rcpf(D * S);
+    const float nu = k.h * wab * S * inv;
+    const float Pi = wab < 0.0f ? (-k.alpha_c * nu + k.beta * nu * nu) * 2.0f * D * inv : 0.0f;
     const float bxx = Bxx - Pi, byy = Byy - Pi, bzz = Bzz - Pi;
     a.ax.add(mb * (bxx * gx + Bxy * gy + Bxz * gz));
     a.ay.add(mb * (Bxy * gx + byy * gy + Byz * gz));
@@ -274,9 +296,9 @@ int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_p
 int reduce_params_launch(const double *p0, const double *p1, int64_t m, double *dparams,
                          int accumulate, hipStream_t s);
 
-// host-side helpers shared by the entry points (rhs.hip)
-int prepass_launch(const GridDev &g, const StateDev &st, int64_t n, const Consts &k,
-                   const Rec64 &rec, int32_t *status, hipStream_t s);
+// rhs.hip
+int prepass_launch(const GridDev &g, const StateDev &st, int64_t n, const Consts &k, double *rec,
+                   int32_t *status, hipStream_t s);
 int check_state(const sph_grid *grid, const sph_state *st);
 int check_params(const sph_grid *grid, const sph_params *pr);
 int check_deriv(const sph_deriv *o);

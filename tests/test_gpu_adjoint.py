@@ -38,14 +38,15 @@ def small(name):
 
 
 @pytest.mark.parametrize("name", ["cube10", "cube8_visc", "cube16"])
-def test_rhs_adjoint_matches_oracle(name):
+@pytest.mark.parametrize("pairs", [False, True])
+def test_rhs_adjoint_matches_oracle(name, pairs):
     w = small(name)
     ref_out = native.rhs_workload(w, want_L=False)
     rng = np.random.default_rng(7)
     cot = {k: rng.normal(size=ref_out[k].shape) / np.abs(ref_out[k]).max() for k in ref_out}
     ref = AD.rhs_vjp(w, cot)
     st = gpu_state(w)
-    g = P.sph_build_cells(st.pos, w.h)
+    g = P.sph_build_cells(st.pos, w.h, skin=0.05 * w.dx, pairs=pairs)
     cg = {k: torch.as_tensor(v).cuda().contiguous() for k, v in cot.items()}
     got = P.sph_rhs_adjoint(g, st, w.params, cg)
     assert P.workspace_status(got["_ws"]) == 0
@@ -74,9 +75,9 @@ def test_rhs_adjoint_partial_cotangents():
     assert float(got["mu"]) == 0.0 and np.all(got["vel"].cpu().numpy() == 0.0)
 
 
-def run_leapfrog(w, steps, skin_dx=0.5):
+def run_leapfrog(w, steps, skin_dx=0.5, pairs=True):
     st = gpu_state(w)
-    g = P.sph_build_cells(st.pos, w.h, skin=skin_dx * w.dx)
+    g = P.sph_build_cells(st.pos, w.h, skin=skin_dx * w.dx, pairs=pairs)
     fin, ck = P.sph_leapfrog(g, st, w.params, w.dt, steps)
     assert P.workspace_status(fin._ws) == 0
     return st, g, fin, ck
@@ -95,10 +96,11 @@ def test_leapfrog_matches_oracle_trajectory():
     assert rel(fin.S.cpu().numpy(), s.numpy()) < 1e-11
 
 
-@pytest.mark.parametrize("name,steps", [("cube10", 8), ("cube8_visc", 20)])
-def test_leapfrog_gradient_matches_oracle(name, steps):
+@pytest.mark.parametrize("name,steps,pairs", [("cube10", 8, False), ("cube10", 8, True),
+                                              ("cube8_visc", 20, True)])
+def test_leapfrog_gradient_matches_oracle(name, steps, pairs):
     w = small(name)
-    st, g, fin, ck = run_leapfrog(w, steps)
+    st, g, fin, ck = run_leapfrog(w, steps, pairs=pairs)
     cot = {"vel": (fin.vel * fin.m).contiguous()}  # d KE / d v_final
     got = P.sph_leapfrog_adjoint(g, st, w.params, w.dt, steps, ck, cot)
     assert P.workspace_status(got["_ws"]) == 0
@@ -113,7 +115,7 @@ def test_leapfrog_gradient_matches_oracle(name, steps):
 def cube40():
     w = W.config(3)
     st = gpu_state(w)
-    g = P.sph_build_cells(st.pos, w.h, skin=0.5 * w.dx)
+    g = P.sph_build_cells(st.pos, w.h, skin=0.5 * w.dx, pairs=True)
     return w, st, g
 
 

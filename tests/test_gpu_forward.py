@@ -24,10 +24,10 @@ def gpu_state(w):
     return P.ParticleState.from_arrays(w.pos, w.vel, w.rho, w.S, w.m)
 
 
-def gpu_rhs(w, precision="fp64", cells_per_h=1, skin=0.0, grid_pos=None):
+def gpu_rhs(w, precision="fp64", cells_per_h=1, skin=0.0, grid_pos=None, pairs=False):
     st = gpu_state(w)
     gp = st.pos if grid_pos is None else torch.as_tensor(grid_pos, dtype=torch.float64).cuda().contiguous()
-    g = P.sph_build_cells(gp, w.h, skin=skin, cells_per_h=cells_per_h)
+    g = P.sph_build_cells(gp, w.h, skin=skin, cells_per_h=cells_per_h, pairs=pairs)
     out = P.sph_rhs(g, st, w.params, precision)
     rc = P.workspace_status(out["_ws"])
     assert rc == 0, rc
@@ -144,13 +144,17 @@ def _variant(name):
 VARIANTS = ["cube16", "cube16_shuffled", "cube12_visc", "cube9_lattice_rotation"]
 
 
+PATHS = {"cells1": dict(cells_per_h=1), "cells2": dict(cells_per_h=2),
+         "pairs": dict(pairs=True), "pairs_skin": dict(pairs=True, skin=0.02)}
+
+
 @pytest.mark.parametrize("name", VARIANTS)
 @pytest.mark.parametrize("precision", ["fp64", "fp32comp"])
-@pytest.mark.parametrize("cells_per_h", [1, 2])
-def test_rhs_matches_oracle(name, precision, cells_per_h):
+@pytest.mark.parametrize("path", list(PATHS))
+def test_rhs_matches_oracle(name, precision, path):
     w = _variant(name)
     ref = native.rhs_workload(w)
-    got = gpu_rhs(w, precision, cells_per_h)
+    got = gpu_rhs(w, precision, **PATHS[path])
     err = normwise(got, ref, w.rho)
     bad = {k: v for k, v in err.items() if not v <= TOL[precision]}
     assert not bad, bad
@@ -164,16 +168,24 @@ def test_rhs_deterministic_and_frozen_grid():
         assert np.array_equal(a[k], b[k])
     # grid built at displaced positions with a skin: same result to rounding
     rng = np.random.default_rng(3)
-    old = w.pos + rng.uniform(-0.2, 0.2, w.pos.shape) * w.dx
+    # displacements below skin/2 = 0.25 dx in Euclidean norm (0.14 sqrt(3) = 0.243)
+    old = w.pos + rng.uniform(-0.14, 0.14, w.pos.shape) * w.dx
     c = gpu_rhs(w, skin=0.5 * w.dx, grid_pos=old)
     err = normwise(c, a)
     assert max(err.values()) < 1e-13
+    d = gpu_rhs(w, skin=0.5 * w.dx, grid_pos=old, pairs=True)
+    assert max(normwise(d, a).values()) < 1e-13
+    e1 = gpu_rhs(w, pairs=True)
+    e2 = gpu_rhs(w, pairs=True)
+    for k in e1:
+        assert np.array_equal(e1[k], e2[k])
 
 
-def test_stale_grid_is_flagged():
+@pytest.mark.parametrize("pairs", [False, True])
+def test_stale_grid_is_flagged(pairs):
     w = W.config(0)
     st = gpu_state(w)
-    g = P.sph_build_cells(st.pos, w.h, skin=0.01 * w.dx)
+    g = P.sph_build_cells(st.pos, w.h, skin=0.01 * w.dx, pairs=pairs)
     st.pos[0, 100] += 0.5 * w.h  # far beyond skin / 2
     out = P.sph_rhs(g, st, w.params)
     assert P.workspace_status(out["_ws"]) == L.SPH_ERR_STALE_GRID
@@ -194,7 +206,7 @@ def test_nonpositive_density_is_flagged():
 def _subsample_parity(w, k, precision, seed):
     idx = W.subsample(w.n, k, seed)
     ref = native.rhs(w.pos, w.vel, w.rho, w.S, w.m, w.param_vector(), targets=idx)
-    got = gpu_rhs(w, precision)
+    got = gpu_rhs(w, precision, skin=0.1 * w.dx, pairs=True)
     got = {kk: v[..., idx] for kk, v in got.items()}
     err = normwise(got, ref, w.rho[idx])
     bad = {kk: v for kk, v in err.items() if not v <= TOL[precision]}
