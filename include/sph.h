@@ -72,7 +72,8 @@ enum sph_op {
  * section 3.5.2 widened by the grid's skin): for every slot s, the slots whose
  * distance was below h + skin at build time.  Slots are grouped by 64; inside
  * group B the j-th candidate of slot s = 64 B + l is slot[block_start[B] + 64 j
- * + l] for j < count[s].  All arrays are device arrays owned by the caller. */
+ * + l] for j < count[s]; each group is padded to its longest list with -1.  All
+ * arrays are device arrays owned by the caller. */
 typedef struct {
     int64_t n;             /* slots */
     double radius;         /* h + skin at build time */
@@ -273,8 +274,10 @@ int sph_rhs_adjoint(const sph_grid *grid, const sph_state *state, const sph_para
  *   s0           initial state (device arrays, user order)
  *   s_final      final state out (may alias the arrays of s0)
  *   checkpoints  device, sph_checkpoint_bytes(n, steps) bytes, or NULL; holds
- *                (x, v, rho, S, F) at the start of every step and at the end,
- *                as needed by sph_leapfrog_adjoint
+ *                (x, v, rho, S, F) at the start of every step and at the end
+ *                (user order) and the velocity gradient behind each F (the
+ *                grid's slot order), as needed by sph_leapfrog_adjoint, which
+ *                must be given the same grid
  * The grid must have been built with a skin covering the trajectory's largest
  * displacement (device flag STALE_GRID otherwise).  Errors: as sph_rhs. */
 int sph_leapfrog(const sph_grid *grid, const sph_state *s0, const sph_params *params,

@@ -100,6 +100,54 @@ __global__ __launch_bounds__(kBlock) void k_adj_L(GridDev g, int64_t n, Consts k
     for (int i = 0; i < 9; ++i) ad.L[i][s] = L[i];
 }
 
+// same over the frozen pair list with cooperative gathers
+__global__ __launch_bounds__(kBlock) void k_adj_L_list(GridDev g, int64_t n, Consts k,
+                                                       const double *__restrict__ rec, AdjRec ad) {
+    __shared__ double2 lbuf[kBlock / 64][64 * 8];
+    double2 *buf = lbuf[threadIdx.x >> 6];
+    const int64_t s = xcd_block(gridDim.x) * kBlock + threadIdx.x;
+    const int64_t w0 = s - __lane_id();
+    if (w0 >= n) return;
+    const bool act = s < n;
+    const int64_t base = g.pl_block[w0 >> 6];
+    const int steps = (int)((g.pl_block[(w0 >> 6) + 1] - base) >> 6);
+    const int cnt = act ? g.pl_count[s] : 0;
+    double2 p0 = make_double2(0, 0), p1 = p0, p2 = p0;
+    if (act) {
+        const double2 *ra = rec2(rec, s);
+        p0 = ra[0]; p1 = ra[1]; p2 = ra[2];
+    }
+    const double xa = p0.x, ya = p0.y, za = p1.x, vxa = p1.y, vya = p2.x, vza = p2.y;
+    double L[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int j = 0; j < steps; ++j) {
+        {
+            const double *const recs[1] = {rec};
+            double2 *const bufs[1] = {buf};
+            wave_gather<1>(recs, bufs, g.pl_slot + base + ((int64_t)j << 6));
+        }
+        wave_sync();
+        if (j < cnt) {
+            const double2 b0 = wave_chunk(buf, 0), b1 = wave_chunk(buf, 1);
+            const double d2 = dist2_exact(xa, ya, za, b0.x, b0.y, b1.x);
+            if (d2 < k.h2) {
+                const double2 b2 = wave_chunk(buf, 2), b7 = wave_chunk(buf, 7);
+                const KernelPieces kp = kernel_pieces(k, d2, rsqrt64(d2));
+                const double F = k.Fn * kp.f;
+                const double gx = F * (xa - b0.x), gy = F * (ya - b0.y), gz = F * (za - b1.x);
+                const double V = b7.x;
+                const double tx = V * (b1.y - vxa), ty = V * (b2.x - vya), tz = V * (b2.y - vza);
+                L[0] = fma(tx, gx, L[0]); L[1] = fma(tx, gy, L[1]); L[2] = fma(tx, gz, L[2]);
+                L[3] = fma(ty, gx, L[3]); L[4] = fma(ty, gy, L[4]); L[5] = fma(ty, gz, L[5]);
+                L[6] = fma(tz, gx, L[6]); L[7] = fma(tz, gy, L[7]); L[8] = fma(tz, gz, L[8]);
+            }
+        }
+        wave_sync();
+    }
+    if (!act) return;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) ad.L[i][s] = L[i];
+}
+
 // post stage (see the file header)
 __global__ __launch_bounds__(kBlock) void k_adj_post(GridDev g, int64_t n, Consts k,
                                                      const double *__restrict__ rec, StateDev st,
@@ -180,126 +228,197 @@ struct AdjAcc {
     double gT[6] = {0, 0, 0, 0, 0, 0};
 };
 
-// pair stage + pre stage (see the file header)
+// Own data of particle c in the pair stage.
+struct AdjOwn {
+    double xc, yc, zc, vxc, vyc, vzc, rc, mc, Vc, Tc[6], Lbc[9], abx, aby, abz, rsc;
+};
+
+// Both roles of the pair (c, b) (see the file header).  b = forward record chunks
+// b0..b7 of the partner, e0..e6 = its adjoint record chunks.
+__device__ inline void adj_pair(const Consts &k, const AdjOwn &o, double d2, double2 b0,
+                                double2 b1, double2 b2, double2 b3, double2 b4, double2 b5,
+                                double2 b6, double2 b7, double2 e0, double2 e1, double2 e2,
+                                double2 e3, double2 e4, double2 e5, double2 e6, AdjAcc &acc) {
+    const double Gn = k.Fn * k.inv_h * k.inv_h;
+    const double Lbb[9] = {e0.x, e0.y, e1.x, e1.y, e2.x, e2.y, e3.x, e3.y, e4.x};
+    const double rx = o.xc - b0.x, ry = o.yc - b0.y, rz = o.zc - b1.x;
+    const double ux = b1.y - o.vxc, uy = b2.x - o.vyc, uz = b2.y - o.vzc;
+    const double rb_ = b3.x, mb = b3.y, Vb = b7.x;
+    const double ir = rsqrt64(d2);
+    const KernelPieces kp = kernel_pieces(k, d2, ir);
+    // G = F'(r) / r:  3 Gn / q inside, Gn (1 - q^2) / q^3 outside (0 at r = 0)
+    const double iq = k.h * ir;
+    const double Gi = 3.0 * Gn * iq;
+    const double Go = Gn * (1.0 - kp.q * kp.q) * iq * iq * iq;
+    const double G = d2 > 0.0 ? (kp.inner ? Gi : Go) : 0.0;
+    const double F = k.Fn * kp.f;
+    const double gx = F * rx, gy = F * ry, gz = F * rz;
+    const double Ax = mb * o.abx - o.mc * e4.y;
+    const double Ay = mb * o.aby - o.mc * e5.x;
+    const double Az = mb * o.abz - o.mc * e5.y;
+    double M[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) M[i] = Vb * o.Lbc[i] + o.Vc * Lbb[i];
+    const double w = -(ux * rx + uy * ry + uz * rz);
+    const Visc vs = viscosity(k, d2, w, o.rc, rb_);
+    const double Pi = vs.Pi;
+    const double B0 = o.Tc[0] + b4.x - Pi, B1 = o.Tc[1] + b4.y - Pi;
+    const double B2 = o.Tc[2] + b5.x - Pi, B3 = o.Tc[3] + b5.y;
+    const double B4 = o.Tc[4] + b6.x, B5 = o.Tc[5] + b6.y;
+    const double gbx = M[0] * ux + M[3] * uy + M[6] * uz + B0 * Ax + B3 * Ay + B4 * Az;
+    const double gby = M[1] * ux + M[4] * uy + M[7] * uz + B3 * Ax + B1 * Ay + B5 * Az;
+    const double gbz = M[2] * ux + M[5] * uy + M[8] * uz + B4 * Ax + B5 * Ay + B2 * Az;
+    const double Pib = -(Ax * gx + Ay * gy + Az * gz);
+    double wb = 0.0, r2b = 0.0;
+    if (w < 0.0) {
+        const double nub = Pib * (-k.alpha_c + 2.0 * k.beta * vs.nu) * vs.coef;
+        wb = nub * k.h * vs.invD;
+        r2b = -nub * vs.nu * vs.invD;
+        acc.grho -= Pib * Pi * 0.5 * vs.coef;  // Pi / (rho_c + rho_b)
+    }
+    const double rsw = o.rsc * mb + e6.x * o.mc;
+    const double rg = rx * gbx + ry * gby + rz * gbz;
+    acc.gx += rsw * gx + F * gbx + G * rg * rx - wb * ux + 2.0 * r2b * rx;
+    acc.gy += rsw * gy + F * gby + G * rg * ry - wb * uy + 2.0 * r2b * ry;
+    acc.gz += rsw * gz + F * gbz + G * rg * rz - wb * uz + 2.0 * r2b * rz;
+    acc.gvx += -(M[0] * gx + M[1] * gy + M[2] * gz) + wb * rx;
+    acc.gvy += -(M[3] * gx + M[4] * gy + M[5] * gz) + wb * ry;
+    acc.gvz += -(M[6] * gx + M[7] * gy + M[8] * gz) + wb * rz;
+    acc.gT[0] += Ax * gx;
+    acc.gT[1] += Ay * gy;
+    acc.gT[2] += Az * gz;
+    acc.gT[3] += Ax * gy + Ay * gx;
+    acc.gT[4] += Ax * gz + Az * gx;
+    acc.gT[5] += Ay * gz + Az * gy;
+    acc.gV += ux * (Lbb[0] * gx + Lbb[1] * gy + Lbb[2] * gz) +
+              uy * (Lbb[3] * gx + Lbb[4] * gy + Lbb[5] * gz) +
+              uz * (Lbb[6] * gx + Lbb[7] * gy + Lbb[8] * gz);
+}
+
+__device__ inline AdjOwn adj_own(const double *rec, const AdjRec &ad, int64_t s) {
+    AdjOwn o;
+    const double2 *ra = rec2(rec, s);
+    const double2 p0 = ra[0], p1 = ra[1], p2 = ra[2], p3 = ra[3], p4 = ra[4], p5 = ra[5],
+                  p6 = ra[6], p7 = ra[7];
+    o.xc = p0.x; o.yc = p0.y; o.zc = p1.x; o.vxc = p1.y; o.vyc = p2.x; o.vzc = p2.y;
+    o.rc = p3.x; o.mc = p3.y; o.Vc = p7.x;
+    o.Tc[0] = p4.x; o.Tc[1] = p4.y; o.Tc[2] = p5.x; o.Tc[3] = p5.y; o.Tc[4] = p6.x; o.Tc[5] = p6.y;
+    const double2 *qa = reinterpret_cast<const double2 *>(ad.arec + s * kAdj);
+    const double2 q0 = qa[0], q1 = qa[1], q2 = qa[2], q3 = qa[3], q4 = qa[4], q5 = qa[5], q6 = qa[6];
+    o.Lbc[0] = q0.x; o.Lbc[1] = q0.y; o.Lbc[2] = q1.x; o.Lbc[3] = q1.y; o.Lbc[4] = q2.x;
+    o.Lbc[5] = q2.y; o.Lbc[6] = q3.x; o.Lbc[7] = q3.y; o.Lbc[8] = q4.x;
+    o.abx = q4.y; o.aby = q5.x; o.abz = q5.y; o.rsc = q6.x;
+    return o;
+}
+
+// pre stage: T = (f S - p I) / rho^2, V = m / rho, pressure, limiter; writes the
+// gradients of user particle a; returns the Y0 contribution
+__device__ inline double adj_pre(const Consts &k, const AdjRec &ad, const AdjOwn &o,
+                                 const AdjAcc &acc, int64_t s, int a, const StateDev &st,
+                                 const GradDev &out) {
+    double S[6] = {st.sxx[a], st.syy[a], st.szz[a], st.sxy[a], st.sxz[a], st.syz[a]};
+    const double j2 = j2_of(S);
+    const bool limited = 3.0 * j2 > k.Y0sq;
+    const double f = limited ? k.Y0sq / (3.0 * j2) : 1.0;
+    const double rc = o.rc;
+    const double ir2 = 1.0 / (rc * rc);
+    double grho = ad.rhob[s] + acc.grho - acc.gV * o.Vc / rc;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) grho += acc.gT[i] * (-2.0 * o.Tc[i] / rc);
+    const bool cut = k.rho_cut > 0.0 && rc / k.rho0 < k.rho_cut;
+    if (!cut) grho += k.c2 * (-(acc.gT[0] + acc.gT[1] + acc.gT[2]) * ir2);
+    double Stb[6], fb = 0.0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        Stb[i] = acc.gT[i] * ir2 + ad.Stb[i][s];
+        fb += Stb[i] * S[i];
+    }
+    double gS[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) gS[i] = f * Stb[i];
+    double y0 = 0.0;
+    if (limited) {
+        const double Jb = -fb * f / j2;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) gS[i] += Jb * (i < 3 ? S[i] : 2.0 * S[i]);
+        y0 = fb * 2.0 * f / k.Y0;
+    }
+    const int A = out.accumulate;
+    put(out.x, a, acc.gx, A);
+    put(out.y, a, acc.gy, A);
+    put(out.z, a, acc.gz, A);
+    put(out.vx, a, acc.gvx, A);
+    put(out.vy, a, acc.gvy, A);
+    put(out.vz, a, acc.gvz, A);
+    put(out.rho, a, grho, A);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) put(out.s[i], a, gS[i], A);
+    return y0;
+}
+
+// pair stage + pre stage (see the file header); cell-sweep path
 __global__ __launch_bounds__(kBlock) void k_adj_pairs(GridDev g, int64_t n, Consts k,
                                                       const double *__restrict__ rec, StateDev st,
                                                       AdjRec ad, GradDev out) {
     const int64_t s = xcd_block(gridDim.x) * kBlock + threadIdx.x;
     double y0_part = 0.0;
     if (s < n) {
-        const double2 *ra = rec2(rec, s);
-        const double2 p0 = ra[0], p1 = ra[1], p2 = ra[2], p3 = ra[3], p4 = ra[4], p5 = ra[5],
-                      p6 = ra[6], p7 = ra[7];
-        const double xc = p0.x, yc = p0.y, zc = p1.x, vxc = p1.y, vyc = p2.x, vzc = p2.y;
-        const double rc = p3.x, mc = p3.y, Vc = p7.x;
-        const double Tc[6] = {p4.x, p4.y, p5.x, p5.y, p6.x, p6.y};
-        const double2 *qa = reinterpret_cast<const double2 *>(ad.arec + s * kAdj);
-        const double2 q0 = qa[0], q1 = qa[1], q2 = qa[2], q3 = qa[3], q4 = qa[4], q5 = qa[5],
-                      q6 = qa[6];
-        const double Lbc[9] = {q0.x, q0.y, q1.x, q1.y, q2.x, q2.y, q3.x, q3.y, q4.x};
-        const double abx = q4.y, aby = q5.x, abz = q5.y, rsc = q6.x;
-        const double Gn = k.Fn * k.inv_h * k.inv_h;
+        const AdjOwn o = adj_own(rec, ad, s);
         AdjAcc acc;
-        for_each_candidate(g, s, xc, yc, zc, k.reach, [&](int t) {
+        for_each_candidate(g, s, o.xc, o.yc, o.zc, k.reach, [&](int t) {
             const double2 *rb = rec2(rec, t);
             const double2 b0 = rb[0], b1 = rb[1];
-            const double d2 = dist2_exact(xc, yc, zc, b0.x, b0.y, b1.x);
+            const double d2 = dist2_exact(o.xc, o.yc, o.zc, b0.x, b0.y, b1.x);
             if (!(d2 < k.h2)) return;
-            const double2 b2 = rb[2], b3 = rb[3], b4 = rb[4], b5 = rb[5], b6 = rb[6], b7 = rb[7];
             const double2 *qb = reinterpret_cast<const double2 *>(ad.arec + (int64_t)t * kAdj);
-            const double2 e0 = qb[0], e1 = qb[1], e2 = qb[2], e3 = qb[3], e4 = qb[4], e5 = qb[5],
-                          e6 = qb[6];
-            const double Lbb[9] = {e0.x, e0.y, e1.x, e1.y, e2.x, e2.y, e3.x, e3.y, e4.x};
-            const double rx = xc - b0.x, ry = yc - b0.y, rz = zc - b1.x;
-            const double ux = b1.y - vxc, uy = b2.x - vyc, uz = b2.y - vzc;
-            const double rb_ = b3.x, mb = b3.y, Vb = b7.x;
-            const double ir = rsqrt64(d2);
-            const KernelPieces kp = kernel_pieces(k, d2, ir);
-            // G = F'(r) / r:  3 Gn / q inside, Gn (1 - q^2) / q^3 outside (0 at r = 0)
-            const double iq = k.h * ir;
-            const double Gi = 3.0 * Gn * iq;
-            const double Go = Gn * (1.0 - kp.q * kp.q) * iq * iq * iq;
-            const double G = d2 > 0.0 ? (kp.inner ? Gi : Go) : 0.0;
-            const double F = k.Fn * kp.f;
-            const double gx = F * rx, gy = F * ry, gz = F * rz;
-            const double Ax = mb * abx - mc * e4.y;
-            const double Ay = mb * aby - mc * e5.x;
-            const double Az = mb * abz - mc * e5.y;
-            double M[9];
-#pragma unroll
-            for (int i = 0; i < 9; ++i) M[i] = Vb * Lbc[i] + Vc * Lbb[i];
-            const double w = -(ux * rx + uy * ry + uz * rz);
-            const Visc vs = viscosity(k, d2, w, rc, rb_);
-            const double Pi = vs.Pi;
-            const double B0 = Tc[0] + b4.x - Pi, B1 = Tc[1] + b4.y - Pi;
-            const double B2 = Tc[2] + b5.x - Pi, B3 = Tc[3] + b5.y;
-            const double B4 = Tc[4] + b6.x, B5 = Tc[5] + b6.y;
-            const double gbx = M[0] * ux + M[3] * uy + M[6] * uz + B0 * Ax + B3 * Ay + B4 * Az;
-            const double gby = M[1] * ux + M[4] * uy + M[7] * uz + B3 * Ax + B1 * Ay + B5 * Az;
-            const double gbz = M[2] * ux + M[5] * uy + M[8] * uz + B4 * Ax + B5 * Ay + B2 * Az;
-            const double Pib = -(Ax * gx + Ay * gy + Az * gz);
-            double wb = 0.0, r2b = 0.0;
-            if (w < 0.0) {
-                const double nub = Pib * (-k.alpha_c + 2.0 * k.beta * vs.nu) * vs.coef;
-                wb = nub * k.h * vs.invD;
-                r2b = -nub * vs.nu * vs.invD;
-                acc.grho -= Pib * Pi * 0.5 * vs.coef;  // Pi / (rho_c + rho_b)
-            }
-            const double rsw = rsc * mb + e6.x * mc;
-            const double rg = rx * gbx + ry * gby + rz * gbz;
-            acc.gx += rsw * gx + F * gbx + G * rg * rx - wb * ux + 2.0 * r2b * rx;
-            acc.gy += rsw * gy + F * gby + G * rg * ry - wb * uy + 2.0 * r2b * ry;
-            acc.gz += rsw * gz + F * gbz + G * rg * rz - wb * uz + 2.0 * r2b * rz;
-            acc.gvx += -(M[0] * gx + M[1] * gy + M[2] * gz) + wb * rx;
-            acc.gvy += -(M[3] * gx + M[4] * gy + M[5] * gz) + wb * ry;
-            acc.gvz += -(M[6] * gx + M[7] * gy + M[8] * gz) + wb * rz;
-            acc.gT[0] += Ax * gx;
-            acc.gT[1] += Ay * gy;
-            acc.gT[2] += Az * gz;
-            acc.gT[3] += Ax * gy + Ay * gx;
-            acc.gT[4] += Ax * gz + Az * gx;
-            acc.gT[5] += Ay * gz + Az * gy;
-            acc.gV += ux * (Lbb[0] * gx + Lbb[1] * gy + Lbb[2] * gz) +
-                      uy * (Lbb[3] * gx + Lbb[4] * gy + Lbb[5] * gz) +
-                      uz * (Lbb[6] * gx + Lbb[7] * gy + Lbb[8] * gz);
+            adj_pair(k, o, d2, b0, b1, rb[2], rb[3], rb[4], rb[5], rb[6], rb[7], qb[0], qb[1],
+                     qb[2], qb[3], qb[4], qb[5], qb[6], acc);
         });
-        // pre stage: T = (f S - p I) / rho^2, V = m / rho, pressure, limiter
-        const int a = g.perm[s];
-        double S[6] = {st.sxx[a], st.syy[a], st.szz[a], st.sxy[a], st.sxz[a], st.syz[a]};
-        const double j2 = j2_of(S);
-        const bool limited = 3.0 * j2 > k.Y0sq;
-        const double f = limited ? k.Y0sq / (3.0 * j2) : 1.0;
-        const double ir2 = 1.0 / (rc * rc);
-        double grho = ad.rhob[s] + acc.grho - acc.gV * Vc / rc;
-#pragma unroll
-        for (int i = 0; i < 6; ++i) grho += acc.gT[i] * (-2.0 * Tc[i] / rc);
-        const bool cut = k.rho_cut > 0.0 && rc / k.rho0 < k.rho_cut;
-        if (!cut) grho += k.c2 * (-(acc.gT[0] + acc.gT[1] + acc.gT[2]) * ir2);
-        double Stb[6], fb = 0.0;
-#pragma unroll
-        for (int i = 0; i < 6; ++i) {
-            Stb[i] = acc.gT[i] * ir2 + ad.Stb[i][s];
-            fb += Stb[i] * S[i];
+        y0_part = adj_pre(k, ad, o, acc, s, g.perm[s], st, out);
+    }
+    const double tot = block_sum(y0_part);
+    if (threadIdx.x == 0) ad.part_y0[blockIdx.x] = tot;
+}
+
+// the same over the frozen pair list with cooperative gathers of both records
+__global__ __launch_bounds__(kBlock) void k_adj_pairs_list(GridDev g, int64_t n, Consts k,
+                                                           const double *__restrict__ rec,
+                                                           StateDev st, AdjRec ad, GradDev out) {
+    __shared__ double2 fbuf[kBlock / 64][64 * 8];
+    __shared__ double2 abuf[kBlock / 64][64 * 8];
+    double2 *bf = fbuf[threadIdx.x >> 6];
+    double2 *ba = abuf[threadIdx.x >> 6];
+    const int64_t s = xcd_block(gridDim.x) * kBlock + threadIdx.x;
+    const int64_t w0 = s - __lane_id();
+    double y0_part = 0.0;
+    if (w0 < n) {
+        const bool act = s < n;
+        const int64_t base = g.pl_block[w0 >> 6];
+        const int steps = (int)((g.pl_block[(w0 >> 6) + 1] - base) >> 6);
+        const int cnt = act ? g.pl_count[s] : 0;
+        const AdjOwn o = adj_own(rec, ad, act ? s : w0);
+        AdjAcc acc;
+        for (int j = 0; j < steps; ++j) {
+            const int32_t *idx = g.pl_slot + base + ((int64_t)j << 6);
+            {
+                const double *const recs[2] = {rec, ad.arec};
+                double2 *const bufs[2] = {bf, ba};
+                wave_gather<2>(recs, bufs, idx);
+            }
+            wave_sync();
+            if (j < cnt) {
+                const double2 b0 = wave_chunk(bf, 0), b1 = wave_chunk(bf, 1);
+                const double d2 = dist2_exact(o.xc, o.yc, o.zc, b0.x, b0.y, b1.x);
+                if (d2 < k.h2)
+                    adj_pair(k, o, d2, b0, b1, wave_chunk(bf, 2), wave_chunk(bf, 3),
+                             wave_chunk(bf, 4), wave_chunk(bf, 5), wave_chunk(bf, 6),
+                             wave_chunk(bf, 7), wave_chunk(ba, 0), wave_chunk(ba, 1),
+                             wave_chunk(ba, 2), wave_chunk(ba, 3), wave_chunk(ba, 4),
+                             wave_chunk(ba, 5), wave_chunk(ba, 6), acc);
+            }
+            wave_sync();
         }
-        double gS[6];
-#pragma unroll
-        for (int i = 0; i < 6; ++i) gS[i] = f * Stb[i];
-        if (limited) {
-            const double Jb = -fb * f / j2;
-#pragma unroll
-            for (int i = 0; i < 6; ++i) gS[i] += Jb * (i < 3 ? S[i] : 2.0 * S[i]);
-            y0_part = fb * 2.0 * f / k.Y0;
-        }
-        const int A = out.accumulate;
-        put(out.x, a, acc.gx, A);
-        put(out.y, a, acc.gy, A);
-        put(out.z, a, acc.gz, A);
-        put(out.vx, a, acc.gvx, A);
-        put(out.vy, a, acc.gvy, A);
-        put(out.vz, a, acc.gvz, A);
-        put(out.rho, a, grho, A);
-#pragma unroll
-        for (int i = 0; i < 6; ++i) put(out.s[i], a, gS[i], A);
+        if (act) y0_part = adj_pre(k, ad, o, acc, s, g.perm[s], st, out);
     }
     const double tot = block_sum(y0_part);
     if (threadIdx.x == 0) ad.part_y0[blockIdx.x] = tot;
@@ -360,7 +479,7 @@ GradDev grad_dev(const sph_fields *g, int accumulate) {
 // accumulated (accumulate != 0) into grad; dparams written or accumulated.
 int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_params *params,
                        const CotDev &cot, const GradDev &grad, double *dparams, int accumulate_params,
-                       Carve &c, hipStream_t s) {
+                       Carve &c, hipStream_t s, const double *L_in) {
     const int64_t n = grid->n;
     GridDev g = grid_dev(grid);
     Consts k = make_consts(*params, g.delta);
@@ -369,16 +488,24 @@ int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_p
     StateDev st = state_dev(state);
     int rc = prepass_launch(g, st, n, k, rec, c.status(), s);
     if (rc) return rc;
-    {
+    if (L_in) {
+        for (int i = 0; i < 9; ++i) ad.L[i] = const_cast<double *>(L_in) + (size_t)i * n;
+    } else {
         TimedRegion t("adjoint_L", s);
-        k_adj_L<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, ad);
+        if (g.pl_count)
+            k_adj_L_list<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, ad);
+        else
+            k_adj_L<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, ad);
         SPH_LAUNCHED();
     }
     k_adj_post<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, cot, ad);
     SPH_LAUNCHED();
     {
         TimedRegion t("adjoint_pairs", s);
-        k_adj_pairs<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, ad, grad);
+        if (g.pl_count)
+            k_adj_pairs_list<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, ad, grad);
+        else
+            k_adj_pairs<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, ad, grad);
         SPH_LAUNCHED();
     }
     return reduce_params_launch(ad.part_mu, ad.part_y0, blocks_for(n), dparams, accumulate_params, s);

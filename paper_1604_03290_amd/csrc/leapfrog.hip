@@ -8,8 +8,8 @@
 //     U_{n+1} = U' + dt/2 F_{n+1}, S <- f_Y(S) S          (kick)
 //
 // f_Y = min(Y0^2 / (3 J2), 1) is the von Mises factor of section 2.6.  The
-// checkpoint of step k holds (x_k, v_k, rho_k, S_k, F_k), 23 arrays of n
-// doubles.  The reverse sweep walks the steps backwards, recomputing U' from
+// checkpoint of step k holds (x_k, v_k, rho_k, S_k, F_k) in user order and the
+// velocity gradient of F_k in the grid's slot order, 32 arrays of n doubles.  The reverse sweep walks the steps backwards, recomputing U' from
 // the checkpoint, and applies in turn the adjoints of the second kick, of the
 // right-hand side at (x_{n+1}, U'), of the drift and of the first kick.
 #include "common.hpp"
@@ -18,7 +18,8 @@
 namespace sph {
 namespace {
 
-constexpr int kArrays = 23;  // x3 v3 rho S6 | a3 drho dS6
+constexpr int kArrays = 32;  // x3 v3 rho S6 | a3 drho dS6 | L9 (slot order)
+constexpr int kLOffset = 23;
 
 struct Fields13 {
     double *p[13];  // x y z vx vy vz rho sxx syy szz sxy sxz syz
@@ -273,11 +274,12 @@ extern "C" int sph_leapfrog(const sph_grid *grid, const sph_state *s0, const sph
     const sph_deriv d = deriv_struct(F);
     const double half = 0.5 * dt;
     const unsigned nb = blocks_for(n);
-    auto rhs = [&]() {
+    auto rhs = [&](int k) {
         Carve w = rc_ws;
-        return rhs_launch(grid, &st, params, SPH_FP64, &d, w, s);
+        double *Lout = checkpoints ? checkpoints + ((size_t)k * kArrays + kLOffset) * n : nullptr;
+        return rhs_launch(grid, &st, params, SPH_FP64, &d, w, s, Lout);
     };
-    if ((rc = rhs())) return rc;
+    if ((rc = rhs(0))) return rc;
     for (int k = 0; k < steps; ++k) {
         if (checkpoints) {
             k_store<<<nb, kBlock, 0, s>>>(U, F, n, checkpoints + (size_t)k * kArrays * n);
@@ -287,7 +289,7 @@ extern "C" int sph_leapfrog(const sph_grid *grid, const sph_state *s0, const sph
         SPH_LAUNCHED();
         k_drift<<<nb, kBlock, 0, s>>>(U, n, dt);
         SPH_LAUNCHED();
-        if ((rc = rhs())) return rc;
+        if ((rc = rhs(k + 1))) return rc;
         k_kick<<<nb, kBlock, 0, s>>>(U, F, U, n, half, params->Y0 * params->Y0);
         SPH_LAUNCHED();
     }
@@ -343,11 +345,12 @@ extern "C" int sph_leapfrog_adjoint(const sph_grid *grid, const sph_state *s0,
     SPH_LAUNCHED();
 
     const GradDev acc = grad_dev(grad0, 1);
-    auto adjoint_at = [&](const sph_state &st, const Deriv10 &gF) {
+    auto adjoint_at = [&](const sph_state &st, const Deriv10 &gF, const double *slab) {
         CotDev cot{gF.p[0], gF.p[1], gF.p[2], gF.p[3],
                    {gF.p[4], gF.p[5], gF.p[6], gF.p[7], gF.p[8], gF.p[9]}, nullptr};
         Carve w = adj_ws;
-        return rhs_adjoint_launch(grid, &st, params, cot, acc, dparams, 1, w, s);
+        return rhs_adjoint_launch(grid, &st, params, cot, acc, dparams, 1, w, s,
+                                  slab + (size_t)kLOffset * n);
     };
     auto kick_adj = [&](const Fields13 &Uin, const Deriv10 &F, const Deriv10 &gF, int accumulate) {
         Ptr12 t;
@@ -377,7 +380,7 @@ extern "C" int sph_leapfrog_adjoint(const sph_grid *grid, const sph_state *s0,
         if ((rc = kick_adj(Up, Fk1, gF1, k + 1 < steps ? 1 : 0))) return rc;
         // right-hand side F_{k+1} = F(x_{k+1}, U')
         const sph_state st1 = state_struct(Upx, s0->m, n);
-        if ((rc = adjoint_at(st1, gF1))) return rc;
+        if ((rc = adjoint_at(st1, gF1, slab_k1))) return rc;
         // drift x_{k+1} = x_k + dt v'
         k_drift_adj<<<nb, kBlock, 0, s>>>(gU, n, dt);
         SPH_LAUNCHED();
@@ -389,5 +392,5 @@ extern "C" int sph_leapfrog_adjoint(const sph_grid *grid, const sph_state *s0,
     }
     // F_0 = F(x_0, U_0)
     const sph_state st0 = state_struct(slab_fields(ck, n), s0->m, n);
-    return adjoint_at(st0, gF1);
+    return adjoint_at(st0, gF1, ck);
 }

@@ -1,73 +1,107 @@
 // Interaction partner lists (section 3.5.2) as a CSR in user order, each row
-// ascending.  Count pass -> scan -> fill pass -> per-row ordering.
+// ascending.  Positions are first gathered into slot order; the count and fill
+// passes take candidates from the grid's pair list when it has one (else from
+// the cell rows) and apply the exact test; each row is then sorted by one
+// wavefront with a bitonic network in LDS.
+#include <climits>
+
 #include "common.hpp"
+#include "rhs_common.hpp"
 
 namespace sph {
 namespace {
 
-struct Pos {
-    const double *__restrict__ x;
-    const double *__restrict__ y;
-    const double *__restrict__ z;
-};
+constexpr int kSortMax = 1024;  // longest row sorted in LDS by one wavefront
 
-__global__ __launch_bounds__(kBlock) void k_nb_count(GridDev g, Pos p, int64_t n, double h2,
-                                                     double reach, int64_t *__restrict__ count,
-                                                     int32_t *__restrict__ status) {
+__global__ __launch_bounds__(kBlock) void k_nb_gather(GridDev g, const double *__restrict__ x,
+                                                      const double *__restrict__ y,
+                                                      const double *__restrict__ z, int64_t n,
+                                                      double4 *__restrict__ pos,
+                                                      int32_t *__restrict__ status) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int a = g.perm[s];
-    const double xa = p.x[a], ya = p.y[a], za = p.z[a];
-    if (!within_cell(g, (int)s, xa, ya, za)) raise_flag(status, SPH_ERR_STALE_GRID);
-    int64_t c = 0;
-    for_each_row(g, xa, ya, za, reach, [&](int s0, int s1) {
-        for (int t = s0; t < s1; ++t) {
-            if (t == s) continue;
-            const int b = g.perm[t];
-            c += dist2_exact(xa, ya, za, p.x[b], p.y[b], p.z[b]) < h2;
-        }
-    });
-    count[a] = c;
+    const double px = x[a], py = y[a], pz = z[a];
+    if (!within_cell(g, (int)s, px, py, pz)) raise_flag(status, SPH_ERR_STALE_GRID);
+    if (!(isfinite(px) && isfinite(py) && isfinite(pz))) raise_flag(status, SPH_ERR_DOMAIN);
+    pos[s] = make_double4(px, py, pz, 0.0);
 }
 
-__global__ __launch_bounds__(kBlock) void k_nb_fill(GridDev g, Pos p, int64_t n, double h2,
-                                                    double reach,
+template <bool kFill>
+__global__ __launch_bounds__(kBlock) void k_nb_pass(GridDev g, const double4 *__restrict__ pos,
+                                                    int64_t n, double h2, double reach,
+                                                    int64_t *__restrict__ count,
                                                     const int64_t *__restrict__ row_ptr,
                                                     int32_t *__restrict__ col) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t s = xcd_block(gridDim.x) * kBlock + threadIdx.x;
     if (s >= n) return;
+    const double4 pa = pos[s];
     const int a = g.perm[s];
-    const double xa = p.x[a], ya = p.y[a], za = p.z[a];
-    int64_t k = row_ptr[a];
-    for_each_row(g, xa, ya, za, reach, [&](int s0, int s1) {
-        for (int t = s0; t < s1; ++t) {
-            if (t == s) continue;
-            const int b = g.perm[t];
-            if (dist2_exact(xa, ya, za, p.x[b], p.y[b], p.z[b]) < h2) col[k++] = b;
+    int64_t k = kFill ? row_ptr[a] : 0;
+    for_each_candidate(g, s, pa.x, pa.y, pa.z, reach, [&](int t) {
+        const double4 pb = pos[t];
+        if (dist2_exact(pa.x, pa.y, pa.z, pb.x, pb.y, pb.z) < h2) {
+            if (kFill) col[k] = g.perm[t];
+            ++k;
         }
     });
+    if (!kFill) count[a] = k;
 }
 
+// one wavefront per row: bitonic sort of the row in LDS (rows longer than
+// kSortMax, which no workload here produces, fall back to an insertion sort)
 __global__ __launch_bounds__(kBlock) void k_nb_sort(const int64_t *__restrict__ row_ptr,
                                                     int64_t n, int32_t *__restrict__ col) {
-    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ int32_t lds[kBlock / 64][kSortMax];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int32_t *buf = lds[wave];
+    const int64_t a = (int64_t)blockIdx.x * (kBlock / 64) + wave;
     if (a >= n) return;
-    const int64_t r0 = row_ptr[a], r1 = row_ptr[a + 1];
-    for (int64_t i = r0 + 1; i < r1; ++i) {
-        const int32_t v = col[i];
-        int64_t j = i - 1;
-        while (j >= r0 && col[j] > v) {
-            col[j + 1] = col[j];
-            --j;
+    const int64_t r0 = row_ptr[a];
+    const int len = (int)(row_ptr[a + 1] - r0);
+    if (len <= 1) return;
+    if (len > kSortMax) {
+        if (lane == 0) {
+            for (int64_t i = r0 + 1; i < r0 + len; ++i) {
+                const int32_t v = col[i];
+                int64_t j = i - 1;
+                while (j >= r0 && col[j] > v) {
+                    col[j + 1] = col[j];
+                    --j;
+                }
+                col[j + 1] = v;
+            }
         }
-        col[j + 1] = v;
+        return;
     }
+    int n2 = 2;
+    while (n2 < len) n2 <<= 1;
+    for (int i = lane; i < n2; i += 64) buf[i] = i < len ? col[r0 + i] : INT_MAX;
+    wave_sync();
+    for (int kk = 2; kk <= n2; kk <<= 1) {
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            for (int i = lane; i < n2; i += 64) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const int32_t u = buf[i], v = buf[ixj];
+                    const bool up = (i & kk) == 0;
+                    if ((u > v) == up) {
+                        buf[i] = v;
+                        buf[ixj] = u;
+                    }
+                }
+            }
+            wave_sync();
+        }
+    }
+    for (int i = lane; i < len; i += 64) col[r0 + i] = buf[i];
 }
 
 }  // namespace
 
 size_t neighbours_ws_bytes(int64_t n) {
     Carve c(nullptr);
+    c.take<double4>(n);
     c.take<int64_t>(n);
     c.take<int64_t>(scan_tmp_elems(n));
     return c.used;
@@ -93,13 +127,15 @@ extern "C" int sph_neighbours(const sph_grid *grid, const double *x, const doubl
     if (ws_bytes < need) return fail(SPH_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
     hipStream_t s = (hipStream_t)stream;
     Carve c(ws);
+    double4 *pos = c.take<double4>(n);
     int64_t *count = c.take<int64_t>(n);
     int64_t *tmp = c.take<int64_t>(scan_tmp_elems(n));
     GridDev g = grid_dev(grid);
-    const Pos p{x, y, z};
     const double reach = (h + g.delta) * (1.0 + 1e-9);
     if ((rc = clear_status(ws, s))) return rc;
-    k_nb_count<<<blocks_for(n), kBlock, 0, s>>>(g, p, n, h * h, reach, count, c.status());
+    k_nb_gather<<<blocks_for(n), kBlock, 0, s>>>(g, x, y, z, n, pos, c.status());
+    SPH_LAUNCHED();
+    k_nb_pass<false><<<blocks_for(n), kBlock, 0, s>>>(g, pos, n, h * h, reach, count, nullptr, nullptr);
     SPH_LAUNCHED();
     if ((rc = exclusive_scan_i64(count, row_ptr, n, tmp, s))) return rc;
     int64_t nnz = 0;
@@ -112,9 +148,9 @@ extern "C" int sph_neighbours(const sph_grid *grid, const double *x, const doubl
     if (nnz > col_cap)
         return fail(SPH_ERR_CAPACITY, "%lld partners exceed capacity %lld", (long long)nnz,
                     (long long)col_cap);
-    k_nb_fill<<<blocks_for(n), kBlock, 0, s>>>(g, p, n, h * h, reach, row_ptr, col);
+    k_nb_pass<true><<<blocks_for(n), kBlock, 0, s>>>(g, pos, n, h * h, reach, nullptr, row_ptr, col);
     SPH_LAUNCHED();
-    k_nb_sort<<<blocks_for(n), kBlock, 0, s>>>(row_ptr, n, col);
+    k_nb_sort<<<blocks_for(n, kBlock / 64), kBlock, 0, s>>>(row_ptr, n, col);
     SPH_LAUNCHED();
     return SPH_OK;
 }

@@ -31,6 +31,10 @@ __global__ __launch_bounds__(kBlock) void k_pl_gather(GridDev g, const double *_
     x0[3 * s + 2] = pz;
 }
 
+// Count pass (kFill = false) or fill pass.  The fill runs over every slot of
+// every group, including the lanes past n of the last group, and writes -1 into
+// the padding after each list so that readers of whole groups never meet an
+// unset entry.
 template <bool kFill>
 __global__ __launch_bounds__(kBlock) void k_pl_scan(GridDev g, const double *__restrict__ x0,
                                                     int64_t n, double r2, double reach,
@@ -38,11 +42,19 @@ __global__ __launch_bounds__(kBlock) void k_pl_scan(GridDev g, const double *__r
                                                     const int64_t *__restrict__ block_start,
                                                     int32_t *__restrict__ slot) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
+    const int64_t nb = (n + kWave - 1) / kWave;
+    if (s >= (kFill ? nb * kWave : n)) return;
+    int64_t base = 0, maxc = 0;
+    if (kFill) {
+        base = block_start[s / kWave] + (s % kWave);
+        maxc = (block_start[s / kWave + 1] - block_start[s / kWave]) / kWave;
+        if (s >= n) {
+            for (int64_t j = 0; j < maxc; ++j) slot[base + kWave * j] = -1;
+            return;
+        }
+    }
     const double xa = x0[3 * s], ya = x0[3 * s + 1], za = x0[3 * s + 2];
     int c = 0;
-    int64_t base = 0;
-    if (kFill) base = block_start[s / kWave] + (s % kWave);
     for_each_row(g, xa, ya, za, reach, [&](int s0, int s1) {
         for (int t = s0; t < s1; ++t) {
             if (t == s) continue;
@@ -52,7 +64,10 @@ __global__ __launch_bounds__(kBlock) void k_pl_scan(GridDev g, const double *__r
             }
         }
     });
-    if (!kFill) count[s] = c;
+    if (kFill)
+        for (int64_t j = c; j < maxc; ++j) slot[base + kWave * j] = -1;
+    else
+        count[s] = c;
 }
 
 // sizes[B] = 64 * (longest list of block B)
@@ -124,7 +139,8 @@ extern "C" int sph_build_pairs(sph_grid *grid, const double *x, const double *y,
     if (total > capacity)
         return fail(SPH_ERR_CAPACITY, "pair list needs %lld entries, capacity %lld",
                     (long long)total, (long long)capacity);
-    k_pl_scan<true><<<blocks_for(n), kBlock, 0, s>>>(g, x0, n, r2, reach, count, block_start, slot);
+    k_pl_scan<true><<<blocks_for(nb * 64), kBlock, 0, s>>>(g, x0, n, r2, reach, count, block_start,
+                                                            slot);
     SPH_LAUNCHED();
     out->n = n;
     out->radius = radius;

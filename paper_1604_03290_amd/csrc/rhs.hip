@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kBlock) void k_narrow(const double *__restrict__ re
 // ---------------------------------------------------------- pairs, FP64 --
 __global__ __launch_bounds__(kBlock) void k_pairs64(GridDev g, int64_t n, Consts k,
                                                     const double *__restrict__ rec, StateDev st,
-                                                    OutDev out) {
+                                                    OutDev out, double *__restrict__ Lout) {
     const int64_t s = xcd_block(gridDim.x) * kBlock + threadIdx.x;
     if (s >= n) return;
     const double2 *ra = rec2(rec, s);
@@ -85,13 +85,70 @@ __global__ __launch_bounds__(kBlock) void k_pairs64(GridDev g, int64_t n, Consts
                b3.y, b7.x, acc);
     });
     postpass(k, g.perm[s], rho_a, acc.L, acc.ax, acc.ay, acc.az, acc.rs, st, out);
+    if (Lout) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) Lout[i * n + s] = acc.L[i];
+    }
+}
+
+// FP64 pair sums over the frozen pair list: the wavefront walks its 64 lists in
+// lock step, gathering the 64 partner records of step j cooperatively.
+__global__ __launch_bounds__(kBlock) void k_pairs64_list(GridDev g, int64_t n, Consts k,
+                                                         const double *__restrict__ rec,
+                                                         StateDev st, OutDev out,
+                                                         double *__restrict__ Lout) {
+    __shared__ double2 lbuf[kBlock / 64][64 * 8];
+    double2 *buf = lbuf[threadIdx.x >> 6];
+    const int64_t s = xcd_block(gridDim.x) * kBlock + threadIdx.x;
+    const int64_t w0 = s - __lane_id();
+    if (w0 >= n) return;  // whole wavefront past the end
+    const bool act = s < n;
+    const int64_t base = g.pl_block[w0 >> 6];
+    const int steps = (int)((g.pl_block[(w0 >> 6) + 1] - base) >> 6);
+    const int cnt = act ? g.pl_count[s] : 0;
+    double2 p0 = make_double2(0, 0), p1 = p0, p2 = p0, p3 = p0, p4 = p0, p5 = p0, p6 = p0;
+    if (act) {
+        const double2 *ra = rec2(rec, s);
+        p0 = ra[0]; p1 = ra[1]; p2 = ra[2]; p3 = ra[3]; p4 = ra[4]; p5 = ra[5]; p6 = ra[6];
+    }
+    const double xa = p0.x, ya = p0.y, za = p1.x, vxa = p1.y, vya = p2.x, vza = p2.y;
+    const double rho_a = p3.x;
+    Acc64 acc;
+    acc.rs = p3.y * k.Wn;  // own term m_a W(0)
+    for (int j = 0; j < steps; ++j) {
+        {
+            const double *const recs[1] = {rec};
+            double2 *const bufs[1] = {buf};
+            wave_gather<1>(recs, bufs, g.pl_slot + base + ((int64_t)j << 6));
+        }
+        wave_sync();
+        if (j < cnt) {
+            const double2 b0 = wave_chunk(buf, 0), b1 = wave_chunk(buf, 1);
+            const double d2 = dist2_exact(xa, ya, za, b0.x, b0.y, b1.x);
+            if (d2 < k.h2) {
+                const double2 b2 = wave_chunk(buf, 2), b3 = wave_chunk(buf, 3);
+                const double2 b4 = wave_chunk(buf, 4), b5 = wave_chunk(buf, 5);
+                const double2 b6 = wave_chunk(buf, 6), b7 = wave_chunk(buf, 7);
+                pair64(k, d2, xa - b0.x, ya - b0.y, za - b1.x, b1.y - vxa, b2.x - vya, b2.y - vza,
+                       rho_a, b3.x, p4.x + b4.x, p4.y + b4.y, p5.x + b5.x, p5.y + b5.y,
+                       p6.x + b6.x, p6.y + b6.y, b3.y, b7.x, acc);
+            }
+        }
+        wave_sync();
+    }
+    if (!act) return;
+    postpass(k, g.perm[s], rho_a, acc.L, acc.ax, acc.ay, acc.az, acc.rs, st, out);
+    if (Lout) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) Lout[i * n + s] = acc.L[i];
+    }
 }
 
 // ----------------------------------------- pairs, FP32 + Kahan sums --
 __global__ __launch_bounds__(kBlock) void k_pairs32(GridDev g, int64_t n, Consts k,
                                                     const double *__restrict__ rec,
                                                     const float *__restrict__ r32, StateDev st,
-                                                    OutDev out) {
+                                                    OutDev out, double *__restrict__ Lout) {
     const int64_t s = xcd_block(gridDim.x) * kBlock + threadIdx.x;
     if (s >= n) return;
     const double2 *ra = rec2(rec, s);
@@ -117,6 +174,10 @@ __global__ __launch_bounds__(kBlock) void k_pairs32(GridDev g, int64_t n, Consts
     for (int c = 0; c < 9; ++c) L[c] = acc.L[c].value();
     const double rs = p3.y * k.Wn + acc.rs.value();
     postpass(k, g.perm[s], p3.x, L, acc.ax.value(), acc.ay.value(), acc.az.value(), rs, st, out);
+    if (Lout) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) Lout[i * n + s] = L[i];
+    }
 }
 
 }  // namespace
@@ -170,7 +231,7 @@ int check_deriv(const sph_deriv *o) {
 
 // Forward right-hand side on a carved workspace (also used by the leapfrog).
 int rhs_launch(const sph_grid *grid, const sph_state *state, const sph_params *params,
-               int precision, const sph_deriv *out, Carve &c, hipStream_t s) {
+               int precision, const sph_deriv *out, Carve &c, hipStream_t s, double *L_out) {
     const int64_t n = grid->n;
     GridDev g = grid_dev(grid);
     Consts k = make_consts(*params, g.delta);
@@ -182,13 +243,16 @@ int rhs_launch(const sph_grid *grid, const sph_state *state, const sph_params *p
     if (rc) return rc;
     if (precision == SPH_FP64) {
         TimedRegion t("pairs_fp64", s);
-        k_pairs64<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, od);
+        if (g.pl_count)
+            k_pairs64_list<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, od, L_out);
+        else
+            k_pairs64<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, od, L_out);
         SPH_LAUNCHED();
     } else {
         k_narrow<<<blocks_for(n), kBlock, 0, s>>>(rec, n, r32);
         SPH_LAUNCHED();
         TimedRegion t("pairs_fp32comp", s);
-        k_pairs32<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, r32, st, od);
+        k_pairs32<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, r32, st, od, L_out);
         SPH_LAUNCHED();
     }
     return SPH_OK;

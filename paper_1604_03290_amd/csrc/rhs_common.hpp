@@ -79,6 +79,52 @@ __device__ inline const float4 *rec4(const float *r32, int64_t s) {
     return reinterpret_cast<const float4 *>(r32 + s * kRec32);
 }
 
+// Orders a wavefront's LDS accesses (writes by some lanes before reads by
+// others); no other synchronisation is needed inside one wavefront.
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Coalesced gather of one record per lane into the wavefront's LDS buffer
+// (64 records of 8 chunks of 16 bytes).  Eight lanes share a record, each
+// moving one chunk, so every load instruction touches 8 records instead of 64;
+// idx[src] is the record of lane src (negative: none, zero-filled).  Chunk c of
+// lane L's record sits at buf[8 L + ((c + L) & 7)], which keeps both the writes
+// and the per-lane reads free of bank conflicts.  Branch free: all index loads,
+// then all record loads (a missing record reads record 0 and is replaced by
+// zeros), then the LDS writes, so each step waits on memory twice.
+// NR record arrays (recs[i], each 16 doubles per record) share the indices.
+template <int NR>
+__device__ inline void wave_gather(const double *const (&recs)[NR], double2 *const (&bufs)[NR],
+                                   const int32_t *__restrict__ idx) {
+    const int lane = __lane_id();
+    const int c = lane & 7;
+    int t[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) t[m] = idx[8 * m + (lane >> 3)];
+    double2 v[NR][8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        const int64_t tt = t[m] < 0 ? 0 : t[m];
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+            v[r][m] = reinterpret_cast<const double2 *>(recs[r] + tt * kRec)[c];
+    }
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        const int src = 8 * m + (lane >> 3);
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+            bufs[r][8 * src + ((c + src) & 7)] = t[m] < 0 ? make_double2(0.0, 0.0) : v[r][m];
+    }
+}
+
+__device__ inline double2 wave_chunk(const double2 *buf, int c) {
+    const int L = __lane_id();
+    return buf[8 * L + ((c + L) & 7)];
+}
+
 // Liquid equation of state with the optional tension cut-off (section 2.5.1).
 __device__ inline double pressure(const Consts &k, double rho) {
     double p = k.c2 * (rho - k.rho0);
@@ -288,9 +334,11 @@ CotDev cot_dev(const sph_deriv_cot *c);
 GradDev grad_dev(const sph_fields *g, int accumulate);
 int check_grad(const sph_fields *g);
 size_t adjoint_ws_bytes(int64_t n);
+// L_in (nullable): the forward velocity gradient of the same state in slot order
+// (9 arrays of n); when null it is recomputed
 int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_params *params,
                        const CotDev &cot, const GradDev &grad, double *dparams, int accumulate_params,
-                       Carve &c, hipStream_t s);
+                       Carve &c, hipStream_t s, const double *L_in = nullptr);
 // dparams[0] (+)= sum of p0, dparams[1] (+)= sum of p1 (null parts skipped),
 // fixed summation order
 int reduce_params_launch(const double *p0, const double *p1, int64_t m, double *dparams,
@@ -302,8 +350,10 @@ int prepass_launch(const GridDev &g, const StateDev &st, int64_t n, const Consts
 int check_state(const sph_grid *grid, const sph_state *st);
 int check_params(const sph_grid *grid, const sph_params *pr);
 int check_deriv(const sph_deriv *o);
+// L_out (nullable): the velocity gradient of every slot, 9 arrays of n (slot order)
 int rhs_launch(const sph_grid *grid, const sph_state *state, const sph_params *params,
-               int precision, const sph_deriv *out, Carve &c, hipStream_t s);
+               int precision, const sph_deriv *out, Carve &c, hipStream_t s,
+               double *L_out = nullptr);
 size_t rhs_ws_bytes(int64_t n);
 
 // Deterministic sum over a 256-thread block (fixed tree); every thread must call it.
