@@ -72,8 +72,9 @@ enum sph_op {
  * section 3.5.2 widened by the grid's skin): for every slot s, the slots whose
  * distance was below h + skin at build time.  Slots are grouped by 64; inside
  * group B the j-th candidate of slot s = 64 B + l is slot[block_start[B] + 64 j
- * + l] for j < count[s]; each group is padded to its longest list with -1.  All
- * arrays are device arrays owned by the caller. */
+ * + l] for j < count[s]; each group is padded to its longest list with the
+ * slot itself (n - 1 for the lanes of the last group past n), so every entry is
+ * a valid slot.  All arrays are device arrays owned by the caller. */
 typedef struct {
     int64_t n;             /* slots */
     double radius;         /* h + skin at build time */

@@ -103,7 +103,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_L(GridDev g, int64_t n, Consts k
 // same over the frozen pair list with cooperative gathers
 __global__ __launch_bounds__(kBlock) void k_adj_L_list(GridDev g, int64_t n, Consts k,
                                                        const double *__restrict__ rec, AdjRec ad) {
-    __shared__ double2 lbuf[kBlock / 64][64 * 8];
+    __shared__ double2 lbuf[kBlock / 64][kLdsWave];
     double2 *buf = lbuf[threadIdx.x >> 6];
     const int64_t s = xcd_block(gridDim.x) * kBlock + threadIdx.x;
     const int64_t w0 = s - __lane_id();
@@ -119,11 +119,17 @@ __global__ __launch_bounds__(kBlock) void k_adj_L_list(GridDev g, int64_t n, Con
     }
     const double xa = p0.x, ya = p0.y, za = p1.x, vxa = p1.y, vya = p2.x, vza = p2.y;
     double L[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const char *recs = reinterpret_cast<const char *>(rec);
+    const int32_t *row = g.pl_slot + base + __lane_id();
+    Fetched<8> f;
+    int e1 = 0;
+    if (steps > 0) f = fetch<8>(recs, kRec * 8, row[0]);
+    if (steps > 1) e1 = row[64];
     for (int j = 0; j < steps; ++j) {
-        {
-            const double *const recs[1] = {rec};
-            double2 *const bufs[1] = {buf};
-            wave_gather<1>(recs, bufs, g.pl_slot + base + ((int64_t)j << 6));
+        stage<8>(buf, f);
+        if (j + 1 < steps) {
+            f = fetch<8>(recs, kRec * 8, e1);
+            if (j + 2 < steps) e1 = row[(int64_t)(j + 2) << 6];
         }
         wave_sync();
         if (j < cnt) {
@@ -384,8 +390,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_pairs(GridDev g, int64_t n, Cons
 __global__ __launch_bounds__(kBlock) void k_adj_pairs_list(GridDev g, int64_t n, Consts k,
                                                            const double *__restrict__ rec,
                                                            StateDev st, AdjRec ad, GradDev out) {
-    __shared__ double2 fbuf[kBlock / 64][64 * 8];
-    __shared__ double2 abuf[kBlock / 64][64 * 8];
+    __shared__ double2 fbuf[kBlock / 64][kLdsWave];
+    __shared__ double2 abuf[kBlock / 64][kLdsWave];
     double2 *bf = fbuf[threadIdx.x >> 6];
     double2 *ba = abuf[threadIdx.x >> 6];
     const int64_t s = xcd_block(gridDim.x) * kBlock + threadIdx.x;
@@ -398,12 +404,15 @@ __global__ __launch_bounds__(kBlock) void k_adj_pairs_list(GridDev g, int64_t n,
         const int cnt = act ? g.pl_count[s] : 0;
         const AdjOwn o = adj_own(rec, ad, act ? s : w0);
         AdjAcc acc;
+        const char *rf = reinterpret_cast<const char *>(rec);
+        const char *ra = reinterpret_cast<const char *>(ad.arec);
+        const int32_t *row = g.pl_slot + base + __lane_id();
+        int e0 = steps > 0 ? row[0] : 0;
         for (int j = 0; j < steps; ++j) {
-            const int32_t *idx = g.pl_slot + base + ((int64_t)j << 6);
             {
-                const double *const recs[2] = {rec, ad.arec};
-                double2 *const bufs[2] = {bf, ba};
-                wave_gather<2>(recs, bufs, idx);
+                stage<8>(bf, fetch<8>(rf, kRec * 8, e0));
+                stage<8>(ba, fetch<8>(ra, kAdj * 8, e0));
+                if (j + 1 < steps) e0 = row[(int64_t)(j + 1) << 6];
             }
             wave_sync();
             if (j < cnt) {

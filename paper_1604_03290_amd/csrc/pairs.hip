@@ -32,9 +32,10 @@ __global__ __launch_bounds__(kBlock) void k_pl_gather(GridDev g, const double *_
 }
 
 // Count pass (kFill = false) or fill pass.  The fill runs over every slot of
-// every group, including the lanes past n of the last group, and writes -1 into
-// the padding after each list so that readers of whole groups never meet an
-// unset entry.
+// every group, including the lanes past n of the last group, and fills the
+// padding after each list with the slot itself (n - 1 for lanes past n), so
+// that every entry of a group is a valid slot and readers of whole groups load
+// without guards.
 template <bool kFill>
 __global__ __launch_bounds__(kBlock) void k_pl_scan(GridDev g, const double *__restrict__ x0,
                                                     int64_t n, double r2, double reach,
@@ -49,7 +50,7 @@ __global__ __launch_bounds__(kBlock) void k_pl_scan(GridDev g, const double *__r
         base = block_start[s / kWave] + (s % kWave);
         maxc = (block_start[s / kWave + 1] - block_start[s / kWave]) / kWave;
         if (s >= n) {
-            for (int64_t j = 0; j < maxc; ++j) slot[base + kWave * j] = -1;
+            for (int64_t j = 0; j < maxc; ++j) slot[base + kWave * j] = (int32_t)(n - 1);
             return;
         }
     }
@@ -65,7 +66,7 @@ __global__ __launch_bounds__(kBlock) void k_pl_scan(GridDev g, const double *__r
         }
     });
     if (kFill)
-        for (int64_t j = c; j < maxc; ++j) slot[base + kWave * j] = -1;
+        for (int64_t j = c; j < maxc; ++j) slot[base + kWave * j] = (int32_t)s;
     else
         count[s] = c;
 }

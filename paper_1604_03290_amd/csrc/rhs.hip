@@ -56,10 +56,13 @@ __global__ __launch_bounds__(kBlock) void k_narrow(const double *__restrict__ re
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const double *r = rec + s * kRec;
-    float4 *o = reinterpret_cast<float4 *>(r32 + s * kRec32);
-    o[0] = make_float4((float)r[3], (float)r[4], (float)r[5], (float)r[6]);
-    o[1] = make_float4((float)r[7], (float)r[14], (float)r[8], (float)r[9]);
-    o[2] = make_float4((float)r[10], (float)r[11], (float)r[12], (float)r[13]);
+    char *o = reinterpret_cast<char *>(r32) + s * kRec32Bytes;
+    *reinterpret_cast<double2 *>(o) = make_double2(r[0], r[1]);
+    *reinterpret_cast<double *>(o + 16) = r[2];
+    *reinterpret_cast<float2 *>(o + 24) = make_float2((float)r[3], (float)r[4]);
+    *reinterpret_cast<float4 *>(o + 32) = make_float4((float)r[5], (float)r[6], (float)r[7], (float)r[14]);
+    *reinterpret_cast<float4 *>(o + 48) = make_float4((float)r[8], (float)r[9], (float)r[10], (float)r[11]);
+    *reinterpret_cast<float4 *>(o + 64) = make_float4((float)r[12], (float)r[13], 0.0f, 0.0f);
 }
 
 // ---------------------------------------------------------- pairs, FP64 --
@@ -97,7 +100,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs64_list(GridDev g, int64_t n, C
                                                          const double *__restrict__ rec,
                                                          StateDev st, OutDev out,
                                                          double *__restrict__ Lout) {
-    __shared__ double2 lbuf[kBlock / 64][64 * 8];
+    __shared__ double2 lbuf[kBlock / 64][kLdsWave];
     double2 *buf = lbuf[threadIdx.x >> 6];
     const int64_t s = xcd_block(gridDim.x) * kBlock + threadIdx.x;
     const int64_t w0 = s - __lane_id();
@@ -115,12 +118,12 @@ __global__ __launch_bounds__(kBlock) void k_pairs64_list(GridDev g, int64_t n, C
     const double rho_a = p3.x;
     Acc64 acc;
     acc.rs = p3.y * k.Wn;  // own term m_a W(0)
+    const char *recs = reinterpret_cast<const char *>(rec);
+    const int32_t *row = g.pl_slot + base + __lane_id();
+    int e0 = steps > 0 ? row[0] : 0;
     for (int j = 0; j < steps; ++j) {
-        {
-            const double *const recs[1] = {rec};
-            double2 *const bufs[1] = {buf};
-            wave_gather<1>(recs, bufs, g.pl_slot + base + ((int64_t)j << 6));
-        }
+        stage<8>(buf, fetch<8>(recs, kRec * 8, e0));
+        if (j + 1 < steps) e0 = row[(int64_t)(j + 1) << 6];
         wave_sync();
         if (j < cnt) {
             const double2 b0 = wave_chunk(buf, 0), b1 = wave_chunk(buf, 1);
@@ -145,39 +148,113 @@ __global__ __launch_bounds__(kBlock) void k_pairs64_list(GridDev g, int64_t n, C
 }
 
 // ----------------------------------------- pairs, FP32 + Kahan sums --
+// unpacked FP32 record of a partner
+struct Src32 {
+    double x, y, z;
+    float vx, vy, vz, rho, m, V, T[6];
+};
+
+__device__ inline Src32 src32(double2 c0, double2 c1, double2 c2, double2 c3, double2 c4) {
+    Src32 r;
+    r.x = c0.x;
+    r.y = c0.y;
+    r.z = c1.x;
+    const float2 a = __builtin_bit_cast(float2, c1.y);
+    const float4 b = __builtin_bit_cast(float4, c2);
+    const float4 t = __builtin_bit_cast(float4, c3);
+    const float4 u = __builtin_bit_cast(float4, c4);
+    r.vx = a.x; r.vy = a.y; r.vz = b.x; r.rho = b.y; r.m = b.z; r.V = b.w;
+    r.T[0] = t.x; r.T[1] = t.y; r.T[2] = t.z; r.T[3] = t.w; r.T[4] = u.x; r.T[5] = u.y;
+    return r;
+}
+
+__device__ inline Src32 load32(const float *r32, int64_t s) {
+    const double2 *p = reinterpret_cast<const double2 *>(reinterpret_cast<const char *>(r32) +
+                                                         s * kRec32Bytes);
+    return src32(p[0], p[1], p[2], p[3], p[4]);
+}
+
+__device__ inline void pair32_of(const Consts32 &kf, const Src32 &a, const Src32 &b, double d2,
+                                 Acc32 &acc) {
+    pair32(kf, (float)d2, (float)(a.x - b.x), (float)(a.y - b.y), (float)(a.z - b.z),
+           b.vx - a.vx, b.vy - a.vy, b.vz - a.vz, a.rho, b.rho, a.T[0] + b.T[0], a.T[1] + b.T[1],
+           a.T[2] + b.T[2], a.T[3] + b.T[3], a.T[4] + b.T[4], a.T[5] + b.T[5], b.m, b.V, acc);
+}
+
+__device__ inline void post32(const Consts &k, int a, double rho_a, double m_a, const Acc32 &acc,
+                              const StateDev &st, const OutDev &out, double *Lout, int64_t n,
+                              int64_t s) {
+    double L[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) L[c] = acc.L[c].value();
+    const double rs = m_a * k.Wn + acc.rs.value();
+    postpass(k, a, rho_a, L, acc.ax.value(), acc.ay.value(), acc.az.value(), rs, st, out);
+    if (Lout) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) Lout[i * n + s] = L[i];
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_pairs32(GridDev g, int64_t n, Consts k,
                                                     const double *__restrict__ rec,
                                                     const float *__restrict__ r32, StateDev st,
                                                     OutDev out, double *__restrict__ Lout) {
     const int64_t s = xcd_block(gridDim.x) * kBlock + threadIdx.x;
     if (s >= n) return;
-    const double2 *ra = rec2(rec, s);
-    const double2 p0 = ra[0], p1 = ra[1], p3 = ra[3];
-    const double xa = p0.x, ya = p0.y, za = p1.x;
-    const float4 *fa = rec4(r32, s);
-    const float4 o0 = fa[0], o1 = fa[1], o2 = fa[2];
+    const Src32 a = load32(r32, s);
+    const double2 p3 = rec2(rec, s)[3];
     const Consts32 kf = narrow(k);
     Acc32 acc;
-    for_each_candidate(g, s, xa, ya, za, k.reach, [&](int t) {
-        const double2 *rb = rec2(rec, t);
-        const double2 b0 = rb[0], b1 = rb[1];
-        const double d2 = dist2_exact(xa, ya, za, b0.x, b0.y, b1.x);
-        if (!(d2 < k.h2)) return;
-        const float4 *fb = rec4(r32, t);
-        const float4 c0 = fb[0], c1 = fb[1], c2 = fb[2];
-        pair32(kf, (float)d2, (float)(xa - b0.x), (float)(ya - b0.y), (float)(za - b1.x),
-               c0.x - o0.x, c0.y - o0.y, c0.z - o0.z, o0.w, c0.w, o1.z + c1.z, o1.w + c1.w,
-               o2.x + c2.x, o2.y + c2.y, o2.z + c2.z, o2.w + c2.w, c1.x, c1.y, acc);
+    for_each_candidate(g, s, a.x, a.y, a.z, k.reach, [&](int t) {
+        const Src32 b = load32(r32, t);
+        const double d2 = dist2_exact(a.x, a.y, a.z, b.x, b.y, b.z);
+        if (d2 < k.h2) pair32_of(kf, a, b, d2, acc);
     });
-    double L[9];
-#pragma unroll
-    for (int c = 0; c < 9; ++c) L[c] = acc.L[c].value();
-    const double rs = p3.y * k.Wn + acc.rs.value();
-    postpass(k, g.perm[s], p3.x, L, acc.ax.value(), acc.ay.value(), acc.az.value(), rs, st, out);
-    if (Lout) {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) Lout[i * n + s] = L[i];
+    post32(k, g.perm[s], p3.x, p3.y, acc, st, out, Lout, n, s);
+}
+
+// FP32 pair sums over the frozen pair list (cooperative gathers of the 80-byte records)
+__global__ __launch_bounds__(kBlock) void k_pairs32_list(GridDev g, int64_t n, Consts k,
+                                                         const double *__restrict__ rec,
+                                                         const float *__restrict__ r32,
+                                                         StateDev st, OutDev out,
+                                                         double *__restrict__ Lout) {
+    __shared__ double2 lbuf[kBlock / 64][kLdsWave];
+    double2 *buf = lbuf[threadIdx.x >> 6];
+    const int64_t s = xcd_block(gridDim.x) * kBlock + threadIdx.x;
+    const int64_t w0 = s - __lane_id();
+    if (w0 >= n) return;
+    const bool act = s < n;
+    const int64_t base = g.pl_block[w0 >> 6];
+    const int steps = (int)((g.pl_block[(w0 >> 6) + 1] - base) >> 6);
+    const int cnt = act ? g.pl_count[s] : 0;
+    const Src32 a = load32(r32, act ? s : w0);
+    const Consts32 kf = narrow(k);
+    Acc32 acc;
+    const char *recs = reinterpret_cast<const char *>(r32);
+    const int32_t *row = g.pl_slot + base + __lane_id();
+    Fetched<5> f;
+    int e1 = 0;
+    if (steps > 0) f = fetch<5>(recs, kRec32Bytes, row[0]);
+    if (steps > 1) e1 = row[64];
+    for (int j = 0; j < steps; ++j) {
+        stage<5>(buf, f);
+        if (j + 1 < steps) {
+            f = fetch<5>(recs, kRec32Bytes, e1);
+            if (j + 2 < steps) e1 = row[(int64_t)(j + 2) << 6];
+        }
+        wave_sync();
+        if (j < cnt) {
+            const Src32 b = src32(wave_chunk(buf, 0), wave_chunk(buf, 1), wave_chunk(buf, 2),
+                                  wave_chunk(buf, 3), wave_chunk(buf, 4));
+            const double d2 = dist2_exact(a.x, a.y, a.z, b.x, b.y, b.z);
+            if (d2 < k.h2) pair32_of(kf, a, b, d2, acc);
+        }
+        wave_sync();
     }
+    if (!act) return;
+    const double2 p3 = rec2(rec, s)[3];
+    post32(k, g.perm[s], p3.x, p3.y, acc, st, out, Lout, n, s);
 }
 
 }  // namespace
@@ -252,7 +329,10 @@ int rhs_launch(const sph_grid *grid, const sph_state *state, const sph_params *p
         k_narrow<<<blocks_for(n), kBlock, 0, s>>>(rec, n, r32);
         SPH_LAUNCHED();
         TimedRegion t("pairs_fp32comp", s);
-        k_pairs32<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, r32, st, od, L_out);
+        if (g.pl_count)
+            k_pairs32_list<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, r32, st, od, L_out);
+        else
+            k_pairs32<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, r32, st, od, L_out);
         SPH_LAUNCHED();
     }
     return SPH_OK;

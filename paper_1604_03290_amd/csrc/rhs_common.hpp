@@ -67,9 +67,11 @@ inline OutDev out_dev(const sph_deriv *o) {
 //   x y z vx | vy vz rho m | T0 T1 T2 T3 | T4 T5 V -
 // with T = sigma / rho^2 (xx, yy, zz, xy, xz, yz) and V = m / rho.
 constexpr int kRec = 16;
-// FP32 copy of the non-position operands, 48 bytes per slot:
-//   vx vy vz rho | m V T0 T1 | T2 T3 T4 T5
-constexpr int kRec32 = 12;
+// FP32 record, 80 bytes per slot: FP64 position (for the exact partner test and
+// the differences) and the FP32 operands:
+//   x y (f64) | z (f64) vx vy | vz rho m V | T0 T1 T2 T3 | T4 T5 - -
+constexpr int kRec32 = 20;  // in floats
+constexpr int kRec32Bytes = 80;
 
 __device__ inline const double2 *rec2(const double *rec, int64_t s) {
     return reinterpret_cast<const double2 *>(rec + s * kRec);
@@ -86,43 +88,83 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-// Coalesced gather of one record per lane into the wavefront's LDS buffer
-// (64 records of 8 chunks of 16 bytes).  Eight lanes share a record, each
-// moving one chunk, so every load instruction touches 8 records instead of 64;
-// idx[src] is the record of lane src (negative: none, zero-filled).  Chunk c of
-// lane L's record sits at buf[8 L + ((c + L) & 7)], which keeps both the writes
-// and the per-lane reads free of bank conflicts.  Branch free: all index loads,
-// then all record loads (a missing record reads record 0 and is replaced by
-// zeros), then the LDS writes, so each step waits on memory twice.
-// NR record arrays (recs[i], each 16 doubles per record) share the indices.
-template <int NR>
-__device__ inline void wave_gather(const double *const (&recs)[NR], double2 *const (&bufs)[NR],
-                                   const int32_t *__restrict__ idx) {
+// Coalesced gather of one partner record per lane into the wavefront's LDS
+// buffer, in two stages so that a loop can overlap the loads of step j + 1 with
+// the arithmetic of step j:
+//   fetch: the lanes load the 64 records of NC 16-byte chunks (record r of lane
+//          r, r = 0..63) into registers with NC load instructions; instruction
+//          i, lane l moves chunk q = 64 i + l, i.e. chunk q % NC of the record
+//          of lane q / NC, so every instruction touches 64 / NC records and no
+//          lane idles.  A lane's partner slot is its own entry of the list row
+//          (one coalesced load by the caller), handed to the loading lanes by
+//          a lane shuffle.
+//   stage: the registers go to the LDS buffer; chunk c of lane L's record sits
+//          at buf[9 L + c]: the odd record stride (144 bytes) spreads the
+//          per-lane reads of one chunk (wave_chunk) over all banks, and every
+//          address is a per-lane base plus a constant offset.
+// Every list entry is a valid slot (padding repeats a slot), so no load is
+// guarded; lanes ignore the records of their padding entries.
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+constexpr int kLdsRec = 9;              // chunks per record slot in LDS (8 + 1 pad)
+constexpr int kLdsWave = 64 * kLdsRec;  // double2 per wavefront buffer  // register pair, no struct copies
+
+template <int NC>
+struct Fetched {
+    dvec2 v[NC];
+};
+
+template <int NC>
+__device__ inline Fetched<NC> fetch(const char *__restrict__ recs, int stride, int entry) {
+    Fetched<NC> f;
     const int lane = __lane_id();
-    const int c = lane & 7;
-    int t[8];
+    if constexpr (NC == 8) {
+        // record of lane 8 i + (lane >> 3), chunk lane & 7: one base pointer and
+        // one shuffle address with constant offsets serve all eight loads; the
+        // eight shuffles are issued together (the empty asm needs all of them)
+        const char *p = recs + (lane & 7) * 16;
+        const int src = (lane >> 3) * 4;
+        uint32_t t[8];
 #pragma unroll
-    for (int m = 0; m < 8; ++m) t[m] = idx[8 * m + (lane >> 3)];
-    double2 v[NR][8];
+        for (int i = 0; i < 8; ++i) t[i] = (uint32_t)__builtin_amdgcn_ds_bpermute(src + 32 * i, entry);
+        asm volatile("" : "+v"(t[0]), "+v"(t[1]), "+v"(t[2]), "+v"(t[3]), "+v"(t[4]), "+v"(t[5]),
+                     "+v"(t[6]), "+v"(t[7]));
+        // a stride opaque to the compiler makes each address one 64-bit multiply-add
+        uint32_t st = (uint32_t)stride;
+        asm("" : "+s"(st));
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
-        const int64_t tt = t[m] < 0 ? 0 : t[m];
+        for (int i = 0; i < 8; ++i)
+            f.v[i] = *reinterpret_cast<const dvec2 *>(p + (uint64_t)t[i] * st);
+    } else {
 #pragma unroll
-        for (int r = 0; r < NR; ++r)
-            v[r][m] = reinterpret_cast<const double2 *>(recs[r] + tt * kRec)[c];
+        for (int i = 0; i < NC; ++i) {
+            const int q = 64 * i + lane;
+            const int r = q / NC, c = q - r * NC;
+            const uint32_t t = (uint32_t)__builtin_amdgcn_ds_bpermute(4 * r, entry);
+            f.v[i] = *reinterpret_cast<const dvec2 *>(recs + (uint64_t)t * (uint32_t)stride + c * 16);
+        }
     }
+    return f;
+}
+
+template <int NC>
+__device__ inline void stage(double2 *buf, const Fetched<NC> &f) {
+    const int lane = __lane_id();
+    if constexpr (NC == 8) {
+        double2 *b = buf + kLdsRec * (lane >> 3) + (lane & 7);
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
-        const int src = 8 * m + (lane >> 3);
+        for (int i = 0; i < 8; ++i) *reinterpret_cast<dvec2 *>(b + 8 * kLdsRec * i) = f.v[i];
+    } else {
 #pragma unroll
-        for (int r = 0; r < NR; ++r)
-            bufs[r][8 * src + ((c + src) & 7)] = t[m] < 0 ? make_double2(0.0, 0.0) : v[r][m];
+        for (int i = 0; i < NC; ++i) {
+            const int q = 64 * i + lane;
+            const int r = q / NC, c = q - r * NC;
+            *reinterpret_cast<dvec2 *>(buf + kLdsRec * r + c) = f.v[i];
+        }
     }
 }
 
 __device__ inline double2 wave_chunk(const double2 *buf, int c) {
-    const int L = __lane_id();
-    return buf[8 * L + ((c + L) & 7)];
+    return buf[kLdsRec * __lane_id() + c];
 }
 
 // Liquid equation of state with the optional tension cut-off (section 2.5.1).
