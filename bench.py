@@ -62,6 +62,56 @@ def load_workload(name):
     return k, w
 
 
+# HBM bytes per launch of the dominant kernel, from two rocprofv3 counter runs of this
+# script (FETCH_SIZE, then WRITE_SIZE), each scaled by what the same counter reads for the
+# 1 GiB calibration copy.  They hold only for the kernel sources they were taken on: the
+# hash of those files is compared at run time and the figure is dropped on a mismatch.
+TRAFFIC = None
+
+KERNEL_SOURCES = {"k_adj_pairs_list": ("adjoint.hip", "rhs_common.hpp", "common.hpp"),
+                  "k_pairs64_list": ("rhs.hip", "rhs_common.hpp", "common.hpp")}
+
+
+def sources_sha(kernel):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_1604_03290_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+HIST_EDGES = [0, 10, 20, 30, 40, 50, 60, 80, 100, 150, 200, 250, 300, 400, 100000]
+
+
+def approaching_fraction(st, row_ptr, col, torch, chunk=1 << 20):
+    """Fraction of ordered pairs with (v_a - v_b) . (x_a - x_b) < 0, which also evaluate
+    the artificial viscosity; computed over row blocks to bound memory."""
+    n = row_ptr.numel() - 1
+    neg, tot = 0, 0
+    for r0 in range(0, n, chunk):
+        r1 = min(n, r0 + chunk)
+        a, b = int(row_ptr[r0]), int(row_ptr[r1])
+        rows = torch.repeat_interleave(torch.arange(r0, r1, device=row_ptr.device),
+                                       row_ptr[r0 + 1:r1 + 1] - row_ptr[r0:r1])
+        cl = col[a:b].long()
+        wab = ((st.vel[:, rows] - st.vel[:, cl]) * (st.pos[:, rows] - st.pos[:, cl])).sum(0)
+        neg += int((wab < 0).sum())
+        tot += b - a
+    return neg / max(tot, 1)
+
+
+def copy_calibration(torch, nbytes=1 << 30):
+    """One plain device copy of a known size (read nbytes, write nbytes): under a
+    counter run its FETCH_SIZE / WRITE_SIZE give the scale of those counters."""
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    return nbytes
+
+
 def median_ms(fn, reps, torch):
     ts = []
     for _ in range(reps):
@@ -96,10 +146,22 @@ def cpu_baseline(w, budget_s=12.0):
         if el > budget_s or reps >= 5000:
             break
     rate = nnz * reps / el
-    return {"value": rate, "unit": UNIT, "cores": native.threads(), "kind": "oracle",
+    cores = native.threads()
+    # one core, as the paper's own CPU comparison (a shorter budget)
+    native.set_threads(1)
+    reps1, t0 = 0, time.perf_counter()
+    while True:
+        native.rhs(sub.pos, sub.vel, sub.rho, sub.S, sub.m, pv, csr=csr, want_L=False)
+        reps1 += 1
+        el1 = time.perf_counter() - t0
+        if el1 > budget_s / 3 or reps1 >= 5000:
+            break
+    native.set_threads(cores)
+    return {"value": rate, "unit": UNIT, "cores": cores, "kind": "oracle",
+            "single_core_value": nnz * reps1 / el1,
             "sample": f"{n_sample} particles nearest the centre of {w.name} ({nnz} ordered pairs), "
                       f"FP64 C oracle right-hand side over precomputed partner lists, {reps} repetitions "
-                      f"in {el:.1f} s"}
+                      f"in {el:.1f} s on {cores} threads; {reps1} repetitions in {el1:.1f} s on one"}
 
 
 def main():
@@ -138,15 +200,25 @@ def main():
     row_ptr, col = P.sph_neighbours(grid, st.pos, w.h, ws=ws_nb)
     nnz0 = int(row_ptr[-1].item())
     # fraction of ordered pairs that approach (w_ab < 0): they also evaluate Pi
-    rows = torch.repeat_interleave(torch.arange(n, device=dev), row_ptr[1:] - row_ptr[:-1])
-    cl = col.long()
-    wab = ((st.vel[:, rows] - st.vel[:, cl]) * (st.pos[:, rows] - st.pos[:, cl])).sum(0)
-    f_app = float((wab < 0).double().mean())
-    del rows, cl, wab
+    f_app = approaching_fraction(st, row_ptr, col, torch)
+    deg = (row_ptr[1:] - row_ptr[:-1]).double()
+    q = torch.quantile(deg[torch.randperm(n, device=dev)[:1 << 20]],
+                       torch.tensor([0.01, 0.5, 0.99], dtype=torch.float64, device=dev))
+    partners = {"min": int(deg.min()), "p01": float(q[0]), "p50": float(q[1]), "p99": float(q[2]),
+                "max": int(deg.max()), "mean": float(deg.mean()),
+                "histogram_edges": HIST_EDGES,
+                "histogram": torch.bincount(torch.bucketize(deg, torch.tensor(
+                    HIST_EDGES[1:-1], dtype=torch.float64, device=dev), right=True),
+                    minlength=len(HIST_EDGES) - 1).tolist()}
+    del deg
     col_cap = int(col.numel()) + n  # room for pairs formed during the trajectory
 
     ws_pairs = P.workspace(L.SPH_OP_PAIRS, n)
     pl_cap = P.sph_build_pairs(grid, st.pos, ws=ws_pairs)
+    cand = int(grid.pairs[1].long().sum())
+    # load balance = mean over max list length per wavefront, summed over wavefronts
+    pair_list = {"entries": pl_cap, "candidates": cand, "true_pairs_fraction": nnz0 / cand,
+                 "load_balance_mean_over_max_per_wave": cand / pl_cap}
 
     def step():
         g = P.sph_build_cells(st.pos, w.h, skin=skin, box=(lo, hi), ws=ws_build)
@@ -166,6 +238,7 @@ def main():
     step_desc = (f"cell build + frozen pair list + partner CSR + {steps_lf}-step leapfrog ({steps_lf + 1} "
                  f"FP64 right-hand sides) + reverse sweep ({steps_lf + 1} adjoints) for d KE / d (v0, mu, Y0)")
 
+    calib = copy_calibration(torch)
     L.timing_reset()
     L.timing_enable(True)
     torch.cuda.synchronize()
@@ -225,10 +298,16 @@ def main():
            "adjoint_pairs": FLOPS_ADJ + FLOPS_ADJ_APPROACH * f_app,
            "adjoint_L": FLOPS_ADJ_L}[dom]
     achieved = fpp * nnz / (avg_ms * 1e-3) / 1e12
+    kname = {"pairs_fp64": "k_pairs64_list", "adjoint_pairs": "k_adj_pairs_list", "adjoint_L": "k_adj_L_list"}[dom]
+    traffic = None
+    if TRAFFIC and TRAFFIC["kernel"] == kname and TRAFFIC["workload"] == w.name and \
+            TRAFFIC["sources_sha256"] == sources_sha(kname):
+        traffic = TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
     roofline = {"bound": "alu",
-                "kernel": {"pairs_fp64": "k_pairs64", "adjoint_pairs": "k_adj_pairs", "adjoint_L": "k_adj_L"}[dom],
+                "kernel": kname,
                 "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
+                "traffic_unit": "bytes per launch (HBM read + write, counter-scaled)",
                 "avg_launch_ms": avg_ms, "launches": launches, "flops_per_pair": fpp,
                 "share_of_step": tot_ms / args.steps / ms_step,
                 "other": {k: {"avg_launch_ms": v[0] / max(v[1], 1), "launches": v[1]} for k, v in kern.items()}}
@@ -240,11 +319,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "particles": n, "ordered_pairs_per_rhs": nnz,
                    "ordered_pairs_start_end": [nnz0, nnz1], "skin_over_dx": 0.25,
-                   "approaching_pair_fraction": f_app,
+                   "approaching_pair_fraction": f_app, "partners_per_particle": partners,
+                   "pair_list": pair_list,
                    "h_over_dx": 2.4, "leapfrog_steps": steps_lf, "step": step_desc,
                    "grid_dims": list(dims)},
         "roofline": roofline,
         "forms": forms,
+        "copy_calibration_bytes": calib,
         "wall_s": wall,
     }
     if not args.no_cpu_baseline:

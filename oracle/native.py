@@ -29,6 +29,7 @@ def lib():
             _build.build()
         L = C.CDLL(_build.LIB)
         L.orc_threads.restype = C.c_int
+        L.orc_set_threads.argtypes = [C.c_int]
         L.orc_kernel.argtypes = [_d, _d, _pd, _pd]
         L.orc_count_neighbours.argtypes = [_i64, _pd, _d, _pi64, _i64, _pi64]
         L.orc_count_neighbours.restype = _i64
@@ -55,6 +56,11 @@ def _i64a(a):
 def threads() -> int:
     """OpenMP threads the oracle uses (OMP_NUM_THREADS or the core count)."""
     return int(lib().orc_threads())
+
+
+def set_threads(k: int) -> None:
+    """OpenMP threads for later calls (timing only)."""
+    lib().orc_set_threads(int(k))
 
 
 def kernel(r: float, h: float):

@@ -65,6 +65,16 @@ int orc_threads(void)
 #endif
 }
 
+/* Sets the OpenMP thread count of later calls (timing only; results do not depend on it). */
+void orc_set_threads(int k)
+{
+#ifdef _OPENMP
+    if (k > 0) omp_set_num_threads(k);
+#else
+    (void)k;
+#endif
+}
+
 /* ---------------------------------------------------------------- kernel --
  * Cubic B-spline (section 3.1.1, kernel function), D = 3, s = 8/pi:
  *   W  = s/h^3 (6q^3 - 6q^2 + 1)       0 <= q < 1/2
