@@ -276,9 +276,10 @@ int sph_rhs_adjoint(const sph_grid *grid, const sph_state *state, const sph_para
  *   s_final      final state out (may alias the arrays of s0)
  *   checkpoints  device, sph_checkpoint_bytes(n, steps) bytes, or NULL; holds
  *                (x, v, rho, S, F) at the start of every step and at the end
- *                (user order) and the velocity gradient behind each F (the
- *                grid's slot order), as needed by sph_leapfrog_adjoint, which
- *                must be given the same grid
+ *                and the velocity gradient behind each F, all in the grid's
+ *                slot order (the trajectory is integrated in slot order), as
+ *                needed by sph_leapfrog_adjoint, which must be given the same
+ *                grid
  * The grid must have been built with a skin covering the trajectory's largest
  * displacement (device flag STALE_GRID otherwise).  Errors: as sph_rhs. */
 int sph_leapfrog(const sph_grid *grid, const sph_state *s0, const sph_params *params,

@@ -161,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_post(GridDev g, int64_t n, Const
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double mu_part = 0.0;
     if (s < n) {
-        const int a = g.perm[s];
+        const int a = io_index(g, s);
         double L[3][3];
 #pragma unroll
         for (int i = 0; i < 9; ++i) L[i / 3][i % 3] = ad.L[i][s];
@@ -380,7 +380,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_pairs(GridDev g, int64_t n, Cons
             adj_pair(k, o, d2, b0, b1, rb[2], rb[3], rb[4], rb[5], rb[6], rb[7], qb[0], qb[1],
                      qb[2], qb[3], qb[4], qb[5], qb[6], acc);
         });
-        y0_part = adj_pre(k, ad, o, acc, s, g.perm[s], st, out);
+        y0_part = adj_pre(k, ad, o, acc, s, io_index(g, s), st, out);
     }
     const double tot = block_sum(y0_part);
     if (threadIdx.x == 0) ad.part_y0[blockIdx.x] = tot;
@@ -427,7 +427,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_pairs_list(GridDev g, int64_t n,
             }
             wave_sync();
         }
-        if (act) y0_part = adj_pre(k, ad, o, acc, s, g.perm[s], st, out);
+        if (act) y0_part = adj_pre(k, ad, o, acc, s, io_index(g, s), st, out);
     }
     const double tot = block_sum(y0_part);
     if (threadIdx.x == 0) ad.part_y0[blockIdx.x] = tot;
@@ -488,9 +488,10 @@ GradDev grad_dev(const sph_fields *g, int accumulate) {
 // accumulated (accumulate != 0) into grad; dparams written or accumulated.
 int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_params *params,
                        const CotDev &cot, const GradDev &grad, double *dparams, int accumulate_params,
-                       Carve &c, hipStream_t s, const double *L_in) {
+                       Carve &c, hipStream_t s, const double *L_in, bool slot_state) {
     const int64_t n = grid->n;
     GridDev g = grid_dev(grid);
+    if (slot_state) g.io = nullptr;
     Consts k = make_consts(*params, g.delta);
     double *rec = c.take<double>((size_t)n * kRec);
     AdjRec ad = carve_adj(c, n);

@@ -63,6 +63,9 @@ struct GridDev {
     double cell, inv_cell;
     double delta;  // tolerated movement since binning: skin / 2
     const int32_t *__restrict__ perm;
+    // index of slot s in the state and output arrays: perm[s] (user order), or s
+    // itself when the caller keeps its arrays in slot order (null)
+    const int32_t *__restrict__ io;
     const int32_t *__restrict__ cell_start;
     const int32_t *__restrict__ cell_of;
     // frozen candidate-pair list (null count = none)
@@ -85,6 +88,7 @@ inline GridDev grid_dev(const sph_grid *g) {
     d.inv_cell = 1.0 / g->cell;
     d.delta = 0.5 * g->skin;
     d.perm = g->perm;
+    d.io = g->perm;
     d.cell_start = g->cell_start;
     d.cell_of = g->cell_of;
     d.pl_count = g->pairs ? g->pairs->count : nullptr;
@@ -96,6 +100,8 @@ inline GridDev grid_dev(const sph_grid *g) {
 }
 
 int check_grid(const sph_grid *g);
+
+__device__ inline int io_index(const GridDev &g, int64_t s) { return g.io ? g.io[s] : (int)s; }
 
 __device__ inline int cell_index(double p, double lo, double inv_cell, int ncell) {
     double t = floor((p - lo) * inv_cell);

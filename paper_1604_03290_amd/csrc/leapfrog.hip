@@ -8,8 +8,11 @@
 //     U_{n+1} = U' + dt/2 F_{n+1}, S <- f_Y(S) S          (kick)
 //
 // f_Y = min(Y0^2 / (3 J2), 1) is the von Mises factor of section 2.6.  The
-// checkpoint of step k holds (x_k, v_k, rho_k, S_k, F_k) in user order and the
-// velocity gradient of F_k in the grid's slot order, 32 arrays of n doubles.  The reverse sweep walks the steps backwards, recomputing U' from
+// trajectory is integrated in the grid's slot order (the state is permuted once
+// at the start and back at the end), so every per-particle pass reads and
+// writes contiguous arrays.  The checkpoint of step k holds (x_k, v_k, rho_k,
+// S_k, F_k) and the velocity gradient behind F_k, 32 arrays of n doubles in
+// slot order.  The reverse sweep walks the steps backwards, recomputing U' from
 // the checkpoint, and applies in turn the adjoints of the second kick, of the
 // right-hand side at (x_{n+1}, U'), of the drift and of the first kick.
 #include "common.hpp"
@@ -69,6 +72,31 @@ __global__ __launch_bounds__(kBlock) void k_store(Fields13 f, Deriv10 d, int64_t
     for (int c = 0; c < 13; ++c) slab[c * n + i] = f.p[c][i];
 #pragma unroll
     for (int c = 0; c < 10; ++c) slab[(13 + c) * n + i] = d.p[c][i];
+}
+
+// user order -> slot order: dst[c][s] = src[c][perm[s]] (a null source gives 0)
+struct Src14 {
+    const double *p[14];
+};
+struct Dst14 {
+    double *p[14];
+};
+
+__global__ __launch_bounds__(kBlock) void k_to_slots(Src14 src, Dst14 dst, int nc,
+                                                     const int32_t *__restrict__ perm, int64_t n) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int a = perm[s];
+    for (int c = 0; c < nc; ++c) dst.p[c][s] = src.p[c] ? src.p[c][a] : 0.0;
+}
+
+// slot order -> user order: dst[c][perm[s]] = src[c][s]
+__global__ __launch_bounds__(kBlock) void k_to_users(Src14 src, Dst14 dst, int nc,
+                                                     const int32_t *__restrict__ perm, int64_t n) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int a = perm[s];
+    for (int c = 0; c < nc; ++c) dst.p[c][a] = src.p[c][s];
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill(double *p, int64_t n, double v) {
@@ -204,13 +232,37 @@ sph_state state_struct(const Fields13 &f, const double *m, int64_t n) {
     return s;
 }
 
-int copy_fields(const sph_state *src, const Fields13 &dst, int64_t n, hipStream_t s) {
-    const double *p[13] = {src->x,   src->y,   src->z,   src->vx,  src->vy,  src->vz, src->rho,
-                           src->sxx, src->syy, src->szz, src->sxy, src->sxz, src->syz};
-    for (int c = 0; c < 13; ++c)
-        if (p[c] != dst.p[c])
-            SPH_HIP_TRY(hipMemcpyAsync(dst.p[c], p[c], n * sizeof(double), hipMemcpyDeviceToDevice, s));
+// state (13 arrays) and masses, user order -> slot order
+int state_to_slots(const sph_grid *grid, const sph_state *src, const Fields13 &dst, double *m,
+                   hipStream_t s) {
+    const Src14 a{{src->x, src->y, src->z, src->vx, src->vy, src->vz, src->rho, src->sxx,
+                   src->syy, src->szz, src->sxy, src->sxz, src->syz, src->m}};
+    Dst14 b;
+    for (int c = 0; c < 13; ++c) b.p[c] = dst.p[c];
+    b.p[13] = m;
+    k_to_slots<<<blocks_for(grid->n), kBlock, 0, s>>>(a, b, 14, grid->perm, grid->n);
+    SPH_LAUNCHED();
     return SPH_OK;
+}
+
+// 13 fields, slot order -> user order
+int fields_to_users(const sph_grid *grid, const Fields13 &src, const Fields13 &dst, hipStream_t s) {
+    Src14 a;
+    Dst14 b;
+    for (int c = 0; c < 13; ++c) {
+        a.p[c] = src.p[c];
+        b.p[c] = dst.p[c];
+    }
+    a.p[13] = nullptr;
+    b.p[13] = nullptr;
+    k_to_users<<<blocks_for(grid->n), kBlock, 0, s>>>(a, b, 13, grid->perm, grid->n);
+    SPH_LAUNCHED();
+    return SPH_OK;
+}
+
+GradDev grad_of(const Fields13 &f) {
+    return GradDev{f.p[0], f.p[1], f.p[2], f.p[3], f.p[4], f.p[5], f.p[6],
+                   {f.p[7], f.p[8], f.p[9], f.p[10], f.p[11], f.p[12]}, 1};
 }
 
 int check_lf(const sph_grid *grid, const sph_state *s0, const sph_params *params, double dt,
@@ -227,17 +279,20 @@ int check_lf(const sph_grid *grid, const sph_state *s0, const sph_params *params
 
 size_t leapfrog_ws_bytes(int64_t n) {
     Carve c(nullptr);
-    carve_deriv(c, n);
+    carve_deriv(c, n);   // F, slot order
+    carve_fields(c, n);  // state, slot order
+    c.take<double>(n);   // masses, slot order
     c.used += rhs_ws_bytes(n);
     return c.used;
 }
 
 size_t leapfrog_adjoint_ws_bytes(int64_t n) {
     Carve c(nullptr);
-    carve_fields(c, n);  // cotangent of the state
+    carve_fields(c, n);  // cotangent of the state, slot order
     carve_fields(c, n);  // U' (only v, rho, S used; x points at the next checkpoint)
     carve_deriv(c, n);   // cotangent of F_{n+1}
     carve_deriv(c, n);   // cotangent of F_n
+    c.take<double>(n);   // masses, slot order
     c.take<double>(blocks_for(n));
     c.used += adjoint_ws_bytes(n);
     return c.used;
@@ -266,18 +321,19 @@ extern "C" int sph_leapfrog(const sph_grid *grid, const sph_state *s0, const sph
     if ((rc = clear_status(ws, s))) return rc;
     Carve c(ws);
     Deriv10 F = carve_deriv(c, n);
-    Carve rc_ws(ws);  // the right-hand side shares the status word, carves after F
+    const Fields13 U = carve_fields(c, n);
+    double *m = c.take<double>(n);
+    Carve rc_ws(ws);  // the right-hand side shares the status word, carves after these
     rc_ws.used = c.used;
-    const Fields13 U = fields_of(s_final);
-    if ((rc = copy_fields(s0, U, n, s))) return rc;
-    const sph_state st = state_struct(U, s0->m, n);
+    if ((rc = state_to_slots(grid, s0, U, m, s))) return rc;
+    const sph_state st = state_struct(U, m, n);
     const sph_deriv d = deriv_struct(F);
     const double half = 0.5 * dt;
     const unsigned nb = blocks_for(n);
     auto rhs = [&](int k) {
         Carve w = rc_ws;
         double *Lout = checkpoints ? checkpoints + ((size_t)k * kArrays + kLOffset) * n : nullptr;
-        return rhs_launch(grid, &st, params, SPH_FP64, &d, w, s, Lout);
+        return rhs_launch(grid, &st, params, SPH_FP64, &d, w, s, Lout, true);
     };
     if ((rc = rhs(0))) return rc;
     for (int k = 0; k < steps; ++k) {
@@ -297,7 +353,7 @@ extern "C" int sph_leapfrog(const sph_grid *grid, const sph_state *s0, const sph
         k_store<<<nb, kBlock, 0, s>>>(U, F, n, checkpoints + (size_t)steps * kArrays * n);
         SPH_LAUNCHED();
     }
-    return SPH_OK;
+    return fields_to_users(grid, U, fields_of(s_final), s);
 }
 
 extern "C" int sph_leapfrog_adjoint(const sph_grid *grid, const sph_state *s0,
@@ -316,10 +372,11 @@ extern "C" int sph_leapfrog_adjoint(const sph_grid *grid, const sph_state *s0,
     hipStream_t s = (hipStream_t)stream;
     if ((rc = clear_status(ws, s))) return rc;
     Carve c(ws);
-    const Fields13 gU = fields_of(grad0);  // cotangent of the current state, in place
+    const Fields13 gU = carve_fields(c, n);  // cotangent of the current state, slot order
     Fields13 Up = carve_fields(c, n);
     Deriv10 gF1 = carve_deriv(c, n);
     Deriv10 gF0 = carve_deriv(c, n);
+    double *m = c.take<double>(n);
     double *part = c.take<double>(blocks_for(n));
     Carve adj_ws(ws);
     adj_ws.used = c.used;
@@ -328,29 +385,27 @@ extern "C" int sph_leapfrog_adjoint(const sph_grid *grid, const sph_state *s0,
     double *ck = const_cast<double *>(checkpoints);
     const double Y0 = params->Y0;
 
-    // cotangent of the final state
-    const double *cf[13] = {cot_final->x,   cot_final->y,   cot_final->z,   cot_final->vx,
-                            cot_final->vy,  cot_final->vz,  cot_final->rho, cot_final->sxx,
-                            cot_final->syy, cot_final->szz, cot_final->sxy, cot_final->sxz,
-                            cot_final->syz};
-    for (int i = 0; i < 13; ++i) {
-        if (cf[i]) {
-            SPH_HIP_TRY(hipMemcpyAsync(gU.p[i], cf[i], n * sizeof(double), hipMemcpyDeviceToDevice, s));
-        } else {
-            k_fill<<<nb, kBlock, 0, s>>>(gU.p[i], n, 0.0);
-            SPH_LAUNCHED();
-        }
+    // cotangent of the final state and the masses, into slot order
+    {
+        const Src14 a{{cot_final->x, cot_final->y, cot_final->z, cot_final->vx, cot_final->vy,
+                       cot_final->vz, cot_final->rho, cot_final->sxx, cot_final->syy,
+                       cot_final->szz, cot_final->sxy, cot_final->sxz, cot_final->syz, s0->m}};
+        Dst14 b;
+        for (int i = 0; i < 13; ++i) b.p[i] = gU.p[i];
+        b.p[13] = m;
+        k_to_slots<<<nb, kBlock, 0, s>>>(a, b, 14, grid->perm, n);
+        SPH_LAUNCHED();
     }
     k_fill<<<1, 2, 0, s>>>(dparams, 2, 0.0);
     SPH_LAUNCHED();
 
-    const GradDev acc = grad_dev(grad0, 1);
+    const GradDev acc = grad_of(gU);
     auto adjoint_at = [&](const sph_state &st, const Deriv10 &gF, const double *slab) {
         CotDev cot{gF.p[0], gF.p[1], gF.p[2], gF.p[3],
                    {gF.p[4], gF.p[5], gF.p[6], gF.p[7], gF.p[8], gF.p[9]}, nullptr};
         Carve w = adj_ws;
         return rhs_adjoint_launch(grid, &st, params, cot, acc, dparams, 1, w, s,
-                                  slab + (size_t)kLOffset * n);
+                                  slab + (size_t)kLOffset * n, true);
     };
     auto kick_adj = [&](const Fields13 &Uin, const Deriv10 &F, const Deriv10 &gF, int accumulate) {
         Ptr12 t;
@@ -379,7 +434,7 @@ extern "C" int sph_leapfrog_adjoint(const sph_grid *grid, const sph_state *s0,
         // (F_{k+1} already holds the first kick of step k+1 unless k+1 = steps)
         if ((rc = kick_adj(Up, Fk1, gF1, k + 1 < steps ? 1 : 0))) return rc;
         // right-hand side F_{k+1} = F(x_{k+1}, U')
-        const sph_state st1 = state_struct(Upx, s0->m, n);
+        const sph_state st1 = state_struct(Upx, m, n);
         if ((rc = adjoint_at(st1, gF1, slab_k1))) return rc;
         // drift x_{k+1} = x_k + dt v'
         k_drift_adj<<<nb, kBlock, 0, s>>>(gU, n, dt);
@@ -391,6 +446,7 @@ extern "C" int sph_leapfrog_adjoint(const sph_grid *grid, const sph_state *s0,
         gF0 = tmp;
     }
     // F_0 = F(x_0, U_0)
-    const sph_state st0 = state_struct(slab_fields(ck, n), s0->m, n);
-    return adjoint_at(st0, gF1, ck);
+    const sph_state st0 = state_struct(slab_fields(ck, n), m, n);
+    if ((rc = adjoint_at(st0, gF1, ck))) return rc;
+    return fields_to_users(grid, gU, fields_of(grad0), s);
 }

@@ -29,7 +29,7 @@ __global__ __launch_bounds__(kBlock) void k_prepass(GridDev g, StateDev st, int6
                                                     int32_t *__restrict__ status) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
-    const int a = g.perm[s];
+    const int a = io_index(g, s);
     const double x = st.x[a], y = st.y[a], z = st.z[a];
     if (!within_cell(g, (int)s, x, y, z)) raise_flag(status, SPH_ERR_STALE_GRID);
     const double rho = st.rho[a];
@@ -87,7 +87,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs64(GridDev g, int64_t n, Consts
                b3.x, p4.x + b4.x, p4.y + b4.y, p5.x + b5.x, p5.y + b5.y, p6.x + b6.x, p6.y + b6.y,
                b3.y, b7.x, acc);
     });
-    postpass(k, g.perm[s], rho_a, acc.L, acc.ax, acc.ay, acc.az, acc.rs, st, out);
+    postpass(k, io_index(g, s), rho_a, acc.L, acc.ax, acc.ay, acc.az, acc.rs, st, out);
     if (Lout) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) Lout[i * n + s] = acc.L[i];
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs64_list(GridDev g, int64_t n, C
         wave_sync();
     }
     if (!act) return;
-    postpass(k, g.perm[s], rho_a, acc.L, acc.ax, acc.ay, acc.az, acc.rs, st, out);
+    postpass(k, io_index(g, s), rho_a, acc.L, acc.ax, acc.ay, acc.az, acc.rs, st, out);
     if (Lout) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) Lout[i * n + s] = acc.L[i];
@@ -210,7 +210,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs32(GridDev g, int64_t n, Consts
         const double d2 = dist2_exact(a.x, a.y, a.z, b.x, b.y, b.z);
         if (d2 < k.h2) pair32_of(kf, a, b, d2, acc);
     });
-    post32(k, g.perm[s], p3.x, p3.y, acc, st, out, Lout, n, s);
+    post32(k, io_index(g, s), p3.x, p3.y, acc, st, out, Lout, n, s);
 }
 
 // FP32 pair sums over the frozen pair list (cooperative gathers of the 80-byte records)
@@ -254,7 +254,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs32_list(GridDev g, int64_t n, C
     }
     if (!act) return;
     const double2 p3 = rec2(rec, s)[3];
-    post32(k, g.perm[s], p3.x, p3.y, acc, st, out, Lout, n, s);
+    post32(k, io_index(g, s), p3.x, p3.y, acc, st, out, Lout, n, s);
 }
 
 }  // namespace
@@ -308,9 +308,11 @@ int check_deriv(const sph_deriv *o) {
 
 // Forward right-hand side on a carved workspace (also used by the leapfrog).
 int rhs_launch(const sph_grid *grid, const sph_state *state, const sph_params *params,
-               int precision, const sph_deriv *out, Carve &c, hipStream_t s, double *L_out) {
+               int precision, const sph_deriv *out, Carve &c, hipStream_t s, double *L_out,
+               bool slot_state) {
     const int64_t n = grid->n;
     GridDev g = grid_dev(grid);
+    if (slot_state) g.io = nullptr;
     Consts k = make_consts(*params, g.delta);
     double *rec = c.take<double>((size_t)n * kRec);
     float *r32 = c.take<float>((size_t)n * kRec32);

@@ -377,10 +377,12 @@ GradDev grad_dev(const sph_fields *g, int accumulate);
 int check_grad(const sph_fields *g);
 size_t adjoint_ws_bytes(int64_t n);
 // L_in (nullable): the forward velocity gradient of the same state in slot order
-// (9 arrays of n); when null it is recomputed
+// (9 arrays of n); when null it is recomputed.  slot_state: the state, cotangent
+// and gradient arrays are in the grid's slot order instead of user order.
 int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_params *params,
                        const CotDev &cot, const GradDev &grad, double *dparams, int accumulate_params,
-                       Carve &c, hipStream_t s, const double *L_in = nullptr);
+                       Carve &c, hipStream_t s, const double *L_in = nullptr,
+                       bool slot_state = false);
 // dparams[0] (+)= sum of p0, dparams[1] (+)= sum of p1 (null parts skipped),
 // fixed summation order
 int reduce_params_launch(const double *p0, const double *p1, int64_t m, double *dparams,
@@ -392,10 +394,11 @@ int prepass_launch(const GridDev &g, const StateDev &st, int64_t n, const Consts
 int check_state(const sph_grid *grid, const sph_state *st);
 int check_params(const sph_grid *grid, const sph_params *pr);
 int check_deriv(const sph_deriv *o);
-// L_out (nullable): the velocity gradient of every slot, 9 arrays of n (slot order)
+// L_out (nullable): the velocity gradient of every slot, 9 arrays of n (slot order).
+// slot_state: the state and output arrays are in the grid's slot order.
 int rhs_launch(const sph_grid *grid, const sph_state *state, const sph_params *params,
                int precision, const sph_deriv *out, Carve &c, hipStream_t s,
-               double *L_out = nullptr);
+               double *L_out = nullptr, bool slot_state = false);
 size_t rhs_ws_bytes(int64_t n);
 
 // Deterministic sum over a 256-thread block (fixed tree); every thread must call it.
