@@ -34,6 +34,7 @@ METRIC = "pair interactions/s for sph_rhs (FP64 vs FP32-comp) and adjoint, 1 MI3
 UNIT = "pair interactions/s"
 PEAK_FP64_TFLOPS = 78.6  # MI355X vector FP64
 PEAK_HBM_GBS = 8000.0
+CELLS_PER_H = 2  # cell edge (h + skin) / 2: fewer candidates per row sweep than edge h + skin
 
 # Algorithmic FP64 operations per ordered pair (FMA = 2, square root and division = 1):
 # right-hand side = distance, square root, kernel, gradient, density sum, velocity
@@ -180,7 +181,7 @@ def main():
     steps_lf = max(w.steps, 1)
     skin = 0.25 * w.dx
     lo, hi = P.api.default_box(st.pos, w.h, skin)
-    dims, ncells, _ = L.grid_geometry(lo, hi, w.h, skin, 1)
+    dims, ncells, _ = L.grid_geometry(lo, hi, w.h, skin, CELLS_PER_H)
     n = w.n
     ws_build = P.workspace(L.SPH_OP_BUILD, n, ncells)
     ws_nb = P.workspace(L.SPH_OP_NEIGHBOURS, n)
@@ -196,7 +197,7 @@ def main():
     cot = {"vel": torch.empty_like(st.vel)}
     grad = P.api._fields(n, dev)
 
-    grid = P.sph_build_cells(st.pos, w.h, skin=skin, box=(lo, hi), ws=ws_build)
+    grid = P.sph_build_cells(st.pos, w.h, skin=skin, cells_per_h=CELLS_PER_H, box=(lo, hi), ws=ws_build)
     row_ptr, col = P.sph_neighbours(grid, st.pos, w.h, ws=ws_nb)
     nnz0 = int(row_ptr[-1].item())
     # fraction of ordered pairs that approach (w_ab < 0): they also evaluate Pi
@@ -221,7 +222,7 @@ def main():
                  "load_balance_mean_over_max_per_wave": cand / pl_cap}
 
     def step():
-        g = P.sph_build_cells(st.pos, w.h, skin=skin, box=(lo, hi), ws=ws_build)
+        g = P.sph_build_cells(st.pos, w.h, skin=skin, cells_per_h=CELLS_PER_H, box=(lo, hi), ws=ws_build)
         P.sph_build_pairs(g, st.pos, capacity=pl_cap, ws=ws_pairs)
         P.sph_neighbours(g, st.pos, w.h, col_cap=col_cap, ws=ws_nb)
         P.sph_leapfrog(g, st, w.params, w.dt, steps_lf, checkpoints=ck, out=fin, ws=ws_lf)
@@ -261,15 +262,15 @@ def main():
 
     # per-form rates on the initial state (median of reps); the right-hand side and the
     # adjoint read the frozen pair list, the "cells" form sweeps the cell rows instead
-    g = P.sph_build_cells(st.pos, w.h, skin=skin, box=(lo, hi), ws=ws_build)
+    g = P.sph_build_cells(st.pos, w.h, skin=skin, cells_per_h=CELLS_PER_H, box=(lo, hi), ws=ws_build)
     forms = {"build_cells": {"ms": median_ms(
-        lambda: P.sph_build_cells(st.pos, w.h, skin=skin, box=(lo, hi), ws=ws_build), args.form_reps, torch)}}
+        lambda: P.sph_build_cells(st.pos, w.h, skin=skin, cells_per_h=CELLS_PER_H, box=(lo, hi), ws=ws_build), args.form_reps, torch)}}
     forms["build_pairs"] = {"ms": median_ms(
         lambda: P.sph_build_pairs(g, st.pos, capacity=pl_cap, ws=ws_pairs), args.form_reps, torch),
         "entries": pl_cap}
     forms["neighbours_csr"] = {"ms": median_ms(
         lambda: P.sph_neighbours(g, st.pos, w.h, col_cap=col_cap, ws=ws_nb), args.form_reps, torch)}
-    gc = P.sph_build_cells(st.pos, w.h, skin=skin, box=(lo, hi))
+    gc = P.sph_build_cells(st.pos, w.h, skin=skin, cells_per_h=CELLS_PER_H, box=(lo, hi))
     oc = P.api.new_deriv(n)
     ms = median_ms(lambda: P.sph_rhs(gc, st, w.params, "fp64", out=oc, ws=ws_rhs), args.form_reps, torch)
     forms["rhs_fp64_cell_sweep"] = {"ms": ms, "pairs_per_s": nnz0 / (ms * 1e-3)}
@@ -321,7 +322,7 @@ def main():
                    "ordered_pairs_start_end": [nnz0, nnz1], "skin_over_dx": 0.25,
                    "approaching_pair_fraction": f_app, "partners_per_particle": partners,
                    "pair_list": pair_list,
-                   "h_over_dx": 2.4, "leapfrog_steps": steps_lf, "step": step_desc,
+                   "h_over_dx": 2.4, "cells_per_h": CELLS_PER_H, "leapfrog_steps": steps_lf, "step": step_desc,
                    "grid_dims": list(dims)},
         "roofline": roofline,
         "forms": forms,

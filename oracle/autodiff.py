@@ -169,6 +169,29 @@ def leapfrog(pos, vel, rho, S6, m, par, steps: int, dt: float, mu=None, Y0=None)
     return x, v, r, S
 
 
+def leapfrog_grad_all(w, steps: int, dt: float, cot: dict):
+    """Gradients of the linear objective J = sum over fields f of <cot[f], f_final>
+    (fields pos (3, n), vel (3, n), rho (n), S (6, n); missing ones count as zero)
+    with respect to every initial field and to (mu, Y0).
+    Returns dict J, pos, vel, rho, S (initial-state gradients), mu, Y0."""
+    pos, vel, rho, S, m, par = as_tensors(w)
+    for t in (pos, vel, rho, S):
+        t.requires_grad_(True)
+    mu = torch.tensor(float(par[3]), dtype=DT, requires_grad=True)
+    Y0 = torch.tensor(float(par[4]), dtype=DT, requires_grad=True)
+    final = dict(zip(("pos", "vel", "rho", "S"),
+                     leapfrog(pos, vel, rho, S, m, par, steps, dt, mu=mu, Y0=Y0)))
+    J = sum((torch.from_numpy(np.asarray(cot[k], dtype=np.float64)) * final[k]).sum()
+            for k in final if k in cot)
+    g = torch.autograd.grad(J, [pos, vel, rho, S, mu, Y0], allow_unused=True)
+    like = (w.pos, w.vel, w.rho, w.S)
+    out = {k: (g[i].detach().numpy() if g[i] is not None else np.zeros_like(like[i]))
+           for i, k in enumerate(("pos", "vel", "rho", "S"))}
+    out.update(J=float(J.detach()), mu=float(g[4]) if g[4] is not None else 0.0,
+               Y0=float(g[5]) if g[5] is not None else 0.0)
+    return out
+
+
 def leapfrog_grad(w, steps: int, dt: float, objective: str = "ke", direction=None):
     """Gradients of a final-state objective with respect to (v0, mu, Y0).
 

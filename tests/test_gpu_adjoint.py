@@ -75,9 +75,9 @@ def test_rhs_adjoint_partial_cotangents():
     assert float(got["mu"]) == 0.0 and np.all(got["vel"].cpu().numpy() == 0.0)
 
 
-def run_leapfrog(w, steps, skin_dx=0.5, pairs=True):
+def run_leapfrog(w, steps, skin_dx=0.5, pairs=True, cells_per_h=1):
     st = gpu_state(w)
-    g = P.sph_build_cells(st.pos, w.h, skin=skin_dx * w.dx, pairs=pairs)
+    g = P.sph_build_cells(st.pos, w.h, skin=skin_dx * w.dx, cells_per_h=cells_per_h, pairs=pairs)
     fin, ck = P.sph_leapfrog(g, st, w.params, w.dt, steps)
     assert P.workspace_status(fin._ws) == 0
     return st, g, fin, ck
@@ -96,11 +96,11 @@ def test_leapfrog_matches_oracle_trajectory():
     assert rel(fin.S.cpu().numpy(), s.numpy()) < 1e-11
 
 
-@pytest.mark.parametrize("name,steps,pairs", [("cube10", 8, False), ("cube10", 8, True),
-                                              ("cube8_visc", 20, True)])
-def test_leapfrog_gradient_matches_oracle(name, steps, pairs):
+@pytest.mark.parametrize("name,steps,pairs,cph", [("cube10", 8, False, 1), ("cube10", 8, True, 1),
+                                                  ("cube10", 8, True, 2), ("cube8_visc", 20, True, 1)])
+def test_leapfrog_gradient_matches_oracle(name, steps, pairs, cph):
     w = small(name)
-    st, g, fin, ck = run_leapfrog(w, steps, pairs=pairs)
+    st, g, fin, ck = run_leapfrog(w, steps, pairs=pairs, cells_per_h=cph)
     cot = {"vel": (fin.vel * fin.m).contiguous()}  # d KE / d v_final
     got = P.sph_leapfrog_adjoint(g, st, w.params, w.dt, steps, ck, cot)
     assert P.workspace_status(got["_ws"]) == 0
@@ -108,6 +108,31 @@ def test_leapfrog_gradient_matches_oracle(name, steps, pairs):
     assert rel(got["vel"].cpu().numpy(), ref["v0"]) < 1e-10
     assert abs(float(got["mu"]) - ref["mu"]) <= 1e-10 * abs(ref["mu"])
     assert abs(float(got["Y0"]) - ref["Y0"]) <= 1e-10 * abs(ref["Y0"])
+
+
+def test_leapfrog_gradient_all_fields_matches_oracle():
+    """A linear objective of every final field: gradients of every initial field
+    (exercises the slot-order permutations of state, cotangent and gradient)."""
+    w = small("cube8_visc")
+    steps = 6
+    st, g, fin, ck = run_leapfrog(w, steps, pairs=True, cells_per_h=2)
+    rng = np.random.default_rng(11)
+    cot = {"pos": rng.normal(size=(3, w.n)), "vel": rng.normal(size=(3, w.n)),
+           "rho": rng.normal(size=w.n) * 1e-3, "S": rng.normal(size=(6, w.n)) * 1e-9}
+    got = P.sph_leapfrog_adjoint(g, st, w.params, w.dt, steps, ck,
+                                 {k: torch.as_tensor(v).cuda().contiguous() for k, v in cot.items()})
+    assert P.workspace_status(got["_ws"]) == 0
+    ref = AD.leapfrog_grad_all(w, steps, w.dt, cot)
+    for k in ("pos", "vel", "rho", "S"):
+        assert rel(got[k].cpu().numpy(), ref[k]) < 1e-10, k
+    assert abs(float(got["mu"]) - ref["mu"]) <= 1e-10 * abs(ref["mu"])
+    assert abs(float(got["Y0"]) - ref["Y0"]) <= 1e-10 * abs(ref["Y0"])
+    # the final state itself
+    pos, vel, rho, S, m, par = AD.as_tensors(w)
+    with torch.no_grad():
+        x, v, r, s = AD.leapfrog(pos, vel, rho, S, m, par, steps, w.dt)
+    assert rel(fin.pos.cpu().numpy() - w.pos, x.numpy() - w.pos) < 1e-11
+    assert rel(fin.S.cpu().numpy(), s.numpy()) < 1e-11
 
 
 # ------------------------------------------------ full size: 64,000 particles, 20 steps

@@ -145,7 +145,8 @@ VARIANTS = ["cube16", "cube16_shuffled", "cube12_visc", "cube9_lattice_rotation"
 
 
 PATHS = {"cells1": dict(cells_per_h=1), "cells2": dict(cells_per_h=2),
-         "pairs": dict(pairs=True), "pairs_skin": dict(pairs=True, skin=0.02)}
+         "pairs": dict(pairs=True), "pairs_skin": dict(pairs=True, skin=0.02),
+         "pairs2_skin": dict(pairs=True, skin=0.02, cells_per_h=2)}
 
 
 @pytest.mark.parametrize("name", VARIANTS)

@@ -88,6 +88,33 @@ def test_leapfrog_gradients_match_finite_differences():
     assert abs(fd - ad) <= 1e-6 * abs(ad)
 
 
+def test_leapfrog_all_field_gradients_match_finite_differences():
+    """Linear objective of every final field; finite differences along random
+    directions of the initial positions, density and stress."""
+    w = small(seed=23, n_side=5)
+    steps, dt = 3, 0.2 * w.dx / 5000.0
+    rng = np.random.default_rng(4)
+    cot = {"pos": rng.normal(size=(3, w.n)), "vel": rng.normal(size=(3, w.n)),
+           "rho": rng.normal(size=w.n) * 1e-3, "S": rng.normal(size=(6, w.n)) * 1e-9}
+    g = AD.leapfrog_grad_all(w, steps, dt, cot)
+
+    def J(**kw):
+        pos, vel, rho, S, m, par = AD.as_tensors(w)
+        args = dict(pos=pos, rho=rho, S=S)
+        for k, v in kw.items():
+            args[k] = torch.from_numpy(np.ascontiguousarray(v, dtype=np.float64))
+        with torch.no_grad():
+            f = AD.leapfrog(args["pos"], vel, args["rho"], args["S"], m, par, steps, dt)
+        return sum(float((torch.from_numpy(cot[k]) * t).sum()) for k, t in zip(("pos", "vel", "rho", "S"), f))
+
+    for name, base, scale in (("pos", w.pos, 1e-4 * w.dx), ("rho", w.rho, 1e-6 * 2700.0),
+                              ("S", w.S, 1e-6 * 6.75e7)):
+        d = rng.normal(size=base.shape)
+        fd = (J(**{name: base + scale * d}) - J(**{name: base - scale * d})) / (2 * scale)
+        ad = float((g[name] * d).sum())
+        assert abs(fd - ad) <= 1e-6 * max(abs(ad), 1e-300), (name, fd, ad)
+
+
 @pytest.mark.parametrize("axis", ["px", "py", "pz"])
 def test_momentum_objective_closed_form(axis):
     w = small(seed=31, n_side=5)
