@@ -34,9 +34,9 @@ def gpu_rhs(w, precision="fp64", cells_per_h=1, skin=0.0, grid_pos=None, pairs=F
     return {k: v.cpu().numpy() for k, v in out.items() if k != "_ws"}
 
 
-def gpu_csr(w_pos, h, cells_per_h=1, skin=0.0):
+def gpu_csr(w_pos, h, cells_per_h=1, skin=0.0, pairs=False):
     pos = torch.as_tensor(w_pos, dtype=torch.float64).cuda().contiguous()
-    g = P.sph_build_cells(pos, h, skin=skin, cells_per_h=cells_per_h)
+    g = P.sph_build_cells(pos, h, skin=skin, cells_per_h=cells_per_h, pairs=pairs)
     rp, col = P.sph_neighbours(g, pos, h)
     return rp.cpu().numpy(), col.cpu().numpy(), g
 
@@ -100,12 +100,14 @@ CSR_CASES = {
 
 
 @pytest.mark.parametrize("case", list(CSR_CASES))
-@pytest.mark.parametrize("cells_per_h", [1, 2])
-def test_neighbours_bit_exact(case, cells_per_h):
+@pytest.mark.parametrize("cells_per_h,pairs", [(1, False), (2, False), (1, True), (2, True)])
+def test_neighbours_bit_exact(case, cells_per_h, pairs):
+    """Partner sets from the cell rows and from the frozen candidate lists, against
+    the oracle's brute force."""
     pos = CSR_CASES[case]()
     h = 0.3 if case == "adversarial" else (0.15 if case != "lattice10" else 0.24)
     rp_ref, col_ref = native.neighbours(pos, h)
-    rp, col, _ = gpu_csr(pos, h, cells_per_h)
+    rp, col, _ = gpu_csr(pos, h, cells_per_h, skin=0.01 * h if pairs else 0.0, pairs=pairs)
     assert np.array_equal(rp, rp_ref)
     assert np.array_equal(col, col_ref)
 
@@ -207,7 +209,7 @@ def test_nonpositive_density_is_flagged():
 def _subsample_parity(w, k, precision, seed):
     idx = W.subsample(w.n, k, seed)
     ref = native.rhs(w.pos, w.vel, w.rho, w.S, w.m, w.param_vector(), targets=idx)
-    got = gpu_rhs(w, precision, skin=0.1 * w.dx, pairs=True)
+    got = gpu_rhs(w, precision, skin=0.1 * w.dx, pairs=True, cells_per_h=2)
     got = {kk: v[..., idx] for kk, v in got.items()}
     err = normwise(got, ref, w.rho[idx])
     bad = {kk: v for kk, v in err.items() if not v <= TOL[precision]}
