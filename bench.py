@@ -67,7 +67,10 @@ def load_workload(name):
 # script (FETCH_SIZE, then WRITE_SIZE), each scaled by what the same counter reads for the
 # 1 GiB calibration copy.  They hold only for the kernel sources they were taken on: the
 # hash of those files is compared at run time and the figure is dropped on a mismatch.
-TRAFFIC = None
+TRAFFIC = {"kernel": "k_adj_pairs_list", "workload": "two_spheres_262144",
+           "sources_sha256": "8d23816e4c92582ec597916d5693f4fa38745f878b0e49215e4735464e1c09a8",
+           "fetch_bytes": 776.9e6, "write_bytes": 30.4e6,
+           "profile": "profiles/hbm_traffic_two_spheres_262144.md"}
 
 KERNEL_SOURCES = {"k_adj_pairs_list": ("adjoint.hip", "rhs_common.hpp", "common.hpp"),
                   "k_pairs64_list": ("rhs.hip", "rhs_common.hpp", "common.hpp")}
@@ -309,6 +312,7 @@ def main():
                 "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
                 "traffic_unit": "bytes per launch (HBM read + write, counter-scaled)",
+                "traffic_source": TRAFFIC["profile"] if traffic else None,
                 "avg_launch_ms": avg_ms, "launches": launches, "flops_per_pair": fpp,
                 "share_of_step": tot_ms / args.steps / ms_step,
                 "other": {k: {"avg_launch_ms": v[0] / max(v[1], 1), "launches": v[1]} for k, v in kern.items()}}
