@@ -182,7 +182,11 @@ def main():
     dev = "cuda"
     st = P.ParticleState.from_arrays(w.pos, w.vel, w.rho, w.S, w.m, dev)
     steps_lf = max(w.steps, 1)
-    skin = 0.25 * w.dx
+    # Skin of the frozen grid and list: twice the largest displacement the trajectory can
+    # make at its initial speeds, with 50 % margin (skin / 2 must cover every particle's
+    # movement; the device flag STALE_GRID would end the run otherwise), at least 0.02 dx.
+    vmax = float(np.sqrt((w.vel ** 2).sum(0)).max())
+    skin = max(3.0 * vmax * steps_lf * w.dt, 0.02 * w.dx)
     lo, hi = P.api.default_box(st.pos, w.h, skin)
     dims, ncells, _ = L.grid_geometry(lo, hi, w.h, skin, CELLS_PER_H)
     n = w.n
@@ -323,7 +327,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "particles": n, "ordered_pairs_per_rhs": nnz,
-                   "ordered_pairs_start_end": [nnz0, nnz1], "skin_over_dx": 0.25,
+                   "ordered_pairs_start_end": [nnz0, nnz1], "skin_over_dx": skin / w.dx,
                    "approaching_pair_fraction": f_app, "partners_per_particle": partners,
                    "pair_list": pair_list,
                    "h_over_dx": 2.4, "cells_per_h": CELLS_PER_H, "leapfrog_steps": steps_lf, "step": step_desc,
