@@ -410,20 +410,20 @@ __global__ __launch_bounds__(kBlock) void k_adj_pairs_list(GridDev g, int64_t n,
         int e0 = steps > 0 ? row[0] : 0;
         for (int j = 0; j < steps; ++j) {
             {
-                stage<8>(bf, fetch<8>(rf, kRec * 8, e0));
-                stage<8>(ba, fetch<8>(ra, kAdj * 8, e0));
+                gather_dma(rf, kRec * 8, e0, bf);
+                gather_dma(ra, kAdj * 8, e0, ba);
                 if (j + 1 < steps) e0 = row[(int64_t)(j + 1) << 6];
             }
             wave_sync();
             if (j < cnt) {
-                const double2 b0 = wave_chunk(bf, 0), b1 = wave_chunk(bf, 1);
+                const double2 b0 = dma_chunk(bf, 0), b1 = dma_chunk(bf, 1);
                 const double d2 = dist2_exact(o.xc, o.yc, o.zc, b0.x, b0.y, b1.x);
                 if (d2 < k.h2)
-                    adj_pair(k, o, d2, b0, b1, wave_chunk(bf, 2), wave_chunk(bf, 3),
-                             wave_chunk(bf, 4), wave_chunk(bf, 5), wave_chunk(bf, 6),
-                             wave_chunk(bf, 7), wave_chunk(ba, 0), wave_chunk(ba, 1),
-                             wave_chunk(ba, 2), wave_chunk(ba, 3), wave_chunk(ba, 4),
-                             wave_chunk(ba, 5), wave_chunk(ba, 6), acc);
+                    adj_pair(k, o, d2, b0, b1, dma_chunk(bf, 2), dma_chunk(bf, 3),
+                             dma_chunk(bf, 4), dma_chunk(bf, 5), dma_chunk(bf, 6),
+                             dma_chunk(bf, 7), dma_chunk(ba, 0), dma_chunk(ba, 1),
+                             dma_chunk(ba, 2), dma_chunk(ba, 3), dma_chunk(ba, 4),
+                             dma_chunk(ba, 5), dma_chunk(ba, 6), acc);
             }
             wave_sync();
         }

@@ -122,16 +122,16 @@ __global__ __launch_bounds__(kBlock) void k_pairs64_list(GridDev g, int64_t n, C
     const int32_t *row = g.pl_slot + base + __lane_id();
     int e0 = steps > 0 ? row[0] : 0;
     for (int j = 0; j < steps; ++j) {
-        stage<8>(buf, fetch<8>(recs, kRec * 8, e0));
+        gather_dma(recs, kRec * 8, e0, buf);
         if (j + 1 < steps) e0 = row[(int64_t)(j + 1) << 6];
         wave_sync();
         if (j < cnt) {
-            const double2 b0 = wave_chunk(buf, 0), b1 = wave_chunk(buf, 1);
+            const double2 b0 = dma_chunk(buf, 0), b1 = dma_chunk(buf, 1);
             const double d2 = dist2_exact(xa, ya, za, b0.x, b0.y, b1.x);
             if (d2 < k.h2) {
-                const double2 b2 = wave_chunk(buf, 2), b3 = wave_chunk(buf, 3);
-                const double2 b4 = wave_chunk(buf, 4), b5 = wave_chunk(buf, 5);
-                const double2 b6 = wave_chunk(buf, 6), b7 = wave_chunk(buf, 7);
+                const double2 b2 = dma_chunk(buf, 2), b3 = dma_chunk(buf, 3);
+                const double2 b4 = dma_chunk(buf, 4), b5 = dma_chunk(buf, 5);
+                const double2 b6 = dma_chunk(buf, 6), b7 = dma_chunk(buf, 7);
                 pair64(k, d2, xa - b0.x, ya - b0.y, za - b1.x, b1.y - vxa, b2.x - vya, b2.y - vza,
                        rho_a, b3.x, p4.x + b4.x, p4.y + b4.y, p5.x + b5.x, p5.y + b5.y,
                        p6.x + b6.x, p6.y + b6.y, b3.y, b7.x, acc);

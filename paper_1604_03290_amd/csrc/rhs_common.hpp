@@ -146,6 +146,39 @@ __device__ inline Fetched<NC> fetch(const char *__restrict__ recs, int stride, i
     return f;
 }
 
+// Direct-to-LDS form of the same gather for 8-chunk records: the loads write
+// LDS themselves (global_load_lds_dwordx4, 1 KB per instruction, no registers
+// and no LDS stores), so instruction i fills positions 64 i .. 64 i + 63 and the
+// record r = 8 i + (lane >> 3) loaded there lands with chunk c at
+// buf[8 r + ((c + r) & 7)]: each lane loads the chunk that the rotation puts
+// under it.  The rotation keeps the per-lane reads (dma_chunk) nearly free of
+// bank conflicts.  The compiler waits for the loads before the first LDS read.
+__device__ inline void gather_dma(const char *__restrict__ recs, int stride, int entry,
+                                  double2 *buf) {
+    const int lane = __lane_id();
+    const int r0 = lane >> 3;
+    const int cc = ((lane & 7) - r0) & 7;
+    const char *p = recs + cc * 16;
+    const int src = r0 * 4;
+    uint32_t t[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) t[i] = (uint32_t)__builtin_amdgcn_ds_bpermute(src + 32 * i, entry);
+    asm volatile("" : "+v"(t[0]), "+v"(t[1]), "+v"(t[2]), "+v"(t[3]), "+v"(t[4]), "+v"(t[5]),
+                 "+v"(t[6]), "+v"(t[7]));
+    uint32_t st = (uint32_t)stride;
+    asm("" : "+s"(st));
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        __builtin_amdgcn_global_load_lds(
+            reinterpret_cast<const void *>(p + (uint64_t)t[i] * st),
+            (__attribute__((address_space(3))) void *)(buf + 64 * i), 16, 0, 0);
+}
+
+__device__ inline double2 dma_chunk(const double2 *buf, int c) {
+    const int L = __lane_id();
+    return buf[8 * L + ((c + L) & 7)];
+}
+
 template <int NC>
 __device__ inline void stage(double2 *buf, const Fetched<NC> &f) {
     const int lane = __lane_id();
