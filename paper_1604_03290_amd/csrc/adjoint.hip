@@ -121,22 +121,16 @@ __global__ __launch_bounds__(kBlock) void k_adj_L_list(GridDev g, int64_t n, Con
     double L[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     const char *recs = reinterpret_cast<const char *>(rec);
     const int32_t *row = g.pl_slot + base + __lane_id();
-    Fetched<8> f;
-    int e1 = 0;
-    if (steps > 0) f = fetch<8>(recs, kRec * 8, row[0]);
-    if (steps > 1) e1 = row[64];
+    int e0 = steps > 0 ? row[0] : 0;
     for (int j = 0; j < steps; ++j) {
-        stage<8>(buf, f);
-        if (j + 1 < steps) {
-            f = fetch<8>(recs, kRec * 8, e1);
-            if (j + 2 < steps) e1 = row[(int64_t)(j + 2) << 6];
-        }
+        gather_dma(recs, kRec * 8, e0, buf);
+        if (j + 1 < steps) e0 = row[(int64_t)(j + 1) << 6];
         wave_sync();
         if (j < cnt) {
-            const double2 b0 = wave_chunk(buf, 0), b1 = wave_chunk(buf, 1);
+            const double2 b0 = dma_chunk(buf, 0), b1 = dma_chunk(buf, 1);
             const double d2 = dist2_exact(xa, ya, za, b0.x, b0.y, b1.x);
             if (d2 < k.h2) {
-                const double2 b2 = wave_chunk(buf, 2), b7 = wave_chunk(buf, 7);
+                const double2 b2 = dma_chunk(buf, 2), b7 = dma_chunk(buf, 7);
                 const KernelPieces kp = kernel_pieces(k, d2, rsqrt64(d2));
                 const double F = k.Fn * kp.f;
                 const double gx = F * (xa - b0.x), gy = F * (ya - b0.y), gz = F * (za - b1.x);

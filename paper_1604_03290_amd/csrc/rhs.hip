@@ -233,20 +233,14 @@ __global__ __launch_bounds__(kBlock) void k_pairs32_list(GridDev g, int64_t n, C
     Acc32 acc;
     const char *recs = reinterpret_cast<const char *>(r32);
     const int32_t *row = g.pl_slot + base + __lane_id();
-    Fetched<5> f;
-    int e1 = 0;
-    if (steps > 0) f = fetch<5>(recs, kRec32Bytes, row[0]);
-    if (steps > 1) e1 = row[64];
+    int e0 = steps > 0 ? row[0] : 0;
     for (int j = 0; j < steps; ++j) {
-        stage<5>(buf, f);
-        if (j + 1 < steps) {
-            f = fetch<5>(recs, kRec32Bytes, e1);
-            if (j + 2 < steps) e1 = row[(int64_t)(j + 2) << 6];
-        }
+        gather_dma5(recs, kRec32Bytes, e0, buf);
+        if (j + 1 < steps) e0 = row[(int64_t)(j + 1) << 6];
         wave_sync();
         if (j < cnt) {
-            const Src32 b = src32(wave_chunk(buf, 0), wave_chunk(buf, 1), wave_chunk(buf, 2),
-                                  wave_chunk(buf, 3), wave_chunk(buf, 4));
+            const Src32 b = src32(dma5_chunk(buf, 0), dma5_chunk(buf, 1), dma5_chunk(buf, 2),
+                                  dma5_chunk(buf, 3), dma5_chunk(buf, 4));
             const double d2 = dist2_exact(a.x, a.y, a.z, b.x, b.y, b.z);
             if (d2 < k.h2) pair32_of(kf, a, b, d2, acc);
         }

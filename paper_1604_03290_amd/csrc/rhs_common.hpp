@@ -89,67 +89,19 @@ __device__ inline void wave_sync() {
 }
 
 // Coalesced gather of one partner record per lane into the wavefront's LDS
-// buffer, in two stages so that a loop can overlap the loads of step j + 1 with
-// the arithmetic of step j:
-//   fetch: the lanes load the 64 records of NC 16-byte chunks (record r of lane
-//          r, r = 0..63) into registers with NC load instructions; instruction
-//          i, lane l moves chunk q = 64 i + l, i.e. chunk q % NC of the record
-//          of lane q / NC, so every instruction touches 64 / NC records and no
-//          lane idles.  A lane's partner slot is its own entry of the list row
-//          (one coalesced load by the caller), handed to the loading lanes by
-//          a lane shuffle.
-//   stage: the registers go to the LDS buffer; chunk c of lane L's record sits
-//          at buf[9 L + c]: the odd record stride (144 bytes) spreads the
-//          per-lane reads of one chunk (wave_chunk) over all banks, and every
-//          address is a per-lane base plus a constant offset.
-// Every list entry is a valid slot (padding repeats a slot), so no load is
-// guarded; lanes ignore the records of their padding entries.
-typedef double dvec2 __attribute__((ext_vector_type(2)));
-constexpr int kLdsRec = 9;              // chunks per record slot in LDS (8 + 1 pad)
-constexpr int kLdsWave = 64 * kLdsRec;  // double2 per wavefront buffer  // register pair, no struct copies
+// buffer.  Each lane holds its list entry of the step (one coalesced load by
+// the caller); lane shuffles hand the entries to the lanes that load the
+// records' 16-byte chunks, so that every load instruction moves whole records
+// (eight 128-byte lines for the FP64 records) instead of one chunk of 64
+// scattered records.  Every list entry is a valid slot (padding repeats a
+// slot), so no load is guarded; lanes ignore the records of their padding
+// entries.
+constexpr int kLdsWave = 64 * 8;  // double2 per wavefront buffer (64 records of 128 bytes)
 
-template <int NC>
-struct Fetched {
-    dvec2 v[NC];
-};
-
-template <int NC>
-__device__ inline Fetched<NC> fetch(const char *__restrict__ recs, int stride, int entry) {
-    Fetched<NC> f;
-    const int lane = __lane_id();
-    if constexpr (NC == 8) {
-        // record of lane 8 i + (lane >> 3), chunk lane & 7: one base pointer and
-        // one shuffle address with constant offsets serve all eight loads; the
-        // eight shuffles are issued together (the empty asm needs all of them)
-        const char *p = recs + (lane & 7) * 16;
-        const int src = (lane >> 3) * 4;
-        uint32_t t[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) t[i] = (uint32_t)__builtin_amdgcn_ds_bpermute(src + 32 * i, entry);
-        asm volatile("" : "+v"(t[0]), "+v"(t[1]), "+v"(t[2]), "+v"(t[3]), "+v"(t[4]), "+v"(t[5]),
-                     "+v"(t[6]), "+v"(t[7]));
-        // a stride opaque to the compiler makes each address one 64-bit multiply-add
-        uint32_t st = (uint32_t)stride;
-        asm("" : "+s"(st));
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-            f.v[i] = *reinterpret_cast<const dvec2 *>(p + (uint64_t)t[i] * st);
-    } else {
-#pragma unroll
-        for (int i = 0; i < NC; ++i) {
-            const int q = 64 * i + lane;
-            const int r = q / NC, c = q - r * NC;
-            const uint32_t t = (uint32_t)__builtin_amdgcn_ds_bpermute(4 * r, entry);
-            f.v[i] = *reinterpret_cast<const dvec2 *>(recs + (uint64_t)t * (uint32_t)stride + c * 16);
-        }
-    }
-    return f;
-}
-
-// Direct-to-LDS form of the same gather for 8-chunk records: the loads write
-// LDS themselves (global_load_lds_dwordx4, 1 KB per instruction, no registers
-// and no LDS stores), so instruction i fills positions 64 i .. 64 i + 63 and the
-// record r = 8 i + (lane >> 3) loaded there lands with chunk c at
+// 8-chunk records: the loads write LDS themselves (global_load_lds_dwordx4, 1 KB
+// per instruction, no registers and no LDS stores), so instruction i fills
+// positions 64 i .. 64 i + 63 and the record r = 8 i + (lane >> 3) loaded there
+// lands with chunk c at
 // buf[8 r + ((c + r) & 7)]: each lane loads the chunk that the rotation puts
 // under it.  The rotation keeps the per-lane reads (dma_chunk) nearly free of
 // bank conflicts.  The compiler waits for the loads before the first LDS read.
@@ -174,30 +126,34 @@ __device__ inline void gather_dma(const char *__restrict__ recs, int stride, int
             (__attribute__((address_space(3))) void *)(buf + 64 * i), 16, 0, 0);
 }
 
-__device__ inline double2 dma_chunk(const double2 *buf, int c) {
-    const int L = __lane_id();
-    return buf[8 * L + ((c + L) & 7)];
-}
-
-template <int NC>
-__device__ inline void stage(double2 *buf, const Fetched<NC> &f) {
+// The same for the 5-chunk FP32 record: position q = 64 i + lane holds chunk
+// q % 5 of record q / 5, so record r's chunk c sits at buf[5 r + c] (the odd
+// stride avoids bank conflicts).
+__device__ inline void gather_dma5(const char *__restrict__ recs, int stride, int entry,
+                                   double2 *buf) {
     const int lane = __lane_id();
-    if constexpr (NC == 8) {
-        double2 *b = buf + kLdsRec * (lane >> 3) + (lane & 7);
+    uint32_t t[5];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) *reinterpret_cast<dvec2 *>(b + 8 * kLdsRec * i) = f.v[i];
-    } else {
+    for (int i = 0; i < 5; ++i)
+        t[i] = (uint32_t)__builtin_amdgcn_ds_bpermute(4 * ((64 * i + lane) / 5), entry);
 #pragma unroll
-        for (int i = 0; i < NC; ++i) {
-            const int q = 64 * i + lane;
-            const int r = q / NC, c = q - r * NC;
-            *reinterpret_cast<dvec2 *>(buf + kLdsRec * r + c) = f.v[i];
-        }
+    for (int i = 0; i < 5; ++i) asm volatile("" : "+v"(t[i]));
+    uint32_t st = (uint32_t)stride;
+    asm("" : "+s"(st));
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        const int c = (64 * i + lane) % 5;
+        __builtin_amdgcn_global_load_lds(
+            reinterpret_cast<const void *>(recs + (uint64_t)t[i] * st + c * 16),
+            (__attribute__((address_space(3))) void *)(buf + 64 * i), 16, 0, 0);
     }
 }
 
-__device__ inline double2 wave_chunk(const double2 *buf, int c) {
-    return buf[kLdsRec * __lane_id() + c];
+__device__ inline double2 dma5_chunk(const double2 *buf, int c) { return buf[5 * __lane_id() + c]; }
+
+__device__ inline double2 dma_chunk(const double2 *buf, int c) {
+    const int L = __lane_id();
+    return buf[8 * L + ((c + L) & 7)];
 }
 
 // Liquid equation of state with the optional tension cut-off (section 2.5.1).
