@@ -48,6 +48,7 @@ struct AdjRec {
     double *Stb[6];    // partial cotangent of f_Y S from the rotation terms (stored components)
     double *part_mu;   // per-block partial sums
     double *part_y0;
+    int add_parts;     // add the block sums to part_* instead of writing them
 };
 
 inline AdjRec carve_adj(Carve &c, int64_t n) {
@@ -58,6 +59,7 @@ inline AdjRec carve_adj(Carve &c, int64_t n) {
     for (int i = 0; i < 6; ++i) r.Stb[i] = c.take<double>(n);
     r.part_mu = c.take<double>(blocks_for(n));
     r.part_y0 = c.take<double>(blocks_for(n));
+    r.add_parts = 0;
     return r;
 }
 
@@ -220,7 +222,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_post(GridDev g, int64_t n, Const
         o[7] = make_double2(0.0, 0.0);
     }
     const double tot = block_sum(mu_part);
-    if (threadIdx.x == 0) ad.part_mu[blockIdx.x] = tot;
+    if (threadIdx.x == 0) put(ad.part_mu, blockIdx.x, tot, ad.add_parts);
 }
 
 struct AdjAcc {
@@ -377,7 +379,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_pairs(GridDev g, int64_t n, Cons
         y0_part = adj_pre(k, ad, o, acc, s, io_index(g, s), st, out);
     }
     const double tot = block_sum(y0_part);
-    if (threadIdx.x == 0) ad.part_y0[blockIdx.x] = tot;
+    if (threadIdx.x == 0) put(ad.part_y0, blockIdx.x, tot, ad.add_parts);
 }
 
 // the same over the frozen pair list with cooperative gathers of both records
@@ -424,7 +426,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_pairs_list(GridDev g, int64_t n,
         if (act) y0_part = adj_pre(k, ad, o, acc, s, io_index(g, s), st, out);
     }
     const double tot = block_sum(y0_part);
-    if (threadIdx.x == 0) ad.part_y0[blockIdx.x] = tot;
+    if (threadIdx.x == 0) put(ad.part_y0, blockIdx.x, tot, ad.add_parts);
 }
 
 }  // namespace
@@ -482,13 +484,19 @@ GradDev grad_dev(const sph_fields *g, int accumulate) {
 // accumulated (accumulate != 0) into grad; dparams written or accumulated.
 int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_params *params,
                        const CotDev &cot, const GradDev &grad, double *dparams, int accumulate_params,
-                       Carve &c, hipStream_t s, const double *L_in, bool slot_state) {
+                       Carve &c, hipStream_t s, const double *L_in, bool slot_state,
+                       double *acc_parts) {
     const int64_t n = grid->n;
     GridDev g = grid_dev(grid);
     if (slot_state) g.io = nullptr;
     Consts k = make_consts(*params, g.delta);
     double *rec = c.take<double>((size_t)n * kRec);
     AdjRec ad = carve_adj(c, n);
+    if (acc_parts) {
+        ad.part_mu = acc_parts;
+        ad.part_y0 = acc_parts + blocks_for(n);
+        ad.add_parts = 1;
+    }
     StateDev st = state_dev(state);
     int rc = prepass_launch(g, st, n, k, rec, c.status(), s);
     if (rc) return rc;
@@ -512,6 +520,7 @@ int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_p
             k_adj_pairs<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, ad, grad);
         SPH_LAUNCHED();
     }
+    if (acc_parts) return SPH_OK;  // the caller reduces its accumulators
     return reduce_params_launch(ad.part_mu, ad.part_y0, blocks_for(n), dparams, accumulate_params, s);
 }
 

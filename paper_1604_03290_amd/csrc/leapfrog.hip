@@ -41,37 +41,58 @@ __device__ inline void limit6(double S[6], double Y0sq) {
     }
 }
 
-// U (in) -> U' (out): v += h a, rho += h drho, S = f_Y(S + h dS)(S + h dS)
-__global__ __launch_bounds__(kBlock) void k_kick(Fields13 in, Deriv10 d, Fields13 out, int64_t n,
-                                                 double h, double Y0sq) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// The kick at one particle: v += h a, rho += h drho, S = f_Y(S + h dS)(S + h dS).
+// Every kick of the forward pass and its recomputation in the reverse sweep go
+// through this one function, so they round identically.
+__device__ inline void kick_at(double v[3], double &rho, double S[6], const double F[10], double h,
+                               double Y0sq) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) out.p[3 + c][i] = in.p[3 + c][i] + h * d.p[c][i];
-    out.p[6][i] = in.p[6][i] + h * d.p[3][i];
-    double S[6];
+    for (int c = 0; c < 3; ++c) v[c] = v[c] + h * F[c];
+    rho = rho + h * F[3];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) S[c] = in.p[7 + c][i] + h * d.p[4 + c][i];
+    for (int c = 0; c < 6; ++c) S[c] = S[c] + h * F[4 + c];
     limit6(S, Y0sq);
-#pragma unroll
-    for (int c = 0; c < 6; ++c) out.p[7 + c][i] = S[c];
 }
 
-__global__ __launch_bounds__(kBlock) void k_drift(Fields13 f, int64_t n, double dt) {
+// One pass between two right-hand sides: with kick2 the second kick of the
+// previous step (U_k = kick(U', F_k)); with slab the checkpoint (U_k, F_k); with
+// kick1 the first kick and the drift of the next step (U' = kick(U_k, F_k),
+// x += dt v').
+__global__ __launch_bounds__(kBlock) void k_advance(Fields13 u, Deriv10 d, double *slab, int64_t n,
+                                                    double h, double dt, double Y0sq, int kick2,
+                                                    int kick1) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    double v[3], rho, S[6], F[10];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) f.p[c][i] += dt * f.p[3 + c][i];
-}
-
-// copy (state, derivative) into a checkpoint slab of kArrays * n doubles
-__global__ __launch_bounds__(kBlock) void k_store(Fields13 f, Deriv10 d, int64_t n, double *slab) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    for (int c = 0; c < 10; ++c) F[c] = d.p[c][i];
 #pragma unroll
-    for (int c = 0; c < 13; ++c) slab[c * n + i] = f.p[c][i];
+    for (int c = 0; c < 3; ++c) v[c] = u.p[3 + c][i];
+    rho = u.p[6][i];
 #pragma unroll
-    for (int c = 0; c < 10; ++c) slab[(13 + c) * n + i] = d.p[c][i];
+    for (int c = 0; c < 6; ++c) S[c] = u.p[7 + c][i];
+    if (kick2) kick_at(v, rho, S, F, h, Y0sq);
+    if (slab) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) slab[c * n + i] = u.p[c][i];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) slab[(3 + c) * n + i] = v[c];
+        slab[6 * n + i] = rho;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) slab[(7 + c) * n + i] = S[c];
+#pragma unroll
+        for (int c = 0; c < 10; ++c) slab[(13 + c) * n + i] = F[c];
+    }
+    if (kick1) {
+        kick_at(v, rho, S, F, h, Y0sq);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) u.p[c][i] += dt * v[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u.p[3 + c][i] = v[c];
+    u.p[6][i] = rho;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) u.p[7 + c][i] = S[c];
 }
 
 // user order -> slot order: dst[c][s] = src[c][perm[s]] (a null source gives 0)
@@ -104,67 +125,103 @@ __global__ __launch_bounds__(kBlock) void k_fill(double *p, int64_t n, double v)
     if (i < n) p[i] = v;
 }
 
-// Adjoint of the kick U_out = kick(U_in, F): given S_in, dS and the cotangent of
-// U_out in gU (updated in place to the cotangent of U_in), writes or adds the
-// cotangent of F into gF and leaves the Y0 contribution in per-block partials.
-struct Ptr12 {
-    const double *p[12];  // S_in (6) then dS (6)
-};
+// Adjoint of the kick U_out = kick(U_in, F) at particle i: given S_in, dS and
+// the cotangent of U_out in gU (updated in place to the cotangent of U_in),
+// writes or adds the cotangent of F into gF; returns the Y0 contribution.
+__device__ inline double kick_adj_at(const double S_in[6], const double dS[6], const Fields13 &gU,
+                                     const Deriv10 &gF, int64_t i, double h, double Y0,
+                                     int accumulate) {
+    double S[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) S[c] = S_in[c] + h * dS[c];
+    double Sb[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) Sb[c] = gU.p[7 + c][i];
+    const double j2 = j2_of(S);
+    const double Y0sq = Y0 * Y0;
+    double out[6], y0p = 0.0;
+    if (3.0 * j2 > Y0sq) {
+        const double f = Y0sq / (3.0 * j2);
+        double fb = 0.0;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) fb += Sb[c] * S[c];
+        const double Jb = -fb * f / j2;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) out[c] = f * Sb[c] + Jb * (c < 3 ? S[c] : 2.0 * S[c]);
+        y0p = fb * 2.0 * f / Y0;
+    } else {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) out[c] = Sb[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) gU.p[7 + c][i] = out[c];
+    double v[10];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c] = h * gU.p[3 + c][i];
+    v[3] = h * gU.p[6][i];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[4 + c] = h * out[c];
+#pragma unroll
+    for (int c = 0; c < 10; ++c) {
+        if (accumulate)
+            gF.p[c][i] += v[c];
+        else
+            gF.p[c][i] = v[c];
+    }
+    return y0p;
+}
 
-__global__ __launch_bounds__(kBlock) void k_kick_adj(Ptr12 Sin_dS, Fields13 gU,
-                                                     Deriv10 gF, int64_t n, double h, double Y0,
-                                                     int accumulate, double *part_y0) {
+// Reverse sweep, first pass of step k: recompute U' = kick(U_k, F_k) into Up
+// and apply the adjoint of the second kick U_{k+1} =
+// kick(U', F_{k+1}); the Y0 contribution is added to the block's accumulator.
+__global__ __launch_bounds__(kBlock) void k_rev_kick2(Fields13 Uk, Deriv10 Fk, Fields13 Up,
+                                                      Deriv10 Fk1, Fields13 gU, Deriv10 gF,
+                                                      int64_t n, double h, double Y0,
+                                                      int accumulate, double *acc_y0) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double y0p = 0.0;
     if (i < n) {
-        double S[6];
+        double v[3], rho = Uk.p[6][i], S[6], F[10], dS[6];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) S[c] = Sin_dS.p[c][i] + h * Sin_dS.p[6 + c][i];
-        double Sb[6];
+        for (int c = 0; c < 3; ++c) v[c] = Uk.p[3 + c][i];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) Sb[c] = gU.p[7 + c][i];
-        const double j2 = j2_of(S);
-        const double Y0sq = Y0 * Y0;
-        double out[6];
-        if (3.0 * j2 > Y0sq) {
-            const double f = Y0sq / (3.0 * j2);
-            double fb = 0.0;
+        for (int c = 0; c < 6; ++c) S[c] = Uk.p[7 + c][i];
 #pragma unroll
-            for (int c = 0; c < 6; ++c) fb += Sb[c] * S[c];
-            const double Jb = -fb * f / j2;
+        for (int c = 0; c < 10; ++c) F[c] = Fk.p[c][i];
+        kick_at(v, rho, S, F, h, Y0 * Y0);
 #pragma unroll
-            for (int c = 0; c < 6; ++c) out[c] = f * Sb[c] + Jb * (c < 3 ? S[c] : 2.0 * S[c]);
-            y0p = fb * 2.0 * f / Y0;
-        } else {
+        for (int c = 0; c < 3; ++c) Up.p[3 + c][i] = v[c];
+        Up.p[6][i] = rho;
 #pragma unroll
-            for (int c = 0; c < 6; ++c) out[c] = Sb[c];
-        }
+        for (int c = 0; c < 6; ++c) Up.p[7 + c][i] = S[c];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) gU.p[7 + c][i] = out[c];
-        double v[10];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) v[c] = h * gU.p[3 + c][i];
-        v[3] = h * gU.p[6][i];
-#pragma unroll
-        for (int c = 0; c < 6; ++c) v[4 + c] = h * out[c];
-#pragma unroll
-        for (int c = 0; c < 10; ++c) {
-            if (accumulate)
-                gF.p[c][i] += v[c];
-            else
-                gF.p[c][i] = v[c];
-        }
+        for (int c = 0; c < 6; ++c) dS[c] = Fk1.p[4 + c][i];
+        y0p = kick_adj_at(S, dS, gU, gF, i, h, Y0, accumulate);
     }
     const double tot = block_sum(y0p);
-    if (threadIdx.x == 0) part_y0[blockIdx.x] = tot;
+    if (threadIdx.x == 0) acc_y0[blockIdx.x] += tot;
 }
 
-// adjoint of the drift: vbar += dt xbar
-__global__ __launch_bounds__(kBlock) void k_drift_adj(Fields13 gU, int64_t n, double dt) {
+// Reverse sweep, last pass of step k: adjoint of the drift (vbar += dt xbar),
+// then of the first kick U' = kick(U_k, F_k) (fresh cotangent of F_k).
+__global__ __launch_bounds__(kBlock) void k_rev_kick1(Fields13 Uk, Deriv10 Fk, Fields13 gU,
+                                                      Deriv10 gF, int64_t n, double h, double dt,
+                                                      double Y0, double *acc_y0) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    double y0p = 0.0;
+    if (i < n) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) gU.p[3 + c][i] += dt * gU.p[c][i];
+        for (int c = 0; c < 3; ++c) gU.p[3 + c][i] += dt * gU.p[c][i];
+        double S[6], dS[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            S[c] = Uk.p[7 + c][i];
+            dS[c] = Fk.p[4 + c][i];
+        }
+        y0p = kick_adj_at(S, dS, gU, gF, i, h, Y0, 0);
+    }
+    const double tot = block_sum(y0p);
+    if (threadIdx.x == 0) acc_y0[blockIdx.x] += tot;
 }
 
 Fields13 fields_of(const sph_fields *f) {
@@ -293,7 +350,7 @@ size_t leapfrog_adjoint_ws_bytes(int64_t n) {
     carve_deriv(c, n);   // cotangent of F_{n+1}
     carve_deriv(c, n);   // cotangent of F_n
     c.take<double>(n);   // masses, slot order
-    c.take<double>(blocks_for(n));
+    c.take<double>(2 * blocks_for(n));  // per-block mu and Y0 accumulators
     c.used += adjoint_ws_bytes(n);
     return c.used;
 }
@@ -335,24 +392,16 @@ extern "C" int sph_leapfrog(const sph_grid *grid, const sph_state *s0, const sph
         double *Lout = checkpoints ? checkpoints + ((size_t)k * kArrays + kLOffset) * n : nullptr;
         return rhs_launch(grid, &st, params, SPH_FP64, &d, w, s, Lout, true);
     };
+    const double Y0sq = params->Y0 * params->Y0;
+    auto slab = [&](int k) { return checkpoints ? checkpoints + (size_t)k * kArrays * n : nullptr; };
     if ((rc = rhs(0))) return rc;
     for (int k = 0; k < steps; ++k) {
-        if (checkpoints) {
-            k_store<<<nb, kBlock, 0, s>>>(U, F, n, checkpoints + (size_t)k * kArrays * n);
-            SPH_LAUNCHED();
-        }
-        k_kick<<<nb, kBlock, 0, s>>>(U, F, U, n, half, params->Y0 * params->Y0);
-        SPH_LAUNCHED();
-        k_drift<<<nb, kBlock, 0, s>>>(U, n, dt);
+        k_advance<<<nb, kBlock, 0, s>>>(U, F, slab(k), n, half, dt, Y0sq, k > 0, 1);
         SPH_LAUNCHED();
         if ((rc = rhs(k + 1))) return rc;
-        k_kick<<<nb, kBlock, 0, s>>>(U, F, U, n, half, params->Y0 * params->Y0);
-        SPH_LAUNCHED();
     }
-    if (checkpoints) {
-        k_store<<<nb, kBlock, 0, s>>>(U, F, n, checkpoints + (size_t)steps * kArrays * n);
-        SPH_LAUNCHED();
-    }
+    k_advance<<<nb, kBlock, 0, s>>>(U, F, slab(steps), n, half, dt, Y0sq, 1, 0);
+    SPH_LAUNCHED();
     return fields_to_users(grid, U, fields_of(s_final), s);
 }
 
@@ -377,7 +426,7 @@ extern "C" int sph_leapfrog_adjoint(const sph_grid *grid, const sph_state *s0,
     Deriv10 gF1 = carve_deriv(c, n);
     Deriv10 gF0 = carve_deriv(c, n);
     double *m = c.take<double>(n);
-    double *part = c.take<double>(blocks_for(n));
+    double *parts = c.take<double>(2 * blocks_for(n));  // per-block mu and Y0 accumulators
     Carve adj_ws(ws);
     adj_ws.used = c.used;
     const unsigned nb = blocks_for(n);
@@ -396,8 +445,9 @@ extern "C" int sph_leapfrog_adjoint(const sph_grid *grid, const sph_state *s0,
         k_to_slots<<<nb, kBlock, 0, s>>>(a, b, 14, grid->perm, n);
         SPH_LAUNCHED();
     }
-    k_fill<<<1, 2, 0, s>>>(dparams, 2, 0.0);
+    k_fill<<<blocks_for(2 * nb), kBlock, 0, s>>>(parts, 2 * nb, 0.0);
     SPH_LAUNCHED();
+    double *acc_y0 = parts + nb;
 
     const GradDev acc = grad_of(gU);
     auto adjoint_at = [&](const sph_state &st, const Deriv10 &gF, const double *slab) {
@@ -405,17 +455,7 @@ extern "C" int sph_leapfrog_adjoint(const sph_grid *grid, const sph_state *s0,
                    {gF.p[4], gF.p[5], gF.p[6], gF.p[7], gF.p[8], gF.p[9]}, nullptr};
         Carve w = adj_ws;
         return rhs_adjoint_launch(grid, &st, params, cot, acc, dparams, 1, w, s,
-                                  slab + (size_t)kLOffset * n, true);
-    };
-    auto kick_adj = [&](const Fields13 &Uin, const Deriv10 &F, const Deriv10 &gF, int accumulate) {
-        Ptr12 t;
-        for (int c6 = 0; c6 < 6; ++c6) {
-            t.p[c6] = Uin.p[7 + c6];
-            t.p[6 + c6] = F.p[4 + c6];
-        }
-        k_kick_adj<<<nb, kBlock, 0, s>>>(t, gU, gF, n, half, Y0, accumulate, part);
-        SPH_LAUNCHED();
-        return reduce_params_launch(nullptr, part, nb, dparams, 1, s);
+                                  slab + (size_t)kLOffset * n, true, parts);
     };
 
     for (int k = steps - 1; k >= 0; --k) {
@@ -425,22 +465,21 @@ extern "C" int sph_leapfrog_adjoint(const sph_grid *grid, const sph_state *s0,
         const Deriv10 Fk = slab_deriv(slab_k, n);
         const Fields13 Uk1 = slab_fields(slab_k1, n);
         const Deriv10 Fk1 = slab_deriv(slab_k1, n);
-        // U' = kick(U_k, F_k); its positions are x_{k+1}
-        k_kick<<<nb, kBlock, 0, s>>>(Uk, Fk, Up, n, half, Y0 * Y0);
+        // U' = kick(U_k, F_k) (its positions are x_{k+1}), then the adjoint of the
+        // second kick U_{k+1} = kick(U', F_{k+1}): cotangent of U' and of F_{k+1}
+        // (F_{k+1} already holds the first kick of step k+1 unless k+1 = steps)
+        k_rev_kick2<<<nb, kBlock, 0, s>>>(Uk, Fk, Up, Fk1, gU, gF1, n, half, Y0,
+                                          k + 1 < steps ? 1 : 0, acc_y0);
         SPH_LAUNCHED();
         Fields13 Upx = Up;
         for (int c3 = 0; c3 < 3; ++c3) Upx.p[c3] = Uk1.p[c3];
-        // second kick U_{k+1} = kick(U', F_{k+1}): cotangent of U' and of F_{k+1}
-        // (F_{k+1} already holds the first kick of step k+1 unless k+1 = steps)
-        if ((rc = kick_adj(Up, Fk1, gF1, k + 1 < steps ? 1 : 0))) return rc;
         // right-hand side F_{k+1} = F(x_{k+1}, U')
         const sph_state st1 = state_struct(Upx, m, n);
         if ((rc = adjoint_at(st1, gF1, slab_k1))) return rc;
-        // drift x_{k+1} = x_k + dt v'
-        k_drift_adj<<<nb, kBlock, 0, s>>>(gU, n, dt);
+        // drift x_{k+1} = x_k + dt v', then the first kick U' = kick(U_k, F_k):
+        // cotangent of U_k, fresh cotangent of F_k
+        k_rev_kick1<<<nb, kBlock, 0, s>>>(Uk, Fk, gU, gF0, n, half, dt, Y0, acc_y0);
         SPH_LAUNCHED();
-        // first kick U' = kick(U_k, F_k): cotangent of U_k, fresh cotangent of F_k
-        if ((rc = kick_adj(Uk, Fk, gF0, 0))) return rc;
         Deriv10 tmp = gF1;
         gF1 = gF0;
         gF0 = tmp;
@@ -448,5 +487,7 @@ extern "C" int sph_leapfrog_adjoint(const sph_grid *grid, const sph_state *s0,
     // F_0 = F(x_0, U_0)
     const sph_state st0 = state_struct(slab_fields(ck, n), m, n);
     if ((rc = adjoint_at(st0, gF1, ck))) return rc;
+    // dparams = the accumulators summed in a fixed order
+    if ((rc = reduce_params_launch(parts, acc_y0, nb, dparams, 0, s))) return rc;
     return fields_to_users(grid, gU, fields_of(grad0), s);
 }

@@ -368,10 +368,12 @@ size_t adjoint_ws_bytes(int64_t n);
 // L_in (nullable): the forward velocity gradient of the same state in slot order
 // (9 arrays of n); when null it is recomputed.  slot_state: the state, cotangent
 // and gradient arrays are in the grid's slot order instead of user order.
+// acc_parts (nullable): 2 ceil(n / 256) per-block accumulators (mu, then Y0) to
+// which the launch adds its block sums instead of reducing into dparams.
 int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_params *params,
                        const CotDev &cot, const GradDev &grad, double *dparams, int accumulate_params,
                        Carve &c, hipStream_t s, const double *L_in = nullptr,
-                       bool slot_state = false);
+                       bool slot_state = false, double *acc_parts = nullptr);
 // dparams[0] (+)= sum of p0, dparams[1] (+)= sum of p1 (null parts skipped),
 // fixed summation order
 int reduce_params_launch(const double *p0, const double *p1, int64_t m, double *dparams,
