@@ -123,9 +123,12 @@ typedef struct {
  * linear equation of state p = c^2 (rho - rho0) (section 2.5.1); mu: shear
  * modulus; Y0: von Mises yield stress (section 2.6); alpha, beta, eps_v:
  * artificial viscosity (section 3.1.3); rho_cut: pressure is set to zero where
- * rho / rho0 < rho_cut (tension cut-off of section 2.5.1; 0 disables it). */
+ * rho / rho0 < rho_cut (tension cut-off of section 2.5.1; 0 disables it);
+ * correction: 1 applies the correction tensor of section 3.1.6 (linear
+ * consistency) to the velocity gradient that drives the stress rate, 0 uses the
+ * standard gradient. */
 typedef struct {
-    double h, rho0, c, mu, Y0, alpha, beta, eps_v, rho_cut;
+    double h, rho0, c, mu, Y0, alpha, beta, eps_v, rho_cut, correction;
 } sph_params;
 
 /* Time derivatives (outputs) in user order.  rho_sum may be NULL. */

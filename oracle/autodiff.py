@@ -9,7 +9,9 @@ readings as ``sph_oracle.c`` (see its header for the passages):
   kernel (section 3.1.1), liquid equation of state (section 2.5.1), von Mises
   limiter f_Y = min(Y0^2/(3 J2), 1) (section 2.6), density sum, continuity,
   momentum with artificial viscosity (section 3.1.2, 3.1.3), standard velocity
-  gradient (section 3.1.6), Hooke's law with Jaumann terms R S - S R (section 2.4).
+  gradient or the corrected one L C with C = M^-1, M = sum_b V_b (x_b - x_a) (x)
+  grad_a W_ab (section 3.1.6; identity where M is singular), Hooke's law with
+  Jaumann terms R S - S R (section 2.4).
 
 Also the kick-drift-kick leapfrog used to drive the adjoint (the paper's own
 integrators are the predictor-corrector and RK3 of section 3.4; the leapfrog
@@ -70,12 +72,31 @@ def limit(S6: torch.Tensor, Y0) -> torch.Tensor:
     return yield_factor(S6, Y0) * S6
 
 
+def correction_tensor(M: torch.Tensor) -> torch.Tensor:
+    """C = M^-1 (3, 3, n) by the adjugate; the identity where det M <= 1e-12 (tr M / 3)^3."""
+    m = M
+    A = torch.stack([
+        torch.stack([m[1, 1] * m[2, 2] - m[1, 2] * m[2, 1], m[0, 2] * m[2, 1] - m[0, 1] * m[2, 2],
+                     m[0, 1] * m[1, 2] - m[0, 2] * m[1, 1]]),
+        torch.stack([m[1, 2] * m[2, 0] - m[1, 0] * m[2, 2], m[0, 0] * m[2, 2] - m[0, 2] * m[2, 0],
+                     m[0, 2] * m[1, 0] - m[0, 0] * m[1, 2]]),
+        torch.stack([m[1, 0] * m[2, 1] - m[1, 1] * m[2, 0], m[0, 1] * m[2, 0] - m[0, 0] * m[2, 1],
+                     m[0, 0] * m[1, 1] - m[0, 1] * m[1, 0]])])
+    det = m[0, 0] * A[0, 0] + m[0, 1] * A[1, 0] + m[0, 2] * A[2, 0]
+    t = (m[0, 0] + m[1, 1] + m[2, 2]) / 3.0
+    ok = (det > 1e-12 * t * t * t) & torch.isfinite(det)
+    eye = torch.eye(3, dtype=DT).unsqueeze(-1).expand_as(M)
+    return torch.where(ok, A / torch.where(ok, det, torch.ones_like(det)), eye)
+
+
 def rhs(pos, vel, rho, S6, m, par, mu=None, Y0=None, pairs=None):
     """Right-hand side of every particle.  ``par`` = {h, rho0, c, mu, Y0, alpha,
-    beta, eps_v, rho_cut}; ``mu``/``Y0`` may be tensors (differentiable)
-    overriding par[3]/par[4].  Returns dict acc (3, n), drho, dS (6, n), rho_sum, L (3, 3, n)."""
+    beta, eps_v, rho_cut, correction}; ``mu``/``Y0`` may be tensors (differentiable)
+    overriding par[3]/par[4].  Returns dict acc (3, n), drho, dS (6, n), rho_sum, L (3, 3, n)
+    (L: the gradient that drives the stress rate, corrected when par[9] != 0)."""
     h, rho0, c = float(par[0]), float(par[1]), float(par[2])
     alpha, beta, eps_v, rho_cut = float(par[5]), float(par[6]), float(par[7]), float(par[8])
+    corr = len(par) > 9 and float(par[9]) != 0.0
     mu = float(par[3]) if mu is None else mu
     Y0 = float(par[4]) if Y0 is None else Y0
     n = rho.shape[0]
@@ -119,6 +140,12 @@ def rhs(pos, vel, rho, S6, m, par, mu=None, Y0=None, pairs=None):
     B = T[:, :, i] + T[:, :, j] - Pi * eye
     accp = mj * (B * gW.unsqueeze(0)).sum(1)
     acc = torch.zeros(3, n, dtype=DT).index_add(1, i, accp)
+
+    # corrected gradient (the continuity sum above stays as printed)
+    if corr:
+        Mp = -(V[j] * rv).unsqueeze(1) * gW.unsqueeze(0)  # (x_b - x_a)^a d_g W
+        M = torch.zeros(3, 3, n, dtype=DT).index_add(2, i, Mp)
+        L = torch.einsum("agn,gbn->abn", L, correction_tensor(M))
 
     # postpass: Hooke + Jaumann
     Lt = L.transpose(0, 1)

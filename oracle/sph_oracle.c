@@ -20,7 +20,8 @@
  *   density sum   eq. (density_by_kernel_sum), section 3.1.2
  *   continuity    eq. (continuity_equation_sph), section 3.1.2
  *   momentum      eqs. (accel) and (accel_artvisc), artificial viscosity (section 3.1.3)
- *   gradient      section 3.1.6, standard SPH velocity derivative (uncorrected)
+ *   gradient      section 3.1.6, standard SPH velocity derivative, or with the
+ *                 correction tensor of the same section (linear consistency)
  *   stress rate   eqs. (stresstensor_evolution), (strain_rate_tensor), (rotation_terms),
  *                 section 2.4
  *
@@ -37,12 +38,19 @@
  *     use the limited stress.
  *   - mean sound speed: the linear equation of state has one sound speed c.
  *   - the density sum includes the particle's own term m_a W(0).
+ *   - correction tensor: C is the inverse of the matrix of the identity the
+ *     section states, M = sum_b V_b (x_b - x_a) (x) grad_a W_ab, so that M C = I
+ *     (the printed definition with (x_a - x_b) contradicts that identity); the
+ *     corrected gradient L C drives the strain and rotation rates, while the
+ *     continuity equation keeps its own (uncorrected) sum.  Where M is singular
+ *     (det M <= 1e-12 (tr M / 3)^3, e.g. fewer than three non-coplanar
+ *     partners) the standard gradient is used.
  *
  * Layout: structure of arrays.  pos and vel are (3, n) row-major (x row, y row,
  * z row); S is (6, n) in the order xx, yy, zz, xy, xz, yz; outputs follow the
  * same layout with the target count nt in place of n; L is (9, nt) row-major
  * over (alpha, beta) with L^{alpha beta} = dv^alpha / dx^beta.
- * par = {h, rho0, c, mu, Y0, alpha, beta, eps_v, rho_cut}.
+ * par = {h, rho0, c, mu, Y0, alpha, beta, eps_v, rho_cut, correction}.
  */
 #include <math.h>
 #include <stdint.h>
@@ -52,7 +60,7 @@
 #include <omp.h>
 #endif
 
-enum { P_H, P_RHO0, P_C, P_MU, P_Y0, P_ALPHA, P_BETA, P_EPSV, P_RHOCUT };
+enum { P_H, P_RHO0, P_C, P_MU, P_Y0, P_ALPHA, P_BETA, P_EPSV, P_RHOCUT, P_CORR };
 
 static const double PI_ = 3.14159265358979323846;
 
@@ -255,8 +263,39 @@ void orc_prepass(int64_t n, const double *rho, const double *S, const double *pa
  *   edot = (L + L^T)/2,  R = (L - L^T)/2,  S~ = f_Y S
  *   dS_a = 2 mu (edot - tr(edot) I / 3) + R S~ - S~ R
  *
+ * With the correction, L is replaced by L C before the stress rate.
+ *
  * Outputs (per target): acc (3, nt), drho (nt), dS (6, nt), rho_sum (nt),
- * and L (9, nt) when L != NULL.                                           */
+ * and L (9, nt) when L != NULL: the gradient that drives the stress rate
+ * (L C with the correction).                                               */
+/* C = M^{-1} by the adjugate when M is regular (see the reading in the header),
+ * the identity otherwise.  Returns 1 when the inverse was taken. */
+static int correction_tensor(const double M[3][3], double C[3][3])
+{
+    double A[3][3];
+    A[0][0] = M[1][1] * M[2][2] - M[1][2] * M[2][1];
+    A[0][1] = M[0][2] * M[2][1] - M[0][1] * M[2][2];
+    A[0][2] = M[0][1] * M[1][2] - M[0][2] * M[1][1];
+    A[1][0] = M[1][2] * M[2][0] - M[1][0] * M[2][2];
+    A[1][1] = M[0][0] * M[2][2] - M[0][2] * M[2][0];
+    A[1][2] = M[0][2] * M[1][0] - M[0][0] * M[1][2];
+    A[2][0] = M[1][0] * M[2][1] - M[1][1] * M[2][0];
+    A[2][1] = M[0][1] * M[2][0] - M[0][0] * M[2][1];
+    A[2][2] = M[0][0] * M[1][1] - M[0][1] * M[1][0];
+    const double det = M[0][0] * A[0][0] + M[0][1] * A[1][0] + M[0][2] * A[2][0];
+    const double t = (M[0][0] + M[1][1] + M[2][2]) / 3.0;
+    if (!(det > 1e-12 * t * t * t) || !isfinite(det)) {
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                C[i][j] = i == j ? 1.0 : 0.0;
+        return 0;
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            C[i][j] = A[i][j] / det;
+    return 1;
+}
+
 void orc_rhs(int64_t n, const double *pos, const double *vel, const double *rho,
              const double *S, const double *m, const double *par,
              const int64_t *targets, int64_t nt, const int64_t *row_ptr, const int32_t *col,
@@ -264,6 +303,7 @@ void orc_rhs(int64_t n, const double *pos, const double *vel, const double *rho,
 {
     const double h = par[P_H], c = par[P_C], mu = par[P_MU];
     const double alpha = par[P_ALPHA], beta = par[P_BETA], eps_v = par[P_EPSV];
+    const int corr = par[P_CORR] != 0.0;
     const double *x = pos, *y = pos + n, *z = pos + 2 * n;
     const double *vx = vel, *vy = vel + n, *vz = vel + 2 * n;
     if (!targets)
@@ -291,6 +331,7 @@ void orc_rhs(int64_t n, const double *pos, const double *vel, const double *rho,
         double cont = 0.0;
         double ac[3] = {0.0, 0.0, 0.0};
         double L[3][3] = {{0.0}};
+        double Mc[3][3] = {{0.0}}; /* sum_b V_b (x_b - x_a) (x) grad_a W_ab */
 
         for (int64_t k = row_ptr[t]; k < row_ptr[t + 1]; ++k) {
             const int64_t b = col[k];
@@ -323,6 +364,10 @@ void orc_rhs(int64_t n, const double *pos, const double *vel, const double *rho,
             for (int al = 0; al < 3; ++al)
                 for (int be = 0; be < 3; ++be)
                     L[al][be] += Vb * (vb[al] - va[al]) * gW[be];
+            if (corr)
+                for (int al = 0; al < 3; ++al)
+                    for (int ga = 0; ga < 3; ++ga)
+                        Mc[al][ga] += Vb * (xb[al] - xa[al]) * gW[ga];
 
             /* artificial viscosity */
             double wab = 0.0;
@@ -344,6 +389,20 @@ void orc_rhs(int64_t n, const double *pos, const double *vel, const double *rho,
                 }
                 ac[al] += m[b] * s;
             }
+        }
+
+        /* corrected velocity gradient L C (the continuity sum above stays as printed) */
+        if (corr) {
+            double C[3][3], Lc[3][3];
+            correction_tensor(Mc, C);
+            for (int al = 0; al < 3; ++al)
+                for (int be = 0; be < 3; ++be) {
+                    double v = 0.0;
+                    for (int ga = 0; ga < 3; ++ga)
+                        v += L[al][ga] * C[ga][be];
+                    Lc[al][be] = v;
+                }
+            memcpy(L, Lc, sizeof L);
         }
 
         /* stress rate: Hooke term plus Jaumann rotation terms on the limited S */

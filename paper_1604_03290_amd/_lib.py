@@ -65,7 +65,7 @@ class State(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [(k, C.c_double) for k in
-                ("h", "rho0", "c", "mu", "Y0", "alpha", "beta", "eps_v", "rho_cut")]
+                ("h", "rho0", "c", "mu", "Y0", "alpha", "beta", "eps_v", "rho_cut", "correction")]
 
 
 _DERIV = ("ax", "ay", "az", "drho", "dsxx", "dsyy", "dszz", "dsxy", "dsxz", "dsyz", "rho_sum")

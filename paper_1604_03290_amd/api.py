@@ -16,7 +16,7 @@ import torch
 from . import _lib as L
 
 F64 = torch.float64
-PARAM_ORDER = ("h", "rho0", "c", "mu", "Y0", "alpha", "beta", "eps_v", "rho_cut")
+PARAM_ORDER = ("h", "rho0", "c", "mu", "Y0", "alpha", "beta", "eps_v", "rho_cut", "correction")
 DERIV_KEYS = ("acc", "drho", "dS", "rho_sum")
 
 
@@ -71,7 +71,8 @@ class ParticleState:
 
 def params_struct(params) -> L.Params:
     if isinstance(params, dict):
-        vals = [float(params[k]) for k in PARAM_ORDER]
+        vals = [float(params.get(k, 0.0)) if k == "correction" else float(params[k])
+                for k in PARAM_ORDER]
     else:
         vals = [float(v) for v in params]
     return L.Params(*vals)

@@ -33,10 +33,11 @@ MATERIAL = dict(
     beta=0.0,
     eps_v=0.01,
     rho_cut=0.0,
+    correction=0.0,
 )
 
 # order of the scalar parameter vector shared by every consumer
-PARAM_ORDER = ("h", "rho0", "c", "mu", "Y0", "alpha", "beta", "eps_v", "rho_cut")
+PARAM_ORDER = ("h", "rho0", "c", "mu", "Y0", "alpha", "beta", "eps_v", "rho_cut", "correction")
 
 CONFIG_NAMES = {
     0: "cube16_fp64_4096",
