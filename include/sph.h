@@ -279,8 +279,8 @@ int sph_rhs_adjoint(const sph_grid *grid, const sph_state *state, const sph_para
  *   s_final      final state out (may alias the arrays of s0)
  *   checkpoints  device, sph_checkpoint_bytes(n, steps) bytes, or NULL; holds
  *                (x, v, rho, S, F) at the start of every step and at the end
- *                and the velocity gradient behind each F, all in the grid's
- *                slot order (the trajectory is integrated in slot order), as
+ *                and the velocity gradient behind each F (with the correction
+ *                tensor also its moment matrix), all in the grid's slot order (the trajectory is integrated in slot order), as
  *                needed by sph_leapfrog_adjoint, which must be given the same
  *                grid
  * The grid must have been built with a skin covering the trajectory's largest

@@ -11,8 +11,8 @@
 // trajectory is integrated in the grid's slot order (the state is permuted once
 // at the start and back at the end), so every per-particle pass reads and
 // writes contiguous arrays.  The checkpoint of step k holds (x_k, v_k, rho_k,
-// S_k, F_k) and the velocity gradient behind F_k, 32 arrays of n doubles in
-// slot order.  The reverse sweep walks the steps backwards, recomputing U' from
+// S_k, F_k), the velocity gradient behind F_k and, with the correction tensor,
+// its moment matrix: 38 arrays of n doubles in slot order.  The reverse sweep walks the steps backwards, recomputing U' from
 // the checkpoint, and applies in turn the adjoints of the second kick, of the
 // right-hand side at (x_{n+1}, U'), of the drift and of the first kick.
 #include "common.hpp"
@@ -21,7 +21,7 @@
 namespace sph {
 namespace {
 
-constexpr int kArrays = 32;  // x3 v3 rho S6 | a3 drho dS6 | L9 (slot order)
+constexpr int kArrays = 38;  // x3 v3 rho S6 | a3 drho dS6 | L9 | M6 (slot order; M with the correction)
 constexpr int kLOffset = 23;
 
 struct Fields13 {
@@ -415,6 +415,8 @@ extern "C" int sph_leapfrog_adjoint(const sph_grid *grid, const sph_state *s0,
     if ((rc = check_lf(grid, s0, params, dt, steps)) || (rc = check_grad(grad0))) return rc;
     if (!checkpoints || !cot_final || !dparams || !ws)
         return fail(SPH_ERR_INVALID_ARG, "null pointer");
+    if (params->correction != 0.0)
+        return fail(SPH_ERR_NOT_IMPLEMENTED, "adjoint with the correction tensor");
     const int64_t n = grid->n;
     const size_t need = leapfrog_adjoint_ws_bytes(n);
     if (ws_bytes < need) return fail(SPH_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);

@@ -66,6 +66,7 @@ __global__ __launch_bounds__(kBlock) void k_narrow(const double *__restrict__ re
 }
 
 // ---------------------------------------------------------- pairs, FP64 --
+template <bool kCorr>
 __global__ __launch_bounds__(kBlock) void k_pairs64(GridDev g, int64_t n, Consts k,
                                                     const double *__restrict__ rec, StateDev st,
                                                     OutDev out, double *__restrict__ Lout) {
@@ -83,19 +84,25 @@ __global__ __launch_bounds__(kBlock) void k_pairs64(GridDev g, int64_t n, Consts
         const double d2 = dist2_exact(xa, ya, za, b0.x, b0.y, b1.x);
         if (!(d2 < k.h2)) return;
         const double2 b2 = rb[2], b3 = rb[3], b4 = rb[4], b5 = rb[5], b6 = rb[6], b7 = rb[7];
-        pair64(k, d2, xa - b0.x, ya - b0.y, za - b1.x, b1.y - vxa, b2.x - vya, b2.y - vza, rho_a,
+        pair64<kCorr>(k, d2, xa - b0.x, ya - b0.y, za - b1.x, b1.y - vxa, b2.x - vya, b2.y - vza, rho_a,
                b3.x, p4.x + b4.x, p4.y + b4.y, p5.x + b5.x, p5.y + b5.y, p6.x + b6.x, p6.y + b6.y,
                b3.y, b7.x, acc);
     });
-    postpass(k, io_index(g, s), rho_a, acc.L, acc.ax, acc.ay, acc.az, acc.rs, st, out);
+    postpass(k, io_index(g, s), rho_a, acc.L, acc.ax, acc.ay, acc.az, acc.rs, st, out,
+             kCorr ? acc.M : nullptr);
     if (Lout) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) Lout[i * n + s] = acc.L[i];
+        if (kCorr) {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) Lout[(9 + i) * n + s] = acc.M[i];
+        }
     }
 }
 
 // FP64 pair sums over the frozen pair list: the wavefront walks its 64 lists in
 // lock step, gathering the 64 partner records of step j cooperatively.
+template <bool kCorr>
 __global__ __launch_bounds__(kBlock) void k_pairs64_list(GridDev g, int64_t n, Consts k,
                                                          const double *__restrict__ rec,
                                                          StateDev st, OutDev out,
@@ -132,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs64_list(GridDev g, int64_t n, C
                 const double2 b2 = dma_chunk(buf, 2), b3 = dma_chunk(buf, 3);
                 const double2 b4 = dma_chunk(buf, 4), b5 = dma_chunk(buf, 5);
                 const double2 b6 = dma_chunk(buf, 6), b7 = dma_chunk(buf, 7);
-                pair64(k, d2, xa - b0.x, ya - b0.y, za - b1.x, b1.y - vxa, b2.x - vya, b2.y - vza,
+                pair64<kCorr>(k, d2, xa - b0.x, ya - b0.y, za - b1.x, b1.y - vxa, b2.x - vya, b2.y - vza,
                        rho_a, b3.x, p4.x + b4.x, p4.y + b4.y, p5.x + b5.x, p5.y + b5.y,
                        p6.x + b6.x, p6.y + b6.y, b3.y, b7.x, acc);
             }
@@ -140,10 +147,15 @@ __global__ __launch_bounds__(kBlock) void k_pairs64_list(GridDev g, int64_t n, C
         wave_sync();
     }
     if (!act) return;
-    postpass(k, io_index(g, s), rho_a, acc.L, acc.ax, acc.ay, acc.az, acc.rs, st, out);
+    postpass(k, io_index(g, s), rho_a, acc.L, acc.ax, acc.ay, acc.az, acc.rs, st, out,
+             kCorr ? acc.M : nullptr);
     if (Lout) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) Lout[i * n + s] = acc.L[i];
+        if (kCorr) {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) Lout[(9 + i) * n + s] = acc.M[i];
+        }
     }
 }
 
@@ -174,27 +186,37 @@ __device__ inline Src32 load32(const float *r32, int64_t s) {
     return src32(p[0], p[1], p[2], p[3], p[4]);
 }
 
+template <bool kCorr>
 __device__ inline void pair32_of(const Consts32 &kf, const Src32 &a, const Src32 &b, double d2,
                                  Acc32 &acc) {
-    pair32(kf, (float)d2, (float)(a.x - b.x), (float)(a.y - b.y), (float)(a.z - b.z),
+    pair32<kCorr>(kf, (float)d2, (float)(a.x - b.x), (float)(a.y - b.y), (float)(a.z - b.z),
            b.vx - a.vx, b.vy - a.vy, b.vz - a.vz, a.rho, b.rho, a.T[0] + b.T[0], a.T[1] + b.T[1],
            a.T[2] + b.T[2], a.T[3] + b.T[3], a.T[4] + b.T[4], a.T[5] + b.T[5], b.m, b.V, acc);
 }
 
+template <bool kCorr>
 __device__ inline void post32(const Consts &k, int a, double rho_a, double m_a, const Acc32 &acc,
                               const StateDev &st, const OutDev &out, double *Lout, int64_t n,
                               int64_t s) {
-    double L[9];
+    double L[9], M[6];
 #pragma unroll
     for (int c = 0; c < 9; ++c) L[c] = acc.L[c].value();
+#pragma unroll
+    for (int c = 0; c < 6; ++c) M[c] = kCorr ? acc.M[c].value() : 0.0;
     const double rs = m_a * k.Wn + acc.rs.value();
-    postpass(k, a, rho_a, L, acc.ax.value(), acc.ay.value(), acc.az.value(), rs, st, out);
+    postpass(k, a, rho_a, L, acc.ax.value(), acc.ay.value(), acc.az.value(), rs, st, out,
+             kCorr ? M : nullptr);
     if (Lout) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) Lout[i * n + s] = L[i];
+        if (kCorr) {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) Lout[(9 + i) * n + s] = M[i];
+        }
     }
 }
 
+template <bool kCorr>
 __global__ __launch_bounds__(kBlock) void k_pairs32(GridDev g, int64_t n, Consts k,
                                                     const double *__restrict__ rec,
                                                     const float *__restrict__ r32, StateDev st,
@@ -208,12 +230,13 @@ __global__ __launch_bounds__(kBlock) void k_pairs32(GridDev g, int64_t n, Consts
     for_each_candidate(g, s, a.x, a.y, a.z, k.reach, [&](int t) {
         const Src32 b = load32(r32, t);
         const double d2 = dist2_exact(a.x, a.y, a.z, b.x, b.y, b.z);
-        if (d2 < k.h2) pair32_of(kf, a, b, d2, acc);
+        if (d2 < k.h2) pair32_of<kCorr>(kf, a, b, d2, acc);
     });
-    post32(k, io_index(g, s), p3.x, p3.y, acc, st, out, Lout, n, s);
+    post32<kCorr>(k, io_index(g, s), p3.x, p3.y, acc, st, out, Lout, n, s);
 }
 
 // FP32 pair sums over the frozen pair list (cooperative gathers of the 80-byte records)
+template <bool kCorr>
 __global__ __launch_bounds__(kBlock) void k_pairs32_list(GridDev g, int64_t n, Consts k,
                                                          const double *__restrict__ rec,
                                                          const float *__restrict__ r32,
@@ -242,13 +265,13 @@ __global__ __launch_bounds__(kBlock) void k_pairs32_list(GridDev g, int64_t n, C
             const Src32 b = src32(dma5_chunk(buf, 0), dma5_chunk(buf, 1), dma5_chunk(buf, 2),
                                   dma5_chunk(buf, 3), dma5_chunk(buf, 4));
             const double d2 = dist2_exact(a.x, a.y, a.z, b.x, b.y, b.z);
-            if (d2 < k.h2) pair32_of(kf, a, b, d2, acc);
+            if (d2 < k.h2) pair32_of<kCorr>(kf, a, b, d2, acc);
         }
         wave_sync();
     }
     if (!act) return;
     const double2 p3 = rec2(rec, s)[3];
-    post32(k, io_index(g, s), p3.x, p3.y, acc, st, out, Lout, n, s);
+    post32<kCorr>(k, io_index(g, s), p3.x, p3.y, acc, st, out, Lout, n, s);
 }
 
 }  // namespace
@@ -279,8 +302,8 @@ int check_state(const sph_grid *grid, const sph_state *st) {
 
 int check_params(const sph_grid *grid, const sph_params *pr) {
     if (!pr) return fail(SPH_ERR_INVALID_ARG, "params is NULL");
-    const double v[] = {pr->h,     pr->rho0, pr->c,     pr->mu,     pr->Y0,
-                        pr->alpha, pr->beta, pr->eps_v, pr->rho_cut};
+    const double v[] = {pr->h,     pr->rho0, pr->c,     pr->mu,      pr->Y0,
+                        pr->alpha, pr->beta, pr->eps_v, pr->rho_cut, pr->correction};
     for (double q : v)
         if (!std::isfinite(q)) return fail(SPH_ERR_INVALID_ARG, "non-finite parameter");
     if (!(pr->h > 0.0) || !(pr->rho0 > 0.0) || !(pr->c > 0.0))
@@ -288,6 +311,8 @@ int check_params(const sph_grid *grid, const sph_params *pr) {
     if (pr->mu < 0.0 || !(pr->Y0 > 0.0) || pr->eps_v <= 0.0 || pr->rho_cut < 0.0)
         return fail(SPH_ERR_INVALID_ARG, "mu >= 0, Y0 > 0, eps_v > 0, rho_cut >= 0 required");
     if (pr->h > grid->h) return fail(SPH_ERR_INVALID_ARG, "h exceeds the grid's support radius");
+    if (pr->correction != 0.0 && pr->correction != 1.0)
+        return fail(SPH_ERR_INVALID_ARG, "correction must be 0 or 1");
     return SPH_OK;
 }
 
@@ -316,19 +341,29 @@ int rhs_launch(const sph_grid *grid, const sph_state *state, const sph_params *p
     if (rc) return rc;
     if (precision == SPH_FP64) {
         TimedRegion t("pairs_fp64", s);
-        if (g.pl_count)
-            k_pairs64_list<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, od, L_out);
+        const dim3 gb(blocks_for(n)), tb(kBlock);
+        if (g.pl_count && k.corr)
+            k_pairs64_list<true><<<gb, tb, 0, s>>>(g, n, k, rec, st, od, L_out);
+        else if (g.pl_count)
+            k_pairs64_list<false><<<gb, tb, 0, s>>>(g, n, k, rec, st, od, L_out);
+        else if (k.corr)
+            k_pairs64<true><<<gb, tb, 0, s>>>(g, n, k, rec, st, od, L_out);
         else
-            k_pairs64<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, od, L_out);
+            k_pairs64<false><<<gb, tb, 0, s>>>(g, n, k, rec, st, od, L_out);
         SPH_LAUNCHED();
     } else {
         k_narrow<<<blocks_for(n), kBlock, 0, s>>>(rec, n, r32);
         SPH_LAUNCHED();
         TimedRegion t("pairs_fp32comp", s);
-        if (g.pl_count)
-            k_pairs32_list<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, r32, st, od, L_out);
+        const dim3 gb(blocks_for(n)), tb(kBlock);
+        if (g.pl_count && k.corr)
+            k_pairs32_list<true><<<gb, tb, 0, s>>>(g, n, k, rec, r32, st, od, L_out);
+        else if (g.pl_count)
+            k_pairs32_list<false><<<gb, tb, 0, s>>>(g, n, k, rec, r32, st, od, L_out);
+        else if (k.corr)
+            k_pairs32<true><<<gb, tb, 0, s>>>(g, n, k, rec, r32, st, od, L_out);
         else
-            k_pairs32<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, r32, st, od, L_out);
+            k_pairs32<false><<<gb, tb, 0, s>>>(g, n, k, rec, r32, st, od, L_out);
         SPH_LAUNCHED();
     }
     return SPH_OK;

@@ -12,6 +12,7 @@ struct Consts {
     double Fn;  // 6 s / h^5
     double rho0, c2, mu, Y0, Y0sq;
     double alpha_c, beta, epsh2, rho_cut;
+    int corr;  // correction tensor of section 3.1.6 on the stress-rate gradient
 };
 
 inline Consts make_consts(const sph_params &p, double delta) {
@@ -32,6 +33,7 @@ inline Consts make_consts(const sph_params &p, double delta) {
     k.beta = p.beta;
     k.epsh2 = p.eps_v * p.h * p.h;
     k.rho_cut = p.rho_cut;
+    k.corr = p.correction != 0.0;
     return k;
 }
 
@@ -239,10 +241,14 @@ struct Acc64 {
     double rs = 0.0;
     double L[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     double ax = 0.0, ay = 0.0, az = 0.0;
+    // with the correction: M = sum_b V_b (x_b - x_a) (x) grad_a W_ab, which is
+    // -V_b F r r^T per pair and so symmetric (xx yy zz xy xz yz)
+    double M[6] = {0, 0, 0, 0, 0, 0};
 };
 
 // One ordered pair (a target, b partner).  r = x_a - x_b, dv = v_b - v_a,
 // B = T_a + T_b (six components).
+template <bool kCorr = false>
 __device__ inline void pair64(const Consts &k, double d2, double rx, double ry, double rz,
                               double dvx, double dvy, double dvz, double ra, double rb,
                               double Bxx, double Byy, double Bzz, double Bxy, double Bxz,
@@ -268,6 +274,16 @@ __device__ inline void pair64(const Consts &k, double d2, double rx, double ry, 
     a.ax = fma(mb, bxx * gx + Bxy * gy + Bxz * gz, a.ax);
     a.ay = fma(mb, Bxy * gx + byy * gy + Byz * gz, a.ay);
     a.az = fma(mb, Bxz * gx + Byz * gy + bzz * gz, a.az);
+    if constexpr (kCorr) {
+        const double P = -Vb * F;
+        const double px = P * rx, py = P * ry, pz = P * rz;
+        a.M[0] = fma(px, rx, a.M[0]);
+        a.M[1] = fma(py, ry, a.M[1]);
+        a.M[2] = fma(pz, rz, a.M[2]);
+        a.M[3] = fma(px, ry, a.M[3]);
+        a.M[4] = fma(px, rz, a.M[4]);
+        a.M[5] = fma(py, rz, a.M[5]);
+    }
 }
 
 // Kahan-compensated single-precision sum (Kahan 1965): c carries the low-order
@@ -284,9 +300,10 @@ struct Kahan {
 };
 
 struct Acc32 {
-    Kahan rs, L[9], ax, ay, az;
+    Kahan rs, L[9], ax, ay, az, M[6];
 };
 
+template <bool kCorr = false>
 __device__ inline void pair32(const Consts32 &k, float d2, float rx, float ry, float rz, float dvx,
                               float dvy, float dvz, float ra, float rb, float Bxx, float Byy,
                               float Bzz, float Bxy, float Bxz, float Byz, float mb, float Vb,
@@ -319,18 +336,71 @@ __device__ inline void pair32(const Consts32 &k, float d2, float rx, float ry, f
     a.ax.add(mb * (bxx * gx + Bxy * gy + Bxz * gz));
     a.ay.add(mb * (Bxy * gx + byy * gy + Byz * gz));
     a.az.add(mb * (Bxz * gx + Byz * gy + bzz * gz));
+    if constexpr (kCorr) {
+        const float P = -Vb * F;
+        const float px = P * rx, py = P * ry, pz = P * rz;
+        a.M[0].add(px * rx);
+        a.M[1].add(py * ry);
+        a.M[2].add(pz * rz);
+        a.M[3].add(px * ry);
+        a.M[4].add(px * rz);
+        a.M[5].add(py * rz);
+    }
+}
+
+// Correction tensor C = M^{-1} of a symmetric M (xx yy zz xy xz yz) by the
+// adjugate, into C[3 i + j]; the identity where det M <= 1e-12 (tr M / 3)^3
+// (fewer than three non-coplanar partners).  Section 3.1.6.
+__device__ inline void correction_tensor(const double M[6], double C[9]) {
+    const double a = M[0], b = M[1], c = M[2], d = M[3], e = M[4], f = M[5];
+    const double A00 = b * c - f * f, A01 = e * f - d * c, A02 = d * f - e * b;
+    const double A11 = a * c - e * e, A12 = e * d - a * f, A22 = a * b - d * d;
+    const double det = a * A00 + d * A01 + e * A02;
+    const double t = (a + b + c) / 3.0;
+    if (det > 1e-12 * t * t * t && isfinite(det)) {
+        const double id = 1.0 / det;
+        C[0] = A00 * id; C[1] = A01 * id; C[2] = A02 * id;
+        C[3] = A01 * id; C[4] = A11 * id; C[5] = A12 * id;
+        C[6] = A02 * id; C[7] = A12 * id; C[8] = A22 * id;
+    } else {
+        C[0] = 1.0; C[1] = 0.0; C[2] = 0.0;
+        C[3] = 0.0; C[4] = 1.0; C[5] = 0.0;
+        C[6] = 0.0; C[7] = 0.0; C[8] = 1.0;
+    }
+}
+
+// Lc = L C (row-major 3x3)
+__device__ inline void corrected_gradient(const double L[9], const double M[6], double Lc[9]) {
+    double C[9];
+    correction_tensor(M, C);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            Lc[3 * i + j] = L[3 * i] * C[j] + L[3 * i + 1] * C[3 + j] + L[3 * i + 2] * C[6 + j];
 }
 
 // Stress rate (Hooke + Jaumann, section 2.4) and continuity for user particle a
 // from its velocity gradient L (L[3 i + j] = dv_i / dx_j), written with the
 // other outputs.  S~ = f_Y S;  dS = 2 mu (sym L - tr L / 3 I) + R S~ - S~ R.
-__device__ inline void postpass(const Consts &k, int a, double rho, const double L[9], double ax,
+// With M (the correction's moment matrix), the strain and rotation rates use
+// L C; the continuity equation keeps tr L.
+__device__ inline void postpass(const Consts &k, int a, double rho, const double L0[9], double ax,
                                 double ay, double az, double rs, const StateDev &st,
-                                const OutDev &o) {
+                                const OutDev &o, const double *M = nullptr) {
     double S[6] = {st.sxx[a], st.syy[a], st.szz[a], st.sxy[a], st.sxz[a], st.syz[a]};
     const double f = yield_factor(k, S);
     const double sa = f * S[0], sb = f * S[1], sc = f * S[2];
     const double sd = f * S[3], se = f * S[4], sf = f * S[5];
+    o.drho[a] = -rho * (L0[0] + L0[4] + L0[8]);
+    double Lc[9];
+    if (M) {
+        corrected_gradient(L0, M, Lc);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) Lc[i] = L0[i];
+    }
+    const double *L = Lc;
     const double tr = L[0] + L[4] + L[8];
     const double wz = 0.5 * (L[1] - L[3]);  // R_xy
     const double wy = 0.5 * (L[2] - L[6]);  // R_xz
@@ -342,7 +412,6 @@ __device__ inline void postpass(const Consts &k, int a, double rho, const double
     o.dsxy[a] = k.mu * (L[1] + L[3]) + wz * (sb - sa) + wy * sf + wx * se;
     o.dsxz[a] = k.mu * (L[2] + L[6]) + wy * (sc - sa) + wz * sf - wx * sd;
     o.dsyz[a] = k.mu * (L[5] + L[7]) + wx * (sc - sb) - wz * se - wy * sd;
-    o.drho[a] = -rho * tr;
     o.ax[a] = ax;
     o.ay[a] = ay;
     o.az[a] = az;
@@ -385,7 +454,8 @@ int prepass_launch(const GridDev &g, const StateDev &st, int64_t n, const Consts
 int check_state(const sph_grid *grid, const sph_state *st);
 int check_params(const sph_grid *grid, const sph_params *pr);
 int check_deriv(const sph_deriv *o);
-// L_out (nullable): the velocity gradient of every slot, 9 arrays of n (slot order).
+// L_out (nullable): the velocity gradient of every slot, 9 arrays of n (slot order),
+// followed with the correction by its moment matrix M, 6 arrays (xx yy zz xy xz yz).
 // slot_state: the state and output arrays are in the grid's slot order.
 int rhs_launch(const sph_grid *grid, const sph_state *state, const sph_params *params,
                int precision, const sph_deriv *out, Carve &c, hipStream_t s,

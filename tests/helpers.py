@@ -15,25 +15,34 @@ def split(out: dict) -> dict:
                 dszz=s[2], dsxy=s[3], dsxz=s[4], dsyz=s[5], rho_sum=np.asarray(out["rho_sum"]))
 
 
-def scales(ref: dict, rho=None) -> dict:
+def scales(ref: dict, rho=None, mu=None) -> dict:
     """Error scale of every output field: the field's own max |ref|, floored at GROUP_FLOOR
     times the max of the vector/tensor it belongs to (acceleration components, stress-rate
     components; drho against rho * |L| when the reference carries L), so that components
     that vanish by symmetry are measured against the size of their group, not against
-    roundoff."""
+    roundoff.  With ``mu``, a stress-rate component is measured against at least the
+    Hooke term's size 2 mu max|L|, the size its rounding scales with: where the strain
+    rate cancels to zero (a rigid rotation under the corrected gradient) the result is
+    the rotation terms alone, far smaller than the terms that cancelled."""
     r = split(ref)
     g = {"acc": max(np.abs(r[k]).max() for k in ("ax", "ay", "az")),
          "dS": max(np.abs(r[k]).max() for k in ("dsxx", "dsyy", "dszz", "dsxy", "dsxz", "dsyz")),
          "drho": np.abs(r["drho"]).max(), "rho_sum": np.abs(r["rho_sum"]).max()}
     if "L" in ref and rho is not None:
         g["drho"] = max(g["drho"], np.abs(np.asarray(rho)).max() * np.abs(np.asarray(ref["L"])).max())
-    return {k: max(np.abs(r[k]).max(), GROUP_FLOOR * g[GROUPS[k]]) for k in FIELDS}
+    sc = {k: max(np.abs(r[k]).max(), GROUP_FLOOR * g[GROUPS[k]]) for k in FIELDS}
+    if "L" in ref and mu is not None:
+        hooke = 2.0 * mu * np.abs(np.asarray(ref["L"])).max()
+        for k in FIELDS:
+            if GROUPS[k] == "dS":
+                sc[k] = max(sc[k], hooke)
+    return sc
 
 
-def normwise(got: dict, ref: dict, rho=None) -> dict:
+def normwise(got: dict, ref: dict, rho=None, mu=None) -> dict:
     """max_a |got - ref| / scale for every output field (see ``scales``)."""
     gg, rr = split(got), split(ref)
-    sc = scales(ref, rho)
+    sc = scales(ref, rho, mu)
     res = {}
     for k in FIELDS:
         err = np.abs(gg[k] - rr[k]).max()

@@ -228,3 +228,53 @@ def test_two_spheres_subsample(precision):
 def test_bullet_into_cube_subsample(precision):
     w = W.config(2, state="random")
     _subsample_parity(w, 1024, precision, seed=12)
+
+
+CORR_PATHS = ["cells1", "cells2", "pairs_skin", "pairs2_skin"]
+
+
+@pytest.mark.parametrize("name", ["cube16_shuffled", "cube12_visc", "cube9_lattice_rotation"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32comp"])
+@pytest.mark.parametrize("path", CORR_PATHS)
+def test_rhs_corrected_matches_oracle(name, precision, path):
+    """Corrected velocity gradient (section 3.1.6): same bars as the standard form, the
+    stress-rate scale counting the Hooke term 2 mu |L| (the corrected rigid rotation
+    cancels its strain rate exactly, leaving only the much smaller rotation terms)."""
+    w = _variant(name)
+    w.params["correction"] = 1.0
+    ref = native.rhs_workload(w)
+    got = gpu_rhs(w, precision, **PATHS[path])
+    mu = w.params["mu"]
+    err = normwise(got, ref, w.rho, mu)
+    bad = {k: v for k, v in err.items() if not v <= TOL[precision]}
+    assert not bad, bad
+    w.params["correction"] = 0.0  # the comparison has teeth: the forms differ
+    plain = native.rhs_workload(w)
+    assert max(normwise(plain, ref, w.rho, mu).values()) > 1e3 * TOL[precision]
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32comp", 1e-4)])
+@pytest.mark.parametrize("path", ["cells1", "pairs2_skin"])
+def test_rhs_corrected_linear_field_exact(precision, tol, path):
+    """A linear velocity field v = A x + b with S = 0 gives dS = 2 mu dev(sym A) at every
+    particle, surface included, once the gradient is corrected (A M C = A)."""
+    w = W.cube(12, 0.1, seed=4, jitter=0.1, state="rest", correction=1.0)
+    rng = np.random.default_rng(6)
+    A = rng.normal(size=(3, 3)) * 100.0
+    w.vel = np.ascontiguousarray(A @ w.pos + rng.normal(size=(3, 1)))
+    got = gpu_rhs(w, precision, **PATHS[path])
+    E = 0.5 * (A + A.T)
+    D = 2 * w.params["mu"] * (E - np.trace(E) / 3 * np.eye(3))
+    want = np.array([D[0, 0], D[1, 1], D[2, 2], D[0, 1], D[0, 2], D[1, 2]])
+    err = np.abs(got["dS"] - want[:, None]).max() / np.abs(want).max()
+    assert err < tol, err
+
+
+def test_corrected_adjoint_is_refused():
+    w = W.config(0)
+    w.params["correction"] = 1.0
+    st = gpu_state(w)
+    g = P.sph_build_cells(st.pos, w.h)
+    with pytest.raises(L.SphError) as e:
+        P.sph_rhs_adjoint(g, st, w.params, {"acc": torch.ones(3, w.n, dtype=torch.float64).cuda()})
+    assert e.value.code == L.SPH_ERR_NOT_IMPLEMENTED

@@ -36,7 +36,7 @@ def test_workspace_sizes():
         b = L.workspace_bytes(op, 100000, 10000)
         assert 0 < a <= b
     assert L.workspace_bytes(99, 10, 10) == 0
-    assert L.checkpoint_bytes(10, 2) == 3 * 32 * 10 * 8
+    assert L.checkpoint_bytes(10, 2) == 3 * 38 * 10 * 8
 
 
 def test_grid_geometry():
