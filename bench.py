@@ -72,7 +72,7 @@ TRAFFIC = {"kernel": "k_adj_pairs_list", "workload": "two_spheres_262144",
            "fetch_bytes": 776.9e6, "write_bytes": 30.4e6,
            "profile": "profiles/hbm_traffic_two_spheres_262144.md"}
 
-KERNEL_SOURCES = {"k_adj_pairs_list": ("adjoint.hip", "rhs_common.hpp", "common.hpp"),
+KERNEL_SOURCES = {"k_adj_pairs_list": ("adjoint.hip", "adjoint.hpp", "rhs_common.hpp", "common.hpp"),
                   "k_pairs64_list": ("rhs.hip", "rhs_common.hpp", "common.hpp")}
 
 
@@ -182,11 +182,17 @@ def main():
     dev = "cuda"
     st = P.ParticleState.from_arrays(w.pos, w.vel, w.rho, w.S, w.m, dev)
     steps_lf = max(w.steps, 1)
-    # Skin of the frozen grid and list: twice the largest displacement the trajectory can
-    # make at its initial speeds, with 50 % margin (skin / 2 must cover every particle's
-    # movement; the device flag STALE_GRID would end the run otherwise), at least 0.02 dx.
-    vmax = float(np.sqrt((w.vel ** 2).sum(0)).max())
-    skin = max(3.0 * vmax * steps_lf * w.dt, 0.02 * w.dx)
+    # Skin of the frozen grid and list: twice the largest displacement the trajectory makes,
+    # with 50 % margin (skin / 2 must cover every particle's movement; the device flag
+    # STALE_GRID would end the run otherwise), at least 0.02 dx.  The displacement is
+    # measured on one untimed trajectory under a grid with a generous skin of one dx.
+    g0 = P.sph_build_cells(st.pos, w.h, skin=w.dx, cells_per_h=CELLS_PER_H)
+    P.sph_build_pairs(g0, st.pos)
+    f0, _ = P.sph_leapfrog(g0, st, w.params, w.dt, steps_lf, checkpoints=False)
+    L.check(P.workspace_status(f0._ws))
+    dmax = float(((f0.pos - st.pos) ** 2).sum(0).sqrt().max())
+    del g0, f0
+    skin = max(3.0 * dmax, 0.02 * w.dx)
     lo, hi = P.api.default_box(st.pos, w.h, skin)
     dims, ncells, _ = L.grid_geometry(lo, hi, w.h, skin, CELLS_PER_H)
     n = w.n

@@ -31,37 +31,12 @@
 //
 // mu_bar and Y0_bar are reduced per block with a fixed tree and then by one
 // block in a fixed order, so results are reproducible bit for bit.
+#include "adjoint.hpp"
 #include "common.hpp"
 #include "rhs_common.hpp"
 #include "timing.hpp"
 
 namespace sph {
-
-// Adjoint operand records, one 128-byte record per slot:
-//   Lbar(9) | abar(3) | rho_sum bar | - - -
-constexpr int kAdj = 16;
-
-struct AdjRec {
-    double *L[9];      // forward velocity gradient (slot order)
-    double *arec;      // adjoint records [n][kAdj]
-    double *rhob;      // partial density cotangent from the post stage
-    double *Stb[6];    // partial cotangent of f_Y S from the rotation terms (stored components)
-    double *part_mu;   // per-block partial sums
-    double *part_y0;
-    int add_parts;     // add the block sums to part_* instead of writing them
-};
-
-inline AdjRec carve_adj(Carve &c, int64_t n) {
-    AdjRec r;
-    for (int i = 0; i < 9; ++i) r.L[i] = c.take<double>(n);
-    r.arec = c.take<double>((size_t)n * kAdj);
-    r.rhob = c.take<double>(n);
-    for (int i = 0; i < 6; ++i) r.Stb[i] = c.take<double>(n);
-    r.part_mu = c.take<double>(blocks_for(n));
-    r.part_y0 = c.take<double>(blocks_for(n));
-    r.add_parts = 0;
-    return r;
-}
 
 namespace {
 
@@ -158,68 +133,14 @@ __global__ __launch_bounds__(kBlock) void k_adj_post(GridDev g, int64_t n, Const
     double mu_part = 0.0;
     if (s < n) {
         const int a = io_index(g, s);
-        double L[3][3];
+        double L[9], c6[6];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) L[i / 3][i % 3] = ad.L[i][s];
-        const double rho = rec[s * kRec + 6];
-        double S[6] = {st.sxx[a], st.syy[a], st.szz[a], st.sxy[a], st.sxz[a], st.syz[a]};
-        const double f = yield_factor(k, S);
-        const double St[3][3] = {{f * S[0], f * S[3], f * S[4]},
-                                 {f * S[3], f * S[1], f * S[5]},
-                                 {f * S[4], f * S[5], f * S[2]}};
-        double c6[6];
+        for (int i = 0; i < 9; ++i) L[i] = ad.L[i][s];
+        const double S[6] = {st.sxx[a], st.syy[a], st.szz[a], st.sxy[a], st.sxz[a], st.syz[a]};
 #pragma unroll
         for (int i = 0; i < 6; ++i) c6[i] = ld(cot.ds[i], a);
-        const double G[3][3] = {{c6[0], 0.5 * c6[3], 0.5 * c6[4]},
-                                {0.5 * c6[3], c6[1], 0.5 * c6[5]},
-                                {0.5 * c6[4], 0.5 * c6[5], c6[2]}};
-        const double rdot = ld(cot.drho, a);
-        const double trG = G[0][0] + G[1][1] + G[2][2];
-        double R[3][3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) R[i][j] = 0.5 * (L[i][j] - L[j][i]);
-        double Lb[9];
-        double mu_b = 0.0;
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const double D = G[i][j] - (i == j ? trG / 3.0 : 0.0);
-                double P = 0.0;  // (G S~ - S~ G)_ij
-#pragma unroll
-                for (int m = 0; m < 3; ++m) P += G[i][m] * St[m][j] - St[i][m] * G[m][j];
-                Lb[3 * i + j] = (i == j ? -rho * rdot : 0.0) + 2.0 * k.mu * D + P;
-                mu_b += 2.0 * D * L[i][j];
-            }
-        mu_part = mu_b;
-        ad.rhob[s] = -(L[0][0] + L[1][1] + L[2][2]) * rdot;
-        double Sb[3][3];  // G R - R G
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                double v = 0.0;
-#pragma unroll
-                for (int m = 0; m < 3; ++m) v += G[i][m] * R[m][j] - R[i][m] * G[m][j];
-                Sb[i][j] = v;
-            }
-        ad.Stb[0][s] = Sb[0][0];
-        ad.Stb[1][s] = Sb[1][1];
-        ad.Stb[2][s] = Sb[2][2];
-        ad.Stb[3][s] = Sb[0][1] + Sb[1][0];
-        ad.Stb[4][s] = Sb[0][2] + Sb[2][0];
-        ad.Stb[5][s] = Sb[1][2] + Sb[2][1];
-        double2 *o = reinterpret_cast<double2 *>(ad.arec + s * kAdj);
-        o[0] = make_double2(Lb[0], Lb[1]);
-        o[1] = make_double2(Lb[2], Lb[3]);
-        o[2] = make_double2(Lb[4], Lb[5]);
-        o[3] = make_double2(Lb[6], Lb[7]);
-        o[4] = make_double2(Lb[8], ld(cot.ax, a));
-        o[5] = make_double2(ld(cot.ay, a), ld(cot.az, a));
-        o[6] = make_double2(ld(cot.rho_sum, a), 0.0);
-        o[7] = make_double2(0.0, 0.0);
+        mu_part = adj_post_at(k, s, L, rec[s * kRec + 6], S, c6, ld(cot.drho, a), ld(cot.ax, a),
+                              ld(cot.ay, a), ld(cot.az, a), ld(cot.rho_sum, a), ad);
     }
     const double tot = block_sum(mu_part);
     if (threadIdx.x == 0) put(ad.part_mu, blockIdx.x, tot, ad.add_parts);
@@ -485,21 +406,26 @@ GradDev grad_dev(const sph_fields *g, int accumulate) {
 int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_params *params,
                        const CotDev &cot, const GradDev &grad, double *dparams, int accumulate_params,
                        Carve &c, hipStream_t s, const double *L_in, bool slot_state,
-                       double *acc_parts) {
+                       double *acc_parts, bool post_ready) {
     const int64_t n = grid->n;
     GridDev g = grid_dev(grid);
     if (slot_state) g.io = nullptr;
     Consts k = make_consts(*params, g.delta);
-    double *rec = c.take<double>((size_t)n * kRec);
-    AdjRec ad = carve_adj(c, n);
+    const AdjBuffers bufs = adj_buffers(c, n);
+    double *rec = bufs.rec;
+    AdjRec ad = bufs.ad;
     if (acc_parts) {
         ad.part_mu = acc_parts;
         ad.part_y0 = acc_parts + blocks_for(n);
         ad.add_parts = 1;
     }
     StateDev st = state_dev(state);
-    int rc = prepass_launch(g, st, n, k, rec, c.status(), s);
-    if (rc) return rc;
+    int rc;
+    if (post_ready) {
+        if (!L_in || !acc_parts) return fail(SPH_ERR_INVALID_ARG, "post stage not prepared");
+    } else if ((rc = prepass_launch(g, st, n, k, rec, c.status(), s))) {
+        return rc;
+    }
     if (L_in) {
         for (int i = 0; i < 9; ++i) ad.L[i] = const_cast<double *>(L_in) + (size_t)i * n;
     } else {
@@ -510,8 +436,10 @@ int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_p
             k_adj_L<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, ad);
         SPH_LAUNCHED();
     }
-    k_adj_post<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, cot, ad);
-    SPH_LAUNCHED();
+    if (!post_ready) {
+        k_adj_post<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, cot, ad);
+        SPH_LAUNCHED();
+    }
     {
         TimedRegion t("adjoint_pairs", s);
         if (g.pl_count)

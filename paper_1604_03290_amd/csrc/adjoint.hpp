@@ -1,0 +1,116 @@
+// Internals of the right-hand side's adjoint shared by adjoint.hip and the
+// leapfrog's reverse sweep (which fuses the post stage into its kick pass).
+#pragma once
+
+#include "common.hpp"
+#include "rhs_common.hpp"
+
+namespace sph {
+
+// Adjoint operand records, one 128-byte record per slot:
+//   Lbar(9) | abar(3) | rho_sum bar | - - -
+constexpr int kAdj = 16;
+
+struct AdjRec {
+    double *L[9];      // forward velocity gradient (slot order)
+    double *arec;      // adjoint records [n][kAdj]
+    double *rhob;      // partial density cotangent from the post stage
+    double *Stb[6];    // partial cotangent of f_Y S from the rotation terms (stored components)
+    double *part_mu;   // per-block partial sums
+    double *part_y0;
+    int add_parts;     // add the block sums to part_* instead of writing them
+};
+
+inline AdjRec carve_adj(Carve &c, int64_t n) {
+    AdjRec r;
+    for (int i = 0; i < 9; ++i) r.L[i] = c.take<double>(n);
+    r.arec = c.take<double>((size_t)n * kAdj);
+    r.rhob = c.take<double>(n);
+    for (int i = 0; i < 6; ++i) r.Stb[i] = c.take<double>(n);
+    r.part_mu = c.take<double>(blocks_for(n));
+    r.part_y0 = c.take<double>(blocks_for(n));
+    r.add_parts = 0;
+    return r;
+}
+
+// The operand records and adjoint buffers of rhs_adjoint_launch, its first carves.
+struct AdjBuffers {
+    double *rec;
+    AdjRec ad;
+};
+
+inline AdjBuffers adj_buffers(Carve &c, int64_t n) {
+    AdjBuffers b;
+    b.rec = c.take<double>((size_t)n * kRec);
+    b.ad = carve_adj(c, n);
+    return b;
+}
+
+// Post stage at slot s (see adjoint.hip's header): from the forward velocity
+// gradient L (row-major), density rho and stress S (before the limiter) of the
+// particle and the cotangents of its outputs (c6: stored dS components, rdot:
+// drho, ax..az: acceleration, rs_cot: rho_sum), writes the adjoint record, the
+// partial density cotangent and the rotation terms' stress cotangent; returns
+// the particle's mu contribution.
+__device__ inline double adj_post_at(const Consts &k, int64_t s, const double Lv[9], double rho,
+                                     const double S[6], const double c6[6], double rdot, double ax,
+                                     double ay, double az, double rs_cot, const AdjRec &ad) {
+    double L[3][3];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) L[i / 3][i % 3] = Lv[i];
+    const double f = yield_factor(k, S);
+    const double St[3][3] = {{f * S[0], f * S[3], f * S[4]},
+                             {f * S[3], f * S[1], f * S[5]},
+                             {f * S[4], f * S[5], f * S[2]}};
+    const double G[3][3] = {{c6[0], 0.5 * c6[3], 0.5 * c6[4]},
+                            {0.5 * c6[3], c6[1], 0.5 * c6[5]},
+                            {0.5 * c6[4], 0.5 * c6[5], c6[2]}};
+    const double trG = G[0][0] + G[1][1] + G[2][2];
+    double R[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) R[i][j] = 0.5 * (L[i][j] - L[j][i]);
+    double Lb[9];
+    double mu_b = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const double D = G[i][j] - (i == j ? trG / 3.0 : 0.0);
+            double P = 0.0;  // (G S~ - S~ G)_ij
+#pragma unroll
+            for (int m = 0; m < 3; ++m) P += G[i][m] * St[m][j] - St[i][m] * G[m][j];
+            Lb[3 * i + j] = (i == j ? -rho * rdot : 0.0) + 2.0 * k.mu * D + P;
+            mu_b += 2.0 * D * L[i][j];
+        }
+    ad.rhob[s] = -(L[0][0] + L[1][1] + L[2][2]) * rdot;
+    double Sb[3][3];  // G R - R G
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            double v = 0.0;
+#pragma unroll
+            for (int m = 0; m < 3; ++m) v += G[i][m] * R[m][j] - R[i][m] * G[m][j];
+            Sb[i][j] = v;
+        }
+    ad.Stb[0][s] = Sb[0][0];
+    ad.Stb[1][s] = Sb[1][1];
+    ad.Stb[2][s] = Sb[2][2];
+    ad.Stb[3][s] = Sb[0][1] + Sb[1][0];
+    ad.Stb[4][s] = Sb[0][2] + Sb[2][0];
+    ad.Stb[5][s] = Sb[1][2] + Sb[2][1];
+    double2 *o = reinterpret_cast<double2 *>(ad.arec + s * kAdj);
+    o[0] = make_double2(Lb[0], Lb[1]);
+    o[1] = make_double2(Lb[2], Lb[3]);
+    o[2] = make_double2(Lb[4], Lb[5]);
+    o[3] = make_double2(Lb[6], Lb[7]);
+    o[4] = make_double2(Lb[8], ax);
+    o[5] = make_double2(ay, az);
+    o[6] = make_double2(rs_cot, 0.0);
+    o[7] = make_double2(0.0, 0.0);
+    return mu_b;
+}
+
+}  // namespace sph

@@ -15,6 +15,7 @@
 // its moment matrix: 38 arrays of n doubles in slot order.  The reverse sweep walks the steps backwards, recomputing U' from
 // the checkpoint, and applies in turn the adjoints of the second kick, of the
 // right-hand side at (x_{n+1}, U'), of the drift and of the first kick.
+#include "adjoint.hpp"
 #include "common.hpp"
 #include "rhs_common.hpp"
 
@@ -57,10 +58,13 @@ __device__ inline void kick_at(double v[3], double &rho, double S[6], const doub
 // One pass between two right-hand sides: with kick2 the second kick of the
 // previous step (U_k = kick(U', F_k)); with slab the checkpoint (U_k, F_k); with
 // kick1 the first kick and the drift of the next step (U' = kick(U_k, F_k),
-// x += dt v').
+// x += dt v') and the operand records of the next right-hand side (its prepass).
 __global__ __launch_bounds__(kBlock) void k_advance(Fields13 u, Deriv10 d, double *slab, int64_t n,
                                                     double h, double dt, double Y0sq, int kick2,
-                                                    int kick1) {
+                                                    int kick1, GridDev g, Consts k,
+                                                    const double *__restrict__ m,
+                                                    double *__restrict__ rec,
+                                                    int32_t *__restrict__ status) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double v[3], rho, S[6], F[10];
@@ -85,8 +89,13 @@ __global__ __launch_bounds__(kBlock) void k_advance(Fields13 u, Deriv10 d, doubl
     }
     if (kick1) {
         kick_at(v, rho, S, F, h, Y0sq);
+        double x[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) u.p[c][i] += dt * v[c];
+        for (int c = 0; c < 3; ++c) {
+            x[c] = u.p[c][i] + dt * v[c];
+            u.p[c][i] = x[c];
+        }
+        write_rec(g, k, i, x[0], x[1], x[2], v[0], v[1], v[2], rho, S, m[i], rec, status);
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) u.p[3 + c][i] = v[c];
@@ -127,10 +136,11 @@ __global__ __launch_bounds__(kBlock) void k_fill(double *p, int64_t n, double v)
 
 // Adjoint of the kick U_out = kick(U_in, F) at particle i: given S_in, dS and
 // the cotangent of U_out in gU (updated in place to the cotangent of U_in),
-// writes or adds the cotangent of F into gF; returns the Y0 contribution.
+// writes or adds the cotangent of F into gF (and, with Fout, returns its new
+// value there); returns the Y0 contribution.
 __device__ inline double kick_adj_at(const double S_in[6], const double dS[6], const Fields13 &gU,
                                      const Deriv10 &gF, int64_t i, double h, double Y0,
-                                     int accumulate) {
+                                     int accumulate, double *Fout = nullptr) {
     double S[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) S[c] = S_in[c] + h * dS[c];
@@ -163,23 +173,30 @@ __device__ inline double kick_adj_at(const double S_in[6], const double dS[6], c
     for (int c = 0; c < 6; ++c) v[4 + c] = h * out[c];
 #pragma unroll
     for (int c = 0; c < 10; ++c) {
-        if (accumulate)
-            gF.p[c][i] += v[c];
-        else
-            gF.p[c][i] = v[c];
+        const double r = accumulate ? gF.p[c][i] + v[c] : v[c];
+        gF.p[c][i] = r;
+        if (Fout) Fout[c] = r;
     }
     return y0p;
 }
 
 // Reverse sweep, first pass of step k: recompute U' = kick(U_k, F_k) into Up
-// and apply the adjoint of the second kick U_{k+1} =
-// kick(U', F_{k+1}); the Y0 contribution is added to the block's accumulator.
+// and apply the adjoint of the second kick U_{k+1} = kick(U', F_{k+1}); then the
+// first stages of the adjoint of F_{k+1} = F(x_{k+1}, U'): its operand records
+// (prepass) and its post stage, from the checkpointed velocity gradient L_{k+1}
+// and the cotangent of F_{k+1} just completed.  The Y0 and mu contributions are
+// added to the block's accumulators.
 __global__ __launch_bounds__(kBlock) void k_rev_kick2(Fields13 Uk, Deriv10 Fk, Fields13 Up,
                                                       Deriv10 Fk1, Fields13 gU, Deriv10 gF,
                                                       int64_t n, double h, double Y0,
-                                                      int accumulate, double *acc_y0) {
+                                                      int accumulate, double *acc_y0,
+                                                      const double *__restrict__ x1,
+                                                      const double *__restrict__ L1, GridDev g,
+                                                      Consts k, const double *__restrict__ m,
+                                                      double *__restrict__ rec, AdjRec ad,
+                                                      double *acc_mu, int32_t *__restrict__ status) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double y0p = 0.0;
+    double y0p = 0.0, mup = 0.0;
     if (i < n) {
         double v[3], rho = Uk.p[6][i], S[6], F[10], dS[6];
 #pragma unroll
@@ -196,10 +213,22 @@ __global__ __launch_bounds__(kBlock) void k_rev_kick2(Fields13 Uk, Deriv10 Fk, F
         for (int c = 0; c < 6; ++c) Up.p[7 + c][i] = S[c];
 #pragma unroll
         for (int c = 0; c < 6; ++c) dS[c] = Fk1.p[4 + c][i];
-        y0p = kick_adj_at(S, dS, gU, gF, i, h, Y0, accumulate);
+        double cF[10];
+        y0p = kick_adj_at(S, dS, gU, gF, i, h, Y0, accumulate, cF);
+        const double mi = m[i];
+        write_rec(g, k, i, x1[i], x1[n + i], x1[2 * n + i], v[0], v[1], v[2], rho, S, mi, rec,
+                  status);
+        double L[9];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) L[c] = L1[c * n + i];
+        mup = adj_post_at(k, i, L, rho, S, cF + 4, cF[3], cF[0], cF[1], cF[2], 0.0, ad);
     }
     const double tot = block_sum(y0p);
-    if (threadIdx.x == 0) acc_y0[blockIdx.x] += tot;
+    const double tot_mu = block_sum(mup);
+    if (threadIdx.x == 0) {
+        acc_y0[blockIdx.x] += tot;
+        acc_mu[blockIdx.x] += tot_mu;
+    }
 }
 
 // Reverse sweep, last pass of step k: adjoint of the drift (vbar += dt xbar),
@@ -390,17 +419,24 @@ extern "C" int sph_leapfrog(const sph_grid *grid, const sph_state *s0, const sph
     auto rhs = [&](int k) {
         Carve w = rc_ws;
         double *Lout = checkpoints ? checkpoints + ((size_t)k * kArrays + kLOffset) * n : nullptr;
-        return rhs_launch(grid, &st, params, SPH_FP64, &d, w, s, Lout, true);
+        return rhs_launch(grid, &st, params, SPH_FP64, &d, w, s, Lout, true, k > 0);
     };
     const double Y0sq = params->Y0 * params->Y0;
     auto slab = [&](int k) { return checkpoints ? checkpoints + (size_t)k * kArrays * n : nullptr; };
+    GridDev g = grid_dev(grid);
+    g.io = nullptr;
+    const Consts kc = make_consts(*params, g.delta);
+    double *rec = rhs_rec_of(rc_ws, n);
+    int32_t *status = c.status();
     if ((rc = rhs(0))) return rc;
     for (int k = 0; k < steps; ++k) {
-        k_advance<<<nb, kBlock, 0, s>>>(U, F, slab(k), n, half, dt, Y0sq, k > 0, 1);
+        k_advance<<<nb, kBlock, 0, s>>>(U, F, slab(k), n, half, dt, Y0sq, k > 0, 1, g, kc, m, rec,
+                                        status);
         SPH_LAUNCHED();
         if ((rc = rhs(k + 1))) return rc;
     }
-    k_advance<<<nb, kBlock, 0, s>>>(U, F, slab(steps), n, half, dt, Y0sq, 1, 0);
+    k_advance<<<nb, kBlock, 0, s>>>(U, F, slab(steps), n, half, dt, Y0sq, 1, 0, g, kc, m, rec,
+                                    status);
     SPH_LAUNCHED();
     return fields_to_users(grid, U, fields_of(s_final), s);
 }
@@ -452,13 +488,21 @@ extern "C" int sph_leapfrog_adjoint(const sph_grid *grid, const sph_state *s0,
     double *acc_y0 = parts + nb;
 
     const GradDev acc = grad_of(gU);
-    auto adjoint_at = [&](const sph_state &st, const Deriv10 &gF, const double *slab) {
+    auto adjoint_at = [&](const sph_state &st, const Deriv10 &gF, const double *slab,
+                          bool post_ready) {
         CotDev cot{gF.p[0], gF.p[1], gF.p[2], gF.p[3],
                    {gF.p[4], gF.p[5], gF.p[6], gF.p[7], gF.p[8], gF.p[9]}, nullptr};
         Carve w = adj_ws;
         return rhs_adjoint_launch(grid, &st, params, cot, acc, dparams, 1, w, s,
-                                  slab + (size_t)kLOffset * n, true, parts);
+                                  slab + (size_t)kLOffset * n, true, parts, post_ready);
     };
+    // buffers of the fused prepass and post stage (those of rhs_adjoint_launch)
+    GridDev g = grid_dev(grid);
+    g.io = nullptr;
+    const Consts kc = make_consts(*params, g.delta);
+    Carve ab_ws = adj_ws;
+    const AdjBuffers ab = adj_buffers(ab_ws, n);
+    int32_t *status = c.status();
 
     for (int k = steps - 1; k >= 0; --k) {
         double *slab_k = ck + (size_t)k * kArrays * n;
@@ -471,13 +515,15 @@ extern "C" int sph_leapfrog_adjoint(const sph_grid *grid, const sph_state *s0,
         // second kick U_{k+1} = kick(U', F_{k+1}): cotangent of U' and of F_{k+1}
         // (F_{k+1} already holds the first kick of step k+1 unless k+1 = steps)
         k_rev_kick2<<<nb, kBlock, 0, s>>>(Uk, Fk, Up, Fk1, gU, gF1, n, half, Y0,
-                                          k + 1 < steps ? 1 : 0, acc_y0);
+                                          k + 1 < steps ? 1 : 0, acc_y0, Uk1.p[0],
+                                          slab_k1 + (size_t)kLOffset * n, g, kc, m, ab.rec,
+                                          ab.ad, parts, status);
         SPH_LAUNCHED();
         Fields13 Upx = Up;
         for (int c3 = 0; c3 < 3; ++c3) Upx.p[c3] = Uk1.p[c3];
-        // right-hand side F_{k+1} = F(x_{k+1}, U')
+        // right-hand side F_{k+1} = F(x_{k+1}, U'): its pair stage
         const sph_state st1 = state_struct(Upx, m, n);
-        if ((rc = adjoint_at(st1, gF1, slab_k1))) return rc;
+        if ((rc = adjoint_at(st1, gF1, slab_k1, true))) return rc;
         // drift x_{k+1} = x_k + dt v', then the first kick U' = kick(U_k, F_k):
         // cotangent of U_k, fresh cotangent of F_k
         k_rev_kick1<<<nb, kBlock, 0, s>>>(Uk, Fk, gU, gF0, n, half, dt, Y0, acc_y0);
@@ -488,7 +534,7 @@ extern "C" int sph_leapfrog_adjoint(const sph_grid *grid, const sph_state *s0,
     }
     // F_0 = F(x_0, U_0)
     const sph_state st0 = state_struct(slab_fields(ck, n), m, n);
-    if ((rc = adjoint_at(st0, gF1, ck))) return rc;
+    if ((rc = adjoint_at(st0, gF1, ck, false))) return rc;
     // dparams = the accumulators summed in a fixed order
     if ((rc = reduce_params_launch(parts, acc_y0, nb, dparams, 0, s))) return rc;
     return fields_to_users(grid, gU, fields_of(grad0), s);

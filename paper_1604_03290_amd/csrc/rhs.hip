@@ -30,24 +30,9 @@ __global__ __launch_bounds__(kBlock) void k_prepass(GridDev g, StateDev st, int6
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int a = io_index(g, s);
-    const double x = st.x[a], y = st.y[a], z = st.z[a];
-    if (!within_cell(g, (int)s, x, y, z)) raise_flag(status, SPH_ERR_STALE_GRID);
-    const double rho = st.rho[a];
-    if (!(rho > 0.0) || !isfinite(rho)) raise_flag(status, SPH_ERR_DOMAIN);
-    double S[6] = {st.sxx[a], st.syy[a], st.szz[a], st.sxy[a], st.sxz[a], st.syz[a]};
-    const double p = pressure(k, rho);
-    const double f = yield_factor(k, S);
-    const double ir2 = 1.0 / (rho * rho);
-    const double m = st.m[a];
-    double2 *r = reinterpret_cast<double2 *>(rec + s * kRec);
-    r[0] = make_double2(x, y);
-    r[1] = make_double2(z, st.vx[a]);
-    r[2] = make_double2(st.vy[a], st.vz[a]);
-    r[3] = make_double2(rho, m);
-    r[4] = make_double2((f * S[0] - p) * ir2, (f * S[1] - p) * ir2);
-    r[5] = make_double2((f * S[2] - p) * ir2, f * S[3] * ir2);
-    r[6] = make_double2(f * S[4] * ir2, f * S[5] * ir2);
-    r[7] = make_double2(m / rho, 0.0);
+    const double S[6] = {st.sxx[a], st.syy[a], st.szz[a], st.sxy[a], st.sxz[a], st.syz[a]};
+    write_rec(g, k, s, st.x[a], st.y[a], st.z[a], st.vx[a], st.vy[a], st.vz[a], st.rho[a], S,
+              st.m[a], rec, status);
 }
 
 // FP32 copies of the pair operands (positions stay FP64 for the exact test)
@@ -326,19 +311,22 @@ int check_deriv(const sph_deriv *o) {
 }
 
 // Forward right-hand side on a carved workspace (also used by the leapfrog).
+double *rhs_rec_of(Carve c, int64_t n) { return c.take<double>((size_t)n * kRec); }
+
 int rhs_launch(const sph_grid *grid, const sph_state *state, const sph_params *params,
                int precision, const sph_deriv *out, Carve &c, hipStream_t s, double *L_out,
-               bool slot_state) {
+               bool slot_state, bool rec_ready) {
     const int64_t n = grid->n;
     GridDev g = grid_dev(grid);
     if (slot_state) g.io = nullptr;
     Consts k = make_consts(*params, g.delta);
-    double *rec = c.take<double>((size_t)n * kRec);
+    double *rec = rhs_rec_of(c, n);
+    c.take<double>((size_t)n * kRec);
     float *r32 = c.take<float>((size_t)n * kRec32);
     StateDev st = state_dev(state);
     OutDev od = out_dev(out);
-    int rc = prepass_launch(g, st, n, k, rec, c.status(), s);
-    if (rc) return rc;
+    int rc;
+    if (!rec_ready && (rc = prepass_launch(g, st, n, k, rec, c.status(), s))) return rc;
     if (precision == SPH_FP64) {
         TimedRegion t("pairs_fp64", s);
         const dim3 gb(blocks_for(n)), tb(kBlock);

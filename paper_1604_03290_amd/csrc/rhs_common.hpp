@@ -176,6 +176,31 @@ __device__ inline double yield_factor(const Consts &k, const double S[6]) {
     return j3 > k.Y0sq ? k.Y0sq / j3 : 1.0;
 }
 
+// Operand record of slot s (pressure, limiter, T = sigma / rho^2, V = m / rho) from
+// the particle's state; raises STALE_GRID when the particle left its cell (or its
+// list position) by more than skin / 2 and DOMAIN for a non-positive or
+// non-finite density.  The prepass and the leapfrog's fused passes write every
+// record through this one function.
+__device__ inline void write_rec(const GridDev &g, const Consts &k, int64_t s, double x, double y,
+                                 double z, double vx, double vy, double vz, double rho,
+                                 const double S[6], double m, double *__restrict__ rec,
+                                 int32_t *__restrict__ status) {
+    if (!within_cell(g, (int)s, x, y, z)) raise_flag(status, SPH_ERR_STALE_GRID);
+    if (!(rho > 0.0) || !isfinite(rho)) raise_flag(status, SPH_ERR_DOMAIN);
+    const double p = pressure(k, rho);
+    const double f = yield_factor(k, S);
+    const double ir2 = 1.0 / (rho * rho);
+    double2 *r = reinterpret_cast<double2 *>(rec + s * kRec);
+    r[0] = make_double2(x, y);
+    r[1] = make_double2(z, vx);
+    r[2] = make_double2(vy, vz);
+    r[3] = make_double2(rho, m);
+    r[4] = make_double2((f * S[0] - p) * ir2, (f * S[1] - p) * ir2);
+    r[5] = make_double2((f * S[2] - p) * ir2, f * S[3] * ir2);
+    r[6] = make_double2(f * S[4] * ir2, f * S[5] * ir2);
+    r[7] = make_double2(m / rho, 0.0);
+}
+
 // 1/sqrt(x): hardware estimate refined by two Newton steps y <- y (3 - x y^2) / 2
 // (full double precision); +inf at 0.
 __device__ inline double rsqrt64(double x) {
@@ -439,10 +464,14 @@ size_t adjoint_ws_bytes(int64_t n);
 // and gradient arrays are in the grid's slot order instead of user order.
 // acc_parts (nullable): 2 ceil(n / 256) per-block accumulators (mu, then Y0) to
 // which the launch adds its block sums instead of reducing into dparams.
+// post_ready: the operand records and the post stage's outputs (adj_buffers of
+// this carve) are already written, with the mu block sums added to acc_parts;
+// only the pair stage runs (L_in required).
 int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_params *params,
                        const CotDev &cot, const GradDev &grad, double *dparams, int accumulate_params,
                        Carve &c, hipStream_t s, const double *L_in = nullptr,
-                       bool slot_state = false, double *acc_parts = nullptr);
+                       bool slot_state = false, double *acc_parts = nullptr,
+                       bool post_ready = false);
 // dparams[0] (+)= sum of p0, dparams[1] (+)= sum of p1 (null parts skipped),
 // fixed summation order
 int reduce_params_launch(const double *p0, const double *p1, int64_t m, double *dparams,
@@ -457,9 +486,13 @@ int check_deriv(const sph_deriv *o);
 // L_out (nullable): the velocity gradient of every slot, 9 arrays of n (slot order),
 // followed with the correction by its moment matrix M, 6 arrays (xx yy zz xy xz yz).
 // slot_state: the state and output arrays are in the grid's slot order.
+// rec_ready: the operand records (the first carve, rhs_rec_of) already hold the
+// state's records, so the prepass is skipped.
 int rhs_launch(const sph_grid *grid, const sph_state *state, const sph_params *params,
                int precision, const sph_deriv *out, Carve &c, hipStream_t s,
-               double *L_out = nullptr, bool slot_state = false);
+               double *L_out = nullptr, bool slot_state = false, bool rec_ready = false);
+// where rhs_launch on a carve that starts like c keeps its operand records
+double *rhs_rec_of(Carve c, int64_t n);
 size_t rhs_ws_bytes(int64_t n);
 
 // Deterministic sum over a 256-thread block (fixed tree); every thread must call it.
