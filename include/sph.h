@@ -262,7 +262,10 @@ int sph_rhs(const sph_grid *grid, const sph_state *state, const sph_params *para
  * partner set is the one sph_rhs uses at the same positions; every pair term
  * vanishes with its first derivative at distance h, so the product is exact.
  * Gather form: each particle sums its own terms from its partners' data; no
- * atomics, reproducible bit for bit.  Errors as sph_rhs. */
+ * atomics, reproducible bit for bit.  With params->correction = 1 the
+ * correction tensor C = M^-1 is differentiated too (M depends on positions and,
+ * through V = m / rho, on densities); where C fell back to the identity M gets
+ * no cotangent.  Errors as sph_rhs. */
 int sph_rhs_adjoint(const sph_grid *grid, const sph_state *state, const sph_params *params,
                     const sph_deriv_cot *cot, const sph_state_grad *grad, double *dparams,
                     void *ws, size_t ws_bytes, void *stream);

@@ -49,7 +49,20 @@ __device__ inline void put(double *p, int i, double v, int acc) {
         p[i] = v;
 }
 
-// forward velocity gradient of every slot
+// moment matrix of the correction (xx yy zz xy xz yz) += P r r^T, P = -V F
+__device__ inline void moment_add(double M[6], double V, double F, double rx, double ry, double rz) {
+    const double P = -V * F;
+    const double px = P * rx, py = P * ry, pz = P * rz;
+    M[0] = fma(px, rx, M[0]);
+    M[1] = fma(py, ry, M[1]);
+    M[2] = fma(pz, rz, M[2]);
+    M[3] = fma(px, ry, M[3]);
+    M[4] = fma(px, rz, M[4]);
+    M[5] = fma(py, rz, M[5]);
+}
+
+// forward velocity gradient (and with the correction its moment matrix) of every slot
+template <bool kCorr>
 __global__ __launch_bounds__(kBlock) void k_adj_L(GridDev g, int64_t n, Consts k,
                                                   const double *__restrict__ rec, AdjRec ad) {
     const int64_t s = xcd_block(gridDim.x) * kBlock + threadIdx.x;
@@ -58,6 +71,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_L(GridDev g, int64_t n, Consts k
     const double2 p0 = ra[0], p1 = ra[1], p2 = ra[2];
     const double xa = p0.x, ya = p0.y, za = p1.x, vxa = p1.y, vya = p2.x, vza = p2.y;
     double L[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double M[6] = {0, 0, 0, 0, 0, 0};
     for_each_candidate(g, s, xa, ya, za, k.reach, [&](int t) {
         const double2 *rb = rec2(rec, t);
         const double2 b0 = rb[0], b1 = rb[1];
@@ -72,12 +86,18 @@ __global__ __launch_bounds__(kBlock) void k_adj_L(GridDev g, int64_t n, Consts k
         L[0] = fma(tx, gx, L[0]); L[1] = fma(tx, gy, L[1]); L[2] = fma(tx, gz, L[2]);
         L[3] = fma(ty, gx, L[3]); L[4] = fma(ty, gy, L[4]); L[5] = fma(ty, gz, L[5]);
         L[6] = fma(tz, gx, L[6]); L[7] = fma(tz, gy, L[7]); L[8] = fma(tz, gz, L[8]);
+        if (kCorr) moment_add(M, V, F, xa - b0.x, ya - b0.y, za - b1.x);
     });
 #pragma unroll
     for (int i = 0; i < 9; ++i) ad.L[i][s] = L[i];
+    if (kCorr) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) ad.M[i][s] = M[i];
+    }
 }
 
 // same over the frozen pair list with cooperative gathers
+template <bool kCorr>
 __global__ __launch_bounds__(kBlock) void k_adj_L_list(GridDev g, int64_t n, Consts k,
                                                        const double *__restrict__ rec, AdjRec ad) {
     __shared__ double2 lbuf[kBlock / 64][kLdsWave];
@@ -96,6 +116,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_L_list(GridDev g, int64_t n, Con
     }
     const double xa = p0.x, ya = p0.y, za = p1.x, vxa = p1.y, vya = p2.x, vza = p2.y;
     double L[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double M[6] = {0, 0, 0, 0, 0, 0};
     const char *recs = reinterpret_cast<const char *>(rec);
     const int32_t *row = g.pl_slot + base + __lane_id();
     int e0 = steps > 0 ? row[0] : 0;
@@ -116,6 +137,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_L_list(GridDev g, int64_t n, Con
                 L[0] = fma(tx, gx, L[0]); L[1] = fma(tx, gy, L[1]); L[2] = fma(tx, gz, L[2]);
                 L[3] = fma(ty, gx, L[3]); L[4] = fma(ty, gy, L[4]); L[5] = fma(ty, gz, L[5]);
                 L[6] = fma(tz, gx, L[6]); L[7] = fma(tz, gy, L[7]); L[8] = fma(tz, gz, L[8]);
+                if (kCorr) moment_add(M, V, F, xa - b0.x, ya - b0.y, za - b1.x);
             }
         }
         wave_sync();
@@ -123,6 +145,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_L_list(GridDev g, int64_t n, Con
     if (!act) return;
 #pragma unroll
     for (int i = 0; i < 9; ++i) ad.L[i][s] = L[i];
+    if (kCorr) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) ad.M[i][s] = M[i];
+    }
 }
 
 // post stage (see the file header)
@@ -139,8 +165,14 @@ __global__ __launch_bounds__(kBlock) void k_adj_post(GridDev g, int64_t n, Const
         const double S[6] = {st.sxx[a], st.syy[a], st.szz[a], st.sxy[a], st.sxz[a], st.syz[a]};
 #pragma unroll
         for (int i = 0; i < 6; ++i) c6[i] = ld(cot.ds[i], a);
-        mu_part = adj_post_at(k, s, L, rec[s * kRec + 6], S, c6, ld(cot.drho, a), ld(cot.ax, a),
-                              ld(cot.ay, a), ld(cot.az, a), ld(cot.rho_sum, a), ad);
+        double M[6];
+        if (k.corr) {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) M[i] = ad.M[i][s];
+        }
+        mu_part = adj_post_at(k, s, L, k.corr ? M : nullptr, rec[s * kRec + 6], S, c6,
+                              ld(cot.drho, a), ld(cot.ax, a), ld(cot.ay, a), ld(cot.az, a),
+                              ld(cot.rho_sum, a), ad);
     }
     const double tot = block_sum(mu_part);
     if (threadIdx.x == 0) put(ad.part_mu, blockIdx.x, tot, ad.add_parts);
@@ -157,11 +189,17 @@ struct AdjOwn {
 };
 
 // Both roles of the pair (c, b) (see the file header).  b = forward record chunks
-// b0..b7 of the partner, e0..e6 = its adjoint record chunks.
+// b0..b7 of the partner, e0..e6 = its adjoint record chunks.  With the
+// correction, Mc and Mb are the symmetrised cotangents of the moment matrices
+// of c and b, whose terms P r r^T (P = -V_b F, r = x_c - x_b) add
+//   xbar_c += -[V_b (2 F Mc r + (r.Mc r) G r) + V_c (2 F Mb r + (r.Mb r) G r)],
+//   Vbar_c += -F (r.Mb r).
+template <bool kCorr = false>
 __device__ inline void adj_pair(const Consts &k, const AdjOwn &o, double d2, double2 b0,
                                 double2 b1, double2 b2, double2 b3, double2 b4, double2 b5,
                                 double2 b6, double2 b7, double2 e0, double2 e1, double2 e2,
-                                double2 e3, double2 e4, double2 e5, double2 e6, AdjAcc &acc) {
+                                double2 e3, double2 e4, double2 e5, double2 e6, AdjAcc &acc,
+                                const double *Mc = nullptr, const double *Mb = nullptr) {
     const double Gn = k.Fn * k.inv_h * k.inv_h;
     const double Lbb[9] = {e0.x, e0.y, e1.x, e1.y, e2.x, e2.y, e3.x, e3.y, e4.x};
     const double rx = o.xc - b0.x, ry = o.yc - b0.y, rz = o.zc - b1.x;
@@ -216,6 +254,22 @@ __device__ inline void adj_pair(const Consts &k, const AdjOwn &o, double d2, dou
     acc.gV += ux * (Lbb[0] * gx + Lbb[1] * gy + Lbb[2] * gz) +
               uy * (Lbb[3] * gx + Lbb[4] * gy + Lbb[5] * gz) +
               uz * (Lbb[6] * gx + Lbb[7] * gy + Lbb[8] * gz);
+    if constexpr (kCorr) {
+        const double cx = Mc[0] * rx + Mc[3] * ry + Mc[4] * rz;
+        const double cy = Mc[3] * rx + Mc[1] * ry + Mc[5] * rz;
+        const double cz = Mc[4] * rx + Mc[5] * ry + Mc[2] * rz;
+        const double qx = Mb[0] * rx + Mb[3] * ry + Mb[4] * rz;
+        const double qy = Mb[3] * rx + Mb[1] * ry + Mb[5] * rz;
+        const double qz = Mb[4] * rx + Mb[5] * ry + Mb[2] * rz;
+        const double qc = rx * cx + ry * cy + rz * cz;
+        const double qb = rx * qx + ry * qy + rz * qz;
+        const double F2 = 2.0 * F;
+        const double sG = (Vb * qc + o.Vc * qb) * G;
+        acc.gx -= F2 * (Vb * cx + o.Vc * qx) + sG * rx;
+        acc.gy -= F2 * (Vb * cy + o.Vc * qy) + sG * ry;
+        acc.gz -= F2 * (Vb * cz + o.Vc * qz) + sG * rz;
+        acc.gV -= F * qb;
+    }
 }
 
 __device__ inline AdjOwn adj_own(const double *rec, const AdjRec &ad, int64_t s) {
@@ -279,7 +333,9 @@ __device__ inline double adj_pre(const Consts &k, const AdjRec &ad, const AdjOwn
     return y0;
 }
 
-// pair stage + pre stage (see the file header); cell-sweep path
+// pair stage + pre stage (see the file header); cell-sweep path, and with the
+// correction tensor the only path (also over a pair list)
+template <bool kCorr>
 __global__ __launch_bounds__(kBlock) void k_adj_pairs(GridDev g, int64_t n, Consts k,
                                                       const double *__restrict__ rec, StateDev st,
                                                       AdjRec ad, GradDev out) {
@@ -288,14 +344,24 @@ __global__ __launch_bounds__(kBlock) void k_adj_pairs(GridDev g, int64_t n, Cons
     if (s < n) {
         const AdjOwn o = adj_own(rec, ad, s);
         AdjAcc acc;
+        double Mc[6] = {0, 0, 0, 0, 0, 0};
+        if (kCorr) {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) Mc[i] = ad.Mb[i][s];
+        }
         for_each_candidate(g, s, o.xc, o.yc, o.zc, k.reach, [&](int t) {
             const double2 *rb = rec2(rec, t);
             const double2 b0 = rb[0], b1 = rb[1];
             const double d2 = dist2_exact(o.xc, o.yc, o.zc, b0.x, b0.y, b1.x);
             if (!(d2 < k.h2)) return;
             const double2 *qb = reinterpret_cast<const double2 *>(ad.arec + (int64_t)t * kAdj);
-            adj_pair(k, o, d2, b0, b1, rb[2], rb[3], rb[4], rb[5], rb[6], rb[7], qb[0], qb[1],
-                     qb[2], qb[3], qb[4], qb[5], qb[6], acc);
+            double Mb[6] = {0, 0, 0, 0, 0, 0};
+            if (kCorr) {
+#pragma unroll
+                for (int i = 0; i < 6; ++i) Mb[i] = ad.Mb[i][t];
+            }
+            adj_pair<kCorr>(k, o, d2, b0, b1, rb[2], rb[3], rb[4], rb[5], rb[6], rb[7], qb[0],
+                            qb[1], qb[2], qb[3], qb[4], qb[5], qb[6], acc, Mc, Mb);
         });
         y0_part = adj_pre(k, ad, o, acc, s, io_index(g, s), st, out);
     }
@@ -428,12 +494,19 @@ int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_p
     }
     if (L_in) {
         for (int i = 0; i < 9; ++i) ad.L[i] = const_cast<double *>(L_in) + (size_t)i * n;
+        if (k.corr)
+            for (int i = 0; i < 6; ++i) ad.M[i] = const_cast<double *>(L_in) + (size_t)(9 + i) * n;
     } else {
         TimedRegion t("adjoint_L", s);
-        if (g.pl_count)
-            k_adj_L_list<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, ad);
+        const dim3 gb(blocks_for(n)), tb(kBlock);
+        if (g.pl_count && k.corr)
+            k_adj_L_list<true><<<gb, tb, 0, s>>>(g, n, k, rec, ad);
+        else if (g.pl_count)
+            k_adj_L_list<false><<<gb, tb, 0, s>>>(g, n, k, rec, ad);
+        else if (k.corr)
+            k_adj_L<true><<<gb, tb, 0, s>>>(g, n, k, rec, ad);
         else
-            k_adj_L<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, ad);
+            k_adj_L<false><<<gb, tb, 0, s>>>(g, n, k, rec, ad);
         SPH_LAUNCHED();
     }
     if (!post_ready) {
@@ -442,10 +515,12 @@ int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_p
     }
     {
         TimedRegion t("adjoint_pairs", s);
-        if (g.pl_count)
+        if (k.corr)
+            k_adj_pairs<true><<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, ad, grad);
+        else if (g.pl_count)
             k_adj_pairs_list<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, ad, grad);
         else
-            k_adj_pairs<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, ad, grad);
+            k_adj_pairs<false><<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, ad, grad);
         SPH_LAUNCHED();
     }
     if (acc_parts) return SPH_OK;  // the caller reduces its accumulators
@@ -476,8 +551,6 @@ extern "C" int sph_rhs_adjoint(const sph_grid *grid, const sph_state *state,
         return rc;
     if (!cot) return fail(SPH_ERR_INVALID_ARG, "cotangent struct is NULL");
     if (!dparams || !ws) return fail(SPH_ERR_INVALID_ARG, "null pointer");
-    if (params->correction != 0.0)
-        return fail(SPH_ERR_NOT_IMPLEMENTED, "adjoint with the correction tensor");
     const size_t need = adjoint_ws_bytes(grid->n);
     if (ws_bytes < need) return fail(SPH_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
     hipStream_t s = (hipStream_t)stream;

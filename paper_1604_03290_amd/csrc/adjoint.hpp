@@ -13,6 +13,8 @@ constexpr int kAdj = 16;
 
 struct AdjRec {
     double *L[9];      // forward velocity gradient (slot order)
+    double *M[6];      // with the correction: forward moment matrix (xx yy zz xy xz yz)
+    double *Mb[6];     // with the correction: its cotangent, symmetrised
     double *arec;      // adjoint records [n][kAdj]
     double *rhob;      // partial density cotangent from the post stage
     double *Stb[6];    // partial cotangent of f_Y S from the rotation terms (stored components)
@@ -24,6 +26,8 @@ struct AdjRec {
 inline AdjRec carve_adj(Carve &c, int64_t n) {
     AdjRec r;
     for (int i = 0; i < 9; ++i) r.L[i] = c.take<double>(n);
+    for (int i = 0; i < 6; ++i) r.M[i] = c.take<double>(n);
+    for (int i = 0; i < 6; ++i) r.Mb[i] = c.take<double>(n);
     r.arec = c.take<double>((size_t)n * kAdj);
     r.rhob = c.take<double>(n);
     for (int i = 0; i < 6; ++i) r.Stb[i] = c.take<double>(n);
@@ -52,12 +56,28 @@ inline AdjBuffers adj_buffers(Carve &c, int64_t n) {
 // drho, ax..az: acceleration, rs_cot: rho_sum), writes the adjoint record, the
 // partial density cotangent and the rotation terms' stress cotangent; returns
 // the particle's mu contribution.
-__device__ inline double adj_post_at(const Consts &k, int64_t s, const double Lv[9], double rho,
-                                     const double S[6], const double c6[6], double rdot, double ax,
-                                     double ay, double az, double rs_cot, const AdjRec &ad) {
-    double L[3][3];
+//
+// With the correction tensor (Mv: the moment matrix, non-null) the strain and
+// rotation rates see Lc = L C, C = M^-1 (section 3.1.6), so with Lcbar their
+// cotangent:  Lbar = Lcbar C^T - rho drho_bar I,  Cbar = L^T Lcbar and
+// Mbar = -C^T Cbar C^T, stored symmetrised in ad.Mb (zero where C fell back to
+// the identity); mu_bar and S~_bar use Lc.
+__device__ inline double adj_post_at(const Consts &k, int64_t s, const double Lv[9],
+                                     const double *Mv, double rho, const double S[6],
+                                     const double c6[6], double rdot, double ax, double ay,
+                                     double az, double rs_cot, const AdjRec &ad) {
+    double L[3][3], C[9];
+    const bool inv = Mv ? correction_tensor(Mv, C) : false;
+    if (Mv) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) L[i / 3][i % 3] = Lv[i];
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                L[i][j] = Lv[3 * i] * C[j] + Lv[3 * i + 1] * C[3 + j] + Lv[3 * i + 2] * C[6 + j];
+    } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) L[i / 3][i % 3] = Lv[i];
+    }
     const double f = yield_factor(k, S);
     const double St[3][3] = {{f * S[0], f * S[3], f * S[4]},
                              {f * S[3], f * S[1], f * S[5]},
@@ -81,10 +101,44 @@ __device__ inline double adj_post_at(const Consts &k, int64_t s, const double Lv
             double P = 0.0;  // (G S~ - S~ G)_ij
 #pragma unroll
             for (int m = 0; m < 3; ++m) P += G[i][m] * St[m][j] - St[i][m] * G[m][j];
-            Lb[3 * i + j] = (i == j ? -rho * rdot : 0.0) + 2.0 * k.mu * D + P;
+            Lb[3 * i + j] = Mv ? 2.0 * k.mu * D + P : (i == j ? -rho * rdot : 0.0) + 2.0 * k.mu * D + P;
             mu_b += 2.0 * D * L[i][j];
         }
-    ad.rhob[s] = -(L[0][0] + L[1][1] + L[2][2]) * rdot;
+    if (Mv) {
+        // Lb holds Lcbar here
+        double Cb[9], T[9], Mb[9];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                Cb[3 * i + j] = Lv[i] * Lb[j] + Lv[3 + i] * Lb[3 + j] + Lv[6 + i] * Lb[6 + j];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                T[3 * i + j] = Cb[3 * i] * C[3 * j] + Cb[3 * i + 1] * C[3 * j + 1] + Cb[3 * i + 2] * C[3 * j + 2];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                Mb[3 * i + j] = -(C[i] * T[j] + C[3 + i] * T[3 + j] + C[6 + i] * T[6 + j]);
+        const double z = inv ? 1.0 : 0.0;
+        ad.Mb[0][s] = z * Mb[0];
+        ad.Mb[1][s] = z * Mb[4];
+        ad.Mb[2][s] = z * Mb[8];
+        ad.Mb[3][s] = z * 0.5 * (Mb[1] + Mb[3]);
+        ad.Mb[4][s] = z * 0.5 * (Mb[2] + Mb[6]);
+        ad.Mb[5][s] = z * 0.5 * (Mb[5] + Mb[7]);
+        double Lu[9];  // Lcbar C^T
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                Lu[3 * i + j] = Lb[3 * i] * C[3 * j] + Lb[3 * i + 1] * C[3 * j + 1] + Lb[3 * i + 2] * C[3 * j + 2];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) Lb[i] = Lu[i] + (i % 4 == 0 ? -rho * rdot : 0.0);
+    }
+    ad.rhob[s] = -(Lv[0] + Lv[4] + Lv[8]) * rdot;
     double Sb[3][3];  // G R - R G
 #pragma unroll
     for (int i = 0; i < 3; ++i)

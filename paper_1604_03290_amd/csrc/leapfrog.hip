@@ -221,7 +221,13 @@ __global__ __launch_bounds__(kBlock) void k_rev_kick2(Fields13 Uk, Deriv10 Fk, F
         double L[9];
 #pragma unroll
         for (int c = 0; c < 9; ++c) L[c] = L1[c * n + i];
-        mup = adj_post_at(k, i, L, rho, S, cF + 4, cF[3], cF[0], cF[1], cF[2], 0.0, ad);
+        double M[6];
+        if (k.corr) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) M[c] = L1[(9 + c) * n + i];
+        }
+        mup = adj_post_at(k, i, L, k.corr ? M : nullptr, rho, S, cF + 4, cF[3], cF[0], cF[1],
+                          cF[2], 0.0, ad);
     }
     const double tot = block_sum(y0p);
     const double tot_mu = block_sum(mup);
@@ -451,8 +457,6 @@ extern "C" int sph_leapfrog_adjoint(const sph_grid *grid, const sph_state *s0,
     if ((rc = check_lf(grid, s0, params, dt, steps)) || (rc = check_grad(grad0))) return rc;
     if (!checkpoints || !cot_final || !dparams || !ws)
         return fail(SPH_ERR_INVALID_ARG, "null pointer");
-    if (params->correction != 0.0)
-        return fail(SPH_ERR_NOT_IMPLEMENTED, "adjoint with the correction tensor");
     const int64_t n = grid->n;
     const size_t need = leapfrog_adjoint_ws_bytes(n);
     if (ws_bytes < need) return fail(SPH_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);

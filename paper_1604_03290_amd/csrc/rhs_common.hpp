@@ -375,8 +375,9 @@ __device__ inline void pair32(const Consts32 &k, float d2, float rx, float ry, f
 
 // Correction tensor C = M^{-1} of a symmetric M (xx yy zz xy xz yz) by the
 // adjugate, into C[3 i + j]; the identity where det M <= 1e-12 (tr M / 3)^3
-// (fewer than three non-coplanar partners).  Section 3.1.6.
-__device__ inline void correction_tensor(const double M[6], double C[9]) {
+// (fewer than three non-coplanar partners) or is not finite, and then false.
+// Section 3.1.6.
+__device__ inline bool correction_tensor(const double M[6], double C[9]) {
     const double a = M[0], b = M[1], c = M[2], d = M[3], e = M[4], f = M[5];
     const double A00 = b * c - f * f, A01 = e * f - d * c, A02 = d * f - e * b;
     const double A11 = a * c - e * e, A12 = e * d - a * f, A22 = a * b - d * d;
@@ -387,11 +388,12 @@ __device__ inline void correction_tensor(const double M[6], double C[9]) {
         C[0] = A00 * id; C[1] = A01 * id; C[2] = A02 * id;
         C[3] = A01 * id; C[4] = A11 * id; C[5] = A12 * id;
         C[6] = A02 * id; C[7] = A12 * id; C[8] = A22 * id;
-    } else {
-        C[0] = 1.0; C[1] = 0.0; C[2] = 0.0;
-        C[3] = 0.0; C[4] = 1.0; C[5] = 0.0;
-        C[6] = 0.0; C[7] = 0.0; C[8] = 1.0;
+        return true;
     }
+    C[0] = 1.0; C[1] = 0.0; C[2] = 0.0;
+    C[3] = 0.0; C[4] = 1.0; C[5] = 0.0;
+    C[6] = 0.0; C[7] = 0.0; C[8] = 1.0;
+    return false;
 }
 
 // Lc = L C (row-major 3x3)

@@ -60,6 +60,32 @@ def test_rhs_adjoint_matches_oracle(name, pairs):
         assert torch.equal(got[k], again[k]), k
 
 
+@pytest.mark.parametrize("name", ["cube10", "cube8_visc"])
+@pytest.mark.parametrize("pairs", [False, True])
+def test_rhs_adjoint_corrected_matches_oracle(name, pairs):
+    """The correction tensor of section 3.1.6 in the adjoint: the cotangent of the
+    moment matrix and its pair terms, against reverse-mode AD of the oracle."""
+    w = small(name)
+    w.params["correction"] = 1.0
+    ref_out = native.rhs_workload(w, want_L=False)
+    rng = np.random.default_rng(17)
+    cot = {k: rng.normal(size=ref_out[k].shape) / np.abs(ref_out[k]).max() for k in ref_out}
+    ref = AD.rhs_vjp(w, cot)
+    st = gpu_state(w)
+    g = P.sph_build_cells(st.pos, w.h, skin=0.05 * w.dx, pairs=pairs)
+    cg = {k: torch.as_tensor(v).cuda().contiguous() for k, v in cot.items()}
+    got = P.sph_rhs_adjoint(g, st, w.params, cg)
+    assert P.workspace_status(got["_ws"]) == 0
+    for k in ("pos", "vel", "rho", "S"):
+        assert rel(got[k].cpu().numpy(), ref[k]) < 1e-11, k
+    assert abs(float(got["mu"]) - ref["mu"]) <= 1e-11 * abs(ref["mu"])
+    assert abs(float(got["Y0"]) - ref["Y0"]) <= 1e-11 * abs(ref["Y0"])
+    # the comparison has teeth: the uncorrected gradient differs
+    w.params["correction"] = 0.0
+    plain = AD.rhs_vjp(w, cot)
+    assert rel(plain["pos"], ref["pos"]) > 1e-4
+
+
 def test_rhs_adjoint_partial_cotangents():
     w = small("cube10")
     ref_out = native.rhs_workload(w, want_L=False)
@@ -221,3 +247,28 @@ def test_full_size_gradient_matches_oracle_golden(cube40):
     assert abs(float((gv * d).sum()) - gold["v0_dot_direction"]) <= 1e-9 * abs(gold["v0_dot_direction"])
     ref = np.array(gold["v0_sample"])
     assert np.abs(gv[:, gold["sample_index"]] - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
+def test_leapfrog_gradient_corrected_matches_oracle():
+    """Leapfrog and reverse sweep with the correction tensor: every field's gradient
+    (the checkpoint carries the moment matrix beside L)."""
+    w = small("cube8_visc")
+    w.params["correction"] = 1.0
+    steps = 6
+    st, g, fin, ck = run_leapfrog(w, steps, pairs=True, cells_per_h=2)
+    rng = np.random.default_rng(12)
+    cot = {"pos": rng.normal(size=(3, w.n)), "vel": rng.normal(size=(3, w.n)),
+           "rho": rng.normal(size=w.n) * 1e-3, "S": rng.normal(size=(6, w.n)) * 1e-9}
+    got = P.sph_leapfrog_adjoint(g, st, w.params, w.dt, steps, ck,
+                                 {k: torch.as_tensor(v).cuda().contiguous() for k, v in cot.items()})
+    assert P.workspace_status(got["_ws"]) == 0
+    ref = AD.leapfrog_grad_all(w, steps, w.dt, cot)
+    for k in ("pos", "vel", "rho", "S"):
+        assert rel(got[k].cpu().numpy(), ref[k]) < 1e-10, k
+    assert abs(float(got["mu"]) - ref["mu"]) <= 1e-10 * abs(ref["mu"])
+    assert abs(float(got["Y0"]) - ref["Y0"]) <= 1e-10 * abs(ref["Y0"])
+    pos, vel, rho, S, m, par = AD.as_tensors(w)
+    with torch.no_grad():
+        x, v, r, s = AD.leapfrog(pos, vel, rho, S, m, par, steps, w.dt)
+    assert rel(fin.pos.cpu().numpy() - w.pos, x.numpy() - w.pos) < 1e-11
+    assert rel(fin.S.cpu().numpy(), s.numpy()) < 1e-11

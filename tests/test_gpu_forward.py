@@ -269,12 +269,3 @@ def test_rhs_corrected_linear_field_exact(precision, tol, path):
     err = np.abs(got["dS"] - want[:, None]).max() / np.abs(want).max()
     assert err < tol, err
 
-
-def test_corrected_adjoint_is_refused():
-    w = W.config(0)
-    w.params["correction"] = 1.0
-    st = gpu_state(w)
-    g = P.sph_build_cells(st.pos, w.h)
-    with pytest.raises(L.SphError) as e:
-        P.sph_rhs_adjoint(g, st, w.params, {"acc": torch.ones(3, w.n, dtype=torch.float64).cuda()})
-    assert e.value.code == L.SPH_ERR_NOT_IMPLEMENTED
