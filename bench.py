@@ -68,8 +68,8 @@ def load_workload(name):
 # 1 GiB calibration copy.  They hold only for the kernel sources they were taken on: the
 # hash of those files is compared at run time and the figure is dropped on a mismatch.
 TRAFFIC = {"kernel": "k_adj_pairs_list", "workload": "two_spheres_262144",
-           "sources_sha256": "8d23816e4c92582ec597916d5693f4fa38745f878b0e49215e4735464e1c09a8",
-           "fetch_bytes": 776.9e6, "write_bytes": 30.4e6,
+           "sources_sha256": "4e69a4245b82610a309fdb211cc6ce1af272ee94209b08118445c6dbcd175ef4",
+           "fetch_bytes": 750.8e6, "write_bytes": 30.4e6,
            "profile": "profiles/hbm_traffic_two_spheres_262144.md"}
 
 KERNEL_SOURCES = {"k_adj_pairs_list": ("adjoint.hip", "adjoint.hpp", "rhs_common.hpp", "common.hpp"),
@@ -186,8 +186,7 @@ def main():
     # with 50 % margin (skin / 2 must cover every particle's movement; the device flag
     # STALE_GRID would end the run otherwise), at least 0.02 dx.  The displacement is
     # measured on one untimed trajectory under a grid with a generous skin of one dx.
-    g0 = P.sph_build_cells(st.pos, w.h, skin=w.dx, cells_per_h=CELLS_PER_H)
-    P.sph_build_pairs(g0, st.pos)
+    g0 = P.sph_build_cells(st.pos, w.h, skin=w.dx, cells_per_h=CELLS_PER_H)  # cell sweeps, no list
     f0, _ = P.sph_leapfrog(g0, st, w.params, w.dt, steps_lf, checkpoints=False)
     L.check(P.workspace_status(f0._ws))
     dmax = float(((f0.pos - st.pos) ** 2).sum(0).sqrt().max())

@@ -165,12 +165,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_post(GridDev g, int64_t n, Const
         const double S[6] = {st.sxx[a], st.syy[a], st.szz[a], st.sxy[a], st.sxz[a], st.syz[a]};
 #pragma unroll
         for (int i = 0; i < 6; ++i) c6[i] = ld(cot.ds[i], a);
-        double M[6];
+        double M[6] = {0, 0, 0, 0, 0, 0};
         if (k.corr) {
 #pragma unroll
             for (int i = 0; i < 6; ++i) M[i] = ad.M[i][s];
         }
-        mu_part = adj_post_at(k, s, L, k.corr ? M : nullptr, rec[s * kRec + 6], S, c6,
+        mu_part = adj_post_at(k, s, L, k.corr, M, rec[s * kRec + 6], S, c6,
                               ld(cot.drho, a), ld(cot.ax, a), ld(cot.ay, a), ld(cot.az, a),
                               ld(cot.rho_sum, a), ad);
     }

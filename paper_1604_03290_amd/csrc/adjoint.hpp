@@ -57,18 +57,18 @@ inline AdjBuffers adj_buffers(Carve &c, int64_t n) {
 // partial density cotangent and the rotation terms' stress cotangent; returns
 // the particle's mu contribution.
 //
-// With the correction tensor (Mv: the moment matrix, non-null) the strain and
+// With the correction tensor (corr; Mv: the moment matrix) the strain and
 // rotation rates see Lc = L C, C = M^-1 (section 3.1.6), so with Lcbar their
 // cotangent:  Lbar = Lcbar C^T - rho drho_bar I,  Cbar = L^T Lcbar and
 // Mbar = -C^T Cbar C^T, stored symmetrised in ad.Mb (zero where C fell back to
 // the identity); mu_bar and S~_bar use Lc.
-__device__ inline double adj_post_at(const Consts &k, int64_t s, const double Lv[9],
-                                     const double *Mv, double rho, const double S[6],
+__device__ inline double adj_post_at(const Consts &k, int64_t s, const double Lv[9], bool corr,
+                                     const double Mv[6], double rho, const double S[6],
                                      const double c6[6], double rdot, double ax, double ay,
                                      double az, double rs_cot, const AdjRec &ad) {
     double L[3][3], C[9];
-    const bool inv = Mv ? correction_tensor(Mv, C) : false;
-    if (Mv) {
+    const bool inv = corr ? correction_tensor(Mv, C) : false;
+    if (corr) {
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -101,10 +101,10 @@ __device__ inline double adj_post_at(const Consts &k, int64_t s, const double Lv
             double P = 0.0;  // (G S~ - S~ G)_ij
 #pragma unroll
             for (int m = 0; m < 3; ++m) P += G[i][m] * St[m][j] - St[i][m] * G[m][j];
-            Lb[3 * i + j] = Mv ? 2.0 * k.mu * D + P : (i == j ? -rho * rdot : 0.0) + 2.0 * k.mu * D + P;
+            Lb[3 * i + j] = corr ? 2.0 * k.mu * D + P : (i == j ? -rho * rdot : 0.0) + 2.0 * k.mu * D + P;
             mu_b += 2.0 * D * L[i][j];
         }
-    if (Mv) {
+    if (corr) {
         // Lb holds Lcbar here
         double Cb[9], T[9], Mb[9];
 #pragma unroll
