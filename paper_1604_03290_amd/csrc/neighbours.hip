@@ -1,8 +1,10 @@
 // Interaction partner lists (section 3.5.2) as a CSR in user order, each row
-// ascending.  Positions are first gathered into slot order; the count and fill
-// passes take candidates from the grid's pair list when it has one (else from
-// the cell rows) and apply the exact test; each row is then sorted by one
-// wavefront with a bitonic network in LDS.
+// ascending.  Positions are first gathered into slot order; a count pass takes
+// candidates from the grid's pair list when it has one (else from the cell rows)
+// and applies the exact test; then one wavefront per row repeats the test over the
+// row's candidates, packs the partners in LDS, sorts them in registers with a
+// bitonic network and writes the row with whole-wavefront stores.  Rows longer
+// than kRowMax are written unsorted and sorted afterwards in LDS.
 #include <climits>
 
 #include "common.hpp"
@@ -27,31 +29,150 @@ __global__ __launch_bounds__(kBlock) void k_nb_gather(GridDev g, const double *_
     pos[s] = make_double4(px, py, pz, 0.0);
 }
 
-template <bool kFill>
-__global__ __launch_bounds__(kBlock) void k_nb_pass(GridDev g, const double4 *__restrict__ pos,
-                                                    int64_t n, double h2, double reach,
-                                                    int64_t *__restrict__ count,
-                                                    const int64_t *__restrict__ row_ptr,
-                                                    int32_t *__restrict__ col) {
+// partners of every slot (the exact test over its candidates), in user order
+__global__ __launch_bounds__(kBlock) void k_nb_count(GridDev g, const double4 *__restrict__ pos,
+                                                     int64_t n, double h2, double reach,
+                                                     int64_t *__restrict__ count) {
     const int64_t s = xcd_block(gridDim.x) * kBlock + threadIdx.x;
     if (s >= n) return;
     const double4 pa = pos[s];
-    const int a = g.perm[s];
-    int64_t k = kFill ? row_ptr[a] : 0;
+    int64_t k = 0;
     for_each_candidate(g, s, pa.x, pa.y, pa.z, reach, [&](int t) {
         const double4 pb = pos[t];
-        if (dist2_exact(pa.x, pa.y, pa.z, pb.x, pb.y, pb.z) < h2) {
-            if (kFill) col[k] = g.perm[t];
-            ++k;
-        }
+        if (dist2_exact(pa.x, pa.y, pa.z, pb.x, pb.y, pb.z) < h2) ++k;
     });
-    if (!kFill) count[a] = k;
+    count[g.perm[s]] = k;
 }
 
-// one wavefront per row: bitonic sort of the row in LDS (rows longer than
-// kSortMax, which no workload here produces, fall back to an insertion sort)
+constexpr int kRowMax = 256;  // longest row sorted in registers (4 per lane)
+
+// Bitonic sort, ascending, of the 64 E values v[e] (value i = 64 e + lane) held by
+// one wavefront.
+template <int E>
+__device__ inline void wave_bitonic(int32_t (&v)[E]) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int k = 2; k <= 64 * E; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= 64) {
+                const int je = j >> 6;
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int f = e ^ je;
+                    if (f > e) {
+                        const bool up = (((64 * e + lane) & k) == 0);
+                        const int32_t a = v[e], b = v[f];
+                        const bool sw = up ? (a > b) : (a < b);
+                        v[e] = sw ? b : a;
+                        v[f] = sw ? a : b;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int i = 64 * e + lane;
+                    const int32_t o = __shfl_xor(v[e], j);
+                    const bool up = (i & k) == 0;
+                    const bool lower = (lane & j) == 0;  // i < partner
+                    // the lower index keeps the min when ascending, the max otherwise
+                    const bool take_min = lower == up;
+                    v[e] = take_min ? min(v[e], o) : max(v[e], o);
+                }
+            }
+        }
+    }
+}
+
+template <int E>
+__device__ inline void sort_store_row(const int32_t *buf, int len, int32_t *__restrict__ out) {
+    const int lane = __lane_id();
+    int32_t v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = 64 * e + lane;
+        v[e] = i < len ? buf[i] : INT_MAX;
+    }
+    wave_bitonic<E>(v);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = 64 * e + lane;
+        if (i < len) out[i] = v[e];
+    }
+}
+
+// Fill and sort, one wavefront per slot: the lanes test the slot's candidates 64 at
+// a time and append the partners' user indices to an LDS buffer in candidate order
+// (ballot prefix), then the row is sorted and stored.  Rows longer than kRowMax go
+// to memory in candidate order for k_nb_sort.
+__global__ __launch_bounds__(kBlock) void k_nb_rows(GridDev g, const double4 *__restrict__ pos,
+                                                    int64_t n, double h2, double reach,
+                                                    const int64_t *__restrict__ row_ptr,
+                                                    int32_t *__restrict__ col) {
+    __shared__ int32_t lds[kBlock / 64][kRowMax];
+    int32_t *buf = lds[threadIdx.x >> 6];
+    const int64_t s = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (s >= n) return;
+    const int lane = __lane_id();
+    const double4 pa = pos[s];
+    const int a = g.perm[s];
+    const int64_t r0 = row_ptr[a];
+    const int len = (int)(row_ptr[a + 1] - r0);
+    int32_t *out = col + r0;
+    const bool big = len > kRowMax;
+    int k = 0;  // partners found so far (wavefront-uniform)
+    auto test = [&](int t, bool valid) {
+        bool hit = false;
+        int32_t u = 0;
+        if (valid) {
+            const double4 pb = pos[t];
+            hit = dist2_exact(pa.x, pa.y, pa.z, pb.x, pb.y, pb.z) < h2;
+            u = g.perm[t];
+        }
+        const unsigned long long m = __ballot(hit);
+        if (hit) {
+            const int at = k + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((unsigned)m, 0));
+            if (at < len) {  // the count pass found len partners with the same test
+                if (big)
+                    out[at] = u;
+                else
+                    buf[at] = u;
+            }
+        }
+        k += __popcll(m);
+    };
+    if (g.pl_count) {
+        const int c = g.pl_count[s];
+        const int32_t *p = g.pl_slot + g.pl_block[s >> 6] + (s & 63);
+        for (int j0 = 0; j0 < c; j0 += 64) {
+            const int j = j0 + lane;
+            test(j < c ? p[(int64_t)j << 6] : 0, j < c);
+        }
+    } else {
+        for_each_row(g, pa.x, pa.y, pa.z, reach, [&](int s0, int s1) {
+            for (int t0 = s0; t0 < s1; t0 += 64) {
+                const int t = t0 + lane;
+                test(t, t < s1 && t != (int)s);
+            }
+        });
+    }
+    if (big) return;
+    wave_sync();
+    if (len <= 64)
+        sort_store_row<1>(buf, len, out);
+    else if (len <= 128)
+        sort_store_row<2>(buf, len, out);
+    else
+        sort_store_row<4>(buf, len, out);
+}
+
+// one wavefront per row longer than min_len: bitonic sort of the row in LDS (rows
+// longer than kSortMax, which no workload here produces, fall back to an
+// insertion sort)
 __global__ __launch_bounds__(kBlock) void k_nb_sort(const int64_t *__restrict__ row_ptr,
-                                                    int64_t n, int32_t *__restrict__ col) {
+                                                    int64_t n, int32_t *__restrict__ col,
+                                                    int min_len) {
     __shared__ int32_t lds[kBlock / 64][kSortMax];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int32_t *buf = lds[wave];
@@ -59,7 +180,7 @@ __global__ __launch_bounds__(kBlock) void k_nb_sort(const int64_t *__restrict__ 
     if (a >= n) return;
     const int64_t r0 = row_ptr[a];
     const int len = (int)(row_ptr[a + 1] - r0);
-    if (len <= 1) return;
+    if (len <= 1 || len <= min_len) return;  // shorter rows are sorted already
     if (len > kSortMax) {
         if (lane == 0) {
             for (int64_t i = r0 + 1; i < r0 + len; ++i) {
@@ -135,7 +256,7 @@ extern "C" int sph_neighbours(const sph_grid *grid, const double *x, const doubl
     if ((rc = clear_status(ws, s))) return rc;
     k_nb_gather<<<blocks_for(n), kBlock, 0, s>>>(g, x, y, z, n, pos, c.status());
     SPH_LAUNCHED();
-    k_nb_pass<false><<<blocks_for(n), kBlock, 0, s>>>(g, pos, n, h * h, reach, count, nullptr, nullptr);
+    k_nb_count<<<blocks_for(n), kBlock, 0, s>>>(g, pos, n, h * h, reach, count);
     SPH_LAUNCHED();
     if ((rc = exclusive_scan_i64(count, row_ptr, n, tmp, s))) return rc;
     int64_t nnz = 0;
@@ -148,9 +269,10 @@ extern "C" int sph_neighbours(const sph_grid *grid, const double *x, const doubl
     if (nnz > col_cap)
         return fail(SPH_ERR_CAPACITY, "%lld partners exceed capacity %lld", (long long)nnz,
                     (long long)col_cap);
-    k_nb_pass<true><<<blocks_for(n), kBlock, 0, s>>>(g, pos, n, h * h, reach, nullptr, row_ptr, col);
+    if (nnz == 0) return SPH_OK;
+    k_nb_rows<<<blocks_for(n, kBlock / 64), kBlock, 0, s>>>(g, pos, n, h * h, reach, row_ptr, col);
     SPH_LAUNCHED();
-    k_nb_sort<<<blocks_for(n, kBlock / 64), kBlock, 0, s>>>(row_ptr, n, col);
+    k_nb_sort<<<blocks_for(n, kBlock / 64), kBlock, 0, s>>>(row_ptr, n, col, kRowMax);
     SPH_LAUNCHED();
     return SPH_OK;
 }

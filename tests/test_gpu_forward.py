@@ -91,7 +91,21 @@ def test_build_cells_structure(cells_per_h):
     assert torch.equal(g.perm, g2.perm)
 
 
+def clumps(h=0.3, seed=4):
+    """Separate dense clumps whose rows hold 49, 99, 199 and 299 partners (one, two
+    and four values per lane in the register sort, and the long-row path)."""
+    rng = np.random.default_rng(seed)
+    pts = []
+    for i, m in enumerate((50, 100, 200, 300)):
+        c = np.array([3.0 * i, 0.0, 0.0])
+        d = rng.normal(size=(m, 3))
+        d *= (rng.uniform(0, 1, (m, 1)) ** (1 / 3)) * 0.45 * h / np.linalg.norm(d, axis=1, keepdims=True)
+        pts += list(c + d)
+    return np.ascontiguousarray(np.array(pts).T)
+
+
 CSR_CASES = {
+    "clumps": lambda: clumps(),
     "cube16": lambda: W.config(0).pos,
     "cube16_shuffled": lambda: W.cube(16, 1 / 16, seed=5, shuffle=True).pos,
     "lattice10": lambda: W.cube(10, 0.1, seed=1, jitter=0.0).pos,
@@ -105,7 +119,7 @@ def test_neighbours_bit_exact(case, cells_per_h, pairs):
     """Partner sets from the cell rows and from the frozen candidate lists, against
     the oracle's brute force."""
     pos = CSR_CASES[case]()
-    h = 0.3 if case == "adversarial" else (0.15 if case != "lattice10" else 0.24)
+    h = 0.3 if case in ("adversarial", "clumps") else (0.15 if case != "lattice10" else 0.24)
     rp_ref, col_ref = native.neighbours(pos, h)
     rp, col, _ = gpu_csr(pos, h, cells_per_h, skin=0.01 * h if pairs else 0.0, pairs=pairs)
     assert np.array_equal(rp, rp_ref)
