@@ -170,7 +170,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_post(GridDev g, int64_t n, Const
 #pragma unroll
             for (int i = 0; i < 6; ++i) M[i] = ad.M[i][s];
         }
-        mu_part = adj_post_at(k, s, L, k.corr, M, rec[s * kRec + 6], S, c6,
+        mu_part = adj_post_at(k, s, L, k.corr, M, rec[s * kRec + 6], rec[s * kRec + 14], S, c6,
                               ld(cot.drho, a), ld(cot.ax, a), ld(cot.ay, a), ld(cot.az, a),
                               ld(cot.rho_sum, a), ad);
     }
@@ -369,21 +369,21 @@ __global__ __launch_bounds__(kBlock) void k_adj_pairs(GridDev g, int64_t n, Cons
     if (threadIdx.x == 0) put(ad.part_y0, blockIdx.x, tot, ad.add_parts);
 }
 
-// the same over the frozen pair list with cooperative gathers of both records
-__global__ __launch_bounds__(kBlock) void k_adj_pairs_list(GridDev g, int64_t n, Consts k,
-                                                           const double *__restrict__ rec,
-                                                           StateDev st, AdjRec ad, GradDev out) {
-    __shared__ double2 fbuf[kBlock / 64][kLdsWave];
-    __shared__ double2 abuf[kBlock / 64][kLdsWave];
-    double2 *bf = fbuf[threadIdx.x >> 6];
-    double2 *ba = abuf[threadIdx.x >> 6];
-    const int64_t s = xcd_block(gridDim.x) * kBlock + threadIdx.x;
-    const int64_t w0 = s - __lane_id();
+// the same over the frozen pair list, one wavefront per block: seven chunks of
+// each partner's two records gathered cooperatively; the Y0 sums per wavefront
+__global__ __launch_bounds__(64) void k_adj_pairs_list(GridDev g, int64_t n, Consts k,
+                                                       const double *__restrict__ rec,
+                                                       StateDev st, AdjRec ad, GradDev out) {
+    __shared__ double2 bf[64 * 7];
+    __shared__ double2 ba[64 * 7];
+    const int64_t w = xcd_block(gridDim.x);
+    const int64_t w0 = w * 64;
+    const int64_t s = w0 + threadIdx.x;
     double y0_part = 0.0;
     if (w0 < n) {
         const bool act = s < n;
-        const int64_t base = g.pl_block[w0 >> 6];
-        const int steps = (int)((g.pl_block[(w0 >> 6) + 1] - base) >> 6);
+        const int64_t base = g.pl_block[w];
+        const int steps = (int)((g.pl_block[w + 1] - base) >> 6);
         const int cnt = act ? g.pl_count[s] : 0;
         const AdjOwn o = adj_own(rec, ad, act ? s : w0);
         AdjAcc acc;
@@ -393,27 +393,31 @@ __global__ __launch_bounds__(kBlock) void k_adj_pairs_list(GridDev g, int64_t n,
         int e0 = steps > 0 ? row[0] : 0;
         for (int j = 0; j < steps; ++j) {
             {
-                gather_dma(rf, kRec * 8, e0, bf);
-                gather_dma(ra, kAdj * 8, e0, ba);
+                gather_dma7(rf, kRec * 8, e0, bf);
+                gather_dma7(ra, kAdj * 8, e0, ba);
                 if (j + 1 < steps) e0 = row[(int64_t)(j + 1) << 6];
             }
             wave_sync();
             if (j < cnt) {
-                const double2 b0 = dma_chunk(bf, 0), b1 = dma_chunk(bf, 1);
+                const double2 b0 = dma7_chunk(bf, 0), b1 = dma7_chunk(bf, 1);
                 const double d2 = dist2_exact(o.xc, o.yc, o.zc, b0.x, b0.y, b1.x);
-                if (d2 < k.h2)
-                    adj_pair(k, o, d2, b0, b1, dma_chunk(bf, 2), dma_chunk(bf, 3),
-                             dma_chunk(bf, 4), dma_chunk(bf, 5), dma_chunk(bf, 6),
-                             dma_chunk(bf, 7), dma_chunk(ba, 0), dma_chunk(ba, 1),
-                             dma_chunk(ba, 2), dma_chunk(ba, 3), dma_chunk(ba, 4),
-                             dma_chunk(ba, 5), dma_chunk(ba, 6), acc);
+                if (d2 < k.h2) {
+                    const double2 e6 = dma7_chunk(ba, 6);
+                    adj_pair(k, o, d2, b0, b1, dma7_chunk(bf, 2), dma7_chunk(bf, 3),
+                             dma7_chunk(bf, 4), dma7_chunk(bf, 5), dma7_chunk(bf, 6),
+                             make_double2(e6.y, 0.0), dma7_chunk(ba, 0), dma7_chunk(ba, 1),
+                             dma7_chunk(ba, 2), dma7_chunk(ba, 3), dma7_chunk(ba, 4),
+                             dma7_chunk(ba, 5), e6, acc);
+                }
             }
             wave_sync();
         }
         if (act) y0_part = adj_pre(k, ad, o, acc, s, io_index(g, s), st, out);
     }
-    const double tot = block_sum(y0_part);
-    if (threadIdx.x == 0) put(ad.part_y0, blockIdx.x, tot, ad.add_parts);
+    // fixed-order wavefront sum
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) y0_part += __shfl_xor(y0_part, off);
+    if (threadIdx.x == 0) put(ad.part_y0, (int)w, y0_part, ad.add_parts);
 }
 
 }  // namespace
@@ -421,13 +425,15 @@ __global__ __launch_bounds__(kBlock) void k_adj_pairs_list(GridDev g, int64_t n,
 namespace {
 // one block: dparams[i] (+)= sum of part_i in a fixed order (a null part is skipped)
 __global__ __launch_bounds__(kBlock) void k_reduce_params(const double *__restrict__ p0,
+                                                          int64_t m0,
                                                           const double *__restrict__ p1,
-                                                          int64_t m, double *dparams, int accumulate) {
+                                                          int64_t m1, double *dparams,
+                                                          int accumulate) {
     double a = 0.0, b = 0.0;
-    for (int64_t i = threadIdx.x; i < m; i += kBlock) {
-        if (p0) a += p0[i];
-        if (p1) b += p1[i];
-    }
+    if (p0)
+        for (int64_t i = threadIdx.x; i < m0; i += kBlock) a += p0[i];
+    if (p1)
+        for (int64_t i = threadIdx.x; i < m1; i += kBlock) b += p1[i];
     a = block_sum(a);
     b = block_sum(b);
     if (threadIdx.x == 0) {
@@ -443,9 +449,9 @@ __global__ __launch_bounds__(kBlock) void k_reduce_params(const double *__restri
 
 }  // namespace
 
-int reduce_params_launch(const double *p0, const double *p1, int64_t m, double *dparams,
-                         int accumulate, hipStream_t s) {
-    k_reduce_params<<<1, kBlock, 0, s>>>(p0, p1, m, dparams, accumulate);
+int reduce_params_launch(const double *p0, int64_t m0, const double *p1, int64_t m1,
+                         double *dparams, int accumulate, hipStream_t s) {
+    k_reduce_params<<<1, kBlock, 0, s>>>(p0, m0, p1, m1, dparams, accumulate);
     SPH_LAUNCHED();
     return SPH_OK;
 }
@@ -518,13 +524,15 @@ int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_p
         if (k.corr)
             k_adj_pairs<true><<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, ad, grad);
         else if (g.pl_count)
-            k_adj_pairs_list<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, ad, grad);
+            k_adj_pairs_list<<<blocks_for(n, 64), 64, 0, s>>>(g, n, k, rec, st, ad, grad);
         else
             k_adj_pairs<false><<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, ad, grad);
         SPH_LAUNCHED();
     }
     if (acc_parts) return SPH_OK;  // the caller reduces its accumulators
-    return reduce_params_launch(ad.part_mu, ad.part_y0, blocks_for(n), dparams, accumulate_params, s);
+    const int64_t m_y0 = g.pl_count && !k.corr ? blocks_for(n, 64) : blocks_for(n);
+    return reduce_params_launch(ad.part_mu, blocks_for(n), ad.part_y0, m_y0, dparams,
+                                accumulate_params, s);
 }
 
 int check_grad(const sph_fields *g) {

@@ -8,7 +8,9 @@
 namespace sph {
 
 // Adjoint operand records, one 128-byte record per slot:
-//   Lbar(9) | abar(3) | rho_sum bar | - - -
+//   Lbar(9) | abar(3) | rho_sum bar, V | - -
+// (V = m / rho travels here so that the list kernel gathers seven chunks of each
+// record: the forward record's first seven and this one's.)
 constexpr int kAdj = 16;
 
 struct AdjRec {
@@ -18,8 +20,8 @@ struct AdjRec {
     double *arec;      // adjoint records [n][kAdj]
     double *rhob;      // partial density cotangent from the post stage
     double *Stb[6];    // partial cotangent of f_Y S from the rotation terms (stored components)
-    double *part_mu;   // per-block partial sums
-    double *part_y0;
+    double *part_mu;   // per-block partial sums (ceil(n / 256))
+    double *part_y0;   // per block, or per wavefront for the list kernel (ceil(n / 64))
     int add_parts;     // add the block sums to part_* instead of writing them
 };
 
@@ -32,7 +34,7 @@ inline AdjRec carve_adj(Carve &c, int64_t n) {
     r.rhob = c.take<double>(n);
     for (int i = 0; i < 6; ++i) r.Stb[i] = c.take<double>(n);
     r.part_mu = c.take<double>(blocks_for(n));
-    r.part_y0 = c.take<double>(blocks_for(n));
+    r.part_y0 = c.take<double>(blocks_for(n, 64));
     r.add_parts = 0;
     return r;
 }
@@ -51,7 +53,7 @@ inline AdjBuffers adj_buffers(Carve &c, int64_t n) {
 }
 
 // Post stage at slot s (see adjoint.hip's header): from the forward velocity
-// gradient L (row-major), density rho and stress S (before the limiter) of the
+// gradient L (row-major), density rho, volume V and stress S (before the limiter) of the
 // particle and the cotangents of its outputs (c6: stored dS components, rdot:
 // drho, ax..az: acceleration, rs_cot: rho_sum), writes the adjoint record, the
 // partial density cotangent and the rotation terms' stress cotangent; returns
@@ -63,7 +65,7 @@ inline AdjBuffers adj_buffers(Carve &c, int64_t n) {
 // Mbar = -C^T Cbar C^T, stored symmetrised in ad.Mb (zero where C fell back to
 // the identity); mu_bar and S~_bar use Lc.
 __device__ inline double adj_post_at(const Consts &k, int64_t s, const double Lv[9], bool corr,
-                                     const double Mv[6], double rho, const double S[6],
+                                     const double Mv[6], double rho, double V, const double S[6],
                                      const double c6[6], double rdot, double ax, double ay,
                                      double az, double rs_cot, const AdjRec &ad) {
     double L[3][3], C[9];
@@ -162,7 +164,7 @@ __device__ inline double adj_post_at(const Consts &k, int64_t s, const double Lv
     o[3] = make_double2(Lb[6], Lb[7]);
     o[4] = make_double2(Lb[8], ax);
     o[5] = make_double2(ay, az);
-    o[6] = make_double2(rs_cot, 0.0);
+    o[6] = make_double2(rs_cot, V);
     o[7] = make_double2(0.0, 0.0);
     return mu_b;
 }

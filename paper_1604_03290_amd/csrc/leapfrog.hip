@@ -227,7 +227,8 @@ __global__ __launch_bounds__(kBlock) void k_rev_kick2(Fields13 Uk, Deriv10 Fk, F
             for (int c = 0; c < 6; ++c) M[c] = L1[(9 + c) * n + i];
         }
         const double c6[6] = {cF[4], cF[5], cF[6], cF[7], cF[8], cF[9]};
-        mup = adj_post_at(k, i, L, k.corr, M, rho, S, c6, cF[3], cF[0], cF[1], cF[2], 0.0, ad);
+        mup = adj_post_at(k, i, L, k.corr, M, rho, mi / rho, S, c6, cF[3], cF[0], cF[1], cF[2],
+                          0.0, ad);
     }
     const double tot = block_sum(y0p);
     const double tot_mu = block_sum(mup);
@@ -385,7 +386,7 @@ size_t leapfrog_adjoint_ws_bytes(int64_t n) {
     carve_deriv(c, n);   // cotangent of F_{n+1}
     carve_deriv(c, n);   // cotangent of F_n
     c.take<double>(n);   // masses, slot order
-    c.take<double>(2 * blocks_for(n));  // per-block mu and Y0 accumulators
+    c.take<double>(blocks_for(n) + blocks_for(n, 64));  // mu and Y0 accumulators
     c.used += adjoint_ws_bytes(n);
     return c.used;
 }
@@ -468,7 +469,9 @@ extern "C" int sph_leapfrog_adjoint(const sph_grid *grid, const sph_state *s0,
     Deriv10 gF1 = carve_deriv(c, n);
     Deriv10 gF0 = carve_deriv(c, n);
     double *m = c.take<double>(n);
-    double *parts = c.take<double>(2 * blocks_for(n));  // per-block mu and Y0 accumulators
+    // mu accumulators per block, then Y0 per block (kicks) or per wavefront (pairs)
+    const unsigned nw = blocks_for(n, 64);
+    double *parts = c.take<double>(blocks_for(n) + nw);
     Carve adj_ws(ws);
     adj_ws.used = c.used;
     const unsigned nb = blocks_for(n);
@@ -487,7 +490,7 @@ extern "C" int sph_leapfrog_adjoint(const sph_grid *grid, const sph_state *s0,
         k_to_slots<<<nb, kBlock, 0, s>>>(a, b, 14, grid->perm, n);
         SPH_LAUNCHED();
     }
-    k_fill<<<blocks_for(2 * nb), kBlock, 0, s>>>(parts, 2 * nb, 0.0);
+    k_fill<<<blocks_for(nb + nw), kBlock, 0, s>>>(parts, nb + nw, 0.0);
     SPH_LAUNCHED();
     double *acc_y0 = parts + nb;
 
@@ -540,6 +543,6 @@ extern "C" int sph_leapfrog_adjoint(const sph_grid *grid, const sph_state *s0,
     const sph_state st0 = state_struct(slab_fields(ck, n), m, n);
     if ((rc = adjoint_at(st0, gF1, ck, false))) return rc;
     // dparams = the accumulators summed in a fixed order
-    if ((rc = reduce_params_launch(parts, acc_y0, nb, dparams, 0, s))) return rc;
+    if ((rc = reduce_params_launch(parts, nb, acc_y0, nw, dparams, 0, s))) return rc;
     return fields_to_users(grid, gU, fields_of(grad0), s);
 }

@@ -151,6 +151,31 @@ __device__ inline void gather_dma5(const char *__restrict__ recs, int stride, in
     }
 }
 
+// The same for the first seven chunks of 128-byte records: position q = 64 i + lane
+// holds chunk q % 7 of record q / 7, so record r's chunk c sits at buf[7 r + c]
+// (the odd stride avoids bank conflicts); 448 chunks, seven instructions.
+__device__ inline void gather_dma7(const char *__restrict__ recs, int stride, int entry,
+                                   double2 *buf) {
+    const int lane = __lane_id();
+    uint32_t t[7];
+#pragma unroll
+    for (int i = 0; i < 7; ++i)
+        t[i] = (uint32_t)__builtin_amdgcn_ds_bpermute(4 * ((64 * i + lane) / 7), entry);
+#pragma unroll
+    for (int i = 0; i < 7; ++i) asm volatile("" : "+v"(t[i]));
+    uint32_t st = (uint32_t)stride;
+    asm("" : "+s"(st));
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+        const int c = (64 * i + lane) % 7;
+        __builtin_amdgcn_global_load_lds(
+            reinterpret_cast<const void *>(recs + (uint64_t)t[i] * st + c * 16),
+            (__attribute__((address_space(3))) void *)(buf + 64 * i), 16, 0, 0);
+    }
+}
+
+__device__ inline double2 dma7_chunk(const double2 *buf, int c) { return buf[7 * __lane_id() + c]; }
+
 __device__ inline double2 dma5_chunk(const double2 *buf, int c) { return buf[5 * __lane_id() + c]; }
 
 __device__ inline double2 dma_chunk(const double2 *buf, int c) {
@@ -464,8 +489,9 @@ size_t adjoint_ws_bytes(int64_t n);
 // L_in (nullable): the forward velocity gradient of the same state in slot order
 // (9 arrays of n); when null it is recomputed.  slot_state: the state, cotangent
 // and gradient arrays are in the grid's slot order instead of user order.
-// acc_parts (nullable): 2 ceil(n / 256) per-block accumulators (mu, then Y0) to
-// which the launch adds its block sums instead of reducing into dparams.
+// acc_parts (nullable): ceil(n / 256) per-block mu accumulators followed by
+// ceil(n / 64) Y0 accumulators (per block, or per wavefront for the list kernel)
+// to which the launch adds its sums instead of reducing into dparams.
 // post_ready: the operand records and the post stage's outputs (adj_buffers of
 // this carve) are already written, with the mu block sums added to acc_parts;
 // only the pair stage runs (L_in required).
@@ -474,10 +500,10 @@ int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_p
                        Carve &c, hipStream_t s, const double *L_in = nullptr,
                        bool slot_state = false, double *acc_parts = nullptr,
                        bool post_ready = false);
-// dparams[0] (+)= sum of p0, dparams[1] (+)= sum of p1 (null parts skipped),
-// fixed summation order
-int reduce_params_launch(const double *p0, const double *p1, int64_t m, double *dparams,
-                         int accumulate, hipStream_t s);
+// dparams[0] (+)= sum of p0[0..m0), dparams[1] (+)= sum of p1[0..m1) (null parts
+// skipped), fixed summation order
+int reduce_params_launch(const double *p0, int64_t m0, const double *p1, int64_t m1,
+                         double *dparams, int accumulate, hipStream_t s);
 
 // rhs.hip
 int prepass_launch(const GridDev &g, const StateDev &st, int64_t n, const Consts &k, double *rec,
