@@ -77,11 +77,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_L(GridDev g, int64_t n, Consts k
         const double2 b0 = rb[0], b1 = rb[1];
         const double d2 = dist2_exact(xa, ya, za, b0.x, b0.y, b1.x);
         if (!(d2 < k.h2)) return;
-        const double2 b2 = rb[2], b7 = rb[7];
+        const double2 b2 = rb[2], b3 = rb[3];
         const KernelPieces kp = kernel_pieces(k, d2, rsqrt64(d2));
         const double F = k.Fn * kp.f;
         const double gx = F * (xa - b0.x), gy = F * (ya - b0.y), gz = F * (za - b1.x);
-        const double V = b7.x;
+        const double V = b3.y;
         const double tx = V * (b1.y - vxa), ty = V * (b2.x - vya), tz = V * (b2.y - vza);
         L[0] = fma(tx, gx, L[0]); L[1] = fma(tx, gy, L[1]); L[2] = fma(tx, gz, L[2]);
         L[3] = fma(ty, gx, L[3]); L[4] = fma(ty, gy, L[4]); L[5] = fma(ty, gz, L[5]);
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_L(GridDev g, int64_t n, Consts k
 template <bool kCorr>
 __global__ __launch_bounds__(kBlock) void k_adj_L_list(GridDev g, int64_t n, Consts k,
                                                        const double *__restrict__ rec, AdjRec ad) {
-    __shared__ double2 lbuf[kBlock / 64][kLdsWave];
+    __shared__ double2 lbuf[kBlock / 64][64 * 7];
     double2 *buf = lbuf[threadIdx.x >> 6];
     const int64_t s = xcd_block(gridDim.x) * kBlock + threadIdx.x;
     const int64_t w0 = s - __lane_id();
@@ -121,18 +121,18 @@ __global__ __launch_bounds__(kBlock) void k_adj_L_list(GridDev g, int64_t n, Con
     const int32_t *row = g.pl_slot + base + __lane_id();
     int e0 = steps > 0 ? row[0] : 0;
     for (int j = 0; j < steps; ++j) {
-        gather_dma(recs, kRec * 8, e0, buf);
+        gather_dma<7>(recs, kRec * 8, e0, buf);
         if (j + 1 < steps) e0 = row[(int64_t)(j + 1) << 6];
         wave_sync();
         if (j < cnt) {
-            const double2 b0 = dma_chunk(buf, 0), b1 = dma_chunk(buf, 1);
+            const double2 b0 = dma_chunk<7>(buf, 0), b1 = dma_chunk<7>(buf, 1);
             const double d2 = dist2_exact(xa, ya, za, b0.x, b0.y, b1.x);
             if (d2 < k.h2) {
-                const double2 b2 = dma_chunk(buf, 2), b7 = dma_chunk(buf, 7);
+                const double2 b2 = dma_chunk<7>(buf, 2), b3 = dma_chunk<7>(buf, 3);
                 const KernelPieces kp = kernel_pieces(k, d2, rsqrt64(d2));
                 const double F = k.Fn * kp.f;
                 const double gx = F * (xa - b0.x), gy = F * (ya - b0.y), gz = F * (za - b1.x);
-                const double V = b7.x;
+                const double V = b3.y;
                 const double tx = V * (b1.y - vxa), ty = V * (b2.x - vya), tz = V * (b2.y - vza);
                 L[0] = fma(tx, gx, L[0]); L[1] = fma(tx, gy, L[1]); L[2] = fma(tx, gz, L[2]);
                 L[3] = fma(ty, gx, L[3]); L[4] = fma(ty, gy, L[4]); L[5] = fma(ty, gz, L[5]);
@@ -170,7 +170,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_post(GridDev g, int64_t n, Const
 #pragma unroll
             for (int i = 0; i < 6; ++i) M[i] = ad.M[i][s];
         }
-        mu_part = adj_post_at(k, s, L, k.corr, M, rec[s * kRec + 6], rec[s * kRec + 14], S, c6,
+        mu_part = adj_post_at(k, s, L, k.corr, M, rec[s * kRec + 6], S, c6,
                               ld(cot.drho, a), ld(cot.ax, a), ld(cot.ay, a), ld(cot.az, a),
                               ld(cot.rho_sum, a), ad);
     }
@@ -189,7 +189,7 @@ struct AdjOwn {
 };
 
 // Both roles of the pair (c, b) (see the file header).  b = forward record chunks
-// b0..b7 of the partner, e0..e6 = its adjoint record chunks.  With the
+// b0..b6 of the partner (its mass is V rho), e0..e6 = its adjoint record chunks.  With the
 // correction, Mc and Mb are the symmetrised cotangents of the moment matrices
 // of c and b, whose terms P r r^T (P = -V_b F, r = x_c - x_b) add
 //   xbar_c += -[V_b (2 F Mc r + (r.Mc r) G r) + V_c (2 F Mb r + (r.Mb r) G r)],
@@ -197,14 +197,14 @@ struct AdjOwn {
 template <bool kCorr = false>
 __device__ inline void adj_pair(const Consts &k, const AdjOwn &o, double d2, double2 b0,
                                 double2 b1, double2 b2, double2 b3, double2 b4, double2 b5,
-                                double2 b6, double2 b7, double2 e0, double2 e1, double2 e2,
-                                double2 e3, double2 e4, double2 e5, double2 e6, AdjAcc &acc,
+                                double2 b6, double2 e0, double2 e1, double2 e2, double2 e3,
+                                double2 e4, double2 e5, double2 e6, AdjAcc &acc,
                                 const double *Mc = nullptr, const double *Mb = nullptr) {
     const double Gn = k.Fn * k.inv_h * k.inv_h;
     const double Lbb[9] = {e0.x, e0.y, e1.x, e1.y, e2.x, e2.y, e3.x, e3.y, e4.x};
     const double rx = o.xc - b0.x, ry = o.yc - b0.y, rz = o.zc - b1.x;
     const double ux = b1.y - o.vxc, uy = b2.x - o.vyc, uz = b2.y - o.vzc;
-    const double rb_ = b3.x, mb = b3.y, Vb = b7.x;
+    const double rb_ = b3.x, Vb = b3.y, mb = Vb * rb_;
     const double ir = rsqrt64(d2);
     const KernelPieces kp = kernel_pieces(k, d2, ir);
     // G = F'(r) / r:  3 Gn / q inside, Gn (1 - q^2) / q^3 outside (0 at r = 0)
@@ -278,7 +278,7 @@ __device__ inline AdjOwn adj_own(const double *rec, const AdjRec &ad, int64_t s)
     const double2 p0 = ra[0], p1 = ra[1], p2 = ra[2], p3 = ra[3], p4 = ra[4], p5 = ra[5],
                   p6 = ra[6], p7 = ra[7];
     o.xc = p0.x; o.yc = p0.y; o.zc = p1.x; o.vxc = p1.y; o.vyc = p2.x; o.vzc = p2.y;
-    o.rc = p3.x; o.mc = p3.y; o.Vc = p7.x;
+    o.rc = p3.x; o.Vc = p3.y; o.mc = p7.x;
     o.Tc[0] = p4.x; o.Tc[1] = p4.y; o.Tc[2] = p5.x; o.Tc[3] = p5.y; o.Tc[4] = p6.x; o.Tc[5] = p6.y;
     const double2 *qa = reinterpret_cast<const double2 *>(ad.arec + s * kAdj);
     const double2 q0 = qa[0], q1 = qa[1], q2 = qa[2], q3 = qa[3], q4 = qa[4], q5 = qa[5], q6 = qa[6];
@@ -360,8 +360,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_pairs(GridDev g, int64_t n, Cons
 #pragma unroll
                 for (int i = 0; i < 6; ++i) Mb[i] = ad.Mb[i][t];
             }
-            adj_pair<kCorr>(k, o, d2, b0, b1, rb[2], rb[3], rb[4], rb[5], rb[6], rb[7], qb[0],
-                            qb[1], qb[2], qb[3], qb[4], qb[5], qb[6], acc, Mc, Mb);
+            adj_pair<kCorr>(k, o, d2, b0, b1, rb[2], rb[3], rb[4], rb[5], rb[6], qb[0], qb[1],
+                            qb[2], qb[3], qb[4], qb[5], qb[6], acc, Mc, Mb);
         });
         y0_part = adj_pre(k, ad, o, acc, s, io_index(g, s), st, out);
     }
@@ -369,8 +369,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_pairs(GridDev g, int64_t n, Cons
     if (threadIdx.x == 0) put(ad.part_y0, blockIdx.x, tot, ad.add_parts);
 }
 
-// the same over the frozen pair list, one wavefront per block: seven chunks of
-// each partner's two records gathered cooperatively; the Y0 sums per wavefront
+// the same over the frozen pair list, one wavefront per block: the first seven
+// chunks of each partner's two records gathered cooperatively; Y0 sums per wavefront
 __global__ __launch_bounds__(64) void k_adj_pairs_list(GridDev g, int64_t n, Consts k,
                                                        const double *__restrict__ rec,
                                                        StateDev st, AdjRec ad, GradDev out) {
@@ -393,22 +393,20 @@ __global__ __launch_bounds__(64) void k_adj_pairs_list(GridDev g, int64_t n, Con
         int e0 = steps > 0 ? row[0] : 0;
         for (int j = 0; j < steps; ++j) {
             {
-                gather_dma7(rf, kRec * 8, e0, bf);
-                gather_dma7(ra, kAdj * 8, e0, ba);
+                gather_dma<7>(rf, kRec * 8, e0, bf);
+                gather_dma<7>(ra, kAdj * 8, e0, ba);
                 if (j + 1 < steps) e0 = row[(int64_t)(j + 1) << 6];
             }
             wave_sync();
             if (j < cnt) {
-                const double2 b0 = dma7_chunk(bf, 0), b1 = dma7_chunk(bf, 1);
+                const double2 b0 = dma_chunk<7>(bf, 0), b1 = dma_chunk<7>(bf, 1);
                 const double d2 = dist2_exact(o.xc, o.yc, o.zc, b0.x, b0.y, b1.x);
-                if (d2 < k.h2) {
-                    const double2 e6 = dma7_chunk(ba, 6);
-                    adj_pair(k, o, d2, b0, b1, dma7_chunk(bf, 2), dma7_chunk(bf, 3),
-                             dma7_chunk(bf, 4), dma7_chunk(bf, 5), dma7_chunk(bf, 6),
-                             make_double2(e6.y, 0.0), dma7_chunk(ba, 0), dma7_chunk(ba, 1),
-                             dma7_chunk(ba, 2), dma7_chunk(ba, 3), dma7_chunk(ba, 4),
-                             dma7_chunk(ba, 5), e6, acc);
-                }
+                if (d2 < k.h2)
+                    adj_pair(k, o, d2, b0, b1, dma_chunk<7>(bf, 2), dma_chunk<7>(bf, 3),
+                             dma_chunk<7>(bf, 4), dma_chunk<7>(bf, 5), dma_chunk<7>(bf, 6),
+                             dma_chunk<7>(ba, 0), dma_chunk<7>(ba, 1), dma_chunk<7>(ba, 2),
+                             dma_chunk<7>(ba, 3), dma_chunk<7>(ba, 4), dma_chunk<7>(ba, 5),
+                             dma_chunk<7>(ba, 6), acc);
             }
             wave_sync();
         }

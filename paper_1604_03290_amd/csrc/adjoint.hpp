@@ -7,10 +7,8 @@
 
 namespace sph {
 
-// Adjoint operand records, one 128-byte record per slot:
-//   Lbar(9) | abar(3) | rho_sum bar, V | - -
-// (V = m / rho travels here so that the list kernel gathers seven chunks of each
-// record: the forward record's first seven and this one's.)
+// Adjoint operand records, one 128-byte record per slot (seven chunks used):
+//   Lbar(9) | abar(3) | rho_sum bar | - - -
 constexpr int kAdj = 16;
 
 struct AdjRec {
@@ -53,7 +51,7 @@ inline AdjBuffers adj_buffers(Carve &c, int64_t n) {
 }
 
 // Post stage at slot s (see adjoint.hip's header): from the forward velocity
-// gradient L (row-major), density rho, volume V and stress S (before the limiter) of the
+// gradient L (row-major), density rho and stress S (before the limiter) of the
 // particle and the cotangents of its outputs (c6: stored dS components, rdot:
 // drho, ax..az: acceleration, rs_cot: rho_sum), writes the adjoint record, the
 // partial density cotangent and the rotation terms' stress cotangent; returns
@@ -65,7 +63,7 @@ inline AdjBuffers adj_buffers(Carve &c, int64_t n) {
 // Mbar = -C^T Cbar C^T, stored symmetrised in ad.Mb (zero where C fell back to
 // the identity); mu_bar and S~_bar use Lc.
 __device__ inline double adj_post_at(const Consts &k, int64_t s, const double Lv[9], bool corr,
-                                     const double Mv[6], double rho, double V, const double S[6],
+                                     const double Mv[6], double rho, const double S[6],
                                      const double c6[6], double rdot, double ax, double ay,
                                      double az, double rs_cot, const AdjRec &ad) {
     double L[3][3], C[9];
@@ -164,7 +162,7 @@ __device__ inline double adj_post_at(const Consts &k, int64_t s, const double Lv
     o[3] = make_double2(Lb[6], Lb[7]);
     o[4] = make_double2(Lb[8], ax);
     o[5] = make_double2(ay, az);
-    o[6] = make_double2(rs_cot, V);
+    o[6] = make_double2(rs_cot, 0.0);
     o[7] = make_double2(0.0, 0.0);
     return mu_b;
 }

@@ -227,8 +227,7 @@ __global__ __launch_bounds__(kBlock) void k_rev_kick2(Fields13 Uk, Deriv10 Fk, F
             for (int c = 0; c < 6; ++c) M[c] = L1[(9 + c) * n + i];
         }
         const double c6[6] = {cF[4], cF[5], cF[6], cF[7], cF[8], cF[9]};
-        mup = adj_post_at(k, i, L, k.corr, M, rho, mi / rho, S, c6, cF[3], cF[0], cF[1], cF[2],
-                          0.0, ad);
+        mup = adj_post_at(k, i, L, k.corr, M, rho, S, c6, cF[3], cF[0], cF[1], cF[2], 0.0, ad);
     }
     const double tot = block_sum(y0p);
     const double tot_mu = block_sum(mup);

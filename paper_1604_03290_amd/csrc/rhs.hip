@@ -45,7 +45,7 @@ __global__ __launch_bounds__(kBlock) void k_narrow(const double *__restrict__ re
     *reinterpret_cast<double2 *>(o) = make_double2(r[0], r[1]);
     *reinterpret_cast<double *>(o + 16) = r[2];
     *reinterpret_cast<float2 *>(o + 24) = make_float2((float)r[3], (float)r[4]);
-    *reinterpret_cast<float4 *>(o + 32) = make_float4((float)r[5], (float)r[6], (float)r[7], (float)r[14]);
+    *reinterpret_cast<float4 *>(o + 32) = make_float4((float)r[5], (float)r[6], (float)r[14], (float)r[7]);
     *reinterpret_cast<float4 *>(o + 48) = make_float4((float)r[8], (float)r[9], (float)r[10], (float)r[11]);
     *reinterpret_cast<float4 *>(o + 64) = make_float4((float)r[12], (float)r[13], 0.0f, 0.0f);
 }
@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs64(GridDev g, int64_t n, Consts
     const double xa = p0.x, ya = p0.y, za = p1.x, vxa = p1.y, vya = p2.x, vza = p2.y;
     const double rho_a = p3.x;
     Acc64 acc;
-    acc.rs = p3.y * k.Wn;  // own term m_a W(0)
+    acc.rs = ra[7].x * k.Wn;  // own term m_a W(0)
     for_each_candidate(g, s, xa, ya, za, k.reach, [&](int t) {
         const double2 *rb = rec2(rec, t);
         const double2 b0 = rb[0], b1 = rb[1];
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs64(GridDev g, int64_t n, Consts
         const double2 b2 = rb[2], b3 = rb[3], b4 = rb[4], b5 = rb[5], b6 = rb[6], b7 = rb[7];
         pair64<kCorr>(k, d2, xa - b0.x, ya - b0.y, za - b1.x, b1.y - vxa, b2.x - vya, b2.y - vza, rho_a,
                b3.x, p4.x + b4.x, p4.y + b4.y, p5.x + b5.x, p5.y + b5.y, p6.x + b6.x, p6.y + b6.y,
-               b3.y, b7.x, acc);
+               b7.x, b3.y, acc);
     });
     postpass(k, io_index(g, s), rho_a, acc.L, acc.ax, acc.ay, acc.az, acc.rs, st, out,
              kCorr ? acc.M : nullptr);
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs64_list(GridDev g, int64_t n, C
                                                          const double *__restrict__ rec,
                                                          StateDev st, OutDev out,
                                                          double *__restrict__ Lout) {
-    __shared__ double2 lbuf[kBlock / 64][kLdsWave];
+    __shared__ double2 lbuf[kBlock / 64][64 * 8];
     double2 *buf = lbuf[threadIdx.x >> 6];
     const int64_t s = xcd_block(gridDim.x) * kBlock + threadIdx.x;
     const int64_t w0 = s - __lane_id();
@@ -101,32 +101,32 @@ __global__ __launch_bounds__(kBlock) void k_pairs64_list(GridDev g, int64_t n, C
     const int64_t base = g.pl_block[w0 >> 6];
     const int steps = (int)((g.pl_block[(w0 >> 6) + 1] - base) >> 6);
     const int cnt = act ? g.pl_count[s] : 0;
-    double2 p0 = make_double2(0, 0), p1 = p0, p2 = p0, p3 = p0, p4 = p0, p5 = p0, p6 = p0;
+    double2 p0 = make_double2(0, 0), p1 = p0, p2 = p0, p3 = p0, p4 = p0, p5 = p0, p6 = p0, p7 = p0;
     if (act) {
         const double2 *ra = rec2(rec, s);
-        p0 = ra[0]; p1 = ra[1]; p2 = ra[2]; p3 = ra[3]; p4 = ra[4]; p5 = ra[5]; p6 = ra[6];
+        p0 = ra[0]; p1 = ra[1]; p2 = ra[2]; p3 = ra[3]; p4 = ra[4]; p5 = ra[5]; p6 = ra[6]; p7 = ra[7];
     }
     const double xa = p0.x, ya = p0.y, za = p1.x, vxa = p1.y, vya = p2.x, vza = p2.y;
     const double rho_a = p3.x;
     Acc64 acc;
-    acc.rs = p3.y * k.Wn;  // own term m_a W(0)
+    acc.rs = p7.x * k.Wn;  // own term m_a W(0)
     const char *recs = reinterpret_cast<const char *>(rec);
     const int32_t *row = g.pl_slot + base + __lane_id();
     int e0 = steps > 0 ? row[0] : 0;
     for (int j = 0; j < steps; ++j) {
-        gather_dma(recs, kRec * 8, e0, buf);
+        gather_dma8(recs, kRec * 8, e0, buf);
         if (j + 1 < steps) e0 = row[(int64_t)(j + 1) << 6];
         wave_sync();
         if (j < cnt) {
-            const double2 b0 = dma_chunk(buf, 0), b1 = dma_chunk(buf, 1);
+            const double2 b0 = dma8_chunk(buf, 0), b1 = dma8_chunk(buf, 1);
             const double d2 = dist2_exact(xa, ya, za, b0.x, b0.y, b1.x);
             if (d2 < k.h2) {
-                const double2 b2 = dma_chunk(buf, 2), b3 = dma_chunk(buf, 3);
-                const double2 b4 = dma_chunk(buf, 4), b5 = dma_chunk(buf, 5);
-                const double2 b6 = dma_chunk(buf, 6), b7 = dma_chunk(buf, 7);
+                const double2 b2 = dma8_chunk(buf, 2), b3 = dma8_chunk(buf, 3);
+                const double2 b4 = dma8_chunk(buf, 4), b5 = dma8_chunk(buf, 5);
+                const double2 b6 = dma8_chunk(buf, 6), b7 = dma8_chunk(buf, 7);
                 pair64<kCorr>(k, d2, xa - b0.x, ya - b0.y, za - b1.x, b1.y - vxa, b2.x - vya, b2.y - vza,
                        rho_a, b3.x, p4.x + b4.x, p4.y + b4.y, p5.x + b5.x, p5.y + b5.y,
-                       p6.x + b6.x, p6.y + b6.y, b3.y, b7.x, acc);
+                       p6.x + b6.x, p6.y + b6.y, b7.x, b3.y, acc);
             }
         }
         wave_sync();
@@ -209,7 +209,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs32(GridDev g, int64_t n, Consts
     const int64_t s = xcd_block(gridDim.x) * kBlock + threadIdx.x;
     if (s >= n) return;
     const Src32 a = load32(r32, s);
-    const double2 p3 = rec2(rec, s)[3];
+    const double2 p3 = rec2(rec, s)[3], p7 = rec2(rec, s)[7];
     const Consts32 kf = narrow(k);
     Acc32 acc;
     for_each_candidate(g, s, a.x, a.y, a.z, k.reach, [&](int t) {
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs32(GridDev g, int64_t n, Consts
         const double d2 = dist2_exact(a.x, a.y, a.z, b.x, b.y, b.z);
         if (d2 < k.h2) pair32_of<kCorr>(kf, a, b, d2, acc);
     });
-    post32<kCorr>(k, io_index(g, s), p3.x, p3.y, acc, st, out, Lout, n, s);
+    post32<kCorr>(k, io_index(g, s), p3.x, p7.x, acc, st, out, Lout, n, s);
 }
 
 // FP32 pair sums over the frozen pair list (cooperative gathers of the 80-byte records)
@@ -227,7 +227,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs32_list(GridDev g, int64_t n, C
                                                          const float *__restrict__ r32,
                                                          StateDev st, OutDev out,
                                                          double *__restrict__ Lout) {
-    __shared__ double2 lbuf[kBlock / 64][kLdsWave];
+    __shared__ double2 lbuf[kBlock / 64][64 * 5];
     double2 *buf = lbuf[threadIdx.x >> 6];
     const int64_t s = xcd_block(gridDim.x) * kBlock + threadIdx.x;
     const int64_t w0 = s - __lane_id();
@@ -243,20 +243,20 @@ __global__ __launch_bounds__(kBlock) void k_pairs32_list(GridDev g, int64_t n, C
     const int32_t *row = g.pl_slot + base + __lane_id();
     int e0 = steps > 0 ? row[0] : 0;
     for (int j = 0; j < steps; ++j) {
-        gather_dma5(recs, kRec32Bytes, e0, buf);
+        gather_dma<5>(recs, kRec32Bytes, e0, buf);
         if (j + 1 < steps) e0 = row[(int64_t)(j + 1) << 6];
         wave_sync();
         if (j < cnt) {
-            const Src32 b = src32(dma5_chunk(buf, 0), dma5_chunk(buf, 1), dma5_chunk(buf, 2),
-                                  dma5_chunk(buf, 3), dma5_chunk(buf, 4));
+            const Src32 b = src32(dma_chunk<5>(buf, 0), dma_chunk<5>(buf, 1), dma_chunk<5>(buf, 2),
+                                  dma_chunk<5>(buf, 3), dma_chunk<5>(buf, 4));
             const double d2 = dist2_exact(a.x, a.y, a.z, b.x, b.y, b.z);
             if (d2 < k.h2) pair32_of<kCorr>(kf, a, b, d2, acc);
         }
         wave_sync();
     }
     if (!act) return;
-    const double2 p3 = rec2(rec, s)[3];
-    post32<kCorr>(k, io_index(g, s), p3.x, p3.y, acc, st, out, Lout, n, s);
+    const double2 p3 = rec2(rec, s)[3], p7 = rec2(rec, s)[7];
+    post32<kCorr>(k, io_index(g, s), p3.x, p7.x, acc, st, out, Lout, n, s);
 }
 
 }  // namespace

@@ -64,10 +64,11 @@ inline OutDev out_dev(const sph_deriv *o) {
                   o->dszz, o->dsxy, o->dsxz, o->dsyz, o->rho_sum};
 }
 
-// Slot-ordered operand records, one 128-byte record per slot so that a partner
-// is gathered with eight 16-byte loads:
-//   x y z vx | vy vz rho m | T0 T1 T2 T3 | T4 T5 V -
-// with T = sigma / rho^2 (xx, yy, zz, xy, xz, yz) and V = m / rho.
+// Slot-ordered operand records, one 128-byte record per slot:
+//   x y z vx | vy vz rho V | T0 T1 T2 T3 | T4 T5 m -
+// with T = sigma / rho^2 (xx, yy, zz, xy, xz, yz) and V = m / rho.  A partner's
+// first seven 16-byte chunks carry everything its pair terms need (its mass being
+// V rho), which the adjoint's gathers use; the forward kernels read all eight.
 constexpr int kRec = 16;
 // FP32 record, 80 bytes per slot: FP64 position (for the exact partner test and
 // the differences) and the FP32 operands:
@@ -90,25 +91,53 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-// Coalesced gather of one partner record per lane into the wavefront's LDS
-// buffer.  Each lane holds its list entry of the step (one coalesced load by
-// the caller); lane shuffles hand the entries to the lanes that load the
-// records' 16-byte chunks, so that every load instruction moves whole records
-// (eight 128-byte lines for the FP64 records) instead of one chunk of 64
-// scattered records.  Every list entry is a valid slot (padding repeats a
-// slot), so no load is guarded; lanes ignore the records of their padding
-// entries.
-constexpr int kLdsWave = 64 * 8;  // double2 per wavefront buffer (64 records of 128 bytes)
-
-// 8-chunk records: the loads write LDS themselves (global_load_lds_dwordx4, 1 KB
-// per instruction, no registers and no LDS stores), so instruction i fills
-// positions 64 i .. 64 i + 63 and the record r = 8 i + (lane >> 3) loaded there
-// lands with chunk c at
-// buf[8 r + ((c + r) & 7)]: each lane loads the chunk that the rotation puts
-// under it.  The rotation keeps the per-lane reads (dma_chunk) nearly free of
-// bank conflicts.  The compiler waits for the loads before the first LDS read.
+// Coalesced gather of the first N 16-byte chunks of one partner record per lane
+// into the wavefront's LDS buffer (64 N chunks).  Each lane holds its list entry of
+// the step (one coalesced load by the caller); lane shuffles hand the entries to
+// the lanes that load the records' chunks, so that each load instruction moves
+// whole records (about eight 128-byte lines) instead of one chunk of 64 scattered
+// records.  The loads write LDS themselves (global_load_lds_dwordx4, 1 KB per
+// instruction, no registers and no LDS stores): instruction i fills positions
+// 64 i .. 64 i + 63, position q holding chunk q % N of record q / N, so record r's
+// chunk c sits at buf[N r + c] (an odd N keeps the per-lane reads free of bank
+// conflicts).  Every list entry is a valid slot (padding repeats a slot), so no
+// load is guarded; lanes ignore the records of their padding entries.  The
+// compiler waits for the loads before the first LDS read.
+template <int N>
 __device__ inline void gather_dma(const char *__restrict__ recs, int stride, int entry,
                                   double2 *buf) {
+    static_assert(N % 2 == 1, "odd chunk counts avoid LDS bank conflicts");
+    const int lane = __lane_id();
+    uint32_t t[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        t[i] = (uint32_t)__builtin_amdgcn_ds_bpermute(4 * ((64 * i + lane) / N), entry);
+    // one barrier for all entries: the shuffles complete together, then the loads issue
+    if constexpr (N == 7)
+        asm volatile("" : "+v"(t[0]), "+v"(t[1]), "+v"(t[2]), "+v"(t[3]), "+v"(t[4]), "+v"(t[5]),
+                     "+v"(t[6]));
+    else if constexpr (N == 5)
+        asm volatile("" : "+v"(t[0]), "+v"(t[1]), "+v"(t[2]), "+v"(t[3]), "+v"(t[4]));
+    else
+        static_assert(N == 5 || N == 7, "gather widths in use");
+    uint32_t st = (uint32_t)stride;
+    asm("" : "+s"(st));
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const int c = (64 * i + lane) % N;
+        __builtin_amdgcn_global_load_lds(
+            reinterpret_cast<const void *>(recs + (uint64_t)t[i] * st + c * 16),
+            (__attribute__((address_space(3))) void *)(buf + 64 * i), 16, 0, 0);
+    }
+}
+
+// All eight chunks of 128-byte records, eight whole records (cache lines) per
+// instruction: instruction i loads records r = 8 i + (lane >> 3), chunk c landing
+// at buf[8 r + ((c + r) & 7)], a rotation that keeps the per-lane reads free of bank
+// conflicts.  (Seven chunks per record spread one instruction over ten lines,
+// which costs the forward kernel more than the eighth chunk's bytes.)
+__device__ inline void gather_dma8(const char *__restrict__ recs, int stride, int entry,
+                                   double2 *buf) {
     const int lane = __lane_id();
     const int r0 = lane >> 3;
     const int cc = ((lane & 7) - r0) & 7;
@@ -128,59 +157,15 @@ __device__ inline void gather_dma(const char *__restrict__ recs, int stride, int
             (__attribute__((address_space(3))) void *)(buf + 64 * i), 16, 0, 0);
 }
 
-// The same for the 5-chunk FP32 record: position q = 64 i + lane holds chunk
-// q % 5 of record q / 5, so record r's chunk c sits at buf[5 r + c] (the odd
-// stride avoids bank conflicts).
-__device__ inline void gather_dma5(const char *__restrict__ recs, int stride, int entry,
-                                   double2 *buf) {
-    const int lane = __lane_id();
-    uint32_t t[5];
-#pragma unroll
-    for (int i = 0; i < 5; ++i)
-        t[i] = (uint32_t)__builtin_amdgcn_ds_bpermute(4 * ((64 * i + lane) / 5), entry);
-#pragma unroll
-    for (int i = 0; i < 5; ++i) asm volatile("" : "+v"(t[i]));
-    uint32_t st = (uint32_t)stride;
-    asm("" : "+s"(st));
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-        const int c = (64 * i + lane) % 5;
-        __builtin_amdgcn_global_load_lds(
-            reinterpret_cast<const void *>(recs + (uint64_t)t[i] * st + c * 16),
-            (__attribute__((address_space(3))) void *)(buf + 64 * i), 16, 0, 0);
-    }
-}
-
-// The same for the first seven chunks of 128-byte records: position q = 64 i + lane
-// holds chunk q % 7 of record q / 7, so record r's chunk c sits at buf[7 r + c]
-// (the odd stride avoids bank conflicts); 448 chunks, seven instructions.
-__device__ inline void gather_dma7(const char *__restrict__ recs, int stride, int entry,
-                                   double2 *buf) {
-    const int lane = __lane_id();
-    uint32_t t[7];
-#pragma unroll
-    for (int i = 0; i < 7; ++i)
-        t[i] = (uint32_t)__builtin_amdgcn_ds_bpermute(4 * ((64 * i + lane) / 7), entry);
-#pragma unroll
-    for (int i = 0; i < 7; ++i) asm volatile("" : "+v"(t[i]));
-    uint32_t st = (uint32_t)stride;
-    asm("" : "+s"(st));
-#pragma unroll
-    for (int i = 0; i < 7; ++i) {
-        const int c = (64 * i + lane) % 7;
-        __builtin_amdgcn_global_load_lds(
-            reinterpret_cast<const void *>(recs + (uint64_t)t[i] * st + c * 16),
-            (__attribute__((address_space(3))) void *)(buf + 64 * i), 16, 0, 0);
-    }
-}
-
-__device__ inline double2 dma7_chunk(const double2 *buf, int c) { return buf[7 * __lane_id() + c]; }
-
-__device__ inline double2 dma5_chunk(const double2 *buf, int c) { return buf[5 * __lane_id() + c]; }
-
-__device__ inline double2 dma_chunk(const double2 *buf, int c) {
+__device__ inline double2 dma8_chunk(const double2 *buf, int c) {
     const int L = __lane_id();
     return buf[8 * L + ((c + L) & 7)];
+}
+
+// chunk c of this lane's record in a gather_dma<N> buffer
+template <int N>
+__device__ inline double2 dma_chunk(const double2 *buf, int c) {
+    return buf[N * __lane_id() + c];
 }
 
 // Liquid equation of state with the optional tension cut-off (section 2.5.1).
@@ -219,11 +204,11 @@ __device__ inline void write_rec(const GridDev &g, const Consts &k, int64_t s, d
     r[0] = make_double2(x, y);
     r[1] = make_double2(z, vx);
     r[2] = make_double2(vy, vz);
-    r[3] = make_double2(rho, m);
+    r[3] = make_double2(rho, m / rho);
     r[4] = make_double2((f * S[0] - p) * ir2, (f * S[1] - p) * ir2);
     r[5] = make_double2((f * S[2] - p) * ir2, f * S[3] * ir2);
     r[6] = make_double2(f * S[4] * ir2, f * S[5] * ir2);
-    r[7] = make_double2(m / rho, 0.0);
+    r[7] = make_double2(m, 0.0);
 }
 
 // 1/sqrt(x): hardware estimate refined by two Newton steps y <- y (3 - x y^2) / 2
