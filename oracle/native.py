@@ -39,6 +39,8 @@ def lib():
         L.orc_prepass.argtypes = [_i64, _pd, _pd, _pd, _pd, _pd, _pd]
         L.orc_rhs.argtypes = [_i64, _pd, _pd, _pd, _pd, _pd, _pd, _pi64, _i64, _pi64, _pi32,
                               _pd, _pd, _pd, _pd, _pd]
+        L.orc_rhs2.argtypes = [_i64, _pd, _pd, _pd, _pd, _pd, _pd, _pi64, _i64, _pi64, _pi32,
+                               _pd, _pd, _pd, _pd, _pd, _pd, _pd]
         _lib = L
     return _lib
 
@@ -113,12 +115,14 @@ def prepass(rho, S, par):
     return dict(p=p, fy=f, sigma=sig)
 
 
-def rhs(pos, vel, rho, S, m, par, targets=None, csr=None, want_L: bool = True):
+def rhs(pos, vel, rho, S, m, par, targets=None, csr=None, want_L: bool = True,
+        want_extra: bool = False):
     """Right-hand side for ``targets`` (all particles when None).
 
     ``csr`` = (row_ptr, col) partner lists of the targets; computed by brute
     force when omitted.  Returns dict acc (3, nt), drho (nt), dS (6, nt),
-    rho_sum (nt) and L (9, nt).
+    rho_sum (nt) and L (9, nt); with ``want_extra`` also du (nt), the specific
+    internal energy rate, and xv (3, nt), dx/dt with XSPH.
     """
     pos, ppos = _f64(pos)
     vel, pvel = _f64(vel)
@@ -143,15 +147,21 @@ def rhs(pos, vel, rho, S, m, par, targets=None, csr=None, want_L: bool = True):
     dS = np.zeros((6, nt))
     rs = np.zeros(nt)
     L = np.zeros((9, nt)) if want_L else None
-    lib().orc_rhs(n, ppos, pvel, prho, pS, pm, ppar, ptg, nt, prow, col.ctypes.data_as(_pi32),
-                  acc.ctypes.data_as(_pd), drho.ctypes.data_as(_pd), dS.ctypes.data_as(_pd),
-                  rs.ctypes.data_as(_pd), L.ctypes.data_as(_pd) if want_L else None)
+    du = np.zeros(nt) if want_extra else None
+    xv = np.zeros((3, nt)) if want_extra else None
+    pnull = lambda a: a.ctypes.data_as(_pd) if a is not None else None
+    lib().orc_rhs2(n, ppos, pvel, prho, pS, pm, ppar, ptg, nt, prow, col.ctypes.data_as(_pi32),
+                   acc.ctypes.data_as(_pd), drho.ctypes.data_as(_pd), dS.ctypes.data_as(_pd),
+                   rs.ctypes.data_as(_pd), pnull(L), pnull(du), pnull(xv))
     out = dict(acc=acc, drho=drho, dS=dS, rho_sum=rs)
     if want_L:
         out["L"] = L
+    if want_extra:
+        out["du"] = du
+        out["xv"] = xv
     return out
 
 
-def rhs_workload(w, targets=None, csr=None, want_L: bool = True):
+def rhs_workload(w, targets=None, csr=None, want_L: bool = True, want_extra: bool = False):
     """``rhs`` on a ``workloads.Workload``."""
-    return rhs(w.pos, w.vel, w.rho, w.S, w.m, w.param_vector(), targets, csr, want_L)
+    return rhs(w.pos, w.vel, w.rho, w.S, w.m, w.param_vector(), targets, csr, want_L, want_extra)

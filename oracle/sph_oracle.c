@@ -24,6 +24,9 @@
  *                 correction tensor of the same section (linear consistency)
  *   stress rate   eqs. (stresstensor_evolution), (strain_rate_tensor), (rotation_terms),
  *                 section 2.4
+ *   energy        eq. (energy_sph), section 3.1.2
+ *   art. stress   section 3.1.4 (tensile instability), added to the momentum bracket
+ *   XSPH          section 3.1.5, the smoothed particle velocity dx/dt
  *
  * Readings of ambiguous passages (each is also listed in the design notes):
  *   - h is the kernel's support radius, as in the kernel definition; the same
@@ -45,12 +48,24 @@
  *     continuity equation keeps its own (uncorrected) sum.  Where M is singular
  *     (det M <= 1e-12 (tr M / 3)^3, e.g. fewer than three non-coplanar
  *     partners) the standard gradient is used.
+ *   - energy equation: as printed, with dW/dx_b = -grad_a W; the bracket also
+ *     holds -Pi*_ab I (the section on artificial viscosity adds it to the energy
+ *     equation as well), i.e. the momentum bracket without artificial stress, so
+ *     that sum_a m_a (v_a . dv_a/dt + du_a/dt) vanishes pair by pair.
+ *   - artificial stress: a particle counts as "in tension" when its pressure is
+ *     negative; then zeta_a = -eps_s sigma_a / rho_a^2 (the whole tensor), else
+ *     zeta_a = 0; f = W(r_ab) / W(dmpd) with dmpd a parameter (the lattice
+ *     spacing of the initial distribution), raised to the power n.
+ *   - XSPH: the printed weight 2 m_b / (rho_a rho_b) is not a velocity; the
+ *     weight is 2 m_b / (rho_a + rho_b) (the mean density of the pair, as in the
+ *     method the section cites).
  *
  * Layout: structure of arrays.  pos and vel are (3, n) row-major (x row, y row,
  * z row); S is (6, n) in the order xx, yy, zz, xy, xz, yz; outputs follow the
  * same layout with the target count nt in place of n; L is (9, nt) row-major
  * over (alpha, beta) with L^{alpha beta} = dv^alpha / dx^beta.
- * par = {h, rho0, c, mu, Y0, alpha, beta, eps_v, rho_cut, correction}.
+ * par = {h, rho0, c, mu, Y0, alpha, beta, eps_v, rho_cut, correction, eps_s, n_s,
+ *        dmpd, xsph}.
  */
 #include <math.h>
 #include <stdint.h>
@@ -60,7 +75,8 @@
 #include <omp.h>
 #endif
 
-enum { P_H, P_RHO0, P_C, P_MU, P_Y0, P_ALPHA, P_BETA, P_EPSV, P_RHOCUT, P_CORR };
+enum { P_H, P_RHO0, P_C, P_MU, P_Y0, P_ALPHA, P_BETA, P_EPSV, P_RHOCUT, P_CORR,
+       P_EPSS, P_NS, P_DMPD, P_XSPH };
 
 static const double PI_ = 3.14159265358979323846;
 
@@ -296,14 +312,20 @@ static int correction_tensor(const double M[3][3], double C[3][3])
     return 1;
 }
 
-void orc_rhs(int64_t n, const double *pos, const double *vel, const double *rho,
-             const double *S, const double *m, const double *par,
-             const int64_t *targets, int64_t nt, const int64_t *row_ptr, const int32_t *col,
-             double *acc, double *drho, double *dS, double *rho_sum, double *Lout)
+/* du (nullable): specific internal energy rate; xv (nullable, (3, nt)): dx/dt */
+void orc_rhs2(int64_t n, const double *pos, const double *vel, const double *rho,
+              const double *S, const double *m, const double *par,
+              const int64_t *targets, int64_t nt, const int64_t *row_ptr, const int32_t *col,
+              double *acc, double *drho, double *dS, double *rho_sum, double *Lout,
+              double *du, double *xv)
 {
     const double h = par[P_H], c = par[P_C], mu = par[P_MU];
     const double alpha = par[P_ALPHA], beta = par[P_BETA], eps_v = par[P_EPSV];
     const int corr = par[P_CORR] != 0.0;
+    const double eps_s = par[P_EPSS], n_s = par[P_NS], xsph = par[P_XSPH];
+    double Wmpd = 1.0, dWmpd;
+    if (eps_s > 0.0)
+        orc_kernel(par[P_DMPD], h, &Wmpd, &dWmpd);
     const double *x = pos, *y = pos + n, *z = pos + 2 * n;
     const double *vx = vel, *vy = vel + n, *vz = vel + 2 * n;
     if (!targets)
@@ -330,6 +352,9 @@ void orc_rhs(int64_t n, const double *pos, const double *vel, const double *rho,
         double rs = m[a] * W0;
         double cont = 0.0;
         double ac[3] = {0.0, 0.0, 0.0};
+        double ue = 0.0;                    /* energy sum */
+        double xs[3] = {0.0, 0.0, 0.0};     /* XSPH sum */
+        const int tens_a = p[a] < 0.0;
         double L[3][3] = {{0.0}};
         double Mc[3][3] = {{0.0}}; /* sum_b V_b (x_b - x_a) (x) grad_a W_ab */
 
@@ -379,16 +404,33 @@ void orc_rhs(int64_t n, const double *pos, const double *vel, const double *rho,
                 Pi = (-alpha * c * nu + beta * nu * nu) / (0.5 * (ra + rb));
             }
 
-            /* momentum */
+            /* artificial stress factor (zeta_a + zeta_b) f^n, zeta = -eps_s sigma / rho^2 in tension */
+            const int tens_b = p[b] < 0.0;
+            double fn = 0.0;
+            if (eps_s > 0.0 && (tens_a || tens_b))
+                fn = pow(W / Wmpd, n_s);
+
+            /* momentum (with artificial stress) and energy (without it) */
             for (int al = 0; al < 3; ++al) {
                 double s = 0.0;
                 for (int be = 0; be < 3; ++be) {
                     const double B = siga[al][be] / (ra * ra) + sigb[al][be] / (rb * rb)
                                      - (al == be ? Pi : 0.0);
-                    s += B * gW[be];
+                    double zeta = 0.0;
+                    if (tens_a)
+                        zeta += -eps_s * siga[al][be] / (ra * ra);
+                    if (tens_b)
+                        zeta += -eps_s * sigb[al][be] / (rb * rb);
+                    s += (B + zeta * fn) * gW[be];
+                    /* energy: (1/2) m_b B (v_a - v_b)^al dW/dx_b^be, dW/dx_b = -gW */
+                    ue += 0.5 * m[b] * B * (va[al] - vb[al]) * (-gW[be]);
                 }
                 ac[al] += m[b] * s;
             }
+
+            /* XSPH: 2 m_b / (rho_a + rho_b) (v_b - v_a) W */
+            for (int d = 0; d < 3; ++d)
+                xs[d] += 2.0 * m[b] / (ra + rb) * (vb[d] - va[d]) * W;
         }
 
         /* corrected velocity gradient L C (the continuity sum above stays as printed) */
@@ -437,6 +479,11 @@ void orc_rhs(int64_t n, const double *pos, const double *vel, const double *rho,
         dS[4 * nt + t] = dSm[0][2];
         dS[5 * nt + t] = dSm[1][2];
         rho_sum[t] = rs;
+        if (du)
+            du[t] = ue;
+        if (xv)
+            for (int d = 0; d < 3; ++d)
+                xv[d * nt + t] = va[d] + xsph * xs[d];
         if (Lout)
             for (int al = 0; al < 3; ++al)
                 for (int be = 0; be < 3; ++be)
@@ -445,4 +492,13 @@ void orc_rhs(int64_t n, const double *pos, const double *vel, const double *rho,
     free(p);
     free(fy);
     free(sg);
+}
+
+void orc_rhs(int64_t n, const double *pos, const double *vel, const double *rho,
+             const double *S, const double *m, const double *par,
+             const int64_t *targets, int64_t nt, const int64_t *row_ptr, const int32_t *col,
+             double *acc, double *drho, double *dS, double *rho_sum, double *Lout)
+{
+    orc_rhs2(n, pos, vel, rho, S, m, par, targets, nt, row_ptr, col, acc, drho, dS, rho_sum,
+             Lout, NULL, NULL);
 }

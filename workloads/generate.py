@@ -34,10 +34,14 @@ MATERIAL = dict(
     eps_v=0.01,
     rho_cut=0.0,
     correction=0.0,
+    eps_s=0.0,   # artificial stress off (0.2 where used)
+    n_s=4.0,     # its exponent
+    xsph=0.0,    # XSPH off (0.5 where used)
 )
 
 # order of the scalar parameter vector shared by every consumer
-PARAM_ORDER = ("h", "rho0", "c", "mu", "Y0", "alpha", "beta", "eps_v", "rho_cut", "correction")
+PARAM_ORDER = ("h", "rho0", "c", "mu", "Y0", "alpha", "beta", "eps_v", "rho_cut", "correction",
+               "eps_s", "n_s", "dmpd", "xsph")
 
 CONFIG_NAMES = {
     0: "cube16_fp64_4096",
@@ -97,6 +101,7 @@ class Workload:
 def _params(h: float, **over) -> dict:
     p = dict(MATERIAL)
     p["h"] = float(h)
+    p["dmpd"] = float(h) / H_OVER_DX  # mean particle distance of the initial lattice
     p.update(over)
     return p
 
