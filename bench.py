@@ -298,6 +298,18 @@ def main():
         ref = outs["fp64"][k]
         errs[k] = float((outs["fp32comp"][k] - ref).abs().max() / ref.abs().max())
     forms["rhs_fp32comp"]["normwise_error_vs_fp64"] = errs
+    # the next rows of the pair loop: energy equation, artificial stress (eps_s 0.2, n 4,
+    # on a copy of the state whose densities are spread by +-0.5 % so that half of the
+    # particles are in tension) and XSPH (0.5), FP64, same list
+    sx = P.ParticleState(st.pos, st.vel, st.rho * (1.0 + 0.005 * (2.0 * torch.rand(
+        n, dtype=torch.float64, device=dev, generator=torch.Generator(dev).manual_seed(5)) - 1.0)),
+        st.S, st.m)
+    px = dict(w.params, eps_s=0.2, n_s=4.0, xsph=0.5)
+    ox = P.api.new_deriv(n, extra=True)
+    ms = median_ms(lambda: P.sph_rhs(g, sx, px, "fp64", out=ox, ws=ws_rhs), args.form_reps, torch)
+    forms["rhs_fp64_energy_artstress_xsph"] = {
+        "ms": ms, "pairs_per_s": nnz0 / (ms * 1e-3),
+        "particles_in_tension": int((sx.rho < w.params["rho0"]).sum())}
     forms["fp32comp_speedup_vs_fp64"] = forms["rhs_fp64"]["ms"] / forms["rhs_fp32comp"]["ms"]
     cg = {k: torch.randn_like(outs["fp64"][k]) for k in fields}
     ms = median_ms(lambda: P.sph_rhs_adjoint(g, st, w.params, cg, ws=ws_adj), args.form_reps, torch)

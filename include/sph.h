@@ -126,17 +126,30 @@ typedef struct {
  * rho / rho0 < rho_cut (tension cut-off of section 2.5.1; 0 disables it);
  * correction: 1 applies the correction tensor of section 3.1.6 (linear
  * consistency) to the velocity gradient that drives the stress rate, 0 uses the
- * standard gradient. */
+ * standard gradient; eps_s, n_s, dmpd: artificial stress of section 3.1.4 (0
+ * disables it): a particle with negative pressure contributes
+ * zeta = -eps_s sigma / rho^2 to the momentum bracket, scaled by
+ * (W(r) / W(dmpd))^n_s, dmpd in (0, h) being the mean particle distance of the
+ * initial distribution (FP64 forms only; the adjoints refuse it); xsph: XSPH
+ * factor in [0, 1] (section 3.1.5), used by the dx/dt output. */
 typedef struct {
     double h, rho0, c, mu, Y0, alpha, beta, eps_v, rho_cut, correction;
+    double eps_s, n_s, dmpd, xsph;
 } sph_params;
 
-/* Time derivatives (outputs) in user order.  rho_sum may be NULL. */
+/* Time derivatives (outputs) in user order.  rho_sum may be NULL.  du and
+ * dx, dy, dz (all four NULL, or none) request the specific internal energy rate
+ * (eq. energy_sph; the bracket holds -Pi* I as in the momentum equation, without
+ * the artificial stress) and the particle velocity dx/dt with XSPH (section
+ * 3.1.5: v_a + xsph sum_b 2 m_b / (rho_a + rho_b) (v_b - v_a) W_ab; = v_a when
+ * xsph = 0); FP64 only. */
 typedef struct {
     double *ax, *ay, *az;
     double *drho;
     double *dsxx, *dsyy, *dszz, *dsxy, *dsxz, *dsyz;
     double *rho_sum;
+    double *du;
+    double *dx, *dy, *dz;
 } sph_deriv;
 
 /* Cotangents of the derivatives (inputs of the adjoint), user order.  A NULL

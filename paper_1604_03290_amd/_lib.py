@@ -65,7 +65,8 @@ class State(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [(k, C.c_double) for k in
-                ("h", "rho0", "c", "mu", "Y0", "alpha", "beta", "eps_v", "rho_cut", "correction")]
+                ("h", "rho0", "c", "mu", "Y0", "alpha", "beta", "eps_v", "rho_cut", "correction",
+                 "eps_s", "n_s", "dmpd", "xsph")]
 
 
 _DERIV = ("ax", "ay", "az", "drho", "dsxx", "dsyy", "dszz", "dsxy", "dsxz", "dsyz", "rho_sum")
@@ -73,7 +74,7 @@ _FIELDS = ("x", "y", "z", "vx", "vy", "vz", "rho", "sxx", "syy", "szz", "sxy", "
 
 
 class Deriv(C.Structure):
-    _fields_ = [(k, _pd) for k in _DERIV]
+    _fields_ = [(k, _pd) for k in _DERIV + ("du", "dx", "dy", "dz")]
 
 
 class DerivCot(C.Structure):

@@ -16,7 +16,10 @@ import torch
 from . import _lib as L
 
 F64 = torch.float64
-PARAM_ORDER = ("h", "rho0", "c", "mu", "Y0", "alpha", "beta", "eps_v", "rho_cut", "correction")
+PARAM_ORDER = ("h", "rho0", "c", "mu", "Y0", "alpha", "beta", "eps_v", "rho_cut", "correction",
+               "eps_s", "n_s", "dmpd", "xsph")
+# parameters that may be left out of a dict (their neutral values)
+PARAM_DEFAULTS = {"correction": 0.0, "eps_s": 0.0, "n_s": 4.0, "dmpd": 0.0, "xsph": 0.0}
 DERIV_KEYS = ("acc", "drho", "dS", "rho_sum")
 
 
@@ -71,7 +74,7 @@ class ParticleState:
 
 def params_struct(params) -> L.Params:
     if isinstance(params, dict):
-        vals = [float(params.get(k, 0.0)) if k == "correction" else float(params[k])
+        vals = [float(params.get(k, PARAM_DEFAULTS[k])) if k in PARAM_DEFAULTS else float(params[k])
                 for k in PARAM_ORDER]
     else:
         vals = [float(v) for v in params]
@@ -207,11 +210,16 @@ def sph_neighbours(grid: CellGrid, pos: torch.Tensor, h: float, col_cap: int | N
     return row_ptr, col[: int(nnz.value)]
 
 
-def new_deriv(n: int, device="cuda"):
-    return dict(acc=torch.empty(3, n, dtype=F64, device=device),
-                drho=torch.empty(n, dtype=F64, device=device),
-                dS=torch.empty(6, n, dtype=F64, device=device),
-                rho_sum=torch.empty(n, dtype=F64, device=device))
+def new_deriv(n: int, device="cuda", extra: bool = False):
+    """Output arrays of sph_rhs; with ``extra`` also du (n) and xv (3, n) = dx/dt."""
+    d = dict(acc=torch.empty(3, n, dtype=F64, device=device),
+             drho=torch.empty(n, dtype=F64, device=device),
+             dS=torch.empty(6, n, dtype=F64, device=device),
+             rho_sum=torch.empty(n, dtype=F64, device=device))
+    if extra:
+        d["du"] = torch.empty(n, dtype=F64, device=device)
+        d["xv"] = torch.empty(3, n, dtype=F64, device=device)
+    return d
 
 
 def deriv_struct(d: dict, cls=L.Deriv):
@@ -219,9 +227,18 @@ def deriv_struct(d: dict, cls=L.Deriv):
     for t in (a, s, d["drho"]):
         _dev(t)
     rs = d.get("rho_sum")
-    return cls(a[0].data_ptr(), a[1].data_ptr(), a[2].data_ptr(), d["drho"].data_ptr(),
-               s[0].data_ptr(), s[1].data_ptr(), s[2].data_ptr(), s[3].data_ptr(),
-               s[4].data_ptr(), s[5].data_ptr(), rs.data_ptr() if rs is not None else None)
+    p = lambda t: t.data_ptr() if t is not None else None
+    args = [a[0].data_ptr(), a[1].data_ptr(), a[2].data_ptr(), d["drho"].data_ptr(),
+            s[0].data_ptr(), s[1].data_ptr(), s[2].data_ptr(), s[3].data_ptr(),
+            s[4].data_ptr(), s[5].data_ptr(), p(rs)]
+    if cls is L.Deriv:
+        du, xv = d.get("du"), d.get("xv")
+        for t in (du, xv):
+            if t is not None:
+                _dev(t)
+        args += [p(du)] + ([xv[0].data_ptr(), xv[1].data_ptr(), xv[2].data_ptr()]
+                           if xv is not None else [None, None, None])
+    return cls(*args)
 
 
 def fields_struct(pos, vel, rho, S, cls=L.Fields):
@@ -240,11 +257,12 @@ def precision_code(precision) -> int:
 
 
 def sph_rhs(grid: CellGrid, state: ParticleState, params, precision="fp64", out=None,
-            ws: torch.Tensor | None = None) -> dict:
-    """Right-hand side (C: sph_rhs): dict acc (3, n), drho (n), dS (6, n), rho_sum (n)."""
+            ws: torch.Tensor | None = None, extra: bool = False) -> dict:
+    """Right-hand side (C: sph_rhs): dict acc (3, n), drho (n), dS (6, n), rho_sum (n);
+    with ``extra`` (or an ``out`` holding them) also du (n) and xv (3, n) = dx/dt."""
     n = state.n
     if out is None:
-        out = new_deriv(n, state.rho.device)
+        out = new_deriv(n, state.rho.device, extra)
     if ws is None:
         ws = workspace(L.SPH_OP_RHS, n, 0, state.rho.device)
     cs = state.c_state()

@@ -557,6 +557,8 @@ extern "C" int sph_rhs_adjoint(const sph_grid *grid, const sph_state *state,
         return rc;
     if (!cot) return fail(SPH_ERR_INVALID_ARG, "cotangent struct is NULL");
     if (!dparams || !ws) return fail(SPH_ERR_INVALID_ARG, "null pointer");
+    if (params->eps_s > 0.0)
+        return fail(SPH_ERR_NOT_IMPLEMENTED, "adjoint with the artificial stress");
     const size_t need = adjoint_ws_bytes(grid->n);
     if (ws_bytes < need) return fail(SPH_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
     hipStream_t s = (hipStream_t)stream;

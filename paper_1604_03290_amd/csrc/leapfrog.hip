@@ -301,6 +301,7 @@ sph_deriv deriv_struct(const Deriv10 &d) {
     o.dsxz = d.p[8];
     o.dsyz = d.p[9];
     o.rho_sum = nullptr;
+    o.du = o.dx = o.dy = o.dz = nullptr;
     return o;
 }
 
@@ -364,6 +365,8 @@ int check_lf(const sph_grid *grid, const sph_state *s0, const sph_params *params
         return rc;
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SPH_ERR_INVALID_ARG, "dt must be positive");
     if (steps < 1) return fail(SPH_ERR_INVALID_ARG, "steps must be >= 1");
+    if (params->xsph != 0.0)
+        return fail(SPH_ERR_NOT_IMPLEMENTED, "the leapfrog drifts with v (no XSPH)");
     return SPH_OK;
 }
 
@@ -457,6 +460,8 @@ extern "C" int sph_leapfrog_adjoint(const sph_grid *grid, const sph_state *s0,
     if ((rc = check_lf(grid, s0, params, dt, steps)) || (rc = check_grad(grad0))) return rc;
     if (!checkpoints || !cot_final || !dparams || !ws)
         return fail(SPH_ERR_INVALID_ARG, "null pointer");
+    if (params->eps_s > 0.0)
+        return fail(SPH_ERR_NOT_IMPLEMENTED, "adjoint with the artificial stress");
     const int64_t n = grid->n;
     const size_t need = leapfrog_adjoint_ws_bytes(n);
     if (ws_bytes < need) return fail(SPH_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);

@@ -16,6 +16,8 @@
 // W'(r)/r = 6 s/h^5 f(q) with w = 1 - 6q^2 + 6q^3, f = 3q - 2 for q < 1/2 and
 // w = 2 (1-q)^3, f = -(1-q)^2 / q for 1/2 <= q < 1, so grad_a W_ab =
 // (W'/r)(x_a - x_b) stays finite as r -> 0.
+#include <type_traits>
+
 #include "common.hpp"
 #include "rhs_common.hpp"
 #include "timing.hpp"
@@ -51,7 +53,7 @@ __global__ __launch_bounds__(kBlock) void k_narrow(const double *__restrict__ re
 }
 
 // ---------------------------------------------------------- pairs, FP64 --
-template <bool kCorr>
+template <bool kCorr, bool kExt>
 __global__ __launch_bounds__(kBlock) void k_pairs64(GridDev g, int64_t n, Consts k,
                                                     const double *__restrict__ rec, StateDev st,
                                                     OutDev out, double *__restrict__ Lout) {
@@ -63,18 +65,22 @@ __global__ __launch_bounds__(kBlock) void k_pairs64(GridDev g, int64_t n, Consts
     const double rho_a = p3.x;
     Acc64 acc;
     acc.rs = ra[7].x * k.Wn;  // own term m_a W(0)
+    const double Ta[6] = {p4.x, p4.y, p5.x, p5.y, p6.x, p6.y};
+    const bool tens_a = kExt && in_tension(k, rho_a);
     for_each_candidate(g, s, xa, ya, za, k.reach, [&](int t) {
         const double2 *rb = rec2(rec, t);
         const double2 b0 = rb[0], b1 = rb[1];
         const double d2 = dist2_exact(xa, ya, za, b0.x, b0.y, b1.x);
         if (!(d2 < k.h2)) return;
         const double2 b2 = rb[2], b3 = rb[3], b4 = rb[4], b5 = rb[5], b6 = rb[6], b7 = rb[7];
-        pair64<kCorr>(k, d2, xa - b0.x, ya - b0.y, za - b1.x, b1.y - vxa, b2.x - vya, b2.y - vza, rho_a,
-               b3.x, p4.x + b4.x, p4.y + b4.y, p5.x + b5.x, p5.y + b5.y, p6.x + b6.x, p6.y + b6.y,
-               b7.x, b3.y, acc);
+        const double Tb[6] = {b4.x, b4.y, b5.x, b5.y, b6.x, b6.y};
+        pair64<kCorr, kExt>(k, d2, xa - b0.x, ya - b0.y, za - b1.x, b1.y - vxa, b2.x - vya,
+                            b2.y - vza, rho_a, b3.x, p4.x + b4.x, p4.y + b4.y, p5.x + b5.x,
+                            p5.y + b5.y, p6.x + b6.x, p6.y + b6.y, b7.x, b3.y, acc, Ta, Tb, tens_a);
     });
     postpass(k, io_index(g, s), rho_a, acc.L, acc.ax, acc.ay, acc.az, acc.rs, st, out,
              kCorr ? acc.M : nullptr);
+    if (kExt) postpass_ext(k, io_index(g, s), acc, st, out);
     if (Lout) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) Lout[i * n + s] = acc.L[i];
@@ -87,7 +93,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs64(GridDev g, int64_t n, Consts
 
 // FP64 pair sums over the frozen pair list: the wavefront walks its 64 lists in
 // lock step, gathering the 64 partner records of step j cooperatively.
-template <bool kCorr>
+template <bool kCorr, bool kExt>
 __global__ __launch_bounds__(kBlock) void k_pairs64_list(GridDev g, int64_t n, Consts k,
                                                          const double *__restrict__ rec,
                                                          StateDev st, OutDev out,
@@ -110,6 +116,8 @@ __global__ __launch_bounds__(kBlock) void k_pairs64_list(GridDev g, int64_t n, C
     const double rho_a = p3.x;
     Acc64 acc;
     acc.rs = p7.x * k.Wn;  // own term m_a W(0)
+    const double Ta[6] = {p4.x, p4.y, p5.x, p5.y, p6.x, p6.y};
+    const bool tens_a = kExt && in_tension(k, rho_a);
     const char *recs = reinterpret_cast<const char *>(rec);
     const int32_t *row = g.pl_slot + base + __lane_id();
     int e0 = steps > 0 ? row[0] : 0;
@@ -124,9 +132,11 @@ __global__ __launch_bounds__(kBlock) void k_pairs64_list(GridDev g, int64_t n, C
                 const double2 b2 = dma8_chunk(buf, 2), b3 = dma8_chunk(buf, 3);
                 const double2 b4 = dma8_chunk(buf, 4), b5 = dma8_chunk(buf, 5);
                 const double2 b6 = dma8_chunk(buf, 6), b7 = dma8_chunk(buf, 7);
-                pair64<kCorr>(k, d2, xa - b0.x, ya - b0.y, za - b1.x, b1.y - vxa, b2.x - vya, b2.y - vza,
-                       rho_a, b3.x, p4.x + b4.x, p4.y + b4.y, p5.x + b5.x, p5.y + b5.y,
-                       p6.x + b6.x, p6.y + b6.y, b7.x, b3.y, acc);
+                const double Tb[6] = {b4.x, b4.y, b5.x, b5.y, b6.x, b6.y};
+                pair64<kCorr, kExt>(k, d2, xa - b0.x, ya - b0.y, za - b1.x, b1.y - vxa, b2.x - vya,
+                                    b2.y - vza, rho_a, b3.x, p4.x + b4.x, p4.y + b4.y, p5.x + b5.x,
+                                    p5.y + b5.y, p6.x + b6.x, p6.y + b6.y, b7.x, b3.y, acc, Ta, Tb,
+                                    tens_a);
             }
         }
         wave_sync();
@@ -134,6 +144,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs64_list(GridDev g, int64_t n, C
     if (!act) return;
     postpass(k, io_index(g, s), rho_a, acc.L, acc.ax, acc.ay, acc.az, acc.rs, st, out,
              kCorr ? acc.M : nullptr);
+    if (kExt) postpass_ext(k, io_index(g, s), acc, st, out);
     if (Lout) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) Lout[i * n + s] = acc.L[i];
@@ -287,8 +298,9 @@ int check_state(const sph_grid *grid, const sph_state *st) {
 
 int check_params(const sph_grid *grid, const sph_params *pr) {
     if (!pr) return fail(SPH_ERR_INVALID_ARG, "params is NULL");
-    const double v[] = {pr->h,     pr->rho0, pr->c,     pr->mu,      pr->Y0,
-                        pr->alpha, pr->beta, pr->eps_v, pr->rho_cut, pr->correction};
+    const double v[] = {pr->h,     pr->rho0,    pr->c,     pr->mu,   pr->Y0,   pr->alpha,
+                        pr->beta,  pr->eps_v,   pr->rho_cut, pr->correction, pr->eps_s, pr->n_s,
+                        pr->dmpd,  pr->xsph};
     for (double q : v)
         if (!std::isfinite(q)) return fail(SPH_ERR_INVALID_ARG, "non-finite parameter");
     if (!(pr->h > 0.0) || !(pr->rho0 > 0.0) || !(pr->c > 0.0))
@@ -298,6 +310,10 @@ int check_params(const sph_grid *grid, const sph_params *pr) {
     if (pr->h > grid->h) return fail(SPH_ERR_INVALID_ARG, "h exceeds the grid's support radius");
     if (pr->correction != 0.0 && pr->correction != 1.0)
         return fail(SPH_ERR_INVALID_ARG, "correction must be 0 or 1");
+    if (pr->eps_s < 0.0 || !(pr->xsph >= 0.0 && pr->xsph <= 1.0))
+        return fail(SPH_ERR_INVALID_ARG, "eps_s >= 0 and 0 <= xsph <= 1 required");
+    if (pr->eps_s > 0.0 && (!(pr->n_s > 0.0) || !(pr->dmpd > 0.0) || !(pr->dmpd < pr->h)))
+        return fail(SPH_ERR_INVALID_ARG, "artificial stress needs n_s > 0 and 0 < dmpd < h");
     return SPH_OK;
 }
 
@@ -307,6 +323,8 @@ int check_deriv(const sph_deriv *o) {
                          o->dsxy, o->dsxz, o->dsyz};
     for (const double *q : p)
         if (!q) return fail(SPH_ERR_INVALID_ARG, "output array is NULL");
+    if (!(o->dx && o->dy && o->dz) && (o->dx || o->dy || o->dz))
+        return fail(SPH_ERR_INVALID_ARG, "dx, dy and dz are given together or not at all");
     return SPH_OK;
 }
 
@@ -327,19 +345,32 @@ int rhs_launch(const sph_grid *grid, const sph_state *state, const sph_params *p
     OutDev od = out_dev(out);
     int rc;
     if (!rec_ready && (rc = prepass_launch(g, st, n, k, rec, c.status(), s))) return rc;
+    const bool ext = k.eps_s > 0.0 || od.du || od.dx;
     if (precision == SPH_FP64) {
         TimedRegion t("pairs_fp64", s);
         const dim3 gb(blocks_for(n)), tb(kBlock);
-        if (g.pl_count && k.corr)
-            k_pairs64_list<true><<<gb, tb, 0, s>>>(g, n, k, rec, st, od, L_out);
-        else if (g.pl_count)
-            k_pairs64_list<false><<<gb, tb, 0, s>>>(g, n, k, rec, st, od, L_out);
+        auto launch = [&](auto corr, auto extra) {
+            constexpr bool C = decltype(corr)::value, E = decltype(extra)::value;
+            if (g.pl_count)
+                k_pairs64_list<C, E><<<gb, tb, 0, s>>>(g, n, k, rec, st, od, L_out);
+            else
+                k_pairs64<C, E><<<gb, tb, 0, s>>>(g, n, k, rec, st, od, L_out);
+        };
+        using T = std::true_type;
+        using F = std::false_type;
+        if (k.corr && ext)
+            launch(T{}, T{});
         else if (k.corr)
-            k_pairs64<true><<<gb, tb, 0, s>>>(g, n, k, rec, st, od, L_out);
+            launch(T{}, F{});
+        else if (ext)
+            launch(F{}, T{});
         else
-            k_pairs64<false><<<gb, tb, 0, s>>>(g, n, k, rec, st, od, L_out);
+            launch(F{}, F{});
         SPH_LAUNCHED();
     } else {
+        if (ext)
+            return fail(SPH_ERR_NOT_IMPLEMENTED,
+                        "artificial stress, energy and XSPH outputs are FP64 only");
         k_narrow<<<blocks_for(n), kBlock, 0, s>>>(rec, n, r32);
         SPH_LAUNCHED();
         TimedRegion t("pairs_fp32comp", s);

@@ -13,7 +13,17 @@ struct Consts {
     double rho0, c2, mu, Y0, Y0sq;
     double alpha_c, beta, epsh2, rho_cut;
     int corr;  // correction tensor of section 3.1.6 on the stress-rate gradient
+    // artificial stress (section 3.1.4): eps_s, exponent, 1 / w(dmpd / h); XSPH factor
+    double eps_s, n_s, inv_wm, xsph;
+    int n_int;  // the exponent when it is a whole number in 1..16 (powers by multiplication), else 0
 };
+
+// Kernel shape w(q) of section 3.1.1 (W = s/h^3 w), host side.
+inline double kernel_shape(double q) {
+    if (q < 0.5) return 1.0 + 6.0 * q * q * (q - 1.0);
+    if (q < 1.0) return 2.0 * (1.0 - q) * (1.0 - q) * (1.0 - q);
+    return 0.0;
+}
 
 inline Consts make_consts(const sph_params &p, double delta) {
     Consts k;
@@ -34,6 +44,11 @@ inline Consts make_consts(const sph_params &p, double delta) {
     k.epsh2 = p.eps_v * p.h * p.h;
     k.rho_cut = p.rho_cut;
     k.corr = p.correction != 0.0;
+    k.eps_s = p.eps_s;
+    k.n_s = p.n_s;
+    k.inv_wm = p.eps_s > 0.0 ? 1.0 / kernel_shape(p.dmpd / p.h) : 0.0;
+    k.xsph = p.xsph;
+    k.n_int = (p.n_s >= 1.0 && p.n_s <= 16.0 && p.n_s == (double)(int)p.n_s) ? (int)p.n_s : 0;
     return k;
 }
 
@@ -57,11 +72,12 @@ inline StateDev state_dev(const sph_state *s) {
 
 struct OutDev {
     double *ax, *ay, *az, *drho, *dsxx, *dsyy, *dszz, *dsxy, *dsxz, *dsyz, *rho_sum;
+    double *du, *dx, *dy, *dz;  // energy rate and dx/dt (null unless requested)
 };
 
 inline OutDev out_dev(const sph_deriv *o) {
-    return OutDev{o->ax,   o->ay,   o->az,   o->drho, o->dsxx,   o->dsyy,
-                  o->dszz, o->dsxy, o->dsxz, o->dsyz, o->rho_sum};
+    return OutDev{o->ax,   o->ay,   o->az,   o->drho, o->dsxx,    o->dsyy, o->dszz, o->dsxy,
+                  o->dsxz, o->dsyz, o->rho_sum, o->du, o->dx, o->dy, o->dz};
 }
 
 // Slot-ordered operand records, one 128-byte record per slot:
@@ -279,15 +295,33 @@ struct Acc64 {
     // with the correction: M = sum_b V_b (x_b - x_a) (x) grad_a W_ab, which is
     // -V_b F r r^T per pair and so symmetric (xx yy zz xy xz yz)
     double M[6] = {0, 0, 0, 0, 0, 0};
+    // with the extra terms: energy sum (twice du/dt) and XSPH velocity sum
+    double du = 0.0, xs[3] = {0, 0, 0};
 };
 
+// f^n for a fractional exponent, out of line so that the pair loop does not carry
+// the registers of pow
+__device__ __attribute__((noinline)) inline double pow_frac(double f, double n) { return pow(f, n); }
+
+// Tension test of the artificial stress: negative pressure (section 2.5.1's
+// cut-off sets the pressure to zero)
+__device__ inline bool in_tension(const Consts &k, double rho) {
+    return rho < k.rho0 && !(k.rho_cut > 0.0 && rho / k.rho0 < k.rho_cut);
+}
+
 // One ordered pair (a target, b partner).  r = x_a - x_b, dv = v_b - v_a,
-// B = T_a + T_b (six components).
-template <bool kCorr = false>
+// B = T_a + T_b (six components).  With kExt also: the artificial stress
+// (zeta_a + zeta_b) (w / w(dmpd))^n in the momentum bracket (Ta, Tb: the two
+// particles' T, tens_a: a in tension), the energy sum m_b B : dv (x) grad_a W
+// (the momentum bracket without artificial stress) and the XSPH sum
+// 2 m_b / (rho_a + rho_b) dv W.
+template <bool kCorr = false, bool kExt = false>
 __device__ inline void pair64(const Consts &k, double d2, double rx, double ry, double rz,
                               double dvx, double dvy, double dvz, double ra, double rb,
                               double Bxx, double Byy, double Bzz, double Bxy, double Bxz,
-                              double Byz, double mb, double Vb, Acc64 &a) {
+                              double Byz, double mb, double Vb, Acc64 &a,
+                              const double *Ta = nullptr, const double *Tb = nullptr,
+                              bool tens_a = false) {
     const double ir = rsqrt64(d2);
     const KernelPieces kp = kernel_pieces(k, d2, ir);
     const double F = k.Fn * kp.f;
@@ -306,9 +340,39 @@ __device__ inline void pair64(const Consts &k, double d2, double rx, double ry, 
     const double wab = -(dvx * rx + dvy * ry + dvz * rz);
     const double Pi = viscosity(k, d2, wab, ra, rb).Pi;
     const double bxx = Bxx - Pi, byy = Byy - Pi, bzz = Bzz - Pi;
-    a.ax = fma(mb, bxx * gx + Bxy * gy + Bxz * gz, a.ax);
-    a.ay = fma(mb, Bxy * gx + byy * gy + Byz * gz, a.ay);
-    a.az = fma(mb, Bxz * gx + Byz * gy + bzz * gz, a.az);
+    const double qx = bxx * gx + Bxy * gy + Bxz * gz;
+    const double qy = Bxy * gx + byy * gy + Byz * gz;
+    const double qz = Bxz * gx + Byz * gy + bzz * gz;
+    if constexpr (kExt) {
+        // energy: B : dv (x) g = dv . (B g)
+        a.du = fma(mb, dvx * qx + dvy * qy + dvz * qz, a.du);
+        // XSPH
+        const double xw = 2.0 * mb * k.Wn * kp.w / (ra + rb);
+        a.xs[0] = fma(xw, dvx, a.xs[0]);
+        a.xs[1] = fma(xw, dvy, a.xs[1]);
+        a.xs[2] = fma(xw, dvz, a.xs[2]);
+        // artificial stress
+        const bool tens_b = in_tension(k, rb);
+        if (k.eps_s > 0.0 && (tens_a || tens_b)) {
+            const double f = kp.w * k.inv_wm;
+            double fn = f;
+            if (k.n_int > 0) {
+                for (int e = 1; e < k.n_int; ++e) fn *= f;
+            } else {
+                fn = pow_frac(f, k.n_s);
+            }
+            const double za = tens_a ? -k.eps_s : 0.0, zb = tens_b ? -k.eps_s : 0.0;
+            double Z[6];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) Z[i] = (za * Ta[i] + zb * Tb[i]) * fn;
+            a.ax = fma(mb, Z[0] * gx + Z[3] * gy + Z[4] * gz, a.ax);
+            a.ay = fma(mb, Z[3] * gx + Z[1] * gy + Z[5] * gz, a.ay);
+            a.az = fma(mb, Z[4] * gx + Z[5] * gy + Z[2] * gz, a.az);
+        }
+    }
+    a.ax = fma(mb, qx, a.ax);
+    a.ay = fma(mb, qy, a.ay);
+    a.az = fma(mb, qz, a.az);
     if constexpr (kCorr) {
         const double P = -Vb * F;
         const double px = P * rx, py = P * ry, pz = P * rz;
@@ -453,6 +517,18 @@ __device__ inline void postpass(const Consts &k, int a, double rho, const double
     o.ay[a] = ay;
     o.az[a] = az;
     if (o.rho_sum) o.rho_sum[a] = rs;
+}
+
+// The extra outputs of user particle a: du/dt (eq. energy_sph, half the
+// accumulated sum) and dx/dt = v_a + xsph * (XSPH sum).
+__device__ inline void postpass_ext(const Consts &k, int a, const Acc64 &acc, const StateDev &st,
+                                    const OutDev &o) {
+    if (o.du) o.du[a] = 0.5 * acc.du;
+    if (o.dx) {
+        o.dx[a] = st.vx[a] + k.xsph * acc.xs[0];
+        o.dy[a] = st.vy[a] + k.xsph * acc.xs[1];
+        o.dz[a] = st.vz[a] + k.xsph * acc.xs[2];
+    }
 }
 
 // Cotangents of the right-hand side's outputs (user order; null = zero).

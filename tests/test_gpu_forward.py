@@ -283,3 +283,88 @@ def test_rhs_corrected_linear_field_exact(precision, tol, path):
     err = np.abs(got["dS"] - want[:, None]).max() / np.abs(want).max()
     assert err < tol, err
 
+
+
+# ---- energy equation, artificial stress, XSPH (sections 3.1.2, 3.1.4, 3.1.5) ----
+
+def gpu_rhs_extra(w, **path):
+    st = gpu_state(w)
+    g = P.sph_build_cells(st.pos, w.h, skin=path.get("skin", 0.0),
+                          cells_per_h=path.get("cells_per_h", 1), pairs=path.get("pairs", False))
+    out = P.sph_rhs(g, st, w.params, "fp64", extra=True)
+    assert P.workspace_status(out["_ws"]) == 0
+    return {k: v.cpu().numpy() for k, v in out.items() if k != "_ws"}
+
+
+def extra_err(got, ref, v):
+    """du against its max, and the XSPH correction dx/dt - v against its own max."""
+    e = {"du": np.abs(got["du"] - ref["du"]).max() / np.abs(ref["du"]).max()}
+    c = ref["xv"] - v
+    e["xsph"] = np.abs((got["xv"] - v) - c).max() / np.abs(c).max()
+    return e
+
+
+@pytest.mark.parametrize("path", ["cells1", "pairs2_skin"])
+@pytest.mark.parametrize("name", ["cube16", "cube12_visc"])
+def test_rhs_extra_terms_match_oracle(name, path):
+    w = _variant(name)
+    w.params.update(eps_s=0.2, n_s=4.0, xsph=0.5)
+    assert (w.rho < w.params["rho0"]).any()  # some particles in tension
+    ref = native.rhs_workload(w, want_extra=True)
+    got = gpu_rhs_extra(w, **PATHS[path])
+    err = normwise(got, ref, w.rho)
+    bad = {k: v for k, v in err.items() if not v <= TOL["fp64"]}
+    assert not bad, bad
+    err = extra_err(got, ref, w.vel)
+    assert max(err.values()) <= TOL["fp64"], err
+    w.params["eps_s"] = 0.0  # the artificial stress acts on this state
+    plain = native.rhs_workload(w)
+    assert np.abs(plain["acc"] - ref["acc"]).max() > 1e-6 * np.abs(ref["acc"]).max()
+
+
+def test_rhs_extra_outputs_leave_the_rest_unchanged():
+    w = W.config(0)
+    plain = gpu_rhs(w, pairs=True)
+    ext = gpu_rhs_extra(w, pairs=True)
+    for k in ("acc", "drho", "dS", "rho_sum"):
+        assert np.array_equal(plain[k], ext[k]), k
+    assert np.array_equal(ext["xv"], w.vel)  # xsph = 0
+    ref = native.rhs_workload(w, want_extra=True)
+    assert np.abs(ext["du"] - ref["du"]).max() <= TOL["fp64"] * np.abs(ref["du"]).max()
+
+
+def test_extra_terms_refused_where_not_built():
+    w = W.config(0)
+    w.params.update(eps_s=0.2)
+    st = gpu_state(w)
+    g = P.sph_build_cells(st.pos, w.h)
+    with pytest.raises(L.SphError) as e:
+        P.sph_rhs(g, st, w.params, "fp32comp")
+    assert e.value.code == L.SPH_ERR_NOT_IMPLEMENTED
+    with pytest.raises(L.SphError) as e:
+        P.sph_rhs_adjoint(g, st, w.params, {"acc": torch.ones(3, w.n, dtype=torch.float64).cuda()})
+    assert e.value.code == L.SPH_ERR_NOT_IMPLEMENTED
+    w.params.update(eps_s=0.0, xsph=0.5)
+    with pytest.raises(L.SphError) as e:
+        P.sph_leapfrog(g, st, w.params, w.dt, 2)
+    assert e.value.code == L.SPH_ERR_NOT_IMPLEMENTED
+    w.params.update(xsph=0.0, eps_s=0.2, dmpd=2.0 * w.h)
+    with pytest.raises(L.SphError) as e:
+        P.sph_rhs(g, st, w.params)
+    assert e.value.code == L.SPH_ERR_INVALID_ARG
+
+
+def test_two_spheres_extra_terms_subsample():
+    w = W.config(1)
+    rng = np.random.default_rng(8)
+    w.vel += rng.normal(0, 50.0, w.vel.shape)
+    w.rho = w.rho * rng.uniform(0.995, 1.005, w.n)
+    w.params.update(eps_s=0.2, n_s=4.0, xsph=0.5)
+    idx = W.subsample(w.n, 2048, 13)
+    ref = native.rhs(w.pos, w.vel, w.rho, w.S, w.m, w.param_vector(), targets=idx, want_extra=True)
+    got = gpu_rhs_extra(w, pairs=True, skin=0.1 * w.dx, cells_per_h=2)
+    got = {k: v[..., idx] for k, v in got.items()}
+    err = normwise(got, ref, w.rho[idx])
+    bad = {k: v for k, v in err.items() if not v <= TOL["fp64"]}
+    assert not bad, bad
+    assert max(extra_err(got, ref, w.vel[:, idx]).values()) <= TOL["fp64"]
