@@ -241,7 +241,18 @@ def test_two_spheres_subsample(precision):
 @pytest.mark.parametrize("precision", ["fp64", "fp32comp"])
 def test_bullet_into_cube_subsample(precision):
     w = W.config(2, state="random")
-    _subsample_parity(w, 1024, precision, seed=12)
+    _subsample_parity(w, 4096, precision, seed=12)
+
+
+@pytest.fixture(scope="module")
+def nonuniform():
+    return W.config(4)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32comp"])
+def test_nonuniform_subsample(nonuniform, precision):
+    """8,388,608 particles, 9 to 255 partners: sampled targets against the oracle."""
+    _subsample_parity(nonuniform, 1024, precision, seed=14)
 
 
 CORR_PATHS = ["cells1", "cells2", "pairs_skin", "pairs2_skin"]
