@@ -39,8 +39,9 @@ def lib():
         L.orc_prepass.argtypes = [_i64, _pd, _pd, _pd, _pd, _pd, _pd]
         L.orc_rhs.argtypes = [_i64, _pd, _pd, _pd, _pd, _pd, _pd, _pi64, _i64, _pi64, _pi32,
                               _pd, _pd, _pd, _pd, _pd]
-        L.orc_rhs2.argtypes = [_i64, _pd, _pd, _pd, _pd, _pd, _pd, _pi64, _i64, _pi64, _pi32,
-                               _pd, _pd, _pd, _pd, _pd, _pd, _pd]
+        L.orc_rhs2.argtypes = [_i64, _pd, _pd, _pd, _pd, _pd, _pd, _pd, _pi64, _i64, _pi64,
+                               _pi32, _pd, _pd, _pd, _pd, _pd, _pd, _pd]
+        L.orc_eos.argtypes = [_i64, _pd, _pd, _pd, _pd, _pd]
         _lib = L
     return _lib
 
@@ -115,14 +116,26 @@ def prepass(rho, S, par):
     return dict(p=p, fy=f, sigma=sig)
 
 
+def eos(rho, par, u=None):
+    """(pressure, squared sound speed) of every particle (sections 2.5.1 to 2.5.3)."""
+    rho, prho = _f64(rho)
+    par, ppar = _f64(par)
+    pu = _f64(u)[1] if u is not None else None
+    p = np.zeros(rho.shape[0])
+    c2 = np.zeros(rho.shape[0])
+    lib().orc_eos(rho.shape[0], prho, pu, ppar, p.ctypes.data_as(_pd), c2.ctypes.data_as(_pd))
+    return p, c2
+
+
 def rhs(pos, vel, rho, S, m, par, targets=None, csr=None, want_L: bool = True,
-        want_extra: bool = False):
+        want_extra: bool = False, u=None):
     """Right-hand side for ``targets`` (all particles when None).
 
     ``csr`` = (row_ptr, col) partner lists of the targets; computed by brute
     force when omitted.  Returns dict acc (3, nt), drho (nt), dS (6, nt),
     rho_sum (nt) and L (9, nt); with ``want_extra`` also du (nt), the specific
-    internal energy rate, and xv (3, nt), dx/dt with XSPH.
+    internal energy rate, and xv (3, nt), dx/dt with XSPH.  ``u``: specific internal
+    energy (the Tillotson equation's second input; zero when None).
     """
     pos, ppos = _f64(pos)
     vel, pvel = _f64(vel)
@@ -150,7 +163,8 @@ def rhs(pos, vel, rho, S, m, par, targets=None, csr=None, want_L: bool = True,
     du = np.zeros(nt) if want_extra else None
     xv = np.zeros((3, nt)) if want_extra else None
     pnull = lambda a: a.ctypes.data_as(_pd) if a is not None else None
-    lib().orc_rhs2(n, ppos, pvel, prho, pS, pm, ppar, ptg, nt, prow, col.ctypes.data_as(_pi32),
+    uarr = _f64(u) if u is not None else (None, None)
+    lib().orc_rhs2(n, ppos, pvel, prho, uarr[1], pS, pm, ppar, ptg, nt, prow, col.ctypes.data_as(_pi32),
                    acc.ctypes.data_as(_pd), drho.ctypes.data_as(_pd), dS.ctypes.data_as(_pd),
                    rs.ctypes.data_as(_pd), pnull(L), pnull(du), pnull(xv))
     out = dict(acc=acc, drho=drho, dS=dS, rho_sum=rs)
@@ -164,4 +178,5 @@ def rhs(pos, vel, rho, S, m, par, targets=None, csr=None, want_L: bool = True,
 
 def rhs_workload(w, targets=None, csr=None, want_L: bool = True, want_extra: bool = False):
     """``rhs`` on a ``workloads.Workload``."""
-    return rhs(w.pos, w.vel, w.rho, w.S, w.m, w.param_vector(), targets, csr, want_L, want_extra)
+    return rhs(w.pos, w.vel, w.rho, w.S, w.m, w.param_vector(), targets, csr, want_L, want_extra,
+               getattr(w, "u", None))

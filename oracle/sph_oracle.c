@@ -15,7 +15,8 @@
  *
  *   partners      section 3.5.2 (neighbour search): b != a, distance below h
  *   kernel        section 3.1.1 (kernel function): cubic B-spline, support h, D = 3
- *   pressure      section 2.5.1 (liquid equation of state), optional cut-off
+ *   pressure      section 2.5.1 (liquid equation of state), optional cut-off;
+ *                 section 2.5.2 (Murnaghan) and 2.5.3 (Tillotson) as alternatives
  *   limiter       section 2.6 (plastic material equations), von Mises f_Y
  *   density sum   eq. (density_by_kernel_sum), section 3.1.2
  *   continuity    eq. (continuity_equation_sph), section 3.1.2
@@ -59,13 +60,22 @@
  *   - XSPH: the printed weight 2 m_b / (rho_a rho_b) is not a velocity; the
  *     weight is 2 m_b / (rho_a + rho_b) (the mean density of the pair, as in the
  *     method the section cites).
+ *   - equations of state: Murnaghan with K0 = rho0 c^2 (the liquid relation
+ *     c^2 = K0 / rho0) and the same tension cut-off as the liquid equation;
+ *     Tillotson with the compressed form for rho >= rho0 or u <= E_iv, the
+ *     expanded form for rho < rho0 and u >= E_cv, and in between the linear
+ *     interpolation in u.  The sound speed of each particle (averaged over the
+ *     pair in Pi) is the thermodynamic one, c^2 = dp/drho|u + p/rho^2 dp/du|rho
+ *     (floored at 0); for the liquid equation it is c.
  *
  * Layout: structure of arrays.  pos and vel are (3, n) row-major (x row, y row,
  * z row); S is (6, n) in the order xx, yy, zz, xy, xz, yz; outputs follow the
  * same layout with the target count nt in place of n; L is (9, nt) row-major
  * over (alpha, beta) with L^{alpha beta} = dv^alpha / dx^beta.
  * par = {h, rho0, c, mu, Y0, alpha, beta, eps_v, rho_cut, correction, eps_s, n_s,
- *        dmpd, xsph}.
+ *        dmpd, xsph, eos (0 liquid, 1 Murnaghan, 2 Tillotson), n_M, a_T, b_T, A_T,
+ *        B_T, E0_T, alpha_T, beta_T, E_iv, E_cv}; u (specific internal energy) is
+ *        an input of the Tillotson equation (NULL = 0).
  */
 #include <math.h>
 #include <stdint.h>
@@ -76,7 +86,91 @@
 #endif
 
 enum { P_H, P_RHO0, P_C, P_MU, P_Y0, P_ALPHA, P_BETA, P_EPSV, P_RHOCUT, P_CORR,
-       P_EPSS, P_NS, P_DMPD, P_XSPH };
+       P_EPSS, P_NS, P_DMPD, P_XSPH, P_EOS, P_NM, P_AT, P_BT, P_AAT, P_BBT, P_E0T, P_ALT,
+       P_BET, P_EIV, P_ECV };
+
+/* Tillotson pressure of the compressed (cold) form, eq. (tillo1), and its partial
+ * derivatives in rho and u */
+static void tillotson1(const double *par, double rho, double u, double *p, double *dpr, double *dpu)
+{
+    const double rho0 = par[P_RHO0], a = par[P_AT], b = par[P_BT], A = par[P_AAT], B = par[P_BBT];
+    const double E0 = par[P_E0T];
+    const double eta = rho / rho0, chi = eta - 1.0;
+    const double w = 1.0 + u / (E0 * eta * eta);
+    const double dw_drho = -2.0 * u / (E0 * eta * eta * eta) / rho0;
+    const double dw_du = 1.0 / (E0 * eta * eta);
+    *p = (a + b / w) * rho * u + A * chi + B * chi * chi;
+    *dpr = (a + b / w) * u - b / (w * w) * dw_drho * rho * u + (A + 2.0 * B * chi) / rho0;
+    *dpu = (a + b / w) * rho - b / (w * w) * dw_du * rho * u;
+}
+
+/* Tillotson pressure of the expanded form, eq. (tillo2), and its partial derivatives */
+static void tillotson2(const double *par, double rho, double u, double *p, double *dpr, double *dpu)
+{
+    const double rho0 = par[P_RHO0], a = par[P_AT], b = par[P_BT], A = par[P_AAT];
+    const double E0 = par[P_E0T], al = par[P_ALT], be = par[P_BET];
+    const double eta = rho / rho0, chi = eta - 1.0;
+    const double w = 1.0 + u / (E0 * eta * eta);
+    const double dw_drho = -2.0 * u / (E0 * eta * eta * eta) / rho0;
+    const double dw_du = 1.0 / (E0 * eta * eta);
+    const double z = rho0 / rho - 1.0, dz = -rho0 / (rho * rho);
+    const double eb = exp(-be * z), ea = exp(-al * z * z);
+    const double inner = b * rho * u / w + A * chi * eb;
+    const double dinner_dr = b * u / w - b * rho * u / (w * w) * dw_drho + A / rho0 * eb
+                             + A * chi * eb * (-be * dz);
+    const double dinner_du = b * rho / w - b * rho * u / (w * w) * dw_du;
+    *p = a * rho * u + inner * ea;
+    *dpr = a * u + dinner_dr * ea + inner * ea * (-2.0 * al * z * dz);
+    *dpu = a * rho + dinner_du * ea;
+}
+
+/* Pressure and squared sound speed of one particle (sections 2.5.1 to 2.5.3) */
+static void eos(const double *par, double rho, double u, double *p_out, double *c2_out)
+{
+    const double c = par[P_C], rho0 = par[P_RHO0];
+    const int kind = (int)par[P_EOS];
+    double p, c2;
+    if (kind == 1) { /* Murnaghan, K0 = rho0 c^2 */
+        const double n = par[P_NM], K0 = rho0 * c * c, eta = rho / rho0;
+        p = K0 / n * (pow(eta, n) - 1.0);
+        c2 = K0 / rho0 * pow(eta, n - 1.0);
+        if (par[P_RHOCUT] > 0.0 && eta < par[P_RHOCUT])
+            p = 0.0;
+    } else if (kind == 2) { /* Tillotson */
+        double p1, r1, u1, p2, r2, u2;
+        const double Eiv = par[P_EIV], Ecv = par[P_ECV];
+        double dpr, dpu;
+        if (rho >= rho0 || u <= Eiv) {
+            tillotson1(par, rho, u, &p, &dpr, &dpu);
+        } else if (u >= Ecv) {
+            tillotson2(par, rho, u, &p, &dpr, &dpu);
+        } else {
+            tillotson1(par, rho, u, &p1, &r1, &u1);
+            tillotson2(par, rho, u, &p2, &r2, &u2);
+            const double t = (u - Eiv) / (Ecv - Eiv);
+            p = (1.0 - t) * p1 + t * p2;
+            dpr = (1.0 - t) * r1 + t * r2;
+            dpu = (1.0 - t) * u1 + t * u2 + (p2 - p1) / (Ecv - Eiv);
+        }
+        c2 = dpr + p / (rho * rho) * dpu;
+        if (c2 < 0.0)
+            c2 = 0.0;
+    } else { /* liquid */
+        p = c * c * (rho - rho0);
+        if (par[P_RHOCUT] > 0.0 && rho / rho0 < par[P_RHOCUT])
+            p = 0.0;
+        c2 = c * c;
+    }
+    *p_out = p;
+    *c2_out = c2;
+}
+
+void orc_eos(int64_t n, const double *rho, const double *u, const double *par, double *p,
+             double *c2)
+{
+    for (int64_t i = 0; i < n; ++i)
+        eos(par, rho[i], u ? u[i] : 0.0, &p[i], &c2[i]);
+}
 
 static const double PI_ = 3.14159265358979323846;
 
@@ -222,13 +316,14 @@ static void to_matrix(const double *s6, int64_t n, int64_t i, double M[3][3])
     M[1][2] = M[2][1] = s6[5 * n + i];
 }
 
-static void one_prepass(int64_t n, int64_t i, const double *rho, const double *S,
-                        const double *par, double *p_out, double *f_out, double sig[3][3])
+static void one_prepass(int64_t n, int64_t i, const double *rho, const double *u,
+                        const double *S, const double *par, double *p_out, double *f_out,
+                        double *cs_out, double sig[3][3])
 {
-    const double c = par[P_C], rho0 = par[P_RHO0], Y0 = par[P_Y0];
-    double p = c * c * (rho[i] - rho0);
-    if (par[P_RHOCUT] > 0.0 && rho[i] / rho0 < par[P_RHOCUT])
-        p = 0.0;
+    const double Y0 = par[P_Y0];
+    double p, c2;
+    eos(par, rho[i], u ? u[i] : 0.0, &p, &c2);
+    *cs_out = sqrt(c2);
     double Sm[3][3];
     to_matrix(S, n, i, Sm);
     double J2 = 0.0;
@@ -251,8 +346,8 @@ void orc_prepass(int64_t n, const double *rho, const double *S, const double *pa
 {
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
-        double sig[3][3];
-        one_prepass(n, i, rho, S, par, &p[i], &fy[i], sig);
+        double sig[3][3], cs;
+        one_prepass(n, i, rho, NULL, S, par, &p[i], &fy[i], &cs, sig);
         sigma[0 * n + i] = sig[0][0];
         sigma[1 * n + i] = sig[1][1];
         sigma[2 * n + i] = sig[2][2];
@@ -314,12 +409,12 @@ static int correction_tensor(const double M[3][3], double C[3][3])
 
 /* du (nullable): specific internal energy rate; xv (nullable, (3, nt)): dx/dt */
 void orc_rhs2(int64_t n, const double *pos, const double *vel, const double *rho,
-              const double *S, const double *m, const double *par,
+              const double *u, const double *S, const double *m, const double *par,
               const int64_t *targets, int64_t nt, const int64_t *row_ptr, const int32_t *col,
               double *acc, double *drho, double *dS, double *rho_sum, double *Lout,
               double *du, double *xv)
 {
-    const double h = par[P_H], c = par[P_C], mu = par[P_MU];
+    const double h = par[P_H], mu = par[P_MU];
     const double alpha = par[P_ALPHA], beta = par[P_BETA], eps_v = par[P_EPSV];
     const int corr = par[P_CORR] != 0.0;
     const double eps_s = par[P_EPSS], n_s = par[P_NS], xsph = par[P_XSPH];
@@ -334,8 +429,19 @@ void orc_rhs2(int64_t n, const double *pos, const double *vel, const double *rho
     /* per-particle stress (prepass) for every particle */
     double *p = (double *)malloc(sizeof(double) * (size_t)n);
     double *fy = (double *)malloc(sizeof(double) * (size_t)n);
+    double *cs = (double *)malloc(sizeof(double) * (size_t)n);
     double *sg = (double *)malloc(sizeof(double) * 6 * (size_t)n);
-    orc_prepass(n, rho, S, par, p, fy, sg);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double sig[3][3];
+        one_prepass(n, i, rho, u, S, par, &p[i], &fy[i], &cs[i], sig);
+        sg[0 * n + i] = sig[0][0];
+        sg[1 * n + i] = sig[1][1];
+        sg[2 * n + i] = sig[2][2];
+        sg[3 * n + i] = sig[0][1];
+        sg[4 * n + i] = sig[0][2];
+        sg[5 * n + i] = sig[1][2];
+    }
 
     double W0, dW0;
     orc_kernel(0.0, h, &W0, &dW0);
@@ -401,7 +507,8 @@ void orc_rhs2(int64_t n, const double *pos, const double *vel, const double *rho
             double Pi = 0.0;
             if (wab < 0.0) {
                 const double nu = h * wab / (r2 + eps_v * h * h);
-                Pi = (-alpha * c * nu + beta * nu * nu) / (0.5 * (ra + rb));
+                const double cbar = 0.5 * (cs[a] + cs[b]);
+                Pi = (-alpha * cbar * nu + beta * nu * nu) / (0.5 * (ra + rb));
             }
 
             /* artificial stress factor (zeta_a + zeta_b) f^n, zeta = -eps_s sigma / rho^2 in tension */
@@ -491,6 +598,7 @@ void orc_rhs2(int64_t n, const double *pos, const double *vel, const double *rho
     }
     free(p);
     free(fy);
+    free(cs);
     free(sg);
 }
 
@@ -499,6 +607,6 @@ void orc_rhs(int64_t n, const double *pos, const double *vel, const double *rho,
              const int64_t *targets, int64_t nt, const int64_t *row_ptr, const int32_t *col,
              double *acc, double *drho, double *dS, double *rho_sum, double *Lout)
 {
-    orc_rhs2(n, pos, vel, rho, S, m, par, targets, nt, row_ptr, col, acc, drho, dS, rho_sum,
-             Lout, NULL, NULL);
+    orc_rhs2(n, pos, vel, rho, NULL, S, m, par, targets, nt, row_ptr, col, acc, drho, dS,
+             rho_sum, Lout, NULL, NULL);
 }

@@ -37,11 +37,17 @@ MATERIAL = dict(
     eps_s=0.0,   # artificial stress off (0.2 where used)
     n_s=4.0,     # its exponent
     xsph=0.0,    # XSPH off (0.5 where used)
+    eos=0.0,     # 0 liquid, 1 Murnaghan, 2 Tillotson
+    n_M=4.0,     # Murnaghan exponent (K0 = rho0 c^2)
+    # Tillotson parameters of aluminium 6061 (section 4, impact cratering experiment)
+    a_T=0.5, b_T=1.63, A_T=75.2e9, B_T=65e9, E0_T=5e6, alpha_T=5.0, beta_T=5.0,
+    E_iv=3e6, E_cv=13.9e6,
 )
 
 # order of the scalar parameter vector shared by every consumer
 PARAM_ORDER = ("h", "rho0", "c", "mu", "Y0", "alpha", "beta", "eps_v", "rho_cut", "correction",
-               "eps_s", "n_s", "dmpd", "xsph")
+               "eps_s", "n_s", "dmpd", "xsph", "eos", "n_M", "a_T", "b_T", "A_T", "B_T", "E0_T",
+               "alpha_T", "beta_T", "E_iv", "E_cv")
 
 CONFIG_NAMES = {
     0: "cube16_fp64_4096",
