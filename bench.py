@@ -310,6 +310,14 @@ def main():
     forms["rhs_fp64_energy_artstress_xsph"] = {
         "ms": ms, "pairs_per_s": nnz0 / (ms * 1e-3),
         "particles_in_tension": int((sx.rho < w.params["rho0"]).sum())}
+    # Tillotson equation of state (aluminium constants) on the same spread densities with
+    # specific internal energies drawn over its cold, partial and full vaporisation ranges
+    su = P.ParticleState(sx.pos, sx.vel, sx.rho, sx.S, sx.m, 2e7 * torch.rand(
+        n, dtype=torch.float64, device=dev, generator=torch.Generator(dev).manual_seed(6)))
+    pt = dict(w.params, eos=2.0)
+    ot = P.api.new_deriv(n)
+    ms = median_ms(lambda: P.sph_rhs(g, su, pt, "fp64", out=ot, ws=ws_rhs), args.form_reps, torch)
+    forms["rhs_fp64_tillotson"] = {"ms": ms, "pairs_per_s": nnz0 / (ms * 1e-3)}
     forms["fp32comp_speedup_vs_fp64"] = forms["rhs_fp64"]["ms"] / forms["rhs_fp32comp"]["ms"]
     cg = {k: torch.randn_like(outs["fp64"][k]) for k in fields}
     ms = median_ms(lambda: P.sph_rhs_adjoint(g, st, w.params, cg, ws=ws_adj), args.form_reps, torch)

@@ -109,7 +109,9 @@ typedef struct {
                              the list instead of sweeping the cells */
 } sph_grid;
 
-/* Particle state (inputs), all device arrays of length n, user order. */
+/* Particle state (inputs), all device arrays of length n, user order.  u, the
+ * specific internal energy, is read by the Tillotson equation of state only and may
+ * be NULL (zero). */
 typedef struct {
     int64_t n;
     const double *x, *y, *z;
@@ -117,6 +119,7 @@ typedef struct {
     const double *rho;
     const double *sxx, *syy, *szz, *sxy, *sxz, *syz;
     const double *m;
+    const double *u;
 } sph_state;
 
 /* Material and numerical constants (SI units).  h: support radius; rho0, c:
@@ -131,10 +134,18 @@ typedef struct {
  * zeta = -eps_s sigma / rho^2 to the momentum bracket, scaled by
  * (W(r) / W(dmpd))^n_s, dmpd in (0, h) being the mean particle distance of the
  * initial distribution (FP64 forms only; the adjoints refuse it); xsph: XSPH
- * factor in [0, 1] (section 3.1.5), used by the dx/dt output. */
+ * factor in [0, 1] (section 3.1.5), used by the dx/dt output; eos: 0 the liquid
+ * equation above, 1 Murnaghan (section 2.5.2, exponent n_M, K0 = rho0 c^2), 2
+ * Tillotson (section 2.5.3, constants a_T .. E_cv; compressed form for rho >= rho0
+ * or u <= E_iv, expanded form for rho < rho0 and u >= E_cv, linear in u between).
+ * With eos 1 or 2 each particle's sound speed is the thermodynamic one,
+ * c^2 = dp/drho|u + p / rho^2 dp/du|rho (floored at 0), and Pi uses the pair's mean
+ * (FP64 forward only; the FP32 form, the adjoints and, for Tillotson, the leapfrog
+ * refuse them). */
 typedef struct {
     double h, rho0, c, mu, Y0, alpha, beta, eps_v, rho_cut, correction;
     double eps_s, n_s, dmpd, xsph;
+    double eos, n_M, a_T, b_T, A_T, B_T, E0_T, alpha_T, beta_T, E_iv, E_cv;
 } sph_params;
 
 /* Time derivatives (outputs) in user order.  rho_sum may be NULL.  du and

@@ -60,13 +60,14 @@ class Grid(C.Structure):
 class State(C.Structure):
     _fields_ = [("n", C.c_int64)] + [(k, _pd) for k in
                                      ("x", "y", "z", "vx", "vy", "vz", "rho", "sxx", "syy", "szz",
-                                      "sxy", "sxz", "syz", "m")]
+                                      "sxy", "sxz", "syz", "m", "u")]
 
 
 class Params(C.Structure):
     _fields_ = [(k, C.c_double) for k in
                 ("h", "rho0", "c", "mu", "Y0", "alpha", "beta", "eps_v", "rho_cut", "correction",
-                 "eps_s", "n_s", "dmpd", "xsph")]
+                 "eps_s", "n_s", "dmpd", "xsph", "eos", "n_M", "a_T", "b_T", "A_T", "B_T", "E0_T",
+                 "alpha_T", "beta_T", "E_iv", "E_cv")]
 
 
 _DERIV = ("ax", "ay", "az", "drho", "dsxx", "dsyy", "dszz", "dsxy", "dsxz", "dsyz", "rho_sum")

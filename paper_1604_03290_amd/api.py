@@ -17,9 +17,13 @@ from . import _lib as L
 
 F64 = torch.float64
 PARAM_ORDER = ("h", "rho0", "c", "mu", "Y0", "alpha", "beta", "eps_v", "rho_cut", "correction",
-               "eps_s", "n_s", "dmpd", "xsph")
-# parameters that may be left out of a dict (their neutral values)
-PARAM_DEFAULTS = {"correction": 0.0, "eps_s": 0.0, "n_s": 4.0, "dmpd": 0.0, "xsph": 0.0}
+               "eps_s", "n_s", "dmpd", "xsph", "eos", "n_M", "a_T", "b_T", "A_T", "B_T", "E0_T",
+               "alpha_T", "beta_T", "E_iv", "E_cv")
+# parameters that may be left out of a dict: neutral values, and for the equations of
+# state the liquid equation with aluminium 6061's Tillotson constants (section 4)
+PARAM_DEFAULTS = {"correction": 0.0, "eps_s": 0.0, "n_s": 4.0, "dmpd": 0.0, "xsph": 0.0,
+                  "eos": 0.0, "n_M": 4.0, "a_T": 0.5, "b_T": 1.63, "A_T": 75.2e9, "B_T": 65e9,
+                  "E0_T": 5e6, "alpha_T": 5.0, "beta_T": 5.0, "E_iv": 3e6, "E_cv": 13.9e6}
 DERIV_KEYS = ("acc", "drho", "dS", "rho_sum")
 
 
@@ -46,30 +50,35 @@ class ParticleState:
     rho: torch.Tensor  # (n,)
     S: torch.Tensor    # (6, n)
     m: torch.Tensor    # (n,)
+    u: torch.Tensor | None = None  # (n,) specific internal energy (Tillotson only)
 
     @property
     def n(self) -> int:
         return int(self.rho.shape[0])
 
     @classmethod
-    def from_arrays(cls, pos, vel, rho, S, m, device="cuda"):
+    def from_arrays(cls, pos, vel, rho, S, m, device="cuda", u=None):
         t = lambda a: torch.as_tensor(a, dtype=F64).to(device).contiguous()
-        return cls(t(pos), t(vel), t(rho), t(S), t(m))
+        return cls(t(pos), t(vel), t(rho), t(S), t(m), t(u) if u is not None else None)
 
     def clone(self) -> "ParticleState":
         return ParticleState(self.pos.clone(), self.vel.clone(), self.rho.clone(), self.S.clone(),
-                             self.m.clone())
+                             self.m.clone(), self.u.clone() if self.u is not None else None)
 
     def c_state(self) -> L.State:
         for t in (self.pos, self.vel, self.rho, self.S, self.m):
             _dev(t)
         n = self.n
         assert self.pos.shape == (3, n) and self.vel.shape == (3, n) and self.S.shape == (6, n)
+        if self.u is not None:
+            _dev(self.u)
+            assert self.u.shape == (n,)
         p, v, s = self.pos, self.vel, self.S
         return L.State(n, p[0].data_ptr(), p[1].data_ptr(), p[2].data_ptr(), v[0].data_ptr(),
                        v[1].data_ptr(), v[2].data_ptr(), self.rho.data_ptr(), s[0].data_ptr(),
                        s[1].data_ptr(), s[2].data_ptr(), s[3].data_ptr(), s[4].data_ptr(),
-                       s[5].data_ptr(), self.m.data_ptr())
+                       s[5].data_ptr(), self.m.data_ptr(),
+                       self.u.data_ptr() if self.u is not None else None)
 
 
 def params_struct(params) -> L.Params:

@@ -221,7 +221,7 @@ __device__ inline void adj_pair(const Consts &k, const AdjOwn &o, double d2, dou
 #pragma unroll
     for (int i = 0; i < 9; ++i) M[i] = Vb * o.Lbc[i] + o.Vc * Lbb[i];
     const double w = -(ux * rx + uy * ry + uz * rz);
-    const Visc vs = viscosity(k, d2, w, o.rc, rb_);
+    const Visc vs = viscosity(k, d2, w, o.rc, rb_, k.alpha_c);
     const double Pi = vs.Pi;
     const double B0 = o.Tc[0] + b4.x - Pi, B1 = o.Tc[1] + b4.y - Pi;
     const double B2 = o.Tc[2] + b5.x - Pi, B3 = o.Tc[3] + b5.y;
@@ -559,6 +559,8 @@ extern "C" int sph_rhs_adjoint(const sph_grid *grid, const sph_state *state,
     if (!dparams || !ws) return fail(SPH_ERR_INVALID_ARG, "null pointer");
     if (params->eps_s > 0.0)
         return fail(SPH_ERR_NOT_IMPLEMENTED, "adjoint with the artificial stress");
+    if (params->eos != 0.0)
+        return fail(SPH_ERR_NOT_IMPLEMENTED, "adjoint with the Murnaghan or Tillotson equation");
     const size_t need = adjoint_ws_bytes(grid->n);
     if (ws_bytes < need) return fail(SPH_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
     hipStream_t s = (hipStream_t)stream;

@@ -216,8 +216,8 @@ __global__ __launch_bounds__(kBlock) void k_rev_kick2(Fields13 Uk, Deriv10 Fk, F
         double cF[10];
         y0p = kick_adj_at(S, dS, gU, gF, i, h, Y0, accumulate, cF);
         const double mi = m[i];
-        write_rec(g, k, i, x1[i], x1[n + i], x1[2 * n + i], v[0], v[1], v[2], rho, S, mi, rec,
-                  status);
+        write_rec<false>(g, k, i, x1[i], x1[n + i], x1[2 * n + i], v[0], v[1], v[2], rho, S, mi,
+                         rec, status);
         double L[9];
 #pragma unroll
         for (int c = 0; c < 9; ++c) L[c] = L1[c * n + i];
@@ -322,6 +322,7 @@ sph_state state_struct(const Fields13 &f, const double *m, int64_t n) {
     s.sxz = f.p[11];
     s.syz = f.p[12];
     s.m = m;
+    s.u = nullptr;
     return s;
 }
 
@@ -367,6 +368,8 @@ int check_lf(const sph_grid *grid, const sph_state *s0, const sph_params *params
     if (steps < 1) return fail(SPH_ERR_INVALID_ARG, "steps must be >= 1");
     if (params->xsph != 0.0)
         return fail(SPH_ERR_NOT_IMPLEMENTED, "the leapfrog drifts with v (no XSPH)");
+    if (params->eos == 2.0)
+        return fail(SPH_ERR_NOT_IMPLEMENTED, "the leapfrog does not evolve u (Tillotson)");
     return SPH_OK;
 }
 
@@ -462,6 +465,8 @@ extern "C" int sph_leapfrog_adjoint(const sph_grid *grid, const sph_state *s0,
         return fail(SPH_ERR_INVALID_ARG, "null pointer");
     if (params->eps_s > 0.0)
         return fail(SPH_ERR_NOT_IMPLEMENTED, "adjoint with the artificial stress");
+    if (params->eos != 0.0)
+        return fail(SPH_ERR_NOT_IMPLEMENTED, "adjoint with the Murnaghan or Tillotson equation");
     const int64_t n = grid->n;
     const size_t need = leapfrog_adjoint_ws_bytes(n);
     if (ws_bytes < need) return fail(SPH_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);

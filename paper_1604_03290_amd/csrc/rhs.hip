@@ -34,7 +34,7 @@ __global__ __launch_bounds__(kBlock) void k_prepass(GridDev g, StateDev st, int6
     const int a = io_index(g, s);
     const double S[6] = {st.sxx[a], st.syy[a], st.szz[a], st.sxy[a], st.sxz[a], st.syz[a]};
     write_rec(g, k, s, st.x[a], st.y[a], st.z[a], st.vx[a], st.vy[a], st.vz[a], st.rho[a], S,
-              st.m[a], rec, status);
+              st.m[a], rec, status, st.u ? st.u[a] : 0.0);
 }
 
 // FP32 copies of the pair operands (positions stay FP64 for the exact test)
@@ -65,6 +65,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs64(GridDev g, int64_t n, Consts
     const double rho_a = p3.x;
     Acc64 acc;
     acc.rs = ra[7].x * k.Wn;  // own term m_a W(0)
+    const double c_a = ra[7].y;
     const double Ta[6] = {p4.x, p4.y, p5.x, p5.y, p6.x, p6.y};
     const bool tens_a = kExt && in_tension(k, rho_a);
     for_each_candidate(g, s, xa, ya, za, k.reach, [&](int t) {
@@ -76,7 +77,8 @@ __global__ __launch_bounds__(kBlock) void k_pairs64(GridDev g, int64_t n, Consts
         const double Tb[6] = {b4.x, b4.y, b5.x, b5.y, b6.x, b6.y};
         pair64<kCorr, kExt>(k, d2, xa - b0.x, ya - b0.y, za - b1.x, b1.y - vxa, b2.x - vya,
                             b2.y - vza, rho_a, b3.x, p4.x + b4.x, p4.y + b4.y, p5.x + b5.x,
-                            p5.y + b5.y, p6.x + b6.x, p6.y + b6.y, b7.x, b3.y, acc, Ta, Tb, tens_a);
+                            p5.y + b5.y, p6.x + b6.x, p6.y + b6.y, b7.x, b3.y, acc, Ta, Tb, tens_a,
+                            c_a, b7.y);
     });
     postpass(k, io_index(g, s), rho_a, acc.L, acc.ax, acc.ay, acc.az, acc.rs, st, out,
              kCorr ? acc.M : nullptr);
@@ -116,6 +118,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs64_list(GridDev g, int64_t n, C
     const double rho_a = p3.x;
     Acc64 acc;
     acc.rs = p7.x * k.Wn;  // own term m_a W(0)
+    const double c_a = p7.y;
     const double Ta[6] = {p4.x, p4.y, p5.x, p5.y, p6.x, p6.y};
     const bool tens_a = kExt && in_tension(k, rho_a);
     const char *recs = reinterpret_cast<const char *>(rec);
@@ -136,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs64_list(GridDev g, int64_t n, C
                 pair64<kCorr, kExt>(k, d2, xa - b0.x, ya - b0.y, za - b1.x, b1.y - vxa, b2.x - vya,
                                     b2.y - vza, rho_a, b3.x, p4.x + b4.x, p4.y + b4.y, p5.x + b5.x,
                                     p5.y + b5.y, p6.x + b6.x, p6.y + b6.y, b7.x, b3.y, acc, Ta, Tb,
-                                    tens_a);
+                                    tens_a, c_a, b7.y);
             }
         }
         wave_sync();
@@ -298,9 +301,11 @@ int check_state(const sph_grid *grid, const sph_state *st) {
 
 int check_params(const sph_grid *grid, const sph_params *pr) {
     if (!pr) return fail(SPH_ERR_INVALID_ARG, "params is NULL");
-    const double v[] = {pr->h,     pr->rho0,    pr->c,     pr->mu,   pr->Y0,   pr->alpha,
-                        pr->beta,  pr->eps_v,   pr->rho_cut, pr->correction, pr->eps_s, pr->n_s,
-                        pr->dmpd,  pr->xsph};
+    const double v[] = {pr->h,       pr->rho0,   pr->c,     pr->mu,      pr->Y0,    pr->alpha,
+                        pr->beta,    pr->eps_v,  pr->rho_cut, pr->correction, pr->eps_s, pr->n_s,
+                        pr->dmpd,    pr->xsph,   pr->eos,   pr->n_M,     pr->a_T,   pr->b_T,
+                        pr->A_T,     pr->B_T,    pr->E0_T,  pr->alpha_T, pr->beta_T, pr->E_iv,
+                        pr->E_cv};
     for (double q : v)
         if (!std::isfinite(q)) return fail(SPH_ERR_INVALID_ARG, "non-finite parameter");
     if (!(pr->h > 0.0) || !(pr->rho0 > 0.0) || !(pr->c > 0.0))
@@ -314,6 +319,11 @@ int check_params(const sph_grid *grid, const sph_params *pr) {
         return fail(SPH_ERR_INVALID_ARG, "eps_s >= 0 and 0 <= xsph <= 1 required");
     if (pr->eps_s > 0.0 && (!(pr->n_s > 0.0) || !(pr->dmpd > 0.0) || !(pr->dmpd < pr->h)))
         return fail(SPH_ERR_INVALID_ARG, "artificial stress needs n_s > 0 and 0 < dmpd < h");
+    if (pr->eos != 0.0 && pr->eos != 1.0 && pr->eos != 2.0)
+        return fail(SPH_ERR_INVALID_ARG, "eos must be 0 (liquid), 1 (Murnaghan) or 2 (Tillotson)");
+    if (pr->eos == 1.0 && !(pr->n_M > 0.0)) return fail(SPH_ERR_INVALID_ARG, "n_M must be positive");
+    if (pr->eos == 2.0 && (!(pr->E0_T > 0.0) || !(pr->E_cv > pr->E_iv) || pr->E_iv < 0.0))
+        return fail(SPH_ERR_INVALID_ARG, "Tillotson needs E0_T > 0 and 0 <= E_iv < E_cv");
     return SPH_OK;
 }
 
@@ -345,7 +355,7 @@ int rhs_launch(const sph_grid *grid, const sph_state *state, const sph_params *p
     OutDev od = out_dev(out);
     int rc;
     if (!rec_ready && (rc = prepass_launch(g, st, n, k, rec, c.status(), s))) return rc;
-    const bool ext = k.eps_s > 0.0 || od.du || od.dx;
+    const bool ext = k.eps_s > 0.0 || od.du || od.dx || k.eos != 0;
     if (precision == SPH_FP64) {
         TimedRegion t("pairs_fp64", s);
         const dim3 gb(blocks_for(n)), tb(kBlock);
@@ -370,7 +380,8 @@ int rhs_launch(const sph_grid *grid, const sph_state *state, const sph_params *p
     } else {
         if (ext)
             return fail(SPH_ERR_NOT_IMPLEMENTED,
-                        "artificial stress, energy and XSPH outputs are FP64 only");
+                        "artificial stress, energy and XSPH outputs and the Murnaghan and "
+                        "Tillotson equations are FP64 only");
         k_narrow<<<blocks_for(n), kBlock, 0, s>>>(rec, n, r32);
         SPH_LAUNCHED();
         TimedRegion t("pairs_fp32comp", s);

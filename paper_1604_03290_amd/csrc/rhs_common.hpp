@@ -16,6 +16,9 @@ struct Consts {
     // artificial stress (section 3.1.4): eps_s, exponent, 1 / w(dmpd / h); XSPH factor
     double eps_s, n_s, inv_wm, xsph;
     int n_int;  // the exponent when it is a whole number in 1..16 (powers by multiplication), else 0
+    // equation of state: 0 liquid, 1 Murnaghan (n_M, K0 = rho0 c^2), 2 Tillotson
+    int eos;
+    double alpha, c, n_M, K0, aT, bT, AT, BT, E0T, alT, beT, Eiv, Ecv;
 };
 
 // Kernel shape w(q) of section 3.1.1 (W = s/h^3 w), host side.
@@ -49,6 +52,20 @@ inline Consts make_consts(const sph_params &p, double delta) {
     k.inv_wm = p.eps_s > 0.0 ? 1.0 / kernel_shape(p.dmpd / p.h) : 0.0;
     k.xsph = p.xsph;
     k.n_int = (p.n_s >= 1.0 && p.n_s <= 16.0 && p.n_s == (double)(int)p.n_s) ? (int)p.n_s : 0;
+    k.eos = (int)p.eos;
+    k.alpha = p.alpha;
+    k.c = p.c;
+    k.n_M = p.n_M;
+    k.K0 = p.rho0 * p.c * p.c;
+    k.aT = p.a_T;
+    k.bT = p.b_T;
+    k.AT = p.A_T;
+    k.BT = p.B_T;
+    k.E0T = p.E0_T;
+    k.alT = p.alpha_T;
+    k.beT = p.beta_T;
+    k.Eiv = p.E_iv;
+    k.Ecv = p.E_cv;
     return k;
 }
 
@@ -63,11 +80,12 @@ __host__ __device__ inline Consts32 narrow(const Consts &k) {
 
 struct StateDev {
     const double *x, *y, *z, *vx, *vy, *vz, *rho, *sxx, *syy, *szz, *sxy, *sxz, *syz, *m;
+    const double *u;  // specific internal energy (Tillotson), null = 0
 };
 
 inline StateDev state_dev(const sph_state *s) {
-    return StateDev{s->x,   s->y,   s->z,   s->vx,  s->vy,  s->vz,  s->rho,
-                    s->sxx, s->syy, s->szz, s->sxy, s->sxz, s->syz, s->m};
+    return StateDev{s->x,   s->y,   s->z,   s->vx,  s->vy,  s->vz,  s->rho, s->sxx,
+                    s->syy, s->szz, s->sxy, s->sxz, s->syz, s->m,   s->u};
 }
 
 struct OutDev {
@@ -81,10 +99,12 @@ inline OutDev out_dev(const sph_deriv *o) {
 }
 
 // Slot-ordered operand records, one 128-byte record per slot:
-//   x y z vx | vy vz rho V | T0 T1 T2 T3 | T4 T5 m -
+//   x y z vx | vy vz rho V | T0 T1 T2 T3 | T4 T5 m c
 // with T = sigma / rho^2 (xx, yy, zz, xy, xz, yz) and V = m / rho.  A partner's
 // first seven 16-byte chunks carry everything its pair terms need (its mass being
-// V rho), which the adjoint's gathers use; the forward kernels read all eight.
+// V rho), which the adjoint's gathers use; the forward kernels read all eight (the
+// eighth also holds the sound speed c, which other equations of state than the
+// liquid one vary per particle).
 constexpr int kRec = 16;
 // FP32 record, 80 bytes per slot: FP64 position (for the exact partner test and
 // the differences) and the FP32 operands:
@@ -191,6 +211,71 @@ __device__ inline double pressure(const Consts &k, double rho) {
     return p;
 }
 
+// Tillotson pressure (section 2.5.3) of one form with its partial derivatives in rho
+// and u.  Compressed form: p = (a + b / w) rho u + A chi + B chi^2, w = 1 + u /
+// (E0 eta^2); expanded form: p = a rho u + (b rho u / w + A chi e^{-beta z})
+// e^{-alpha z^2}, z = rho0 / rho - 1.
+struct PDer {
+    double p, dr, du;
+};
+
+__device__ inline PDer tillotson_form(const Consts &k, double rho, double u, bool expanded) {
+    const double eta = rho / k.rho0, chi = eta - 1.0;
+    const double ie2 = 1.0 / (k.E0T * eta * eta);
+    const double w = 1.0 + u * ie2;
+    const double iw = 1.0 / w;
+    const double w_r = -2.0 * u * ie2 / rho;  // dw/drho
+    const double g = k.bT * rho * u * iw;     // b rho u / w
+    const double g_r = k.bT * u * iw - g * iw * w_r;
+    const double g_u = k.bT * rho * iw - g * iw * ie2;
+    PDer d;
+    if (!expanded) {
+        d.p = k.aT * rho * u + g + k.AT * chi + k.BT * chi * chi;
+        d.dr = k.aT * u + g_r + (k.AT + 2.0 * k.BT * chi) / k.rho0;
+        d.du = k.aT * rho + g_u;
+        return d;
+    }
+    const double z = k.rho0 / rho - 1.0, z_r = -k.rho0 / (rho * rho);
+    const double eb = exp(-k.beT * z), ea = exp(-k.alT * z * z);
+    const double q = g + k.AT * chi * eb;
+    const double q_r = g_r + k.AT * eb / k.rho0 - k.AT * chi * eb * k.beT * z_r;
+    d.p = k.aT * rho * u + q * ea;
+    d.dr = k.aT * u + q_r * ea - q * ea * 2.0 * k.alT * z * z_r;
+    d.du = k.aT * rho + g_u * ea;
+    return d;
+}
+
+// Pressure and sound speed of one particle: the liquid equation (above), Murnaghan
+// (section 2.5.2) or Tillotson (section 2.5.3, its regions joined linearly in u), the
+// sound speed from c^2 = dp/drho|u + p / rho^2 dp/du|rho, at least 0.
+__device__ inline void eos_pc(const Consts &k, double rho, double u, double &p, double &cs) {
+    if (k.eos == 1) {
+        const double eta = rho / k.rho0;
+        const double en1 = pow(eta, k.n_M - 1.0);
+        p = k.K0 / k.n_M * (en1 * eta - 1.0);
+        if (k.rho_cut > 0.0 && eta < k.rho_cut) p = 0.0;
+        cs = sqrt(k.K0 / k.rho0 * en1);
+    } else if (k.eos == 2) {
+        PDer d;
+        if (rho >= k.rho0 || u <= k.Eiv) {
+            d = tillotson_form(k, rho, u, false);
+        } else if (u >= k.Ecv) {
+            d = tillotson_form(k, rho, u, true);
+        } else {
+            const PDer a = tillotson_form(k, rho, u, false), b = tillotson_form(k, rho, u, true);
+            const double t = (u - k.Eiv) / (k.Ecv - k.Eiv);
+            d.p = (1.0 - t) * a.p + t * b.p;
+            d.dr = (1.0 - t) * a.dr + t * b.dr;
+            d.du = (1.0 - t) * a.du + t * b.du + (b.p - a.p) / (k.Ecv - k.Eiv);
+        }
+        p = d.p;
+        cs = sqrt(fmax(d.dr + d.p / (rho * rho) * d.du, 0.0));
+    } else {
+        p = pressure(k, rho);
+        cs = k.c;
+    }
+}
+
 // Second invariant J2 = S:S / 2 of a symmetric stress stored as six components.
 __device__ inline double j2_of(const double S[6]) {
     return 0.5 * (S[0] * S[0] + S[1] * S[1] + S[2] * S[2]) + (S[3] * S[3] + S[4] * S[4] + S[5] * S[5]);
@@ -206,14 +291,22 @@ __device__ inline double yield_factor(const Consts &k, const double S[6]) {
 // the particle's state; raises STALE_GRID when the particle left its cell (or its
 // list position) by more than skin / 2 and DOMAIN for a non-positive or
 // non-finite density.  The prepass and the leapfrog's fused passes write every
-// record through this one function.
+// record through this one function; kEos = false limits it to the liquid equation
+// (the adjoint's passes, which refuse the others).
+template <bool kEos = true>
 __device__ inline void write_rec(const GridDev &g, const Consts &k, int64_t s, double x, double y,
                                  double z, double vx, double vy, double vz, double rho,
                                  const double S[6], double m, double *__restrict__ rec,
-                                 int32_t *__restrict__ status) {
+                                 int32_t *__restrict__ status, double u = 0.0) {
     if (!within_cell(g, (int)s, x, y, z)) raise_flag(status, SPH_ERR_STALE_GRID);
     if (!(rho > 0.0) || !isfinite(rho)) raise_flag(status, SPH_ERR_DOMAIN);
-    const double p = pressure(k, rho);
+    double p, cs;
+    if constexpr (kEos) {
+        eos_pc(k, rho, u, p, cs);
+    } else {
+        p = pressure(k, rho);
+        cs = k.c;
+    }
     const double f = yield_factor(k, S);
     const double ir2 = 1.0 / (rho * rho);
     double2 *r = reinterpret_cast<double2 *>(rec + s * kRec);
@@ -224,7 +317,7 @@ __device__ inline void write_rec(const GridDev &g, const Consts &k, int64_t s, d
     r[4] = make_double2((f * S[0] - p) * ir2, (f * S[1] - p) * ir2);
     r[5] = make_double2((f * S[2] - p) * ir2, f * S[3] * ir2);
     r[6] = make_double2(f * S[4] * ir2, f * S[5] * ir2);
-    r[7] = make_double2(m, 0.0);
+    r[7] = make_double2(m, cs);
 }
 
 // 1/sqrt(x): hardware estimate refined by two Newton steps y <- y (3 - x y^2) / 2
@@ -276,14 +369,15 @@ struct Visc {
     double Pi, nu, invD, coef;
 };
 
-__device__ inline Visc viscosity(const Consts &k, double d2, double w, double ra, double rb) {
+__device__ inline Visc viscosity(const Consts &k, double d2, double w, double ra, double rb,
+                                 double alpha_c) {
     Visc v;
     const double D = d2 + k.epsh2, S = ra + rb;
     const double inv = rcp64(D * S);
     v.invD = S * inv;        // 1 / D
     v.coef = 2.0 * D * inv;  // 2 / (rho_a + rho_b)
     v.nu = k.h * w * v.invD;
-    const double Pi = (-k.alpha_c * v.nu + k.beta * v.nu * v.nu) * v.coef;
+    const double Pi = (-alpha_c * v.nu + k.beta * v.nu * v.nu) * v.coef;
     v.Pi = w < 0.0 ? Pi : 0.0;
     return v;
 }
@@ -321,7 +415,7 @@ __device__ inline void pair64(const Consts &k, double d2, double rx, double ry, 
                               double Bxx, double Byy, double Bzz, double Bxy, double Bxz,
                               double Byz, double mb, double Vb, Acc64 &a,
                               const double *Ta = nullptr, const double *Tb = nullptr,
-                              bool tens_a = false) {
+                              bool tens_a = false, double ca = 0.0, double cb = 0.0) {
     const double ir = rsqrt64(d2);
     const KernelPieces kp = kernel_pieces(k, d2, ir);
     const double F = k.Fn * kp.f;
@@ -338,7 +432,8 @@ __device__ inline void pair64(const Consts &k, double d2, double rx, double ry, 
     a.L[7] = fma(tz, gy, a.L[7]);
     a.L[8] = fma(tz, gz, a.L[8]);
     const double wab = -(dvx * rx + dvy * ry + dvz * rz);
-    const double Pi = viscosity(k, d2, wab, ra, rb).Pi;
+    // the pair's mean sound speed (section 3.1.3); one value for the liquid equation
+    const double Pi = viscosity(k, d2, wab, ra, rb, kExt ? k.alpha * (0.5 * (ca + cb)) : k.alpha_c).Pi;
     const double bxx = Bxx - Pi, byy = Byy - Pi, bzz = Bzz - Pi;
     const double qx = bxx * gx + Bxy * gy + Bxz * gz;
     const double qy = Bxy * gx + byy * gy + Byz * gz;

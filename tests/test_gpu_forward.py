@@ -379,3 +379,47 @@ def test_two_spheres_extra_terms_subsample():
     bad = {k: v for k, v in err.items() if not v <= TOL["fp64"]}
     assert not bad, bad
     assert max(extra_err(got, ref, w.vel[:, idx]).values()) <= TOL["fp64"]
+
+
+# ---- Murnaghan and Tillotson equations of state (sections 2.5.2, 2.5.3) ----
+
+def eos_variant(kind, seed=21):
+    w = W.cube(12, 0.1, seed=seed, eos=float(kind), alpha=1.0, beta=1.0)
+    rng = np.random.default_rng(seed)
+    w.rho = w.params["rho0"] * rng.uniform(0.85, 1.15, w.n)
+    if kind == 2:
+        w.u = rng.uniform(0.0, 2e7, w.n)  # cold, partly and fully vaporised regions
+    return w
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+@pytest.mark.parametrize("path", ["cells1", "pairs2_skin"])
+def test_rhs_equations_of_state_match_oracle(kind, path):
+    w = eos_variant(kind)
+    ref = native.rhs_workload(w)
+    st = P.ParticleState.from_arrays(w.pos, w.vel, w.rho, w.S, w.m, u=getattr(w, "u", None))
+    pth = PATHS[path]
+    g = P.sph_build_cells(st.pos, w.h, skin=pth.get("skin", 0.0), cells_per_h=pth.get("cells_per_h", 1),
+                          pairs=pth.get("pairs", False))
+    out = P.sph_rhs(g, st, w.params, "fp64")
+    assert P.workspace_status(out["_ws"]) == 0
+    got = {k: v.cpu().numpy() for k, v in out.items() if k != "_ws"}
+    err = normwise(got, ref, w.rho)
+    bad = {k: v for k, v in err.items() if not v <= TOL["fp64"]}
+    assert not bad, bad
+    w.params["eos"] = 0.0  # the equations differ from the liquid one on this state
+    plain = native.rhs_workload(w)
+    assert max(normwise(plain, ref, w.rho).values()) > 1e-3
+
+
+def test_equations_of_state_refused_where_not_built():
+    w = eos_variant(2)
+    st = P.ParticleState.from_arrays(w.pos, w.vel, w.rho, w.S, w.m, u=w.u)
+    g = P.sph_build_cells(st.pos, w.h)
+    for call in (lambda: P.sph_rhs(g, st, w.params, "fp32comp"),
+                 lambda: P.sph_leapfrog(g, st, w.params, w.dt, 2),
+                 lambda: P.sph_rhs_adjoint(g, st, w.params,
+                                           {"acc": torch.ones(3, w.n, dtype=torch.float64).cuda()})):
+        with pytest.raises(L.SphError) as e:
+            call()
+        assert e.value.code == L.SPH_ERR_NOT_IMPLEMENTED
