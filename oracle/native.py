@@ -39,8 +39,9 @@ def lib():
         L.orc_prepass.argtypes = [_i64, _pd, _pd, _pd, _pd, _pd, _pd]
         L.orc_rhs.argtypes = [_i64, _pd, _pd, _pd, _pd, _pd, _pd, _pi64, _i64, _pi64, _pi32,
                               _pd, _pd, _pd, _pd, _pd]
-        L.orc_rhs2.argtypes = [_i64, _pd, _pd, _pd, _pd, _pd, _pd, _pd, _pi64, _i64, _pi64,
-                               _pi32, _pd, _pd, _pd, _pd, _pd, _pd, _pd]
+        L.orc_rhs2.argtypes = [_i64, _pd, _pd, _pd, _pd, _pd, _pd, _pd, _pd, _pi64, _i64,
+                               _pi64, _pi32, _pd, _pd, _pd, _pd, _pd, _pd, _pd]
+        L.orc_prepass2.argtypes = [_i64, _pd, _pd, _pd, _pd, _pd, _pd, _pd, _pd, _pd]
         L.orc_eos.argtypes = [_i64, _pd, _pd, _pd, _pd, _pd]
         _lib = L
     return _lib
@@ -116,6 +117,21 @@ def prepass(rho, S, par):
     return dict(p=p, fy=f, sigma=sig)
 
 
+def prepass2(rho, S, par, u=None, d=None):
+    """Pressure, limiter factor, sound speed and the (damaged) stress sigma (6, n)."""
+    rho, prho = _f64(rho)
+    S, pS = _f64(S)
+    par, ppar = _f64(par)
+    pu = _f64(u)[1] if u is not None else None
+    pd_ = _f64(d)[1] if d is not None else None
+    n = rho.shape[0]
+    p, f, cs = np.zeros(n), np.zeros(n), np.zeros(n)
+    sig = np.zeros((6, n))
+    lib().orc_prepass2(n, prho, pu, pd_, pS, ppar, p.ctypes.data_as(_pd), f.ctypes.data_as(_pd),
+                       cs.ctypes.data_as(_pd), sig.ctypes.data_as(_pd))
+    return dict(p=p, fy=f, cs=cs, sigma=sig)
+
+
 def eos(rho, par, u=None):
     """(pressure, squared sound speed) of every particle (sections 2.5.1 to 2.5.3)."""
     rho, prho = _f64(rho)
@@ -128,14 +144,14 @@ def eos(rho, par, u=None):
 
 
 def rhs(pos, vel, rho, S, m, par, targets=None, csr=None, want_L: bool = True,
-        want_extra: bool = False, u=None):
+        want_extra: bool = False, u=None, d=None):
     """Right-hand side for ``targets`` (all particles when None).
 
     ``csr`` = (row_ptr, col) partner lists of the targets; computed by brute
     force when omitted.  Returns dict acc (3, nt), drho (nt), dS (6, nt),
     rho_sum (nt) and L (9, nt); with ``want_extra`` also du (nt), the specific
     internal energy rate, and xv (3, nt), dx/dt with XSPH.  ``u``: specific internal
-    energy (the Tillotson equation's second input; zero when None).
+    energy (the Tillotson equation's second input; zero when None); ``d``: damage.
     """
     pos, ppos = _f64(pos)
     vel, pvel = _f64(vel)
@@ -164,7 +180,9 @@ def rhs(pos, vel, rho, S, m, par, targets=None, csr=None, want_L: bool = True,
     xv = np.zeros((3, nt)) if want_extra else None
     pnull = lambda a: a.ctypes.data_as(_pd) if a is not None else None
     uarr = _f64(u) if u is not None else (None, None)
-    lib().orc_rhs2(n, ppos, pvel, prho, uarr[1], pS, pm, ppar, ptg, nt, prow, col.ctypes.data_as(_pi32),
+    darr = _f64(d) if d is not None else (None, None)
+    lib().orc_rhs2(n, ppos, pvel, prho, uarr[1], darr[1], pS, pm, ppar, ptg, nt, prow,
+                   col.ctypes.data_as(_pi32),
                    acc.ctypes.data_as(_pd), drho.ctypes.data_as(_pd), dS.ctypes.data_as(_pd),
                    rs.ctypes.data_as(_pd), pnull(L), pnull(du), pnull(xv))
     out = dict(acc=acc, drho=drho, dS=dS, rho_sum=rs)
@@ -179,4 +197,4 @@ def rhs(pos, vel, rho, S, m, par, targets=None, csr=None, want_L: bool = True,
 def rhs_workload(w, targets=None, csr=None, want_L: bool = True, want_extra: bool = False):
     """``rhs`` on a ``workloads.Workload``."""
     return rhs(w.pos, w.vel, w.rho, w.S, w.m, w.param_vector(), targets, csr, want_L, want_extra,
-               getattr(w, "u", None))
+               getattr(w, "u", None), getattr(w, "d", None))

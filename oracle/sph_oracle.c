@@ -60,6 +60,9 @@
  *   - XSPH: the printed weight 2 m_b / (rho_a rho_b) is not a velocity; the
  *     weight is 2 m_b / (rho_a + rho_b) (the mean density of the pair, as in the
  *     method the section cites).
+ *   - damage (section 2.7): sigma_d = -p^ I + (1 - d) f_Y S with p^ = p for p >= 0
+ *     and (1 - d) p for p < 0; the damaged stress enters the momentum equation,
+ *     the stress rate still evolves S.
  *   - equations of state: Murnaghan with K0 = rho0 c^2 (the liquid relation
  *     c^2 = K0 / rho0) and the same tension cut-off as the liquid equation;
  *     Tillotson with the compressed form for rho >= rho0 or u <= E_iv, the
@@ -75,7 +78,8 @@
  * par = {h, rho0, c, mu, Y0, alpha, beta, eps_v, rho_cut, correction, eps_s, n_s,
  *        dmpd, xsph, eos (0 liquid, 1 Murnaghan, 2 Tillotson), n_M, a_T, b_T, A_T,
  *        B_T, E0_T, alpha_T, beta_T, E_iv, E_cv}; u (specific internal energy) is
- *        an input of the Tillotson equation (NULL = 0).
+ *        an input of the Tillotson equation (NULL = 0); dmg, the damage d in
+ *        [0, 1], scales the stress (NULL = intact).
  */
 #include <math.h>
 #include <stdint.h>
@@ -317,8 +321,8 @@ static void to_matrix(const double *s6, int64_t n, int64_t i, double M[3][3])
 }
 
 static void one_prepass(int64_t n, int64_t i, const double *rho, const double *u,
-                        const double *S, const double *par, double *p_out, double *f_out,
-                        double *cs_out, double sig[3][3])
+                        const double *dmg, const double *S, const double *par, double *p_out,
+                        double *f_out, double *cs_out, double sig[3][3])
 {
     const double Y0 = par[P_Y0];
     double p, c2;
@@ -334,9 +338,11 @@ static void one_prepass(int64_t n, int64_t i, const double *rho, const double *u
     double f = 1.0;
     if (3.0 * J2 > Y0 * Y0)
         f = Y0 * Y0 / (3.0 * J2);
+    const double d = dmg ? dmg[i] : 0.0;
+    const double ph = p >= 0.0 ? p : (1.0 - d) * p; /* damage relieves tension only */
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b)
-            sig[a][b] = f * Sm[a][b] - (a == b ? p : 0.0);
+            sig[a][b] = (1.0 - d) * f * Sm[a][b] - (a == b ? ph : 0.0);
     *p_out = p;
     *f_out = f;
 }
@@ -347,7 +353,25 @@ void orc_prepass(int64_t n, const double *rho, const double *S, const double *pa
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         double sig[3][3], cs;
-        one_prepass(n, i, rho, NULL, S, par, &p[i], &fy[i], &cs, sig);
+        one_prepass(n, i, rho, NULL, NULL, S, par, &p[i], &fy[i], &cs, sig);
+        sigma[0 * n + i] = sig[0][0];
+        sigma[1 * n + i] = sig[1][1];
+        sigma[2 * n + i] = sig[2][2];
+        sigma[3 * n + i] = sig[0][1];
+        sigma[4 * n + i] = sig[0][2];
+        sigma[5 * n + i] = sig[1][2];
+    }
+}
+
+/* prepass with the specific internal energy and the damage (NULL = 0) */
+void orc_prepass2(int64_t n, const double *rho, const double *u, const double *dmg,
+                  const double *S, const double *par, double *p, double *fy, double *cs,
+                  double *sigma)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double sig[3][3];
+        one_prepass(n, i, rho, u, dmg, S, par, &p[i], &fy[i], &cs[i], sig);
         sigma[0 * n + i] = sig[0][0];
         sigma[1 * n + i] = sig[1][1];
         sigma[2 * n + i] = sig[2][2];
@@ -409,7 +433,8 @@ static int correction_tensor(const double M[3][3], double C[3][3])
 
 /* du (nullable): specific internal energy rate; xv (nullable, (3, nt)): dx/dt */
 void orc_rhs2(int64_t n, const double *pos, const double *vel, const double *rho,
-              const double *u, const double *S, const double *m, const double *par,
+              const double *u, const double *dmg, const double *S, const double *m,
+              const double *par,
               const int64_t *targets, int64_t nt, const int64_t *row_ptr, const int32_t *col,
               double *acc, double *drho, double *dS, double *rho_sum, double *Lout,
               double *du, double *xv)
@@ -434,7 +459,7 @@ void orc_rhs2(int64_t n, const double *pos, const double *vel, const double *rho
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         double sig[3][3];
-        one_prepass(n, i, rho, u, S, par, &p[i], &fy[i], &cs[i], sig);
+        one_prepass(n, i, rho, u, dmg, S, par, &p[i], &fy[i], &cs[i], sig);
         sg[0 * n + i] = sig[0][0];
         sg[1 * n + i] = sig[1][1];
         sg[2 * n + i] = sig[2][2];
@@ -607,6 +632,6 @@ void orc_rhs(int64_t n, const double *pos, const double *vel, const double *rho,
              const int64_t *targets, int64_t nt, const int64_t *row_ptr, const int32_t *col,
              double *acc, double *drho, double *dS, double *rho_sum, double *Lout)
 {
-    orc_rhs2(n, pos, vel, rho, NULL, S, m, par, targets, nt, row_ptr, col, acc, drho, dS,
+    orc_rhs2(n, pos, vel, rho, NULL, NULL, S, m, par, targets, nt, row_ptr, col, acc, drho, dS,
              rho_sum, Lout, NULL, NULL);
 }

@@ -15,5 +15,6 @@ from .generate import (  # noqa: F401
     lattice_cube,
     random_state,
     subsample,
+    flaws,
     CONFIG_NAMES,
 )

@@ -307,6 +307,29 @@ def two_particles(xa, xb, va=(0, 0, 0), vb=(0, 0, 0), rho=(2700.0, 2700.0), S=No
                     np.array(m, dtype=np.float64), float(h), float(h) / H_OVER_DX, p)
 
 
+def flaws(n: int, volume: float, k_w: float, m_w: float, seed: int):
+    """Activation threshold strains of the damage model's preprocessing (the damage model
+    of section 3): flaw j = 1, 2, ... goes to a particle drawn uniformly at random with
+    threshold (j / (k_w volume))^(1 / m_w) (Weibull parameters k_w, m_w), until every
+    particle holds at least one.  Returns (flaw_ptr int64 [n + 1], flaw_eps [total]), each
+    particle's thresholds ascending."""
+    rng = np.random.default_rng(seed)
+    draws = max(64, int(n * (np.log(n) + 12.0)))
+    owner = rng.integers(0, n, draws)
+    seen, first = np.unique(owner, return_index=True)
+    if seen.size < n:
+        raise RuntimeError("too few draws to give every particle a flaw")
+    total = int(first.max()) + 1
+    owner = owner[:total]
+    j = np.arange(1, total + 1, dtype=np.float64)
+    eps = (j / (k_w * volume)) ** (1.0 / m_w)
+    order = np.argsort(owner, kind="stable")
+    counts = np.bincount(owner, minlength=n)
+    ptr = np.zeros(n + 1, dtype=np.int64)
+    ptr[1:] = np.cumsum(counts)
+    return ptr, np.ascontiguousarray(eps[order])
+
+
 def subsample(n: int, k: int, seed: int) -> np.ndarray:
     """k distinct particle indices drawn uniformly without replacement, ascending."""
     rng = np.random.default_rng(seed)
