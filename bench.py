@@ -318,6 +318,18 @@ def main():
     ot = P.api.new_deriv(n)
     ms = median_ms(lambda: P.sph_rhs(g, su, pt, "fp64", out=ot, ws=ws_rhs), args.form_reps, torch)
     forms["rhs_fp64_tillotson"] = {"ms": ms, "pairs_per_s": nnz0 / (ms * 1e-3)}
+    # Grady-Kipp damage on the spread densities: damage uniform in [0, 1], flaws of
+    # basalt's Weibull law (k = 1e61 m^-3, m = 16) over the bodies' volume, about
+    # N ln N of them; the damaged stress in the pair loop and the damage rates
+    import workloads as W
+    fptr, feps = W.flaws(n, float(np.sum(w.m) / w.params["rho0"]), 1e61, 16.0, 7)
+    sd = P.ParticleState(sx.pos, sx.vel, sx.rho, sx.S, sx.m, None, torch.rand(
+        n, dtype=torch.float64, device=dev, generator=torch.Generator(dev).manual_seed(8)),
+        torch.as_tensor(fptr).to(dev), torch.as_tensor(feps).to(dev))
+    od = P.api.new_deriv(n, damage=True)
+    ms = median_ms(lambda: P.sph_rhs(g, sd, w.params, "fp64", out=od, ws=ws_rhs), args.form_reps, torch)
+    forms["rhs_fp64_damage"] = {"ms": ms, "pairs_per_s": nnz0 / (ms * 1e-3), "flaws": int(fptr[-1]),
+                                "particles_with_active_flaws": int((od["n_act"] > 0).sum())}
     forms["fp32comp_speedup_vs_fp64"] = forms["rhs_fp64"]["ms"] / forms["rhs_fp32comp"]["ms"]
     cg = {k: torch.randn_like(outs["fp64"][k]) for k in fields}
     ms = median_ms(lambda: P.sph_rhs_adjoint(g, st, w.params, cg, ws=ws_adj), args.form_reps, torch)

@@ -111,7 +111,14 @@ typedef struct {
 
 /* Particle state (inputs), all device arrays of length n, user order.  u, the
  * specific internal energy, is read by the Tillotson equation of state only and may
- * be NULL (zero). */
+ * be NULL (zero).  d, the damage of the Grady-Kipp model (section 2.7, in [0, 1]),
+ * may be NULL (intact material); with it the stress that enters the momentum
+ * equation is sigma_d = -p^ I + (1 - d) f_Y S, p^ = p for p >= 0 and (1 - d) p
+ * below.  flaw_ptr (int64, n + 1 entries, flaw_ptr[0] = 0, non-decreasing) and
+ * flaw_eps (flaw_ptr[n] entries) list each particle's activation threshold
+ * strains, ascending within a particle (section 3.2); they are read only for the
+ * damage-rate outputs of sph_deriv and may be NULL otherwise.  The adjoints and the
+ * leapfrog refuse damage. */
 typedef struct {
     int64_t n;
     const double *x, *y, *z;
@@ -120,6 +127,9 @@ typedef struct {
     const double *sxx, *syy, *szz, *sxy, *sxz, *syz;
     const double *m;
     const double *u;
+    const double *d;
+    const int64_t *flaw_ptr;
+    const double *flaw_eps;
 } sph_state;
 
 /* Material and numerical constants (SI units).  h: support radius; rho0, c:
@@ -153,7 +163,15 @@ typedef struct {
  * (eq. energy_sph; the bracket holds -Pi* I as in the momentum equation, without
  * the artificial stress) and the particle velocity dx/dt with XSPH (section
  * 3.1.5: v_a + xsph sum_b 2 m_b / (rho_a + rho_b) (v_b - v_a) W_ab; = v_a when
- * xsph = 0); FP64 only. */
+ * xsph = 0); FP64 only.  dd3 and n_act (both NULL, or neither; the state's flaw
+ * lists are then required) request the damage model's rate d(d^(1/3))/dt and the
+ * number of activated flaws (section 3.2): with sigma_max the largest principal
+ * value of sigma_d, the strain eps = sigma_max / ((1 - d) E) (infinite at d = 1),
+ * E = 9 K mu / (3 K + mu), K = rho0 c^2 (A_T for Tillotson); n_act counts the
+ * particle's thresholds below eps; dd3 = n_act c_g / R_s with
+ * c_g = 0.4 sqrt((K + 4/3 (1 - d) mu) / rho) and R_s = (3 m / (4 pi rho))^(1/3),
+ * and 0 once d n_tot >= n_act (the limiter d <= n_act / n_tot, n_tot the
+ * particle's flaw count). */
 typedef struct {
     double *ax, *ay, *az;
     double *drho;
@@ -161,6 +179,8 @@ typedef struct {
     double *rho_sum;
     double *du;
     double *dx, *dy, *dz;
+    double *dd3;
+    int32_t *n_act;
 } sph_deriv;
 
 /* Cotangents of the derivatives (inputs of the adjoint), user order.  A NULL
@@ -263,7 +283,8 @@ int sph_neighbours(const sph_grid *grid, const double *x, const double *y, const
 /* Right-hand side for every particle, with the partner set re-derived from
  * the grid at the current positions:
  *   prepass   p = c^2 (rho - rho0) (section 2.5.1); f_Y = min(Y0^2 / (3 J2), 1),
- *             J2 = S:S / 2 (section 2.6); sigma = -p I + f_Y S (section 2.2)
+ *             J2 = S:S / 2 (section 2.6); sigma = -p I + f_Y S (section 2.2), or
+ *             sigma_d with damage (section 2.7), and the damage rate outputs
  *   pairs     rho_sum_a = m_a W(0) + sum_b m_b W_ab  (eq. density_by_kernel_sum)
  *             L_a = sum_b (m_b/rho_b) (v_b - v_a) (x) grad_a W_ab  (section 3.1.6)
  *             a_a = sum_b m_b [sigma_a/rho_a^2 + sigma_b/rho_b^2 - Pi*_ab I] grad_a W_ab

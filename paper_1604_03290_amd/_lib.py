@@ -60,7 +60,8 @@ class Grid(C.Structure):
 class State(C.Structure):
     _fields_ = [("n", C.c_int64)] + [(k, _pd) for k in
                                      ("x", "y", "z", "vx", "vy", "vz", "rho", "sxx", "syy", "szz",
-                                      "sxy", "sxz", "syz", "m", "u")]
+                                      "sxy", "sxz", "syz", "m", "u", "d", "flaw_ptr",
+                                      "flaw_eps")]
 
 
 class Params(C.Structure):
@@ -75,7 +76,7 @@ _FIELDS = ("x", "y", "z", "vx", "vy", "vz", "rho", "sxx", "syy", "szz", "sxy", "
 
 
 class Deriv(C.Structure):
-    _fields_ = [(k, _pd) for k in _DERIV + ("du", "dx", "dy", "dz")]
+    _fields_ = [(k, _pd) for k in _DERIV + ("du", "dx", "dy", "dz", "dd3", "n_act")]
 
 
 class DerivCot(C.Structure):

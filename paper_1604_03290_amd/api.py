@@ -51,34 +51,48 @@ class ParticleState:
     S: torch.Tensor    # (6, n)
     m: torch.Tensor    # (n,)
     u: torch.Tensor | None = None  # (n,) specific internal energy (Tillotson only)
+    d: torch.Tensor | None = None  # (n,) damage
+    flaw_ptr: torch.Tensor | None = None  # (n + 1,) int64 offsets of the flaw lists
+    flaw_eps: torch.Tensor | None = None  # (flaw_ptr[n],) activation thresholds
 
     @property
     def n(self) -> int:
         return int(self.rho.shape[0])
 
     @classmethod
-    def from_arrays(cls, pos, vel, rho, S, m, device="cuda", u=None):
-        t = lambda a: torch.as_tensor(a, dtype=F64).to(device).contiguous()
-        return cls(t(pos), t(vel), t(rho), t(S), t(m), t(u) if u is not None else None)
+    def from_arrays(cls, pos, vel, rho, S, m, device="cuda", u=None, d=None, flaws=None):
+        t = lambda a: torch.as_tensor(a, dtype=F64).to(device).contiguous() if a is not None else None
+        fp = fe = None
+        if flaws is not None:
+            fp = torch.as_tensor(flaws[0], dtype=torch.int64).to(device).contiguous()
+            fe = t(flaws[1])
+        return cls(t(pos), t(vel), t(rho), t(S), t(m), t(u), t(d), fp, fe)
 
     def clone(self) -> "ParticleState":
+        c = lambda t: t.clone() if t is not None else None
         return ParticleState(self.pos.clone(), self.vel.clone(), self.rho.clone(), self.S.clone(),
-                             self.m.clone(), self.u.clone() if self.u is not None else None)
+                             self.m.clone(), c(self.u), c(self.d), c(self.flaw_ptr), c(self.flaw_eps))
 
     def c_state(self) -> L.State:
         for t in (self.pos, self.vel, self.rho, self.S, self.m):
             _dev(t)
         n = self.n
         assert self.pos.shape == (3, n) and self.vel.shape == (3, n) and self.S.shape == (6, n)
-        if self.u is not None:
-            _dev(self.u)
-            assert self.u.shape == (n,)
+        for t in (self.u, self.d):
+            if t is not None:
+                _dev(t)
+                assert t.shape == (n,)
+        if self.flaw_ptr is not None:
+            _dev(self.flaw_ptr, torch.int64)
+            _dev(self.flaw_eps)
+            assert self.flaw_ptr.shape == (n + 1,)
         p, v, s = self.pos, self.vel, self.S
+        q = lambda t: t.data_ptr() if t is not None else None
         return L.State(n, p[0].data_ptr(), p[1].data_ptr(), p[2].data_ptr(), v[0].data_ptr(),
                        v[1].data_ptr(), v[2].data_ptr(), self.rho.data_ptr(), s[0].data_ptr(),
                        s[1].data_ptr(), s[2].data_ptr(), s[3].data_ptr(), s[4].data_ptr(),
-                       s[5].data_ptr(), self.m.data_ptr(),
-                       self.u.data_ptr() if self.u is not None else None)
+                       s[5].data_ptr(), self.m.data_ptr(), q(self.u), q(self.d), q(self.flaw_ptr),
+                       q(self.flaw_eps))
 
 
 def params_struct(params) -> L.Params:
@@ -219,8 +233,9 @@ def sph_neighbours(grid: CellGrid, pos: torch.Tensor, h: float, col_cap: int | N
     return row_ptr, col[: int(nnz.value)]
 
 
-def new_deriv(n: int, device="cuda", extra: bool = False):
-    """Output arrays of sph_rhs; with ``extra`` also du (n) and xv (3, n) = dx/dt."""
+def new_deriv(n: int, device="cuda", extra: bool = False, damage: bool = False):
+    """Output arrays of sph_rhs; with ``extra`` also du (n) and xv (3, n) = dx/dt, with
+    ``damage`` dd3 (n) = d(d^(1/3))/dt and n_act (n, int32)."""
     d = dict(acc=torch.empty(3, n, dtype=F64, device=device),
              drho=torch.empty(n, dtype=F64, device=device),
              dS=torch.empty(6, n, dtype=F64, device=device),
@@ -228,6 +243,9 @@ def new_deriv(n: int, device="cuda", extra: bool = False):
     if extra:
         d["du"] = torch.empty(n, dtype=F64, device=device)
         d["xv"] = torch.empty(3, n, dtype=F64, device=device)
+    if damage:
+        d["dd3"] = torch.empty(n, dtype=F64, device=device)
+        d["n_act"] = torch.empty(n, dtype=torch.int32, device=device)
     return d
 
 
@@ -247,6 +265,12 @@ def deriv_struct(d: dict, cls=L.Deriv):
                 _dev(t)
         args += [p(du)] + ([xv[0].data_ptr(), xv[1].data_ptr(), xv[2].data_ptr()]
                            if xv is not None else [None, None, None])
+        dd3, na = d.get("dd3"), d.get("n_act")
+        if dd3 is not None:
+            _dev(dd3)
+        if na is not None:
+            _dev(na, torch.int32)
+        args += [p(dd3), p(na)]
     return cls(*args)
 
 
@@ -266,12 +290,13 @@ def precision_code(precision) -> int:
 
 
 def sph_rhs(grid: CellGrid, state: ParticleState, params, precision="fp64", out=None,
-            ws: torch.Tensor | None = None, extra: bool = False) -> dict:
+            ws: torch.Tensor | None = None, extra: bool = False, damage: bool = False) -> dict:
     """Right-hand side (C: sph_rhs): dict acc (3, n), drho (n), dS (6, n), rho_sum (n);
-    with ``extra`` (or an ``out`` holding them) also du (n) and xv (3, n) = dx/dt."""
+    with ``extra`` (or an ``out`` holding them) also du (n) and xv (3, n) = dx/dt, with
+    ``damage`` the damage model's dd3 (n) and n_act (n) (the state's flaw lists needed)."""
     n = state.n
     if out is None:
-        out = new_deriv(n, state.rho.device, extra)
+        out = new_deriv(n, state.rho.device, extra, damage)
     if ws is None:
         ws = workspace(L.SPH_OP_RHS, n, 0, state.rho.device)
     cs = state.c_state()

@@ -561,6 +561,7 @@ extern "C" int sph_rhs_adjoint(const sph_grid *grid, const sph_state *state,
         return fail(SPH_ERR_NOT_IMPLEMENTED, "adjoint with the artificial stress");
     if (params->eos != 0.0)
         return fail(SPH_ERR_NOT_IMPLEMENTED, "adjoint with the Murnaghan or Tillotson equation");
+    if (state->d) return fail(SPH_ERR_NOT_IMPLEMENTED, "adjoint with damage");
     const size_t need = adjoint_ws_bytes(grid->n);
     if (ws_bytes < need) return fail(SPH_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
     hipStream_t s = (hipStream_t)stream;

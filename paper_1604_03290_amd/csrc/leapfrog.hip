@@ -302,6 +302,8 @@ sph_deriv deriv_struct(const Deriv10 &d) {
     o.dsyz = d.p[9];
     o.rho_sum = nullptr;
     o.du = o.dx = o.dy = o.dz = nullptr;
+    o.dd3 = nullptr;
+    o.n_act = nullptr;
     return o;
 }
 
@@ -323,6 +325,9 @@ sph_state state_struct(const Fields13 &f, const double *m, int64_t n) {
     s.syz = f.p[12];
     s.m = m;
     s.u = nullptr;
+    s.d = nullptr;
+    s.flaw_ptr = nullptr;
+    s.flaw_eps = nullptr;
     return s;
 }
 
@@ -370,6 +375,7 @@ int check_lf(const sph_grid *grid, const sph_state *s0, const sph_params *params
         return fail(SPH_ERR_NOT_IMPLEMENTED, "the leapfrog drifts with v (no XSPH)");
     if (params->eos == 2.0)
         return fail(SPH_ERR_NOT_IMPLEMENTED, "the leapfrog does not evolve u (Tillotson)");
+    if (s0->d) return fail(SPH_ERR_NOT_IMPLEMENTED, "the leapfrog does not evolve damage");
     return SPH_OK;
 }
 

@@ -26,15 +26,25 @@ namespace sph {
 namespace {
 
 // --------------------------------------------------------------- prepass --
+// dd3 / nact (null unless requested): the damage model's rates (section 3.2)
 __global__ __launch_bounds__(kBlock) void k_prepass(GridDev g, StateDev st, int64_t n, Consts k,
                                                     double *__restrict__ rec,
-                                                    int32_t *__restrict__ status) {
+                                                    int32_t *__restrict__ status, double *dd3,
+                                                    int32_t *nact) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int a = io_index(g, s);
     const double S[6] = {st.sxx[a], st.syy[a], st.szz[a], st.sxy[a], st.sxz[a], st.syz[a]};
-    write_rec(g, k, s, st.x[a], st.y[a], st.z[a], st.vx[a], st.vy[a], st.vz[a], st.rho[a], S,
-              st.m[a], rec, status, st.u ? st.u[a] : 0.0);
+    const double d = st.d ? st.d[a] : 0.0, rho = st.rho[a], m = st.m[a];
+    const double p = write_rec(g, k, s, st.x[a], st.y[a], st.z[a], st.vx[a], st.vy[a], st.vz[a],
+                               rho, S, m, rec, status, st.u ? st.u[a] : 0.0, d);
+    if (dd3) {
+        const double f = (1.0 - d) * yield_factor(k, S);
+        const double ph = p >= 0.0 ? p : (1.0 - d) * p;
+        const double sig[6] = {f * S[0] - ph, f * S[1] - ph, f * S[2] - ph,
+                               f * S[3],      f * S[4],      f * S[5]};
+        damage_rate(k, st, n, a, sig, rho, m, d, dd3, nact, status);
+    }
 }
 
 // FP32 copies of the pair operands (positions stay FP64 for the exact test)
@@ -67,7 +77,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs64(GridDev g, int64_t n, Consts
     acc.rs = ra[7].x * k.Wn;  // own term m_a W(0)
     const double c_a = ra[7].y;
     const double Ta[6] = {p4.x, p4.y, p5.x, p5.y, p6.x, p6.y};
-    const bool tens_a = kExt && in_tension(k, rho_a);
+    const bool tens_a = kExt && signbit(c_a);
     for_each_candidate(g, s, xa, ya, za, k.reach, [&](int t) {
         const double2 *rb = rec2(rec, t);
         const double2 b0 = rb[0], b1 = rb[1];
@@ -120,7 +130,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs64_list(GridDev g, int64_t n, C
     acc.rs = p7.x * k.Wn;  // own term m_a W(0)
     const double c_a = p7.y;
     const double Ta[6] = {p4.x, p4.y, p5.x, p5.y, p6.x, p6.y};
-    const bool tens_a = kExt && in_tension(k, rho_a);
+    const bool tens_a = kExt && signbit(c_a);
     const char *recs = reinterpret_cast<const char *>(rec);
     const int32_t *row = g.pl_slot + base + __lane_id();
     int e0 = steps > 0 ? row[0] : 0;
@@ -276,8 +286,9 @@ __global__ __launch_bounds__(kBlock) void k_pairs32_list(GridDev g, int64_t n, C
 }  // namespace
 
 int prepass_launch(const GridDev &g, const StateDev &st, int64_t n, const Consts &k, double *rec,
-                   int32_t *status, hipStream_t s) {
-    k_prepass<<<blocks_for(n), kBlock, 0, s>>>(g, st, n, k, rec, status);
+                   int32_t *status, hipStream_t s, const OutDev *od) {
+    k_prepass<<<blocks_for(n), kBlock, 0, s>>>(g, st, n, k, rec, status, od ? od->dd3 : nullptr,
+                                               od ? od->n_act : nullptr);
     SPH_LAUNCHED();
     return SPH_OK;
 }
@@ -296,6 +307,8 @@ int check_state(const sph_grid *grid, const sph_state *st) {
                          st->sxx, st->syy, st->szz, st->sxy, st->sxz, st->syz, st->m};
     for (const double *q : p)
         if (!q) return fail(SPH_ERR_INVALID_ARG, "state array is NULL");
+    if (!st->flaw_ptr != !st->flaw_eps)
+        return fail(SPH_ERR_INVALID_ARG, "flaw_ptr and flaw_eps are given together or not at all");
     return SPH_OK;
 }
 
@@ -335,6 +348,16 @@ int check_deriv(const sph_deriv *o) {
         if (!q) return fail(SPH_ERR_INVALID_ARG, "output array is NULL");
     if (!(o->dx && o->dy && o->dz) && (o->dx || o->dy || o->dz))
         return fail(SPH_ERR_INVALID_ARG, "dx, dy and dz are given together or not at all");
+    if (!o->dd3 != !o->n_act)
+        return fail(SPH_ERR_INVALID_ARG, "dd3 and n_act are given together or not at all");
+    return SPH_OK;
+}
+
+int check_damage(const sph_state *st, const sph_params *pr, const sph_deriv *o) {
+    if (o->dd3 && !st->flaw_ptr)
+        return fail(SPH_ERR_INVALID_ARG, "damage rates need the flaw lists");
+    if (o->dd3 && !(pr->mu > 0.0))
+        return fail(SPH_ERR_INVALID_ARG, "damage rates need mu > 0 (Young's modulus)");
     return SPH_OK;
 }
 
@@ -354,7 +377,9 @@ int rhs_launch(const sph_grid *grid, const sph_state *state, const sph_params *p
     StateDev st = state_dev(state);
     OutDev od = out_dev(out);
     int rc;
-    if (!rec_ready && (rc = prepass_launch(g, st, n, k, rec, c.status(), s))) return rc;
+    if (od.dd3 && rec_ready)
+        return fail(SPH_ERR_NOT_IMPLEMENTED, "damage rates need the prepass");
+    if (!rec_ready && (rc = prepass_launch(g, st, n, k, rec, c.status(), s, &od))) return rc;
     const bool ext = k.eps_s > 0.0 || od.du || od.dx || k.eos != 0;
     if (precision == SPH_FP64) {
         TimedRegion t("pairs_fp64", s);
@@ -409,7 +434,8 @@ extern "C" int sph_rhs(const sph_grid *grid, const sph_state *state, const sph_p
     clear_error();
     int rc;
     if ((rc = check_grid(grid)) || (rc = check_state(grid, state)) ||
-        (rc = check_params(grid, params)) || (rc = check_deriv(out)))
+        (rc = check_params(grid, params)) || (rc = check_deriv(out)) ||
+        (rc = check_damage(state, params, out)))
         return rc;
     if (precision != SPH_FP64 && precision != SPH_FP32_COMP)
         return fail(SPH_ERR_INVALID_ARG, "unknown precision %d", precision);

@@ -19,6 +19,9 @@ struct Consts {
     // equation of state: 0 liquid, 1 Murnaghan (n_M, K0 = rho0 c^2), 2 Tillotson
     int eos;
     double alpha, c, n_M, K0, aT, bT, AT, BT, E0T, alT, beT, Eiv, Ecv;
+    // damage model (section 3.2): bulk modulus K (rho0 c^2, A_T for Tillotson) and
+    // Young's modulus E = 9 K mu / (3 K + mu)
+    double Kd, Ey;
 };
 
 // Kernel shape w(q) of section 3.1.1 (W = s/h^3 w), host side.
@@ -66,6 +69,8 @@ inline Consts make_consts(const sph_params &p, double delta) {
     k.beT = p.beta_T;
     k.Eiv = p.E_iv;
     k.Ecv = p.E_cv;
+    k.Kd = k.eos == 2 ? p.A_T : k.K0;
+    k.Ey = 9.0 * k.Kd * p.mu / (3.0 * k.Kd + p.mu);
     return k;
 }
 
@@ -81,26 +86,34 @@ __host__ __device__ inline Consts32 narrow(const Consts &k) {
 struct StateDev {
     const double *x, *y, *z, *vx, *vy, *vz, *rho, *sxx, *syy, *szz, *sxy, *sxz, *syz, *m;
     const double *u;  // specific internal energy (Tillotson), null = 0
+    const double *d;  // damage, null = 0
+    const int64_t *fp;  // flaw lists: offsets (n + 1) and ascending thresholds
+    const double *fe;
 };
 
 inline StateDev state_dev(const sph_state *s) {
     return StateDev{s->x,   s->y,   s->z,   s->vx,  s->vy,  s->vz,  s->rho, s->sxx,
-                    s->syy, s->szz, s->sxy, s->sxz, s->syz, s->m,   s->u};
+                    s->syy, s->szz, s->sxy, s->sxz, s->syz, s->m,   s->u,   s->d,
+                    s->flaw_ptr, s->flaw_eps};
 }
 
 struct OutDev {
     double *ax, *ay, *az, *drho, *dsxx, *dsyy, *dszz, *dsxy, *dsxz, *dsyz, *rho_sum;
     double *du, *dx, *dy, *dz;  // energy rate and dx/dt (null unless requested)
+    double *dd3;                // damage rate d(d^(1/3))/dt and activated flaws (idem)
+    int32_t *n_act;
 };
 
 inline OutDev out_dev(const sph_deriv *o) {
     return OutDev{o->ax,   o->ay,   o->az,   o->drho, o->dsxx,    o->dsyy, o->dszz, o->dsxy,
-                  o->dsxz, o->dsyz, o->rho_sum, o->du, o->dx, o->dy, o->dz};
+                  o->dsxz, o->dsyz, o->rho_sum, o->du, o->dx, o->dy, o->dz, o->dd3, o->n_act};
 }
 
 // Slot-ordered operand records, one 128-byte record per slot:
 //   x y z vx | vy vz rho V | T0 T1 T2 T3 | T4 T5 m c
-// with T = sigma / rho^2 (xx, yy, zz, xy, xz, yz) and V = m / rho.  A partner's
+// with T = sigma / rho^2 (xx, yy, zz, xy, xz, yz), V = m / rho and c the sound
+// speed, negated (sign bit set, also for 0) when the pressure is negative: the
+// artificial stress's tension test.  A partner's
 // first seven 16-byte chunks carry everything its pair terms need (its mass being
 // V rho), which the adjoint's gathers use; the forward kernels read all eight (the
 // eighth also holds the sound speed c, which other equations of state than the
@@ -290,14 +303,16 @@ __device__ inline double yield_factor(const Consts &k, const double S[6]) {
 // Operand record of slot s (pressure, limiter, T = sigma / rho^2, V = m / rho) from
 // the particle's state; raises STALE_GRID when the particle left its cell (or its
 // list position) by more than skin / 2 and DOMAIN for a non-positive or
-// non-finite density.  The prepass and the leapfrog's fused passes write every
+// non-finite density.  With damage d the stress is sigma_d = -p^ I + (1 - d) f_Y S,
+// p^ = p for p >= 0 and (1 - d) p below (section 2.7); d = 0 gives sigma exactly.
+// Returns the pressure p.  The prepass and the leapfrog's fused passes write every
 // record through this one function; kEos = false limits it to the liquid equation
 // (the adjoint's passes, which refuse the others).
 template <bool kEos = true>
-__device__ inline void write_rec(const GridDev &g, const Consts &k, int64_t s, double x, double y,
-                                 double z, double vx, double vy, double vz, double rho,
-                                 const double S[6], double m, double *__restrict__ rec,
-                                 int32_t *__restrict__ status, double u = 0.0) {
+__device__ inline double write_rec(const GridDev &g, const Consts &k, int64_t s, double x, double y,
+                                   double z, double vx, double vy, double vz, double rho,
+                                   const double S[6], double m, double *__restrict__ rec,
+                                   int32_t *__restrict__ status, double u = 0.0, double d = 0.0) {
     if (!within_cell(g, (int)s, x, y, z)) raise_flag(status, SPH_ERR_STALE_GRID);
     if (!(rho > 0.0) || !isfinite(rho)) raise_flag(status, SPH_ERR_DOMAIN);
     double p, cs;
@@ -307,17 +322,69 @@ __device__ inline void write_rec(const GridDev &g, const Consts &k, int64_t s, d
         p = pressure(k, rho);
         cs = k.c;
     }
-    const double f = yield_factor(k, S);
+    const double f = (1.0 - d) * yield_factor(k, S);
+    const double ph = p >= 0.0 ? p : (1.0 - d) * p;
     const double ir2 = 1.0 / (rho * rho);
     double2 *r = reinterpret_cast<double2 *>(rec + s * kRec);
     r[0] = make_double2(x, y);
     r[1] = make_double2(z, vx);
     r[2] = make_double2(vy, vz);
     r[3] = make_double2(rho, m / rho);
-    r[4] = make_double2((f * S[0] - p) * ir2, (f * S[1] - p) * ir2);
-    r[5] = make_double2((f * S[2] - p) * ir2, f * S[3] * ir2);
+    r[4] = make_double2((f * S[0] - ph) * ir2, (f * S[1] - ph) * ir2);
+    r[5] = make_double2((f * S[2] - ph) * ir2, f * S[3] * ir2);
     r[6] = make_double2(f * S[4] * ir2, f * S[5] * ir2);
-    r[7] = make_double2(m, cs);
+    r[7] = make_double2(m, p < 0.0 ? -cs : cs);
+    return p;
+}
+
+// Largest eigenvalue of a symmetric 3x3 matrix (xx yy zz xy xz yz) by the
+// trigonometric solution of its characteristic cubic (O. K. Smith, Commun. ACM 4,
+// 1961): with q = tr / 3 and B = (A - q I) / p, p^2 = |A - q I|^2 / 6, the roots are
+// q + 2 p cos(acos(det B / 2) / 3 + 2 pi j / 3), the largest at j = 0.
+__device__ inline double sym3_max_eig(const double a[6]) {
+    const double q = (a[0] + a[1] + a[2]) * (1.0 / 3.0);
+    const double b0 = a[0] - q, b1 = a[1] - q, b2 = a[2] - q;
+    const double off = a[3] * a[3] + a[4] * a[4] + a[5] * a[5];
+    const double p2 = (b0 * b0 + b1 * b1 + b2 * b2 + 2.0 * off) * (1.0 / 6.0);
+    if (!(p2 > 0.0)) return q;
+    const double pp = sqrt(p2);
+    const double det = b0 * (b1 * b2 - a[5] * a[5]) - a[3] * (a[3] * b2 - a[5] * a[4]) +
+                       a[4] * (a[3] * a[5] - b1 * a[4]);
+    const double r = fmin(fmax(det / (2.0 * p2 * pp), -1.0), 1.0);
+    return q + 2.0 * pp * cos(acos(r) * (1.0 / 3.0));
+}
+
+// Damage model of section 3.2 for one particle (a: user index): the strain
+// eps = sigma_max / ((1 - d) E) from the damaged stress sig (infinite at d = 1), the
+// number of the particle's flaw thresholds below it, and the growth rate
+// n_act c_g / R_s of d^(1/3), zero once d n_tot >= n_act (the limiter).  Flaw
+// offsets that are not ordered within [0, fp[n]] raise DOMAIN and count no flaw.
+__device__ inline void damage_rate(const Consts &k, const StateDev &st, int64_t n, int a,
+                                   const double sig[6], double rho, double m, double d,
+                                   double *dd3, int32_t *nact, int32_t *__restrict__ status) {
+    const int64_t lo = st.fp[a], hi = st.fp[a + 1], end = st.fp[n];
+    if (lo < 0 || hi < lo || hi > end) {
+        raise_flag(status, SPH_ERR_DOMAIN);
+        dd3[a] = 0.0;
+        nact[a] = 0;
+        return;
+    }
+    const double smax = sym3_max_eig(sig);
+    const double eps = d < 1.0 ? smax / ((1.0 - d) * k.Ey) : INFINITY;
+    int64_t l = lo, r = hi;  // first threshold >= eps
+    while (l < r) {
+        const int64_t mid = l + ((r - l) >> 1);
+        if (st.fe[mid] < eps)
+            l = mid + 1;
+        else
+            r = mid;
+    }
+    const int32_t na = (int32_t)(l - lo);
+    const double cg = 0.4 * sqrt((k.Kd + 4.0 / 3.0 * (1.0 - d) * k.mu) / rho);
+    const double Rs = cbrt(3.0 * m / (4.0 * M_PI * rho));
+    const double ntot = (double)(hi - lo);
+    dd3[a] = d * ntot < (double)na ? na * cg / Rs : 0.0;
+    nact[a] = na;
 }
 
 // 1/sqrt(x): hardware estimate refined by two Newton steps y <- y (3 - x y^2) / 2
@@ -397,18 +464,13 @@ struct Acc64 {
 // the registers of pow
 __device__ __attribute__((noinline)) inline double pow_frac(double f, double n) { return pow(f, n); }
 
-// Tension test of the artificial stress: negative pressure (section 2.5.1's
-// cut-off sets the pressure to zero)
-__device__ inline bool in_tension(const Consts &k, double rho) {
-    return rho < k.rho0 && !(k.rho_cut > 0.0 && rho / k.rho0 < k.rho_cut);
-}
-
 // One ordered pair (a target, b partner).  r = x_a - x_b, dv = v_b - v_a,
 // B = T_a + T_b (six components).  With kExt also: the artificial stress
 // (zeta_a + zeta_b) (w / w(dmpd))^n in the momentum bracket (Ta, Tb: the two
 // particles' T, tens_a: a in tension), the energy sum m_b B : dv (x) grad_a W
 // (the momentum bracket without artificial stress) and the XSPH sum
-// 2 m_b / (rho_a + rho_b) dv W.
+// 2 m_b / (rho_a + rho_b) dv W; ca, cb are the records' sound speeds, whose sign
+// bit marks tension.
 template <bool kCorr = false, bool kExt = false>
 __device__ inline void pair64(const Consts &k, double d2, double rx, double ry, double rz,
                               double dvx, double dvy, double dvz, double ra, double rb,
@@ -433,7 +495,8 @@ __device__ inline void pair64(const Consts &k, double d2, double rx, double ry, 
     a.L[8] = fma(tz, gz, a.L[8]);
     const double wab = -(dvx * rx + dvy * ry + dvz * rz);
     // the pair's mean sound speed (section 3.1.3); one value for the liquid equation
-    const double Pi = viscosity(k, d2, wab, ra, rb, kExt ? k.alpha * (0.5 * (ca + cb)) : k.alpha_c).Pi;
+    const double Pi =
+        viscosity(k, d2, wab, ra, rb, kExt ? k.alpha * (0.5 * (fabs(ca) + fabs(cb))) : k.alpha_c).Pi;
     const double bxx = Bxx - Pi, byy = Byy - Pi, bzz = Bzz - Pi;
     const double qx = bxx * gx + Bxy * gy + Bxz * gz;
     const double qy = Bxy * gx + byy * gy + Byz * gz;
@@ -447,7 +510,7 @@ __device__ inline void pair64(const Consts &k, double d2, double rx, double ry, 
         a.xs[1] = fma(xw, dvy, a.xs[1]);
         a.xs[2] = fma(xw, dvz, a.xs[2]);
         // artificial stress
-        const bool tens_b = in_tension(k, rb);
+        const bool tens_b = signbit(cb);
         if (k.eps_s > 0.0 && (tens_a || tens_b)) {
             const double f = kp.w * k.inv_wm;
             double fn = f;
@@ -662,8 +725,9 @@ int reduce_params_launch(const double *p0, int64_t m0, const double *p1, int64_t
                          double *dparams, int accumulate, hipStream_t s);
 
 // rhs.hip
+// od (nullable): outputs whose dd3 / n_act, when set, receive the damage rates
 int prepass_launch(const GridDev &g, const StateDev &st, int64_t n, const Consts &k, double *rec,
-                   int32_t *status, hipStream_t s);
+                   int32_t *status, hipStream_t s, const OutDev *od = nullptr);
 int check_state(const sph_grid *grid, const sph_state *st);
 int check_params(const sph_grid *grid, const sph_params *pr);
 int check_deriv(const sph_deriv *o);

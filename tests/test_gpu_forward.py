@@ -423,3 +423,142 @@ def test_equations_of_state_refused_where_not_built():
         with pytest.raises(L.SphError) as e:
             call()
         assert e.value.code == L.SPH_ERR_NOT_IMPLEMENTED
+
+
+def test_tillotson_artificial_stress_takes_tension_from_the_pressure():
+    # with u > 0 the Tillotson pressure stays positive somewhat below rho0: the tension
+    # test must follow the pressure, not the density
+    w = eos_variant(2)
+    w.params.update(eps_s=0.2, n_s=4.0)
+    p, _ = native.eos(w.rho, w.param_vector(), w.u)
+    assert ((w.rho < w.params["rho0"]) & (p >= 0)).any()
+    ref = native.rhs_workload(w)
+    st = P.ParticleState.from_arrays(w.pos, w.vel, w.rho, w.S, w.m, u=w.u)
+    g = P.sph_build_cells(st.pos, w.h, skin=0.05 * w.dx, cells_per_h=2, pairs=True)
+    out = P.sph_rhs(g, st, w.params, "fp64")
+    assert P.workspace_status(out["_ws"]) == 0
+    got = {k: v.cpu().numpy() for k, v in out.items() if k != "_ws"}
+    err = normwise(got, ref, w.rho)
+    bad = {k: v for k, v in err.items() if not v <= TOL["fp64"]}
+    assert not bad, bad
+
+
+# ---- Grady-Kipp damage (sections 2.7, 3.2) ----
+
+def damage_variant(seed=31, eos=0.0):
+    """A cube whose strains straddle its flaws' activation thresholds: 80 % of the
+    particles slightly expanded (tension of about 10 MPa), the rest compressed, deviators
+    of 4 MPa, damage uniform in [0, 1] with exact 0 and 1 mixed in; basalt's Weibull
+    parameters (k = 1e61 m^-3, m = 16) over the cube's volume."""
+    w = W.cube(12, 0.1, seed=seed, alpha=1.0, beta=1.0, eos=eos)
+    rng = np.random.default_rng(seed)
+    r0 = w.params["rho0"]
+    w.rho = r0 * (1.0 - rng.normal(1.5e-4, 0.6e-4, w.n))
+    comp = rng.random(w.n) < 0.2
+    w.rho[comp] = r0 * (1.0 + rng.uniform(0, 3e-4, comp.sum()))
+    w.S = rng.normal(0, 4e6, (6, w.n))
+    d = rng.uniform(0, 1, w.n)
+    d[rng.random(w.n) < 0.2] = 0.0
+    d[rng.random(w.n) < 0.05] = 1.0
+    w.d = d
+    lo, hi = w.box(0.0)
+    w.flaws = W.flaws(w.n, float(np.prod(hi - lo + w.dx)), 1e61, 16.0, seed + 1)
+    return w
+
+
+def gpu_rhs_damage(w, precision="fp64", damage=True, d=True, **path):
+    st = P.ParticleState.from_arrays(w.pos, w.vel, w.rho, w.S, w.m, d=w.d if d else None,
+                                     flaws=w.flaws if damage else None)
+    g = P.sph_build_cells(st.pos, w.h, skin=path.get("skin", 0.0),
+                          cells_per_h=path.get("cells_per_h", 1), pairs=path.get("pairs", False))
+    out = P.sph_rhs(g, st, w.params, precision, damage=damage)
+    assert P.workspace_status(out["_ws"]) == 0
+    return {k: v.cpu().numpy() for k, v in out.items() if k != "_ws"}
+
+
+def check_damage_rates(got, w):
+    from oracle import damage as D
+    ptr, eps = w.flaws
+    rate, nact, e = D.rates(w.rho, w.S, w.m, w.param_vector(), ptr, eps, d=w.d)
+    # a strain within 1e-12 of a threshold may land on either side of it
+    near = np.zeros(w.n, dtype=bool)
+    for a in range(w.n):
+        f = eps[ptr[a]:ptr[a + 1]]
+        near[a] = np.isfinite(e[a]) and np.min(np.abs(f - e[a])) <= 1e-12 * abs(e[a])
+    same = got["n_act"] == nact
+    assert np.all(same | near)
+    assert np.all(np.abs(got["n_act"] - nact) <= 1)
+    assert ((nact > 0) & (nact < np.diff(ptr))).any() and (nact == 0).any() and (rate > 0).any()
+    r, g = rate[same], got["dd3"][same]
+    assert np.all(np.abs(g - r) <= 1e-13 * np.abs(r)), np.abs(g - r).max()
+
+
+@pytest.mark.parametrize("precision,path", [("fp64", "cells1"), ("fp64", "pairs2_skin"),
+                                            ("fp32comp", "pairs2_skin")])
+def test_rhs_damage_matches_oracle(precision, path):
+    w = damage_variant()
+    ref = native.rhs_workload(w)
+    got = gpu_rhs_damage(w, precision, **PATHS[path])
+    err = normwise(got, ref, w.rho)
+    bad = {k: v for k, v in err.items() if not v <= TOL[precision]}
+    assert not bad, bad
+    check_damage_rates(got, w)
+    intact = w.copy()
+    plain = native.rhs_workload(intact)  # the damage acts on this state
+    assert np.abs(plain["acc"] - ref["acc"]).max() > 1e-3 * np.abs(ref["acc"]).max()
+
+
+def test_rhs_damage_with_tillotson_and_artificial_stress():
+    w = damage_variant(seed=37, eos=2.0)
+    w.u = np.random.default_rng(37).uniform(0.0, 5e6, w.n)
+    w.params.update(eps_s=0.2, n_s=4.0)
+    ref = native.rhs_workload(w)
+    st = P.ParticleState.from_arrays(w.pos, w.vel, w.rho, w.S, w.m, u=w.u, d=w.d, flaws=w.flaws)
+    g = P.sph_build_cells(st.pos, w.h, skin=0.05 * w.dx, cells_per_h=2, pairs=True)
+    out = P.sph_rhs(g, st, w.params, "fp64", damage=True)
+    assert P.workspace_status(out["_ws"]) == 0
+    got = {k: v.cpu().numpy() for k, v in out.items() if k != "_ws"}
+    err = normwise(got, ref, w.rho)
+    bad = {k: v for k, v in err.items() if not v <= TOL["fp64"]}
+    assert not bad, bad
+    from oracle import damage as D
+    ptr, eps = w.flaws
+    rate, nact, _ = D.rates(w.rho, w.S, w.m, w.param_vector(), ptr, eps, u=w.u, d=w.d)
+    same = got["n_act"] == nact
+    assert same.mean() > 0.99
+    assert np.all(np.abs(got["dd3"][same] - rate[same]) <= 1e-13 * np.abs(rate[same]))
+
+
+def test_zero_damage_and_rate_outputs_change_nothing():
+    w = damage_variant(seed=33)
+    base = gpu_rhs_damage(w, damage=False, d=False, pairs=True)
+    w.d = np.zeros(w.n)
+    zero = gpu_rhs_damage(w, damage=True, pairs=True)
+    for k in ("acc", "drho", "dS", "rho_sum"):
+        assert np.array_equal(base[k], zero[k]), k
+
+
+def test_damage_refused_where_not_built_and_bad_flaw_lists_flagged():
+    w = damage_variant(seed=35)
+    st = P.ParticleState.from_arrays(w.pos, w.vel, w.rho, w.S, w.m, d=w.d, flaws=w.flaws)
+    g = P.sph_build_cells(st.pos, w.h)
+    for call in (lambda: P.sph_leapfrog(g, st, w.params, w.dt, 2),
+                 lambda: P.sph_rhs_adjoint(g, st, w.params,
+                                           {"acc": torch.ones(3, w.n, dtype=torch.float64).cuda()})):
+        with pytest.raises(L.SphError) as e:
+            call()
+        assert e.value.code == L.SPH_ERR_NOT_IMPLEMENTED
+    bare = P.ParticleState.from_arrays(w.pos, w.vel, w.rho, w.S, w.m, d=w.d)
+    with pytest.raises(L.SphError) as e:
+        P.sph_rhs(g, bare, w.params, damage=True)
+    assert e.value.code == L.SPH_ERR_INVALID_ARG
+    with pytest.raises(L.SphError) as e:
+        P.sph_rhs(g, st, dict(w.params, mu=0.0), damage=True)
+    assert e.value.code == L.SPH_ERR_INVALID_ARG
+    # offsets out of order: flagged, no flaw counted, every read within [0, flaw_ptr[n])
+    ptr = w.flaws[0].copy()
+    ptr[1], ptr[2] = ptr[2], ptr[1]
+    bad = P.ParticleState.from_arrays(w.pos, w.vel, w.rho, w.S, w.m, d=w.d, flaws=(ptr, w.flaws[1]))
+    out = P.sph_rhs(g, bad, w.params, damage=True)
+    assert P.workspace_status(out["_ws"]) == L.SPH_ERR_DOMAIN
+    assert int(out["n_act"][1]) == 0 and float(out["dd3"][1]) == 0.0
