@@ -1,4 +1,4 @@
-"""ctypes front end of the C oracle (``sph_oracle.c``).  Test infrastructure.
+"""ctypes front end of the C oracle (``sph_oracle.c``, ``gravity.c``).  Test infrastructure.
 
 Arrays are numpy float64 structure-of-arrays: pos/vel (3, n), S (6, n),
 rho/m (n,).  ``par`` is the parameter vector {h, rho0, c, mu, Y0, alpha,
@@ -43,6 +43,10 @@ def lib():
                                _pi64, _pi32, _pd, _pd, _pd, _pd, _pd, _pd, _pd]
         L.orc_prepass2.argtypes = [_i64, _pd, _pd, _pd, _pd, _pd, _pd, _pd, _pd, _pd]
         L.orc_eos.argtypes = [_i64, _pd, _pd, _pd, _pd, _pd]
+        L.orc_gravity.argtypes = [_i64, _pd, _pd, _d, _d, _d, _pd, _pi64]
+        L.orc_gravity.restype = _i64
+        L.orc_gravity_tree.argtypes = [_i64, _pd, _pd, _i64, _pi32, _pi64, _pd, _pd]
+        L.orc_gravity_tree.restype = _i64
         _lib = L
     return _lib
 
@@ -198,3 +202,36 @@ def rhs_workload(w, targets=None, csr=None, want_L: bool = True, want_extra: boo
     """``rhs`` on a ``workloads.Workload``."""
     return rhs(w.pos, w.vel, w.rho, w.S, w.m, w.param_vector(), targets, csr, want_L, want_extra,
                getattr(w, "u", None), getattr(w, "d", None))
+
+
+def gravity(pos, m, G: float, theta: float, eps: float = 0.0):
+    """Barnes-Hut monopole gravity (section 3.3): dict acc (3, n), count (n) and
+    nodes (the number of inner nodes)."""
+    pos, ppos = _f64(pos)
+    m, pm = _f64(m)
+    n = m.shape[0]
+    acc = np.zeros((3, n))
+    cnt = np.zeros(n, dtype=np.int64)
+    nn = lib().orc_gravity(n, ppos, pm, G, theta, eps, acc.ctypes.data_as(_pd),
+                           cnt.ctypes.data_as(_pi64))
+    return dict(acc=acc, count=cnt, nodes=int(nn))
+
+
+def gravity_tree(pos, m):
+    """The oracle's inner nodes: depth (k,), corner (k, 3) integer cube corner at
+    that depth, mass (k,), com (k, 3)."""
+    pos, ppos = _f64(pos)
+    m, pm = _f64(m)
+    n = m.shape[0]
+    cap = 0
+    while True:
+        depth = np.zeros(max(cap, 1), dtype=np.int32)
+        corner = np.zeros((max(cap, 1), 3), dtype=np.int64)
+        mass = np.zeros(max(cap, 1))
+        com = np.zeros((max(cap, 1), 3))
+        nn = lib().orc_gravity_tree(n, ppos, pm, cap, depth.ctypes.data_as(_pi32),
+                                    corner.ctypes.data_as(_pi64), mass.ctypes.data_as(_pd),
+                                    com.ctypes.data_as(_pd))
+        if nn <= cap:
+            return dict(depth=depth[:nn], corner=corner[:nn], mass=mass[:nn], com=com[:nn])
+        cap = int(nn)
