@@ -65,7 +65,8 @@ enum sph_op {
     SPH_OP_ADJOINT = 3,
     SPH_OP_LEAPFROG = 4,
     SPH_OP_LEAPFROG_ADJOINT = 5,
-    SPH_OP_PAIRS = 6
+    SPH_OP_PAIRS = 6,
+    SPH_OP_GRAVITY = 7   /* ncells: inner-node capacity of the tree (<= 0: 2 n) */
 };
 
 /* Frozen candidate-pair list built by sph_build_pairs (the interaction list of
@@ -314,6 +315,42 @@ int sph_rhs(const sph_grid *grid, const sph_state *state, const sph_params *para
 int sph_rhs_adjoint(const sph_grid *grid, const sph_state *state, const sph_params *params,
                     const sph_deriv_cot *cot, const sph_state_grad *grad, double *dparams,
                     void *ws, size_t ws_bytes, void *stream);
+
+/* Self-gravity by the Barnes-Hut tree with monopoles (section 3.3, eq.
+ * gravitational_force; the octree of section 3.5.1):
+ *   tree      root cube of edge s0 = max over axes of (max x - min x) at the per-axis
+ *             minima; a node of depth d has edge s0 / 2^d; the inner nodes are the
+ *             cubes that hold two or more particles, the particles are the leaves.
+ *             Octant membership uses q = floor((x - lo) / s0 * 2^21) clamped to
+ *             [0, 2^21 - 1] (q = 0 when s0 = 0); depth 21 is the last, its cubes'
+ *             particles are all leaves of it.  Children are ordered by octant
+ *             4 bx + 2 by + bz (the axis bits of q at that depth).
+ *   monopole  each inner node carries its total mass and centre of mass, summed over
+ *             its children in that order (an inner child counts as m_c at x_c).
+ *   walk      from the root in that order: an inner node with edge s and distance r
+ *             from the particle to its centre of mass acts as one pseudo-particle
+ *             when s / r < theta, else its children are visited; every other leaf
+ *             acts directly; each acting body p adds
+ *             a += G m_p (x_p - x_a) / (r + eps)^3 (nothing at r = 0).
+ *             theta = 0 gives the direct sum.
+ * Every sum and test is evaluated in double precision in the order stated, without
+ * fused multiply-adds, so the result does not depend on the launch.
+ *   x, y, z, m  device, n particles (user order); m > 0
+ *   G           gravitational constant; theta in [0, 1); eps >= 0 (the distance
+ *               added to r, the paper's second smoothing scheme)
+ *   ax, ay, az  device, n, overwritten
+ *   count       device int32 [n] or NULL: bodies each particle took a term from
+ *   node_cap    inner nodes the workspace holds (the ncells argument of
+ *               sph_workspace_bytes(SPH_OP_GRAVITY, n, node_cap); <= 0: 2 n)
+ *   nodes_out   host or NULL, receives the number of inner nodes
+ * Synchronises the stream once (to learn the tree's size).  Errors: INVALID_ARG,
+ * CAPACITY (more inner nodes than node_cap: nothing is written to the outputs,
+ * *nodes_out holds the requirement), WORKSPACE, HIP.  Device flag DOMAIN for a
+ * non-finite position or a mass that is not positive and finite. */
+int sph_gravity(const double *x, const double *y, const double *z, const double *m, int64_t n,
+                double G, double theta, double eps, double *ax, double *ay, double *az,
+                int32_t *count, int64_t node_cap, int64_t *nodes_out, void *ws, size_t ws_bytes,
+                void *stream);
 
 /* Kick-drift-kick leapfrog that drives the gradient workloads (the paper's
  * own integrators are those of section 3.4).  With U = (v, rho, S) and

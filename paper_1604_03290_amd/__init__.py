@@ -13,6 +13,7 @@ from .api import (  # noqa: F401
     ParticleState,
     sph_build_cells,
     sph_build_pairs,
+    sph_gravity,
     sph_leapfrog,
     sph_leapfrog_adjoint,
     sph_neighbours,

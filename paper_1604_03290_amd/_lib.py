@@ -29,7 +29,7 @@ SPH_FP64 = 0
 SPH_FP32_COMP = 1
 
 SPH_OP_BUILD, SPH_OP_NEIGHBOURS, SPH_OP_RHS, SPH_OP_ADJOINT = 0, 1, 2, 3
-SPH_OP_LEAPFROG, SPH_OP_LEAPFROG_ADJOINT, SPH_OP_PAIRS = 4, 5, 6
+SPH_OP_LEAPFROG, SPH_OP_LEAPFROG_ADJOINT, SPH_OP_PAIRS, SPH_OP_GRAVITY = 4, 5, 6, 7
 
 _NAMES = {0: "SPH_OK", -1: "SPH_ERR_INVALID_ARG", -2: "SPH_ERR_CAPACITY", -3: "SPH_ERR_WORKSPACE",
           -4: "SPH_ERR_HIP", -5: "SPH_ERR_DOMAIN", -6: "SPH_ERR_NOT_IMPLEMENTED",
@@ -120,6 +120,9 @@ def lib():
                                      P(C.c_int64), _pd, C.c_size_t, _vp]
         L.sph_rhs.argtypes = [P(Grid), P(State), P(Params), C.c_int, P(Deriv), _pd, C.c_size_t,
                               _vp]
+        L.sph_gravity.argtypes = [_pd, _pd, _pd, _pd, C.c_int64, C.c_double, C.c_double,
+                                  C.c_double, _pd, _pd, _pd, _pd, C.c_int64, P(C.c_int64), _pd,
+                                  C.c_size_t, _vp]
         L.sph_rhs_adjoint.argtypes = [P(Grid), P(State), P(Params), P(DerivCot), P(Fields), _pd,
                                       _pd, C.c_size_t, _vp]
         L.sph_leapfrog.argtypes = [P(Grid), P(State), P(Params), C.c_double, C.c_int, P(Fields),

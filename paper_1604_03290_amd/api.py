@@ -233,6 +233,38 @@ def sph_neighbours(grid: CellGrid, pos: torch.Tensor, h: float, col_cap: int | N
     return row_ptr, col[: int(nnz.value)]
 
 
+def sph_gravity(pos: torch.Tensor, m: torch.Tensor, G: float, theta: float, eps: float = 0.0,
+                count: bool = False, node_cap: int = 0, ws: torch.Tensor | None = None) -> dict:
+    """Barnes-Hut monopole self-gravity (C: sph_gravity): dict acc (3, n), nodes (inner
+    nodes of the tree) and, with ``count``, count (n, int32) bodies per particle.
+    Synchronises once; retries once with the reported capacity when the tree outgrows
+    ``node_cap`` (0: 2 n)."""
+    _dev(pos)
+    _dev(m)
+    n = int(m.shape[0])
+    assert pos.shape == (3, n)
+    dev = m.device
+    acc = torch.empty(3, n, dtype=F64, device=dev)
+    cnt = torch.empty(n, dtype=torch.int32, device=dev) if count else None
+    nodes = C.c_int64()
+    for attempt in range(2):
+        if ws is None or attempt:
+            ws = workspace(L.SPH_OP_GRAVITY, n, node_cap, dev)
+        rc = L.lib().sph_gravity(_ptr(pos[0]), _ptr(pos[1]), _ptr(pos[2]), _ptr(m), n, float(G),
+                                 float(theta), float(eps), _ptr(acc[0]), _ptr(acc[1]), _ptr(acc[2]),
+                                 _ptr(cnt) if cnt is not None else None, node_cap, C.byref(nodes),
+                                 _ptr(ws), ws.numel(), _stream())
+        if rc == L.SPH_ERR_CAPACITY and attempt == 0:
+            node_cap = int(nodes.value)
+            continue
+        L.check(rc)
+        break
+    out = dict(acc=acc, nodes=int(nodes.value), _ws=ws)
+    if cnt is not None:
+        out["count"] = cnt
+    return out
+
+
 def new_deriv(n: int, device="cuda", extra: bool = False, damage: bool = False):
     """Output arrays of sph_rhs; with ``extra`` also du (n) and xv (3, n) = dx/dt, with
     ``damage`` dd3 (n) = d(d^(1/3))/dt and n_act (n, int32)."""

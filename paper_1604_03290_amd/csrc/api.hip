@@ -26,6 +26,7 @@ size_t adjoint_ws_bytes(int64_t n);
 size_t leapfrog_ws_bytes(int64_t n);
 size_t leapfrog_adjoint_ws_bytes(int64_t n);
 size_t pairs_ws_bytes(int64_t n);
+size_t gravity_ws_bytes(int64_t n, int64_t node_cap);
 
 }  // namespace sph
 
@@ -37,6 +38,7 @@ extern "C" const char *sph_last_error(void) { return g_err; }
 
 extern "C" size_t sph_workspace_bytes(int op, int64_t n, int64_t ncells) {
     if (n <= 0) n = 1;
+    if (op == SPH_OP_GRAVITY) return gravity_ws_bytes(n, ncells);
     if (ncells <= 0) ncells = 1;
     switch (op) {
         case SPH_OP_BUILD: return build_ws_bytes(n, ncells);

@@ -1,0 +1,113 @@
+"""Barnes-Hut monopole self-gravity on the GPU (section 3.3) against the oracle: the
+same tree (inner-node count), the same bodies per particle (exact counts) and the
+accelerations, on clouds, a lattice (many exact ties of s / r with theta), the
+two-sphere workload in full, coincident particles and a single particle; capacity,
+domain and argument errors."""
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import native
+import paper_1604_03290_amd as P
+from paper_1604_03290_amd import _lib as L
+
+pytestmark = pytest.mark.gpu
+
+G = 6.674e-11
+
+
+def run(pos, m, theta, eps=0.0, **kw):
+    pt = torch.as_tensor(np.ascontiguousarray(pos), dtype=torch.float64).cuda()
+    mt = torch.as_tensor(np.ascontiguousarray(m), dtype=torch.float64).cuda()
+    out = P.sph_gravity(pt, mt, G, theta, eps, count=True, **kw)
+    assert P.workspace_status(out["_ws"]) == 0
+    return out["acc"].cpu().numpy(), out["count"].cpu().numpy(), out["nodes"]
+
+
+def check(pos, m, theta, eps=0.0, tol=1e-13):
+    acc, cnt, nodes = run(pos, m, theta, eps)
+    ref = native.gravity(pos, m, G, theta, eps)
+    assert nodes == ref["nodes"]
+    assert np.array_equal(cnt, ref["count"])
+    scale = np.abs(ref["acc"]).max()
+    err = np.abs(acc - ref["acc"]).max() / scale
+    assert err <= tol, err
+    return acc, ref
+
+
+def cloud(n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.normal(size=(3, n)), rng.uniform(1.0, 2.0, n)
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.3, 0.5, 0.8])
+@pytest.mark.parametrize("eps", [0.0, 0.01])
+def test_cloud_matches_oracle(theta, eps):
+    pos, m = cloud(3000, 11)
+    check(pos, m, theta, eps)
+
+
+def test_lattice_ties_match_oracle():
+    # an unjittered lattice puts many centres of mass at exact multiples of the node
+    # edge: s / r = theta ties that both sides must decide alike
+    pos = W.lattice_cube(16, 0.1)
+    m = np.full(pos.shape[1], 2.7)
+    for theta in (0.25, 0.5):
+        check(pos, m, theta)
+
+
+def test_two_spheres_match_oracle():
+    w = W.config(1)  # 262,144 particles
+    acc, ref = check(w.pos, w.m, 0.5, eps=0.5 * w.dx, tol=1e-12)
+    assert np.isfinite(acc).all()
+
+
+def test_degenerate_sets():
+    acc, cnt, nodes = run(np.zeros((3, 1)), np.ones(1), 0.5)
+    assert np.all(acc == 0.0) and cnt[0] == 0 and nodes == 0
+    acc, cnt, nodes = run(np.ones((3, 5)), np.ones(5), 0.5)
+    assert np.all(acc == 0.0) and np.all(cnt == 4) and nodes == 22
+    pos, m = cloud(500, 12)
+    pos[:, 7] = pos[:, 3]  # coincident pair
+    pos[:, 9] = pos[:, 8] + 1e-12  # a chain of one-child nodes down to depth 21
+    check(pos, m, 0.5)
+
+
+def test_deterministic():
+    pos, m = cloud(20000, 13)
+    a1, c1, _ = run(pos, m, 0.5)
+    a2, c2, _ = run(pos, m, 0.5)
+    assert np.array_equal(a1, a2) and np.array_equal(c1, c2)
+
+
+def test_capacity_and_errors():
+    pos, m = cloud(2000, 14)
+    pt = torch.as_tensor(pos).cuda().contiguous()
+    mt = torch.as_tensor(m).cuda().contiguous()
+    ws = P.workspace(L.SPH_OP_GRAVITY, 2000, 16)
+    acc = torch.empty(3, 2000, dtype=torch.float64).cuda()
+    nodes = C.c_int64()
+    with pytest.raises(L.SphError) as e:
+        L.check(L.lib().sph_gravity(
+            P.api._ptr(pt[0]), P.api._ptr(pt[1]), P.api._ptr(pt[2]), P.api._ptr(mt), 2000, 1.0, 0.5,
+            0.0, P.api._ptr(acc[0]), P.api._ptr(acc[1]), P.api._ptr(acc[2]), None, 16,
+            C.byref(nodes), P.api._ptr(ws), ws.numel(), P.api._stream()))
+    assert e.value.code == L.SPH_ERR_CAPACITY
+    assert nodes.value == native.gravity(pos, m, 1.0, 0.5)["nodes"]
+    # the binding retries with the reported capacity
+    out = P.sph_gravity(pt, mt, 1.0, 0.5, node_cap=16)
+    ref = native.gravity(pos, m, 1.0, 0.5)
+    assert np.abs(out["acc"].cpu().numpy() - ref["acc"]).max() <= 1e-13 * np.abs(ref["acc"]).max()
+    for bad in (dict(theta=1.0), dict(theta=-0.1), dict(eps=-1.0)):
+        args = dict(theta=0.5, eps=0.0)
+        args.update(bad)
+        with pytest.raises(L.SphError) as e:
+            P.sph_gravity(pt, mt, 1.0, args["theta"], args["eps"])
+        assert e.value.code == L.SPH_ERR_INVALID_ARG
+    m0 = mt.clone()
+    m0[5] = 0.0
+    out = P.sph_gravity(pt, m0, 1.0, 0.5)
+    assert P.workspace_status(out["_ws"]) == L.SPH_ERR_DOMAIN
