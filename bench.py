@@ -330,6 +330,17 @@ def main():
     ms = median_ms(lambda: P.sph_rhs(g, sd, w.params, "fp64", out=od, ws=ws_rhs), args.form_reps, torch)
     forms["rhs_fp64_damage"] = {"ms": ms, "pairs_per_s": nnz0 / (ms * 1e-3), "flaws": int(fptr[-1]),
                                 "particles_with_active_flaws": int((od["n_act"] > 0).sum())}
+    # Barnes-Hut monopole self-gravity (section 3.3) on the same bodies, theta = 0.5 (the
+    # paper's bound), smoothing 0.5 dx: tree build and walk in one call (it synchronises
+    # once to size the tree); terms = pseudo-particles and leaves summed over particles
+    mt = st.m
+    wsg = P.workspace(P._lib.SPH_OP_GRAVITY, n, 0, dev)
+    go = P.sph_gravity(st.pos, mt, 6.674e-11, 0.5, 0.5 * w.dx, count=True, ws=wsg)
+    terms = int(go["count"].to(torch.int64).sum())
+    ms = median_ms(lambda: P.sph_gravity(st.pos, mt, 6.674e-11, 0.5, 0.5 * w.dx, ws=wsg),
+                   args.form_reps, torch)
+    forms["gravity_bh_theta0.5"] = {"ms": ms, "inner_nodes": go["nodes"], "terms": terms,
+                                    "terms_per_s": terms / (ms * 1e-3)}
     forms["fp32comp_speedup_vs_fp64"] = forms["rhs_fp64"]["ms"] / forms["rhs_fp32comp"]["ms"]
     cg = {k: torch.randn_like(outs["fp64"][k]) for k in fields}
     ms = median_ms(lambda: P.sph_rhs_adjoint(g, st, w.params, cg, ws=ws_adj), args.form_reps, torch)

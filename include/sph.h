@@ -329,12 +329,14 @@ int sph_rhs_adjoint(const sph_grid *grid, const sph_state *state, const sph_para
  *             its children in that order (an inner child counts as m_c at x_c).
  *   walk      from the root in that order: an inner node with edge s and distance r
  *             from the particle to its centre of mass acts as one pseudo-particle
- *             when s / r < theta, else its children are visited; every other leaf
- *             acts directly; each acting body p adds
+ *             when s / r < theta, tested as s^2 < theta^2 r^2, else its children are
+ *             visited; every other leaf acts directly; each acting body p adds
  *             a += G m_p (x_p - x_a) / (r + eps)^3 (nothing at r = 0).
  *             theta = 0 gives the direct sum.
- * Every sum and test is evaluated in double precision in the order stated, without
- * fused multiply-adds, so the result does not depend on the launch.
+ * The keys, the monopoles and the opening tests are evaluated in double precision in
+ * the order stated, without fused multiply-adds (so the tree and the bodies each
+ * particle takes are fixed by the input); the force terms use reciprocal square roots
+ * refined to double precision.  Results do not depend on the launch.
  *   x, y, z, m  device, n particles (user order); m > 0
  *   G           gravitational constant; theta in [0, 1); eps >= 0 (the distance
  *               added to r, the paper's second smoothing scheme)

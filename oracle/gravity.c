@@ -30,6 +30,8 @@
  *     distance r from the particle to its centre of mass satisfy s / r < theta
  *     acts as one pseudo-particle, else its children are visited; a leaf other
  *     than the particle itself always acts directly.  theta = 0 is the direct sum.
+ *     The test is evaluated on squares, s^2 < theta^2 r^2 (equivalent for r > 0,
+ *     and false at r = 0 as s / 0 < theta is), which needs no square root.
  * Arithmetic in FP64 without contraction, each sum in the order stated.  */
 #include <math.h>
 #include <stdint.h>
@@ -222,9 +224,9 @@ static void gr_walk(const gr_tree *t, int nd, int64_t a, double G, double theta,
     const double xa = t->pos[a], ya = t->pos[n + a], za = t->pos[2 * n + a];
     const gr_node *k = &t->node[nd];
     const double dx = k->cx - xa, dy = k->cy - ya, dz = k->cz - za;
-    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    const double r2 = dx * dx + dy * dy + dz * dz;
     const double s = ldexp(t->s0, -k->depth);
-    if (s / r < theta) {
+    if (s * s < theta * theta * r2) {
         gr_term(A, G, eps, k->m, dx, dy, dz);
         return;
     }

@@ -16,28 +16,27 @@
 //   keys      bounding cube (reduction), integer coordinates, keys
 //   sort      rocPRIM radix sort of (key, user index), stable
 //   depth     D_i and the number of nodes starting at i; scan -> item offsets
-//   items     leaves (position, mass) and inner nodes (depth, skip), per-depth lists
-//   monopole  one pass per depth, deepest first: mass and centre of mass of each
-//             inner node over its children in octant order
+//   items     leaves (position, mass) and inner nodes (depth, skip), and the list of
+//             inner nodes (the k-th inner node in pre-order is list[k])
+//   monopole  one pass per depth, deepest first, over the inner-node list: mass and
+//             centre of mass of each node of that depth over its children in octant
+//             order
 //   walk      one wavefront walks the items for its 64 particles together: the
 //             item pointer is uniform (its data arrive by scalar loads); a lane
 //             that accepts a node resumes at the node's skip, and the wavefront
 //             descends while any active lane needs to, so every lane takes exactly
-//             the terms, and in the order, of its own walk.
+//             the terms, and in the order, of its own walk.  Both possible next items
+//             (t + 1 and the skip) are fetched while the current one is tested.
 #include <rocprim/device/device_radix_sort.hpp>
 
 #include "common.hpp"
+#include "rhs_common.hpp"
 #include "timing.hpp"
 
 namespace sph {
 namespace {
 
 constexpr int kDepthMax = 21;  // 3 x 21 key bits
-constexpr int kDepths = kDepthMax + 1;
-
-struct DepthOffsets {
-    int64_t off[kDepths];
-};
 
 // ------------------------------------------------------------------ keys --
 __global__ __launch_bounds__(kBlock) void k_bbox_partial(const double *__restrict__ x,
@@ -145,7 +144,7 @@ __global__ __launch_bounds__(kBlock) void k_keys(const double *__restrict__ x,
 
 // ----------------------------------------------------------------- depth --
 // depth shared by sorted keys i and i + 1 (-1 past the last); the number of inner
-// nodes that start at i, c_i = max(0, D_i - D_{i-1}), and per-depth node counts.
+// nodes that start at i, c_i = max(0, D_i - D_{i-1}), and the deepest node's depth.
 __device__ inline int shared_depth(const uint64_t *key, int64_t i, int64_t n) {
     if (i < 0) return -1;
     if (i + 1 >= n) return -1;
@@ -156,16 +155,20 @@ __device__ inline int shared_depth(const uint64_t *key, int64_t i, int64_t n) {
 
 __global__ __launch_bounds__(kBlock) void k_depth(const uint64_t *__restrict__ key, int64_t n,
                                                   int64_t *__restrict__ cnt,
-                                                  unsigned long long *__restrict__ per_depth) {
+                                                  int32_t *__restrict__ max_depth) {
+    __shared__ int bmax;
+    if (threadIdx.x == 0) bmax = -1;
+    __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i > n) return;
-    if (i == n) {
+    if (i < n) {
+        const int d1 = shared_depth(key, i, n), d0 = shared_depth(key, i - 1, n);
+        cnt[i] = d1 > d0 ? d1 - d0 : 0;
+        if (d1 >= 0) atomicMax(&bmax, d1);
+    } else if (i == n) {
         cnt[n] = 0;
-        return;
     }
-    const int d1 = shared_depth(key, i, n), d0 = shared_depth(key, i - 1, n);
-    cnt[i] = d1 > d0 ? d1 - d0 : 0;
-    for (int d = d0 + 1; d <= d1; ++d) atomicAdd(&per_depth[d], 1ull);
+    __syncthreads();
+    if (threadIdx.x == 0 && bmax >= 0) atomicMax(max_depth, bmax);
 }
 
 // ----------------------------------------------------------------- items --
@@ -175,9 +178,8 @@ __global__ __launch_bounds__(kBlock) void k_depth(const uint64_t *__restrict__ k
 __global__ __launch_bounds__(kBlock) void k_items(
     const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ z,
     const double *__restrict__ m, const uint64_t *__restrict__ key, const int32_t *__restrict__ idx,
-    const int64_t *__restrict__ off, int64_t n, DepthOffsets doff,
-    unsigned long long *__restrict__ cursor, int32_t *__restrict__ lists, double4 *__restrict__ pm,
-    int2 *__restrict__ link) {
+    const int64_t *__restrict__ off, int64_t n, int32_t *__restrict__ list,
+    double4 *__restrict__ pm, int2 *__restrict__ link) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const int d1 = shared_depth(key, i, n), d0 = shared_depth(key, i - 1, n);
@@ -197,8 +199,7 @@ __global__ __launch_bounds__(kBlock) void k_items(
         }
         link[t] = make_int2((int)(lo + off[lo]), d);
         pm[t] = make_double4(0.0, 0.0, 0.0, 0.0);
-        const unsigned long long slot = atomicAdd(&cursor[d], 1ull);
-        lists[doff.off[d] + (int64_t)slot] = (int32_t)t;
+        list[off[i] + (t - first)] = (int32_t)t;
     }
     const int a = idx[i];
     link[t] = make_int2((int)(t + 1), (int)(-1 - i));
@@ -206,14 +207,16 @@ __global__ __launch_bounds__(kBlock) void k_items(
 }
 
 // -------------------------------------------------------------- monopole --
-__global__ __launch_bounds__(kBlock) void k_monopole(const int32_t *__restrict__ list, int64_t cnt,
-                                                     double4 *__restrict__ pm,
+__global__ __launch_bounds__(kBlock) void k_monopole(const int32_t *__restrict__ list, int64_t K,
+                                                     int depth, double4 *__restrict__ pm,
                                                      const int2 *__restrict__ link) {
 #pragma clang fp contract(off)
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (j >= cnt) return;
+    if (j >= K) return;
     const int t = list[j];
-    const int end = link[t].x;
+    const int2 lt = link[t];
+    if (lt.y != depth) return;
+    const int end = lt.x;
     double M = 0.0, mx = 0.0, my = 0.0, mz = 0.0;
     for (int c = t + 1; c < end; c = link[c].x) {
         const double4 p = pm[c];
@@ -227,19 +230,39 @@ __global__ __launch_bounds__(kBlock) void k_monopole(const int32_t *__restrict__
 
 // ------------------------------------------------------------------ walk --
 struct GravConsts {
-    double G, theta, eps;
+    double G, th2, eps;  // th2 = theta^2
     int64_t n, T;
 };
 
+// a += G m_p (x_p - x_a) / (r + eps)^3 for r2 = r^2 > 0 (reciprocals by Newton steps
+// from the hardware estimates)
 __device__ inline void add_term(const GravConsts &k, double mp, double dx, double dy, double dz,
-                                double r, double &ax, double &ay, double &az) {
+                                double r2, double &ax, double &ay, double &az) {
+    if (r2 == 0.0) return;
+    const double ir = rsqrt64(r2);
+    double id;
+    if (k.eps > 0.0) {
+        id = rcp64(r2 * ir + k.eps);
+    } else {
+        id = ir;
+    }
+    const double f = k.G * mp * (id * id * id);
+    ax = fma(f, dx, ax);
+    ay = fma(f, dy, ay);
+    az = fma(f, dz, az);
+}
+
+// The opening test s / r < theta is taken as s^2 < theta^2 r^2 with
+// r^2 = (dx dx + dy dy) + dz dz rounded as written (no fused operations), the same
+// arithmetic as the test's definition in the oracle.
+__device__ inline double dist2_plain(double dx, double dy, double dz) {
 #pragma clang fp contract(off)
-    if (r == 0.0) return;
-    const double d = r + k.eps;
-    const double f = k.G * mp / (d * d * d);
-    ax = ax + f * dx;
-    ay = ay + f * dy;
-    az = az + f * dz;
+    return dx * dx + dy * dy + dz * dz;
+}
+
+__device__ inline bool opens_not(double s, double th2, double r2) {
+#pragma clang fp contract(off)
+    return s * s < th2 * r2;
 }
 
 __global__ __launch_bounds__(kBlock) void k_walk(GravConsts k, const double *__restrict__ box,
@@ -252,7 +275,6 @@ __global__ __launch_bounds__(kBlock) void k_walk(GravConsts k, const double *__r
                                                  double *__restrict__ ay_out,
                                                  double *__restrict__ az_out,
                                                  int32_t *__restrict__ count_out) {
-#pragma clang fp contract(off)
     const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const bool live = i0 < k.n;
     const int64_t i = live ? i0 : k.n - 1;  // lanes past n walk the last particle, write nothing
@@ -262,33 +284,35 @@ __global__ __launch_bounds__(kBlock) void k_walk(GravConsts k, const double *__r
     double ax = 0.0, ay = 0.0, az = 0.0;
     int terms = 0;
     int resume = 0;
-    int t = 0;
     const int T = (int)k.T;
+    int t = 0;
+    double4 p = pm[0];
+    int2 l = link[0];
     while (t < T) {
-        t = __builtin_amdgcn_readfirstlane(t);
-        const double4 p = pm[t];
-        const int2 l = link[t];
+        // both possible successors, fetched while this item is tested
+        const int ta = min(t + 1, T - 1), tb = min(l.x, T - 1);
+        const double4 pa = pm[ta], pb = pm[tb];
+        const int2 la = link[ta], lb = link[tb];
         const bool active = t >= resume;
+        bool down = false;
         if (l.y >= 0) {
             const double dx = p.x - xa, dy = p.y - ya, dz = p.z - za;
-            const double r = sqrt(dx * dx + dy * dy + dz * dz);
-            const double s = ldexp(s0, -l.y);
-            const bool take = active && s / r < k.theta;
+            const double r2 = dist2_plain(dx, dy, dz);
+            const bool take = active && opens_not(ldexp(s0, -l.y), k.th2, r2);
             if (take) {
-                add_term(k, p.w, dx, dy, dz, r, ax, ay, az);
+                add_term(k, p.w, dx, dy, dz, r2, ax, ay, az);
                 ++terms;
                 resume = l.x;
             }
-            t = __any(active && !take) ? t + 1 : l.x;
-        } else {
-            if (active && -1 - l.y != i) {
-                const double dx = p.x - xa, dy = p.y - ya, dz = p.z - za;
-                const double r = sqrt(dx * dx + dy * dy + dz * dz);
-                add_term(k, p.w, dx, dy, dz, r, ax, ay, az);
-                ++terms;
-            }
-            t = l.x;
+            down = __any(active && !take);
+        } else if (active && -1 - l.y != i) {
+            const double dx = p.x - xa, dy = p.y - ya, dz = p.z - za;
+            add_term(k, p.w, dx, dy, dz, dist2_plain(dx, dy, dz), ax, ay, az);
+            ++terms;
         }
+        t = down ? t + 1 : l.x;
+        p = down ? pa : pb;
+        l = down ? la : lb;
     }
     if (!live) return;
     const int a = idx[i];
@@ -298,8 +322,8 @@ __global__ __launch_bounds__(kBlock) void k_walk(GravConsts k, const double *__r
     if (count_out) count_out[a] = terms;
 }
 
-__global__ void k_zero_u64(unsigned long long *p, int m) {
-    if ((int)threadIdx.x < m) p[threadIdx.x] = 0ull;
+__global__ void k_set_i32(int32_t *p, int32_t v) {
+    if (threadIdx.x == 0) p[0] = v;
 }
 
 // ------------------------------------------------------------- workspace --
@@ -308,8 +332,8 @@ struct GravWs {
     uint64_t *key[2];
     int32_t *idx[2];
     int64_t *cnt, *off, *scan_tmp;
-    unsigned long long *per_depth, *cursor;  // kDepths each
-    int32_t *lists;
+    int32_t *max_depth;
+    int32_t *list;
     double4 *pm;
     int2 *link;
     void *sort_tmp;
@@ -331,9 +355,8 @@ GravWs carve_grav(Carve &c, int64_t n, int64_t cap) {
     w.cnt = c.take<int64_t>(n + 1);
     w.off = c.take<int64_t>(n + 1);
     w.scan_tmp = c.take<int64_t>(scan_tmp_elems(n + 1));
-    w.per_depth = c.take<unsigned long long>(2 * kDepths);
-    w.cursor = w.per_depth + kDepths;
-    w.lists = c.take<int32_t>(cap);
+    w.max_depth = c.take<int32_t>(1);
+    w.list = c.take<int32_t>(cap);
     w.pm = c.take<double4>(n + cap);
     w.link = c.take<int2>(n + cap);
     w.sort_bytes = sort_bytes_bound(n);
@@ -392,40 +415,32 @@ extern "C" int sph_gravity(const double *x, const double *y, const double *z, co
     const uint64_t *key = kb.current();
     const int32_t *idx = vb.current();
 
-    k_zero_u64<<<1, 64, 0, s>>>(w.per_depth, 2 * kDepths);
+    k_set_i32<<<1, 64, 0, s>>>(w.max_depth, -1);
     SPH_LAUNCHED();
-    k_depth<<<blocks_for(n + 1), kBlock, 0, s>>>(key, n, w.cnt, w.per_depth);
+    k_depth<<<blocks_for(n + 1), kBlock, 0, s>>>(key, n, w.cnt, w.max_depth);
     SPH_LAUNCHED();
     if ((rc = exclusive_scan_i64(w.cnt, w.off, n + 1, w.scan_tmp, s))) return rc;
 
-    // the tree's size: inner nodes K = off[n], and the nodes per depth
+    // the tree's size: inner nodes K = off[n], and the deepest node's depth
     int64_t K = 0;
-    unsigned long long per[kDepths];
+    int32_t dmax = -1;
     SPH_HIP_TRY(hipMemcpyAsync(&K, w.off + n, sizeof K, hipMemcpyDeviceToHost, s));
-    SPH_HIP_TRY(hipMemcpyAsync(per, w.per_depth, sizeof per, hipMemcpyDeviceToHost, s));
+    SPH_HIP_TRY(hipMemcpyAsync(&dmax, w.max_depth, sizeof dmax, hipMemcpyDeviceToHost, s));
     SPH_HIP_TRY(hipStreamSynchronize(s));
     if (nodes_out) *nodes_out = K;
     if (K > cap)
         return fail(SPH_ERR_CAPACITY, "%lld inner nodes exceed capacity %lld", (long long)K,
                     (long long)cap);
-    DepthOffsets doff;
-    int64_t acc = 0;
-    for (int d = 0; d < kDepths; ++d) {
-        doff.off[d] = acc;
-        acc += (int64_t)per[d];
-    }
-    if (acc != K) return fail(SPH_ERR_HIP, "tree bookkeeping: %lld != %lld", (long long)acc, (long long)K);
+    if (dmax > kDepthMax || (K > 0) != (dmax >= 0))
+        return fail(SPH_ERR_HIP, "tree bookkeeping: depth %d with %lld nodes", dmax, (long long)K);
 
-    k_items<<<nb, kBlock, 0, s>>>(x, y, z, m, key, idx, w.off, n, doff, w.cursor, w.lists, w.pm,
-                                  w.link);
+    k_items<<<nb, kBlock, 0, s>>>(x, y, z, m, key, idx, w.off, n, w.list, w.pm, w.link);
     SPH_LAUNCHED();
-    for (int d = kDepthMax; d >= 0; --d) {
-        if (per[d] == 0) continue;
-        k_monopole<<<blocks_for((int64_t)per[d]), kBlock, 0, s>>>(w.lists + doff.off[d],
-                                                                  (int64_t)per[d], w.pm, w.link);
+    for (int d = dmax; d >= 0; --d) {
+        k_monopole<<<blocks_for(K), kBlock, 0, s>>>(w.list, K, d, w.pm, w.link);
         SPH_LAUNCHED();
     }
-    const GravConsts k{G, theta, eps, n, n + K};
+    const GravConsts k{G, theta * theta, eps, n, n + K};
     k_walk<<<nb, kBlock, 0, s>>>(k, w.box, idx, w.pm, w.link, w.off, w.cnt, ax, ay, az, count);
     SPH_LAUNCHED();
     return SPH_OK;
