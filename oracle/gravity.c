@@ -247,22 +247,25 @@ static void gr_walk(const gr_tree *t, int nd, int64_t a, double G, double theta,
             gr_term(A, G, eps, t->m[p], t->pos[p] - xa, t->pos[n + p] - ya, t->pos[2 * n + p] - za);
 }
 
-/* Gravitational acceleration of every particle: pos (3, n), m (n) > 0; acc (3, n);
- * count (n, nullable): pseudo-particles and leaves each particle took a term from.
- * Returns the number of inner nodes. */
+/* Gravitational acceleration of the targets (targets[0..nt) or, when targets is
+ * NULL, every particle, nt = n): pos (3, n), m (n) > 0; acc (3, nt); count (nt,
+ * nullable): pseudo-particles and leaves each target took a term from.  Returns the
+ * number of inner nodes. */
 int64_t orc_gravity(int64_t n, const double *pos, const double *m, double G, double theta,
-                    double eps, double *acc, int64_t *count)
+                    double eps, const int64_t *targets, int64_t nt, double *acc, int64_t *count)
 {
     gr_tree t;
     gr_build(&t, n, pos, m);
+    if (!targets) nt = n;
 #pragma omp parallel for schedule(dynamic, 64)
-    for (int64_t a = 0; a < n; ++a) {
+    for (int64_t j = 0; j < nt; ++j) {
+        const int64_t a = targets ? targets[j] : j;
         gr_acc A = {0.0, 0.0, 0.0, 0};
         gr_walk(&t, 0, a, G, theta, eps, &A);
-        acc[a] = A.ax;
-        acc[n + a] = A.ay;
-        acc[2 * n + a] = A.az;
-        if (count) count[a] = A.count;
+        acc[j] = A.ax;
+        acc[nt + j] = A.ay;
+        acc[2 * nt + j] = A.az;
+        if (count) count[j] = A.count;
     }
     const int64_t nn = n > 0 ? t.nnode : 0;
     gr_free(&t);

@@ -111,3 +111,18 @@ def test_capacity_and_errors():
     m0[5] = 0.0
     out = P.sph_gravity(pt, m0, 1.0, 0.5)
     assert P.workspace_status(out["_ws"]) == L.SPH_ERR_DOMAIN
+
+
+@pytest.mark.parametrize("k", [2, 4])
+def test_full_sizes_on_sampled_bodies(k):
+    # the bullet-into-cube set (2,105,344 bodies) and the non-uniform three-body set
+    # (8,388,608): the whole tree on the GPU, 2,048 sampled bodies against the oracle
+    w = W.config(k)
+    acc, cnt, nodes = run(w.pos, w.m, 0.5, eps=0.5 * w.dx)
+    idx = W.subsample(w.n, 2048, 21)
+    ref = native.gravity(w.pos, w.m, G, 0.5, 0.5 * w.dx, targets=idx)
+    assert nodes == ref["nodes"]
+    assert np.array_equal(cnt[idx], ref["count"])
+    err = np.abs(acc[:, idx] - ref["acc"]).max() / np.abs(ref["acc"]).max()
+    assert err <= 1e-12, err
+    assert np.isfinite(acc).all()
