@@ -337,13 +337,14 @@ int sph_rhs_adjoint(const sph_grid *grid, const sph_state *state, const sph_para
  * the order stated, without fused multiply-adds (so the tree and the bodies each
  * particle takes are fixed by the input); the force terms use reciprocal square roots
  * refined to double precision.  Results do not depend on the launch.
- *   x, y, z, m  device, n particles (user order); m > 0
+ *   x, y, z, m  device, n particles (user order), 1 <= n <= 2^26; m > 0
  *   G           gravitational constant; theta in [0, 1); eps >= 0 (the distance
  *               added to r, the paper's second smoothing scheme)
  *   ax, ay, az  device, n, overwritten
  *   count       device int32 [n] or NULL: bodies each particle took a term from
  *   node_cap    inner nodes the workspace holds (the ncells argument of
- *               sph_workspace_bytes(SPH_OP_GRAVITY, n, node_cap); <= 0: 2 n)
+ *               sph_workspace_bytes(SPH_OP_GRAVITY, n, node_cap); <= 0: 2 n; at
+ *               most 22 n, which no tree exceeds)
  *   nodes_out   host or NULL, receives the number of inner nodes
  * Synchronises the stream once (to learn the tree's size).  Errors: INVALID_ARG,
  * CAPACITY (more inner nodes than node_cap: nothing is written to the outputs,
