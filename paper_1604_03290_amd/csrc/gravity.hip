@@ -108,6 +108,7 @@ __global__ __launch_bounds__(kBlock) void k_bbox_final(const double *__restrict_
 __device__ inline uint32_t quantise(double v, double lo, double s0) {
     if (!(s0 > 0.0)) return 0u;
     const double u = floor((v - lo) / s0 * 2097152.0);  // 2^21
+    if (!(u >= 0.0)) return 0u;  // a non-finite position (flagged by the caller)
     return u >= 2097152.0 ? 2097151u : (uint32_t)u;
 }
 
