@@ -310,6 +310,12 @@ def main():
     forms["rhs_fp64_energy_artstress_xsph"] = {
         "ms": ms, "pairs_per_s": nnz0 / (ms * 1e-3),
         "particles_in_tension": int((sx.rho < w.params["rho0"]).sum())}
+    ox32 = P.api.new_deriv(n, extra=True)
+    ms = median_ms(lambda: P.sph_rhs(g, sx, px, "fp32comp", out=ox32, ws=ws_rhs), args.form_reps, torch)
+    forms["rhs_fp32comp_energy_artstress_xsph"] = {
+        "ms": ms, "pairs_per_s": nnz0 / (ms * 1e-3),
+        "normwise_error_vs_fp64": {k: float((ox32[k] - ox[k]).abs().max() / ox[k].abs().max())
+                                   for k in ("acc", "drho", "dS", "du")}}
     # Tillotson equation of state (aluminium constants) on the same spread densities with
     # specific internal energies drawn over its cold, partial and full vaporisation ranges
     su = P.ParticleState(sx.pos, sx.vel, sx.rho, sx.S, sx.m, 2e7 * torch.rand(

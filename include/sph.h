@@ -144,15 +144,14 @@ typedef struct {
  * disables it): a particle with negative pressure contributes
  * zeta = -eps_s sigma / rho^2 to the momentum bracket, scaled by
  * (W(r) / W(dmpd))^n_s, dmpd in (0, h) being the mean particle distance of the
- * initial distribution (FP64 forms only; the adjoints refuse it); xsph: XSPH
+ * initial distribution (the adjoints refuse it); xsph: XSPH
  * factor in [0, 1] (section 3.1.5), used by the dx/dt output; eos: 0 the liquid
  * equation above, 1 Murnaghan (section 2.5.2, exponent n_M, K0 = rho0 c^2), 2
  * Tillotson (section 2.5.3, constants a_T .. E_cv; compressed form for rho >= rho0
  * or u <= E_iv, expanded form for rho < rho0 and u >= E_cv, linear in u between).
  * With eos 1 or 2 each particle's sound speed is the thermodynamic one,
  * c^2 = dp/drho|u + p / rho^2 dp/du|rho (floored at 0), and Pi uses the pair's mean
- * (FP64 forward only; the FP32 form, the adjoints and, for Tillotson, the leapfrog
- * refuse them). */
+ * (the adjoints and, for Tillotson, the leapfrog refuse them). */
 typedef struct {
     double h, rho0, c, mu, Y0, alpha, beta, eps_v, rho_cut, correction;
     double eps_s, n_s, dmpd, xsph;
@@ -164,7 +163,7 @@ typedef struct {
  * (eq. energy_sph; the bracket holds -Pi* I as in the momentum equation, without
  * the artificial stress) and the particle velocity dx/dt with XSPH (section
  * 3.1.5: v_a + xsph sum_b 2 m_b / (rho_a + rho_b) (v_b - v_a) W_ab; = v_a when
- * xsph = 0); FP64 only.  dd3 and n_act (both NULL, or neither; the state's flaw
+ * xsph = 0).  dd3 and n_act (both NULL, or neither; the state's flaw
  * lists are then required) request the damage model's rate d(d^(1/3))/dt and the
  * number of activated flaws (section 3.2): with sigma_max the largest principal
  * value of sigma_d, the strain eps = sigma_max / ((1 - d) E) (infinite at d = 1),

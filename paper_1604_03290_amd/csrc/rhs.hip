@@ -47,7 +47,9 @@ __global__ __launch_bounds__(kBlock) void k_prepass(GridDev g, StateDev st, int6
     }
 }
 
-// FP32 copies of the pair operands (positions stay FP64 for the exact test)
+// FP32 copies of the pair operands (positions stay FP64 for the exact test), 80 bytes:
+//   x y | z (vx vy) | (vz rho m V) | (T0 T1 T2 T3) | (T4 T5 c -)
+// c being the record's signed sound speed.
 __global__ __launch_bounds__(kBlock) void k_narrow(const double *__restrict__ rec, int64_t n,
                                                    float *__restrict__ r32) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -59,7 +61,7 @@ __global__ __launch_bounds__(kBlock) void k_narrow(const double *__restrict__ re
     *reinterpret_cast<float2 *>(o + 24) = make_float2((float)r[3], (float)r[4]);
     *reinterpret_cast<float4 *>(o + 32) = make_float4((float)r[5], (float)r[6], (float)r[14], (float)r[7]);
     *reinterpret_cast<float4 *>(o + 48) = make_float4((float)r[8], (float)r[9], (float)r[10], (float)r[11]);
-    *reinterpret_cast<float4 *>(o + 64) = make_float4((float)r[12], (float)r[13], 0.0f, 0.0f);
+    *reinterpret_cast<float4 *>(o + 64) = make_float4((float)r[12], (float)r[13], (float)r[15], 0.0f);
 }
 
 // ---------------------------------------------------------- pairs, FP64 --
@@ -172,7 +174,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs64_list(GridDev g, int64_t n, C
 // unpacked FP32 record of a partner
 struct Src32 {
     double x, y, z;
-    float vx, vy, vz, rho, m, V, T[6];
+    float vx, vy, vz, rho, m, V, T[6], c;
 };
 
 __device__ inline Src32 src32(double2 c0, double2 c1, double2 c2, double2 c3, double2 c4) {
@@ -186,6 +188,7 @@ __device__ inline Src32 src32(double2 c0, double2 c1, double2 c2, double2 c3, do
     const float4 u = __builtin_bit_cast(float4, c4);
     r.vx = a.x; r.vy = a.y; r.vz = b.x; r.rho = b.y; r.m = b.z; r.V = b.w;
     r.T[0] = t.x; r.T[1] = t.y; r.T[2] = t.z; r.T[3] = t.w; r.T[4] = u.x; r.T[5] = u.y;
+    r.c = u.z;
     return r;
 }
 
@@ -195,18 +198,27 @@ __device__ inline Src32 load32(const float *r32, int64_t s) {
     return src32(p[0], p[1], p[2], p[3], p[4]);
 }
 
-template <bool kCorr>
+template <bool kCorr, bool kExt>
 __device__ inline void pair32_of(const Consts32 &kf, const Src32 &a, const Src32 &b, double d2,
                                  Acc32 &acc) {
-    pair32<kCorr>(kf, (float)d2, (float)(a.x - b.x), (float)(a.y - b.y), (float)(a.z - b.z),
-           b.vx - a.vx, b.vy - a.vy, b.vz - a.vz, a.rho, b.rho, a.T[0] + b.T[0], a.T[1] + b.T[1],
-           a.T[2] + b.T[2], a.T[3] + b.T[3], a.T[4] + b.T[4], a.T[5] + b.T[5], b.m, b.V, acc);
+    pair32<kCorr, kExt>(kf, (float)d2, (float)(a.x - b.x), (float)(a.y - b.y),
+                        (float)(a.z - b.z), b.vx - a.vx, b.vy - a.vy, b.vz - a.vz, a.rho, b.rho,
+                        a.T[0] + b.T[0], a.T[1] + b.T[1], a.T[2] + b.T[2], a.T[3] + b.T[3],
+                        a.T[4] + b.T[4], a.T[5] + b.T[5], b.m, b.V, acc, a.T, b.T, a.c, b.c);
 }
 
-template <bool kCorr>
+template <bool kCorr, bool kExt>
 __device__ inline void post32(const Consts &k, int a, double rho_a, double m_a, const Acc32 &acc,
                               const StateDev &st, const OutDev &out, double *Lout, int64_t n,
                               int64_t s) {
+    if constexpr (kExt) {
+        if (out.du) out.du[a] = 0.5 * acc.du.value();
+        if (out.dx) {
+            out.dx[a] = st.vx[a] + k.xsph * acc.xs[0].value();
+            out.dy[a] = st.vy[a] + k.xsph * acc.xs[1].value();
+            out.dz[a] = st.vz[a] + k.xsph * acc.xs[2].value();
+        }
+    }
     double L[9], M[6];
 #pragma unroll
     for (int c = 0; c < 9; ++c) L[c] = acc.L[c].value();
@@ -225,7 +237,7 @@ __device__ inline void post32(const Consts &k, int a, double rho_a, double m_a, 
     }
 }
 
-template <bool kCorr>
+template <bool kCorr, bool kExt>
 __global__ __launch_bounds__(kBlock) void k_pairs32(GridDev g, int64_t n, Consts k,
                                                     const double *__restrict__ rec,
                                                     const float *__restrict__ r32, StateDev st,
@@ -239,13 +251,13 @@ __global__ __launch_bounds__(kBlock) void k_pairs32(GridDev g, int64_t n, Consts
     for_each_candidate(g, s, a.x, a.y, a.z, k.reach, [&](int t) {
         const Src32 b = load32(r32, t);
         const double d2 = dist2_exact(a.x, a.y, a.z, b.x, b.y, b.z);
-        if (d2 < k.h2) pair32_of<kCorr>(kf, a, b, d2, acc);
+        if (d2 < k.h2) pair32_of<kCorr, kExt>(kf, a, b, d2, acc);
     });
-    post32<kCorr>(k, io_index(g, s), p3.x, p7.x, acc, st, out, Lout, n, s);
+    post32<kCorr, kExt>(k, io_index(g, s), p3.x, p7.x, acc, st, out, Lout, n, s);
 }
 
 // FP32 pair sums over the frozen pair list (cooperative gathers of the 80-byte records)
-template <bool kCorr>
+template <bool kCorr, bool kExt>
 __global__ __launch_bounds__(kBlock) void k_pairs32_list(GridDev g, int64_t n, Consts k,
                                                          const double *__restrict__ rec,
                                                          const float *__restrict__ r32,
@@ -274,13 +286,13 @@ __global__ __launch_bounds__(kBlock) void k_pairs32_list(GridDev g, int64_t n, C
             const Src32 b = src32(dma_chunk<5>(buf, 0), dma_chunk<5>(buf, 1), dma_chunk<5>(buf, 2),
                                   dma_chunk<5>(buf, 3), dma_chunk<5>(buf, 4));
             const double d2 = dist2_exact(a.x, a.y, a.z, b.x, b.y, b.z);
-            if (d2 < k.h2) pair32_of<kCorr>(kf, a, b, d2, acc);
+            if (d2 < k.h2) pair32_of<kCorr, kExt>(kf, a, b, d2, acc);
         }
         wave_sync();
     }
     if (!act) return;
     const double2 p3 = rec2(rec, s)[3], p7 = rec2(rec, s)[7];
-    post32<kCorr>(k, io_index(g, s), p3.x, p7.x, acc, st, out, Lout, n, s);
+    post32<kCorr, kExt>(k, io_index(g, s), p3.x, p7.x, acc, st, out, Lout, n, s);
 }
 
 }  // namespace
@@ -403,22 +415,27 @@ int rhs_launch(const sph_grid *grid, const sph_state *state, const sph_params *p
             launch(F{}, F{});
         SPH_LAUNCHED();
     } else {
-        if (ext)
-            return fail(SPH_ERR_NOT_IMPLEMENTED,
-                        "artificial stress, energy and XSPH outputs and the Murnaghan and "
-                        "Tillotson equations are FP64 only");
         k_narrow<<<blocks_for(n), kBlock, 0, s>>>(rec, n, r32);
         SPH_LAUNCHED();
         TimedRegion t("pairs_fp32comp", s);
         const dim3 gb(blocks_for(n)), tb(kBlock);
-        if (g.pl_count && k.corr)
-            k_pairs32_list<true><<<gb, tb, 0, s>>>(g, n, k, rec, r32, st, od, L_out);
-        else if (g.pl_count)
-            k_pairs32_list<false><<<gb, tb, 0, s>>>(g, n, k, rec, r32, st, od, L_out);
+        auto launch = [&](auto corr, auto extra) {
+            constexpr bool C = decltype(corr)::value, E = decltype(extra)::value;
+            if (g.pl_count)
+                k_pairs32_list<C, E><<<gb, tb, 0, s>>>(g, n, k, rec, r32, st, od, L_out);
+            else
+                k_pairs32<C, E><<<gb, tb, 0, s>>>(g, n, k, rec, r32, st, od, L_out);
+        };
+        using T = std::true_type;
+        using F = std::false_type;
+        if (k.corr && ext)
+            launch(T{}, T{});
         else if (k.corr)
-            k_pairs32<true><<<gb, tb, 0, s>>>(g, n, k, rec, r32, st, od, L_out);
+            launch(T{}, F{});
+        else if (ext)
+            launch(F{}, T{});
         else
-            k_pairs32<false><<<gb, tb, 0, s>>>(g, n, k, rec, r32, st, od, L_out);
+            launch(F{}, F{});
         SPH_LAUNCHED();
     }
     return SPH_OK;

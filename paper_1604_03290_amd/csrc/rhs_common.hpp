@@ -76,11 +76,14 @@ inline Consts make_consts(const sph_params &p, double delta) {
 
 struct Consts32 {
     float inv_h, Wn, Fn, h, alpha_c, beta, epsh2;
+    float alpha, eps_s, inv_wm, n_s;  // the extended terms (see Consts)
+    int n_int;
 };
 
 __host__ __device__ inline Consts32 narrow(const Consts &k) {
-    return Consts32{(float)k.inv_h, (float)k.Wn, (float)k.Fn, (float)k.h,
-                    (float)k.alpha_c, (float)k.beta, (float)k.epsh2};
+    return Consts32{(float)k.inv_h, (float)k.Wn,    (float)k.Fn,     (float)k.h,
+                    (float)k.alpha_c, (float)k.beta, (float)k.epsh2, (float)k.alpha,
+                    (float)k.eps_s, (float)k.inv_wm, (float)k.n_s,   k.n_int};
 }
 
 struct StateDev {
@@ -558,13 +561,17 @@ struct Kahan {
 
 struct Acc32 {
     Kahan rs, L[9], ax, ay, az, M[6];
+    Kahan du, xs[3];  // the extended terms (twice du/dt, XSPH sum)
 };
 
-template <bool kCorr = false>
+// FP32 form of pair64 (same terms; with kExt the records' sound speeds ca, cb carry
+// the tension sign bit, and Ta, Tb are the two particles' T).
+template <bool kCorr = false, bool kExt = false>
 __device__ inline void pair32(const Consts32 &k, float d2, float rx, float ry, float rz, float dvx,
                               float dvy, float dvz, float ra, float rb, float Bxx, float Byy,
                               float Bzz, float Bxy, float Bxz, float Byz, float mb, float Vb,
-                              Acc32 &a) {
+                              Acc32 &a, const float *Ta = nullptr, const float *Tb = nullptr,
+                              float ca = 0.0f, float cb = 0.0f) {
     const float ir = __builtin_amdgcn_rsqf(d2);
     const float q = d2 > 0.0f ? d2 * ir * k.inv_h : 0.0f;
     const float u = 1.0f - q, u2 = u * u;
@@ -588,11 +595,39 @@ __device__ inline void pair32(const Consts32 &k, float d2, float rx, float ry, f
     const float D = d2 + k.epsh2, S = ra + rb;
     const float inv = __builtin_amdgcn_rcpf(D * S);
     const float nu = k.h * wab * S * inv;
-    const float Pi = wab < 0.0f ? (-k.alpha_c * nu + k.beta * nu * nu) * 2.0f * D * inv : 0.0f;
+    const float alpha_c = kExt ? k.alpha * (0.5f * (fabsf(ca) + fabsf(cb))) : k.alpha_c;
+    const float Pi = wab < 0.0f ? (-alpha_c * nu + k.beta * nu * nu) * 2.0f * D * inv : 0.0f;
     const float bxx = Bxx - Pi, byy = Byy - Pi, bzz = Bzz - Pi;
-    a.ax.add(mb * (bxx * gx + Bxy * gy + Bxz * gz));
-    a.ay.add(mb * (Bxy * gx + byy * gy + Byz * gz));
-    a.az.add(mb * (Bxz * gx + Byz * gy + bzz * gz));
+    float qx = bxx * gx + Bxy * gy + Bxz * gz;
+    float qy = Bxy * gx + byy * gy + Byz * gz;
+    float qz = Bxz * gx + Byz * gy + bzz * gz;
+    if constexpr (kExt) {
+        a.du.add(mb * (dvx * qx + dvy * qy + dvz * qz));
+        const float xw = mb * k.Wn * w * (2.0f * D * inv);  // 2 m_b W / (rho_a + rho_b)
+        a.xs[0].add(xw * dvx);
+        a.xs[1].add(xw * dvy);
+        a.xs[2].add(xw * dvz);
+        const bool ta = signbit(ca), tb = signbit(cb);
+        if (k.eps_s > 0.0f && (ta || tb)) {
+            const float f = w * k.inv_wm;
+            float fn = f;
+            if (k.n_int > 0) {
+                for (int e = 1; e < k.n_int; ++e) fn *= f;
+            } else {
+                fn = powf(f, k.n_s);
+            }
+            const float za = ta ? -k.eps_s : 0.0f, zb = tb ? -k.eps_s : 0.0f;
+            float Z[6];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) Z[i] = (za * Ta[i] + zb * Tb[i]) * fn;
+            qx += Z[0] * gx + Z[3] * gy + Z[4] * gz;
+            qy += Z[3] * gx + Z[1] * gy + Z[5] * gz;
+            qz += Z[4] * gx + Z[5] * gy + Z[2] * gz;
+        }
+    }
+    a.ax.add(mb * qx);
+    a.ay.add(mb * qy);
+    a.az.add(mb * qz);
     if constexpr (kCorr) {
         const float P = -Vb * F;
         const float px = P * rx, py = P * ry, pz = P * rz;

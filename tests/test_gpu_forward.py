@@ -298,11 +298,11 @@ def test_rhs_corrected_linear_field_exact(precision, tol, path):
 
 # ---- energy equation, artificial stress, XSPH (sections 3.1.2, 3.1.4, 3.1.5) ----
 
-def gpu_rhs_extra(w, **path):
+def gpu_rhs_extra(w, precision="fp64", **path):
     st = gpu_state(w)
     g = P.sph_build_cells(st.pos, w.h, skin=path.get("skin", 0.0),
                           cells_per_h=path.get("cells_per_h", 1), pairs=path.get("pairs", False))
-    out = P.sph_rhs(g, st, w.params, "fp64", extra=True)
+    out = P.sph_rhs(g, st, w.params, precision, extra=True)
     assert P.workspace_status(out["_ws"]) == 0
     return {k: v.cpu().numpy() for k, v in out.items() if k != "_ws"}
 
@@ -315,19 +315,20 @@ def extra_err(got, ref, v):
     return e
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32comp"])
 @pytest.mark.parametrize("path", ["cells1", "pairs2_skin"])
 @pytest.mark.parametrize("name", ["cube16", "cube12_visc"])
-def test_rhs_extra_terms_match_oracle(name, path):
+def test_rhs_extra_terms_match_oracle(name, path, precision):
     w = _variant(name)
     w.params.update(eps_s=0.2, n_s=4.0, xsph=0.5)
     assert (w.rho < w.params["rho0"]).any()  # some particles in tension
     ref = native.rhs_workload(w, want_extra=True)
-    got = gpu_rhs_extra(w, **PATHS[path])
+    got = gpu_rhs_extra(w, precision, **PATHS[path])
     err = normwise(got, ref, w.rho)
-    bad = {k: v for k, v in err.items() if not v <= TOL["fp64"]}
+    bad = {k: v for k, v in err.items() if not v <= TOL[precision]}
     assert not bad, bad
     err = extra_err(got, ref, w.vel)
-    assert max(err.values()) <= TOL["fp64"], err
+    assert max(err.values()) <= TOL[precision], err
     w.params["eps_s"] = 0.0  # the artificial stress acts on this state
     plain = native.rhs_workload(w)
     assert np.abs(plain["acc"] - ref["acc"]).max() > 1e-6 * np.abs(ref["acc"]).max()
@@ -349,9 +350,6 @@ def test_extra_terms_refused_where_not_built():
     w.params.update(eps_s=0.2)
     st = gpu_state(w)
     g = P.sph_build_cells(st.pos, w.h)
-    with pytest.raises(L.SphError) as e:
-        P.sph_rhs(g, st, w.params, "fp32comp")
-    assert e.value.code == L.SPH_ERR_NOT_IMPLEMENTED
     with pytest.raises(L.SphError) as e:
         P.sph_rhs_adjoint(g, st, w.params, {"acc": torch.ones(3, w.n, dtype=torch.float64).cuda()})
     assert e.value.code == L.SPH_ERR_NOT_IMPLEMENTED
@@ -392,20 +390,21 @@ def eos_variant(kind, seed=21):
     return w
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32comp"])
 @pytest.mark.parametrize("kind", [1, 2])
 @pytest.mark.parametrize("path", ["cells1", "pairs2_skin"])
-def test_rhs_equations_of_state_match_oracle(kind, path):
+def test_rhs_equations_of_state_match_oracle(kind, path, precision):
     w = eos_variant(kind)
     ref = native.rhs_workload(w)
     st = P.ParticleState.from_arrays(w.pos, w.vel, w.rho, w.S, w.m, u=getattr(w, "u", None))
     pth = PATHS[path]
     g = P.sph_build_cells(st.pos, w.h, skin=pth.get("skin", 0.0), cells_per_h=pth.get("cells_per_h", 1),
                           pairs=pth.get("pairs", False))
-    out = P.sph_rhs(g, st, w.params, "fp64")
+    out = P.sph_rhs(g, st, w.params, precision)
     assert P.workspace_status(out["_ws"]) == 0
     got = {k: v.cpu().numpy() for k, v in out.items() if k != "_ws"}
     err = normwise(got, ref, w.rho)
-    bad = {k: v for k, v in err.items() if not v <= TOL["fp64"]}
+    bad = {k: v for k, v in err.items() if not v <= TOL[precision]}
     assert not bad, bad
     w.params["eos"] = 0.0  # the equations differ from the liquid one on this state
     plain = native.rhs_workload(w)
@@ -416,8 +415,7 @@ def test_equations_of_state_refused_where_not_built():
     w = eos_variant(2)
     st = P.ParticleState.from_arrays(w.pos, w.vel, w.rho, w.S, w.m, u=w.u)
     g = P.sph_build_cells(st.pos, w.h)
-    for call in (lambda: P.sph_rhs(g, st, w.params, "fp32comp"),
-                 lambda: P.sph_leapfrog(g, st, w.params, w.dt, 2),
+    for call in (lambda: P.sph_leapfrog(g, st, w.params, w.dt, 2),
                  lambda: P.sph_rhs_adjoint(g, st, w.params,
                                            {"acc": torch.ones(3, w.n, dtype=torch.float64).cuda()})):
         with pytest.raises(L.SphError) as e:
@@ -425,22 +423,25 @@ def test_equations_of_state_refused_where_not_built():
         assert e.value.code == L.SPH_ERR_NOT_IMPLEMENTED
 
 
-def test_tillotson_artificial_stress_takes_tension_from_the_pressure():
+@pytest.mark.parametrize("precision", ["fp64", "fp32comp"])
+def test_tillotson_artificial_stress_takes_tension_from_the_pressure(precision):
     # with u > 0 the Tillotson pressure stays positive somewhat below rho0: the tension
     # test must follow the pressure, not the density
     w = eos_variant(2)
-    w.params.update(eps_s=0.2, n_s=4.0)
+    w.params.update(eps_s=0.2, n_s=4.0, xsph=0.5)
     p, _ = native.eos(w.rho, w.param_vector(), w.u)
     assert ((w.rho < w.params["rho0"]) & (p >= 0)).any()
-    ref = native.rhs_workload(w)
+    ref = native.rhs_workload(w, want_extra=True)
     st = P.ParticleState.from_arrays(w.pos, w.vel, w.rho, w.S, w.m, u=w.u)
     g = P.sph_build_cells(st.pos, w.h, skin=0.05 * w.dx, cells_per_h=2, pairs=True)
-    out = P.sph_rhs(g, st, w.params, "fp64")
+    out = P.sph_rhs(g, st, w.params, precision, extra=True)
     assert P.workspace_status(out["_ws"]) == 0
     got = {k: v.cpu().numpy() for k, v in out.items() if k != "_ws"}
     err = normwise(got, ref, w.rho)
-    bad = {k: v for k, v in err.items() if not v <= TOL["fp64"]}
+    bad = {k: v for k, v in err.items() if not v <= TOL[precision]}
     assert not bad, bad
+    err = extra_err(got, ref, w.vel)
+    assert max(err.values()) <= TOL[precision], err
 
 
 # ---- Grady-Kipp damage (sections 2.7, 3.2) ----
