@@ -43,6 +43,9 @@ CELLS_PER_H = 2  # cell edge (h + skin) / 2: fewer candidates per row sweep than
 FLOPS_RHS, FLOPS_RHS_APPROACH = 83.0, 10.0
 FLOPS_ADJ, FLOPS_ADJ_APPROACH = 222.0, 23.0
 FLOPS_ADJ_L = 45.0  # the adjoint's recomputation of the velocity gradient
+# gravity walk, per body taken: distance (3), r^2 (5), opening test (3), force with a
+# refined reciprocal square root and the reciprocal of r + eps (11)
+FLOPS_GRAV_TERM = 22
 
 
 def parse():
@@ -346,7 +349,10 @@ def main():
     ms = median_ms(lambda: P.sph_gravity(st.pos, mt, 6.674e-11, 0.5, 0.5 * w.dx, ws=wsg),
                    args.form_reps, torch)
     forms["gravity_bh_theta0.5"] = {"ms": ms, "inner_nodes": go["nodes"], "terms": terms,
-                                    "terms_per_s": terms / (ms * 1e-3)}
+                                    "terms_per_s": terms / (ms * 1e-3),
+                                    "tflops_algorithmic": terms * FLOPS_GRAV_TERM / (ms * 1e-3) / 1e12,
+                                    "frac_of_fp64_peak": terms * FLOPS_GRAV_TERM / (ms * 1e-3) / 1e12
+                                    / PEAK_FP64_TFLOPS}
     forms["fp32comp_speedup_vs_fp64"] = forms["rhs_fp64"]["ms"] / forms["rhs_fp32comp"]["ms"]
     cg = {k: torch.randn_like(outs["fp64"][k]) for k in fields}
     ms = median_ms(lambda: P.sph_rhs_adjoint(g, st, w.params, cg, ws=ws_adj), args.form_reps, torch)

@@ -563,3 +563,26 @@ def test_damage_refused_where_not_built_and_bad_flaw_lists_flagged():
     out = P.sph_rhs(g, bad, w.params, damage=True)
     assert P.workspace_status(out["_ws"]) == L.SPH_ERR_DOMAIN
     assert int(out["n_act"][1]) == 0 and float(out["dd3"][1]) == 0.0
+
+
+def test_damage_at_full_size_on_sampled_targets():
+    # the bullet-into-cube set (2,105,344 particles, random state) with damage uniform in
+    # [0, 1] and basalt flaws over the target's volume: 4,096 sampled targets
+    w = W.config(2, state="random")
+    rng = np.random.default_rng(41)
+    w.d = rng.uniform(0.0, 1.0, w.n)
+    w.flaws = W.flaws(w.n, float(np.sum(w.m) / w.params["rho0"]), 1e61, 16.0, 42)
+    idx = W.subsample(w.n, 4096, 43)
+    ref = native.rhs(w.pos, w.vel, w.rho, w.S, w.m, w.param_vector(), targets=idx, d=w.d)
+    got = gpu_rhs_damage(w, "fp64", skin=0.1 * w.dx, pairs=True, cells_per_h=2)
+    err = normwise({k: v[..., idx] for k, v in got.items()}, ref, w.rho[idx])
+    bad = {k: v for k, v in err.items() if not v <= TOL["fp64"]}
+    assert not bad, bad
+    from oracle import damage as D
+    sub_ptr = np.concatenate([[0], np.cumsum(np.diff(w.flaws[0])[idx])])
+    sub_eps = np.concatenate([w.flaws[1][w.flaws[0][a]:w.flaws[0][a + 1]] for a in idx])
+    rate, nact, _ = D.rates(w.rho[idx], w.S[:, idx], w.m[idx], w.param_vector(), sub_ptr, sub_eps,
+                            d=w.d[idx])
+    same = got["n_act"][idx] == nact
+    assert same.mean() > 0.999
+    assert np.all(np.abs(got["dd3"][idx][same] - rate[same]) <= 1e-13 * np.abs(rate[same]))

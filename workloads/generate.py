@@ -314,13 +314,21 @@ def flaws(n: int, volume: float, k_w: float, m_w: float, seed: int):
     particle holds at least one.  Returns (flaw_ptr int64 [n + 1], flaw_eps [total]), each
     particle's thresholds ascending."""
     rng = np.random.default_rng(seed)
-    draws = max(64, int(n * (np.log(n) + 12.0)))
-    owner = rng.integers(0, n, draws)
-    seen, first = np.unique(owner, return_index=True)
-    if seen.size < n:
-        raise RuntimeError("too few draws to give every particle a flaw")
-    total = int(first.max()) + 1
-    owner = owner[:total]
+    seen = np.zeros(n, dtype=bool)
+    remaining = n
+    chunks = []
+    while True:
+        chunk = rng.integers(0, n, max(n, 64))
+        pos = np.nonzero(~seen[chunk])[0]
+        new, first = np.unique(chunk[pos], return_index=True)
+        if new.size == remaining:  # the last particle without a flaw gets one here
+            chunks.append(chunk[: pos[first].max() + 1])
+            break
+        seen[new] = True
+        remaining -= new.size
+        chunks.append(chunk)
+    owner = np.concatenate(chunks)
+    total = owner.size
     j = np.arange(1, total + 1, dtype=np.float64)
     eps = (j / (k_w * volume)) ** (1.0 / m_w)
     order = np.argsort(owner, kind="stable")
