@@ -11,6 +11,7 @@ from . import _lib  # noqa: F401
 from .api import (  # noqa: F401
     CellGrid,
     ParticleState,
+    SphRhs,
     sph_build_cells,
     sph_build_pairs,
     sph_gravity,

@@ -314,3 +314,38 @@ def test_nonuniform_adjoint_matches_directional_derivative():
     # between two large totals)
     fd = sum(float((cot[k] * (op[k] - om_[k])).sum()) for k in cot) / 2.0
     assert abs(fd - pred) <= 1e-6 * abs(pred), (fd, pred)
+
+
+def test_autograd_function_matches_adjoint_and_oracle():
+    # SphRhs: forward = sph_rhs, backward = sph_rhs_adjoint, through torch.autograd
+    w = small("cube8_visc")
+    ref_out = native.rhs_workload(w, want_L=False)
+    rng = np.random.default_rng(9)
+    cot = {k: rng.normal(size=ref_out[k].shape) / np.abs(ref_out[k]).max() for k in ref_out}
+    ref = AD.rhs_vjp(w, cot)
+    st = gpu_state(w)
+    g = P.sph_build_cells(st.pos, w.h, skin=0.05 * w.dx, pairs=True)
+    leaves = [t.clone().requires_grad_(True) for t in (st.pos, st.vel, st.rho, st.S)]
+    mu = torch.tensor(w.params["mu"], dtype=torch.float64, device="cuda", requires_grad=True)
+    Y0 = torch.tensor(w.params["Y0"], dtype=torch.float64, device="cuda", requires_grad=True)
+    outs = P.SphRhs.apply(*leaves, mu, Y0, g, w.params, st.m)
+    direct = P.sph_rhs(g, st, w.params, "fp64")
+    for k, o in zip(("acc", "drho", "dS", "rho_sum"), outs):
+        assert torch.equal(o, direct[k]), k
+    loss = sum((o * torch.as_tensor(cot[k]).cuda()).sum()
+               for k, o in zip(("acc", "drho", "dS", "rho_sum"), outs))
+    loss.backward()
+    cg = {k: torch.as_tensor(v).cuda().contiguous() for k, v in cot.items()}
+    adj = P.sph_rhs_adjoint(g, st, w.params, cg)
+    for k, t in zip(("pos", "vel", "rho", "S"), leaves):
+        assert torch.equal(t.grad, adj[k]), k
+        assert rel(t.grad.cpu().numpy(), ref[k]) < 1e-11, k
+    assert abs(float(mu.grad) - ref["mu"]) <= 1e-11 * abs(ref["mu"])
+    assert abs(float(Y0.grad) - ref["Y0"]) <= 1e-11 * max(abs(ref["Y0"]), 1e-300)
+    # outputs left out of the loss get zero cotangents
+    leaves2 = [t.clone().requires_grad_(True) for t in (st.pos, st.vel, st.rho, st.S)]
+    outs2 = P.SphRhs.apply(*leaves2, mu.detach(), Y0.detach(), g, w.params, st.m)
+    (outs2[0] * torch.as_tensor(cot["acc"]).cuda()).sum().backward()
+    only = AD.rhs_vjp(w, {"acc": cot["acc"], "drho": np.zeros_like(cot["drho"]),
+                          "dS": np.zeros_like(cot["dS"]), "rho_sum": np.zeros_like(cot["rho_sum"])})
+    assert rel(leaves2[0].grad.cpu().numpy(), only["pos"]) < 1e-11
