@@ -46,7 +46,7 @@ enum sph_status {
     SPH_ERR_CAPACITY = -2,      /* an output array is too small; the required size is returned */
     SPH_ERR_WORKSPACE = -3,     /* workspace smaller than sph_workspace_bytes() */
     SPH_ERR_HIP = -4,           /* a HIP runtime call or launch failed */
-    SPH_ERR_DOMAIN = -5,        /* device flag: non-finite position or non-positive density */
+    SPH_ERR_DOMAIN = -5,        /* device flag: non-finite input or non-positive density */
     SPH_ERR_NOT_IMPLEMENTED = -6,
     SPH_ERR_STALE_GRID = -7     /* device flag: a particle left its cell by more than skin/2 */
 };
@@ -296,7 +296,8 @@ int sph_neighbours(const sph_grid *grid, const double *x, const double *y, const
  * precision: enum sph_precision.  Outputs are overwritten (user order).
  * Errors: INVALID_ARG (state->n != grid->n, h > grid->h, non-finite or
  * non-positive h, c, rho0, negative mu or Y0, ...), WORKSPACE.  Device flags
- * STALE_GRID, DOMAIN. */
+ * STALE_GRID, DOMAIN (non-positive density; non-finite density, velocity or
+ * stress). */
 int sph_rhs(const sph_grid *grid, const sph_state *state, const sph_params *params,
             int precision, const sph_deriv *out, void *ws, size_t ws_bytes, void *stream);
 

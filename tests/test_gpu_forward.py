@@ -211,13 +211,17 @@ def test_stale_grid_is_flagged(pairs):
     assert P.workspace_status(out["_ws"]) == 0
 
 
-def test_nonpositive_density_is_flagged():
+@pytest.mark.parametrize("field,index,value", [("rho", (5,), -1.0), ("rho", (7,), np.inf),
+                                               ("S", (3, 11), np.nan), ("vel", (1, 2), np.inf)])
+def test_bad_state_is_flagged(field, index, value):
     w = W.config(0)
-    w.rho[5] = -1.0
+    getattr(w, field)[index] = value
     st = gpu_state(w)
     g = P.sph_build_cells(st.pos, w.h)
     out = P.sph_rhs(g, st, w.params)
     assert P.workspace_status(out["_ws"]) == L.SPH_ERR_DOMAIN
+    ok = P.sph_rhs(g, gpu_state(W.config(0)), w.params)  # a clean call clears the flag
+    assert P.workspace_status(ok["_ws"]) == 0
 
 
 def _subsample_parity(w, k, precision, seed):
