@@ -590,3 +590,43 @@ def test_damage_at_full_size_on_sampled_targets():
     same = got["n_act"][idx] == nact
     assert same.mean() > 0.999
     assert np.all(np.abs(got["dd3"][idx][same] - rate[same]) <= 1e-13 * np.abs(rate[same]))
+
+
+def _state_on(pos, h, seed, **over):
+    """A random state (velocities, densities, stresses, masses) on given positions."""
+    rng = np.random.default_rng(seed)
+    n = pos.shape[1]
+    vel, rho, S = W.random_state(n, rng, W.MATERIAL["rho0"], W.MATERIAL["c"])
+    m = W.MATERIAL["rho0"] * (h / 2.4) ** 3 * rng.uniform(0.8, 1.2, n)
+    p = dict(W.MATERIAL, h=h, dmpd=h / 2.4, alpha=1.0, beta=1.0, **over)
+    return W.Workload("edge", np.ascontiguousarray(pos), vel, rho, S, m, h, h / 2.4,
+                      {k: p[k] for k in W.generate.PARAM_ORDER})
+
+
+@pytest.mark.parametrize("case", ["single", "pair_at_h", "adversarial", "clumps"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32comp"])
+@pytest.mark.parametrize("path", ["cells1", "pairs2_skin"])
+def test_rhs_edge_sets_match_oracle(case, precision, path):
+    # one particle; two particles exactly h apart (no pair); coincident points, partners
+    # one ulp inside h, points on cell faces and an isolated point; clumps whose rows
+    # hold up to 299 partners
+    h = 0.3
+    pos = {"single": lambda: np.full((3, 1), 0.5),
+           "pair_at_h": lambda: np.array([[0.0, h], [0.0, 0.0], [0.0, 0.0]]),
+           "adversarial": lambda: adversarial(h),
+           "clumps": lambda: clumps(h)}[case]()
+    w = _state_on(pos, h, seed=51)
+    ref = native.rhs_workload(w)
+    pth = dict(PATHS[path])
+    if "skin" in pth:
+        pth["skin"] = 0.01 * h
+    got = gpu_rhs(w, precision, **pth)
+    if case in ("single", "pair_at_h"):
+        # no partner: only the self term of the density sum
+        for k in ("acc", "drho", "dS"):
+            assert np.all(got[k] == 0.0) and np.all(ref[k] == 0.0), k
+        assert np.allclose(got["rho_sum"], ref["rho_sum"], rtol=1e-15)
+        return
+    err = normwise(got, ref, w.rho)
+    bad = {k: v for k, v in err.items() if not v <= TOL[precision]}
+    assert not bad, bad
