@@ -349,3 +349,30 @@ def test_autograd_function_matches_adjoint_and_oracle():
     only = AD.rhs_vjp(w, {"acc": cot["acc"], "drho": np.zeros_like(cot["drho"]),
                           "dS": np.zeros_like(cot["dS"]), "rho_sum": np.zeros_like(cot["rho_sum"])})
     assert rel(leaves2[0].grad.cpu().numpy(), only["pos"]) < 1e-11
+
+
+@pytest.mark.parametrize("case", ["single", "pair_at_h", "clumps"])
+def test_rhs_adjoint_edge_sets(case):
+    # one particle and a pair exactly h apart (no pair terms: only the density sum's
+    # self term, which has no gradient); dense clumps with rows of up to 299 partners
+    import test_gpu_forward as F
+    h = 0.3
+    pos = {"single": lambda: np.full((3, 1), 0.5),
+           "pair_at_h": lambda: np.array([[0.0, h], [0.0, 0.0], [0.0, 0.0]]),
+           "clumps": lambda: F.clumps(h)}[case]()
+    w = F._state_on(pos, h, seed=53)
+    rng = np.random.default_rng(5)
+    ref_out = native.rhs_workload(w, want_L=False)
+    cot = {k: rng.normal(size=ref_out[k].shape) for k in ref_out}
+    st = gpu_state(w)
+    for pairs in (False, True):
+        g = P.sph_build_cells(st.pos, w.h, skin=0.01 * h, pairs=pairs)
+        got = P.sph_rhs_adjoint(g, st, w.params, {k: torch.as_tensor(v).cuda() for k, v in cot.items()})
+        assert P.workspace_status(got["_ws"]) == 0
+        if case != "clumps":
+            for k in ("pos", "vel", "rho", "S"):
+                assert torch.all(got[k] == 0.0), k
+            continue
+        ref = AD.rhs_vjp(w, cot)
+        for k in ("pos", "vel", "rho", "S"):
+            assert rel(got[k].cpu().numpy(), ref[k]) < 1e-11, k
