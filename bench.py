@@ -171,6 +171,20 @@ def cpu_baseline(w, budget_s=12.0):
                       f"in {el:.1f} s on {cores} threads; {reps1} repetitions in {el1:.1f} s on one"}
 
 
+def cpu_gravity_baseline(w, targets=16384):
+    """The gravity oracle beside the GPU form: its tree over every body (built serially)
+    and the walks of a sample of bodies, on the host's threads."""
+    from oracle import native
+    idx = np.linspace(0, w.n - 1, min(targets, w.n)).astype(np.int64)
+    t0 = time.perf_counter()
+    out = native.gravity(w.pos, w.m, 6.674e-11, 0.5, 0.5 * w.dx, targets=idx)
+    el = time.perf_counter() - t0
+    terms = int(out["count"].sum())
+    return {"terms_per_s": terms / el, "cores": native.threads(), "kind": "oracle",
+            "sample": f"tree of all {w.n} bodies and the walks of {idx.size} evenly spaced "
+                      f"bodies ({terms} terms) in {el:.2f} s, tree build included"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -399,6 +413,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w)
+        forms["gravity_bh_theta0.5"]["cpu_oracle"] = cpu_gravity_baseline(w)
     print(json.dumps(result), flush=True)
 
 
