@@ -171,7 +171,7 @@ def cpu_baseline(w, budget_s=12.0):
                       f"in {el:.1f} s on {cores} threads; {reps1} repetitions in {el1:.1f} s on one"}
 
 
-def cpu_gravity_baseline(w, targets=16384):
+def cpu_gravity_baseline(w, targets=131072):
     """The gravity oracle beside the GPU form: its tree over every body (built serially)
     and the walks of a sample of bodies, on the host's threads."""
     from oracle import native
