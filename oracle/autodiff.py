@@ -11,7 +11,9 @@ readings as ``sph_oracle.c`` (see its header for the passages):
   momentum with artificial viscosity (section 3.1.2, 3.1.3), standard velocity
   gradient or the corrected one L C with C = M^-1, M = sum_b V_b (x_b - x_a) (x)
   grad_a W_ab (section 3.1.6; identity where M is singular), Hooke's law with
-  Jaumann terms R S - S R (section 2.4).
+  Jaumann terms R S - S R (section 2.4), and optionally a fixed damage field d
+  (section 2.7): sigma_d = -p^ I + (1 - d) f_Y S, p^ = p for p >= 0 and (1 - d) p
+  below, in the momentum equation only.
 
 Also the kick-drift-kick leapfrog used to drive the adjoint (the paper's own
 integrators are the predictor-corrector and RK3 of section 3.4; the leapfrog
@@ -89,11 +91,12 @@ def correction_tensor(M: torch.Tensor) -> torch.Tensor:
     return torch.where(ok, A / torch.where(ok, det, torch.ones_like(det)), eye)
 
 
-def rhs(pos, vel, rho, S6, m, par, mu=None, Y0=None, pairs=None):
+def rhs(pos, vel, rho, S6, m, par, mu=None, Y0=None, pairs=None, d=None):
     """Right-hand side of every particle.  ``par`` = {h, rho0, c, mu, Y0, alpha,
     beta, eps_v, rho_cut, correction}; ``mu``/``Y0`` may be tensors (differentiable)
-    overriding par[3]/par[4].  Returns dict acc (3, n), drho, dS (6, n), rho_sum, L (3, 3, n)
-    (L: the gradient that drives the stress rate, corrected when par[9] != 0)."""
+    overriding par[3]/par[4]; ``d`` (n) a damage field held fixed.  Returns dict
+    acc (3, n), drho, dS (6, n), rho_sum, L (3, 3, n) (L: the gradient that drives the
+    stress rate, corrected when par[9] != 0)."""
     h, rho0, c = float(par[0]), float(par[1]), float(par[2])
     alpha, beta, eps_v, rho_cut = float(par[5]), float(par[6]), float(par[7]), float(par[8])
     corr = len(par) > 9 and float(par[9]) != 0.0
@@ -111,7 +114,12 @@ def rhs(pos, vel, rho, S6, m, par, mu=None, Y0=None, pairs=None):
     f = yield_factor(S6, Y0)
     St = _mat(f * S6)
     eye = torch.eye(3, dtype=DT).unsqueeze(-1)
-    sig = St - p * eye
+    if d is None:
+        sig = St - p * eye
+    else:
+        keep = 1.0 - torch.as_tensor(np.asarray(d, dtype=np.float64))
+        ph = torch.where(p >= 0, p, keep * p)
+        sig = keep * St - ph * eye
     T = sig / (rho * rho)
 
     # pair terms
@@ -170,7 +178,7 @@ def rhs_vjp(w, cot: dict, pairs=None):
     Y0 = torch.tensor(float(par[4]), dtype=DT, requires_grad=True)
     for t in (pos, vel, rho, S):
         t.requires_grad_(True)
-    out = rhs(pos, vel, rho, S, m, par, mu=mu, Y0=Y0, pairs=pairs)
+    out = rhs(pos, vel, rho, S, m, par, mu=mu, Y0=Y0, pairs=pairs, d=getattr(w, "d", None))
     y = 0.0
     for k in ("acc", "drho", "dS", "rho_sum"):
         y = y + (out[k] * torch.from_numpy(np.asarray(cot[k], dtype=np.float64))).sum()

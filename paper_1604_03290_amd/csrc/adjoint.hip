@@ -27,7 +27,10 @@
 //           No atomics: every particle writes only its own gradient.
 //  pre      per particle: through T = (f_Y S - p I)/rho^2, V = m/rho, the
 //           pressure (section 2.5.1) and the limiter f_Y = min(Y0^2/(3 J2), 1)
-//           (section 2.6) to rho_bar, S_bar and Y0_bar.
+//           (section 2.6) to rho_bar, S_bar and Y0_bar.  With a damage field d
+//           (section 2.7, held fixed) T = ((1 - d) f_Y S - p^ I)/rho^2: the
+//           deviator's cotangent carries the factor 1 - d, and so does the
+//           pressure's slope where p < 0.
 //
 // mu_bar and Y0_bar are reduced per block with a fixed tree and then by one
 // block in a fixed order, so results are reproducible bit for bit.
@@ -288,8 +291,8 @@ __device__ inline AdjOwn adj_own(const double *rec, const AdjRec &ad, int64_t s)
     return o;
 }
 
-// pre stage: T = (f S - p I) / rho^2, V = m / rho, pressure, limiter; writes the
-// gradients of user particle a; returns the Y0 contribution
+// pre stage: T = ((1 - d) f S - p^ I) / rho^2, V = m / rho, pressure, limiter; writes
+// the gradients of user particle a; returns the Y0 contribution
 __device__ inline double adj_pre(const Consts &k, const AdjRec &ad, const AdjOwn &o,
                                  const AdjAcc &acc, int64_t s, int a, const StateDev &st,
                                  const GradDev &out) {
@@ -299,15 +302,17 @@ __device__ inline double adj_pre(const Consts &k, const AdjRec &ad, const AdjOwn
     const double f = limited ? k.Y0sq / (3.0 * j2) : 1.0;
     const double rc = o.rc;
     const double ir2 = 1.0 / (rc * rc);
+    const double keep = st.d ? 1.0 - st.d[a] : 1.0;  // 1 - d
     double grho = ad.rhob[s] + acc.grho - acc.gV * o.Vc / rc;
 #pragma unroll
     for (int i = 0; i < 6; ++i) grho += acc.gT[i] * (-2.0 * o.Tc[i] / rc);
     const bool cut = k.rho_cut > 0.0 && rc / k.rho0 < k.rho_cut;
-    if (!cut) grho += k.c2 * (-(acc.gT[0] + acc.gT[1] + acc.gT[2]) * ir2);
+    const double slope = rc < k.rho0 ? keep * k.c2 : k.c2;  // dp^/drho
+    if (!cut) grho += slope * (-(acc.gT[0] + acc.gT[1] + acc.gT[2]) * ir2);
     double Stb[6], fb = 0.0;
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-        Stb[i] = acc.gT[i] * ir2 + ad.Stb[i][s];
+        Stb[i] = acc.gT[i] * (ir2 * keep) + ad.Stb[i][s];
         fb += Stb[i] * S[i];
     }
     double gS[6];
@@ -561,7 +566,6 @@ extern "C" int sph_rhs_adjoint(const sph_grid *grid, const sph_state *state,
         return fail(SPH_ERR_NOT_IMPLEMENTED, "adjoint with the artificial stress");
     if (params->eos != 0.0)
         return fail(SPH_ERR_NOT_IMPLEMENTED, "adjoint with the Murnaghan or Tillotson equation");
-    if (state->d) return fail(SPH_ERR_NOT_IMPLEMENTED, "adjoint with damage");
     const size_t need = adjoint_ws_bytes(grid->n);
     if (ws_bytes < need) return fail(SPH_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
     hipStream_t s = (hipStream_t)stream;

@@ -376,3 +376,29 @@ def test_rhs_adjoint_edge_sets(case):
         ref = AD.rhs_vjp(w, cot)
         for k in ("pos", "vel", "rho", "S"):
             assert rel(got[k].cpu().numpy(), ref[k]) < 1e-11, k
+
+
+@pytest.mark.parametrize("pairs", [False, True])
+def test_rhs_adjoint_with_damage_matches_oracle(pairs):
+    # a fixed damage field (section 2.7), densities on both sides of rho0: the adjoint
+    # against the reverse-mode product of the oracle's transcription with the same field
+    w = small("cube8_visc")
+    rng = np.random.default_rng(17)
+    w.d = rng.uniform(0.0, 1.0, w.n)
+    w.d[rng.random(w.n) < 0.2] = 0.0
+    w.d[rng.random(w.n) < 0.05] = 1.0
+    w.rho = w.params["rho0"] * rng.uniform(0.995, 1.005, w.n)
+    ref_out = native.rhs_workload(w, want_L=False)
+    cot = {k: rng.normal(size=ref_out[k].shape) / np.abs(ref_out[k]).max() for k in ref_out}
+    ref = AD.rhs_vjp(w, cot)
+    st = P.ParticleState.from_arrays(w.pos, w.vel, w.rho, w.S, w.m, d=w.d)
+    g = P.sph_build_cells(st.pos, w.h, skin=0.05 * w.dx, pairs=pairs)
+    got = P.sph_rhs_adjoint(g, st, w.params, {k: torch.as_tensor(v).cuda() for k, v in cot.items()})
+    assert P.workspace_status(got["_ws"]) == 0
+    for k in ("pos", "vel", "rho", "S"):
+        assert rel(got[k].cpu().numpy(), ref[k]) < 1e-11, k
+    assert abs(float(got["mu"]) - ref["mu"]) <= 1e-11 * abs(ref["mu"])
+    # the damage matters here
+    w.d = None
+    plain = AD.rhs_vjp(w, cot)
+    assert rel(plain["rho"], ref["rho"]) > 1e-3

@@ -136,3 +136,31 @@ def test_unlimited_yield_stress_has_zero_gradient():
     g = AD.leapfrog_grad(w, 3, 0.2 * w.dx / 5000.0, "ke")
     assert g["Y0"] == 0.0
     assert g["mu"] != 0.0
+
+
+def test_torch_transcription_with_damage_matches_c_oracle_and_finite_differences():
+    # a fixed damage field (section 2.7): the transcription against the C oracle, and its
+    # reverse-mode product against central differences of the C oracle in rho and S
+    w = small(seed=13, alpha=1.0, beta=1.0)
+    rng = np.random.default_rng(14)
+    w.d = rng.uniform(0.0, 1.0, w.n)
+    w.rho = w.params["rho0"] * rng.uniform(0.995, 1.005, w.n)  # both signs of p
+    ref = native.rhs_workload(w)
+    out = AD.rhs(*AD.as_tensors(w), d=w.d)
+    for k in ("acc", "drho", "dS", "rho_sum"):
+        a, b = ref[k], out[k].numpy()
+        assert np.abs(a - b).max() <= 1e-14 * np.abs(a).max(), k
+    y = {k: rng.normal(size=ref[k].shape) / np.abs(ref[k]).max() for k in ("acc", "drho", "dS", "rho_sum")}
+    g = AD.rhs_vjp(w, y)
+    for which, scale in (("rho", 2700.0 * 1e-4), ("S", 6.75e7)):
+        u = rng.normal(size=getattr(w, which).shape)
+        ad = float((g[which] * u).sum())
+        eps = 1e-6 * scale
+        vals = []
+        for sgn in (+1, -1):
+            wp = w.copy()
+            wp.d = w.d
+            setattr(wp, which, getattr(w, which) + sgn * eps * u)
+            vals.append(_objective(wp, y))
+        fd = (vals[0] - vals[1]) / (2 * eps)
+        assert abs(fd - ad) <= 1e-6 * abs(ad), (which, fd, ad)
