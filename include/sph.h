@@ -297,7 +297,7 @@ int sph_neighbours(const sph_grid *grid, const double *x, const double *y, const
  * Errors: INVALID_ARG (state->n != grid->n, h > grid->h, non-finite or
  * non-positive h, c, rho0, negative mu or Y0, ...), WORKSPACE.  Device flags
  * STALE_GRID, DOMAIN (non-positive density; non-finite density, velocity or
- * stress). */
+ * stress; damage outside [0, 1]; flaw offsets out of order). */
 int sph_rhs(const sph_grid *grid, const sph_state *state, const sph_params *params,
             int precision, const sph_deriv *out, void *ws, size_t ws_bytes, void *stream);
 

@@ -558,6 +558,10 @@ def test_damage_refused_where_not_built_and_bad_flaw_lists_flagged():
         P.sph_rhs(g, st, dict(w.params, mu=0.0), damage=True)
     assert e.value.code == L.SPH_ERR_INVALID_ARG
     # offsets out of order: flagged, no flaw counted, every read within [0, flaw_ptr[n])
+    d_bad = w.d.copy()
+    d_bad[9] = 1.5
+    out = P.sph_rhs(g, P.ParticleState.from_arrays(w.pos, w.vel, w.rho, w.S, w.m, d=d_bad), w.params)
+    assert P.workspace_status(out["_ws"]) == L.SPH_ERR_DOMAIN
     ptr = w.flaws[0].copy()
     ptr[1], ptr[2] = ptr[2], ptr[1]
     bad = P.ParticleState.from_arrays(w.pos, w.vel, w.rho, w.S, w.m, d=w.d, flaws=(ptr, w.flaws[1]))
