@@ -151,7 +151,8 @@ typedef struct {
  * or u <= E_iv, expanded form for rho < rho0 and u >= E_cv, linear in u between).
  * With eos 1 or 2 each particle's sound speed is the thermodynamic one,
  * c^2 = dp/drho|u + p / rho^2 dp/du|rho (floored at 0), and Pi uses the pair's mean
- * (the adjoints and, for Tillotson, the leapfrog refuse them). */
+ * (sph_rhs_adjoint takes Murnaghan and refuses Tillotson; the leapfrog's adjoint
+ * refuses both, the leapfrog refuses Tillotson). */
 typedef struct {
     double h, rho0, c, mu, Y0, alpha, beta, eps_v, rho_cut, correction;
     double eps_s, n_s, dmpd, xsph;
@@ -311,7 +312,9 @@ int sph_rhs(const sph_grid *grid, const sph_state *state, const sph_params *para
  * atomics, reproducible bit for bit.  With params->correction = 1 the
  * correction tensor C = M^-1 is differentiated too (M depends on positions and,
  * through V = m / rho, on densities); where C fell back to the identity M gets
- * no cotangent.  Errors as sph_rhs. */
+ * no cotangent.  With the Murnaghan equation the pressure's slope and the sound
+ * speeds in Pi are differentiated too.  Errors as sph_rhs, and NOT_IMPLEMENTED for
+ * the artificial stress and the Tillotson equation. */
 int sph_rhs_adjoint(const sph_grid *grid, const sph_state *state, const sph_params *params,
                     const sph_deriv_cot *cot, const sph_state_grad *grad, double *dparams,
                     void *ws, size_t ws_bytes, void *stream);

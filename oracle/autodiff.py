@@ -11,7 +11,10 @@ readings as ``sph_oracle.c`` (see its header for the passages):
   momentum with artificial viscosity (section 3.1.2, 3.1.3), standard velocity
   gradient or the corrected one L C with C = M^-1, M = sum_b V_b (x_b - x_a) (x)
   grad_a W_ab (section 3.1.6; identity where M is singular), Hooke's law with
-  Jaumann terms R S - S R (section 2.4), and optionally a fixed damage field d
+  Jaumann terms R S - S R (section 2.4), the Murnaghan equation of state
+  (section 2.5.2: p = K0/n (eta^n - 1), K0 = rho0 c^2, the same tension cut-off,
+  each particle's sound speed sqrt(K0/rho0 eta^(n-1)) averaged over the pair in Pi)
+  when par[14] = 1, and optionally a fixed damage field d
   (section 2.7): sigma_d = -p^ I + (1 - d) f_Y S, p^ = p for p >= 0 and (1 - d) p
   below, in the momentum equation only.
 
@@ -108,7 +111,18 @@ def rhs(pos, vel, rho, S6, m, par, mu=None, Y0=None, pairs=None, d=None):
     i, j = pairs
 
     # prepass: pressure, limiter, stress
-    p = c * c * (rho - rho0)
+    eos = float(par[14]) if len(par) > 14 else 0.0
+    if eos == 1.0:
+        nM = float(par[15])
+        K0 = rho0 * c * c
+        eta = rho / rho0
+        p = K0 / nM * (eta ** nM - 1.0)
+        cs = torch.sqrt(K0 / rho0 * eta ** (nM - 1.0))
+    elif eos == 0.0:
+        p = c * c * (rho - rho0)
+        cs = None
+    else:
+        raise NotImplementedError("the transcription covers the liquid and Murnaghan equations")
     if rho_cut > 0:
         p = torch.where(rho / rho0 < rho_cut, torch.zeros_like(p), p)
     f = yield_factor(S6, Y0)
@@ -143,7 +157,8 @@ def rhs(pos, vel, rho, S6, m, par, mu=None, Y0=None, pairs=None, d=None):
     L = torch.zeros(3, 3, n, dtype=DT).index_add(2, i, Lp)
     w = (dv * rv).sum(0)
     nu = h * w / (r2 + eps_v * h * h)
-    Pi = torch.where(w < 0, (-alpha * c * nu + beta * nu * nu) / (0.5 * (rho[i] + rho[j])),
+    cbar = c if cs is None else 0.5 * (cs[i] + cs[j])
+    Pi = torch.where(w < 0, (-alpha * cbar * nu + beta * nu * nu) / (0.5 * (rho[i] + rho[j])),
                      torch.zeros_like(w))
     B = T[:, :, i] + T[:, :, j] - Pi * eye
     accp = mj * (B * gW.unsqueeze(0)).sum(1)

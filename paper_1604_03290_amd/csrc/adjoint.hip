@@ -27,7 +27,10 @@
 //           No atomics: every particle writes only its own gradient.
 //  pre      per particle: through T = (f_Y S - p I)/rho^2, V = m/rho, the
 //           pressure (section 2.5.1) and the limiter f_Y = min(Y0^2/(3 J2), 1)
-//           (section 2.6) to rho_bar, S_bar and Y0_bar.  With a damage field d
+//           (section 2.6) to rho_bar, S_bar and Y0_bar.  With the Murnaghan
+//           equation (section 2.5.2) dp/drho = K0/rho0 eta^(n-1) and Pi's mean
+//           sound speed (c_c + c_b)/2 carries rho too: cbar_c += Pibar dPi/dcbar / 2
+//           per pair, rho_bar += cbar_c c_c (n - 1) / (2 rho_c).  With a damage field d
 //           (section 2.7, held fixed) T = ((1 - d) f_Y S - p^ I)/rho^2: the
 //           deviator's cotangent carries the factor 1 - d, and so does the
 //           pressure's slope where p < 0.
@@ -184,12 +187,21 @@ __global__ __launch_bounds__(kBlock) void k_adj_post(GridDev g, int64_t n, Const
 struct AdjAcc {
     double gx = 0, gy = 0, gz = 0, gvx = 0, gvy = 0, gvz = 0, grho = 0, gV = 0;
     double gT[6] = {0, 0, 0, 0, 0, 0};
+    double gc = 0;  // cotangent of the particle's sound speed (Murnaghan)
 };
 
 // Own data of particle c in the pair stage.
 struct AdjOwn {
     double xc, yc, zc, vxc, vyc, vzc, rc, mc, Vc, Tc[6], Lbc[9], abx, aby, abz, rsc;
+    double cc;  // sound speed (the forward record's, sign bit cleared)
 };
+
+// Murnaghan sound speed of a partner from its density, as the forward prepass forms it
+__device__ inline double murnaghan_c(const Consts &k, double rho) {
+    const double eta = rho / k.rho0;
+    const double en1 = pow(eta, k.n_M - 1.0);
+    return sqrt(k.K0 / k.rho0 * en1);
+}
 
 // Both roles of the pair (c, b) (see the file header).  b = forward record chunks
 // b0..b6 of the partner (its mass is V rho), e0..e6 = its adjoint record chunks.  With the
@@ -197,7 +209,7 @@ struct AdjOwn {
 // of c and b, whose terms P r r^T (P = -V_b F, r = x_c - x_b) add
 //   xbar_c += -[V_b (2 F Mc r + (r.Mc r) G r) + V_c (2 F Mb r + (r.Mb r) G r)],
 //   Vbar_c += -F (r.Mb r).
-template <bool kCorr = false>
+template <bool kCorr = false, bool kEos = false>
 __device__ inline void adj_pair(const Consts &k, const AdjOwn &o, double d2, double2 b0,
                                 double2 b1, double2 b2, double2 b3, double2 b4, double2 b5,
                                 double2 b6, double2 e0, double2 e1, double2 e2, double2 e3,
@@ -224,7 +236,9 @@ __device__ inline void adj_pair(const Consts &k, const AdjOwn &o, double d2, dou
 #pragma unroll
     for (int i = 0; i < 9; ++i) M[i] = Vb * o.Lbc[i] + o.Vc * Lbb[i];
     const double w = -(ux * rx + uy * ry + uz * rz);
-    const Visc vs = viscosity(k, d2, w, o.rc, rb_, k.alpha_c);
+    double alpha_c = k.alpha_c;
+    if constexpr (kEos) alpha_c = k.alpha * (0.5 * (o.cc + murnaghan_c(k, rb_)));
+    const Visc vs = viscosity(k, d2, w, o.rc, rb_, alpha_c);
     const double Pi = vs.Pi;
     const double B0 = o.Tc[0] + b4.x - Pi, B1 = o.Tc[1] + b4.y - Pi;
     const double B2 = o.Tc[2] + b5.x - Pi, B3 = o.Tc[3] + b5.y;
@@ -235,10 +249,11 @@ __device__ inline void adj_pair(const Consts &k, const AdjOwn &o, double d2, dou
     const double Pib = -(Ax * gx + Ay * gy + Az * gz);
     double wb = 0.0, r2b = 0.0;
     if (w < 0.0) {
-        const double nub = Pib * (-k.alpha_c + 2.0 * k.beta * vs.nu) * vs.coef;
+        const double nub = Pib * (-alpha_c + 2.0 * k.beta * vs.nu) * vs.coef;
         wb = nub * k.h * vs.invD;
         r2b = -nub * vs.nu * vs.invD;
         acc.grho -= Pib * Pi * 0.5 * vs.coef;  // Pi / (rho_c + rho_b)
+        if constexpr (kEos) acc.gc += Pib * (-k.alpha * vs.nu * vs.coef) * 0.5;
     }
     const double rsw = o.rsc * mb + e6.x * o.mc;
     const double rg = rx * gbx + ry * gby + rz * gbz;
@@ -288,11 +303,13 @@ __device__ inline AdjOwn adj_own(const double *rec, const AdjRec &ad, int64_t s)
     o.Lbc[0] = q0.x; o.Lbc[1] = q0.y; o.Lbc[2] = q1.x; o.Lbc[3] = q1.y; o.Lbc[4] = q2.x;
     o.Lbc[5] = q2.y; o.Lbc[6] = q3.x; o.Lbc[7] = q3.y; o.Lbc[8] = q4.x;
     o.abx = q4.y; o.aby = q5.x; o.abz = q5.y; o.rsc = q6.x;
+    o.cc = fabs(p7.y);
     return o;
 }
 
 // pre stage: T = ((1 - d) f S - p^ I) / rho^2, V = m / rho, pressure, limiter; writes
 // the gradients of user particle a; returns the Y0 contribution
+template <bool kEos = false>
 __device__ inline double adj_pre(const Consts &k, const AdjRec &ad, const AdjOwn &o,
                                  const AdjAcc &acc, int64_t s, int a, const StateDev &st,
                                  const GradDev &out) {
@@ -307,7 +324,12 @@ __device__ inline double adj_pre(const Consts &k, const AdjRec &ad, const AdjOwn
 #pragma unroll
     for (int i = 0; i < 6; ++i) grho += acc.gT[i] * (-2.0 * o.Tc[i] / rc);
     const bool cut = k.rho_cut > 0.0 && rc / k.rho0 < k.rho_cut;
-    const double slope = rc < k.rho0 ? keep * k.c2 : k.c2;  // dp^/drho
+    double dp = k.c2;  // dp/drho
+    if constexpr (kEos) {
+        dp = k.K0 / k.rho0 * pow(rc / k.rho0, k.n_M - 1.0);
+        grho += acc.gc * o.cc * (k.n_M - 1.0) / (2.0 * rc);  // dc/drho = c (n - 1) / (2 rho)
+    }
+    const double slope = rc < k.rho0 ? keep * dp : dp;  // dp^/drho
     if (!cut) grho += slope * (-(acc.gT[0] + acc.gT[1] + acc.gT[2]) * ir2);
     double Stb[6], fb = 0.0;
 #pragma unroll
@@ -340,7 +362,7 @@ __device__ inline double adj_pre(const Consts &k, const AdjRec &ad, const AdjOwn
 
 // pair stage + pre stage (see the file header); cell-sweep path, and with the
 // correction tensor the only path (also over a pair list)
-template <bool kCorr>
+template <bool kCorr, bool kEos>
 __global__ __launch_bounds__(kBlock) void k_adj_pairs(GridDev g, int64_t n, Consts k,
                                                       const double *__restrict__ rec, StateDev st,
                                                       AdjRec ad, GradDev out) {
@@ -365,10 +387,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_pairs(GridDev g, int64_t n, Cons
 #pragma unroll
                 for (int i = 0; i < 6; ++i) Mb[i] = ad.Mb[i][t];
             }
-            adj_pair<kCorr>(k, o, d2, b0, b1, rb[2], rb[3], rb[4], rb[5], rb[6], qb[0], qb[1],
-                            qb[2], qb[3], qb[4], qb[5], qb[6], acc, Mc, Mb);
+            adj_pair<kCorr, kEos>(k, o, d2, b0, b1, rb[2], rb[3], rb[4], rb[5], rb[6], qb[0],
+                                  qb[1], qb[2], qb[3], qb[4], qb[5], qb[6], acc, Mc, Mb);
         });
-        y0_part = adj_pre(k, ad, o, acc, s, io_index(g, s), st, out);
+        y0_part = adj_pre<kEos>(k, ad, o, acc, s, io_index(g, s), st, out);
     }
     const double tot = block_sum(y0_part);
     if (threadIdx.x == 0) put(ad.part_y0, blockIdx.x, tot, ad.add_parts);
@@ -376,6 +398,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_pairs(GridDev g, int64_t n, Cons
 
 // the same over the frozen pair list, one wavefront per block: the first seven
 // chunks of each partner's two records gathered cooperatively; Y0 sums per wavefront
+template <bool kEos>
 __global__ __launch_bounds__(64) void k_adj_pairs_list(GridDev g, int64_t n, Consts k,
                                                        const double *__restrict__ rec,
                                                        StateDev st, AdjRec ad, GradDev out) {
@@ -407,7 +430,7 @@ __global__ __launch_bounds__(64) void k_adj_pairs_list(GridDev g, int64_t n, Con
                 const double2 b0 = dma_chunk<7>(bf, 0), b1 = dma_chunk<7>(bf, 1);
                 const double d2 = dist2_exact(o.xc, o.yc, o.zc, b0.x, b0.y, b1.x);
                 if (d2 < k.h2)
-                    adj_pair(k, o, d2, b0, b1, dma_chunk<7>(bf, 2), dma_chunk<7>(bf, 3),
+                    adj_pair<false, kEos>(k, o, d2, b0, b1, dma_chunk<7>(bf, 2), dma_chunk<7>(bf, 3),
                              dma_chunk<7>(bf, 4), dma_chunk<7>(bf, 5), dma_chunk<7>(bf, 6),
                              dma_chunk<7>(ba, 0), dma_chunk<7>(ba, 1), dma_chunk<7>(ba, 2),
                              dma_chunk<7>(ba, 3), dma_chunk<7>(ba, 4), dma_chunk<7>(ba, 5),
@@ -415,7 +438,7 @@ __global__ __launch_bounds__(64) void k_adj_pairs_list(GridDev g, int64_t n, Con
             }
             wave_sync();
         }
-        if (act) y0_part = adj_pre(k, ad, o, acc, s, io_index(g, s), st, out);
+        if (act) y0_part = adj_pre<kEos>(k, ad, o, acc, s, io_index(g, s), st, out);
     }
     // fixed-order wavefront sum
 #pragma unroll
@@ -524,12 +547,19 @@ int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_p
     }
     {
         TimedRegion t("adjoint_pairs", s);
-        if (k.corr)
-            k_adj_pairs<true><<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, ad, grad);
+        const bool eos = k.eos == 1;
+        if (k.corr && eos)
+            k_adj_pairs<true, true><<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, ad, grad);
+        else if (k.corr)
+            k_adj_pairs<true, false><<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, ad, grad);
+        else if (g.pl_count && eos)
+            k_adj_pairs_list<true><<<blocks_for(n, 64), 64, 0, s>>>(g, n, k, rec, st, ad, grad);
         else if (g.pl_count)
-            k_adj_pairs_list<<<blocks_for(n, 64), 64, 0, s>>>(g, n, k, rec, st, ad, grad);
+            k_adj_pairs_list<false><<<blocks_for(n, 64), 64, 0, s>>>(g, n, k, rec, st, ad, grad);
+        else if (eos)
+            k_adj_pairs<false, true><<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, ad, grad);
         else
-            k_adj_pairs<false><<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, ad, grad);
+            k_adj_pairs<false, false><<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, ad, grad);
         SPH_LAUNCHED();
     }
     if (acc_parts) return SPH_OK;  // the caller reduces its accumulators
@@ -564,8 +594,8 @@ extern "C" int sph_rhs_adjoint(const sph_grid *grid, const sph_state *state,
     if (!dparams || !ws) return fail(SPH_ERR_INVALID_ARG, "null pointer");
     if (params->eps_s > 0.0)
         return fail(SPH_ERR_NOT_IMPLEMENTED, "adjoint with the artificial stress");
-    if (params->eos != 0.0)
-        return fail(SPH_ERR_NOT_IMPLEMENTED, "adjoint with the Murnaghan or Tillotson equation");
+    if (params->eos == 2.0)
+        return fail(SPH_ERR_NOT_IMPLEMENTED, "adjoint with the Tillotson equation");
     const size_t need = adjoint_ws_bytes(grid->n);
     if (ws_bytes < need) return fail(SPH_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
     hipStream_t s = (hipStream_t)stream;

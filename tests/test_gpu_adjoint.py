@@ -402,3 +402,35 @@ def test_rhs_adjoint_with_damage_matches_oracle(pairs):
     w.d = None
     plain = AD.rhs_vjp(w, cot)
     assert rel(plain["rho"], ref["rho"]) > 1e-3
+
+
+@pytest.mark.parametrize("variant", ["cells", "list", "corrected", "damage"])
+def test_rhs_adjoint_murnaghan_matches_oracle(variant):
+    # the Murnaghan equation (section 2.5.2): pressure slope and the per-particle sound
+    # speed in Pi, against the reverse-mode product of the oracle's transcription
+    w = small("cube8_visc")
+    w.params.update(eos=1.0, n_M=4.0, correction=1.0 if variant == "corrected" else 0.0)
+    rng = np.random.default_rng(19)
+    w.rho = w.params["rho0"] * rng.uniform(0.97, 1.03, w.n)
+    if variant == "damage":
+        w.d = rng.uniform(0.0, 1.0, w.n)
+    ref_out = native.rhs_workload(w, want_L=False)
+    cot = {k: rng.normal(size=ref_out[k].shape) / np.abs(ref_out[k]).max() for k in ref_out}
+    ref = AD.rhs_vjp(w, cot)
+    st = P.ParticleState.from_arrays(w.pos, w.vel, w.rho, w.S, w.m, d=getattr(w, "d", None))
+    g = P.sph_build_cells(st.pos, w.h, skin=0.05 * w.dx, pairs=variant != "cells")
+    got = P.sph_rhs_adjoint(g, st, w.params, {k: torch.as_tensor(v).cuda() for k, v in cot.items()})
+    assert P.workspace_status(got["_ws"]) == 0
+    for k in ("pos", "vel", "rho", "S"):
+        assert rel(got[k].cpu().numpy(), ref[k]) < 1e-11, k
+    assert abs(float(got["mu"]) - ref["mu"]) <= 1e-11 * abs(ref["mu"])
+
+
+def test_adjoint_refuses_tillotson():
+    w = small("cube10")
+    w.params.update(eos=2.0)
+    st = gpu_state(w)
+    g = P.sph_build_cells(st.pos, w.h)
+    with pytest.raises(L.SphError) as e:
+        P.sph_rhs_adjoint(g, st, w.params, {"acc": torch.ones(3, w.n, dtype=torch.float64).cuda()})
+    assert e.value.code == L.SPH_ERR_NOT_IMPLEMENTED

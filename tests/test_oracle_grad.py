@@ -164,3 +164,31 @@ def test_torch_transcription_with_damage_matches_c_oracle_and_finite_differences
             vals.append(_objective(wp, y))
         fd = (vals[0] - vals[1]) / (2 * eps)
         assert abs(fd - ad) <= 1e-6 * abs(ad), (which, fd, ad)
+
+
+@pytest.mark.parametrize("rho_cut", [0.0, 0.999])
+def test_torch_transcription_with_murnaghan_matches_c_oracle_and_finite_differences(rho_cut):
+    # the Murnaghan equation (section 2.5.2) with its per-particle sound speed in Pi
+    w = small(seed=15, alpha=1.0, beta=1.0, eos=1.0, n_M=4.0, rho_cut=rho_cut)
+    rng = np.random.default_rng(16)
+    w.rho = w.params["rho0"] * rng.uniform(0.97, 1.03, w.n)
+    ref = native.rhs_workload(w)
+    out = AD.rhs(*AD.as_tensors(w))
+    for k in ("acc", "drho", "dS", "rho_sum"):
+        a, b = ref[k], out[k].numpy()
+        assert np.abs(a - b).max() <= 1e-13 * np.abs(a).max(), k
+    y = {k: rng.normal(size=ref[k].shape) / np.abs(ref[k]).max() for k in ("acc", "drho", "dS", "rho_sum")}
+    g = AD.rhs_vjp(w, y)
+    u = rng.normal(size=w.n)
+    ad = float((g["rho"] * u).sum())
+    eps = 1e-7 * 2700.0
+    vals = []
+    for sgn in (+1, -1):
+        wp = w.copy()
+        wp.rho = w.rho + sgn * eps * u
+        vals.append(_objective(wp, y))
+    fd = (vals[0] - vals[1]) / (2 * eps)
+    assert abs(fd - ad) <= 1e-6 * abs(ad), (fd, ad)
+    # the sound speed's dependence on rho matters: the liquid transcription differs
+    w.params["eos"] = 0.0
+    assert np.abs(AD.rhs(*AD.as_tensors(w))["acc"].numpy() - ref["acc"]).max() > 1e-3 * np.abs(ref["acc"]).max()
