@@ -144,7 +144,7 @@ typedef struct {
  * disables it): a particle with negative pressure contributes
  * zeta = -eps_s sigma / rho^2 to the momentum bracket, scaled by
  * (W(r) / W(dmpd))^n_s, dmpd in (0, h) being the mean particle distance of the
- * initial distribution (the adjoints refuse it); xsph: XSPH
+ * initial distribution (the leapfrog's adjoint refuses it); xsph: XSPH
  * factor in [0, 1] (section 3.1.5), used by the dx/dt output; eos: 0 the liquid
  * equation above, 1 Murnaghan (section 2.5.2, exponent n_M, K0 = rho0 c^2), 2
  * Tillotson (section 2.5.3, constants a_T .. E_cv; compressed form for rho >= rho0
@@ -313,8 +313,9 @@ int sph_rhs(const sph_grid *grid, const sph_state *state, const sph_params *para
  * correction tensor C = M^-1 is differentiated too (M depends on positions and,
  * through V = m / rho, on densities); where C fell back to the identity M gets
  * no cotangent.  With the Murnaghan equation the pressure's slope and the sound
- * speeds in Pi are differentiated too.  Errors as sph_rhs, and NOT_IMPLEMENTED for
- * the artificial stress and the Tillotson equation. */
+ * speeds in Pi are differentiated too, and so is the artificial stress (its tension
+ * switch held).  The du and dx outputs take no cotangent.  Errors as sph_rhs, and
+ * NOT_IMPLEMENTED for the Tillotson equation. */
 int sph_rhs_adjoint(const sph_grid *grid, const sph_state *state, const sph_params *params,
                     const sph_deriv_cot *cot, const sph_state_grad *grad, double *dparams,
                     void *ws, size_t ws_bytes, void *stream);

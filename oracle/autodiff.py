@@ -14,7 +14,9 @@ readings as ``sph_oracle.c`` (see its header for the passages):
   Jaumann terms R S - S R (section 2.4), the Murnaghan equation of state
   (section 2.5.2: p = K0/n (eta^n - 1), K0 = rho0 c^2, the same tension cut-off,
   each particle's sound speed sqrt(K0/rho0 eta^(n-1)) averaged over the pair in Pi)
-  when par[14] = 1, and optionally a fixed damage field d
+  when par[14] = 1, the artificial stress (section 3.1.4: (zeta_a + zeta_b) f^n in the
+  momentum bracket, zeta = -eps_s T for a particle with negative pressure,
+  f = W(r) / W(dmpd)) when par[10] > 0, and optionally a fixed damage field d
   (section 2.7): sigma_d = -p^ I + (1 - d) f_Y S, p^ = p for p >= 0 and (1 - d) p
   below, in the momentum equation only.
 
@@ -161,6 +163,13 @@ def rhs(pos, vel, rho, S6, m, par, mu=None, Y0=None, pairs=None, d=None):
     Pi = torch.where(w < 0, (-alpha * cbar * nu + beta * nu * nu) / (0.5 * (rho[i] + rho[j])),
                      torch.zeros_like(w))
     B = T[:, :, i] + T[:, :, j] - Pi * eye
+    eps_s = float(par[10]) if len(par) > 10 else 0.0
+    if eps_s > 0.0:
+        n_s, dmpd = float(par[11]), float(par[12])
+        qm = dmpd / h
+        Wm = SIGMA3 / h ** 3 * (6 * qm ** 3 - 6 * qm ** 2 + 1 if qm < 0.5 else 2 * (1 - qm) ** 3)
+        zeta = torch.where(p < 0, -eps_s * torch.ones_like(p), torch.zeros_like(p)) * T
+        B = B + (zeta[:, :, i] + zeta[:, :, j]) * (W / Wm) ** n_s
     accp = mj * (B * gW.unsqueeze(0)).sum(1)
     acc = torch.zeros(3, n, dtype=DT).index_add(1, i, accp)
 

@@ -30,13 +30,19 @@
 //           (section 2.6) to rho_bar, S_bar and Y0_bar.  With the Murnaghan
 //           equation (section 2.5.2) dp/drho = K0/rho0 eta^(n-1) and Pi's mean
 //           sound speed (c_c + c_b)/2 carries rho too: cbar_c += Pibar dPi/dcbar / 2
-//           per pair, rho_bar += cbar_c c_c (n - 1) / (2 rho_c).  With a damage field d
+//           per pair, rho_bar += cbar_c c_c (n - 1) / (2 rho_c).  The artificial stress
+//           (section 3.1.4) adds Z = (zeta_c + zeta_b) f^n to B, zeta = -eps_s T in
+//           tension (p < 0, here rho < rho0 outside the cut-off), f = w(q)/w(dmpd):
+//           Tbar_c gains the factor 1 + zeta_c/T_c f^n and
+//           xbar_c += (A . (zeta_c + zeta_b) g) n f^(n-1) g / (w(dmpd) Wn).  With a damage field d
 //           (section 2.7, held fixed) T = ((1 - d) f_Y S - p^ I)/rho^2: the
 //           deviator's cotangent carries the factor 1 - d, and so does the
 //           pressure's slope where p < 0.
 //
 // mu_bar and Y0_bar are reduced per block with a fixed tree and then by one
 // block in a fixed order, so results are reproducible bit for bit.
+#include <type_traits>
+
 #include "adjoint.hpp"
 #include "common.hpp"
 #include "rhs_common.hpp"
@@ -194,6 +200,7 @@ struct AdjAcc {
 struct AdjOwn {
     double xc, yc, zc, vxc, vyc, vzc, rc, mc, Vc, Tc[6], Lbc[9], abx, aby, abz, rsc;
     double cc;  // sound speed (the forward record's, sign bit cleared)
+    bool tens;  // negative pressure (the record's sign bit)
 };
 
 // Murnaghan sound speed of a partner from its density, as the forward prepass forms it
@@ -209,7 +216,7 @@ __device__ inline double murnaghan_c(const Consts &k, double rho) {
 // of c and b, whose terms P r r^T (P = -V_b F, r = x_c - x_b) add
 //   xbar_c += -[V_b (2 F Mc r + (r.Mc r) G r) + V_c (2 F Mb r + (r.Mb r) G r)],
 //   Vbar_c += -F (r.Mb r).
-template <bool kCorr = false, bool kEos = false>
+template <bool kCorr = false, bool kEos = false, bool kAS = false>
 __device__ inline void adj_pair(const Consts &k, const AdjOwn &o, double d2, double2 b0,
                                 double2 b1, double2 b2, double2 b3, double2 b4, double2 b5,
                                 double2 b6, double2 e0, double2 e1, double2 e2, double2 e3,
@@ -240,9 +247,31 @@ __device__ inline void adj_pair(const Consts &k, const AdjOwn &o, double d2, dou
     if constexpr (kEos) alpha_c = k.alpha * (0.5 * (o.cc + murnaghan_c(k, rb_)));
     const Visc vs = viscosity(k, d2, w, o.rc, rb_, alpha_c);
     const double Pi = vs.Pi;
-    const double B0 = o.Tc[0] + b4.x - Pi, B1 = o.Tc[1] + b4.y - Pi;
-    const double B2 = o.Tc[2] + b5.x - Pi, B3 = o.Tc[3] + b5.y;
-    const double B4 = o.Tc[4] + b6.x, B5 = o.Tc[5] + b6.y;
+    double B0 = o.Tc[0] + b4.x - Pi, B1 = o.Tc[1] + b4.y - Pi;
+    double B2 = o.Tc[2] + b5.x - Pi, B3 = o.Tc[3] + b5.y;
+    double B4 = o.Tc[4] + b6.x, B5 = o.Tc[5] + b6.y;
+    // artificial stress: Z0 = zeta_c + zeta_b, fn = f^n, dfn = n f^(n-1) / (w(dmpd) Wn)
+    double Z0[6] = {0, 0, 0, 0, 0, 0}, fn = 0.0, dfn = 0.0, zc = 0.0;
+    if constexpr (kAS) {
+        const bool tb = rb_ < k.rho0 && !(k.rho_cut > 0.0 && rb_ / k.rho0 < k.rho_cut);
+        if (o.tens || tb) {
+            const double f = kp.w * k.inv_wm;
+            if (k.n_int > 0) {
+                fn = f;
+                for (int e = 1; e < k.n_int; ++e) fn *= f;
+            } else {
+                fn = pow_frac(f, k.n_s);
+            }
+            dfn = f > 0.0 ? k.n_s * (fn / f) * k.inv_wm / k.Wn : 0.0;
+            zc = o.tens ? -k.eps_s : 0.0;
+            const double zb = tb ? -k.eps_s : 0.0;
+            const double Tb[6] = {b4.x, b4.y, b5.x, b5.y, b6.x, b6.y};
+#pragma unroll
+            for (int i = 0; i < 6; ++i) Z0[i] = zc * o.Tc[i] + zb * Tb[i];
+            B0 += Z0[0] * fn; B1 += Z0[1] * fn; B2 += Z0[2] * fn;
+            B3 += Z0[3] * fn; B4 += Z0[4] * fn; B5 += Z0[5] * fn;
+        }
+    }
     const double gbx = M[0] * ux + M[3] * uy + M[6] * uz + B0 * Ax + B3 * Ay + B4 * Az;
     const double gby = M[1] * ux + M[4] * uy + M[7] * uz + B3 * Ax + B1 * Ay + B5 * Az;
     const double gbz = M[2] * ux + M[5] * uy + M[8] * uz + B4 * Ax + B5 * Ay + B2 * Az;
@@ -255,7 +284,14 @@ __device__ inline void adj_pair(const Consts &k, const AdjOwn &o, double d2, dou
         acc.grho -= Pib * Pi * 0.5 * vs.coef;  // Pi / (rho_c + rho_b)
         if constexpr (kEos) acc.gc += Pib * (-k.alpha * vs.nu * vs.coef) * 0.5;
     }
-    const double rsw = o.rsc * mb + e6.x * o.mc;
+    double rsw = o.rsc * mb + e6.x * o.mc;
+    if constexpr (kAS) {
+        // d(f^n)/dx_c = dfn g: the scalar A . (Z0 g) rides on the g direction
+        const double zx = Z0[0] * gx + Z0[3] * gy + Z0[4] * gz;
+        const double zy = Z0[3] * gx + Z0[1] * gy + Z0[5] * gz;
+        const double zz = Z0[4] * gx + Z0[5] * gy + Z0[2] * gz;
+        rsw += (Ax * zx + Ay * zy + Az * zz) * dfn;
+    }
     const double rg = rx * gbx + ry * gby + rz * gbz;
     acc.gx += rsw * gx + F * gbx + G * rg * rx - wb * ux + 2.0 * r2b * rx;
     acc.gy += rsw * gy + F * gby + G * rg * ry - wb * uy + 2.0 * r2b * ry;
@@ -263,12 +299,13 @@ __device__ inline void adj_pair(const Consts &k, const AdjOwn &o, double d2, dou
     acc.gvx += -(M[0] * gx + M[1] * gy + M[2] * gz) + wb * rx;
     acc.gvy += -(M[3] * gx + M[4] * gy + M[5] * gz) + wb * ry;
     acc.gvz += -(M[6] * gx + M[7] * gy + M[8] * gz) + wb * rz;
-    acc.gT[0] += Ax * gx;
-    acc.gT[1] += Ay * gy;
-    acc.gT[2] += Az * gz;
-    acc.gT[3] += Ax * gy + Ay * gx;
-    acc.gT[4] += Ax * gz + Az * gx;
-    acc.gT[5] += Ay * gz + Az * gy;
+    const double tf = kAS ? 1.0 + zc * fn : 1.0;  // d(T_c + zeta_c f^n)/dT_c
+    acc.gT[0] += (Ax * gx) * tf;
+    acc.gT[1] += (Ay * gy) * tf;
+    acc.gT[2] += (Az * gz) * tf;
+    acc.gT[3] += (Ax * gy + Ay * gx) * tf;
+    acc.gT[4] += (Ax * gz + Az * gx) * tf;
+    acc.gT[5] += (Ay * gz + Az * gy) * tf;
     acc.gV += ux * (Lbb[0] * gx + Lbb[1] * gy + Lbb[2] * gz) +
               uy * (Lbb[3] * gx + Lbb[4] * gy + Lbb[5] * gz) +
               uz * (Lbb[6] * gx + Lbb[7] * gy + Lbb[8] * gz);
@@ -304,6 +341,7 @@ __device__ inline AdjOwn adj_own(const double *rec, const AdjRec &ad, int64_t s)
     o.Lbc[5] = q2.y; o.Lbc[6] = q3.x; o.Lbc[7] = q3.y; o.Lbc[8] = q4.x;
     o.abx = q4.y; o.aby = q5.x; o.abz = q5.y; o.rsc = q6.x;
     o.cc = fabs(p7.y);
+    o.tens = signbit(p7.y);
     return o;
 }
 
@@ -362,7 +400,7 @@ __device__ inline double adj_pre(const Consts &k, const AdjRec &ad, const AdjOwn
 
 // pair stage + pre stage (see the file header); cell-sweep path, and with the
 // correction tensor the only path (also over a pair list)
-template <bool kCorr, bool kEos>
+template <bool kCorr, bool kEos, bool kAS>
 __global__ __launch_bounds__(kBlock) void k_adj_pairs(GridDev g, int64_t n, Consts k,
                                                       const double *__restrict__ rec, StateDev st,
                                                       AdjRec ad, GradDev out) {
@@ -387,7 +425,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_pairs(GridDev g, int64_t n, Cons
 #pragma unroll
                 for (int i = 0; i < 6; ++i) Mb[i] = ad.Mb[i][t];
             }
-            adj_pair<kCorr, kEos>(k, o, d2, b0, b1, rb[2], rb[3], rb[4], rb[5], rb[6], qb[0],
+            adj_pair<kCorr, kEos, kAS>(k, o, d2, b0, b1, rb[2], rb[3], rb[4], rb[5], rb[6], qb[0],
                                   qb[1], qb[2], qb[3], qb[4], qb[5], qb[6], acc, Mc, Mb);
         });
         y0_part = adj_pre<kEos>(k, ad, o, acc, s, io_index(g, s), st, out);
@@ -398,7 +436,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_pairs(GridDev g, int64_t n, Cons
 
 // the same over the frozen pair list, one wavefront per block: the first seven
 // chunks of each partner's two records gathered cooperatively; Y0 sums per wavefront
-template <bool kEos>
+template <bool kEos, bool kAS>
 __global__ __launch_bounds__(64) void k_adj_pairs_list(GridDev g, int64_t n, Consts k,
                                                        const double *__restrict__ rec,
                                                        StateDev st, AdjRec ad, GradDev out) {
@@ -430,7 +468,7 @@ __global__ __launch_bounds__(64) void k_adj_pairs_list(GridDev g, int64_t n, Con
                 const double2 b0 = dma_chunk<7>(bf, 0), b1 = dma_chunk<7>(bf, 1);
                 const double d2 = dist2_exact(o.xc, o.yc, o.zc, b0.x, b0.y, b1.x);
                 if (d2 < k.h2)
-                    adj_pair<false, kEos>(k, o, d2, b0, b1, dma_chunk<7>(bf, 2), dma_chunk<7>(bf, 3),
+                    adj_pair<false, kEos, kAS>(k, o, d2, b0, b1, dma_chunk<7>(bf, 2), dma_chunk<7>(bf, 3),
                              dma_chunk<7>(bf, 4), dma_chunk<7>(bf, 5), dma_chunk<7>(bf, 6),
                              dma_chunk<7>(ba, 0), dma_chunk<7>(ba, 1), dma_chunk<7>(ba, 2),
                              dma_chunk<7>(ba, 3), dma_chunk<7>(ba, 4), dma_chunk<7>(ba, 5),
@@ -547,19 +585,26 @@ int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_p
     }
     {
         TimedRegion t("adjoint_pairs", s);
-        const bool eos = k.eos == 1;
-        if (k.corr && eos)
-            k_adj_pairs<true, true><<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, ad, grad);
-        else if (k.corr)
-            k_adj_pairs<true, false><<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, ad, grad);
-        else if (g.pl_count && eos)
-            k_adj_pairs_list<true><<<blocks_for(n, 64), 64, 0, s>>>(g, n, k, rec, st, ad, grad);
-        else if (g.pl_count)
-            k_adj_pairs_list<false><<<blocks_for(n, 64), 64, 0, s>>>(g, n, k, rec, st, ad, grad);
+        const bool eos = k.eos == 1, as = k.eps_s > 0.0;
+        auto launch = [&](auto eos_t, auto as_t) {
+            constexpr bool E = decltype(eos_t)::value, A = decltype(as_t)::value;
+            if (k.corr)
+                k_adj_pairs<true, E, A><<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, ad, grad);
+            else if (g.pl_count)
+                k_adj_pairs_list<E, A><<<blocks_for(n, 64), 64, 0, s>>>(g, n, k, rec, st, ad, grad);
+            else
+                k_adj_pairs<false, E, A><<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, ad, grad);
+        };
+        using T = std::true_type;
+        using F = std::false_type;
+        if (eos && as)
+            launch(T{}, T{});
         else if (eos)
-            k_adj_pairs<false, true><<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, ad, grad);
+            launch(T{}, F{});
+        else if (as)
+            launch(F{}, T{});
         else
-            k_adj_pairs<false, false><<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, ad, grad);
+            launch(F{}, F{});
         SPH_LAUNCHED();
     }
     if (acc_parts) return SPH_OK;  // the caller reduces its accumulators
@@ -592,8 +637,6 @@ extern "C" int sph_rhs_adjoint(const sph_grid *grid, const sph_state *state,
         return rc;
     if (!cot) return fail(SPH_ERR_INVALID_ARG, "cotangent struct is NULL");
     if (!dparams || !ws) return fail(SPH_ERR_INVALID_ARG, "null pointer");
-    if (params->eps_s > 0.0)
-        return fail(SPH_ERR_NOT_IMPLEMENTED, "adjoint with the artificial stress");
     if (params->eos == 2.0)
         return fail(SPH_ERR_NOT_IMPLEMENTED, "adjoint with the Tillotson equation");
     const size_t need = adjoint_ws_bytes(grid->n);

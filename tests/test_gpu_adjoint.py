@@ -434,3 +434,28 @@ def test_adjoint_refuses_tillotson():
     with pytest.raises(L.SphError) as e:
         P.sph_rhs_adjoint(g, st, w.params, {"acc": torch.ones(3, w.n, dtype=torch.float64).cuda()})
     assert e.value.code == L.SPH_ERR_NOT_IMPLEMENTED
+
+
+@pytest.mark.parametrize("variant", ["cells", "list", "corrected", "murnaghan_damage", "n2.5"])
+def test_rhs_adjoint_artificial_stress_matches_oracle(variant):
+    # the artificial stress (section 3.1.4) with half the particles in tension
+    w = small("cube8_visc")
+    w.params.update(eps_s=0.2, n_s=2.5 if variant == "n2.5" else 4.0,
+                    correction=1.0 if variant == "corrected" else 0.0)
+    rng = np.random.default_rng(23)
+    w.rho = w.params["rho0"] * rng.uniform(0.99, 1.01, w.n)
+    if variant == "murnaghan_damage":
+        w.params.update(eos=1.0, n_M=4.0)
+        w.d = rng.uniform(0.0, 1.0, w.n)
+    ref_out = native.rhs_workload(w, want_L=False)
+    cot = {k: rng.normal(size=ref_out[k].shape) / np.abs(ref_out[k]).max() for k in ref_out}
+    ref = AD.rhs_vjp(w, cot)
+    st = P.ParticleState.from_arrays(w.pos, w.vel, w.rho, w.S, w.m, d=getattr(w, "d", None))
+    g = P.sph_build_cells(st.pos, w.h, skin=0.05 * w.dx, pairs=variant != "cells")
+    got = P.sph_rhs_adjoint(g, st, w.params, {k: torch.as_tensor(v).cuda() for k, v in cot.items()})
+    assert P.workspace_status(got["_ws"]) == 0
+    for k in ("pos", "vel", "rho", "S"):
+        assert rel(got[k].cpu().numpy(), ref[k]) < 1e-11, k
+    assert abs(float(got["mu"]) - ref["mu"]) <= 1e-11 * abs(ref["mu"])
+    w.params["eps_s"] = 0.0  # the artificial stress matters here
+    assert rel(AD.rhs_vjp(w, cot)["pos"], ref["pos"]) > 1e-6

@@ -192,3 +192,31 @@ def test_torch_transcription_with_murnaghan_matches_c_oracle_and_finite_differen
     # the sound speed's dependence on rho matters: the liquid transcription differs
     w.params["eos"] = 0.0
     assert np.abs(AD.rhs(*AD.as_tensors(w))["acc"].numpy() - ref["acc"]).max() > 1e-3 * np.abs(ref["acc"]).max()
+
+
+@pytest.mark.parametrize("n_s", [4.0, 2.5])
+def test_torch_transcription_with_artificial_stress_matches_c_oracle_and_finite_differences(n_s):
+    # the artificial stress (section 3.1.4), half the particles in tension
+    w = small(seed=17, alpha=1.0, beta=1.0, eps_s=0.2, n_s=n_s)
+    rng = np.random.default_rng(18)
+    w.rho = w.params["rho0"] * rng.uniform(0.99, 1.01, w.n)
+    ref = native.rhs_workload(w)
+    out = AD.rhs(*AD.as_tensors(w))
+    for k in ("acc", "drho", "dS", "rho_sum"):
+        a, b = ref[k], out[k].numpy()
+        assert np.abs(a - b).max() <= 1e-13 * np.abs(a).max(), k
+    y = {k: rng.normal(size=ref[k].shape) / np.abs(ref[k]).max() for k in ("acc", "drho", "dS", "rho_sum")}
+    g = AD.rhs_vjp(w, y)
+    for which, scale in (("pos", w.dx), ("S", 6.75e7), ("rho", 2700.0 * 1e-4)):
+        u = rng.normal(size=getattr(w, which).shape)
+        ad = float((g[which] * u).sum())
+        eps = 1e-6 * scale
+        vals = []
+        for sgn in (+1, -1):
+            wp = w.copy()
+            setattr(wp, which, getattr(w, which) + sgn * eps * u)
+            vals.append(_objective(wp, y))
+        fd = (vals[0] - vals[1]) / (2 * eps)
+        assert abs(fd - ad) <= 1e-6 * abs(ad), (which, fd, ad)
+    w.params["eps_s"] = 0.0  # the artificial stress acts on this state
+    assert np.abs(AD.rhs(*AD.as_tensors(w))["acc"].numpy() - ref["acc"]).max() > 1e-6 * np.abs(ref["acc"]).max()
