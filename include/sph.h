@@ -144,15 +144,15 @@ typedef struct {
  * disables it): a particle with negative pressure contributes
  * zeta = -eps_s sigma / rho^2 to the momentum bracket, scaled by
  * (W(r) / W(dmpd))^n_s, dmpd in (0, h) being the mean particle distance of the
- * initial distribution (the leapfrog's adjoint refuses it); xsph: XSPH
+ * initial distribution; xsph: XSPH
  * factor in [0, 1] (section 3.1.5), used by the dx/dt output; eos: 0 the liquid
  * equation above, 1 Murnaghan (section 2.5.2, exponent n_M, K0 = rho0 c^2), 2
  * Tillotson (section 2.5.3, constants a_T .. E_cv; compressed form for rho >= rho0
  * or u <= E_iv, expanded form for rho < rho0 and u >= E_cv, linear in u between).
  * With eos 1 or 2 each particle's sound speed is the thermodynamic one,
  * c^2 = dp/drho|u + p / rho^2 dp/du|rho (floored at 0), and Pi uses the pair's mean
- * (sph_rhs_adjoint takes Murnaghan and refuses Tillotson; the leapfrog's adjoint
- * refuses both, the leapfrog refuses Tillotson). */
+ * (the adjoints take Murnaghan and refuse Tillotson, which the leapfrog refuses
+ * too). */
 typedef struct {
     double h, rho0, c, mu, Y0, alpha, beta, eps_v, rho_cut, correction;
     double eps_s, n_s, dmpd, xsph;

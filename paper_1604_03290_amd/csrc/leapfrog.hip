@@ -216,8 +216,8 @@ __global__ __launch_bounds__(kBlock) void k_rev_kick2(Fields13 Uk, Deriv10 Fk, F
         double cF[10];
         y0p = kick_adj_at(S, dS, gU, gF, i, h, Y0, accumulate, cF);
         const double mi = m[i];
-        write_rec<false>(g, k, i, x1[i], x1[n + i], x1[2 * n + i], v[0], v[1], v[2], rho, S, mi,
-                         rec, status);
+        write_rec(g, k, i, x1[i], x1[n + i], x1[2 * n + i], v[0], v[1], v[2], rho, S, mi, rec,
+                  status);
         double L[9];
 #pragma unroll
         for (int c = 0; c < 9; ++c) L[c] = L1[c * n + i];
@@ -469,10 +469,6 @@ extern "C" int sph_leapfrog_adjoint(const sph_grid *grid, const sph_state *s0,
     if ((rc = check_lf(grid, s0, params, dt, steps)) || (rc = check_grad(grad0))) return rc;
     if (!checkpoints || !cot_final || !dparams || !ws)
         return fail(SPH_ERR_INVALID_ARG, "null pointer");
-    if (params->eps_s > 0.0)
-        return fail(SPH_ERR_NOT_IMPLEMENTED, "adjoint with the artificial stress");
-    if (params->eos != 0.0)
-        return fail(SPH_ERR_NOT_IMPLEMENTED, "adjoint with the Murnaghan or Tillotson equation");
     const int64_t n = grid->n;
     const size_t need = leapfrog_adjoint_ws_bytes(n);
     if (ws_bytes < need) return fail(SPH_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);

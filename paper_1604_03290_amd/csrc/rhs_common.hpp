@@ -305,13 +305,12 @@ __device__ inline double yield_factor(const Consts &k, const double S[6]) {
 
 // Operand record of slot s (pressure, limiter, T = sigma / rho^2, V = m / rho) from
 // the particle's state; raises STALE_GRID when the particle left its cell (or its
-// list position) by more than skin / 2 and DOMAIN for a non-positive or
-// non-finite density, a non-finite velocity or stress, or a damage outside [0, 1].  With damage d the stress is sigma_d = -p^ I + (1 - d) f_Y S,
-// p^ = p for p >= 0 and (1 - d) p below (section 2.7); d = 0 gives sigma exactly.
-// Returns the pressure p.  The prepass and the leapfrog's fused passes write every
-// record through this one function; kEos = false limits it to the liquid equation
-// (the adjoint's passes, which refuse the others).
-template <bool kEos = true>
+// list position) by more than skin / 2 and DOMAIN for a non-positive or non-finite
+// density, a non-finite velocity or stress, or a damage outside [0, 1].  With damage
+// d the stress is sigma_d = -p^ I + (1 - d) f_Y S, p^ = p for p >= 0 and (1 - d) p
+// below (section 2.7); d = 0 gives sigma exactly.  Returns the pressure p.  The
+// prepass and the leapfrog's fused passes write every record through this one
+// function.
 __device__ inline double write_rec(const GridDev &g, const Consts &k, int64_t s, double x, double y,
                                    double z, double vx, double vy, double vz, double rho,
                                    const double S[6], double m, double *__restrict__ rec,
@@ -322,12 +321,7 @@ __device__ inline double write_rec(const GridDev &g, const Consts &k, int64_t s,
     for (int c = 0; c < 6; ++c) finite = finite && isfinite(S[c]);
     if (!(rho > 0.0) || !finite || !(d >= 0.0 && d <= 1.0)) raise_flag(status, SPH_ERR_DOMAIN);
     double p, cs;
-    if constexpr (kEos) {
-        eos_pc(k, rho, u, p, cs);
-    } else {
-        p = pressure(k, rho);
-        cs = k.c;
-    }
+    eos_pc(k, rho, u, p, cs);
     const double f = (1.0 - d) * yield_factor(k, S);
     const double ph = p >= 0.0 ? p : (1.0 - d) * p;
     const double ir2 = 1.0 / (rho * rho);

@@ -459,3 +459,24 @@ def test_rhs_adjoint_artificial_stress_matches_oracle(variant):
     assert abs(float(got["mu"]) - ref["mu"]) <= 1e-11 * abs(ref["mu"])
     w.params["eps_s"] = 0.0  # the artificial stress matters here
     assert rel(AD.rhs_vjp(w, cot)["pos"], ref["pos"]) > 1e-6
+
+
+@pytest.mark.parametrize("variant", ["murnaghan", "artificial_stress", "both_corrected"])
+def test_leapfrog_gradient_with_murnaghan_and_artificial_stress(variant):
+    w = small("cube8_visc")
+    rng = np.random.default_rng(29)
+    w.rho = w.params["rho0"] * rng.uniform(0.99, 1.01, w.n)
+    if variant in ("murnaghan", "both_corrected"):
+        w.params.update(eos=1.0, n_M=4.0)
+    if variant in ("artificial_stress", "both_corrected"):
+        w.params.update(eps_s=0.2, n_s=4.0)
+    if variant == "both_corrected":
+        w.params.update(correction=1.0)
+    steps = 8
+    st, g, fin, ck = run_leapfrog(w, steps, pairs=True)
+    cot = {"vel": (fin.vel * fin.m).contiguous()}
+    got = P.sph_leapfrog_adjoint(g, st, w.params, w.dt, steps, ck, cot)
+    assert P.workspace_status(got["_ws"]) == 0
+    ref = AD.leapfrog_grad(w, steps, w.dt, "ke")
+    assert rel(got["vel"].cpu().numpy(), ref["v0"]) < 1e-10
+    assert abs(float(got["mu"]) - ref["mu"]) <= 1e-10 * abs(ref["mu"])

@@ -354,10 +354,6 @@ def test_extra_terms_refused_where_not_built():
     w.params.update(eps_s=0.2)
     st = gpu_state(w)
     g = P.sph_build_cells(st.pos, w.h, skin=0.5 * w.dx)
-    with pytest.raises(L.SphError) as e:  # the leapfrog's adjoint
-        fin, ck = P.sph_leapfrog(g, st, w.params, w.dt, 2)
-        P.sph_leapfrog_adjoint(g, st, w.params, w.dt, 2, ck, {"vel": fin.vel.contiguous()})
-    assert e.value.code == L.SPH_ERR_NOT_IMPLEMENTED
     w.params.update(eps_s=0.0, xsph=0.5)
     with pytest.raises(L.SphError) as e:
         P.sph_leapfrog(g, st, w.params, w.dt, 2)
