@@ -185,12 +185,15 @@ typedef struct {
 } sph_deriv;
 
 /* Cotangents of the derivatives (inputs of the adjoint), user order.  A NULL
- * pointer means a zero cotangent. */
+ * pointer means a zero cotangent.  du and dx, dy, dz are the cotangents of the
+ * energy rate and of dx/dt (XSPH) of sph_deriv. */
 typedef struct {
     const double *ax, *ay, *az;
     const double *drho;
     const double *dsxx, *dsyy, *dszz, *dsxy, *dsxz, *dsyz;
     const double *rho_sum;
+    const double *du;
+    const double *dx, *dy, *dz;
 } sph_deriv_cot;
 
 /* Writable per-particle fields (no mass): used for gradients with respect to
@@ -314,8 +317,8 @@ int sph_rhs(const sph_grid *grid, const sph_state *state, const sph_params *para
  * through V = m / rho, on densities); where C fell back to the identity M gets
  * no cotangent.  With the Murnaghan equation the pressure's slope and the sound
  * speeds in Pi are differentiated too, and so is the artificial stress (its tension
- * switch held).  The du and dx outputs take no cotangent.  Errors as sph_rhs, and
- * NOT_IMPLEMENTED for the Tillotson equation. */
+ * switch held), and the energy rate and dx/dt when their cotangents are given.
+ * Errors as sph_rhs, and NOT_IMPLEMENTED for the Tillotson equation. */
 int sph_rhs_adjoint(const sph_grid *grid, const sph_state *state, const sph_params *params,
                     const sph_deriv_cot *cot, const sph_state_grad *grad, double *dparams,
                     void *ws, size_t ws_bytes, void *stream);

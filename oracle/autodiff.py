@@ -16,7 +16,10 @@ readings as ``sph_oracle.c`` (see its header for the passages):
   each particle's sound speed sqrt(K0/rho0 eta^(n-1)) averaged over the pair in Pi)
   when par[14] = 1, the artificial stress (section 3.1.4: (zeta_a + zeta_b) f^n in the
   momentum bracket, zeta = -eps_s T for a particle with negative pressure,
-  f = W(r) / W(dmpd)) when par[10] > 0, and optionally a fixed damage field d
+  f = W(r) / W(dmpd)) when par[10] > 0, the energy rate du/dt = 1/2 sum_b m_b
+  (v_b - v_a) . (B g) with B the momentum bracket without artificial stress (section
+  3.1.2) and the XSPH velocity v_a + xsph sum_b 2 m_b / (rho_a + rho_b) (v_b - v_a) W
+  (section 3.1.5), and optionally a fixed damage field d
   (section 2.7): sigma_d = -p^ I + (1 - d) f_Y S, p^ = p for p >= 0 and (1 - d) p
   below, in the momentum equation only.
 
@@ -163,6 +166,12 @@ def rhs(pos, vel, rho, S6, m, par, mu=None, Y0=None, pairs=None, d=None):
     Pi = torch.where(w < 0, (-alpha * cbar * nu + beta * nu * nu) / (0.5 * (rho[i] + rho[j])),
                      torch.zeros_like(w))
     B = T[:, :, i] + T[:, :, j] - Pi * eye
+    dvb = -dv  # v_b - v_a
+    up = 0.5 * mj * (dvb * (B * gW.unsqueeze(0)).sum(1)).sum(0)
+    du = torch.zeros(n, dtype=DT).index_add(0, i, up)
+    xsph = float(par[13]) if len(par) > 13 else 0.0
+    xs = torch.zeros(3, n, dtype=DT).index_add(1, i, (2.0 * mj / (rho[i] + rho[j]) * W) * dvb)
+    xv = vel + xsph * xs
     eps_s = float(par[10]) if len(par) > 10 else 0.0
     if eps_s > 0.0:
         n_s, dmpd = float(par[11]), float(par[12])
@@ -186,7 +195,7 @@ def rhs(pos, vel, rho, S6, m, par, mu=None, Y0=None, pairs=None, d=None):
     tr = ed[0, 0] + ed[1, 1] + ed[2, 2]
     rot = torch.einsum("agn,gbn->abn", R, St) - torch.einsum("agn,gbn->abn", St, R)
     dSm = 2.0 * mu * (ed - tr / 3.0 * eye) + rot
-    return dict(acc=acc, drho=drho, dS=_six(dSm), rho_sum=rho_sum, L=L)
+    return dict(acc=acc, drho=drho, dS=_six(dSm), rho_sum=rho_sum, L=L, du=du, xv=xv)
 
 
 def as_tensors(w):
@@ -196,7 +205,8 @@ def as_tensors(w):
 
 def rhs_vjp(w, cot: dict, pairs=None):
     """J^T y of one right-hand side: cotangents ``cot`` with keys acc (3, n), drho (n),
-    dS (6, n), rho_sum (n).  Returns gradients pos, vel, rho, S (6, n), mu, Y0."""
+    dS (6, n), rho_sum (n) and optionally du (n) and xv (3, n).  Returns gradients pos,
+    vel, rho, S (6, n), mu, Y0."""
     pos, vel, rho, S, m, par = as_tensors(w)
     mu = torch.tensor(float(par[3]), dtype=DT, requires_grad=True)
     Y0 = torch.tensor(float(par[4]), dtype=DT, requires_grad=True)
@@ -204,8 +214,9 @@ def rhs_vjp(w, cot: dict, pairs=None):
         t.requires_grad_(True)
     out = rhs(pos, vel, rho, S, m, par, mu=mu, Y0=Y0, pairs=pairs, d=getattr(w, "d", None))
     y = 0.0
-    for k in ("acc", "drho", "dS", "rho_sum"):
-        y = y + (out[k] * torch.from_numpy(np.asarray(cot[k], dtype=np.float64))).sum()
+    for k in ("acc", "drho", "dS", "rho_sum", "du", "xv"):
+        if cot.get(k) is not None:
+            y = y + (out[k] * torch.from_numpy(np.asarray(cot[k], dtype=np.float64))).sum()
     g = torch.autograd.grad(y, [pos, vel, rho, S, mu, Y0], allow_unused=True)
     names = ["pos", "vel", "rho", "S", "mu", "Y0"]
     return {k: (v.detach().numpy() if v is not None else None) for k, v in zip(names, g)}

@@ -80,7 +80,7 @@ class Deriv(C.Structure):
 
 
 class DerivCot(C.Structure):
-    _fields_ = [(k, _pd) for k in _DERIV]
+    _fields_ = [(k, _pd) for k in _DERIV + ("du", "dx", "dy", "dz")]
 
 
 class Fields(C.Structure):

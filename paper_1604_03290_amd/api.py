@@ -343,14 +343,16 @@ def sph_rhs(grid: CellGrid, state: ParticleState, params, precision="fp64", out=
 def sph_rhs_adjoint(grid: CellGrid, state: ParticleState, params, cot: dict,
                     ws: torch.Tensor | None = None) -> dict:
     """Vector-Jacobian product of sph_rhs (C: sph_rhs_adjoint).  ``cot`` has keys of
-    sph_rhs's outputs (missing = zero).  Returns gradients pos, vel, rho, S, mu, Y0."""
+    sph_rhs's outputs (acc, drho, dS, rho_sum, du, xv; missing = zero).  Returns
+    gradients pos, vel, rho, S, mu, Y0."""
     n = state.n
     dev = state.rho.device
     z3 = lambda k, shape: _dev(cot[k]) if cot.get(k) is not None else None
     acc, drho, dS, rs = (z3("acc", None), z3("drho", None), z3("dS", None), z3("rho_sum", None))
+    du, xv = z3("du", None), z3("xv", None)
     p = lambda t, i=None: (t[i].data_ptr() if i is not None else t.data_ptr()) if t is not None else None
     dc = L.DerivCot(p(acc, 0), p(acc, 1), p(acc, 2), p(drho), p(dS, 0), p(dS, 1), p(dS, 2),
-                    p(dS, 3), p(dS, 4), p(dS, 5), p(rs))
+                    p(dS, 3), p(dS, 4), p(dS, 5), p(rs), p(du), p(xv, 0), p(xv, 1), p(xv, 2))
     g = dict(pos=torch.empty(3, n, dtype=F64, device=dev), vel=torch.empty(3, n, dtype=F64, device=dev),
              rho=torch.empty(n, dtype=F64, device=dev), S=torch.empty(6, n, dtype=F64, device=dev))
     dparams = torch.empty(2, dtype=F64, device=dev)

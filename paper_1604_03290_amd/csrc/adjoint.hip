@@ -34,7 +34,14 @@
 //           (section 3.1.4) adds Z = (zeta_c + zeta_b) f^n to B, zeta = -eps_s T in
 //           tension (p < 0, here rho < rho0 outside the cut-off), f = w(q)/w(dmpd):
 //           Tbar_c gains the factor 1 + zeta_c/T_c f^n and
-//           xbar_c += (A . (zeta_c + zeta_b) g) n f^(n-1) g / (w(dmpd) Wn).  With a damage field d
+//           xbar_c += (A . (zeta_c + zeta_b) g) n f^(n-1) g / (w(dmpd) Wn).  The
+//           cotangents ubar of du/dt and chi of dx/dt (sections 3.1.2, 3.1.5) add,
+//           with e = (m_b ubar_c + m_c ubar_b)/2, Be = T_c + T_b - Pi I and
+//           kappa = m_b chi_c - m_c chi_b:
+//             gbar += e Be u, vbar_c -= e Be g, Tbar_c += e sym(u (x) g),
+//             Pibar -= e u.g (energy), and vbar_c -= xsph 2 W kappa / S,
+//             xbar_c += xsph 2 (kappa.u) g / S, rhobar_c -= xsph 2 W (kappa.u) / S^2
+//             with S = rho_c + rho_b (XSPH); vbar_c += chi_c (dx/dt = v + ...).  With a damage field d
 //           (section 2.7, held fixed) T = ((1 - d) f_Y S - p^ I)/rho^2: the
 //           deviator's cotangent carries the factor 1 - d, and so does the
 //           pressure's slope where p < 0.
@@ -185,6 +192,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_post(GridDev g, int64_t n, Const
         mu_part = adj_post_at(k, s, L, k.corr, M, rec[s * kRec + 6], S, c6,
                               ld(cot.drho, a), ld(cot.ax, a), ld(cot.ay, a), ld(cot.az, a),
                               ld(cot.rho_sum, a), ad);
+        if (cot.du || cot.dx[0] || cot.dx[1] || cot.dx[2]) {
+            ad.ext[0][s] = ld(cot.du, a);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) ad.ext[1 + i][s] = ld(cot.dx[i], a);
+        }
     }
     const double tot = block_sum(mu_part);
     if (threadIdx.x == 0) put(ad.part_mu, blockIdx.x, tot, ad.add_parts);
@@ -216,12 +228,13 @@ __device__ inline double murnaghan_c(const Consts &k, double rho) {
 // of c and b, whose terms P r r^T (P = -V_b F, r = x_c - x_b) add
 //   xbar_c += -[V_b (2 F Mc r + (r.Mc r) G r) + V_c (2 F Mb r + (r.Mb r) G r)],
 //   Vbar_c += -F (r.Mb r).
-template <bool kCorr = false, bool kEos = false, bool kAS = false>
+template <bool kCorr = false, bool kEos = false, bool kAS = false, bool kXC = false>
 __device__ inline void adj_pair(const Consts &k, const AdjOwn &o, double d2, double2 b0,
                                 double2 b1, double2 b2, double2 b3, double2 b4, double2 b5,
                                 double2 b6, double2 e0, double2 e1, double2 e2, double2 e3,
                                 double2 e4, double2 e5, double2 e6, AdjAcc &acc,
-                                const double *Mc = nullptr, const double *Mb = nullptr) {
+                                const double *Mc = nullptr, const double *Mb = nullptr,
+                                const double *xo = nullptr, const double *xb = nullptr) {
     const double Gn = k.Fn * k.inv_h * k.inv_h;
     const double Lbb[9] = {e0.x, e0.y, e1.x, e1.y, e2.x, e2.y, e3.x, e3.y, e4.x};
     const double rx = o.xc - b0.x, ry = o.yc - b0.y, rz = o.zc - b1.x;
@@ -250,6 +263,7 @@ __device__ inline void adj_pair(const Consts &k, const AdjOwn &o, double d2, dou
     double B0 = o.Tc[0] + b4.x - Pi, B1 = o.Tc[1] + b4.y - Pi;
     double B2 = o.Tc[2] + b5.x - Pi, B3 = o.Tc[3] + b5.y;
     double B4 = o.Tc[4] + b6.x, B5 = o.Tc[5] + b6.y;
+    const double Be[6] = {B0, B1, B2, B3, B4, B5};  // the energy bracket (no artificial stress)
     // artificial stress: Z0 = zeta_c + zeta_b, fn = f^n, dfn = n f^(n-1) / (w(dmpd) Wn)
     double Z0[6] = {0, 0, 0, 0, 0, 0}, fn = 0.0, dfn = 0.0, zc = 0.0;
     if constexpr (kAS) {
@@ -272,10 +286,37 @@ __device__ inline void adj_pair(const Consts &k, const AdjOwn &o, double d2, dou
             B3 += Z0[3] * fn; B4 += Z0[4] * fn; B5 += Z0[5] * fn;
         }
     }
-    const double gbx = M[0] * ux + M[3] * uy + M[6] * uz + B0 * Ax + B3 * Ay + B4 * Az;
-    const double gby = M[1] * ux + M[4] * uy + M[7] * uz + B3 * Ax + B1 * Ay + B5 * Az;
-    const double gbz = M[2] * ux + M[5] * uy + M[8] * uz + B4 * Ax + B5 * Ay + B2 * Az;
-    const double Pib = -(Ax * gx + Ay * gy + Az * gz);
+    double gbx = M[0] * ux + M[3] * uy + M[6] * uz + B0 * Ax + B3 * Ay + B4 * Az;
+    double gby = M[1] * ux + M[4] * uy + M[7] * uz + B3 * Ax + B1 * Ay + B5 * Az;
+    double gbz = M[2] * ux + M[5] * uy + M[8] * uz + B4 * Ax + B5 * Ay + B2 * Az;
+    double Pib = -(Ax * gx + Ay * gy + Az * gz);
+    double rxs = 0.0;  // XSPH: xbar_c += rxs g
+    if constexpr (kXC) {
+        const double e = 0.5 * (mb * xo[0] + o.mc * xb[0]);
+        gbx += e * (Be[0] * ux + Be[3] * uy + Be[4] * uz);
+        gby += e * (Be[3] * ux + Be[1] * uy + Be[5] * uz);
+        gbz += e * (Be[4] * ux + Be[5] * uy + Be[2] * uz);
+        acc.gvx -= e * (Be[0] * gx + Be[3] * gy + Be[4] * gz);
+        acc.gvy -= e * (Be[3] * gx + Be[1] * gy + Be[5] * gz);
+        acc.gvz -= e * (Be[4] * gx + Be[5] * gy + Be[2] * gz);
+        acc.gT[0] += e * (ux * gx);
+        acc.gT[1] += e * (uy * gy);
+        acc.gT[2] += e * (uz * gz);
+        acc.gT[3] += e * (ux * gy + uy * gx);
+        acc.gT[4] += e * (ux * gz + uz * gx);
+        acc.gT[5] += e * (uy * gz + uz * gy);
+        Pib -= e * (ux * gx + uy * gy + uz * gz);
+        const double kx = mb * xo[1] - o.mc * xb[1], ky = mb * xo[2] - o.mc * xb[2],
+                     kz = mb * xo[3] - o.mc * xb[3];
+        const double iS = 1.0 / (o.rc + rb_);
+        const double e2 = 2.0 * k.xsph * iS, Wv = k.Wn * kp.w;
+        const double ku = kx * ux + ky * uy + kz * uz;
+        acc.gvx -= e2 * Wv * kx;
+        acc.gvy -= e2 * Wv * ky;
+        acc.gvz -= e2 * Wv * kz;
+        rxs = e2 * ku;
+        acc.grho -= e2 * Wv * iS * ku;
+    }
     double wb = 0.0, r2b = 0.0;
     if (w < 0.0) {
         const double nub = Pib * (-alpha_c + 2.0 * k.beta * vs.nu) * vs.coef;
@@ -284,7 +325,7 @@ __device__ inline void adj_pair(const Consts &k, const AdjOwn &o, double d2, dou
         acc.grho -= Pib * Pi * 0.5 * vs.coef;  // Pi / (rho_c + rho_b)
         if constexpr (kEos) acc.gc += Pib * (-k.alpha * vs.nu * vs.coef) * 0.5;
     }
-    double rsw = o.rsc * mb + e6.x * o.mc;
+    double rsw = o.rsc * mb + e6.x * o.mc + rxs;
     if constexpr (kAS) {
         // d(f^n)/dx_c = dfn g: the scalar A . (Z0 g) rides on the g direction
         const double zx = Z0[0] * gx + Z0[3] * gy + Z0[4] * gz;
@@ -400,7 +441,7 @@ __device__ inline double adj_pre(const Consts &k, const AdjRec &ad, const AdjOwn
 
 // pair stage + pre stage (see the file header); cell-sweep path, and with the
 // correction tensor the only path (also over a pair list)
-template <bool kCorr, bool kEos, bool kAS>
+template <bool kCorr, bool kEos, bool kAS, bool kXC>
 __global__ __launch_bounds__(kBlock) void k_adj_pairs(GridDev g, int64_t n, Consts k,
                                                       const double *__restrict__ rec, StateDev st,
                                                       AdjRec ad, GradDev out) {
@@ -414,6 +455,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_pairs(GridDev g, int64_t n, Cons
 #pragma unroll
             for (int i = 0; i < 6; ++i) Mc[i] = ad.Mb[i][s];
         }
+        double xo[4] = {0, 0, 0, 0};
+        if (kXC) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) xo[i] = ad.ext[i][s];
+        }
         for_each_candidate(g, s, o.xc, o.yc, o.zc, k.reach, [&](int t) {
             const double2 *rb = rec2(rec, t);
             const double2 b0 = rb[0], b1 = rb[1];
@@ -425,9 +471,20 @@ __global__ __launch_bounds__(kBlock) void k_adj_pairs(GridDev g, int64_t n, Cons
 #pragma unroll
                 for (int i = 0; i < 6; ++i) Mb[i] = ad.Mb[i][t];
             }
-            adj_pair<kCorr, kEos, kAS>(k, o, d2, b0, b1, rb[2], rb[3], rb[4], rb[5], rb[6], qb[0],
-                                  qb[1], qb[2], qb[3], qb[4], qb[5], qb[6], acc, Mc, Mb);
+            double xb[4] = {0, 0, 0, 0};
+            if (kXC) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) xb[i] = ad.ext[i][t];
+            }
+            adj_pair<kCorr, kEos, kAS, kXC>(k, o, d2, b0, b1, rb[2], rb[3], rb[4], rb[5], rb[6],
+                                            qb[0], qb[1], qb[2], qb[3], qb[4], qb[5], qb[6], acc,
+                                            Mc, Mb, xo, xb);
         });
+        if (kXC) {  // dx/dt = v + ...
+            acc.gvx += xo[1];
+            acc.gvy += xo[2];
+            acc.gvz += xo[3];
+        }
         y0_part = adj_pre<kEos>(k, ad, o, acc, s, io_index(g, s), st, out);
     }
     const double tot = block_sum(y0_part);
@@ -529,7 +586,7 @@ size_t adjoint_ws_bytes(int64_t n) {
 
 CotDev cot_dev(const sph_deriv_cot *c) {
     return CotDev{c->ax, c->ay, c->az, c->drho, {c->dsxx, c->dsyy, c->dszz, c->dsxy, c->dsxz, c->dsyz},
-                  c->rho_sum};
+                  c->rho_sum, c->du, {c->dx, c->dy, c->dz}};
 }
 
 GradDev grad_dev(const sph_fields *g, int accumulate) {
@@ -586,14 +643,20 @@ int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_p
     {
         TimedRegion t("adjoint_pairs", s);
         const bool eos = k.eos == 1, as = k.eps_s > 0.0;
+        const bool xc = cot.du || cot.dx[0] || cot.dx[1] || cot.dx[2];
         auto launch = [&](auto eos_t, auto as_t) {
             constexpr bool E = decltype(eos_t)::value, A = decltype(as_t)::value;
-            if (k.corr)
-                k_adj_pairs<true, E, A><<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, ad, grad);
+            const dim3 gb(blocks_for(n)), tb(kBlock);
+            if (xc && k.corr)
+                k_adj_pairs<true, E, A, true><<<gb, tb, 0, s>>>(g, n, k, rec, st, ad, grad);
+            else if (xc)
+                k_adj_pairs<false, E, A, true><<<gb, tb, 0, s>>>(g, n, k, rec, st, ad, grad);
+            else if (k.corr)
+                k_adj_pairs<true, E, A, false><<<gb, tb, 0, s>>>(g, n, k, rec, st, ad, grad);
             else if (g.pl_count)
                 k_adj_pairs_list<E, A><<<blocks_for(n, 64), 64, 0, s>>>(g, n, k, rec, st, ad, grad);
             else
-                k_adj_pairs<false, E, A><<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, ad, grad);
+                k_adj_pairs<false, E, A, false><<<gb, tb, 0, s>>>(g, n, k, rec, st, ad, grad);
         };
         using T = std::true_type;
         using F = std::false_type;
@@ -608,7 +671,8 @@ int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_p
         SPH_LAUNCHED();
     }
     if (acc_parts) return SPH_OK;  // the caller reduces its accumulators
-    const int64_t m_y0 = g.pl_count && !k.corr ? blocks_for(n, 64) : blocks_for(n);
+    const bool per_wave = g.pl_count && !k.corr && !(cot.du || cot.dx[0] || cot.dx[1] || cot.dx[2]);
+    const int64_t m_y0 = per_wave ? blocks_for(n, 64) : blocks_for(n);
     return reduce_params_launch(ad.part_mu, blocks_for(n), ad.part_y0, m_y0, dparams,
                                 accumulate_params, s);
 }

@@ -724,6 +724,7 @@ __device__ inline void postpass_ext(const Consts &k, int a, const Acc64 &acc, co
 // Cotangents of the right-hand side's outputs (user order; null = zero).
 struct CotDev {
     const double *ax, *ay, *az, *drho, *ds[6], *rho_sum;
+    const double *du, *dx[3];  // energy rate and dx/dt (null = zero)
 };
 
 // Gradient destination (user order), overwritten or accumulated.

@@ -480,3 +480,37 @@ def test_leapfrog_gradient_with_murnaghan_and_artificial_stress(variant):
     ref = AD.leapfrog_grad(w, steps, w.dt, "ke")
     assert rel(got["vel"].cpu().numpy(), ref["v0"]) < 1e-10
     assert abs(float(got["mu"]) - ref["mu"]) <= 1e-10 * abs(ref["mu"])
+
+
+@pytest.mark.parametrize("variant", ["cells", "list", "corrected", "all_terms", "du_only", "xv_only"])
+def test_rhs_adjoint_energy_and_xsph_cotangents(variant):
+    # cotangents of du/dt (section 3.1.2) and of dx/dt with XSPH (section 3.1.5)
+    w = small("cube8_visc")
+    w.params.update(xsph=0.5, correction=1.0 if variant == "corrected" else 0.0)
+    rng = np.random.default_rng(31)
+    w.rho = w.params["rho0"] * rng.uniform(0.99, 1.01, w.n)
+    if variant == "all_terms":
+        w.params.update(eps_s=0.2, n_s=4.0, eos=1.0, n_M=4.0)
+        w.d = rng.uniform(0.0, 1.0, w.n)
+    ref_out = native.rhs_workload(w, want_L=False, want_extra=True)
+    cot = {k: rng.normal(size=ref_out[k].shape) / np.abs(ref_out[k]).max()
+           for k in ("acc", "drho", "dS", "rho_sum")}
+    cot["du"] = rng.normal(size=w.n) / np.abs(ref_out["du"]).max()
+    cot["xv"] = rng.normal(size=(3, w.n)) / np.abs(ref_out["xv"] - w.vel).max()
+    if variant == "du_only":
+        cot = {"du": cot["du"]}
+    if variant == "xv_only":
+        cot = {"xv": cot["xv"]}
+    ref = AD.rhs_vjp(w, cot)
+    st = P.ParticleState.from_arrays(w.pos, w.vel, w.rho, w.S, w.m, d=getattr(w, "d", None))
+    g = P.sph_build_cells(st.pos, w.h, skin=0.05 * w.dx, pairs=variant != "cells")
+    got = P.sph_rhs_adjoint(g, st, w.params, {k: torch.as_tensor(v).cuda().contiguous() for k, v in cot.items()})
+    assert P.workspace_status(got["_ws"]) == 0
+    for k in ("pos", "vel", "rho", "S"):
+        gk = got[k].cpu().numpy()
+        if ref[k] is None:  # no dependence (the XSPH sum on the stress)
+            assert np.all(gk == 0.0), k
+            continue
+        assert rel(gk, ref[k]) < 1e-11, k
+    if ref["mu"] is not None and ref["mu"] != 0.0:
+        assert abs(float(got["mu"]) - ref["mu"]) <= 1e-11 * abs(ref["mu"])

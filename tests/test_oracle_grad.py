@@ -220,3 +220,37 @@ def test_torch_transcription_with_artificial_stress_matches_c_oracle_and_finite_
         assert abs(fd - ad) <= 1e-6 * abs(ad), (which, fd, ad)
     w.params["eps_s"] = 0.0  # the artificial stress acts on this state
     assert np.abs(AD.rhs(*AD.as_tensors(w))["acc"].numpy() - ref["acc"]).max() > 1e-6 * np.abs(ref["acc"]).max()
+
+
+def test_torch_transcription_energy_and_xsph_match_c_oracle_and_finite_differences():
+    # du/dt (section 3.1.2) and dx/dt with XSPH (section 3.1.5), with the artificial
+    # stress on (excluded from the energy bracket) and the Murnaghan sound speeds
+    w = small(seed=19, alpha=1.0, beta=1.0, eps_s=0.2, n_s=4.0, xsph=0.5, eos=1.0, n_M=4.0)
+    rng = np.random.default_rng(20)
+    w.rho = w.params["rho0"] * rng.uniform(0.99, 1.01, w.n)
+    ref = native.rhs_workload(w, want_extra=True)
+    out = AD.rhs(*AD.as_tensors(w))
+    for k in ("du", "xv"):
+        a, b = ref[k], out[k].detach().numpy()
+        if k == "xv":
+            a, b = a - w.vel, b - w.vel  # the XSPH correction itself
+        assert np.abs(a - b).max() <= 1e-13 * np.abs(a).max(), k
+    y = {"du": rng.normal(size=w.n) / np.abs(ref["du"]).max(),
+         "xv": rng.normal(size=(3, w.n)) / np.abs(ref["xv"] - w.vel).max()}
+    g = AD.rhs_vjp(w, y)
+
+    def obj(wp):
+        o = native.rhs_workload(wp, want_extra=True)
+        return float((o["du"] * y["du"]).sum() + (o["xv"] * y["xv"]).sum())
+
+    for which, scale in (("pos", w.dx), ("vel", 50.0), ("rho", 2700.0 * 1e-4), ("S", 6.75e7)):
+        u = rng.normal(size=getattr(w, which).shape)
+        ad = float((g[which] * u).sum())
+        eps = 1e-6 * scale
+        vals = []
+        for sgn in (+1, -1):
+            wp = w.copy()
+            setattr(wp, which, getattr(w, which) + sgn * eps * u)
+            vals.append(obj(wp))
+        fd = (vals[0] - vals[1]) / (2 * eps)
+        assert abs(fd - ad) <= 1e-6 * abs(ad), (which, fd, ad)
