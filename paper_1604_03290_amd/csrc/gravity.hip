@@ -36,6 +36,16 @@
 namespace sph {
 namespace {
 
+// One 48-byte tree item (one base address for both scalar loads of the walk):
+// pm = (x, y, z, m): a leaf's position and mass, an inner node's centre of mass and
+// mass once the monopole pass ran; link = (skip, info), info = depth for an inner node
+// and -1 - i for the leaf of sorted position i.
+struct __attribute__((aligned(16))) Item {
+    double4 pm;
+    int2 link;
+    int2 pad;
+};
+
 constexpr int kDepthMax = 21;  // 3 x 21 key bits
 
 // ------------------------------------------------------------------ keys --
@@ -173,14 +183,12 @@ __global__ __launch_bounds__(kBlock) void k_depth(const uint64_t *__restrict__ k
 }
 
 // ----------------------------------------------------------------- items --
-// Item t: pm[t] = (x, y, z, m) (a leaf's position and mass, an inner node's centre
-// of mass and mass once the monopole pass ran); link[t] = (skip, info), info = depth
-// for an inner node and -1 - i for the leaf of sorted position i.
+// Items of sorted position i: its inner nodes (depths D_{i-1} + 1 .. D_i), then its leaf.
 __global__ __launch_bounds__(kBlock) void k_items(
     const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ z,
     const double *__restrict__ m, const uint64_t *__restrict__ key, const int32_t *__restrict__ idx,
     const int64_t *__restrict__ off, int64_t n, int32_t *__restrict__ list,
-    double4 *__restrict__ pm, int2 *__restrict__ link) {
+    Item *__restrict__ it) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const int d1 = shared_depth(key, i, n), d0 = shared_depth(key, i - 1, n);
@@ -198,35 +206,34 @@ __global__ __launch_bounds__(kBlock) void k_items(
             else
                 hi = mid;
         }
-        link[t] = make_int2((int)(lo + off[lo]), d);
-        pm[t] = make_double4(0.0, 0.0, 0.0, 0.0);
+        it[t].link = make_int2((int)(lo + off[lo]), d);
+        it[t].pm = make_double4(0.0, 0.0, 0.0, 0.0);
         list[off[i] + (t - first)] = (int32_t)t;
     }
     const int a = idx[i];
-    link[t] = make_int2((int)(t + 1), (int)(-1 - i));
-    pm[t] = make_double4(x[a], y[a], z[a], m[a]);
+    it[t].link = make_int2((int)(t + 1), (int)(-1 - i));
+    it[t].pm = make_double4(x[a], y[a], z[a], m[a]);
 }
 
 // -------------------------------------------------------------- monopole --
 __global__ __launch_bounds__(kBlock) void k_monopole(const int32_t *__restrict__ list, int64_t K,
-                                                     int depth, double4 *__restrict__ pm,
-                                                     const int2 *__restrict__ link) {
+                                                     int depth, Item *__restrict__ it) {
 #pragma clang fp contract(off)
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= K) return;
     const int t = list[j];
-    const int2 lt = link[t];
+    const int2 lt = it[t].link;
     if (lt.y != depth) return;
     const int end = lt.x;
     double M = 0.0, mx = 0.0, my = 0.0, mz = 0.0;
-    for (int c = t + 1; c < end; c = link[c].x) {
-        const double4 p = pm[c];
+    for (int c = t + 1; c < end; c = it[c].link.x) {
+        const double4 p = it[c].pm;
         M = M + p.w;
         mx = mx + p.w * p.x;
         my = my + p.w * p.y;
         mz = mz + p.w * p.z;
     }
-    pm[t] = make_double4(mx / M, my / M, mz / M, M);
+    it[t].pm = make_double4(mx / M, my / M, mz / M, M);
 }
 
 // ------------------------------------------------------------------ walk --
@@ -268,8 +275,7 @@ __device__ inline bool opens_not(double s, double th2, double r2) {
 
 __global__ __launch_bounds__(kBlock) void k_walk(GravConsts k, const double *__restrict__ box,
                                                  const int32_t *__restrict__ idx,
-                                                 const double4 *__restrict__ pm,
-                                                 const int2 *__restrict__ link,
+                                                 const Item *__restrict__ it,
                                                  const int64_t *__restrict__ off,
                                                  const int64_t *__restrict__ cnt,
                                                  double *__restrict__ ax_out,
@@ -279,7 +285,7 @@ __global__ __launch_bounds__(kBlock) void k_walk(GravConsts k, const double *__r
     const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const bool live = i0 < k.n;
     const int64_t i = live ? i0 : k.n - 1;  // lanes past n walk the last particle, write nothing
-    const double4 me = pm[i + off[i] + cnt[i]];
+    const double4 me = it[i + off[i] + cnt[i]].pm;
     const double xa = me.x, ya = me.y, za = me.z;
     const double s0 = box[3];
     double ax = 0.0, ay = 0.0, az = 0.0;
@@ -287,13 +293,14 @@ __global__ __launch_bounds__(kBlock) void k_walk(GravConsts k, const double *__r
     int resume = 0;
     const int T = (int)k.T;
     int t = 0;
-    double4 p = pm[0];
-    int2 l = link[0];
+    double4 p = it[0].pm;
+    int2 l = it[0].link;
     while (t < T) {
         // both possible successors, fetched while this item is tested
         const int ta = min(t + 1, T - 1), tb = min(l.x, T - 1);
-        const double4 pa = pm[ta], pb = pm[tb];
-        const int2 la = link[ta], lb = link[tb];
+        const Item ia = it[ta], ib = it[tb];
+        const double4 pa = ia.pm, pb = ib.pm;
+        const int2 la = ia.link, lb = ib.link;
         const bool active = t >= resume;
         bool down = false;
         if (l.y >= 0) {
@@ -335,8 +342,7 @@ struct GravWs {
     int64_t *cnt, *off, *scan_tmp;
     int32_t *max_depth;
     int32_t *list;
-    double4 *pm;
-    int2 *link;
+    Item *it;
     void *sort_tmp;
     size_t sort_bytes;
 };
@@ -358,8 +364,7 @@ GravWs carve_grav(Carve &c, int64_t n, int64_t cap) {
     w.scan_tmp = c.take<int64_t>(scan_tmp_elems(n + 1));
     w.max_depth = c.take<int32_t>(1);
     w.list = c.take<int32_t>(cap);
-    w.pm = c.take<double4>(n + cap);
-    w.link = c.take<int2>(n + cap);
+    w.it = c.take<Item>(n + cap);
     w.sort_bytes = sort_bytes_bound(n);
     w.sort_tmp = c.take<char>(w.sort_bytes);
     return w;
@@ -435,14 +440,14 @@ extern "C" int sph_gravity(const double *x, const double *y, const double *z, co
     if (dmax > kDepthMax || (K > 0) != (dmax >= 0))
         return fail(SPH_ERR_HIP, "tree bookkeeping: depth %d with %lld nodes", dmax, (long long)K);
 
-    k_items<<<nb, kBlock, 0, s>>>(x, y, z, m, key, idx, w.off, n, w.list, w.pm, w.link);
+    k_items<<<nb, kBlock, 0, s>>>(x, y, z, m, key, idx, w.off, n, w.list, w.it);
     SPH_LAUNCHED();
     for (int d = dmax; d >= 0; --d) {
-        k_monopole<<<blocks_for(K), kBlock, 0, s>>>(w.list, K, d, w.pm, w.link);
+        k_monopole<<<blocks_for(K), kBlock, 0, s>>>(w.list, K, d, w.it);
         SPH_LAUNCHED();
     }
     const GravConsts k{G, theta * theta, eps, n, n + K};
-    k_walk<<<nb, kBlock, 0, s>>>(k, w.box, idx, w.pm, w.link, w.off, w.cnt, ax, ay, az, count);
+    k_walk<<<nb, kBlock, 0, s>>>(k, w.box, idx, w.it, w.off, w.cnt, ax, ay, az, count);
     SPH_LAUNCHED();
     return SPH_OK;
 }
