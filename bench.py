@@ -394,6 +394,14 @@ def main():
                 "avg_launch_ms": avg_ms, "launches": launches, "flops_per_pair": fpp,
                 "share_of_step": tot_ms / args.steps / ms_step,
                 "other": {k: {"avg_launch_ms": v[0] / max(v[1], 1), "launches": v[1]} for k, v in kern.items()}}
+    # the gather view of the same launch: partner bytes moved through the L1 per launch
+    # (every padded list entry loads its partner's chunks: 7 + 7 chunks of 16 B for the
+    # adjoint, 8 for the forward), at the kernel's average duration
+    gather_b = {"adjoint_pairs": 224, "pairs_fp64": 128}.get(dom)
+    if gather_b:
+        gb = gather_b * pl_cap
+        roofline["gather"] = {"bytes_per_launch": gb, "achieved_TBps": gb / (avg_ms * 1e-3) / 1e12,
+                              "bytes_per_entry": gather_b, "list_entries": pl_cap}
 
     result = {
         "metric": METRIC, "value": pairs_per_step / (ms_step * 1e-3), "unit": UNIT, "n_gpus": 1,
