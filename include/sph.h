@@ -118,8 +118,8 @@ typedef struct {
  * below.  flaw_ptr (int64, n + 1 entries, flaw_ptr[0] = 0, non-decreasing) and
  * flaw_eps (flaw_ptr[n] entries) list each particle's activation threshold
  * strains, ascending within a particle (section 3.2); they are read only for the
- * damage-rate outputs of sph_deriv and may be NULL otherwise.  sph_rhs_adjoint holds
- * d fixed (no cotangent for it); the leapfrog and its adjoint refuse damage. */
+ * damage-rate outputs of sph_deriv and may be NULL otherwise.  The adjoints and the
+ * leapfrog hold d fixed (no cotangent for it, no evolution). */
 typedef struct {
     int64_t n;
     const double *x, *y, *z;

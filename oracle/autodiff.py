@@ -222,17 +222,17 @@ def rhs_vjp(w, cot: dict, pairs=None):
     return {k: (v.detach().numpy() if v is not None else None) for k, v in zip(names, g)}
 
 
-def leapfrog(pos, vel, rho, S6, m, par, steps: int, dt: float, mu=None, Y0=None):
+def leapfrog(pos, vel, rho, S6, m, par, steps: int, dt: float, mu=None, Y0=None, d=None):
     """Kick-drift-kick trajectory; returns the final (pos, vel, rho, S)."""
     Y0v = float(par[4]) if Y0 is None else Y0
-    F = rhs(pos, vel, rho, S6, m, par, mu=mu, Y0=Y0)
+    F = rhs(pos, vel, rho, S6, m, par, mu=mu, Y0=Y0, d=d)
     x, v, r, S = pos, vel, rho, S6
     for _ in range(steps):
         v = v + 0.5 * dt * F["acc"]
         r = r + 0.5 * dt * F["drho"]
         S = limit(S + 0.5 * dt * F["dS"], Y0v)
         x = x + dt * v
-        F = rhs(x, v, r, S, m, par, mu=mu, Y0=Y0)
+        F = rhs(x, v, r, S, m, par, mu=mu, Y0=Y0, d=d)
         v = v + 0.5 * dt * F["acc"]
         r = r + 0.5 * dt * F["drho"]
         S = limit(S + 0.5 * dt * F["dS"], Y0v)
@@ -250,7 +250,8 @@ def leapfrog_grad_all(w, steps: int, dt: float, cot: dict):
     mu = torch.tensor(float(par[3]), dtype=DT, requires_grad=True)
     Y0 = torch.tensor(float(par[4]), dtype=DT, requires_grad=True)
     final = dict(zip(("pos", "vel", "rho", "S"),
-                     leapfrog(pos, vel, rho, S, m, par, steps, dt, mu=mu, Y0=Y0)))
+                     leapfrog(pos, vel, rho, S, m, par, steps, dt, mu=mu, Y0=Y0,
+                              d=getattr(w, "d", None))))
     J = sum((torch.from_numpy(np.asarray(cot[k], dtype=np.float64)) * final[k]).sum()
             for k in final if k in cot)
     g = torch.autograd.grad(J, [pos, vel, rho, S, mu, Y0], allow_unused=True)
@@ -273,7 +274,7 @@ def leapfrog_grad(w, steps: int, dt: float, objective: str = "ke", direction=Non
     vel.requires_grad_(True)
     mu = torch.tensor(float(par[3]), dtype=DT, requires_grad=True)
     Y0 = torch.tensor(float(par[4]), dtype=DT, requires_grad=True)
-    _, vT, _, _ = leapfrog(pos, vel, rho, S, m, par, steps, dt, mu=mu, Y0=Y0)
+    _, vT, _, _ = leapfrog(pos, vel, rho, S, m, par, steps, dt, mu=mu, Y0=Y0, d=getattr(w, "d", None))
     J = objective_value(vT, m, objective, direction)
     g = torch.autograd.grad(J, [vel, mu, Y0], allow_unused=True)
     z = lambda t, like: (t.detach().numpy() if t is not None else np.zeros_like(like))
@@ -301,5 +302,5 @@ def leapfrog_value(w, steps: int, dt: float, objective: str = "ke", direction=No
     with torch.no_grad():
         _, vT, _, _ = leapfrog(pos, vel0, rho, S, m, par, steps, dt,
                                mu=None if mu is None else float(mu),
-                               Y0=None if Y0 is None else float(Y0))
+                               Y0=None if Y0 is None else float(Y0), d=getattr(w, "d", None))
         return float(objective_value(vT, m, objective, direction))

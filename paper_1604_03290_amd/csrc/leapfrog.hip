@@ -64,7 +64,8 @@ __global__ __launch_bounds__(kBlock) void k_advance(Fields13 u, Deriv10 d, doubl
                                                     int kick1, GridDev g, Consts k,
                                                     const double *__restrict__ m,
                                                     double *__restrict__ rec,
-                                                    int32_t *__restrict__ status) {
+                                                    int32_t *__restrict__ status,
+                                                    const double *__restrict__ dmg) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double v[3], rho, S[6], F[10];
@@ -95,7 +96,8 @@ __global__ __launch_bounds__(kBlock) void k_advance(Fields13 u, Deriv10 d, doubl
             x[c] = u.p[c][i] + dt * v[c];
             u.p[c][i] = x[c];
         }
-        write_rec(g, k, i, x[0], x[1], x[2], v[0], v[1], v[2], rho, S, m[i], rec, status);
+        write_rec(g, k, i, x[0], x[1], x[2], v[0], v[1], v[2], rho, S, m[i], rec, status, 0.0,
+                  dmg ? dmg[i] : 0.0);
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) u.p[3 + c][i] = v[c];
@@ -194,7 +196,8 @@ __global__ __launch_bounds__(kBlock) void k_rev_kick2(Fields13 Uk, Deriv10 Fk, F
                                                       const double *__restrict__ L1, GridDev g,
                                                       Consts k, const double *__restrict__ m,
                                                       double *__restrict__ rec, AdjRec ad,
-                                                      double *acc_mu, int32_t *__restrict__ status) {
+                                                      double *acc_mu, int32_t *__restrict__ status,
+                                                      const double *__restrict__ dmg) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double y0p = 0.0, mup = 0.0;
     if (i < n) {
@@ -217,7 +220,7 @@ __global__ __launch_bounds__(kBlock) void k_rev_kick2(Fields13 Uk, Deriv10 Fk, F
         y0p = kick_adj_at(S, dS, gU, gF, i, h, Y0, accumulate, cF);
         const double mi = m[i];
         write_rec(g, k, i, x1[i], x1[n + i], x1[2 * n + i], v[0], v[1], v[2], rho, S, mi, rec,
-                  status);
+                  status, 0.0, dmg ? dmg[i] : 0.0);
         double L[9];
 #pragma unroll
         for (int c = 0; c < 9; ++c) L[c] = L1[c * n + i];
@@ -307,7 +310,7 @@ sph_deriv deriv_struct(const Deriv10 &d) {
     return o;
 }
 
-sph_state state_struct(const Fields13 &f, const double *m, int64_t n) {
+sph_state state_struct(const Fields13 &f, const double *m, int64_t n, const double *d) {
     sph_state s;
     s.n = n;
     s.x = f.p[0];
@@ -325,7 +328,7 @@ sph_state state_struct(const Fields13 &f, const double *m, int64_t n) {
     s.syz = f.p[12];
     s.m = m;
     s.u = nullptr;
-    s.d = nullptr;
+    s.d = d;
     s.flaw_ptr = nullptr;
     s.flaw_eps = nullptr;
     return s;
@@ -340,6 +343,21 @@ int state_to_slots(const sph_grid *grid, const sph_state *src, const Fields13 &d
     for (int c = 0; c < 13; ++c) b.p[c] = dst.p[c];
     b.p[13] = m;
     k_to_slots<<<blocks_for(grid->n), kBlock, 0, s>>>(a, b, 14, grid->perm, grid->n);
+    SPH_LAUNCHED();
+    return SPH_OK;
+}
+
+// damage, user order -> slot order (held fixed over the trajectory)
+int damage_to_slots(const sph_grid *grid, const double *d, double *dst, hipStream_t s) {
+    Src14 a;
+    Dst14 b;
+    for (int c = 0; c < 14; ++c) {
+        a.p[c] = nullptr;
+        b.p[c] = nullptr;
+    }
+    a.p[0] = d;
+    b.p[0] = dst;
+    k_to_slots<<<blocks_for(grid->n), kBlock, 0, s>>>(a, b, 1, grid->perm, grid->n);
     SPH_LAUNCHED();
     return SPH_OK;
 }
@@ -375,7 +393,6 @@ int check_lf(const sph_grid *grid, const sph_state *s0, const sph_params *params
         return fail(SPH_ERR_NOT_IMPLEMENTED, "the leapfrog drifts with v (no XSPH)");
     if (params->eos == 2.0)
         return fail(SPH_ERR_NOT_IMPLEMENTED, "the leapfrog does not evolve u (Tillotson)");
-    if (s0->d) return fail(SPH_ERR_NOT_IMPLEMENTED, "the leapfrog does not evolve damage");
     return SPH_OK;
 }
 
@@ -386,6 +403,7 @@ size_t leapfrog_ws_bytes(int64_t n) {
     carve_deriv(c, n);   // F, slot order
     carve_fields(c, n);  // state, slot order
     c.take<double>(n);   // masses, slot order
+    c.take<double>(n);   // damage, slot order
     c.used += rhs_ws_bytes(n);
     return c.used;
 }
@@ -397,6 +415,7 @@ size_t leapfrog_adjoint_ws_bytes(int64_t n) {
     carve_deriv(c, n);   // cotangent of F_{n+1}
     carve_deriv(c, n);   // cotangent of F_n
     c.take<double>(n);   // masses, slot order
+    c.take<double>(n);   // damage, slot order
     c.take<double>(blocks_for(n) + blocks_for(n, 64));  // mu and Y0 accumulators
     c.used += adjoint_ws_bytes(n);
     return c.used;
@@ -427,10 +446,13 @@ extern "C" int sph_leapfrog(const sph_grid *grid, const sph_state *s0, const sph
     Deriv10 F = carve_deriv(c, n);
     const Fields13 U = carve_fields(c, n);
     double *m = c.take<double>(n);
+    double *dmg = c.take<double>(n);
     Carve rc_ws(ws);  // the right-hand side shares the status word, carves after these
     rc_ws.used = c.used;
     if ((rc = state_to_slots(grid, s0, U, m, s))) return rc;
-    const sph_state st = state_struct(U, m, n);
+    if (s0->d && (rc = damage_to_slots(grid, s0->d, dmg, s))) return rc;
+    if (!s0->d) dmg = nullptr;
+    const sph_state st = state_struct(U, m, n, dmg);
     const sph_deriv d = deriv_struct(F);
     const double half = 0.5 * dt;
     const unsigned nb = blocks_for(n);
@@ -449,12 +471,12 @@ extern "C" int sph_leapfrog(const sph_grid *grid, const sph_state *s0, const sph
     if ((rc = rhs(0))) return rc;
     for (int k = 0; k < steps; ++k) {
         k_advance<<<nb, kBlock, 0, s>>>(U, F, slab(k), n, half, dt, Y0sq, k > 0, 1, g, kc, m, rec,
-                                        status);
+                                        status, dmg);
         SPH_LAUNCHED();
         if ((rc = rhs(k + 1))) return rc;
     }
     k_advance<<<nb, kBlock, 0, s>>>(U, F, slab(steps), n, half, dt, Y0sq, 1, 0, g, kc, m, rec,
-                                    status);
+                                    status, dmg);
     SPH_LAUNCHED();
     return fields_to_users(grid, U, fields_of(s_final), s);
 }
@@ -480,6 +502,7 @@ extern "C" int sph_leapfrog_adjoint(const sph_grid *grid, const sph_state *s0,
     Deriv10 gF1 = carve_deriv(c, n);
     Deriv10 gF0 = carve_deriv(c, n);
     double *m = c.take<double>(n);
+    double *dmg = c.take<double>(n);
     // mu accumulators per block, then Y0 per block (kicks) or per wavefront (pairs)
     const unsigned nw = blocks_for(n, 64);
     double *parts = c.take<double>(blocks_for(n) + nw);
@@ -501,6 +524,8 @@ extern "C" int sph_leapfrog_adjoint(const sph_grid *grid, const sph_state *s0,
         k_to_slots<<<nb, kBlock, 0, s>>>(a, b, 14, grid->perm, n);
         SPH_LAUNCHED();
     }
+    if (s0->d && (rc = damage_to_slots(grid, s0->d, dmg, s))) return rc;
+    if (!s0->d) dmg = nullptr;
     k_fill<<<blocks_for(nb + nw), kBlock, 0, s>>>(parts, nb + nw, 0.0);
     SPH_LAUNCHED();
     double *acc_y0 = parts + nb;
@@ -535,12 +560,12 @@ extern "C" int sph_leapfrog_adjoint(const sph_grid *grid, const sph_state *s0,
         k_rev_kick2<<<nb, kBlock, 0, s>>>(Uk, Fk, Up, Fk1, gU, gF1, n, half, Y0,
                                           k + 1 < steps ? 1 : 0, acc_y0, Uk1.p[0],
                                           slab_k1 + (size_t)kLOffset * n, g, kc, m, ab.rec,
-                                          ab.ad, parts, status);
+                                          ab.ad, parts, status, dmg);
         SPH_LAUNCHED();
         Fields13 Upx = Up;
         for (int c3 = 0; c3 < 3; ++c3) Upx.p[c3] = Uk1.p[c3];
         // right-hand side F_{k+1} = F(x_{k+1}, U'): its pair stage
-        const sph_state st1 = state_struct(Upx, m, n);
+        const sph_state st1 = state_struct(Upx, m, n, dmg);
         if ((rc = adjoint_at(st1, gF1, slab_k1, true))) return rc;
         // drift x_{k+1} = x_k + dt v', then the first kick U' = kick(U_k, F_k):
         // cotangent of U_k, fresh cotangent of F_k
@@ -551,7 +576,7 @@ extern "C" int sph_leapfrog_adjoint(const sph_grid *grid, const sph_state *s0,
         gF0 = tmp;
     }
     // F_0 = F(x_0, U_0)
-    const sph_state st0 = state_struct(slab_fields(ck, n), m, n);
+    const sph_state st0 = state_struct(slab_fields(ck, n), m, n, dmg);
     if ((rc = adjoint_at(st0, gF1, ck, false))) return rc;
     // dparams = the accumulators summed in a fixed order
     if ((rc = reduce_params_launch(parts, nb, acc_y0, nw, dparams, 0, s))) return rc;

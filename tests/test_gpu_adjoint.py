@@ -514,3 +514,31 @@ def test_rhs_adjoint_energy_and_xsph_cotangents(variant):
         assert rel(gk, ref[k]) < 1e-11, k
     if ref["mu"] is not None and ref["mu"] != 0.0:
         assert abs(float(got["mu"]) - ref["mu"]) <= 1e-11 * abs(ref["mu"])
+
+
+def test_leapfrog_with_fixed_damage_trajectory_and_gradient():
+    # a damage field held fixed over the trajectory (section 2.7): states and the
+    # gradient of the final kinetic energy against the oracle's transcription
+    w = small("cube8_visc")
+    rng = np.random.default_rng(37)
+    w.rho = w.params["rho0"] * rng.uniform(0.99, 1.01, w.n)
+    w.d = rng.uniform(0.0, 1.0, w.n)
+    steps = 8
+    st = P.ParticleState.from_arrays(w.pos, w.vel, w.rho, w.S, w.m, d=w.d)
+    g = P.sph_build_cells(st.pos, w.h, skin=0.5 * w.dx, pairs=True)
+    fin, ck = P.sph_leapfrog(g, st, w.params, w.dt, steps)
+    assert P.workspace_status(fin._ws) == 0
+    pos, vel, rho, S, m, par = AD.as_tensors(w)
+    with torch.no_grad():
+        x, v, r, s = AD.leapfrog(pos, vel, rho, S, m, par, steps, w.dt, d=w.d)
+    assert rel(fin.vel.cpu().numpy(), v.numpy()) < 1e-11
+    assert rel(fin.S.cpu().numpy(), s.numpy()) < 1e-11
+    cot = {"vel": (fin.vel * fin.m).contiguous()}
+    got = P.sph_leapfrog_adjoint(g, st, w.params, w.dt, steps, ck, cot)
+    assert P.workspace_status(got["_ws"]) == 0
+    ref = AD.leapfrog_grad(w, steps, w.dt, "ke")
+    assert rel(got["vel"].cpu().numpy(), ref["v0"]) < 1e-10
+    assert abs(float(got["mu"]) - ref["mu"]) <= 1e-10 * abs(ref["mu"])
+    # the damage matters on this trajectory
+    w.d = None
+    assert rel(AD.leapfrog_grad(w, steps, w.dt, "ke")["v0"], ref["v0"]) > 1e-6

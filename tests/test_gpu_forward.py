@@ -540,13 +540,10 @@ def test_zero_damage_and_rate_outputs_change_nothing():
         assert np.array_equal(base[k], zero[k]), k
 
 
-def test_damage_refused_where_not_built_and_bad_flaw_lists_flagged():
+def test_damage_argument_errors_and_bad_flaw_lists_flagged():
     w = damage_variant(seed=35)
     st = P.ParticleState.from_arrays(w.pos, w.vel, w.rho, w.S, w.m, d=w.d, flaws=w.flaws)
     g = P.sph_build_cells(st.pos, w.h)
-    with pytest.raises(L.SphError) as e:
-        P.sph_leapfrog(g, st, w.params, w.dt, 2)
-    assert e.value.code == L.SPH_ERR_NOT_IMPLEMENTED
     bare = P.ParticleState.from_arrays(w.pos, w.vel, w.rho, w.S, w.m, d=w.d)
     with pytest.raises(L.SphError) as e:
         P.sph_rhs(g, bare, w.params, damage=True)
