@@ -373,31 +373,35 @@ class SphRhs(torch.autograd.Function):
     """Differentiable FP64 right-hand side: forward calls sph_rhs, backward calls
     sph_rhs_adjoint (the exact vector-Jacobian product on the same partner set).
 
-    apply(pos, vel, rho, S, mu, Y0, grid, params, m) -> (acc, drho, dS, rho_sum), with pos,
-    vel (3, n), rho (n), S (6, n), m (n) device tensors in user order and mu, Y0 scalar
-    tensors (their values replace params' mu and Y0; their gradients come from the
-    adjoint).  The masses and the remaining constants are not differentiated."""
+    apply(pos, vel, rho, S, mu, Y0, grid, params, m, d=None, extra=False)
+    -> (acc, drho, dS, rho_sum), and with ``extra`` also (du, xv), the energy rate and
+    dx/dt with XSPH.  pos, vel (3, n), rho (n), S (6, n), m (n) are device tensors in
+    user order and mu, Y0 scalar tensors (their values replace params' mu and Y0; their
+    gradients come from the adjoint).  The masses, a damage field d (n) and the other
+    constants are held fixed."""
 
     @staticmethod
-    def forward(ctx, pos, vel, rho, S, mu, Y0, grid, params, m):
+    def forward(ctx, pos, vel, rho, S, mu, Y0, grid, params, m, d=None, extra=False):
         p = dict(params) if isinstance(params, dict) else dict(zip(PARAM_ORDER, params))
         p["mu"] = float(mu)
         p["Y0"] = float(Y0)
         st = ParticleState(pos.detach().contiguous(), vel.detach().contiguous(),
-                           rho.detach().contiguous(), S.detach().contiguous(), m.contiguous())
-        out = sph_rhs(grid, st, p, "fp64")
-        ctx.grid, ctx.params, ctx.state = grid, p, st
+                           rho.detach().contiguous(), S.detach().contiguous(), m.contiguous(),
+                           d=None if d is None else d.detach().contiguous())
+        out = sph_rhs(grid, st, p, "fp64", extra=extra)
+        ctx.grid, ctx.params, ctx.state, ctx.extra = grid, p, st, extra
         ctx.mu_like, ctx.Y0_like = torch.as_tensor(mu), torch.as_tensor(Y0)
-        return out["acc"], out["drho"], out["dS"], out["rho_sum"]
+        res = (out["acc"], out["drho"], out["dS"], out["rho_sum"])
+        return res + ((out["du"], out["xv"]) if extra else ())
 
     @staticmethod
-    def backward(ctx, g_acc, g_drho, g_dS, g_rs):
-        cot = {k: (v.contiguous() if v is not None else None)
-               for k, v in (("acc", g_acc), ("drho", g_drho), ("dS", g_dS), ("rho_sum", g_rs))}
+    def backward(ctx, *grads):
+        names = ("acc", "drho", "dS", "rho_sum", "du", "xv")
+        cot = {k: (v.contiguous() if v is not None else None) for k, v in zip(names, grads)}
         g = sph_rhs_adjoint(ctx.grid, ctx.state, ctx.params, cot)
         gmu = g["mu"].to(ctx.mu_like.device, ctx.mu_like.dtype).reshape(ctx.mu_like.shape)
         gY0 = g["Y0"].to(ctx.Y0_like.device, ctx.Y0_like.dtype).reshape(ctx.Y0_like.shape)
-        return g["pos"], g["vel"], g["rho"], g["S"], gmu, gY0, None, None, None
+        return g["pos"], g["vel"], g["rho"], g["S"], gmu, gY0, None, None, None, None, None
 
 
 def _fields(n, dev):

@@ -542,3 +542,28 @@ def test_leapfrog_with_fixed_damage_trajectory_and_gradient():
     # the damage matters on this trajectory
     w.d = None
     assert rel(AD.leapfrog_grad(w, steps, w.dt, "ke")["v0"], ref["v0"]) > 1e-6
+
+
+def test_autograd_function_with_extra_outputs_and_damage():
+    w = small("cube8_visc")
+    w.params.update(xsph=0.5, eps_s=0.2, n_s=4.0)
+    rng = np.random.default_rng(41)
+    w.rho = w.params["rho0"] * rng.uniform(0.99, 1.01, w.n)
+    w.d = rng.uniform(0.0, 1.0, w.n)
+    ref_out = native.rhs_workload(w, want_L=False, want_extra=True)
+    cot = {k: rng.normal(size=ref_out[k].shape) / np.abs(ref_out[k]).max() for k in ("acc", "drho", "dS", "rho_sum", "du")}
+    cot["xv"] = rng.normal(size=(3, w.n)) / np.abs(ref_out["xv"] - w.vel).max()
+    ref = AD.rhs_vjp(w, cot)
+    st = P.ParticleState.from_arrays(w.pos, w.vel, w.rho, w.S, w.m, d=w.d)
+    g = P.sph_build_cells(st.pos, w.h, skin=0.05 * w.dx, pairs=True)
+    leaves = [t.clone().requires_grad_(True) for t in (st.pos, st.vel, st.rho, st.S)]
+    mu = torch.tensor(w.params["mu"], dtype=torch.float64, device="cuda", requires_grad=True)
+    Y0 = torch.tensor(w.params["Y0"], dtype=torch.float64, device="cuda", requires_grad=True)
+    outs = P.SphRhs.apply(*leaves, mu, Y0, g, w.params, st.m, st.d, True)
+    assert len(outs) == 6
+    loss = sum((o * torch.as_tensor(cot[k]).cuda()).sum()
+               for k, o in zip(("acc", "drho", "dS", "rho_sum", "du", "xv"), outs))
+    loss.backward()
+    for k, t in zip(("pos", "vel", "rho", "S"), leaves):
+        assert rel(t.grad.cpu().numpy(), ref[k]) < 1e-11, k
+    assert abs(float(mu.grad) - ref["mu"]) <= 1e-11 * abs(ref["mu"])
