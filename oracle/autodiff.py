@@ -21,7 +21,12 @@ readings as ``sph_oracle.c`` (see its header for the passages):
   3.1.2) and the XSPH velocity v_a + xsph sum_b 2 m_b / (rho_a + rho_b) (v_b - v_a) W
   (section 3.1.5), and optionally a fixed damage field d
   (section 2.7): sigma_d = -p^ I + (1 - d) f_Y S, p^ = p for p >= 0 and (1 - d) p
-  below, in the momentum equation only.
+  below, in the momentum equation only, and the Tillotson equation of state (section
+  2.5.3) when par[14] = 2: the compressed form for rho >= rho0 or u <= E_iv, the
+  expanded form for u >= E_cv, the two joined linearly in u between, an input u per
+  particle, the sound speed sqrt(max(dp/drho + p / rho^2 dp/du, 0)) whose two partial
+  derivatives autograd forms here with a graph of their own, so that the vector-Jacobian
+  product reaches second derivatives of p (no hand derivation either).
 
 Also the kick-drift-kick leapfrog used to drive the adjoint (the paper's own
 integrators are the predictor-corrector and RK3 of section 3.4; the leapfrog
@@ -99,12 +104,46 @@ def correction_tensor(M: torch.Tensor) -> torch.Tensor:
     return torch.where(ok, A / torch.where(ok, det, torch.ones_like(det)), eye)
 
 
-def rhs(pos, vel, rho, S6, m, par, mu=None, Y0=None, pairs=None, d=None):
+def tillotson(rho, u, par):
+    """Tillotson pressure of section 2.5.3 per particle from eta = rho / rho0 and
+    w = 1 + u / (E0 eta^2): the compressed form a rho u + b rho u / w + A (eta - 1)
+    + B (eta - 1)^2 for rho >= rho0 or u <= E_iv, the expanded form a rho u +
+    (b rho u / w + A (eta - 1) e^{-beta (rho0/rho - 1)}) e^{-alpha (rho0/rho - 1)^2} for
+    u >= E_cv, and the straight line in u between the two in the remaining band."""
+    rho0 = float(par[1])
+    a, b, A, B, E0 = (float(par[k]) for k in (16, 17, 18, 19, 20))
+    al, be, Eiv, Ecv = (float(par[k]) for k in (21, 22, 23, 24))
+    eta = rho / rho0
+    chi = eta - 1.0
+    bw = b * rho * u / (1.0 + u / (E0 * eta * eta))
+    p1 = a * rho * u + bw + A * chi + B * chi * chi
+    z = rho0 / rho - 1.0
+    p2 = a * rho * u + (bw + A * chi * torch.exp(-be * z)) * torch.exp(-al * z * z)
+    t = (u - Eiv) / (Ecv - Eiv)
+    mixed = (1.0 - t) * p1 + t * p2
+    cold = (rho >= rho0) | (u <= Eiv)
+    return torch.where(cold, p1, torch.where(u >= Ecv, p2, mixed))
+
+
+def tillotson_pc(rho, u, par):
+    """Pressure and sound speed of the Tillotson equation; the partial derivatives of p
+    come from autograd on a graph of their own, kept so that c is differentiable."""
+    r = rho if rho.requires_grad else rho.detach().clone().requires_grad_(True)
+    e = u if u.requires_grad else u.detach().clone().requires_grad_(True)
+    with torch.enable_grad():
+        p = tillotson(r, e, par)
+        pr, pu = torch.autograd.grad(p.sum(), [r, e], create_graph=True)
+    c2 = pr + p / (r * r) * pu
+    return p, torch.sqrt(torch.clamp(c2, min=0.0))
+
+
+def rhs(pos, vel, rho, S6, m, par, mu=None, Y0=None, pairs=None, d=None, u=None):
     """Right-hand side of every particle.  ``par`` = {h, rho0, c, mu, Y0, alpha,
     beta, eps_v, rho_cut, correction}; ``mu``/``Y0`` may be tensors (differentiable)
     overriding par[3]/par[4]; ``d`` (n) a damage field held fixed.  Returns dict
     acc (3, n), drho, dS (6, n), rho_sum, L (3, 3, n) (L: the gradient that drives the
-    stress rate, corrected when par[9] != 0)."""
+    stress rate, corrected when par[9] != 0); ``u`` (n) the specific internal energy, a
+    tensor that may require grad, used by the Tillotson equation only."""
     h, rho0, c = float(par[0]), float(par[1]), float(par[2])
     alpha, beta, eps_v, rho_cut = float(par[5]), float(par[6]), float(par[7]), float(par[8])
     corr = len(par) > 9 and float(par[9]) != 0.0
@@ -126,9 +165,13 @@ def rhs(pos, vel, rho, S6, m, par, mu=None, Y0=None, pairs=None, d=None):
     elif eos == 0.0:
         p = c * c * (rho - rho0)
         cs = None
+    elif eos == 2.0:
+        if u is None:
+            u = torch.zeros_like(rho)
+        p, cs = tillotson_pc(rho, u, par)
     else:
-        raise NotImplementedError("the transcription covers the liquid and Murnaghan equations")
-    if rho_cut > 0:
+        raise ValueError("equation of state %r" % eos)
+    if rho_cut > 0 and eos != 2.0:
         p = torch.where(rho / rho0 < rho_cut, torch.zeros_like(p), p)
     f = yield_factor(S6, Y0)
     St = _mat(f * S6)
@@ -206,19 +249,21 @@ def as_tensors(w):
 def rhs_vjp(w, cot: dict, pairs=None):
     """J^T y of one right-hand side: cotangents ``cot`` with keys acc (3, n), drho (n),
     dS (6, n), rho_sum (n) and optionally du (n) and xv (3, n).  Returns gradients pos,
-    vel, rho, S (6, n), mu, Y0."""
+    vel, rho, S (6, n), mu, Y0, and u (n; None unless the equation of state reads it)."""
     pos, vel, rho, S, m, par = as_tensors(w)
+    u = torch.from_numpy(np.asarray(getattr(w, "u", None) if getattr(w, "u", None) is not None
+                                    else np.zeros(w.n), dtype=np.float64)).requires_grad_(True)
     mu = torch.tensor(float(par[3]), dtype=DT, requires_grad=True)
     Y0 = torch.tensor(float(par[4]), dtype=DT, requires_grad=True)
     for t in (pos, vel, rho, S):
         t.requires_grad_(True)
-    out = rhs(pos, vel, rho, S, m, par, mu=mu, Y0=Y0, pairs=pairs, d=getattr(w, "d", None))
+    out = rhs(pos, vel, rho, S, m, par, mu=mu, Y0=Y0, pairs=pairs, d=getattr(w, "d", None), u=u)
     y = 0.0
     for k in ("acc", "drho", "dS", "rho_sum", "du", "xv"):
         if cot.get(k) is not None:
             y = y + (out[k] * torch.from_numpy(np.asarray(cot[k], dtype=np.float64))).sum()
-    g = torch.autograd.grad(y, [pos, vel, rho, S, mu, Y0], allow_unused=True)
-    names = ["pos", "vel", "rho", "S", "mu", "Y0"]
+    g = torch.autograd.grad(y, [pos, vel, rho, S, mu, Y0, u], allow_unused=True)
+    names = ["pos", "vel", "rho", "S", "mu", "Y0", "u"]
     return {k: (v.detach().numpy() if v is not None else None) for k, v in zip(names, g)}
 
 

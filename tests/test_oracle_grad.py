@@ -254,3 +254,50 @@ def test_torch_transcription_energy_and_xsph_match_c_oracle_and_finite_differenc
             vals.append(obj(wp))
         fd = (vals[0] - vals[1]) / (2 * eps)
         assert abs(fd - ad) <= 1e-6 * abs(ad), (which, fd, ad)
+
+
+@pytest.mark.parametrize("regime", ["compressed", "expanded", "band", "mixed"])
+def test_torch_transcription_with_tillotson_matches_c_oracle_and_finite_differences(regime):
+    # the Tillotson equation (section 2.5.3) in each of its regions: the sound speed
+    # comes from autograd here and from hand-derived partials in the C oracle, and
+    # the gradient reaches u through the pressure and through the sound speed
+    w = small(seed=19, alpha=1.0, beta=1.0, eos=2.0)
+    rng = np.random.default_rng(20)
+    rho0, Eiv, Ecv = w.params["rho0"], w.params["E_iv"], w.params["E_cv"]
+    lo, hi = {"compressed": (1.001, 1.03), "expanded": (0.97, 0.999), "band": (0.97, 0.999),
+              "mixed": (0.97, 1.03)}[regime]
+    w.rho = rho0 * rng.uniform(lo, hi, w.n)
+    if regime == "compressed":
+        w.u = rng.uniform(0.0, 2e7, w.n)
+    elif regime == "expanded":
+        w.u = rng.uniform(1.05 * Ecv, 1.5 * Ecv, w.n)
+    elif regime == "band":
+        w.u = rng.uniform(1.05 * Eiv, 0.95 * Ecv, w.n)
+    else:
+        w.u = rng.choice([0.5 * Eiv, 0.5 * (Eiv + Ecv), 1.3 * Ecv], w.n) * rng.uniform(0.95, 1.05, w.n)
+    ref = native.rhs_workload(w, want_L=False, want_extra=True)
+    pos, vel, rho, S, m, par = AD.as_tensors(w)
+    out = AD.rhs(pos, vel, rho, S, m, par, u=torch.from_numpy(w.u))
+    for k in ("acc", "drho", "dS", "rho_sum", "du"):
+        a, b = ref[k], out[k].detach().numpy()
+        assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max(), k
+    keys = ("acc", "drho", "dS", "rho_sum", "du")
+    y = {k: rng.normal(size=ref[k].shape) / np.abs(ref[k]).max() for k in keys}
+    g = AD.rhs_vjp(w, y)
+
+    def objective(wp):
+        o = native.rhs_workload(wp, want_L=False, want_extra=True)
+        return sum(float((o[k] * y[k]).sum()) for k in keys)
+
+    for field, scale in (("rho", 1e-7 * rho0), ("u", 1e-7 * Ecv)):
+        dirn = rng.normal(size=w.n)
+        ad = float((g[field] * dirn).sum())
+        vals = []
+        for sgn in (+1, -1):
+            wp = w.copy()
+            setattr(wp, field, getattr(w, field) + sgn * scale * dirn)
+            vals.append(objective(wp))
+        fd = (vals[0] - vals[1]) / (2 * scale)
+        assert abs(fd - ad) <= 1e-6 * abs(ad), (field, fd, ad)
+    # u acts through the pressure and the sound speed: its gradient is not zero
+    assert np.abs(g["u"]).max() > 0.0

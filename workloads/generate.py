@@ -88,10 +88,14 @@ class Workload:
         return lo, hi
 
     def copy(self) -> "Workload":
-        return Workload(
+        w = Workload(
             self.name, self.pos.copy(), self.vel.copy(), self.rho.copy(), self.S.copy(),
             self.m.copy(), self.h, self.dx, dict(self.params), self.dt, self.steps, dict(self.meta),
         )
+        for k in ("u", "d"):  # optional per-particle fields, set on some workloads
+            if getattr(self, k, None) is not None:
+                setattr(w, k, getattr(self, k).copy())
+        return w
 
     def take(self, idx: np.ndarray) -> "Workload":
         """Sub-set of particles (same constants)."""
