@@ -151,8 +151,8 @@ typedef struct {
  * or u <= E_iv, expanded form for rho < rho0 and u >= E_cv, linear in u between).
  * With eos 1 or 2 each particle's sound speed is the thermodynamic one,
  * c^2 = dp/drho|u + p / rho^2 dp/du|rho (floored at 0), and Pi uses the pair's mean
- * (the adjoints take Murnaghan and refuse Tillotson, which the leapfrog refuses
- * too). */
+ * (the adjoint of one right-hand side takes both, with the gradient of u for
+ * Tillotson; the leapfrog and its adjoint take Murnaghan and refuse Tillotson). */
 typedef struct {
     double h, rho0, c, mu, Y0, alpha, beta, eps_v, rho_cut, correction;
     double eps_s, n_s, dmpd, xsph;
@@ -205,6 +205,8 @@ typedef struct {
     double *vx, *vy, *vz;
     double *rho;
     double *sxx, *syy, *szz, *sxy, *sxz, *syz;
+    double *u; /* gradient of u: written by sph_rhs_adjoint with the Tillotson
+                  equation (required there), otherwise unused and may be NULL */
 } sph_fields;
 
 typedef sph_fields sph_state_grad;
@@ -316,9 +318,13 @@ int sph_rhs(const sph_grid *grid, const sph_state *state, const sph_params *para
  * correction tensor C = M^-1 is differentiated too (M depends on positions and,
  * through V = m / rho, on densities); where C fell back to the identity M gets
  * no cotangent.  With the Murnaghan equation the pressure's slope and the sound
- * speeds in Pi are differentiated too, and so is the artificial stress (its tension
- * switch held), and the energy rate and dx/dt when their cotangents are given.
- * Errors as sph_rhs, and NOT_IMPLEMENTED for the Tillotson equation. */
+ * speeds in Pi are differentiated too; with Tillotson also (grad->u, user order,
+ * overwritten) the gradient with respect to u, through the pressure and through the
+ * sound speed, whose partials need the second derivatives of p (each region's form
+ * differentiated, the region held; the floor of c^2 at 0 passes no gradient).  So is
+ * the artificial stress (its tension switch held), and the energy rate and dx/dt when
+ * their cotangents are given.  Errors as sph_rhs, and INVALID_ARG for Tillotson with
+ * grad->u NULL. */
 int sph_rhs_adjoint(const sph_grid *grid, const sph_state *state, const sph_params *params,
                     const sph_deriv_cot *cot, const sph_state_grad *grad, double *dparams,
                     void *ws, size_t ws_bytes, void *stream);

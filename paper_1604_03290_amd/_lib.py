@@ -84,7 +84,7 @@ class DerivCot(C.Structure):
 
 
 class Fields(C.Structure):
-    _fields_ = [(k, _pd) for k in _FIELDS]
+    _fields_ = [(k, _pd) for k in _FIELDS + ("u",)]
 
 
 class CFields(C.Structure):

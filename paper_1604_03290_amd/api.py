@@ -344,7 +344,7 @@ def sph_rhs_adjoint(grid: CellGrid, state: ParticleState, params, cot: dict,
                     ws: torch.Tensor | None = None) -> dict:
     """Vector-Jacobian product of sph_rhs (C: sph_rhs_adjoint).  ``cot`` has keys of
     sph_rhs's outputs (acc, drho, dS, rho_sum, du, xv; missing = zero).  Returns
-    gradients pos, vel, rho, S, mu, Y0."""
+    gradients pos, vel, rho, S, mu, Y0, and u with the Tillotson equation."""
     n = state.n
     dev = state.rho.device
     z3 = lambda k, shape: _dev(cot[k]) if cot.get(k) is not None else None
@@ -360,6 +360,9 @@ def sph_rhs_adjoint(grid: CellGrid, state: ParticleState, params, cot: dict,
         ws = workspace(L.SPH_OP_ADJOINT, n, 0, dev)
     cs = state.c_state()
     fs = fields_struct(g["pos"], g["vel"], g["rho"], g["S"])
+    if params_struct(params).eos == 2.0:
+        g["u"] = torch.empty(n, dtype=F64, device=dev)
+        fs.u = g["u"].data_ptr()
     L.check(L.lib().sph_rhs_adjoint(C.byref(grid.c), C.byref(cs), C.byref(params_struct(params)),
                                     C.byref(dc), C.byref(fs), _ptr(dparams), _ptr(ws), ws.numel(),
                                     _stream()))

@@ -30,9 +30,15 @@
 //           (section 2.6) to rho_bar, S_bar and Y0_bar.  With the Murnaghan
 //           equation (section 2.5.2) dp/drho = K0/rho0 eta^(n-1) and Pi's mean
 //           sound speed (c_c + c_b)/2 carries rho too: cbar_c += Pibar dPi/dcbar / 2
-//           per pair, rho_bar += cbar_c c_c (n - 1) / (2 rho_c).  The artificial stress
+//           per pair, rho_bar += cbar_c c_c (n - 1) / (2 rho_c).  With Tillotson
+//           (section 2.5.3) c^2 = D = p_rho + p p_u / rho^2, whose partials D_rho and
+//           D_u come from evaluating the region's form on first-order jets in (rho, u):
+//           rho_bar += cbar_c D_rho / (2 c), u_bar += cbar_c D_u / (2 c) + p^_u tr(Tbar)
+//           (-1/rho^2), the partner's sound speed and tension read from its record's
+//           signed c.  The artificial stress
 //           (section 3.1.4) adds Z = (zeta_c + zeta_b) f^n to B, zeta = -eps_s T in
-//           tension (p < 0, here rho < rho0 outside the cut-off), f = w(q)/w(dmpd):
+//           tension (p < 0, for the liquid and Murnaghan equations rho < rho0 outside
+//           the cut-off), f = w(q)/w(dmpd):
 //           Tbar_c gains the factor 1 + zeta_c/T_c f^n and
 //           xbar_c += (A . (zeta_c + zeta_b) g) n f^(n-1) g / (w(dmpd) Wn).  The
 //           cotangents ubar of du/dt and chi of dx/dt (sections 3.1.2, 3.1.5) add,
@@ -228,13 +234,14 @@ __device__ inline double murnaghan_c(const Consts &k, double rho) {
 // of c and b, whose terms P r r^T (P = -V_b F, r = x_c - x_b) add
 //   xbar_c += -[V_b (2 F Mc r + (r.Mc r) G r) + V_c (2 F Mb r + (r.Mb r) G r)],
 //   Vbar_c += -F (r.Mb r).
-template <bool kCorr = false, bool kEos = false, bool kAS = false, bool kXC = false>
+template <bool kCorr = false, int kEos = 0, bool kAS = false, bool kXC = false>
 __device__ inline void adj_pair(const Consts &k, const AdjOwn &o, double d2, double2 b0,
                                 double2 b1, double2 b2, double2 b3, double2 b4, double2 b5,
                                 double2 b6, double2 e0, double2 e1, double2 e2, double2 e3,
                                 double2 e4, double2 e5, double2 e6, AdjAcc &acc,
                                 const double *Mc = nullptr, const double *Mb = nullptr,
-                                const double *xo = nullptr, const double *xb = nullptr) {
+                                const double *xo = nullptr, const double *xb = nullptr,
+                                double cb = 0.0 /* Tillotson: partner's signed c */) {
     const double Gn = k.Fn * k.inv_h * k.inv_h;
     const double Lbb[9] = {e0.x, e0.y, e1.x, e1.y, e2.x, e2.y, e3.x, e3.y, e4.x};
     const double rx = o.xc - b0.x, ry = o.yc - b0.y, rz = o.zc - b1.x;
@@ -257,7 +264,8 @@ __device__ inline void adj_pair(const Consts &k, const AdjOwn &o, double d2, dou
     for (int i = 0; i < 9; ++i) M[i] = Vb * o.Lbc[i] + o.Vc * Lbb[i];
     const double w = -(ux * rx + uy * ry + uz * rz);
     double alpha_c = k.alpha_c;
-    if constexpr (kEos) alpha_c = k.alpha * (0.5 * (o.cc + murnaghan_c(k, rb_)));
+    if constexpr (kEos == 1) alpha_c = k.alpha * (0.5 * (o.cc + murnaghan_c(k, rb_)));
+    if constexpr (kEos == 2) alpha_c = k.alpha * (0.5 * (o.cc + fabs(cb)));
     const Visc vs = viscosity(k, d2, w, o.rc, rb_, alpha_c);
     const double Pi = vs.Pi;
     double B0 = o.Tc[0] + b4.x - Pi, B1 = o.Tc[1] + b4.y - Pi;
@@ -267,7 +275,8 @@ __device__ inline void adj_pair(const Consts &k, const AdjOwn &o, double d2, dou
     // artificial stress: Z0 = zeta_c + zeta_b, fn = f^n, dfn = n f^(n-1) / (w(dmpd) Wn)
     double Z0[6] = {0, 0, 0, 0, 0, 0}, fn = 0.0, dfn = 0.0, zc = 0.0;
     if constexpr (kAS) {
-        const bool tb = rb_ < k.rho0 && !(k.rho_cut > 0.0 && rb_ / k.rho0 < k.rho_cut);
+        const bool tb = kEos == 2 ? signbit(cb)
+                                  : rb_ < k.rho0 && !(k.rho_cut > 0.0 && rb_ / k.rho0 < k.rho_cut);
         if (o.tens || tb) {
             const double f = kp.w * k.inv_wm;
             if (k.n_int > 0) {
@@ -388,7 +397,7 @@ __device__ inline AdjOwn adj_own(const double *rec, const AdjRec &ad, int64_t s)
 
 // pre stage: T = ((1 - d) f S - p^ I) / rho^2, V = m / rho, pressure, limiter; writes
 // the gradients of user particle a; returns the Y0 contribution
-template <bool kEos = false>
+template <int kEos = 0>
 __device__ inline double adj_pre(const Consts &k, const AdjRec &ad, const AdjOwn &o,
                                  const AdjAcc &acc, int64_t s, int a, const StateDev &st,
                                  const GradDev &out) {
@@ -402,13 +411,31 @@ __device__ inline double adj_pre(const Consts &k, const AdjRec &ad, const AdjOwn
     double grho = ad.rhob[s] + acc.grho - acc.gV * o.Vc / rc;
 #pragma unroll
     for (int i = 0; i < 6; ++i) grho += acc.gT[i] * (-2.0 * o.Tc[i] / rc);
-    const bool cut = k.rho_cut > 0.0 && rc / k.rho0 < k.rho_cut;
+    const bool cut = kEos != 2 && k.rho_cut > 0.0 && rc / k.rho0 < k.rho_cut;
     double dp = k.c2;  // dp/drho
-    if constexpr (kEos) {
+    double gu = 0.0;   // Tillotson: cotangent of u
+    if constexpr (kEos == 1) {
         dp = k.K0 / k.rho0 * pow(rc / k.rho0, k.n_M - 1.0);
         grho += acc.gc * o.cc * (k.n_M - 1.0) / (2.0 * rc);  // dc/drho = c (n - 1) / (2 rho)
     }
-    const double slope = rc < k.rho0 ? keep * dp : dp;  // dp^/drho
+    if constexpr (kEos == 2) {
+        // c = sqrt(max(D, 0)), D = dp/drho + p / rho^2 dp/du; the jets carry D's partials
+        const Jet R{rc, 1.0, 0.0}, U{st.u ? st.u[a] : 0.0, 0.0, 1.0};
+        const PDerT<Jet> pd = tillotson_pd(k, R, U);
+        const Jet D = pd.dr + pd.p / (R * R) * pd.du;
+        dp = pd.dr.v;
+        if (D.v > 0.0) {
+            const double ic = 0.5 / sqrt(D.v);
+            grho += acc.gc * D.r * ic;
+            gu += acc.gc * D.u * ic;
+        }
+        const double slope_u = o.tens ? keep * pd.du.v : pd.du.v;  // dp^/du
+        gu += slope_u * (-(acc.gT[0] + acc.gT[1] + acc.gT[2]) * ir2);
+    }
+    // dp^/drho; below zero pressure the damaged slope (p < 0 iff rho < rho0 for the
+    // liquid and Murnaghan equations)
+    const bool tens = kEos == 2 ? o.tens : rc < k.rho0;
+    const double slope = tens ? keep * dp : dp;
     if (!cut) grho += slope * (-(acc.gT[0] + acc.gT[1] + acc.gT[2]) * ir2);
     double Stb[6], fb = 0.0;
 #pragma unroll
@@ -436,12 +463,13 @@ __device__ inline double adj_pre(const Consts &k, const AdjRec &ad, const AdjOwn
     put(out.rho, a, grho, A);
 #pragma unroll
     for (int i = 0; i < 6; ++i) put(out.s[i], a, gS[i], A);
+    if constexpr (kEos == 2) put(out.u, a, gu, A);
     return y0;
 }
 
 // pair stage + pre stage (see the file header); cell-sweep path, and with the
 // correction tensor the only path (also over a pair list)
-template <bool kCorr, bool kEos, bool kAS, bool kXC>
+template <bool kCorr, int kEos, bool kAS, bool kXC>
 __global__ __launch_bounds__(kBlock) void k_adj_pairs(GridDev g, int64_t n, Consts k,
                                                       const double *__restrict__ rec, StateDev st,
                                                       AdjRec ad, GradDev out) {
@@ -478,7 +506,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_pairs(GridDev g, int64_t n, Cons
             }
             adj_pair<kCorr, kEos, kAS, kXC>(k, o, d2, b0, b1, rb[2], rb[3], rb[4], rb[5], rb[6],
                                             qb[0], qb[1], qb[2], qb[3], qb[4], qb[5], qb[6], acc,
-                                            Mc, Mb, xo, xb);
+                                            Mc, Mb, xo, xb, kEos == 2 ? rb[7].y : 0.0);
         });
         if (kXC) {  // dx/dt = v + ...
             acc.gvx += xo[1];
@@ -493,7 +521,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_pairs(GridDev g, int64_t n, Cons
 
 // the same over the frozen pair list, one wavefront per block: the first seven
 // chunks of each partner's two records gathered cooperatively; Y0 sums per wavefront
-template <bool kEos, bool kAS>
+template <int kEos, bool kAS>
 __global__ __launch_bounds__(64) void k_adj_pairs_list(GridDev g, int64_t n, Consts k,
                                                        const double *__restrict__ rec,
                                                        StateDev st, AdjRec ad, GradDev out) {
@@ -591,7 +619,7 @@ CotDev cot_dev(const sph_deriv_cot *c) {
 
 GradDev grad_dev(const sph_fields *g, int accumulate) {
     return GradDev{g->x, g->y, g->z, g->vx, g->vy, g->vz, g->rho,
-                   {g->sxx, g->syy, g->szz, g->sxy, g->sxz, g->syz}, accumulate};
+                   {g->sxx, g->syy, g->szz, g->sxy, g->sxz, g->syz}, accumulate, g->u};
 }
 
 // Adjoint of one right-hand side on a carved workspace; gradients written or
@@ -642,10 +670,11 @@ int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_p
     }
     {
         TimedRegion t("adjoint_pairs", s);
-        const bool eos = k.eos == 1, as = k.eps_s > 0.0;
+        const bool as = k.eps_s > 0.0;
         const bool xc = cot.du || cot.dx[0] || cot.dx[1] || cot.dx[2];
         auto launch = [&](auto eos_t, auto as_t) {
-            constexpr bool E = decltype(eos_t)::value, A = decltype(as_t)::value;
+            constexpr int E = decltype(eos_t)::value;
+            constexpr bool A = decltype(as_t)::value;
             const dim3 gb(blocks_for(n)), tb(kBlock);
             if (xc && k.corr)
                 k_adj_pairs<true, E, A, true><<<gb, tb, 0, s>>>(g, n, k, rec, st, ad, grad);
@@ -653,25 +682,30 @@ int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_p
                 k_adj_pairs<false, E, A, true><<<gb, tb, 0, s>>>(g, n, k, rec, st, ad, grad);
             else if (k.corr)
                 k_adj_pairs<true, E, A, false><<<gb, tb, 0, s>>>(g, n, k, rec, st, ad, grad);
-            else if (g.pl_count)
-                k_adj_pairs_list<E, A><<<blocks_for(n, 64), 64, 0, s>>>(g, n, k, rec, st, ad, grad);
-            else
+            else if (E != 2 && g.pl_count) {
+                // Tillotson reads each partner's sound speed from its eighth record chunk,
+                // which the list kernel does not gather: it takes the cell sweep
+                if constexpr (E != 2)
+                    k_adj_pairs_list<E, A><<<blocks_for(n, 64), 64, 0, s>>>(g, n, k, rec, st, ad, grad);
+            } else
                 k_adj_pairs<false, E, A, false><<<gb, tb, 0, s>>>(g, n, k, rec, st, ad, grad);
         };
         using T = std::true_type;
         using F = std::false_type;
-        if (eos && as)
-            launch(T{}, T{});
-        else if (eos)
-            launch(T{}, F{});
-        else if (as)
-            launch(F{}, T{});
+        using E0 = std::integral_constant<int, 0>;
+        using E1 = std::integral_constant<int, 1>;
+        using E2 = std::integral_constant<int, 2>;
+        if (k.eos == 2)
+            as ? launch(E2{}, T{}) : launch(E2{}, F{});
+        else if (k.eos == 1)
+            as ? launch(E1{}, T{}) : launch(E1{}, F{});
         else
-            launch(F{}, F{});
+            as ? launch(E0{}, T{}) : launch(E0{}, F{});
         SPH_LAUNCHED();
     }
     if (acc_parts) return SPH_OK;  // the caller reduces its accumulators
-    const bool per_wave = g.pl_count && !k.corr && !(cot.du || cot.dx[0] || cot.dx[1] || cot.dx[2]);
+    const bool per_wave = g.pl_count && !k.corr && k.eos != 2 &&
+                          !(cot.du || cot.dx[0] || cot.dx[1] || cot.dx[2]);
     const int64_t m_y0 = per_wave ? blocks_for(n, 64) : blocks_for(n);
     return reduce_params_launch(ad.part_mu, blocks_for(n), ad.part_y0, m_y0, dparams,
                                 accumulate_params, s);
@@ -701,8 +735,8 @@ extern "C" int sph_rhs_adjoint(const sph_grid *grid, const sph_state *state,
         return rc;
     if (!cot) return fail(SPH_ERR_INVALID_ARG, "cotangent struct is NULL");
     if (!dparams || !ws) return fail(SPH_ERR_INVALID_ARG, "null pointer");
-    if (params->eos == 2.0)
-        return fail(SPH_ERR_NOT_IMPLEMENTED, "adjoint with the Tillotson equation");
+    if (params->eos == 2.0 && !grad->u)
+        return fail(SPH_ERR_INVALID_ARG, "the Tillotson adjoint writes the gradient of u: grad->u is NULL");
     const size_t need = adjoint_ws_bytes(grid->n);
     if (ws_bytes < need) return fail(SPH_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
     hipStream_t s = (hipStream_t)stream;

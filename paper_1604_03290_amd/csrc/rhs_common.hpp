@@ -231,33 +231,89 @@ __device__ inline double pressure(const Consts &k, double rho) {
 // and u.  Compressed form: p = (a + b / w) rho u + A chi + B chi^2, w = 1 + u /
 // (E0 eta^2); expanded form: p = a rho u + (b rho u / w + A chi e^{-beta z})
 // e^{-alpha z^2}, z = rho0 / rho - 1.
-struct PDer {
-    double p, dr, du;
+// First-order jet in two variables (value and partials along rho and u): evaluating
+// the Tillotson forms, which already carry dp/drho and dp/du, on jets gives their
+// second partials too, which the adjoint of the sound speed needs.
+struct Jet {
+    double v, r, u;
 };
+__device__ inline Jet operator+(Jet a, Jet b) { return {a.v + b.v, a.r + b.r, a.u + b.u}; }
+__device__ inline Jet operator-(Jet a, Jet b) { return {a.v - b.v, a.r - b.r, a.u - b.u}; }
+__device__ inline Jet operator-(Jet a) { return {-a.v, -a.r, -a.u}; }
+__device__ inline Jet operator*(Jet a, Jet b) {
+    return {a.v * b.v, a.r * b.v + a.v * b.r, a.u * b.v + a.v * b.u};
+}
+__device__ inline Jet operator/(Jet a, Jet b) {
+    const double i = 1.0 / b.v, q = a.v * i;
+    return {q, (a.r - q * b.r) * i, (a.u - q * b.u) * i};
+}
+__device__ inline Jet operator+(double a, Jet b) { return {a + b.v, b.r, b.u}; }
+__device__ inline Jet operator+(Jet a, double b) { return {a.v + b, a.r, a.u}; }
+__device__ inline Jet operator-(double a, Jet b) { return {a - b.v, -b.r, -b.u}; }
+__device__ inline Jet operator-(Jet a, double b) { return {a.v - b, a.r, a.u}; }
+__device__ inline Jet operator*(double a, Jet b) { return {a * b.v, a * b.r, a * b.u}; }
+__device__ inline Jet operator*(Jet a, double b) { return {a.v * b, a.r * b, a.u * b}; }
+__device__ inline Jet operator/(Jet a, double b) { return a * (1.0 / b); }
+__device__ inline Jet operator/(double a, Jet b) {
+    const double i = 1.0 / b.v, q = a * i;
+    return {q, -q * b.r * i, -q * b.u * i};
+}
+__device__ inline double ex(double x) { return exp(x); }
+__device__ inline Jet ex(Jet x) {
+    const double e = exp(x.v);
+    return {e, e * x.r, e * x.u};
+}
+__device__ inline double val(double x) { return x; }
+__device__ inline double val(Jet x) { return x.v; }
 
-__device__ inline PDer tillotson_form(const Consts &k, double rho, double u, bool expanded) {
-    const double eta = rho / k.rho0, chi = eta - 1.0;
-    const double ie2 = 1.0 / (k.E0T * eta * eta);
-    const double w = 1.0 + u * ie2;
-    const double iw = 1.0 / w;
-    const double w_r = -2.0 * u * ie2 / rho;  // dw/drho
-    const double g = k.bT * rho * u * iw;     // b rho u / w
-    const double g_r = k.bT * u * iw - g * iw * w_r;
-    const double g_u = k.bT * rho * iw - g * iw * ie2;
-    PDer d;
+template <class T>
+struct PDerT {
+    T p, dr, du;
+};
+using PDer = PDerT<double>;
+
+// Tillotson pressure (section 2.5.3) of the compressed form, or of the expanded
+// one, with its partial derivatives along rho and u
+template <class T>
+__device__ inline PDerT<T> tillotson_form(const Consts &k, T rho, T u, bool expanded) {
+    const T eta = rho / k.rho0, chi = eta - 1.0;
+    const T ie2 = 1.0 / (k.E0T * eta * eta);
+    const T w = 1.0 + u * ie2;
+    const T iw = 1.0 / w;
+    const T w_r = -2.0 * u * ie2 / rho;  // dw/drho
+    const T g = k.bT * rho * u * iw;     // b rho u / w
+    const T g_r = k.bT * u * iw - g * iw * w_r;
+    const T g_u = k.bT * rho * iw - g * iw * ie2;
+    PDerT<T> d;
     if (!expanded) {
         d.p = k.aT * rho * u + g + k.AT * chi + k.BT * chi * chi;
         d.dr = k.aT * u + g_r + (k.AT + 2.0 * k.BT * chi) / k.rho0;
         d.du = k.aT * rho + g_u;
         return d;
     }
-    const double z = k.rho0 / rho - 1.0, z_r = -k.rho0 / (rho * rho);
-    const double eb = exp(-k.beT * z), ea = exp(-k.alT * z * z);
-    const double q = g + k.AT * chi * eb;
-    const double q_r = g_r + k.AT * eb / k.rho0 - k.AT * chi * eb * k.beT * z_r;
+    const T z = k.rho0 / rho - 1.0, z_r = -k.rho0 / (rho * rho);
+    const T eb = ex(-k.beT * z), ea = ex(-k.alT * z * z);
+    const T q = g + k.AT * chi * eb;
+    const T q_r = g_r + k.AT * eb / k.rho0 - k.AT * chi * eb * k.beT * z_r;
     d.p = k.aT * rho * u + q * ea;
     d.dr = k.aT * u + q_r * ea - q * ea * 2.0 * k.alT * z * z_r;
     d.du = k.aT * rho + g_u * ea;
+    return d;
+}
+
+// Tillotson pressure and partials over its regions: the compressed form for
+// rho >= rho0 or u <= E_iv, the expanded form for u >= E_cv, the two joined linearly
+// in u between
+template <class T>
+__device__ inline PDerT<T> tillotson_pd(const Consts &k, T rho, T u) {
+    if (val(rho) >= k.rho0 || val(u) <= k.Eiv) return tillotson_form(k, rho, u, false);
+    if (val(u) >= k.Ecv) return tillotson_form(k, rho, u, true);
+    const PDerT<T> a = tillotson_form(k, rho, u, false), b = tillotson_form(k, rho, u, true);
+    const T t = (u - k.Eiv) / (k.Ecv - k.Eiv);
+    PDerT<T> d;
+    d.p = (1.0 - t) * a.p + t * b.p;
+    d.dr = (1.0 - t) * a.dr + t * b.dr;
+    d.du = (1.0 - t) * a.du + t * b.du + (b.p - a.p) / (k.Ecv - k.Eiv);
     return d;
 }
 
@@ -272,18 +328,7 @@ __device__ inline void eos_pc(const Consts &k, double rho, double u, double &p, 
         if (k.rho_cut > 0.0 && eta < k.rho_cut) p = 0.0;
         cs = sqrt(k.K0 / k.rho0 * en1);
     } else if (k.eos == 2) {
-        PDer d;
-        if (rho >= k.rho0 || u <= k.Eiv) {
-            d = tillotson_form(k, rho, u, false);
-        } else if (u >= k.Ecv) {
-            d = tillotson_form(k, rho, u, true);
-        } else {
-            const PDer a = tillotson_form(k, rho, u, false), b = tillotson_form(k, rho, u, true);
-            const double t = (u - k.Eiv) / (k.Ecv - k.Eiv);
-            d.p = (1.0 - t) * a.p + t * b.p;
-            d.dr = (1.0 - t) * a.dr + t * b.dr;
-            d.du = (1.0 - t) * a.du + t * b.du + (b.p - a.p) / (k.Ecv - k.Eiv);
-        }
+        const PDer d = tillotson_pd(k, rho, u);
         p = d.p;
         cs = sqrt(fmax(d.dr + d.p / (rho * rho) * d.du, 0.0));
     } else {
@@ -731,6 +776,7 @@ struct CotDev {
 struct GradDev {
     double *x, *y, *z, *vx, *vy, *vz, *rho, *s[6];
     int accumulate;
+    double *u;  // gradient of u (Tillotson), else null
 };
 
 // adjoint.hip

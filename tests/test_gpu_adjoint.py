@@ -2,6 +2,7 @@
 oracle, the leapfrog and its reverse sweep against the oracle's trajectory and
 gradients, and, at the full 64,000-particle / 20-step size, central finite
 differences and the momentum closed form (properties that hold at any size)."""
+import ctypes as C
 import numpy as np
 import pytest
 import torch
@@ -426,14 +427,63 @@ def test_rhs_adjoint_murnaghan_matches_oracle(variant):
     assert abs(float(got["mu"]) - ref["mu"]) <= 1e-11 * abs(ref["mu"])
 
 
-def test_adjoint_refuses_tillotson():
+@pytest.mark.parametrize("variant", ["cells", "list", "corrected", "damage_as", "extra"])
+def test_rhs_adjoint_tillotson_matches_oracle(variant):
+    # the Tillotson equation (section 2.5.3) over its three regions: gradients with
+    # respect to rho and u through the pressure and through the sound speed (second
+    # derivatives of p), against the oracle's reverse-mode product
+    w = small("cube8_visc")
+    w.params.update(eos=2.0, rho_cut=0.0, correction=1.0 if variant == "corrected" else 0.0)
+    rng = np.random.default_rng(23)
+    Eiv, Ecv = w.params["E_iv"], w.params["E_cv"]
+    w.rho = w.params["rho0"] * rng.uniform(0.97, 1.03, w.n)
+    w.u = rng.choice([0.5 * Eiv, 0.5 * (Eiv + Ecv), 1.3 * Ecv], w.n) * rng.uniform(0.95, 1.05, w.n)
+    if variant == "damage_as":
+        w.d = rng.uniform(0.0, 1.0, w.n)
+        w.params.update(eps_s=0.2, n_s=4.0)
+    if variant == "extra":
+        w.params.update(xsph=0.5)
+    ref_out = native.rhs_workload(w, want_L=False, want_extra=variant == "extra")
+    keys = ("acc", "drho", "dS", "rho_sum") + (("du",) if variant == "extra" else ())
+    cot = {k: rng.normal(size=ref_out[k].shape) / np.abs(ref_out[k]).max() for k in keys}
+    if variant == "extra":
+        cot["xv"] = rng.normal(size=(3, w.n)) / np.abs(ref_out["xv"] - w.vel).max()
+    ref = AD.rhs_vjp(w, cot)
+    st = P.ParticleState.from_arrays(w.pos, w.vel, w.rho, w.S, w.m, u=w.u, d=getattr(w, "d", None))
+    g = P.sph_build_cells(st.pos, w.h, skin=0.05 * w.dx, pairs=variant != "cells")
+    got = P.sph_rhs_adjoint(g, st, w.params, {k: torch.as_tensor(v).cuda() for k, v in cot.items()})
+    assert P.workspace_status(got["_ws"]) == 0
+    for k in ("pos", "vel", "rho", "S", "u"):
+        assert rel(got[k].cpu().numpy(), ref[k]) < 1e-11, k
+    assert abs(float(got["mu"]) - ref["mu"]) <= 1e-11 * abs(ref["mu"])
+    if variant == "cells":
+        # the u gradient is not the pressure's alone: the sound speeds in Pi add to it
+        assert np.abs(ref["u"]).max() > 0.0
+        w0 = w.copy()
+        w0.params.update(alpha=0.0, beta=0.0)
+        ref0 = AD.rhs_vjp(w0, cot)
+        assert rel(ref0["u"], ref["u"]) > 1e-6
+
+
+def test_tillotson_adjoint_requires_the_u_gradient():
     w = small("cube10")
     w.params.update(eos=2.0)
     st = gpu_state(w)
     g = P.sph_build_cells(st.pos, w.h)
+    n = w.n
+    out = {k: torch.empty(*sh, dtype=torch.float64).cuda() for k, sh in
+           (("pos", (3, n)), ("vel", (3, n)), ("rho", (n,)), ("S", (6, n)))}
+    fs = P.api.fields_struct(out["pos"], out["vel"], out["rho"], out["S"])
+    acc = torch.ones(3, n, dtype=torch.float64).cuda()
+    dc = L.DerivCot(acc[0].data_ptr(), acc[1].data_ptr(), acc[2].data_ptr())
+    ws = P.workspace(L.SPH_OP_ADJOINT, n, 0)
+    dp = torch.empty(2, dtype=torch.float64).cuda()
+    cs = st.c_state()
     with pytest.raises(L.SphError) as e:
-        P.sph_rhs_adjoint(g, st, w.params, {"acc": torch.ones(3, w.n, dtype=torch.float64).cuda()})
-    assert e.value.code == L.SPH_ERR_NOT_IMPLEMENTED
+        L.check(L.lib().sph_rhs_adjoint(C.byref(g.c), C.byref(cs), C.byref(P.api.params_struct(w.params)),
+                                        C.byref(dc), C.byref(fs), P.api._ptr(dp), P.api._ptr(ws),
+                                        ws.numel(), P.api._stream()))
+    assert e.value.code == L.SPH_ERR_INVALID_ARG
 
 
 @pytest.mark.parametrize("variant", ["cells", "list", "corrected", "murnaghan_damage", "n2.5"])
