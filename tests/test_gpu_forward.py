@@ -504,6 +504,7 @@ def test_rhs_damage_matches_oracle(precision, path):
     assert not bad, bad
     check_damage_rates(got, w)
     intact = w.copy()
+    intact.d = None
     plain = native.rhs_workload(intact)  # the damage acts on this state
     assert np.abs(plain["acc"] - ref["acc"]).max() > 1e-3 * np.abs(ref["acc"]).max()
 
