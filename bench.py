@@ -71,8 +71,8 @@ def load_workload(name):
 # 1 GiB calibration copy.  They hold only for the kernel sources they were taken on: the
 # hash of those files is compared at run time and the figure is dropped on a mismatch.
 TRAFFIC = {"kernel": "k_adj_pairs_list", "workload": "two_spheres_262144",
-           "sources_sha256": "0bf3a74460f0f8c1939cec329daf3ba3e3f8e1be5806d34c79d383729fd551b3",
-           "fetch_bytes": 805.7e6, "write_bytes": 30.5e6,
+           "sources_sha256": "eff156b03f60dad7eaeba77eb4b3ca51b75fb7840460746cf0b865578d347722",
+           "fetch_bytes": 803.5e6, "write_bytes": 30.4e6,
            "profile": "profiles/hbm_traffic_two_spheres_262144.md"}
 
 KERNEL_SOURCES = {"k_adj_pairs_list": ("adjoint.hip", "adjoint.hpp", "rhs_common.hpp", "common.hpp"),
@@ -371,6 +371,9 @@ def main():
     cg = {k: torch.randn_like(outs["fp64"][k]) for k in fields}
     ms = median_ms(lambda: P.sph_rhs_adjoint(g, st, w.params, cg, ws=ws_adj), args.form_reps, torch)
     forms["adjoint_fp64"] = {"ms": ms, "pairs_per_s": nnz0 / (ms * 1e-3)}
+    # the adjoint with the Tillotson equation (gradient of u too; cell-sweep pair kernel)
+    ms = median_ms(lambda: P.sph_rhs_adjoint(g, su, pt, cg, ws=ws_adj), args.form_reps, torch)
+    forms["adjoint_fp64_tillotson"] = {"ms": ms, "pairs_per_s": nnz0 / (ms * 1e-3)}
 
     # dominant kernel of the step
     dom = max(kern, key=lambda k: kern[k][0])

@@ -376,20 +376,22 @@ class SphRhs(torch.autograd.Function):
     """Differentiable FP64 right-hand side: forward calls sph_rhs, backward calls
     sph_rhs_adjoint (the exact vector-Jacobian product on the same partner set).
 
-    apply(pos, vel, rho, S, mu, Y0, grid, params, m, d=None, extra=False)
+    apply(pos, vel, rho, S, mu, Y0, grid, params, m, d=None, extra=False, u=None)
     -> (acc, drho, dS, rho_sum), and with ``extra`` also (du, xv), the energy rate and
-    dx/dt with XSPH.  pos, vel (3, n), rho (n), S (6, n), m (n) are device tensors in
+    dx/dt with XSPH.  ``u`` (n), the specific internal energy read by the Tillotson
+    equation, is differentiable too (its gradient comes from the adjoint).  pos, vel (3, n), rho (n), S (6, n), m (n) are device tensors in
     user order and mu, Y0 scalar tensors (their values replace params' mu and Y0; their
     gradients come from the adjoint).  The masses, a damage field d (n) and the other
     constants are held fixed."""
 
     @staticmethod
-    def forward(ctx, pos, vel, rho, S, mu, Y0, grid, params, m, d=None, extra=False):
+    def forward(ctx, pos, vel, rho, S, mu, Y0, grid, params, m, d=None, extra=False, u=None):
         p = dict(params) if isinstance(params, dict) else dict(zip(PARAM_ORDER, params))
         p["mu"] = float(mu)
         p["Y0"] = float(Y0)
         st = ParticleState(pos.detach().contiguous(), vel.detach().contiguous(),
                            rho.detach().contiguous(), S.detach().contiguous(), m.contiguous(),
+                           u=None if u is None else u.detach().contiguous(),
                            d=None if d is None else d.detach().contiguous())
         out = sph_rhs(grid, st, p, "fp64", extra=extra)
         ctx.grid, ctx.params, ctx.state, ctx.extra = grid, p, st, extra
@@ -404,7 +406,8 @@ class SphRhs(torch.autograd.Function):
         g = sph_rhs_adjoint(ctx.grid, ctx.state, ctx.params, cot)
         gmu = g["mu"].to(ctx.mu_like.device, ctx.mu_like.dtype).reshape(ctx.mu_like.shape)
         gY0 = g["Y0"].to(ctx.Y0_like.device, ctx.Y0_like.dtype).reshape(ctx.Y0_like.shape)
-        return g["pos"], g["vel"], g["rho"], g["S"], gmu, gY0, None, None, None, None, None
+        return (g["pos"], g["vel"], g["rho"], g["S"], gmu, gY0, None, None, None, None, None,
+                g.get("u"))
 
 
 def _fields(n, dev):

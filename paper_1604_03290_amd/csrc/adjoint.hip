@@ -520,13 +520,17 @@ __global__ __launch_bounds__(kBlock) void k_adj_pairs(GridDev g, int64_t n, Cons
 }
 
 // the same over the frozen pair list, one wavefront per block: the first seven
-// chunks of each partner's two records gathered cooperatively; Y0 sums per wavefront
+// chunks of each partner's two records gathered cooperatively (with Tillotson all
+// eight of the forward record, whose last holds the partner's signed sound speed);
+// Y0 sums per wavefront
 template <int kEos, bool kAS>
 __global__ __launch_bounds__(64) void k_adj_pairs_list(GridDev g, int64_t n, Consts k,
                                                        const double *__restrict__ rec,
                                                        StateDev st, AdjRec ad, GradDev out) {
-    __shared__ double2 bf[64 * 7];
+    constexpr int kF = kEos == 2 ? 8 : 7;  // forward-record chunks gathered
+    __shared__ double2 bf[64 * kF];
     __shared__ double2 ba[64 * 7];
+    auto fchunk = [&](int c) { return kF == 8 ? dma8_chunk(bf, c) : dma_chunk<7>(bf, c); };
     const int64_t w = xcd_block(gridDim.x);
     const int64_t w0 = w * 64;
     const int64_t s = w0 + threadIdx.x;
@@ -544,20 +548,24 @@ __global__ __launch_bounds__(64) void k_adj_pairs_list(GridDev g, int64_t n, Con
         int e0 = steps > 0 ? row[0] : 0;
         for (int j = 0; j < steps; ++j) {
             {
-                gather_dma<7>(rf, kRec * 8, e0, bf);
+                if constexpr (kF == 8)
+                    gather_dma8(rf, kRec * 8, e0, bf);
+                else
+                    gather_dma<7>(rf, kRec * 8, e0, bf);
                 gather_dma<7>(ra, kAdj * 8, e0, ba);
                 if (j + 1 < steps) e0 = row[(int64_t)(j + 1) << 6];
             }
             wave_sync();
             if (j < cnt) {
-                const double2 b0 = dma_chunk<7>(bf, 0), b1 = dma_chunk<7>(bf, 1);
+                const double2 b0 = fchunk(0), b1 = fchunk(1);
                 const double d2 = dist2_exact(o.xc, o.yc, o.zc, b0.x, b0.y, b1.x);
                 if (d2 < k.h2)
-                    adj_pair<false, kEos, kAS>(k, o, d2, b0, b1, dma_chunk<7>(bf, 2), dma_chunk<7>(bf, 3),
-                             dma_chunk<7>(bf, 4), dma_chunk<7>(bf, 5), dma_chunk<7>(bf, 6),
+                    adj_pair<false, kEos, kAS>(k, o, d2, b0, b1, fchunk(2), fchunk(3),
+                             fchunk(4), fchunk(5), fchunk(6),
                              dma_chunk<7>(ba, 0), dma_chunk<7>(ba, 1), dma_chunk<7>(ba, 2),
                              dma_chunk<7>(ba, 3), dma_chunk<7>(ba, 4), dma_chunk<7>(ba, 5),
-                             dma_chunk<7>(ba, 6), acc);
+                             dma_chunk<7>(ba, 6), acc, nullptr, nullptr, nullptr, nullptr,
+                             kF == 8 ? fchunk(7).y : 0.0);
             }
             wave_sync();
         }
@@ -682,12 +690,9 @@ int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_p
                 k_adj_pairs<false, E, A, true><<<gb, tb, 0, s>>>(g, n, k, rec, st, ad, grad);
             else if (k.corr)
                 k_adj_pairs<true, E, A, false><<<gb, tb, 0, s>>>(g, n, k, rec, st, ad, grad);
-            else if (E != 2 && g.pl_count) {
-                // Tillotson reads each partner's sound speed from its eighth record chunk,
-                // which the list kernel does not gather: it takes the cell sweep
-                if constexpr (E != 2)
-                    k_adj_pairs_list<E, A><<<blocks_for(n, 64), 64, 0, s>>>(g, n, k, rec, st, ad, grad);
-            } else
+            else if (g.pl_count)
+                k_adj_pairs_list<E, A><<<blocks_for(n, 64), 64, 0, s>>>(g, n, k, rec, st, ad, grad);
+            else
                 k_adj_pairs<false, E, A, false><<<gb, tb, 0, s>>>(g, n, k, rec, st, ad, grad);
         };
         using T = std::true_type;
@@ -704,8 +709,7 @@ int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_p
         SPH_LAUNCHED();
     }
     if (acc_parts) return SPH_OK;  // the caller reduces its accumulators
-    const bool per_wave = g.pl_count && !k.corr && k.eos != 2 &&
-                          !(cot.du || cot.dx[0] || cot.dx[1] || cot.dx[2]);
+    const bool per_wave = g.pl_count && !k.corr && !(cot.du || cot.dx[0] || cot.dx[1] || cot.dx[2]);
     const int64_t m_y0 = per_wave ? blocks_for(n, 64) : blocks_for(n);
     return reduce_params_launch(ad.part_mu, blocks_for(n), ad.part_y0, m_y0, dparams,
                                 accumulate_params, s);

@@ -617,3 +617,28 @@ def test_autograd_function_with_extra_outputs_and_damage():
     for k, t in zip(("pos", "vel", "rho", "S"), leaves):
         assert rel(t.grad.cpu().numpy(), ref[k]) < 1e-11, k
     assert abs(float(mu.grad) - ref["mu"]) <= 1e-11 * abs(ref["mu"])
+
+
+def test_autograd_function_tillotson_gradient_of_u():
+    w = small("cube8_visc")
+    w.params.update(eos=2.0, rho_cut=0.0)
+    rng = np.random.default_rng(43)
+    Eiv, Ecv = w.params["E_iv"], w.params["E_cv"]
+    w.rho = w.params["rho0"] * rng.uniform(0.97, 1.03, w.n)
+    w.u = rng.choice([0.5 * Eiv, 0.5 * (Eiv + Ecv), 1.3 * Ecv], w.n) * rng.uniform(0.95, 1.05, w.n)
+    ref_out = native.rhs_workload(w, want_L=False)
+    keys = ("acc", "drho", "dS", "rho_sum")
+    cot = {k: rng.normal(size=ref_out[k].shape) / np.abs(ref_out[k]).max() for k in keys}
+    ref = AD.rhs_vjp(w, cot)
+    st = P.ParticleState.from_arrays(w.pos, w.vel, w.rho, w.S, w.m, u=w.u)
+    g = P.sph_build_cells(st.pos, w.h, skin=0.05 * w.dx, pairs=True)
+    leaves = [t.clone().requires_grad_(True) for t in (st.pos, st.vel, st.rho, st.S)]
+    u = st.u.clone().requires_grad_(True)
+    mu = torch.tensor(w.params["mu"], dtype=torch.float64, device="cuda")
+    Y0 = torch.tensor(w.params["Y0"], dtype=torch.float64, device="cuda")
+    outs = P.SphRhs.apply(*leaves, mu, Y0, g, w.params, st.m, None, False, u)
+    loss = sum((o * torch.as_tensor(cot[k]).cuda()).sum() for k, o in zip(keys, outs))
+    loss.backward()
+    for k, t in zip(("pos", "vel", "rho", "S"), leaves):
+        assert rel(t.grad.cpu().numpy(), ref[k]) < 1e-11, k
+    assert rel(u.grad.cpu().numpy(), ref["u"]) < 1e-11
