@@ -522,8 +522,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_pairs(GridDev g, int64_t n, Cons
 // the same over the frozen pair list, one wavefront per block: the first seven
 // chunks of each partner's two records gathered cooperatively (with Tillotson all
 // eight of the forward record, whose last holds the partner's signed sound speed);
-// Y0 sums per wavefront
-template <int kEos, bool kAS>
+// Y0 sums per wavefront.  With the du and dx/dt cotangents each lane loads its own
+// partner's four (one list entry per lane and step)
+template <int kEos, bool kAS, bool kXC = false>
 __global__ __launch_bounds__(64) void k_adj_pairs_list(GridDev g, int64_t n, Consts k,
                                                        const double *__restrict__ rec,
                                                        StateDev st, AdjRec ad, GradDev out) {
@@ -542,11 +543,17 @@ __global__ __launch_bounds__(64) void k_adj_pairs_list(GridDev g, int64_t n, Con
         const int cnt = act ? g.pl_count[s] : 0;
         const AdjOwn o = adj_own(rec, ad, act ? s : w0);
         AdjAcc acc;
+        double xo[4] = {0, 0, 0, 0};
+        if constexpr (kXC) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) xo[i] = ad.ext[i][act ? s : w0];
+        }
         const char *rf = reinterpret_cast<const char *>(rec);
         const char *ra = reinterpret_cast<const char *>(ad.arec);
         const int32_t *row = g.pl_slot + base + __lane_id();
         int e0 = steps > 0 ? row[0] : 0;
         for (int j = 0; j < steps; ++j) {
+            const int cur = e0;  // this lane's partner slot of step j
             {
                 if constexpr (kF == 8)
                     gather_dma8(rf, kRec * 8, e0, bf);
@@ -559,15 +566,25 @@ __global__ __launch_bounds__(64) void k_adj_pairs_list(GridDev g, int64_t n, Con
             if (j < cnt) {
                 const double2 b0 = fchunk(0), b1 = fchunk(1);
                 const double d2 = dist2_exact(o.xc, o.yc, o.zc, b0.x, b0.y, b1.x);
+                double xb[4] = {0, 0, 0, 0};
+                if constexpr (kXC) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) xb[i] = ad.ext[i][cur];
+                }
                 if (d2 < k.h2)
-                    adj_pair<false, kEos, kAS>(k, o, d2, b0, b1, fchunk(2), fchunk(3),
+                    adj_pair<false, kEos, kAS, kXC>(k, o, d2, b0, b1, fchunk(2), fchunk(3),
                              fchunk(4), fchunk(5), fchunk(6),
                              dma_chunk<7>(ba, 0), dma_chunk<7>(ba, 1), dma_chunk<7>(ba, 2),
                              dma_chunk<7>(ba, 3), dma_chunk<7>(ba, 4), dma_chunk<7>(ba, 5),
-                             dma_chunk<7>(ba, 6), acc, nullptr, nullptr, nullptr, nullptr,
+                             dma_chunk<7>(ba, 6), acc, nullptr, nullptr, xo, xb,
                              kF == 8 ? fchunk(7).y : 0.0);
             }
             wave_sync();
+        }
+        if constexpr (kXC) {  // dx/dt = v + ...
+            acc.gvx += xo[1];
+            acc.gvy += xo[2];
+            acc.gvz += xo[3];
         }
         if (act) y0_part = adj_pre<kEos>(k, ad, o, acc, s, io_index(g, s), st, out);
     }
@@ -686,6 +703,8 @@ int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_p
             const dim3 gb(blocks_for(n)), tb(kBlock);
             if (xc && k.corr)
                 k_adj_pairs<true, E, A, true><<<gb, tb, 0, s>>>(g, n, k, rec, st, ad, grad);
+            else if (xc && g.pl_count)
+                k_adj_pairs_list<E, A, true><<<blocks_for(n, 64), 64, 0, s>>>(g, n, k, rec, st, ad, grad);
             else if (xc)
                 k_adj_pairs<false, E, A, true><<<gb, tb, 0, s>>>(g, n, k, rec, st, ad, grad);
             else if (k.corr)
@@ -709,7 +728,7 @@ int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_p
         SPH_LAUNCHED();
     }
     if (acc_parts) return SPH_OK;  // the caller reduces its accumulators
-    const bool per_wave = g.pl_count && !k.corr && !(cot.du || cot.dx[0] || cot.dx[1] || cot.dx[2]);
+    const bool per_wave = g.pl_count && !k.corr;
     const int64_t m_y0 = per_wave ? blocks_for(n, 64) : blocks_for(n);
     return reduce_params_launch(ad.part_mu, blocks_for(n), ad.part_y0, m_y0, dparams,
                                 accumulate_params, s);
