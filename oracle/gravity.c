@@ -28,10 +28,14 @@
  *     partner at distance 0 adds nothing.
  *   - walk: from the root, in octant order; an inner node whose edge s and
  *     distance r from the particle to its centre of mass satisfy s / r < theta
+ *     (the criterion as section 3.3 prints it, r = sqrt of the squared distance)
  *     acts as one pseudo-particle, else its children are visited; a leaf other
  *     than the particle itself always acts directly.  theta = 0 is the direct sum.
- *     The test is evaluated on squares, s^2 < theta^2 r^2 (equivalent for r > 0,
- *     and false at r = 0 as s / 0 < theta is), which needs no square root.
+ *   - the squared form s^2 < theta^2 r^2 is the same criterion in real
+ *     arithmetic; rounded, the two can differ when s / r lies within a few ulps of
+ *     theta.  Each target's walk also evaluates the squared form at every node it
+ *     tests and reports (tie) whether the two ever disagreed, so a checker can set
+ *     such walks aside instead of requiring one rounding of the criterion.
  * Arithmetic in FP64 without contraction, each sum in the order stated.  */
 #include <math.h>
 #include <stdint.h>
@@ -203,6 +207,7 @@ static void gr_free(gr_tree *t)
 typedef struct {
     double ax, ay, az;
     int64_t count;
+    int tie;  /* the printed and the squared opening test disagreed at some node */
 } gr_acc;
 
 static void gr_term(gr_acc *A, double G, double eps, double mp, double dx, double dy, double dz)
@@ -226,7 +231,9 @@ static void gr_walk(const gr_tree *t, int nd, int64_t a, double G, double theta,
     const double dx = k->cx - xa, dy = k->cy - ya, dz = k->cz - za;
     const double r2 = dx * dx + dy * dy + dz * dz;
     const double s = ldexp(t->s0, -k->depth);
-    if (s * s < theta * theta * r2) {
+    const int open_far = s / sqrt(r2) < theta;  /* section 3.3: s / r < theta */
+    if (open_far != (s * s < theta * theta * r2)) A->tie = 1;
+    if (open_far) {
         gr_term(A, G, eps, k->m, dx, dy, dz);
         return;
     }
@@ -249,10 +256,12 @@ static void gr_walk(const gr_tree *t, int nd, int64_t a, double G, double theta,
 
 /* Gravitational acceleration of the targets (targets[0..nt) or, when targets is
  * NULL, every particle, nt = n): pos (3, n), m (n) > 0; acc (3, nt); count (nt,
- * nullable): pseudo-particles and leaves each target took a term from.  Returns the
- * number of inner nodes. */
+ * nullable): pseudo-particles and leaves each target took a term from; tie (nt,
+ * nullable): 1 where the target's walk met a node at which s / r < theta and
+ * s^2 < theta^2 r^2 decide differently.  Returns the number of inner nodes. */
 int64_t orc_gravity(int64_t n, const double *pos, const double *m, double G, double theta,
-                    double eps, const int64_t *targets, int64_t nt, double *acc, int64_t *count)
+                    double eps, const int64_t *targets, int64_t nt, double *acc, int64_t *count,
+                    int32_t *tie)
 {
     gr_tree t;
     gr_build(&t, n, pos, m);
@@ -260,12 +269,13 @@ int64_t orc_gravity(int64_t n, const double *pos, const double *m, double G, dou
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t j = 0; j < nt; ++j) {
         const int64_t a = targets ? targets[j] : j;
-        gr_acc A = {0.0, 0.0, 0.0, 0};
+        gr_acc A = {0.0, 0.0, 0.0, 0, 0};
         gr_walk(&t, 0, a, G, theta, eps, &A);
         acc[j] = A.ax;
         acc[nt + j] = A.ay;
         acc[2 * nt + j] = A.az;
         if (count) count[j] = A.count;
+        if (tie) tie[j] = A.tie;
     }
     const int64_t nn = n > 0 ? t.nnode : 0;
     gr_free(&t);

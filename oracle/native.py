@@ -43,7 +43,7 @@ def lib():
                                _pi64, _pi32, _pd, _pd, _pd, _pd, _pd, _pd, _pd]
         L.orc_prepass2.argtypes = [_i64, _pd, _pd, _pd, _pd, _pd, _pd, _pd, _pd, _pd]
         L.orc_eos.argtypes = [_i64, _pd, _pd, _pd, _pd, _pd]
-        L.orc_gravity.argtypes = [_i64, _pd, _pd, _d, _d, _d, _pi64, _i64, _pd, _pi64]
+        L.orc_gravity.argtypes = [_i64, _pd, _pd, _d, _d, _d, _pi64, _i64, _pd, _pi64, _pi32]
         L.orc_gravity.restype = _i64
         L.orc_gravity_tree.argtypes = [_i64, _pd, _pd, _i64, _pi32, _pi64, _pd, _pd]
         L.orc_gravity_tree.restype = _i64
@@ -205,9 +205,11 @@ def rhs_workload(w, targets=None, csr=None, want_L: bool = True, want_extra: boo
 
 
 def gravity(pos, m, G: float, theta: float, eps: float = 0.0, targets=None):
-    """Barnes-Hut monopole gravity (section 3.3): dict acc (3, nt), count (nt) and
-    nodes (the number of inner nodes) for ``targets`` (all particles when None); the
-    tree always holds every particle."""
+    """Barnes-Hut monopole gravity (section 3.3): dict acc (3, nt), count (nt),
+    tie (nt, bool: the walk met a node where the printed test s / r < theta and its
+    squared form s^2 < theta^2 r^2 round to different decisions) and nodes (the
+    number of inner nodes) for ``targets`` (all particles when None); the tree always
+    holds every particle."""
     pos, ppos = _f64(pos)
     m, pm = _f64(m)
     n = m.shape[0]
@@ -218,9 +220,10 @@ def gravity(pos, m, G: float, theta: float, eps: float = 0.0, targets=None):
         nt = tg.shape[0]
     acc = np.zeros((3, nt))
     cnt = np.zeros(nt, dtype=np.int64)
+    tie = np.zeros(nt, dtype=np.int32)
     nn = lib().orc_gravity(n, ppos, pm, G, theta, eps, ptg, nt, acc.ctypes.data_as(_pd),
-                           cnt.ctypes.data_as(_pi64))
-    return dict(acc=acc, count=cnt, nodes=int(nn))
+                           cnt.ctypes.data_as(_pi64), tie.ctypes.data_as(_pi32))
+    return dict(acc=acc, count=cnt, tie=tie.astype(bool), nodes=int(nn))
 
 
 def gravity_tree(pos, m):

@@ -120,3 +120,28 @@ def test_degenerate_trees():
     g = native.gravity(pos, np.array([1.0, 2.0, 3.0]), 1.0, 0.0)
     assert np.allclose(g["acc"][:, 0], [3.0, 0.0, 0.0], rtol=1e-15)
     assert np.allclose(g["acc"][:, 2], [-3.0, 0.0, 0.0], rtol=1e-15)
+
+
+def test_opening_criterion_is_strict_on_the_node_edge_over_the_com_distance():
+    # section 3.3: a node acts as one pseudo-particle when s / r < theta, s its edge
+    # and r the distance to its centre of mass.  Root cube [0, 8]^3 (s0 = 8, set by
+    # the target at the origin and a body at (8, 8, 8)); the octant z >= 4, x, y < 4
+    # (edge 4) holds two unit masses in different sub-octants, centre of mass
+    # (2, 2, 6) exactly, at r = sqrt(44) from the target.  The root (s / r = 8 /
+    # sqrt(43) > 1) is always opened.
+    pos = np.array([[0.0, 8.0, 1.0, 3.0], [0.0, 8.0, 1.0, 3.0], [0.0, 8.0, 5.0, 7.0]])
+    m = np.ones(4)
+    tie = 4.0 / np.sqrt(44.0)
+    above = native.gravity(pos, m, 1.0, np.nextafter(tie, 1.0), targets=[0])
+    at = native.gravity(pos, m, 1.0, tie, targets=[0])
+    below = native.gravity(pos, m, 1.0, np.nextafter(tie, 0.0), targets=[0])
+    assert above["count"][0] == 2  # the body at (8, 8, 8) and the node as one
+    assert at["count"][0] == 3 and below["count"][0] == 3  # the node opened: both bodies
+    # as one pseudo-particle of mass 2 at (2, 2, 6) (G = 1, no smoothing)
+    c = np.array([2.0, 2.0, 6.0])
+    b = np.array([8.0, 8.0, 8.0])
+    want = 2.0 * c / 44.0 ** 1.5 + b / np.linalg.norm(b) ** 3
+    assert np.abs(above["acc"][:, 0] - want).max() <= 1e-15 * np.abs(want).max()
+    p1, p2 = pos[:, 2], pos[:, 3]
+    want3 = p1 / np.linalg.norm(p1) ** 3 + p2 / np.linalg.norm(p2) ** 3 + b / np.linalg.norm(b) ** 3
+    assert np.abs(at["acc"][:, 0] - want3).max() <= 1e-15 * np.abs(want3).max()

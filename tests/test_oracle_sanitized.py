@@ -32,7 +32,7 @@ void orc_rhs2(int64_t, const double *, const double *, const double *, const dou
               int64_t, const int64_t *, const int32_t *, double *, double *, double *, double *,
               double *, double *, double *);
 int64_t orc_gravity(int64_t, const double *, const double *, double, double, double,
-                    const int64_t *, int64_t, double *, int64_t *);
+                    const int64_t *, int64_t, double *, int64_t *, int32_t *);
 int64_t orc_gravity_tree(int64_t, const double *, const double *, int64_t, int32_t *, int64_t *,
                          double *, double *);
 
@@ -87,8 +87,9 @@ int main(void) {
 
     double *ga = malloc(3 * N * sizeof(double));
     int64_t *gc = malloc(N * sizeof(int64_t));
-    const int64_t nn = orc_gravity(N, POS, M, 1.0, 0.5, 0.01, NULL, 0, ga, gc);
-    orc_gravity(N, POS, M, 1.0, 0.0, 0.0, tg, nt, ga, gc);
+    int32_t *gt = malloc(N * sizeof(int32_t));
+    const int64_t nn = orc_gravity(N, POS, M, 1.0, 0.5, 0.01, NULL, 0, ga, gc, gt);
+    orc_gravity(N, POS, M, 1.0, 0.0, 0.0, tg, nt, ga, gc, NULL);
     int32_t *dep = malloc(nn * sizeof(int32_t));
     int64_t *cor = malloc(3 * nn * sizeof(int64_t));
     double *gm = malloc(nn * sizeof(double)), *com = malloc(3 * nn * sizeof(double));
@@ -99,7 +100,7 @@ int main(void) {
                    finite_all(com, 3 * nn);
     free(counts); free(row_ptr); free(col); free(p); free(f); free(cs); free(sig);
     free(acc); free(drho); free(dS); free(rs); free(L); free(du); free(xv);
-    free(tg); free(rp2); free(c2); free(col2); free(ga); free(gc);
+    free(tg); free(rp2); free(c2); free(col2); free(ga); free(gc); free(gt);
     free(dep); free(cor); free(gm); free(com);
     printf("driver %s: %lld partners, %lld inner nodes\n", ok ? "ok" : "NON-FINITE", (long long)nnz,
            (long long)nn);
