@@ -9,6 +9,7 @@ sharing any of the computation.
 from .generate import (  # noqa: F401
     Workload,
     MATERIAL,
+    PARAM_ORDER,
     config,
     cube,
     two_particles,
