@@ -88,7 +88,12 @@ typedef struct {
 } sph_pairs;
 
 /* Uniform grid of cubic cells ("helping grid", section 3.5.2) produced by
- * sph_build_cells.  Cells are numbered c = ix + dims[0] * (iy + dims[1] * iz);
+ * sph_build_cells.  Cells are numbered by tiles of 4 x 4 x 4 cells (x fastest
+ * inside a tile: ix % 4 + 4 (iy % 4) + 16 (iz % 4)), the 64 tiles of a block of
+ * 16 x 16 x 16 cells in Morton order (bits of the tile coordinates interleaved x, y,
+ * z from the lowest), blocks x fastest: c = 4096 (bx + Bx (by + By bz)) + 64 tile +
+ * local, B = ceil(dims / 16) blocks per axis, so consecutive slots form compact
+ * pieces of space;
  * particles outside the box [lo, lo + dims * cell) are binned into the nearest
  * boundary cell, which keeps every partner reachable.  The grid stays valid for
  * later positions as long as no particle has moved by more than skin / 2 since
@@ -96,7 +101,7 @@ typedef struct {
 typedef struct {
     int64_t n;            /* particles binned */
     int32_t dims[3];      /* cells per axis */
-    int64_t ncells;       /* dims[0] * dims[1] * dims[2] */
+    int64_t ncells;       /* 4096 Bx By Bz (cells of the whole blocks) */
     double lo[3];         /* lower corner of cell (0,0,0) */
     double cell;          /* cell edge length */
     double h;             /* largest support radius the grid serves */
@@ -231,7 +236,8 @@ size_t sph_workspace_bytes(int op, int64_t n, int64_t ncells);
 
 /* Host-only: grid geometry for the box [lo, hi] at support radius h, skin and
  * cells_per_h (1 or 2): cell = (h + skin) (1 + 2^-40) / cells_per_h,
- * dims = max(1, ceil((hi - lo) / cell)).  Lets the caller size cell_start. */
+ * dims = max(1, ceil((hi - lo) / cell)), ncells = 4096 prod(ceil(dims / 16)) (the
+ * cells of whole 16^3 blocks, see sph_grid).  Lets the caller size cell_start. */
 int sph_grid_geometry(const double lo[3], const double hi[3], double h, double skin,
                       int cells_per_h, int32_t dims_out[3], int64_t *ncells_out,
                       double *cell_out);

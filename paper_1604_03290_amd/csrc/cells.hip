@@ -1,7 +1,8 @@
 // Cell list ("helping grid" of section 3.5.2): bin, count, scan, scatter, and
 // order every cell by user index.  The slot order is a counting sort on the
-// cell number (one radix digit of size ncells) made deterministic by the
-// per-cell ordering, so repeated builds give identical permutations.
+// cell number (one radix digit of size ncells; cells numbered by tiles and blocks,
+// see common.hpp) made deterministic by the per-cell ordering, so repeated builds
+// give identical permutations.
 #include <cfloat>
 
 #include "common.hpp"
@@ -27,7 +28,7 @@ __global__ __launch_bounds__(kBlock) void k_bin(const double *__restrict__ x,
     const int ix = cell_index(px, g.lox, g.inv_cell, g.nx);
     const int iy = cell_index(py, g.loy, g.inv_cell, g.ny);
     const int iz = cell_index(pz, g.loz, g.inv_cell, g.nz);
-    const int c = (iz * g.ny + iy) * g.nx + ix;
+    const int c = cell_number(ix, iy, iz, g.nbx, g.nby);
     key[i] = c;
     atomicAdd(&count[c], 1);
 }
@@ -82,7 +83,8 @@ int check_grid(const sph_grid *g) {
         return fail(SPH_ERR_INVALID_ARG, "grid arrays are NULL");
     if (g->n <= 0 || g->dims[0] <= 0 || g->dims[1] <= 0 || g->dims[2] <= 0 ||
         !(g->cell > 0.0) || !(g->h > 0.0) || !(g->skin >= 0.0) ||
-        g->ncells != (int64_t)g->dims[0] * g->dims[1] * g->dims[2])
+        g->ncells != (int64_t)kBlockCells * blocks_along(g->dims[0]) * blocks_along(g->dims[1]) *
+                         blocks_along(g->dims[2]))
         return fail(SPH_ERR_INVALID_ARG, "grid is not initialised");
     return SPH_OK;
 }
@@ -103,14 +105,14 @@ extern "C" int sph_grid_geometry(const double lo[3], const double hi[3], double 
     if (cells_per_h != 1 && cells_per_h != 2)
         return fail(SPH_ERR_INVALID_ARG, "cells_per_h must be 1 or 2");
     const double cell = (h + skin) * (1.0 + 0x1p-40) / cells_per_h;
-    int64_t total = 1;
+    int64_t total = kBlockCells;
     for (int d = 0; d < 3; ++d) {
         if (!std::isfinite(lo[d]) || !std::isfinite(hi[d]) || !(hi[d] > lo[d]))
             return fail(SPH_ERR_INVALID_ARG, "box must satisfy lo < hi (axis %d)", d);
         const double cnt = std::ceil((hi[d] - lo[d]) / cell);
         if (cnt > 1.0e6) return fail(SPH_ERR_INVALID_ARG, "more than 1e6 cells along axis %d", d);
         dims_out[d] = cnt < 1.0 ? 1 : (int32_t)cnt;
-        total *= dims_out[d];
+        total *= blocks_along(dims_out[d]);
     }
     if (total >= ((int64_t)1 << 31) - 1) return fail(SPH_ERR_INVALID_ARG, "too many cells");
     *ncells_out = total;

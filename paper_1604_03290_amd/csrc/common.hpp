@@ -57,8 +57,43 @@ __device__ inline void raise_flag(int32_t *status, int32_t code) { atomicCAS(sta
 int clear_status(void *ws, hipStream_t s);
 
 // --------------------------------------------------------------------- grid --
+// Cell numbering.  Cells are grouped in tiles of 4 x 4 x 4 (x fastest inside a tile)
+// and tiles in blocks of 4 x 4 x 4 tiles (16^3 cells, tiles in Morton order inside a
+// block); blocks are numbered x fastest.  Slots follow the cell numbers, so 64
+// consecutive slots (one wavefront of targets) fill a compact 3-D piece of a tile
+// and the slots one XCD works on at a time a compact region, while runs of 4 cells
+// along x stay contiguous for the row sweeps.
+constexpr int kCellTile = 4;  // cells per tile edge
+constexpr int kBlockC = 16;  // cells per block edge
+constexpr int kBlockCells = kBlockC * kBlockC * kBlockC;
+
+__host__ __device__ inline int32_t blocks_along(int32_t cells) { return (cells + kBlockC - 1) / kBlockC; }
+
+// cell number of integer cell coordinates (nbx, nby: blocks along x and y)
+__host__ __device__ inline int32_t cell_number(int ix, int iy, int iz, int nbx, int nby) {
+    const int bx = ix >> 4, by = iy >> 4, bz = iz >> 4;
+    const int tx = (ix >> 2) & 3, ty = (iy >> 2) & 3, tz = (iz >> 2) & 3;
+    const int tile = (tx & 1) | ((ty & 1) << 1) | ((tz & 1) << 2) | ((tx >> 1) << 3) |
+                     ((ty >> 1) << 4) | ((tz >> 1) << 5);
+    const int local = (ix & 3) | ((iy & 3) << 2) | ((iz & 3) << 4);
+    return ((bz * nby + by) * nbx + bx) * kBlockCells + tile * 64 + local;
+}
+
+// inverse of cell_number
+__host__ __device__ inline void cell_coords(int32_t c, int nbx, int nby, int &ix, int &iy, int &iz) {
+    const int b = c / kBlockCells, t = (c >> 6) & 63, l = c & 63;
+    const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
+    const int tx = (t & 1) | (((t >> 3) & 1) << 1);
+    const int ty = ((t >> 1) & 1) | (((t >> 4) & 1) << 1);
+    const int tz = ((t >> 2) & 1) | (((t >> 5) & 1) << 1);
+    ix = bx * kBlockC + tx * kCellTile + (l & 3);
+    iy = by * kBlockC + ty * kCellTile + ((l >> 2) & 3);
+    iz = bz * kBlockC + tz * kCellTile + (l >> 4);
+}
+
 struct GridDev {
     int32_t nx, ny, nz;
+    int32_t nbx, nby;  // blocks of 16^3 cells along x and y
     double lox, loy, loz;
     double cell, inv_cell;
     double delta;  // tolerated movement since binning: skin / 2
@@ -81,6 +116,8 @@ inline GridDev grid_dev(const sph_grid *g) {
     d.nx = g->dims[0];
     d.ny = g->dims[1];
     d.nz = g->dims[2];
+    d.nbx = blocks_along(d.nx);
+    d.nby = blocks_along(d.ny);
     d.lox = g->lo[0];
     d.loy = g->lo[1];
     d.loz = g->lo[2];
@@ -146,10 +183,33 @@ template <class F>
 __device__ inline void for_each_candidate(const GridDev &g, int64_t s, double xa, double ya,
                                           double za, double reach, F &&f);
 
+// Slot ranges of the cells x0..x1 of the row (iy, iz), in increasing x: runs of
+// consecutive cell numbers (a tile's run of 4 cells, and the next tile's when it
+// follows in the numbering) give one range each.
+template <class F>
+__device__ inline void for_each_run(const GridDev &g, int iy, int iz, int x0, int x1, F &&f) {
+    int x = x0;
+    int cx = cell_number(x, iy, iz, g.nbx, g.nby);  // number of cell x
+    int c0 = cx, c1 = cx;                            // the range being merged
+    while (true) {
+        const int e = min(x1, x | (kCellTile - 1));  // last cell of this tile's run
+        c1 = cx + (e - x);
+        x = e + 1;
+        if (x > x1) break;
+        cx = cell_number(x, iy, iz, g.nbx, g.nby);
+        if (cx != c1 + 1) {
+            f(g.cell_start[c0], g.cell_start[c1 + 1]);
+            c0 = cx;
+        }
+    }
+    f(g.cell_start[c0], g.cell_start[c1 + 1]);
+}
+
 // Visits the slot ranges [s0, s1) of every cell row whose box comes within
-// `reach` of p (rows in y-z, a contiguous run of cells along x per row).
+// `reach` of p (rows in y-z, the cells along x in runs of consecutive slots).
 // A partner b of a target at p (|x_b - p| < h) lies within delta of its cell's
-// box, so reach = (h + delta)(1 + 1e-9) visits every partner.
+// box, so reach = (h + delta)(1 + 1e-9) visits every partner.  Rows go in
+// increasing (z, y) and each row in increasing x, slots increasing inside a cell.
 template <class F>
 __device__ inline void for_each_row(const GridDev &g, double px, double py, double pz,
                                     double reach, F &&f) {
@@ -169,8 +229,7 @@ __device__ inline void for_each_row(const GridDev &g, double px, double py, doub
             const double w = sqrt(r2 - d2) * (1.0 + 1e-9);
             const int x0 = cell_index(px - w, g.lox, g.inv_cell, g.nx);
             const int x1 = cell_index(px + w, g.lox, g.inv_cell, g.nx);
-            const int row = (iz * g.ny + iy) * g.nx;
-            f(g.cell_start[row + x0], g.cell_start[row + x1 + 1]);
+            for_each_run(g, iy, iz, x0, x1, f);
         }
     }
 }
@@ -184,10 +243,8 @@ __device__ inline bool within_cell(const GridDev &g, int s, double x, double y, 
         const double lim = g.pl_delta * (1.0 - 1e-9);
         return dx * dx + dy * dy + dz * dz <= lim * lim;
     }
-    const int c = g.cell_of[s];
-    const int ix = c % g.nx;
-    const int iy = (c / g.nx) % g.ny;
-    const int iz = c / (g.nx * g.ny);
+    int ix, iy, iz;
+    cell_coords(g.cell_of[s], g.nbx, g.nby, ix, iy, iz);
     const double lim = g.delta * (1.0 - 1e-9);
     return slab_gap(x, g.lox, g.cell, ix, g.nx) <= lim &&
            slab_gap(y, g.loy, g.cell, iy, g.ny) <= lim &&
@@ -212,6 +269,12 @@ __device__ inline void for_each_candidate(const GridDev &g, int64_t s, double xa
 // ------------------------------------------------------------ B-spline, 3-D --
 // Section 3.1.1: W = s/h^3 w(q), dW/dr = 6s/h^4 g(q), q = r/h, s = 8/pi.
 constexpr double kSigma3 = 2.5464790894703255;  // 8 / pi
+
+// stable LSD radix sort of (uint64 key, int32 value) pairs by key bits [0, bits)
+// (sort.hip); the result lands in buffer *which of the two
+size_t radix_sort_tmp_elems(int64_t n);
+int radix_sort_pairs(uint64_t *key[2], int32_t *val[2], int64_t n, int bits, int32_t *tmp,
+                     int *which, hipStream_t s);
 
 // exclusive scans (scan.hip)
 int exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *tmp, hipStream_t s);

@@ -31,44 +31,129 @@ __global__ __launch_bounds__(kBlock) void k_pl_gather(GridDev g, const double *_
     x0[3 * s + 2] = pz;
 }
 
-// Count pass (kFill = false) or fill pass.  The fill runs over every slot of
-// every group, including the lanes past n of the last group, and fills the
-// padding after each list with the slot itself (n - 1 for lanes past n), so
-// that every entry of a group is a valid slot and readers of whole groups load
-// without guards.
+// Distance from the interval [b0, b1] to the slab of cell i along one axis (the
+// first and last cells extend to infinity, as in slab_gap).
+__device__ inline double box_gap(double b0, double b1, double lo, double cell, int i, int ncell) {
+    const double a = lo + cell * i;
+    const double b = a + cell;
+    double g = 0.0;
+    if (i > 0 && b1 < a) g = a - b1;
+    if (i < ncell - 1 && b0 > b) g = b0 - b;
+    return g;
+}
+
+__device__ inline double wave_min(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ inline double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Count pass (kFill = false) or fill pass, one wavefront per group of 64 slots.
+// Candidates are met in the order of the cell rows (z, then y, increasing), x
+// increasing along a row and slots increasing inside a cell: the order of
+// for_each_row, so each list holds its slot's candidates in the order a cell sweep
+// meets them.  A compact group sweeps the cell region of its bounding box widened
+// by the reach once, cooperatively: the 64 lanes load 64 candidate positions with
+// one coalesced load into LDS, then each lane tests all of them against its own
+// slot (broadcast reads).  A group spread over a region of more than kSpread times
+// one slot's cells (sparse parts of a set) sweeps per lane instead.  The fill
+// writes entry j of lane l at block_start[B] + 64 j + l and pads every list to the
+// group's longest with the slot itself (n - 1 for the lanes past n), so every entry
+// of a group is a valid slot and readers of whole groups load without guards.
+constexpr double kSpread = 8.0;
+
 template <bool kFill>
 __global__ __launch_bounds__(kBlock) void k_pl_scan(GridDev g, const double *__restrict__ x0,
                                                     int64_t n, double r2, double reach,
                                                     int32_t *__restrict__ count,
                                                     const int64_t *__restrict__ block_start,
                                                     int32_t *__restrict__ slot) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double lds[kBlock / 64][3][kWave];
+    double(*cand)[kWave] = lds[threadIdx.x >> 6];
+    const int lane = __lane_id();
     const int64_t nb = (n + kWave - 1) / kWave;
-    if (s >= (kFill ? nb * kWave : n)) return;
+    const int64_t B = (int64_t)blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6);
+    if (B >= nb) return;  // whole wavefront past the end
+    const int64_t s = B * kWave + lane;
+    const bool act = s < n;
+    const int64_t sa = act ? s : B * kWave;  // lanes past n stand on the group's first slot
+    const double xa = x0[3 * sa], ya = x0[3 * sa + 1], za = x0[3 * sa + 2];
     int64_t base = 0, maxc = 0;
     if (kFill) {
-        base = block_start[s / kWave] + (s % kWave);
-        maxc = (block_start[s / kWave + 1] - block_start[s / kWave]) / kWave;
-        if (s >= n) {
-            for (int64_t j = 0; j < maxc; ++j) slot[base + kWave * j] = (int32_t)(n - 1);
-            return;
-        }
+        base = block_start[B] + lane;
+        maxc = (block_start[B + 1] - block_start[B]) / kWave;
     }
-    const double xa = x0[3 * s], ya = x0[3 * s + 1], za = x0[3 * s + 2];
     int c = 0;
-    for_each_row(g, xa, ya, za, reach, [&](int s0, int s1) {
-        for (int t = s0; t < s1; ++t) {
-            if (t == s) continue;
-            if (dist2_exact(xa, ya, za, x0[3 * t], x0[3 * t + 1], x0[3 * t + 2]) < r2) {
-                if (kFill) slot[base + (int64_t)kWave * c] = t;
-                ++c;
+    auto hit = [&](int t) {
+        // the count pass found maxc or fewer with the same test; the guard keeps a
+        // write inside the group even so
+        if (kFill && c < maxc) slot[base + (int64_t)kWave * c] = t;
+        ++c;
+    };
+    const double bx0 = wave_min(xa), bx1 = wave_max(xa);
+    const double by0 = wave_min(ya), by1 = wave_max(ya);
+    const double bz0 = wave_min(za), bz1 = wave_max(za);
+    const int z0 = cell_index(bz0 - reach, g.loz, g.inv_cell, g.nz);
+    const int z1 = cell_index(bz1 + reach, g.loz, g.inv_cell, g.nz);
+    const int y0 = cell_index(by0 - reach, g.loy, g.inv_cell, g.ny);
+    const int y1 = cell_index(by1 + reach, g.loy, g.inv_cell, g.ny);
+    const int x0c = cell_index(bx0 - reach, g.lox, g.inv_cell, g.nx);
+    const int x1c = cell_index(bx1 + reach, g.lox, g.inv_cell, g.nx);
+    const double own = 2.0 * reach * g.inv_cell + 1.0;  // cells along one axis of one slot
+    const double box = (double)(x1c - x0c + 1) * (y1 - y0 + 1) * (z1 - z0 + 1);
+    if (box > kSpread * own * own * own) {
+        if (act)
+            for_each_row(g, xa, ya, za, reach, [&](int s0, int s1) {
+                for (int t = s0; t < s1; ++t) {
+                    if (t == s) continue;
+                    if (dist2_exact(xa, ya, za, x0[3 * t], x0[3 * t + 1], x0[3 * t + 2]) < r2) hit(t);
+                }
+            });
+    } else {
+        const double rr = reach * reach;
+        for (int iz = z0; iz <= z1; ++iz) {
+            const double gz = box_gap(bz0, bz1, g.loz, g.cell, iz, g.nz);
+            if (gz * gz >= rr) continue;
+            for (int iy = y0; iy <= y1; ++iy) {
+                const double gy = box_gap(by0, by1, g.loy, g.cell, iy, g.ny);
+                const double d2 = gz * gz + gy * gy;
+                if (d2 >= rr) continue;
+                const double w = sqrt(rr - d2) * (1.0 + 1e-9);
+                const int xr0 = cell_index(bx0 - w, g.lox, g.inv_cell, g.nx);
+                const int xr1 = cell_index(bx1 + w, g.lox, g.inv_cell, g.nx);
+                for_each_run(g, iy, iz, xr0, xr1, [&](int s0, int s1) {
+                    for (int t0 = s0; t0 < s1; t0 += kWave) {
+                        const int t = t0 + lane;
+                        if (t < s1) {
+                            cand[0][lane] = x0[3 * (int64_t)t];
+                            cand[1][lane] = x0[3 * (int64_t)t + 1];
+                            cand[2][lane] = x0[3 * (int64_t)t + 2];
+                        }
+                        wave_sync();
+                        const int m = min(kWave, s1 - t0);
+                        for (int k = 0; k < m; ++k) {
+                            const int tk = t0 + k;
+                            const double d = dist2_exact(xa, ya, za, cand[0][k], cand[1][k], cand[2][k]);
+                            if (act && d < r2 && tk != s) hit(tk);
+                        }
+                        wave_sync();
+                    }
+                });
             }
         }
-    });
-    if (kFill)
-        for (int64_t j = c; j < maxc; ++j) slot[base + kWave * j] = (int32_t)s;
-    else
+    }
+    if (kFill) {
+        const int32_t pad = act ? (int32_t)s : (int32_t)(n - 1);
+        for (int64_t j = c; j < maxc; ++j) slot[base + kWave * j] = pad;
+    } else if (act) {
         count[s] = c;
+    }
 }
 
 // sizes[B] = 64 * (longest list of block B)
@@ -125,7 +210,8 @@ extern "C" int sph_build_pairs(sph_grid *grid, const double *x, const double *y,
     if ((rc = clear_status(ws, s))) return rc;
     k_pl_gather<<<blocks_for(n), kBlock, 0, s>>>(g, x, y, z, n, x0, c.status());
     SPH_LAUNCHED();
-    k_pl_scan<false><<<blocks_for(n), kBlock, 0, s>>>(g, x0, n, r2, reach, count, nullptr, nullptr);
+    k_pl_scan<false><<<blocks_for(nb, kBlock / 64), kBlock, 0, s>>>(g, x0, n, r2, reach, count,
+                                                                      nullptr, nullptr);
     SPH_LAUNCHED();
     k_pl_sizes<<<blocks_for(nb), kBlock, 0, s>>>(count, n, sizes);
     SPH_LAUNCHED();
@@ -140,8 +226,8 @@ extern "C" int sph_build_pairs(sph_grid *grid, const double *x, const double *y,
     if (total > capacity)
         return fail(SPH_ERR_CAPACITY, "pair list needs %lld entries, capacity %lld",
                     (long long)total, (long long)capacity);
-    k_pl_scan<true><<<blocks_for(nb * 64), kBlock, 0, s>>>(g, x0, n, r2, reach, count, block_start,
-                                                            slot);
+    k_pl_scan<true><<<blocks_for(nb, kBlock / 64), kBlock, 0, s>>>(g, x0, n, r2, reach, count,
+                                                                     block_start, slot);
     SPH_LAUNCHED();
     out->n = n;
     out->radius = radius;

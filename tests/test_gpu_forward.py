@@ -62,6 +62,18 @@ def adversarial(h=0.3, seed=0):
     return np.ascontiguousarray(np.array(pts).T)
 
 
+def cell_number(idx, dims):
+    """The grid's cell numbering: tiles of 4^3 cells (x fastest inside), tiles in
+    Morton order inside blocks of 16^3 cells, blocks x fastest."""
+    nb = (dims + 15) // 16
+    b = idx >> 4
+    t = (idx >> 2) & 3
+    tile = (t[0] & 1) | ((t[1] & 1) << 1) | ((t[2] & 1) << 2) | ((t[0] >> 1) << 3) | \
+        ((t[1] >> 1) << 4) | ((t[2] >> 1) << 5)
+    local = (idx[0] & 3) | ((idx[1] & 3) << 2) | ((idx[2] & 3) << 4)
+    return ((b[2] * nb[1] + b[1]) * nb[0] + b[0]) * 4096 + tile * 64 + local
+
+
 @pytest.mark.parametrize("cells_per_h", [1, 2])
 def test_build_cells_structure(cells_per_h):
     w = W.cube(16, 1 / 16, seed=3, shuffle=True)
@@ -81,8 +93,12 @@ def test_build_cells_structure(cells_per_h):
     lo = np.array(c.lo)
     inv = 1.0 / c.cell
     idx = np.clip(np.floor((w.pos - lo[:, None]) * inv), 0, dims[:, None] - 1).astype(np.int64)
-    cell_id = idx[0] + dims[0] * (idx[1] + dims[1] * idx[2])
-    assert np.array_equal(cell_id[perm], co)
+    assert np.array_equal(cell_number(idx, dims)[perm], co)
+    # 64 consecutive slots (a wavefront's targets) mostly lie in one or two tiles of
+    # 4 x 4 x 4 cells: compact pieces of space
+    ti = idx[:, perm] >> 2
+    tiles = np.array([len({tuple(v) for v in ti[:, s0:s0 + 64].T}) for s0 in range(0, n - 63, 64)])
+    assert (tiles <= 2).mean() >= 0.85 and tiles.max() <= 4, np.bincount(tiles)
     # within a cell, slots follow user index
     same = co[1:] == co[:-1]
     assert np.all(perm[1:][same] > perm[:-1][same])
@@ -255,8 +271,43 @@ def nonuniform():
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32comp"])
 def test_nonuniform_subsample(nonuniform, precision):
-    """8,388,608 particles, 9 to 255 partners: sampled targets against the oracle."""
-    _subsample_parity(nonuniform, 1024, precision, seed=14)
+    """8,388,608 particles, 9 to 255 partners: 4,096 sampled targets against the oracle."""
+    _subsample_parity(nonuniform, 4096, precision, seed=14)
+
+
+def _sampled_rows_bit_exact(w, k, seed):
+    """CSR rows of k sampled particles at full size (pair-list path, cells of (h + skin)
+    / 2, skin 0.1 dx) against the oracle's brute force for those rows (section 3.5.2:
+    the partners are the particles closer than h, ascending, self excluded)."""
+    idx = W.subsample(w.n, k, seed)
+    rp_ref, col_ref = native.neighbours(w.pos, w.h, idx)
+    pos = torch.as_tensor(w.pos, dtype=torch.float64).cuda().contiguous()
+    g = P.sph_build_cells(pos, w.h, skin=0.1 * w.dx, cells_per_h=2, pairs=True)
+    rp, col = P.sph_neighbours(g, pos, w.h)
+    it = torch.as_tensor(idx).cuda()
+    start, end = rp[it], rp[it + 1]
+    lens = (end - start).cpu().numpy()
+    assert np.array_equal(lens, np.diff(rp_ref))
+    flat = torch.repeat_interleave(start, end - start) + \
+        torch.arange(int(lens.sum()), device="cuda") - torch.repeat_interleave(
+            torch.as_tensor(np.concatenate([[0], np.cumsum(lens)[:-1]])).cuda(), end - start)
+    got = col[flat].cpu().numpy()
+    assert np.array_equal(got, col_ref)
+    # the whole CSR is consistent: symmetric count total, rows within bounds
+    assert int(rp[-1]) == int(col.numel()) and int(col.min()) >= 0 and int(col.max()) < w.n
+    return lens
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_full_size_partner_rows_bit_exact(k):
+    w = W.config(k)
+    lens = _sampled_rows_bit_exact(w, 4096, seed=20 + k)
+    assert lens.size == 4096 and lens.max() > 0
+
+
+def test_nonuniform_partner_rows_bit_exact(nonuniform):
+    lens = _sampled_rows_bit_exact(nonuniform, 4096, seed=24)
+    assert lens.min() < 30 and lens.max() > 200  # sparse shell and dense sphere both sampled
 
 
 CORR_PATHS = ["cells1", "cells2", "pairs_skin", "pairs2_skin"]

@@ -42,7 +42,7 @@ def test_workspace_sizes():
 def test_grid_geometry():
     dims, ncells, cell = L.grid_geometry([0, 0, 0], [1, 2, 3], 0.25, 0.05, 1)
     assert cell > 0.3 and cell < 0.3 * (1 + 1e-11)
-    assert dims == (4, 7, 10) and ncells == 280
+    assert dims == (4, 7, 10) and ncells == 4096  # one block of 16^3 cells
     dims2, _, cell2 = L.grid_geometry([0, 0, 0], [1, 2, 3], 0.25, 0.05, 2)
     assert abs(cell2 - cell / 2) < 1e-15 and dims2 == (7, 14, 20)
     for bad in [dict(h=0.0), dict(h=-1.0), dict(h=float("nan")), dict(skin=-1.0),
@@ -79,7 +79,7 @@ def _fake_grid(n=10):
     g = L.Grid()
     g.n = n
     g.dims[0] = g.dims[1] = g.dims[2] = 2
-    g.ncells = 8
+    g.ncells = 4096
     g.cell = 1.0
     g.h = 1.0
     g.skin = 0.0
@@ -139,3 +139,4 @@ def test_rhs_validation_state_and_precision():
     assert lib.sph_rhs(C.byref(g), C.byref(s), C.byref(pr), 7, C.byref(d), ws, 1 << 40, None) == L.SPH_ERR_INVALID_ARG
     d.ax = 0
     assert lib.sph_rhs(C.byref(g), C.byref(s), C.byref(pr), 0, C.byref(d), ws, 1 << 40, None) == L.SPH_ERR_INVALID_ARG
+
