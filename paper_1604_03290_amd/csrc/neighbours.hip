@@ -1,10 +1,12 @@
 // Interaction partner lists (section 3.5.2) as a CSR in user order, each row
 // ascending.  Positions are first gathered into slot order; a count pass takes
 // candidates from the grid's pair list when it has one (else from the cell rows)
-// and applies the exact test; then one wavefront per row repeats the test over the
-// row's candidates, packs the partners in LDS, sorts them in registers with a
-// bitonic network and writes the row with whole-wavefront stores.  Rows longer
-// than kRowMax are written unsorted and sorted afterwards in LDS.
+// and applies the exact test.  From the cell rows, one wavefront per row repeats the
+// test over the row's candidates, packs the partners in LDS, sorts them in registers
+// with a bitonic network and writes the row with whole-wavefront stores.  From the
+// pair list, one wavefront per group of 64 slots writes the group's rows unsorted
+// (tiles of the list in LDS, contiguous stores per row) and a second pass sorts each
+// row in registers.  Rows longer than kRowMax are sorted afterwards in LDS.
 #include <climits>
 
 #include "common.hpp"
@@ -167,6 +169,112 @@ __global__ __launch_bounds__(kBlock) void k_nb_rows(GridDev g, const double4 *__
         sort_store_row<4>(buf, len, out);
 }
 
+// Fill over the frozen pair list, one wavefront per group of 64 slots.  The group's
+// list is taken in tiles of 64 steps (each step one coalesced 256-byte load) into LDS;
+// then for each slot of the group in turn the lanes test 64 of its candidates (a
+// column of the tile, conflict-free with the padded row length) and append the
+// partners' user indices to its row in candidate order (ballot prefix, one contiguous
+// store).  The rows are sorted afterwards by k_nb_sort_rows.
+constexpr int kTileSteps = 64;
+
+__global__ __launch_bounds__(kBlock) void k_nb_fill_list(GridDev g, const double4 *__restrict__ pos,
+                                                         int64_t n, double h2,
+                                                         const int64_t *__restrict__ row_ptr,
+                                                         int32_t *__restrict__ col) {
+    __shared__ int32_t lds[kBlock / 64][kTileSteps][65];
+    int32_t(*tile)[65] = lds[threadIdx.x >> 6];
+    const int lane = __lane_id();
+    const int64_t nb = (n + 63) / 64;
+    const int64_t B = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (B >= nb) return;
+    const int64_t base = g.pl_block[B];
+    const int steps = (int)((g.pl_block[B + 1] - base) >> 6);
+    const int64_t s = B * 64 + lane;
+    const bool act = s < n;
+    // this lane's row: candidates, output offset, length; k = partners written so far
+    const int cnt = act ? g.pl_count[s] : 0;
+    const int64_t r0 = act ? row_ptr[g.perm[s]] : 0;
+    const int len = act ? (int)(row_ptr[g.perm[s] + 1] - r0) : 0;
+    int k = 0;
+    const int rows = (int)min<int64_t>(64, n - B * 64);
+    for (int j0 = 0; j0 < steps; j0 += kTileSteps) {
+        const int m = min(kTileSteps, steps - j0);
+        for (int jj = 0; jj < m; ++jj) tile[jj][lane] = g.pl_slot[base + ((int64_t)(j0 + jj) << 6) + lane];
+        wave_sync();
+        for (int r = 0; r < rows; ++r) {
+            const int cr = __shfl(cnt, r);
+            if (j0 >= cr) continue;  // wavefront-uniform
+            const int64_t sr = B * 64 + r;
+            const double4 pa = pos[sr];
+            const bool valid = j0 + lane < cr;
+            bool hit = false;
+            int32_t u = 0;
+            if (valid) {
+                const int t = tile[lane][r];
+                const double4 pb = pos[t];
+                hit = dist2_exact(pa.x, pa.y, pa.z, pb.x, pb.y, pb.z) < h2;
+                u = g.perm[t];
+            }
+            const unsigned long long mk = __ballot(hit);
+            const int kr = __shfl(k, r);
+            const int lr = __shfl(len, r);
+            const int64_t rr = __shfl(r0, r);
+            if (hit) {
+                const int at = kr + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mk >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo((unsigned)mk, 0));
+                if (at < lr) col[rr + at] = u;  // the count pass found lr with the same test
+            }
+            if (lane == r) k += __popcll(mk);
+        }
+        wave_sync();
+    }
+}
+
+// One wavefront per row: the row (in candidate order) sorted ascending in registers
+// with the bitonic network (rows up to kRowMax; 1, 2 or 4 values per lane) and
+// written back; a row already in order is left as it is.  Longer rows are left to
+// k_nb_sort.
+template <int E>
+__device__ inline void sort_row_inplace(int32_t *__restrict__ row, int len) {
+    const int lane = __lane_id();
+    int32_t v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = 64 * e + lane;
+        v[e] = i < len ? row[i] : INT_MAX;
+    }
+    // in order already? (value i <= value i + 1 for every i)
+    bool ok = true;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int32_t nxt = __shfl_down(v[e], 1);
+        const int32_t nxt_e = e + 1 < E ? __shfl(v[e + 1 < E ? e + 1 : e], 0) : INT_MAX;
+        ok = ok && v[e] <= (lane == 63 ? nxt_e : nxt);
+    }
+    if (__ballot(!ok) == 0) return;
+    wave_bitonic<E>(v);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = 64 * e + lane;
+        if (i < len) row[i] = v[e];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_nb_sort_rows(const int64_t *__restrict__ row_ptr,
+                                                         int64_t n, int32_t *__restrict__ col) {
+    const int64_t a = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (a >= n) return;
+    const int64_t r0 = row_ptr[a];
+    const int len = (int)(row_ptr[a + 1] - r0);
+    if (len <= 1) return;
+    if (len <= 64)
+        sort_row_inplace<1>(col + r0, len);
+    else if (len <= 128)
+        sort_row_inplace<2>(col + r0, len);
+    else if (len <= kRowMax)
+        sort_row_inplace<4>(col + r0, len);
+}
+
 // one wavefront per row longer than min_len: bitonic sort of the row in LDS (rows
 // longer than kSortMax, which no workload here produces, fall back to an
 // insertion sort)
@@ -270,8 +378,16 @@ extern "C" int sph_neighbours(const sph_grid *grid, const double *x, const doubl
         return fail(SPH_ERR_CAPACITY, "%lld partners exceed capacity %lld", (long long)nnz,
                     (long long)col_cap);
     if (nnz == 0) return SPH_OK;
-    k_nb_rows<<<blocks_for(n, kBlock / 64), kBlock, 0, s>>>(g, pos, n, h * h, reach, row_ptr, col);
-    SPH_LAUNCHED();
+    if (g.pl_count) {
+        k_nb_fill_list<<<blocks_for((n + 63) / 64, kBlock / 64), kBlock, 0, s>>>(g, pos, n, h * h,
+                                                                                row_ptr, col);
+        SPH_LAUNCHED();
+        k_nb_sort_rows<<<blocks_for(n, kBlock / 64), kBlock, 0, s>>>(row_ptr, n, col);
+        SPH_LAUNCHED();
+    } else {
+        k_nb_rows<<<blocks_for(n, kBlock / 64), kBlock, 0, s>>>(g, pos, n, h * h, reach, row_ptr, col);
+        SPH_LAUNCHED();
+    }
     k_nb_sort<<<blocks_for(n, kBlock / 64), kBlock, 0, s>>>(row_ptr, n, col, kRowMax);
     SPH_LAUNCHED();
     return SPH_OK;
