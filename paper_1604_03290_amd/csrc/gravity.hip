@@ -14,7 +14,8 @@
 // depths D_{i-1} < d <= D_i, D_i being the depth shared by keys i and i + 1.
 //
 //   keys      bounding cube (reduction), integer coordinates, keys
-//   sort      rocPRIM radix sort of (key, user index), stable
+//   sort      the library's stable LSD radix sort of (key, user index), 8 passes of
+//             8 bits (sort.hip)
 //   depth     D_i and the number of nodes starting at i; scan -> item offsets
 //   items     leaves (position, mass) and inner nodes (depth, skip), and the list of
 //             inner nodes (the k-th inner node in pre-order is list[k])
@@ -27,8 +28,6 @@
 //             descends while any active lane needs to, so every lane takes exactly
 //             the terms, and in the order, of its own walk.  Both possible next items
 //             (t + 1 and the skip) are fetched while the current one is tested.
-#include <rocprim/device/device_radix_sort.hpp>
-
 #include "common.hpp"
 #include "rhs_common.hpp"
 #include "timing.hpp"
@@ -343,11 +342,8 @@ struct GravWs {
     int32_t *max_depth;
     int32_t *list;
     Item *it;
-    void *sort_tmp;
-    size_t sort_bytes;
+    int32_t *sort_tmp;
 };
-
-size_t sort_bytes_bound(int64_t n) { return (size_t)n * 16 + ((size_t)4 << 20); }
 
 int64_t node_capacity(int64_t n, int64_t cap) { return cap > 0 ? cap : 2 * n; }
 
@@ -365,8 +361,7 @@ GravWs carve_grav(Carve &c, int64_t n, int64_t cap) {
     w.max_depth = c.take<int32_t>(1);
     w.list = c.take<int32_t>(cap);
     w.it = c.take<Item>(n + cap);
-    w.sort_bytes = sort_bytes_bound(n);
-    w.sort_tmp = c.take<char>(w.sort_bytes);
+    w.sort_tmp = c.take<int32_t>(radix_sort_tmp_elems(n));
     return w;
 }
 
@@ -412,14 +407,10 @@ extern "C" int sph_gravity(const double *x, const double *y, const double *z, co
     k_keys<<<nb, kBlock, 0, s>>>(x, y, z, m, n, w.box, w.key[0], w.idx[0], c.status());
     SPH_LAUNCHED();
 
-    rocprim::double_buffer<uint64_t> kb(w.key[0], w.key[1]);
-    rocprim::double_buffer<int32_t> vb(w.idx[0], w.idx[1]);
-    size_t sb = 0;
-    SPH_HIP_TRY(rocprim::radix_sort_pairs(nullptr, sb, kb, vb, (unsigned)n, 0, 63, s));
-    if (sb > w.sort_bytes) return fail(SPH_ERR_HIP, "sort needs %zu bytes of scratch", sb);
-    SPH_HIP_TRY(rocprim::radix_sort_pairs(w.sort_tmp, sb, kb, vb, (unsigned)n, 0, 63, s));
-    const uint64_t *key = kb.current();
-    const int32_t *idx = vb.current();
+    int which = 0;
+    if ((rc = radix_sort_pairs(w.key, w.idx, n, 63, w.sort_tmp, &which, s))) return rc;
+    const uint64_t *key = w.key[which];
+    const int32_t *idx = w.idx[which];
 
     k_set_i32<<<1, 64, 0, s>>>(w.max_depth, -1);
     SPH_LAUNCHED();
