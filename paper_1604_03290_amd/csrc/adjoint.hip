@@ -121,11 +121,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_L(GridDev g, int64_t n, Consts k
     }
 }
 
-// same over the frozen pair list with cooperative gathers
+// same over the frozen pair list with cooperative gathers of the partners' first
+// four chunks (position, velocity, density, V: 64 bytes)
 template <bool kCorr>
 __global__ __launch_bounds__(kBlock) void k_adj_L_list(GridDev g, int64_t n, Consts k,
                                                        const double *__restrict__ rec, AdjRec ad) {
-    __shared__ double2 lbuf[kBlock / 64][64 * 7];
+    __shared__ double2 lbuf[kBlock / 64][64 * 4];
     double2 *buf = lbuf[threadIdx.x >> 6];
     const int64_t s = xcd_block(gridDim.x) * kBlock + threadIdx.x;
     const int64_t w0 = s - __lane_id();
@@ -146,14 +147,14 @@ __global__ __launch_bounds__(kBlock) void k_adj_L_list(GridDev g, int64_t n, Con
     const int32_t *row = g.pl_slot + base + __lane_id();
     int e0 = steps > 0 ? row[0] : 0;
     for (int j = 0; j < steps; ++j) {
-        gather_dma<7>(recs, kRec * 8, e0, buf);
+        gather_dma4(recs, kRec * 8, e0, buf);
         if (j + 1 < steps) e0 = row[(int64_t)(j + 1) << 6];
         wave_sync();
         if (j < cnt) {
-            const double2 b0 = dma_chunk<7>(buf, 0), b1 = dma_chunk<7>(buf, 1);
+            const double2 b0 = dma4_chunk(buf, 0), b1 = dma4_chunk(buf, 1);
             const double d2 = dist2_exact(xa, ya, za, b0.x, b0.y, b1.x);
             if (d2 < k.h2) {
-                const double2 b2 = dma_chunk<7>(buf, 2), b3 = dma_chunk<7>(buf, 3);
+                const double2 b2 = dma4_chunk(buf, 2), b3 = dma4_chunk(buf, 3);
                 const KernelPieces kp = kernel_pieces(k, d2, rsqrt64(d2));
                 const double F = k.Fn * kp.f;
                 const double gx = F * (xa - b0.x), gy = F * (ya - b0.y), gz = F * (za - b1.x);

@@ -209,6 +209,35 @@ __device__ inline void gather_dma8(const char *__restrict__ recs, int stride, in
             (__attribute__((address_space(3))) void *)(buf + 64 * i), 16, 0, 0);
 }
 
+// The first four chunks of 128-byte records (position, velocity, density and V),
+// sixteen records per instruction: instruction i loads records r = 16 i + (lane >> 2),
+// chunk c landing at buf[4 r + ((c + (r >> 2)) & 3)], a rotation that keeps the
+// per-lane reads of one chunk free of bank conflicts.
+__device__ inline void gather_dma4(const char *__restrict__ recs, int stride, int entry,
+                                   double2 *buf) {
+    const int lane = __lane_id();
+    const int r0 = lane >> 2;
+    const int cc = ((lane & 3) - (r0 >> 2)) & 3;  // chunk this lane loads (r >> 2 = r0 >> 2 + 4 i)
+    const char *p = recs + cc * 16;
+    const int src = r0 * 4;
+    uint32_t t[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) t[i] = (uint32_t)__builtin_amdgcn_ds_bpermute(src + 64 * i, entry);
+    asm volatile("" : "+v"(t[0]), "+v"(t[1]), "+v"(t[2]), "+v"(t[3]));
+    uint32_t st = (uint32_t)stride;
+    asm("" : "+s"(st));
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        __builtin_amdgcn_global_load_lds(
+            reinterpret_cast<const void *>(p + (uint64_t)t[i] * st),
+            (__attribute__((address_space(3))) void *)(buf + 64 * i), 16, 0, 0);
+}
+
+__device__ inline double2 dma4_chunk(const double2 *buf, int c) {
+    const int L = __lane_id();
+    return buf[4 * L + ((c + (L >> 2)) & 3)];
+}
+
 __device__ inline double2 dma8_chunk(const double2 *buf, int c) {
     const int L = __lane_id();
     return buf[8 * L + ((c + L) & 7)];
