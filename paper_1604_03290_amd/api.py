@@ -394,16 +394,22 @@ class SphRhs(torch.autograd.Function):
                            u=None if u is None else u.detach().contiguous(),
                            d=None if d is None else d.detach().contiguous())
         out = sph_rhs(grid, st, p, "fp64", extra=extra)
-        ctx.grid, ctx.params, ctx.state, ctx.extra = grid, p, st, extra
+        # the inputs are saved through autograd, so that an in-place change between
+        # forward and backward raises instead of differentiating at a changed state
+        ctx.save_for_backward(pos, vel, rho, S, m, u, d)
+        ctx.grid, ctx.params, ctx.extra = grid, p, extra
         ctx.mu_like, ctx.Y0_like = torch.as_tensor(mu), torch.as_tensor(Y0)
         res = (out["acc"], out["drho"], out["dS"], out["rho_sum"])
         return res + ((out["du"], out["xv"]) if extra else ())
 
     @staticmethod
     def backward(ctx, *grads):
+        pos, vel, rho, S, m, u, d = ctx.saved_tensors
+        c = lambda t: None if t is None else t.detach().contiguous()
+        st = ParticleState(c(pos), c(vel), c(rho), c(S), c(m), u=c(u), d=c(d))
         names = ("acc", "drho", "dS", "rho_sum", "du", "xv")
         cot = {k: (v.contiguous() if v is not None else None) for k, v in zip(names, grads)}
-        g = sph_rhs_adjoint(ctx.grid, ctx.state, ctx.params, cot)
+        g = sph_rhs_adjoint(ctx.grid, st, ctx.params, cot)
         gmu = g["mu"].to(ctx.mu_like.device, ctx.mu_like.dtype).reshape(ctx.mu_like.shape)
         gY0 = g["Y0"].to(ctx.Y0_like.device, ctx.Y0_like.dtype).reshape(ctx.Y0_like.shape)
         return (g["pos"], g["vel"], g["rho"], g["S"], gmu, gY0, None, None, None, None, None,

@@ -564,6 +564,13 @@ def test_rhs_adjoint_energy_and_xsph_cotangents(variant):
         assert rel(gk, ref[k]) < 1e-11, k
     if ref["mu"] is not None and ref["mu"] != 0.0:
         assert abs(float(got["mu"]) - ref["mu"]) <= 1e-11 * abs(ref["mu"])
+    # Y0 is reduced per wavefront on the list path, per block on the cell path
+    y0 = 0.0 if ref["Y0"] is None else ref["Y0"]
+    assert abs(float(got["Y0"]) - y0) <= 1e-11 * max(abs(y0), 1e-300), (float(got["Y0"]), y0)
+    # bit-identical repeat (fixed reduction order, no atomics)
+    again = P.sph_rhs_adjoint(g, st, w.params, {k: torch.as_tensor(v).cuda().contiguous() for k, v in cot.items()})
+    for k in ("pos", "vel", "rho", "S", "mu", "Y0"):
+        assert torch.equal(got[k], again[k]), k
 
 
 def test_leapfrog_with_fixed_damage_trajectory_and_gradient():
@@ -617,6 +624,25 @@ def test_autograd_function_with_extra_outputs_and_damage():
     for k, t in zip(("pos", "vel", "rho", "S"), leaves):
         assert rel(t.grad.cpu().numpy(), ref[k]) < 1e-11, k
     assert abs(float(mu.grad) - ref["mu"]) <= 1e-11 * abs(ref["mu"])
+    y0 = 0.0 if ref["Y0"] is None else ref["Y0"]
+    assert abs(float(Y0.grad) - y0) <= 1e-11 * max(abs(y0), 1e-300), (float(Y0.grad), y0)
+
+
+def test_autograd_function_refuses_inputs_changed_in_place():
+    # the inputs are saved through autograd: an in-place change between forward and
+    # backward raises instead of differentiating at the changed state
+    w = small("cube8_visc")
+    st = gpu_state(w)
+    g = P.sph_build_cells(st.pos, w.h, skin=0.05 * w.dx, pairs=True)
+    leaves = [t.clone().requires_grad_(True) for t in (st.pos, st.vel, st.rho, st.S)]
+    x = leaves[0] * 1.0  # a non-leaf the caller can still modify in place
+    mu = torch.tensor(w.params["mu"], dtype=torch.float64, device="cuda")
+    Y0 = torch.tensor(w.params["Y0"], dtype=torch.float64, device="cuda")
+    outs = P.SphRhs.apply(x, *leaves[1:], mu, Y0, g, w.params, st.m)
+    with torch.no_grad():
+        x.add_(1e-3 * w.dx)
+    with pytest.raises(RuntimeError):
+        outs[0].sum().backward()
 
 
 def test_autograd_function_tillotson_gradient_of_u():
