@@ -1,21 +1,26 @@
 #!/usr/bin/env python3
-"""Throughput of the SPH solid-body right-hand side on one MI355X.
+"""Throughput of the SPH solid-body right-hand side and its adjoint on one MI355X.
 
-One step = one pass of the whole hot path over the two-sphere collision
-(262,144 particles, 131,072 per sphere, h = 2.4 dx):
-  cell build (grid frozen for the trajectory, with a skin)   sph_build_cells
-  partner lists (CSR)                                        sph_neighbours
-  10 leapfrog steps = 11 FP64 right-hand sides               sph_leapfrog
-  reverse sweep: gradient of the final kinetic energy with
-  respect to v0, mu and Y0 = 11 adjoint evaluations          sph_leapfrog_adjoint
-The metric counts ordered pair interactions (b != a, |x_a - x_b| < h)
-evaluated by the right-hand sides and by the adjoint.  Inputs are resident
-on the GPU before timing starts.  Per-form rates (FP64 and FP32-compensated
-right-hand side, adjoint) are measured on the same input and reported beside
-the step.
+Default workload: the non-uniform three-body set (8,388,608 particles: a dense
+sphere with about 250 partners per particle, a sphere with about 60 and a sparse
+shell with about 20; h = 2.4 dx).  One step = one pass of the whole hot path over it:
+  cell build (tiled cell numbering)                          sph_build_cells
+  frozen pair list (the interaction list, skin 0)            sph_build_pairs
+  partner lists (CSR, user order, rows ascending)            sph_neighbours
+  FP64 right-hand side                                       sph_rhs
+  FP64 adjoint (vector-Jacobian product, random cotangent)   sph_rhs_adjoint
+The metric counts the ordered pair interactions (b != a, |x_a - x_b| < h) evaluated
+by the right-hand side and by the adjoint: value = 2 nnz / step time.  Inputs are
+resident on the GPU before timing starts.  Reported beside it: the FP32-compensated
+right-hand side (speed and normwise error per output against the FP64 GPU path and
+against the oracle on 4,096 sampled targets), each stage's time, the partner-count
+histogram, the roofline of the step's dominant kernel, the oracle's CPU rate and, on
+the two-sphere collision (262,144 particles), the 10-step leapfrog with its reverse
+sweep and the extended forms (energy, artificial stress, XSPH, Tillotson, damage,
+Barnes-Hut gravity).
 
-Prints one JSON line.  ``--gpus`` above 1 is refused: this build runs on one
-GPU (the multi-GPU decomposition is described in the design notes).
+Prints one JSON line.  ``--gpus`` above 1 is refused: this build runs on one GPU (the
+multi-GPU decomposition is described in the design notes).
 """
 from __future__ import annotations
 
@@ -36,13 +41,17 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X vector FP64
 PEAK_HBM_GBS = 8000.0
 CELLS_PER_H = 2  # cell edge (h + skin) / 2: fewer candidates per row sweep than edge h + skin
 
-# Algorithmic FP64 operations per ordered pair (FMA = 2, square root and division = 1):
-# right-hand side = distance, square root, kernel, gradient, density sum, velocity
-# gradient, stress bracket, acceleration (83) + the artificial viscosity on approaching
-# pairs (10); adjoint pair pass = both roles of the pair (222) + viscosity terms (23).
-FLOPS_RHS, FLOPS_RHS_APPROACH = 83.0, 10.0
-FLOPS_ADJ, FLOPS_ADJ_APPROACH = 222.0, 23.0
-FLOPS_ADJ_L = 45.0  # the adjoint's recomputation of the velocity gradient
+# Algorithmic FP64 operations per ordered pair, the scope's measurement unit: 95 for
+# the right-hand side (distance, square root, kernel and gradient, density sum,
+# velocity gradient, viscosity, stress bracket, acceleration) and 250 for the adjoint
+# (both roles of the pair; the lower end of the 250-300 estimate).  The kernels' own
+# operation counts (FMA = 2, square root and division = 1) are reported beside them:
+# 83 + 10 on approaching pairs (right-hand side), 222 + 23 (adjoint), 45 (the adjoint's
+# velocity-gradient pass).
+FLOPS_PER_PAIR = {"pairs_fp64": 95.0, "adjoint_pairs": 250.0, "adjoint_L": 45.0}
+IMPL_FLOPS = {"pairs_fp64": (83.0, 10.0), "adjoint_pairs": (222.0, 23.0), "adjoint_L": (45.0, 0.0)}
+KERNEL_NAME = {"pairs_fp64": "k_pairs64_list", "adjoint_pairs": "k_adj_pairs_list",
+               "adjoint_L": "k_adj_L_list"}
 # gravity walk, per body taken: distance (3), r^2 (5), opening test (3), force with a
 # refined reciprocal square root and the reciprocal of r + eps (11)
 FLOPS_GRAV_TERM = 22
@@ -53,30 +62,25 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="two_spheres", choices=["two_spheres", "bullet", "nonuniform", "cube40"])
+    ap.add_argument("--workload", default="nonuniform", choices=["nonuniform", "bullet", "two_spheres"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--form-reps", type=int, default=20)
+    ap.add_argument("--no-two-spheres", action="store_true", help="skip the two-sphere section")
+    ap.add_argument("--form-reps", type=int, default=10)
     return ap.parse_args()
 
 
-def load_workload(name):
-    import workloads as W
-    k = {"two_spheres": 1, "bullet": 2, "cube40": 3, "nonuniform": 4}[name]
-    w = W.config(k)
-    return k, w
+WORKLOADS = {"two_spheres": 1, "bullet": 2, "nonuniform": 4}
 
-
-# HBM bytes per launch of the dominant kernel, from two rocprofv3 counter runs of this
-# script (FETCH_SIZE, then WRITE_SIZE), each scaled by what the same counter reads for the
-# 1 GiB calibration copy.  They hold only for the kernel sources they were taken on: the
-# hash of those files is compared at run time and the figure is dropped on a mismatch.
-TRAFFIC = {"kernel": "k_adj_pairs_list", "workload": "two_spheres_262144",
-           "sources_sha256": "26e7b6401953907540c9f4b7caa1b19f9ca7aa10af2a02bdba544adfd466d034",
-           "fetch_bytes": 806.9e6, "write_bytes": 30.5e6,
-           "profile": "profiles/hbm_traffic_two_spheres_262144.md"}
+# Counter figures of the dominant kernel, from rocprofv3 runs of this script (profiles/):
+# HBM bytes per launch (FETCH_SIZE, then WRITE_SIZE, each scaled by what the counter reads
+# for the 1 GiB calibration copy) and the L2 hit rate (TCC_HIT / (TCC_HIT + TCC_MISS)).
+# They hold only for the kernel sources they were taken on: the hash of those files is
+# compared at run time and the figures are dropped on a mismatch.
+COUNTERS = {}
 
 KERNEL_SOURCES = {"k_adj_pairs_list": ("adjoint.hip", "adjoint.hpp", "rhs_common.hpp", "common.hpp"),
-                  "k_pairs64_list": ("rhs.hip", "rhs_common.hpp", "common.hpp")}
+                  "k_pairs64_list": ("rhs.hip", "rhs_common.hpp", "common.hpp"),
+                  "k_adj_L_list": ("adjoint.hip", "adjoint.hpp", "rhs_common.hpp", "common.hpp")}
 
 
 def sources_sha(kernel):
@@ -89,6 +93,17 @@ def sources_sha(kernel):
 
 
 HIST_EDGES = [0, 10, 20, 30, 40, 50, 60, 80, 100, 150, 200, 250, 300, 400, 100000]
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def approaching_fraction(st, row_ptr, col, torch, chunk=1 << 20):
@@ -106,6 +121,19 @@ def approaching_fraction(st, row_ptr, col, torch, chunk=1 << 20):
         neg += int((wab < 0).sum())
         tot += b - a
     return neg / max(tot, 1)
+
+
+def partner_stats(row_ptr, torch):
+    n = row_ptr.numel() - 1
+    dev = row_ptr.device
+    deg = (row_ptr[1:] - row_ptr[:-1]).double()
+    q = torch.quantile(deg[torch.randperm(n, device=dev)[:1 << 20]],
+                       torch.tensor([0.01, 0.5, 0.99], dtype=torch.float64, device=dev))
+    return {"min": int(deg.min()), "p01": float(q[0]), "p50": float(q[1]), "p99": float(q[2]),
+            "max": int(deg.max()), "mean": float(deg.mean()), "histogram_edges": HIST_EDGES,
+            "histogram": torch.bincount(torch.bucketize(deg, torch.tensor(
+                HIST_EDGES[1:-1], dtype=torch.float64, device=dev), right=True),
+                minlength=len(HIST_EDGES) - 1).tolist()}
 
 
 def copy_calibration(torch, nbytes=1 << 30):
@@ -132,43 +160,47 @@ def median_ms(fn, reps, torch):
     return float(np.median(ts))
 
 
-def cpu_baseline(w, budget_s=12.0):
-    """The oracle's right-hand side on a spatially contiguous sample of the workload
-    (the particles nearest the sample centre), partner lists precomputed by the oracle's
-    brute force (not timed), repeated until the budget is used."""
+def normwise(got, ref):
+    """max |got - ref| / max |ref| of one output field."""
+    return float(np.abs(got - ref).max() / np.abs(ref).max())
+
+
+def oracle_targets(w, k=4096, seed=11):
+    """k targets drawn uniformly (seeded) and their partner lists by the oracle's brute
+    force (untimed)."""
+    import workloads as W
     from oracle import native
-    n_sample = min(w.n, 32768)
-    c = w.pos.mean(1)
-    d2 = ((w.pos - c[:, None]) ** 2).sum(0)
-    idx = np.sort(np.argpartition(d2, n_sample - 1)[:n_sample])
-    sub = w.take(idx)
-    csr = native.neighbours(sub.pos, sub.h)
+    idx = W.subsample(w.n, k, seed)
+    csr = native.neighbours(w.pos, w.h, idx)
+    return idx, csr
+
+
+def cpu_baseline(w, idx, csr, budget_s=12.0):
+    """The oracle's right-hand side of the sampled targets over their precomputed partner
+    lists, repeated until the budget is used, on all host threads and on one."""
+    from oracle import native
     nnz = int(csr[0][-1])
-    pv = sub.param_vector()
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        native.rhs(sub.pos, sub.vel, sub.rho, sub.S, sub.m, pv, csr=csr, want_L=False)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el > budget_s or reps >= 5000:
-            break
-    rate = nnz * reps / el
+    pv = w.param_vector()
+
+    def run(budget):
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            native.rhs(w.pos, w.vel, w.rho, w.S, w.m, pv, targets=idx, csr=csr, want_L=False)
+            reps += 1
+            el = time.perf_counter() - t0
+            if el > budget or reps >= 5000:
+                return reps, el
+
+    reps, el = run(budget_s)
     cores = native.threads()
-    # one core, as the paper's own CPU comparison (a shorter budget)
     native.set_threads(1)
-    reps1, t0 = 0, time.perf_counter()
-    while True:
-        native.rhs(sub.pos, sub.vel, sub.rho, sub.S, sub.m, pv, csr=csr, want_L=False)
-        reps1 += 1
-        el1 = time.perf_counter() - t0
-        if el1 > budget_s / 3 or reps1 >= 5000:
-            break
+    reps1, el1 = run(budget_s / 3)
     native.set_threads(cores)
-    return {"value": rate, "unit": UNIT, "cores": cores, "kind": "oracle",
-            "single_core_value": nnz * reps1 / el1,
-            "sample": f"{n_sample} particles nearest the centre of {w.name} ({nnz} ordered pairs), "
-                      f"FP64 C oracle right-hand side over precomputed partner lists, {reps} repetitions "
-                      f"in {el:.1f} s on {cores} threads; {reps1} repetitions in {el1:.1f} s on one"}
+    return {"value": nnz * reps / el, "unit": UNIT, "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(), "single_core_value": nnz * reps1 / el1,
+            "sample": f"{idx.size} targets drawn uniformly from {w.name} ({nnz} ordered pairs), FP64 "
+                      f"C oracle right-hand side over partner lists precomputed by its brute force; "
+                      f"{reps} repetitions in {el:.1f} s on {cores} threads, {reps1} in {el1:.1f} s on one"}
 
 
 def cpu_gravity_baseline(w, targets=131072):
@@ -185,89 +217,76 @@ def cpu_gravity_baseline(w, targets=131072):
                       f"bodies ({terms} terms) in {el:.2f} s, tree build included"}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU "
-                                   "domain decomposition is design-only)"}))
-        sys.exit(2)
-    import torch
-    import paper_1604_03290_amd as P
-    from paper_1604_03290_amd import _lib as L
+def kernel_roofline(kern, nnz, f_app, pl_entries, steps, ms_step):
+    """Roofline entry of the step's dominant kernel from the library's event timings."""
+    dom = max(kern, key=lambda k: kern[k][0])
+    tot_ms, launches = kern[dom]
+    avg_ms = tot_ms / max(launches, 1)
+    fpp = FLOPS_PER_PAIR[dom]
+    impl = IMPL_FLOPS[dom][0] + IMPL_FLOPS[dom][1] * f_app
+    achieved = fpp * nnz / (avg_ms * 1e-3) / 1e12
+    kname = KERNEL_NAME[dom]
+    ctr = COUNTERS.get(kname)
+    ok = ctr is not None and ctr["sources_sha256"] == sources_sha(kname)
+    roof = {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+            "traffic": ctr["fetch_bytes"] + ctr["write_bytes"] if ok else None,
+            "traffic_unit": "bytes per launch (HBM read + write, counter-scaled)",
+            "traffic_source": ctr["profile"] if ok else None,
+            "hbm_GBps": (ctr["fetch_bytes"] + ctr["write_bytes"]) / (avg_ms * 1e-3) / 1e9 if ok else None,
+            "l2_hit_rate": ctr["l2_hit_rate"] if ok else None,
+            "avg_launch_ms": avg_ms, "launches": launches,
+            "flops_per_pair": fpp, "flops_per_pair_implemented": impl,
+            "frac_at_implemented_flops": impl * nnz / (avg_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+            "ordered_pairs_per_launch": nnz,
+            "share_of_step": tot_ms / steps / ms_step,
+            "other": {k: {"avg_launch_ms": v[0] / max(v[1], 1), "launches": v[1]} for k, v in kern.items()}}
+    gather_b = {"adjoint_pairs": 224, "pairs_fp64": 128, "adjoint_L": 64}.get(dom)
+    if gather_b:
+        gb = gather_b * pl_entries
+        roof["gather"] = {"bytes_per_launch": gb, "achieved_TBps": gb / (avg_ms * 1e-3) / 1e12,
+                          "bytes_per_entry": gather_b, "list_entries": pl_entries}
+    return roof
 
-    k, w = load_workload(args.workload)
-    dev = "cuda"
-    st = P.ParticleState.from_arrays(w.pos, w.vel, w.rho, w.S, w.m, dev)
-    steps_lf = max(w.steps, 1)
-    # Skin of the frozen grid and list: twice the largest displacement the trajectory makes,
-    # with 50 % margin (skin / 2 must cover every particle's movement; the device flag
-    # STALE_GRID would end the run otherwise), at least 0.02 dx.  The displacement is
-    # measured on one untimed trajectory under a grid with a generous skin of one dx.
-    g0 = P.sph_build_cells(st.pos, w.h, skin=w.dx, cells_per_h=CELLS_PER_H)  # cell sweeps, no list
-    f0, _ = P.sph_leapfrog(g0, st, w.params, w.dt, steps_lf, checkpoints=False)
-    L.check(P.workspace_status(f0._ws))
-    dmax = float(((f0.pos - st.pos) ** 2).sum(0).sqrt().max())
-    del g0, f0
-    skin = max(3.0 * dmax, 0.02 * w.dx)
+
+def single_state_step(args, w, torch, P, L):
+    """The default step on a one-state workload: cells, list, CSR, FP64 RHS, adjoint."""
+    st = P.ParticleState.from_arrays(w.pos, w.vel, w.rho, w.S, w.m, "cuda")
+    n = w.n
+    skin = 0.0  # one state: the list is the interaction list itself
     lo, hi = P.api.default_box(st.pos, w.h, skin)
     dims, ncells, _ = L.grid_geometry(lo, hi, w.h, skin, CELLS_PER_H)
-    n = w.n
     ws_build = P.workspace(L.SPH_OP_BUILD, n, ncells)
+    ws_pairs = P.workspace(L.SPH_OP_PAIRS, n)
     ws_nb = P.workspace(L.SPH_OP_NEIGHBOURS, n)
     ws_rhs = P.workspace(L.SPH_OP_RHS, n)
-    out = P.api.new_deriv(n)
-
-    ws_lf = P.workspace(L.SPH_OP_LEAPFROG, n)
-    ws_lfa = P.workspace(L.SPH_OP_LEAPFROG_ADJOINT, n)
     ws_adj = P.workspace(L.SPH_OP_ADJOINT, n)
-    ck = torch.empty(L.checkpoint_bytes(n, steps_lf) // 8, dtype=torch.float64, device=dev)
-    fin = P.ParticleState(torch.empty_like(st.pos), torch.empty_like(st.vel), torch.empty_like(st.rho),
-                          torch.empty_like(st.S), st.m)
-    cot = {"vel": torch.empty_like(st.vel)}
-    grad = P.api._fields(n, dev)
-
-    grid = P.sph_build_cells(st.pos, w.h, skin=skin, cells_per_h=CELLS_PER_H, box=(lo, hi), ws=ws_build)
-    row_ptr, col = P.sph_neighbours(grid, st.pos, w.h, ws=ws_nb)
-    nnz0 = int(row_ptr[-1].item())
-    # fraction of ordered pairs that approach (w_ab < 0): they also evaluate Pi
-    f_app = approaching_fraction(st, row_ptr, col, torch)
-    deg = (row_ptr[1:] - row_ptr[:-1]).double()
-    q = torch.quantile(deg[torch.randperm(n, device=dev)[:1 << 20]],
-                       torch.tensor([0.01, 0.5, 0.99], dtype=torch.float64, device=dev))
-    partners = {"min": int(deg.min()), "p01": float(q[0]), "p50": float(q[1]), "p99": float(q[2]),
-                "max": int(deg.max()), "mean": float(deg.mean()),
-                "histogram_edges": HIST_EDGES,
-                "histogram": torch.bincount(torch.bucketize(deg, torch.tensor(
-                    HIST_EDGES[1:-1], dtype=torch.float64, device=dev), right=True),
-                    minlength=len(HIST_EDGES) - 1).tolist()}
-    del deg
-    col_cap = int(col.numel()) + n  # room for pairs formed during the trajectory
-
-    ws_pairs = P.workspace(L.SPH_OP_PAIRS, n)
+    box = (lo, hi)
+    grid = P.sph_build_cells(st.pos, w.h, skin=skin, cells_per_h=CELLS_PER_H, box=box, ws=ws_build)
     pl_cap = P.sph_build_pairs(grid, st.pos, ws=ws_pairs)
+    row_ptr, col = P.sph_neighbours(grid, st.pos, w.h, ws=ws_nb)
+    nnz = int(row_ptr[-1].item())
+    col_cap = int(col.numel())
     cand = int(grid.pairs[1].long().sum())
-    # load balance = mean over max list length per wavefront, summed over wavefronts
-    pair_list = {"entries": pl_cap, "candidates": cand, "true_pairs_fraction": nnz0 / cand,
-                 "load_balance_mean_over_max_per_wave": cand / pl_cap}
+    f_app = approaching_fraction(st, row_ptr, col, torch)
+    partners = partner_stats(row_ptr, torch)
+    del col
+    out = P.api.new_deriv(n)
+    cot = {k: torch.randn(out[k].shape, dtype=torch.float64, device="cuda",
+                          generator=torch.Generator("cuda").manual_seed(3)) for k in P.api.DERIV_KEYS}
+    holder = {}
 
     def step():
-        g = P.sph_build_cells(st.pos, w.h, skin=skin, cells_per_h=CELLS_PER_H, box=(lo, hi), ws=ws_build)
+        g = P.sph_build_cells(st.pos, w.h, skin=skin, cells_per_h=CELLS_PER_H, box=box, ws=ws_build)
         P.sph_build_pairs(g, st.pos, capacity=pl_cap, ws=ws_pairs)
-        P.sph_neighbours(g, st.pos, w.h, col_cap=col_cap, ws=ws_nb)
-        P.sph_leapfrog(g, st, w.params, w.dt, steps_lf, checkpoints=ck, out=fin, ws=ws_lf)
-        torch.mul(fin.vel, fin.m, out=cot["vel"])  # d KE / d v_final
-        P.sph_leapfrog_adjoint(g, st, w.params, w.dt, steps_lf, ck, cot, ws=ws_lfa, grad=grad)
+        holder["csr"] = P.sph_neighbours(g, st.pos, w.h, col_cap=col_cap, ws=ws_nb)
+        P.sph_rhs(g, st, w.params, "fp64", out=out, ws=ws_rhs)
+        holder["grad"] = P.sph_rhs_adjoint(g, st, w.params, cot, ws=ws_adj)
+        holder["g"] = g
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    rp_end, _ = P.sph_neighbours(grid, fin.pos, w.h, ws=ws_nb)
-    nnz1 = int(rp_end[-1].item())
-    nnz = 0.5 * (nnz0 + nnz1)
-    pairs_per_step = 2 * (steps_lf + 1) * nnz
-    step_desc = (f"cell build + frozen pair list + partner CSR + {steps_lf}-step leapfrog ({steps_lf + 1} "
-                 f"FP64 right-hand sides) + reverse sweep ({steps_lf + 1} adjoints) for d KE / d (v0, mu, Y0)")
-
     calib = copy_calibration(torch)
     L.timing_reset()
     L.timing_enable(True)
@@ -284,147 +303,231 @@ def main():
     L.timing_enable(False)
     ms_step = e0.elapsed_time(e1) / args.steps
     kern = {k: L.timing_read(k) for k in ("pairs_fp64", "adjoint_pairs", "adjoint_L")}
+    for wsx in (ws_rhs, ws_adj, ws_nb):
+        rc = P.workspace_status(wsx)
+        if rc != 0:
+            raise RuntimeError(f"device flag {rc}")
+    g = holder["g"]
+    reps = args.form_reps
+    forms = {
+        "build_cells": {"ms": median_ms(lambda: P.sph_build_cells(
+            st.pos, w.h, skin=skin, cells_per_h=CELLS_PER_H, box=box, ws=ws_build), reps, torch)},
+        "build_pairs": {"ms": median_ms(lambda: P.sph_build_pairs(g, st.pos, capacity=pl_cap, ws=ws_pairs),
+                                        reps, torch), "entries": pl_cap},
+        "neighbours_csr": {"ms": median_ms(lambda: P.sph_neighbours(g, st.pos, w.h, col_cap=col_cap, ws=ws_nb),
+                                           reps, torch)},
+    }
+    outs = {}
+    for form in ("fp64", "fp32comp"):
+        o = P.api.new_deriv(n)
+        ms = median_ms(lambda: P.sph_rhs(g, st, w.params, form, out=o, ws=ws_rhs), reps, torch)
+        forms[f"rhs_{form}"] = {"ms": ms, "pairs_per_s": nnz / (ms * 1e-3)}
+        outs[form] = o
+    ms = median_ms(lambda: P.sph_rhs_adjoint(g, st, w.params, cot, ws=ws_adj), reps, torch)
+    forms["adjoint_fp64"] = {"ms": ms, "pairs_per_s": nnz / (ms * 1e-3)}
+    forms["fp32comp_speedup_vs_fp64"] = forms["rhs_fp64"]["ms"] / forms["rhs_fp32comp"]["ms"]
+    fields = ("acc", "drho", "dS", "rho_sum")
+    forms["rhs_fp32comp"]["normwise_error_vs_fp64_gpu"] = {
+        k: float((outs["fp32comp"][k] - outs["fp64"][k]).abs().max() / outs["fp64"][k].abs().max())
+        for k in fields}
+    sample = None
+    if not args.no_cpu_baseline:
+        from oracle import native
+        idx, csr = oracle_targets(w)
+        ref = native.rhs(w.pos, w.vel, w.rho, w.S, w.m, w.param_vector(), targets=idx, csr=csr, want_L=False)
+        it = torch.as_tensor(idx, device="cuda")
+        for form in ("fp64", "fp32comp"):
+            forms[f"rhs_{form}"]["normwise_error_vs_oracle_4096_targets"] = {
+                k: normwise(outs[form][k][..., it].cpu().numpy(), ref[k]) for k in fields}
+        sample = (idx, csr)
+    result = {
+        "ms_per_step": ms_step, "value": 2.0 * nnz / (ms_step * 1e-3), "wall_s": wall,
+        "config": {"workload": w.name, "particles": n, "ordered_pairs_per_rhs": nnz,
+                   "approaching_pair_fraction": f_app, "partners_per_particle": partners,
+                   "pair_list": {"entries": pl_cap, "candidates": cand,
+                                 "true_pairs_fraction": nnz / cand,
+                                 "load_balance_mean_over_max_per_wave": cand / pl_cap},
+                   "skin_over_dx": skin / w.dx, "h_over_dx": 2.4, "cells_per_h": CELLS_PER_H,
+                   "grid_dims": list(dims), "grid_cells": ncells,
+                   "step": "cell build + pair list + partner CSR + FP64 sph_rhs + FP64 sph_rhs_adjoint "
+                           "(random cotangent) on one state"},
+        "roofline": kernel_roofline(kern, nnz, f_app, pl_cap, args.steps, ms_step),
+        "forms": forms,
+        "copy_calibration_bytes": calib,
+    }
+    return result, sample
+
+
+def two_spheres_section(args, w, torch, P, L, full_forms=True):
+    """The two-sphere collision: cell build, list, CSR, 10-step leapfrog (11 FP64 right-
+    hand sides) and its reverse sweep (11 adjoints) for d KE / d (v0, mu, Y0), with the
+    extended forms on the same state."""
+    st = P.ParticleState.from_arrays(w.pos, w.vel, w.rho, w.S, w.m, "cuda")
+    dev = "cuda"
+    n = w.n
+    steps_lf = max(w.steps, 1)
+    # skin of the frozen grid and list: three times the largest displacement of one
+    # untimed trajectory (skin / 2 must cover every particle's movement), at least 0.02 dx
+    g0 = P.sph_build_cells(st.pos, w.h, skin=w.dx, cells_per_h=CELLS_PER_H)
+    f0, _ = P.sph_leapfrog(g0, st, w.params, w.dt, steps_lf, checkpoints=False)
+    L.check(P.workspace_status(f0._ws))
+    dmax = float(((f0.pos - st.pos) ** 2).sum(0).sqrt().max())
+    del g0, f0
+    skin = max(3.0 * dmax, 0.02 * w.dx)
+    lo, hi = P.api.default_box(st.pos, w.h, skin)
+    dims, ncells, _ = L.grid_geometry(lo, hi, w.h, skin, CELLS_PER_H)
+    box = (lo, hi)
+    ws_build = P.workspace(L.SPH_OP_BUILD, n, ncells)
+    ws_nb = P.workspace(L.SPH_OP_NEIGHBOURS, n)
+    ws_rhs = P.workspace(L.SPH_OP_RHS, n)
+    ws_lf = P.workspace(L.SPH_OP_LEAPFROG, n)
+    ws_lfa = P.workspace(L.SPH_OP_LEAPFROG_ADJOINT, n)
+    ws_adj = P.workspace(L.SPH_OP_ADJOINT, n)
+    ws_pairs = P.workspace(L.SPH_OP_PAIRS, n)
+    ck = torch.empty(L.checkpoint_bytes(n, steps_lf) // 8, dtype=torch.float64, device=dev)
+    fin = P.ParticleState(torch.empty_like(st.pos), torch.empty_like(st.vel), torch.empty_like(st.rho),
+                          torch.empty_like(st.S), st.m)
+    cot = {"vel": torch.empty_like(st.vel)}
+    grad = P.api._fields(n, dev)
+    grid = P.sph_build_cells(st.pos, w.h, skin=skin, cells_per_h=CELLS_PER_H, box=box, ws=ws_build)
+    row_ptr, col = P.sph_neighbours(grid, st.pos, w.h, ws=ws_nb)
+    nnz0 = int(row_ptr[-1].item())
+    col_cap = int(col.numel()) + n  # room for pairs formed during the trajectory
+    pl_cap = P.sph_build_pairs(grid, st.pos, ws=ws_pairs)
+
+    def step():
+        g = P.sph_build_cells(st.pos, w.h, skin=skin, cells_per_h=CELLS_PER_H, box=box, ws=ws_build)
+        P.sph_build_pairs(g, st.pos, capacity=pl_cap, ws=ws_pairs)
+        P.sph_neighbours(g, st.pos, w.h, col_cap=col_cap, ws=ws_nb)
+        P.sph_leapfrog(g, st, w.params, w.dt, steps_lf, checkpoints=ck, out=fin, ws=ws_lf)
+        torch.mul(fin.vel, fin.m, out=cot["vel"])  # d KE / d v_final
+        P.sph_leapfrog_adjoint(g, st, w.params, w.dt, steps_lf, ck, cot, ws=ws_lfa, grad=grad)
+
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    rp_end, _ = P.sph_neighbours(grid, fin.pos, w.h, ws=ws_nb)
+    nnz = 0.5 * (nnz0 + int(rp_end[-1].item()))
+    reps = max(args.steps, 3)
+    ms_step = median_ms(step, reps, torch)
     for wsx in (ws_lf, ws_lfa):
         rc = P.workspace_status(wsx)
         if rc != 0:
             raise RuntimeError(f"device flag {rc}")
-
-    # per-form rates on the initial state (median of reps); the right-hand side and the
-    # adjoint read the frozen pair list, the "cells" form sweeps the cell rows instead
-    g = P.sph_build_cells(st.pos, w.h, skin=skin, cells_per_h=CELLS_PER_H, box=(lo, hi), ws=ws_build)
-    forms = {"build_cells": {"ms": median_ms(
-        lambda: P.sph_build_cells(st.pos, w.h, skin=skin, cells_per_h=CELLS_PER_H, box=(lo, hi), ws=ws_build), args.form_reps, torch)}}
-    forms["build_pairs"] = {"ms": median_ms(
-        lambda: P.sph_build_pairs(g, st.pos, capacity=pl_cap, ws=ws_pairs), args.form_reps, torch),
-        "entries": pl_cap}
-    forms["neighbours_csr"] = {"ms": median_ms(
-        lambda: P.sph_neighbours(g, st.pos, w.h, col_cap=col_cap, ws=ws_nb), args.form_reps, torch)}
-    gc = P.sph_build_cells(st.pos, w.h, skin=skin, cells_per_h=CELLS_PER_H, box=(lo, hi))
-    oc = P.api.new_deriv(n)
-    ms = median_ms(lambda: P.sph_rhs(gc, st, w.params, "fp64", out=oc, ws=ws_rhs), args.form_reps, torch)
-    forms["rhs_fp64_cell_sweep"] = {"ms": ms, "pairs_per_s": nnz0 / (ms * 1e-3)}
+    res = {"workload": w.name, "particles": n, "ordered_pairs_per_rhs": nnz, "skin_over_dx": skin / w.dx,
+           "leapfrog_step_ms": ms_step,
+           "leapfrog_step_pairs_per_s": 2 * (steps_lf + 1) * nnz / (ms_step * 1e-3),
+           "leapfrog_step": f"cell build + pair list + partner CSR + {steps_lf}-step leapfrog ({steps_lf + 1} "
+                            f"FP64 right-hand sides) + reverse sweep ({steps_lf + 1} adjoints)"}
+    if not full_forms:
+        return res
+    g = grid
+    fr = args.form_reps
+    forms = {}
     outs = {}
     for form in ("fp64", "fp32comp"):
         o = P.api.new_deriv(n)
-        ms = median_ms(lambda: P.sph_rhs(g, st, w.params, form, out=o, ws=ws_rhs), args.form_reps, torch)
+        ms = median_ms(lambda: P.sph_rhs(g, st, w.params, form, out=o, ws=ws_rhs), fr, torch)
         forms[f"rhs_{form}"] = {"ms": ms, "pairs_per_s": nnz0 / (ms * 1e-3)}
         outs[form] = o
-    fields = {"acc": 3, "drho": 1, "dS": 6, "rho_sum": 1}
-    errs = {}
-    for k in fields:
-        ref = outs["fp64"][k]
-        errs[k] = float((outs["fp32comp"][k] - ref).abs().max() / ref.abs().max())
-    forms["rhs_fp32comp"]["normwise_error_vs_fp64"] = errs
-    # the next rows of the pair loop: energy equation, artificial stress (eps_s 0.2, n 4,
-    # on a copy of the state whose densities are spread by +-0.5 % so that half of the
-    # particles are in tension) and XSPH (0.5), FP64, same list
+    forms["rhs_fp32comp"]["normwise_error_vs_fp64_gpu"] = {
+        k: float((outs["fp32comp"][k] - outs["fp64"][k]).abs().max() / outs["fp64"][k].abs().max())
+        for k in ("acc", "drho", "dS", "rho_sum")}
+    gc = P.sph_build_cells(st.pos, w.h, skin=skin, cells_per_h=CELLS_PER_H, box=box)
+    oc = P.api.new_deriv(n)
+    ms = median_ms(lambda: P.sph_rhs(gc, st, w.params, "fp64", out=oc, ws=ws_rhs), fr, torch)
+    forms["rhs_fp64_cell_sweep"] = {"ms": ms, "pairs_per_s": nnz0 / (ms * 1e-3)}
+    # energy equation, artificial stress (eps_s 0.2, n 4, on a copy whose densities are
+    # spread by +-0.5 % so that half of the particles are in tension) and XSPH (0.5)
     sx = P.ParticleState(st.pos, st.vel, st.rho * (1.0 + 0.005 * (2.0 * torch.rand(
         n, dtype=torch.float64, device=dev, generator=torch.Generator(dev).manual_seed(5)) - 1.0)),
         st.S, st.m)
     px = dict(w.params, eps_s=0.2, n_s=4.0, xsph=0.5)
     ox = P.api.new_deriv(n, extra=True)
-    ms = median_ms(lambda: P.sph_rhs(g, sx, px, "fp64", out=ox, ws=ws_rhs), args.form_reps, torch)
-    forms["rhs_fp64_energy_artstress_xsph"] = {
-        "ms": ms, "pairs_per_s": nnz0 / (ms * 1e-3),
-        "particles_in_tension": int((sx.rho < w.params["rho0"]).sum())}
+    ms = median_ms(lambda: P.sph_rhs(g, sx, px, "fp64", out=ox, ws=ws_rhs), fr, torch)
+    forms["rhs_fp64_energy_artstress_xsph"] = {"ms": ms, "pairs_per_s": nnz0 / (ms * 1e-3),
+                                               "particles_in_tension": int((sx.rho < w.params["rho0"]).sum())}
     ox32 = P.api.new_deriv(n, extra=True)
-    ms = median_ms(lambda: P.sph_rhs(g, sx, px, "fp32comp", out=ox32, ws=ws_rhs), args.form_reps, torch)
+    ms = median_ms(lambda: P.sph_rhs(g, sx, px, "fp32comp", out=ox32, ws=ws_rhs), fr, torch)
     forms["rhs_fp32comp_energy_artstress_xsph"] = {
         "ms": ms, "pairs_per_s": nnz0 / (ms * 1e-3),
-        "normwise_error_vs_fp64": {k: float((ox32[k] - ox[k]).abs().max() / ox[k].abs().max())
-                                   for k in ("acc", "drho", "dS", "du")}}
-    # Tillotson equation of state (aluminium constants) on the same spread densities with
-    # specific internal energies drawn over its cold, partial and full vaporisation ranges
+        "normwise_error_vs_fp64_gpu": {k: float((ox32[k] - ox[k]).abs().max() / ox[k].abs().max())
+                                       for k in ("acc", "drho", "dS", "du")}}
+    # Tillotson (aluminium constants) with u over its cold to vaporised range
     su = P.ParticleState(sx.pos, sx.vel, sx.rho, sx.S, sx.m, 2e7 * torch.rand(
         n, dtype=torch.float64, device=dev, generator=torch.Generator(dev).manual_seed(6)))
     pt = dict(w.params, eos=2.0)
     ot = P.api.new_deriv(n)
-    ms = median_ms(lambda: P.sph_rhs(g, su, pt, "fp64", out=ot, ws=ws_rhs), args.form_reps, torch)
+    ms = median_ms(lambda: P.sph_rhs(g, su, pt, "fp64", out=ot, ws=ws_rhs), fr, torch)
     forms["rhs_fp64_tillotson"] = {"ms": ms, "pairs_per_s": nnz0 / (ms * 1e-3)}
-    # Grady-Kipp damage on the spread densities: damage uniform in [0, 1], flaws of
-    # basalt's Weibull law (k = 1e61 m^-3, m = 16) over the bodies' volume, about
-    # N ln N of them; the damaged stress in the pair loop and the damage rates
+    # Grady-Kipp damage: d uniform in [0, 1], basalt's Weibull flaws over the bodies
     import workloads as W
     fptr, feps = W.flaws(n, float(np.sum(w.m) / w.params["rho0"]), 1e61, 16.0, 7)
     sd = P.ParticleState(sx.pos, sx.vel, sx.rho, sx.S, sx.m, None, torch.rand(
         n, dtype=torch.float64, device=dev, generator=torch.Generator(dev).manual_seed(8)),
         torch.as_tensor(fptr).to(dev), torch.as_tensor(feps).to(dev))
     od = P.api.new_deriv(n, damage=True)
-    ms = median_ms(lambda: P.sph_rhs(g, sd, w.params, "fp64", out=od, ws=ws_rhs), args.form_reps, torch)
+    ms = median_ms(lambda: P.sph_rhs(g, sd, w.params, "fp64", out=od, ws=ws_rhs), fr, torch)
     forms["rhs_fp64_damage"] = {"ms": ms, "pairs_per_s": nnz0 / (ms * 1e-3), "flaws": int(fptr[-1]),
                                 "particles_with_active_flaws": int((od["n_act"] > 0).sum())}
-    # Barnes-Hut monopole self-gravity (section 3.3) on the same bodies, theta = 0.5 (the
-    # paper's bound), smoothing 0.5 dx: tree build and walk in one call (it synchronises
-    # once to size the tree); terms = pseudo-particles and leaves summed over particles
-    mt = st.m
+    cg = {k: torch.randn_like(outs["fp64"][k]) for k in ("acc", "drho", "dS", "rho_sum")}
+    ms = median_ms(lambda: P.sph_rhs_adjoint(g, st, w.params, cg, ws=ws_adj), fr, torch)
+    forms["adjoint_fp64"] = {"ms": ms, "pairs_per_s": nnz0 / (ms * 1e-3)}
+    ms = median_ms(lambda: P.sph_rhs_adjoint(g, su, pt, cg, ws=ws_adj), fr, torch)
+    forms["adjoint_fp64_tillotson"] = {"ms": ms, "pairs_per_s": nnz0 / (ms * 1e-3)}
+    # Barnes-Hut monopole self-gravity (section 3.3), theta = 0.5, smoothing 0.5 dx
     wsg = P.workspace(P._lib.SPH_OP_GRAVITY, n, 0, dev)
-    go = P.sph_gravity(st.pos, mt, 6.674e-11, 0.5, 0.5 * w.dx, count=True, ws=wsg)
+    go = P.sph_gravity(st.pos, st.m, 6.674e-11, 0.5, 0.5 * w.dx, count=True, ws=wsg)
     terms = int(go["count"].to(torch.int64).sum())
-    ms = median_ms(lambda: P.sph_gravity(st.pos, mt, 6.674e-11, 0.5, 0.5 * w.dx, ws=wsg),
-                   args.form_reps, torch)
+    ms = median_ms(lambda: P.sph_gravity(st.pos, st.m, 6.674e-11, 0.5, 0.5 * w.dx, ws=wsg), fr, torch)
     forms["gravity_bh_theta0.5"] = {"ms": ms, "inner_nodes": go["nodes"], "terms": terms,
                                     "terms_per_s": terms / (ms * 1e-3),
                                     "tflops_algorithmic": terms * FLOPS_GRAV_TERM / (ms * 1e-3) / 1e12,
                                     "frac_of_fp64_peak": terms * FLOPS_GRAV_TERM / (ms * 1e-3) / 1e12
                                     / PEAK_FP64_TFLOPS}
-    forms["fp32comp_speedup_vs_fp64"] = forms["rhs_fp64"]["ms"] / forms["rhs_fp32comp"]["ms"]
-    cg = {k: torch.randn_like(outs["fp64"][k]) for k in fields}
-    ms = median_ms(lambda: P.sph_rhs_adjoint(g, st, w.params, cg, ws=ws_adj), args.form_reps, torch)
-    forms["adjoint_fp64"] = {"ms": ms, "pairs_per_s": nnz0 / (ms * 1e-3)}
-    # the adjoint with the Tillotson equation (gradient of u too; cell-sweep pair kernel)
-    ms = median_ms(lambda: P.sph_rhs_adjoint(g, su, pt, cg, ws=ws_adj), args.form_reps, torch)
-    forms["adjoint_fp64_tillotson"] = {"ms": ms, "pairs_per_s": nnz0 / (ms * 1e-3)}
-
-    # dominant kernel of the step
-    dom = max(kern, key=lambda k: kern[k][0])
-    tot_ms, launches = kern[dom]
-    avg_ms = tot_ms / max(launches, 1)
-    fpp = {"pairs_fp64": FLOPS_RHS + FLOPS_RHS_APPROACH * f_app,
-           "adjoint_pairs": FLOPS_ADJ + FLOPS_ADJ_APPROACH * f_app,
-           "adjoint_L": FLOPS_ADJ_L}[dom]
-    achieved = fpp * nnz / (avg_ms * 1e-3) / 1e12
-    kname = {"pairs_fp64": "k_pairs64_list", "adjoint_pairs": "k_adj_pairs_list", "adjoint_L": "k_adj_L_list"}[dom]
-    traffic = None
-    if TRAFFIC and TRAFFIC["kernel"] == kname and TRAFFIC["workload"] == w.name and \
-            TRAFFIC["sources_sha256"] == sources_sha(kname):
-        traffic = TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
-    roofline = {"bound": "alu",
-                "kernel": kname,
-                "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
-                "traffic_unit": "bytes per launch (HBM read + write, counter-scaled)",
-                "traffic_source": TRAFFIC["profile"] if traffic else None,
-                "avg_launch_ms": avg_ms, "launches": launches, "flops_per_pair": fpp,
-                "share_of_step": tot_ms / args.steps / ms_step,
-                "other": {k: {"avg_launch_ms": v[0] / max(v[1], 1), "launches": v[1]} for k, v in kern.items()}}
-    # the gather view of the same launch: partner bytes moved through the L1 per launch
-    # (every padded list entry loads its partner's chunks: 7 + 7 chunks of 16 B for the
-    # adjoint, 8 for the forward), at the kernel's average duration
-    gather_b = {"adjoint_pairs": 224, "pairs_fp64": 128}.get(dom)
-    if gather_b:
-        gb = gather_b * pl_cap
-        roofline["gather"] = {"bytes_per_launch": gb, "achieved_TBps": gb / (avg_ms * 1e-3) / 1e12,
-                              "bytes_per_entry": gather_b, "list_entries": pl_cap}
-
-    result = {
-        "metric": METRIC, "value": pairs_per_step / (ms_step * 1e-3), "unit": UNIT, "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": w.name, "particles": n, "ordered_pairs_per_rhs": nnz,
-                   "ordered_pairs_start_end": [nnz0, nnz1], "skin_over_dx": skin / w.dx,
-                   "approaching_pair_fraction": f_app, "partners_per_particle": partners,
-                   "pair_list": pair_list,
-                   "h_over_dx": 2.4, "cells_per_h": CELLS_PER_H, "leapfrog_steps": steps_lf, "step": step_desc,
-                   "grid_dims": list(dims)},
-        "roofline": roofline,
-        "forms": forms,
-        "copy_calibration_bytes": calib,
-        "wall_s": wall,
-    }
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(w)
         forms["gravity_bh_theta0.5"]["cpu_oracle"] = cpu_gravity_baseline(w)
+    res["forms"] = forms
+    return res
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the multi-GPU "
+                                   "domain decomposition is design only)"}))
+        sys.exit(2)
+    import torch
+    import workloads as W
+    import paper_1604_03290_amd as P
+    from paper_1604_03290_amd import _lib as L
+
+    k = WORKLOADS[args.workload]
+    w = W.config(k)
+    if args.workload == "two_spheres":
+        sec = two_spheres_section(args, w, torch, P, L)
+        result = {"metric": METRIC, "value": sec["leapfrog_step_pairs_per_s"], "unit": UNIT, "n_gpus": 1,
+                  "steps": max(args.steps, 3), "warmup": args.warmup, "ms_per_step": sec["leapfrog_step_ms"],
+                  "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+                  "data": "synthetic", "config": {"workload": w.name, "step": sec["leapfrog_step"]},
+                  "two_spheres": sec}
+        print(json.dumps(result), flush=True)
+        return
+    res, sample = single_state_step(args, w, torch, P, L)
+    result = {
+        "metric": METRIC, "value": res["value"], "unit": UNIT, "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic", "config": res["config"], "roofline": res["roofline"],
+        "forms": res["forms"], "copy_calibration_bytes": res["copy_calibration_bytes"],
+        "wall_s": res["wall_s"],
+    }
+    if sample is not None:
+        result["cpu_baseline"] = cpu_baseline(w, *sample)
+    if not args.no_two_spheres:
+        del w
+        torch.cuda.empty_cache()
+        result["two_spheres_262144"] = two_spheres_section(args, W.config(1), torch, P, L)
     print(json.dumps(result), flush=True)
 
 
