@@ -9,7 +9,10 @@
  *  - Every array pointer is a DEVICE pointer owned by the caller (for example
  *    the data pointer of a contiguous torch tensor).  The library allocates no
  *    device memory and keeps no state between calls; scratch space is passed in
- *    as a caller-owned workspace whose size sph_workspace_bytes() returns.
+ *    as a caller-owned workspace whose size sph_workspace_bytes() returns.  Two
+ *    exceptions: sph_rhs_noalloc works in a static device array of the library
+ *    (for callers that cannot allocate), and the diagnostic timing table
+ *    (sph_timing_*, off by default) keeps HIP events between calls.
  *  - Particle data are structure-of-arrays in double precision, one array per
  *    component, as in the paper's implementation section (section 3.5):
  *    positions x, y, z; velocities vx, vy, vz; density rho; mass m; deviatoric
@@ -312,6 +315,26 @@ int sph_neighbours(const sph_grid *grid, const double *x, const double *y, const
  * stress; damage outside [0, 1]; flaw offsets out of order). */
 int sph_rhs(const sph_grid *grid, const sph_state *state, const sph_params *params,
             int precision, const sph_deriv *out, void *ws, size_t ws_bytes, void *stream);
+
+/* Largest particle count sph_rhs_noalloc serves. */
+#define SPH_NOALLOC_MAX_N 262144
+
+/* sph_rhs without a workspace, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same outputs as sph_rhs (same kernels, bit for bit); its scratch is a
+ * static device array of the library sized for SPH_NOALLOC_MAX_N particles (about
+ * 52 MiB), which every device the library runs on holds until the process ends.  The
+ * call allocates nothing (no hipMalloc, hipFree or allocating library routine); the
+ * first call on a device looks up that device's copy of the array.
+ *   status  device int32 or NULL: receives the call's device flag (SPH_OK, or
+ *           SPH_ERR_STALE_GRID / SPH_ERR_DOMAIN as sph_workspace_status reports them
+ *           for sph_rhs), written on the stream after the right-hand side
+ * Every call on one device shares that device's scratch, and each call overwrites
+ * it, so calls that overlap on one device (on different streams or threads) race:
+ * serialise them.  Errors: as sph_rhs, and CAPACITY when grid->n exceeds
+ * SPH_NOALLOC_MAX_N. */
+int sph_rhs_noalloc(const sph_grid *grid, const sph_state *state, const sph_params *params,
+                    int precision, const sph_deriv *out, int32_t *status, void *stream);
 
 /* Vector-Jacobian product of sph_rhs in double precision: given
  * cotangents of (a, drho, dS, rho_sum) returns the gradients with respect to

@@ -20,6 +20,7 @@ from .api import (  # noqa: F401
     sph_neighbours,
     sph_rhs,
     sph_rhs_adjoint,
+    sph_rhs_noalloc,
     workspace,
     workspace_status,
 )

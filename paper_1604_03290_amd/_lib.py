@@ -30,6 +30,7 @@ SPH_FP32_COMP = 1
 
 SPH_OP_BUILD, SPH_OP_NEIGHBOURS, SPH_OP_RHS, SPH_OP_ADJOINT = 0, 1, 2, 3
 SPH_OP_LEAPFROG, SPH_OP_LEAPFROG_ADJOINT, SPH_OP_PAIRS, SPH_OP_GRAVITY = 4, 5, 6, 7
+SPH_NOALLOC_MAX_N = 262144  # include/sph.h
 
 _NAMES = {0: "SPH_OK", -1: "SPH_ERR_INVALID_ARG", -2: "SPH_ERR_CAPACITY", -3: "SPH_ERR_WORKSPACE",
           -4: "SPH_ERR_HIP", -5: "SPH_ERR_DOMAIN", -6: "SPH_ERR_NOT_IMPLEMENTED",
@@ -120,6 +121,7 @@ def lib():
                                      P(C.c_int64), _pd, C.c_size_t, _vp]
         L.sph_rhs.argtypes = [P(Grid), P(State), P(Params), C.c_int, P(Deriv), _pd, C.c_size_t,
                               _vp]
+        L.sph_rhs_noalloc.argtypes = [P(Grid), P(State), P(Params), C.c_int, P(Deriv), _pd, _vp]
         L.sph_gravity.argtypes = [_pd, _pd, _pd, _pd, C.c_int64, C.c_double, C.c_double,
                                   C.c_double, _pd, _pd, _pd, _pd, C.c_int64, P(C.c_int64), _pd,
                                   C.c_size_t, _vp]

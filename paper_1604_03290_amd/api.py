@@ -340,6 +340,23 @@ def sph_rhs(grid: CellGrid, state: ParticleState, params, precision="fp64", out=
     return out
 
 
+def sph_rhs_noalloc(grid: CellGrid, state: ParticleState, params, precision="fp64",
+                    out=None, status: torch.Tensor | None = None) -> dict:
+    """sph_rhs on the library's static scratch instead of a workspace (C: sph_rhs_noalloc);
+    at most SPH_NOALLOC_MAX_N particles.  ``status`` (int32 device tensor of one element,
+    optional) receives the device flag.  Calls that overlap on one GPU race."""
+    n = state.n
+    if out is None:
+        out = new_deriv(n, state.rho.device)
+    if status is not None:
+        _dev(status, torch.int32)
+    cs = state.c_state()
+    d = deriv_struct(out)
+    L.check(L.lib().sph_rhs_noalloc(C.byref(grid.c), C.byref(cs), C.byref(params_struct(params)),
+                                    precision_code(precision), C.byref(d), _ptr(status), _stream()))
+    return out
+
+
 def sph_rhs_adjoint(grid: CellGrid, state: ParticleState, params, cot: dict,
                     ws: torch.Tensor | None = None) -> dict:
     """Vector-Jacobian product of sph_rhs (C: sph_rhs_adjoint).  ``cot`` has keys of

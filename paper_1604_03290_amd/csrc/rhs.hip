@@ -16,6 +16,7 @@
 // W'(r)/r = 6 s/h^5 f(q) with w = 1 - 6q^2 + 6q^3, f = 3q - 2 for q < 1/2 and
 // w = 2 (1-q)^3, f = -(1-q)^2 / q for 1/2 <= q < 1, so grad_a W_ab =
 // (W'/r)(x_a - x_b) stays finite as r -> 0.
+#include <mutex>
 #include <type_traits>
 
 #include "common.hpp"
@@ -378,7 +379,7 @@ double *rhs_rec_of(Carve c, int64_t n) { return c.take<double>((size_t)n * kRec)
 
 int rhs_launch(const sph_grid *grid, const sph_state *state, const sph_params *params,
                int precision, const sph_deriv *out, Carve &c, hipStream_t s, double *L_out,
-               bool slot_state, bool rec_ready) {
+               bool slot_state, bool rec_ready, bool timed) {
     const int64_t n = grid->n;
     GridDev g = grid_dev(grid);
     if (slot_state) g.io = nullptr;
@@ -394,7 +395,7 @@ int rhs_launch(const sph_grid *grid, const sph_state *state, const sph_params *p
     if (!rec_ready && (rc = prepass_launch(g, st, n, k, rec, c.status(), s, &od))) return rc;
     const bool ext = k.eps_s > 0.0 || od.du || od.dx || k.eos != 0;
     if (precision == SPH_FP64) {
-        TimedRegion t("pairs_fp64", s);
+        TimedRegion t(timed ? "pairs_fp64" : nullptr, s);
         const dim3 gb(blocks_for(n)), tb(kBlock);
         auto launch = [&](auto corr, auto extra) {
             constexpr bool C = decltype(corr)::value, E = decltype(extra)::value;
@@ -417,7 +418,7 @@ int rhs_launch(const sph_grid *grid, const sph_state *state, const sph_params *p
     } else {
         k_narrow<<<blocks_for(n), kBlock, 0, s>>>(rec, n, r32);
         SPH_LAUNCHED();
-        TimedRegion t("pairs_fp32comp", s);
+        TimedRegion t(timed ? "pairs_fp32comp" : nullptr, s);
         const dim3 gb(blocks_for(n)), tb(kBlock);
         auto launch = [&](auto corr, auto extra) {
             constexpr bool C = decltype(corr)::value, E = decltype(extra)::value;
@@ -441,9 +442,78 @@ int rhs_launch(const sph_grid *grid, const sph_state *state, const sph_params *p
     return SPH_OK;
 }
 
+// ------------------------------------------------ the allocation-free variant --
+// Scratch of sph_rhs_noalloc: the workspace of sph_rhs for up to kNoallocMaxN
+// particles (status word, FP64 operand records, FP32 records), held by every device
+// the library runs on until the process ends.
+constexpr int64_t kNoallocMaxN = SPH_NOALLOC_MAX_N;
+constexpr size_t kNoallocBytes =
+    kAlign + (size_t)kNoallocMaxN * kRec * sizeof(double) + (size_t)kNoallocMaxN * kRec32 * sizeof(float);
+static_assert(kNoallocMaxN % 64 == 0, "record arrays stay 256-byte aligned");
+__device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+namespace {
+
+// Device address of this device's copy of `scratch` (the array's name is only a
+// host-side stand-in in host code), looked up once per device with that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_of_current_device(void **out) {
+    int dev = -1;
+    SPH_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(SPH_ERR_INVALID_ARG, "device %d beyond the %d the library tracks", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        SPH_HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(SPH_ERR_HIP, "hipGetSymbolAddress returned no address for the scratch");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SPH_OK;
+}
+
+__global__ void k_copy_status(const int32_t *__restrict__ from, int32_t *__restrict__ to) { *to = *from; }
+
+}  // namespace
+
 }  // namespace sph
 
 using namespace sph;
+
+extern "C" int sph_rhs_noalloc(const sph_grid *grid, const sph_state *state,
+                               const sph_params *params, int precision, const sph_deriv *out,
+                               int32_t *status, void *stream) {
+    clear_error();
+    int rc;
+    if ((rc = check_grid(grid)) || (rc = check_state(grid, state)) ||
+        (rc = check_params(grid, params)) || (rc = check_deriv(out)) ||
+        (rc = check_damage(state, params, out)))
+        return rc;
+    if (precision != SPH_FP64 && precision != SPH_FP32_COMP)
+        return fail(SPH_ERR_INVALID_ARG, "unknown precision %d", precision);
+    if (grid->n > kNoallocMaxN)
+        return fail(SPH_ERR_CAPACITY, "sph_rhs_noalloc serves at most %lld particles (%lld given)",
+                    (long long)kNoallocMaxN, (long long)grid->n);
+    if (rhs_ws_bytes(grid->n) > kNoallocBytes)
+        return fail(SPH_ERR_CAPACITY, "scratch smaller than the workspace of %lld particles",
+                    (long long)grid->n);
+    void *ws = nullptr;
+    if ((rc = scratch_of_current_device(&ws))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = clear_status(ws, s))) return rc;
+    Carve c(ws);
+    if ((rc = rhs_launch(grid, state, params, precision, out, c, s, nullptr, false, false, false)))
+        return rc;
+    if (status) {
+        k_copy_status<<<1, 1, 0, s>>>(reinterpret_cast<const int32_t *>(ws), status);
+        SPH_LAUNCHED();
+    }
+    return SPH_OK;
+}
 
 extern "C" int sph_rhs(const sph_grid *grid, const sph_state *state, const sph_params *params,
                        int precision, const sph_deriv *out, void *ws, size_t ws_bytes,

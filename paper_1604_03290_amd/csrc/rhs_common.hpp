@@ -844,9 +844,11 @@ int check_deriv(const sph_deriv *o);
 // slot_state: the state and output arrays are in the grid's slot order.
 // rec_ready: the operand records (the first carve, rhs_rec_of) already hold the
 // state's records, so the prepass is skipped.
+// timed: bracket the pair kernel for the diagnostic timing table when it is enabled.
 int rhs_launch(const sph_grid *grid, const sph_state *state, const sph_params *params,
                int precision, const sph_deriv *out, Carve &c, hipStream_t s,
-               double *L_out = nullptr, bool slot_state = false, bool rec_ready = false);
+               double *L_out = nullptr, bool slot_state = false, bool rec_ready = false,
+               bool timed = true);
 // where rhs_launch on a carve that starts like c keeps its operand records
 double *rhs_rec_of(Carve c, int64_t n);
 size_t rhs_ws_bytes(int64_t n);

@@ -34,7 +34,7 @@ Slot &slot(const char *name) {
 bool timing_on() { return g_on; }
 
 TimedRegion::TimedRegion(const char *name, hipStream_t s) : stream(s) {
-    if (!g_on) return;
+    if (!g_on || !name) return;
     std::lock_guard<std::mutex> lk(g_mu);
     Slot &sl = slot(name);
     if (sl.used == sl.pool.size()) {

@@ -8,7 +8,7 @@ namespace sph {
 bool timing_on();
 
 // Records a start event at construction and a stop event at destruction on
-// the given stream, when timing is enabled.
+// the given stream, when timing is enabled (a null name records nothing).
 struct TimedRegion {
     hipStream_t stream;
     hipEvent_t start = nullptr, stop = nullptr;

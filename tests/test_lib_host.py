@@ -140,3 +140,16 @@ def test_rhs_validation_state_and_precision():
     d.ax = 0
     assert lib.sph_rhs(C.byref(g), C.byref(s), C.byref(pr), 0, C.byref(d), ws, 1 << 40, None) == L.SPH_ERR_INVALID_ARG
 
+
+def test_noalloc_rejects_sizes_beyond_its_scratch():
+    # host-side checks of sph_rhs_noalloc run before any device work
+    lib = L.lib()
+    pr = L.Params(*GOOD.values())
+    n = L.SPH_NOALLOC_MAX_N + 1
+    g, s, d = _fake_grid(n), _fake_state(n), _fake_deriv()
+    rc = lib.sph_rhs_noalloc(C.byref(g), C.byref(s), C.byref(pr), 0, C.byref(d), None, None)
+    assert rc == L.SPH_ERR_CAPACITY
+    assert "262144" in lib.sph_last_error().decode()
+    g, s = _fake_grid(10), _fake_state(10)
+    assert lib.sph_rhs_noalloc(C.byref(g), C.byref(s), C.byref(pr), 5, C.byref(d), None, None) == L.SPH_ERR_INVALID_ARG
+    assert lib.sph_rhs_noalloc(None, C.byref(s), C.byref(pr), 0, C.byref(d), None, None) == L.SPH_ERR_INVALID_ARG
