@@ -95,6 +95,11 @@ def sources_sha(kernel):
 HIST_EDGES = [0, 10, 20, 30, 40, 50, 60, 80, 100, 150, 200, 250, 300, 400, 100000]
 
 
+def log(msg):
+    """Progress of the run, one line per stage, on stderr (stdout carries only the JSON line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -284,10 +289,12 @@ def single_state_step(args, w, torch, P, L):
         holder["grad"] = P.sph_rhs_adjoint(g, st, w.params, cot, ws=ws_adj)
         holder["g"] = g
 
+    log(f"{w.name}: {nnz} ordered pairs, list of {pl_cap} entries; warm-up")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     calib = copy_calibration(torch)
+    log(f"{w.name}: timing {args.steps} steps")
     L.timing_reset()
     L.timing_enable(True)
     torch.cuda.synchronize()
@@ -307,6 +314,7 @@ def single_state_step(args, w, torch, P, L):
         rc = P.workspace_status(wsx)
         if rc != 0:
             raise RuntimeError(f"device flag {rc}")
+    log(f"{w.name}: {ms_step:.3f} ms per step; forms")
     g = holder["g"]
     reps = args.form_reps
     forms = {
@@ -333,6 +341,7 @@ def single_state_step(args, w, torch, P, L):
     sample = None
     if not args.no_cpu_baseline:
         from oracle import native
+        log(f"{w.name}: oracle on 4,096 targets")
         idx, csr = oracle_targets(w)
         ref = native.rhs(w.pos, w.vel, w.rho, w.S, w.m, w.param_vector(), targets=idx, csr=csr, want_L=False)
         it = torch.as_tensor(idx, device="cuda")
@@ -503,6 +512,7 @@ def main():
     from paper_1604_03290_amd import _lib as L
 
     k = WORKLOADS[args.workload]
+    log(f"generating workload {args.workload}")
     w = W.config(k)
     if args.workload == "two_spheres":
         sec = two_spheres_section(args, w, torch, P, L)
@@ -523,10 +533,12 @@ def main():
         "wall_s": res["wall_s"],
     }
     if sample is not None:
+        log("cpu baseline")
         result["cpu_baseline"] = cpu_baseline(w, *sample)
     if not args.no_two_spheres:
         del w
         torch.cuda.empty_cache()
+        log("two-sphere collision section")
         result["two_spheres_262144"] = two_spheres_section(args, W.config(1), torch, P, L)
     print(json.dumps(result), flush=True)
 

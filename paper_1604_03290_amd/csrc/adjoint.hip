@@ -145,16 +145,21 @@ __global__ __launch_bounds__(kBlock) void k_adj_L_list(GridDev g, int64_t n, Con
     double M[6] = {0, 0, 0, 0, 0, 0};
     const char *recs = reinterpret_cast<const char *>(rec);
     const int32_t *row = g.pl_slot + base + __lane_id();
-    int e0 = steps > 0 ? row[0] : 0;
+    // one step ahead, as in the pair kernels
+    if (steps > 0) gather_dma4(recs, kRec * 8, row[0], buf);
+    int nxt = steps > 1 ? row[64] : 0;
     for (int j = 0; j < steps; ++j) {
-        gather_dma4(recs, kRec * 8, e0, buf);
-        if (j + 1 < steps) e0 = row[(int64_t)(j + 1) << 6];
+        wait_vm();
+        const double2 b0 = dma4_chunk(buf, 0), b1 = dma4_chunk(buf, 1), b2 = dma4_chunk(buf, 2),
+                      b3 = dma4_chunk(buf, 3);
         wave_sync();
+        if (j + 1 < steps) {
+            gather_dma4(recs, kRec * 8, nxt, buf);
+            if (j + 2 < steps) nxt = row[(int64_t)(j + 2) << 6];
+        }
         if (j < cnt) {
-            const double2 b0 = dma4_chunk(buf, 0), b1 = dma4_chunk(buf, 1);
             const double d2 = dist2_exact(xa, ya, za, b0.x, b0.y, b1.x);
             if (d2 < k.h2) {
-                const double2 b2 = dma4_chunk(buf, 2), b3 = dma4_chunk(buf, 3);
                 const KernelPieces kp = kernel_pieces(k, d2, rsqrt64(d2));
                 const double F = k.Fn * kp.f;
                 const double gx = F * (xa - b0.x), gy = F * (ya - b0.y), gz = F * (za - b1.x);
@@ -166,7 +171,6 @@ __global__ __launch_bounds__(kBlock) void k_adj_L_list(GridDev g, int64_t n, Con
                 if (kCorr) moment_add(M, V, F, xa - b0.x, ya - b0.y, za - b1.x);
             }
         }
-        wave_sync();
     }
     if (!act) return;
 #pragma unroll
@@ -552,35 +556,47 @@ __global__ __launch_bounds__(64) void k_adj_pairs_list(GridDev g, int64_t n, Con
         const char *rf = reinterpret_cast<const char *>(rec);
         const char *ra = reinterpret_cast<const char *>(ad.arec);
         const int32_t *row = g.pl_slot + base + __lane_id();
-        int e0 = steps > 0 ? row[0] : 0;
+        // One step ahead: the gathers of step j + 1 are in flight while step j is
+        // evaluated.  Each lane reads its step-j chunks into registers, the wavefront
+        // syncs, and only then are the buffers refilled.
+        auto gather = [&](int e) {
+            if constexpr (kF == 8)
+                gather_dma8(rf, kRec * 8, e, bf);
+            else
+                gather_dma<7>(rf, kRec * 8, e, bf);
+            gather_dma<7>(ra, kAdj * 8, e, ba);
+        };
+        int cur = steps > 0 ? row[0] : 0;  // this lane's partner slot of step j
+        if (steps > 0) gather(cur);
+        int nxt = steps > 1 ? row[64] : 0;
         for (int j = 0; j < steps; ++j) {
-            const int cur = e0;  // this lane's partner slot of step j
-            {
-                if constexpr (kF == 8)
-                    gather_dma8(rf, kRec * 8, e0, bf);
-                else
-                    gather_dma<7>(rf, kRec * 8, e0, bf);
-                gather_dma<7>(ra, kAdj * 8, e0, ba);
-                if (j + 1 < steps) e0 = row[(int64_t)(j + 1) << 6];
-            }
+            wait_vm();
+            const double2 b0 = fchunk(0), b1 = fchunk(1), b2 = fchunk(2), b3 = fchunk(3),
+                          b4 = fchunk(4), b5 = fchunk(5), b6 = fchunk(6);
+            const double cb = kF == 8 ? fchunk(7).y : 0.0;
+            const double2 q0 = dma_chunk<7>(ba, 0), q1 = dma_chunk<7>(ba, 1),
+                          q2 = dma_chunk<7>(ba, 2), q3 = dma_chunk<7>(ba, 3),
+                          q4 = dma_chunk<7>(ba, 4), q5 = dma_chunk<7>(ba, 5),
+                          q6 = dma_chunk<7>(ba, 6);
             wave_sync();
+            const int mine = cur;
+            if (j + 1 < steps) {
+                gather(nxt);
+                cur = nxt;
+                if (j + 2 < steps) nxt = row[(int64_t)(j + 2) << 6];
+            }
             if (j < cnt) {
-                const double2 b0 = fchunk(0), b1 = fchunk(1);
                 const double d2 = dist2_exact(o.xc, o.yc, o.zc, b0.x, b0.y, b1.x);
                 double xb[4] = {0, 0, 0, 0};
                 if constexpr (kXC) {
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) xb[i] = ad.ext[i][cur];
+                    for (int i = 0; i < 4; ++i) xb[i] = ad.ext[i][mine];
                 }
                 if (d2 < k.h2)
-                    adj_pair<false, kEos, kAS, kXC>(k, o, d2, b0, b1, fchunk(2), fchunk(3),
-                             fchunk(4), fchunk(5), fchunk(6),
-                             dma_chunk<7>(ba, 0), dma_chunk<7>(ba, 1), dma_chunk<7>(ba, 2),
-                             dma_chunk<7>(ba, 3), dma_chunk<7>(ba, 4), dma_chunk<7>(ba, 5),
-                             dma_chunk<7>(ba, 6), acc, nullptr, nullptr, xo, xb,
-                             kF == 8 ? fchunk(7).y : 0.0);
+                    adj_pair<false, kEos, kAS, kXC>(k, o, d2, b0, b1, b2, b3, b4, b5, b6, q0, q1,
+                                                    q2, q3, q4, q5, q6, acc, nullptr, nullptr, xo,
+                                                    xb, cb);
             }
-            wave_sync();
         }
         if constexpr (kXC) {  // dx/dt = v + ...
             acc.gvx += xo[1];

@@ -136,18 +136,24 @@ __global__ __launch_bounds__(kBlock) void k_pairs64_list(GridDev g, int64_t n, C
     const bool tens_a = kExt && signbit(c_a);
     const char *recs = reinterpret_cast<const char *>(rec);
     const int32_t *row = g.pl_slot + base + __lane_id();
-    int e0 = steps > 0 ? row[0] : 0;
+    // One step ahead: each lane reads its step-j record into registers, the wavefront
+    // syncs, the gathers of step j + 1 are issued, and step j is evaluated while
+    // they are in flight.
+    if (steps > 0) gather_dma8(recs, kRec * 8, row[0], buf);
+    int nxt = steps > 1 ? row[64] : 0;
     for (int j = 0; j < steps; ++j) {
-        gather_dma8(recs, kRec * 8, e0, buf);
-        if (j + 1 < steps) e0 = row[(int64_t)(j + 1) << 6];
+        wait_vm();
+        const double2 b0 = dma8_chunk(buf, 0), b1 = dma8_chunk(buf, 1), b2 = dma8_chunk(buf, 2),
+                      b3 = dma8_chunk(buf, 3), b4 = dma8_chunk(buf, 4), b5 = dma8_chunk(buf, 5),
+                      b6 = dma8_chunk(buf, 6), b7 = dma8_chunk(buf, 7);
         wave_sync();
+        if (j + 1 < steps) {
+            gather_dma8(recs, kRec * 8, nxt, buf);
+            if (j + 2 < steps) nxt = row[(int64_t)(j + 2) << 6];
+        }
         if (j < cnt) {
-            const double2 b0 = dma8_chunk(buf, 0), b1 = dma8_chunk(buf, 1);
             const double d2 = dist2_exact(xa, ya, za, b0.x, b0.y, b1.x);
             if (d2 < k.h2) {
-                const double2 b2 = dma8_chunk(buf, 2), b3 = dma8_chunk(buf, 3);
-                const double2 b4 = dma8_chunk(buf, 4), b5 = dma8_chunk(buf, 5);
-                const double2 b6 = dma8_chunk(buf, 6), b7 = dma8_chunk(buf, 7);
                 const double Tb[6] = {b4.x, b4.y, b5.x, b5.y, b6.x, b6.y};
                 pair64<kCorr, kExt>(k, d2, xa - b0.x, ya - b0.y, za - b1.x, b1.y - vxa, b2.x - vya,
                                     b2.y - vza, rho_a, b3.x, p4.x + b4.x, p4.y + b4.y, p5.x + b5.x,
@@ -155,7 +161,6 @@ __global__ __launch_bounds__(kBlock) void k_pairs64_list(GridDev g, int64_t n, C
                                     tens_a, c_a, b7.y);
             }
         }
-        wave_sync();
     }
     if (!act) return;
     postpass(k, io_index(g, s), rho_a, acc.L, acc.ax, acc.ay, acc.az, acc.rs, st, out,
@@ -278,18 +283,22 @@ __global__ __launch_bounds__(kBlock) void k_pairs32_list(GridDev g, int64_t n, C
     Acc32 acc;
     const char *recs = reinterpret_cast<const char *>(r32);
     const int32_t *row = g.pl_slot + base + __lane_id();
-    int e0 = steps > 0 ? row[0] : 0;
+    // one step ahead, as in the FP64 kernel
+    if (steps > 0) gather_dma<5>(recs, kRec32Bytes, row[0], buf);
+    int nxt = steps > 1 ? row[64] : 0;
     for (int j = 0; j < steps; ++j) {
-        gather_dma<5>(recs, kRec32Bytes, e0, buf);
-        if (j + 1 < steps) e0 = row[(int64_t)(j + 1) << 6];
+        wait_vm();
+        const Src32 b = src32(dma_chunk<5>(buf, 0), dma_chunk<5>(buf, 1), dma_chunk<5>(buf, 2),
+                              dma_chunk<5>(buf, 3), dma_chunk<5>(buf, 4));
         wave_sync();
+        if (j + 1 < steps) {
+            gather_dma<5>(recs, kRec32Bytes, nxt, buf);
+            if (j + 2 < steps) nxt = row[(int64_t)(j + 2) << 6];
+        }
         if (j < cnt) {
-            const Src32 b = src32(dma_chunk<5>(buf, 0), dma_chunk<5>(buf, 1), dma_chunk<5>(buf, 2),
-                                  dma_chunk<5>(buf, 3), dma_chunk<5>(buf, 4));
             const double d2 = dist2_exact(a.x, a.y, a.z, b.x, b.y, b.z);
             if (d2 < k.h2) pair32_of<kCorr, kExt>(kf, a, b, d2, acc);
         }
-        wave_sync();
     }
     if (!act) return;
     const double2 p3 = rec2(rec, s)[3], p7 = rec2(rec, s)[7];

@@ -143,6 +143,10 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// Waits until every vector-memory load of the wavefront has completed (s_waitcnt
+// vmcnt(0), other counters untouched): the LDS-direct gathers of a step have landed.
+__device__ inline void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // Coalesced gather of the first N 16-byte chunks of one partner record per lane
 // into the wavefront's LDS buffer (64 N chunks).  Each lane holds its list entry of
 // the step (one coalesced load by the caller); lane shuffles hand the entries to
