@@ -122,18 +122,22 @@ __global__ __launch_bounds__(kBlock) void k_adj_L(GridDev g, int64_t n, Consts k
 }
 
 // same over the frozen pair list with cooperative gathers of the partners' first
-// four chunks (position, velocity, density, V: 64 bytes)
+// four chunks (position, velocity, density, V: 64 bytes), kSplit wavefronts per block
+// of 64 slots as in the forward list kernels
 template <bool kCorr>
-__global__ __launch_bounds__(kBlock) void k_adj_L_list(GridDev g, int64_t n, Consts k,
-                                                       const double *__restrict__ rec, AdjRec ad) {
-    __shared__ double2 lbuf[kBlock / 64][64 * 4];
-    double2 *buf = lbuf[threadIdx.x >> 6];
-    const int64_t s = xcd_block(gridDim.x) * kBlock + threadIdx.x;
-    const int64_t w0 = s - __lane_id();
-    if (w0 >= n) return;
+__global__ __launch_bounds__(64 * kSplit) void k_adj_L_list(GridDev g, int64_t n, Consts k,
+                                                            const double *__restrict__ rec,
+                                                            AdjRec ad) {
+    __shared__ double2 lbuf[kSplit][64 * 4];
+    const int q = threadIdx.x >> 6;
+    double2 *buf = lbuf[q];
+    const int64_t w = xcd_block(gridDim.x);
+    const int64_t w0 = w * 64;
+    if (w0 >= n) return;  // whole workgroup past the end
+    const int64_t s = w0 + __lane_id();
     const bool act = s < n;
-    const int64_t base = g.pl_block[w0 >> 6];
-    const int steps = (int)((g.pl_block[(w0 >> 6) + 1] - base) >> 6);
+    const int64_t base = g.pl_block[w];
+    const int steps = (int)((g.pl_block[w + 1] - base) >> 6);
     const int cnt = act ? g.pl_count[s] : 0;
     double2 p0 = make_double2(0, 0), p1 = p0, p2 = p0;
     if (act) {
@@ -141,21 +145,23 @@ __global__ __launch_bounds__(kBlock) void k_adj_L_list(GridDev g, int64_t n, Con
         p0 = ra[0]; p1 = ra[1]; p2 = ra[2];
     }
     const double xa = p0.x, ya = p0.y, za = p1.x, vxa = p1.y, vya = p2.x, vza = p2.y;
-    double L[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    double M[6] = {0, 0, 0, 0, 0, 0};
+    double v[kCorr ? 15 : 9];
+#pragma unroll
+    for (int i = 0; i < (kCorr ? 15 : 9); ++i) v[i] = 0.0;
+    double *L = v, *M = v + 9;  // M: the moment matrix (kCorr)
     const char *recs = reinterpret_cast<const char *>(rec);
     const int32_t *row = g.pl_slot + base + __lane_id();
     // one step ahead, as in the pair kernels
-    if (steps > 0) gather_dma4(recs, kRec * 8, row[0], buf);
-    int nxt = steps > 1 ? row[64] : 0;
-    for (int j = 0; j < steps; ++j) {
+    if (q < steps) gather_dma4(recs, kRec * 8, row[(int64_t)q << 6], buf);
+    int nxt = q + kSplit < steps ? row[(int64_t)(q + kSplit) << 6] : 0;
+    for (int j = q; j < steps; j += kSplit) {
         wait_vm();
         const double2 b0 = dma4_chunk(buf, 0), b1 = dma4_chunk(buf, 1), b2 = dma4_chunk(buf, 2),
                       b3 = dma4_chunk(buf, 3);
         wave_sync();
-        if (j + 1 < steps) {
+        if (j + kSplit < steps) {
             gather_dma4(recs, kRec * 8, nxt, buf);
-            if (j + 2 < steps) nxt = row[(int64_t)(j + 2) << 6];
+            if (j + 2 * kSplit < steps) nxt = row[(int64_t)(j + 2 * kSplit) << 6];
         }
         if (j < cnt) {
             const double d2 = dist2_exact(xa, ya, za, b0.x, b0.y, b1.x);
@@ -172,7 +178,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_L_list(GridDev g, int64_t n, Con
             }
         }
     }
-    if (!act) return;
+    fold_waves<kSplit, kSplit * 64 * 4 * 2>(v, reinterpret_cast<double *>(lbuf));
+    if (q != 0 || !act) return;
 #pragma unroll
     for (int i = 0; i < 9; ++i) ad.L[i][s] = L[i];
     if (kCorr) {
@@ -218,6 +225,20 @@ struct AdjAcc {
     double gT[6] = {0, 0, 0, 0, 0, 0};
     double gc = 0;  // cotangent of the particle's sound speed (Murnaghan)
 };
+
+// The sums of the P wavefronts of the list kernel's workgroup added into wavefront 0
+// (fold_waves, in wavefront order).
+template <int P, int Cap>
+__device__ inline void fold_adj(AdjAcc &a, double *scratch) {
+    double v[15] = {a.gx, a.gy, a.gz, a.gvx, a.gvy, a.gvz, a.grho, a.gV,
+                    a.gT[0], a.gT[1], a.gT[2], a.gT[3], a.gT[4], a.gT[5], a.gc};
+    fold_waves<P, Cap>(v, scratch);
+    a.gx = v[0]; a.gy = v[1]; a.gz = v[2]; a.gvx = v[3]; a.gvy = v[4]; a.gvz = v[5];
+    a.grho = v[6]; a.gV = v[7];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) a.gT[i] = v[8 + i];
+    a.gc = v[14];
+}
 
 // Own data of particle c in the pair stage.
 struct AdjOwn {
@@ -524,91 +545,96 @@ __global__ __launch_bounds__(kBlock) void k_adj_pairs(GridDev g, int64_t n, Cons
     if (threadIdx.x == 0) put(ad.part_y0, blockIdx.x, tot, ad.add_parts);
 }
 
-// the same over the frozen pair list, one wavefront per block: the first seven
-// chunks of each partner's two records gathered cooperatively (with Tillotson all
-// eight of the forward record, whose last holds the partner's signed sound speed);
-// Y0 sums per wavefront.  With the du and dx/dt cotangents each lane loads its own
-// partner's four (one list entry per lane and step)
+// the same over the frozen pair list: a workgroup of kSplitAdj wavefronts takes one
+// block of 64 slots, wavefront q evaluating steps q, q + kSplitAdj, ... (the first seven
+// chunks of each partner's two records gathered cooperatively; with Tillotson all eight
+// of the forward record, whose last holds the partner's signed sound speed); the
+// partial sums are folded into wavefront 0, which runs the pre stage and the Y0 sum.
+// With the du and dx/dt cotangents each lane loads its own partner's four (one list
+// entry per lane and step)
 template <int kEos, bool kAS, bool kXC = false>
-__global__ __launch_bounds__(64) void k_adj_pairs_list(GridDev g, int64_t n, Consts k,
-                                                       const double *__restrict__ rec,
-                                                       StateDev st, AdjRec ad, GradDev out) {
+__global__ __launch_bounds__(64 * kSplitAdj) void k_adj_pairs_list(GridDev g, int64_t n, Consts k,
+                                                                   const double *__restrict__ rec,
+                                                                   StateDev st, AdjRec ad,
+                                                                   GradDev out) {
     constexpr int kF = kEos == 2 ? 8 : 7;  // forward-record chunks gathered
-    __shared__ double2 bf[64 * kF];
-    __shared__ double2 ba[64 * 7];
+    __shared__ double2 lbuf[kSplitAdj][64 * (kF + 7)];
+    const int q = threadIdx.x >> 6;
+    double2 *bf = lbuf[q];
+    double2 *ba = bf + 64 * kF;
     auto fchunk = [&](int c) { return kF == 8 ? dma8_chunk(bf, c) : dma_chunk<7>(bf, c); };
     const int64_t w = xcd_block(gridDim.x);
     const int64_t w0 = w * 64;
-    const int64_t s = w0 + threadIdx.x;
-    double y0_part = 0.0;
-    if (w0 < n) {
-        const bool act = s < n;
-        const int64_t base = g.pl_block[w];
-        const int steps = (int)((g.pl_block[w + 1] - base) >> 6);
-        const int cnt = act ? g.pl_count[s] : 0;
-        const AdjOwn o = adj_own(rec, ad, act ? s : w0);
-        AdjAcc acc;
-        double xo[4] = {0, 0, 0, 0};
-        if constexpr (kXC) {
+    if (w0 >= n) return;  // whole workgroup past the end
+    const int64_t s = w0 + __lane_id();
+    const bool act = s < n;
+    const int64_t base = g.pl_block[w];
+    const int steps = (int)((g.pl_block[w + 1] - base) >> 6);
+    const int cnt = act ? g.pl_count[s] : 0;
+    const AdjOwn o = adj_own(rec, ad, act ? s : w0);
+    AdjAcc acc;
+    double xo[4] = {0, 0, 0, 0};
+    if constexpr (kXC) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) xo[i] = ad.ext[i][act ? s : w0];
-        }
-        const char *rf = reinterpret_cast<const char *>(rec);
-        const char *ra = reinterpret_cast<const char *>(ad.arec);
-        const int32_t *row = g.pl_slot + base + __lane_id();
-        // One step ahead: the gathers of step j + 1 are in flight while step j is
-        // evaluated.  Each lane reads its step-j chunks into registers, the wavefront
-        // syncs, and only then are the buffers refilled.
-        auto gather = [&](int e) {
-            if constexpr (kF == 8)
-                gather_dma8(rf, kRec * 8, e, bf);
-            else
-                gather_dma<7>(rf, kRec * 8, e, bf);
-            gather_dma<7>(ra, kAdj * 8, e, ba);
-        };
-        int cur = steps > 0 ? row[0] : 0;  // this lane's partner slot of step j
-        if (steps > 0) gather(cur);
-        int nxt = steps > 1 ? row[64] : 0;
-        for (int j = 0; j < steps; ++j) {
-            wait_vm();
-            const double2 b0 = fchunk(0), b1 = fchunk(1), b2 = fchunk(2), b3 = fchunk(3),
-                          b4 = fchunk(4), b5 = fchunk(5), b6 = fchunk(6);
-            const double cb = kF == 8 ? fchunk(7).y : 0.0;
-            const double2 q0 = dma_chunk<7>(ba, 0), q1 = dma_chunk<7>(ba, 1),
-                          q2 = dma_chunk<7>(ba, 2), q3 = dma_chunk<7>(ba, 3),
-                          q4 = dma_chunk<7>(ba, 4), q5 = dma_chunk<7>(ba, 5),
-                          q6 = dma_chunk<7>(ba, 6);
-            wave_sync();
-            const int mine = cur;
-            if (j + 1 < steps) {
-                gather(nxt);
-                cur = nxt;
-                if (j + 2 < steps) nxt = row[(int64_t)(j + 2) << 6];
-            }
-            if (j < cnt) {
-                const double d2 = dist2_exact(o.xc, o.yc, o.zc, b0.x, b0.y, b1.x);
-                double xb[4] = {0, 0, 0, 0};
-                if constexpr (kXC) {
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) xb[i] = ad.ext[i][mine];
-                }
-                if (d2 < k.h2)
-                    adj_pair<false, kEos, kAS, kXC>(k, o, d2, b0, b1, b2, b3, b4, b5, b6, q0, q1,
-                                                    q2, q3, q4, q5, q6, acc, nullptr, nullptr, xo,
-                                                    xb, cb);
-            }
-        }
-        if constexpr (kXC) {  // dx/dt = v + ...
-            acc.gvx += xo[1];
-            acc.gvy += xo[2];
-            acc.gvz += xo[3];
-        }
-        if (act) y0_part = adj_pre<kEos>(k, ad, o, acc, s, io_index(g, s), st, out);
+        for (int i = 0; i < 4; ++i) xo[i] = ad.ext[i][act ? s : w0];
     }
+    const char *rf = reinterpret_cast<const char *>(rec);
+    const char *ra = reinterpret_cast<const char *>(ad.arec);
+    const int32_t *row = g.pl_slot + base + __lane_id();
+    // One step ahead: the gathers of step j + kSplitAdj are in flight while step j is
+    // evaluated.  Each lane reads its step-j chunks into registers, the wavefront
+    // syncs, and only then are the buffers refilled.
+    auto gather = [&](int e) {
+        if constexpr (kF == 8)
+            gather_dma8(rf, kRec * 8, e, bf);
+        else
+            gather_dma<7>(rf, kRec * 8, e, bf);
+        gather_dma<7>(ra, kAdj * 8, e, ba);
+    };
+    int cur = q < steps ? row[(int64_t)q << 6] : 0;  // this lane's partner slot of step j
+    if (q < steps) gather(cur);
+    int nxt = q + kSplitAdj < steps ? row[(int64_t)(q + kSplitAdj) << 6] : 0;
+    for (int j = q; j < steps; j += kSplitAdj) {
+        wait_vm();
+        const double2 b0 = fchunk(0), b1 = fchunk(1), b2 = fchunk(2), b3 = fchunk(3),
+                      b4 = fchunk(4), b5 = fchunk(5), b6 = fchunk(6);
+        const double cb = kF == 8 ? fchunk(7).y : 0.0;
+        const double2 q0 = dma_chunk<7>(ba, 0), q1 = dma_chunk<7>(ba, 1),
+                      q2 = dma_chunk<7>(ba, 2), q3 = dma_chunk<7>(ba, 3),
+                      q4 = dma_chunk<7>(ba, 4), q5 = dma_chunk<7>(ba, 5),
+                      q6 = dma_chunk<7>(ba, 6);
+        wave_sync();
+        const int mine = cur;
+        if (j + kSplitAdj < steps) {
+            gather(nxt);
+            cur = nxt;
+            if (j + 2 * kSplitAdj < steps) nxt = row[(int64_t)(j + 2 * kSplitAdj) << 6];
+        }
+        if (j < cnt) {
+            const double d2 = dist2_exact(o.xc, o.yc, o.zc, b0.x, b0.y, b1.x);
+            double xb[4] = {0, 0, 0, 0};
+            if constexpr (kXC) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) xb[i] = ad.ext[i][mine];
+            }
+            if (d2 < k.h2)
+                adj_pair<false, kEos, kAS, kXC>(k, o, d2, b0, b1, b2, b3, b4, b5, b6, q0, q1,
+                                                q2, q3, q4, q5, q6, acc, nullptr, nullptr, xo,
+                                                xb, cb);
+        }
+    }
+    fold_adj<kSplitAdj, kSplitAdj * 64 * (kF + 7) * 2>(acc, reinterpret_cast<double *>(lbuf));
+    if (q != 0) return;
+    if constexpr (kXC) {  // dx/dt = v + ...
+        acc.gvx += xo[1];
+        acc.gvy += xo[2];
+        acc.gvz += xo[3];
+    }
+    double y0_part = act ? adj_pre<kEos>(k, ad, o, acc, s, io_index(g, s), st, out) : 0.0;
     // fixed-order wavefront sum
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) y0_part += __shfl_xor(y0_part, off);
-    if (threadIdx.x == 0) put(ad.part_y0, (int)w, y0_part, ad.add_parts);
+    if (__lane_id() == 0) put(ad.part_y0, (int)w, y0_part, ad.add_parts);
 }
 
 }  // namespace
@@ -696,10 +722,11 @@ int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_p
     } else {
         TimedRegion t("adjoint_L", s);
         const dim3 gb(blocks_for(n)), tb(kBlock);
+        const dim3 gl(blocks_for(n, 64)), tl(64 * kSplit);
         if (g.pl_count && k.corr)
-            k_adj_L_list<true><<<gb, tb, 0, s>>>(g, n, k, rec, ad);
+            k_adj_L_list<true><<<gl, tl, 0, s>>>(g, n, k, rec, ad);
         else if (g.pl_count)
-            k_adj_L_list<false><<<gb, tb, 0, s>>>(g, n, k, rec, ad);
+            k_adj_L_list<false><<<gl, tl, 0, s>>>(g, n, k, rec, ad);
         else if (k.corr)
             k_adj_L<true><<<gb, tb, 0, s>>>(g, n, k, rec, ad);
         else
@@ -721,13 +748,13 @@ int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_p
             if (xc && k.corr)
                 k_adj_pairs<true, E, A, true><<<gb, tb, 0, s>>>(g, n, k, rec, st, ad, grad);
             else if (xc && g.pl_count)
-                k_adj_pairs_list<E, A, true><<<blocks_for(n, 64), 64, 0, s>>>(g, n, k, rec, st, ad, grad);
+                k_adj_pairs_list<E, A, true><<<blocks_for(n, 64), 64 * kSplitAdj, 0, s>>>(g, n, k, rec, st, ad, grad);
             else if (xc)
                 k_adj_pairs<false, E, A, true><<<gb, tb, 0, s>>>(g, n, k, rec, st, ad, grad);
             else if (k.corr)
                 k_adj_pairs<true, E, A, false><<<gb, tb, 0, s>>>(g, n, k, rec, st, ad, grad);
             else if (g.pl_count)
-                k_adj_pairs_list<E, A><<<blocks_for(n, 64), 64, 0, s>>>(g, n, k, rec, st, ad, grad);
+                k_adj_pairs_list<E, A><<<blocks_for(n, 64), 64 * kSplitAdj, 0, s>>>(g, n, k, rec, st, ad, grad);
             else
                 k_adj_pairs<false, E, A, false><<<gb, tb, 0, s>>>(g, n, k, rec, st, ad, grad);
         };

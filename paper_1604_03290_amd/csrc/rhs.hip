@@ -106,21 +106,25 @@ __global__ __launch_bounds__(kBlock) void k_pairs64(GridDev g, int64_t n, Consts
     }
 }
 
-// FP64 pair sums over the frozen pair list: the wavefront walks its 64 lists in
-// lock step, gathering the 64 partner records of step j cooperatively.
+// FP64 pair sums over the frozen pair list: a workgroup of kSplit wavefronts takes one
+// block of 64 slots, wavefront q walking the 64 lists in lock step over steps q,
+// q + kSplit, ... and gathering the 64 partner records of each step cooperatively;
+// the partial sums are folded into wavefront 0, which runs the postpass.
 template <bool kCorr, bool kExt>
-__global__ __launch_bounds__(kBlock) void k_pairs64_list(GridDev g, int64_t n, Consts k,
-                                                         const double *__restrict__ rec,
-                                                         StateDev st, OutDev out,
-                                                         double *__restrict__ Lout) {
-    __shared__ double2 lbuf[kBlock / 64][64 * 8];
-    double2 *buf = lbuf[threadIdx.x >> 6];
-    const int64_t s = xcd_block(gridDim.x) * kBlock + threadIdx.x;
-    const int64_t w0 = s - __lane_id();
-    if (w0 >= n) return;  // whole wavefront past the end
+__global__ __launch_bounds__(64 * kSplit) void k_pairs64_list(GridDev g, int64_t n, Consts k,
+                                                              const double *__restrict__ rec,
+                                                              StateDev st, OutDev out,
+                                                              double *__restrict__ Lout) {
+    __shared__ double2 lbuf[kSplit][64 * 8];
+    const int q = threadIdx.x >> 6;
+    double2 *buf = lbuf[q];
+    const int64_t w = xcd_block(gridDim.x);
+    const int64_t w0 = w * 64;
+    if (w0 >= n) return;  // whole workgroup past the end
+    const int64_t s = w0 + __lane_id();
     const bool act = s < n;
-    const int64_t base = g.pl_block[w0 >> 6];
-    const int steps = (int)((g.pl_block[(w0 >> 6) + 1] - base) >> 6);
+    const int64_t base = g.pl_block[w];
+    const int steps = (int)((g.pl_block[w + 1] - base) >> 6);
     const int cnt = act ? g.pl_count[s] : 0;
     double2 p0 = make_double2(0, 0), p1 = p0, p2 = p0, p3 = p0, p4 = p0, p5 = p0, p6 = p0, p7 = p0;
     if (act) {
@@ -130,26 +134,26 @@ __global__ __launch_bounds__(kBlock) void k_pairs64_list(GridDev g, int64_t n, C
     const double xa = p0.x, ya = p0.y, za = p1.x, vxa = p1.y, vya = p2.x, vza = p2.y;
     const double rho_a = p3.x;
     Acc64 acc;
-    acc.rs = p7.x * k.Wn;  // own term m_a W(0)
+    if (q == 0) acc.rs = p7.x * k.Wn;  // own term m_a W(0), once
     const double c_a = p7.y;
     const double Ta[6] = {p4.x, p4.y, p5.x, p5.y, p6.x, p6.y};
     const bool tens_a = kExt && signbit(c_a);
     const char *recs = reinterpret_cast<const char *>(rec);
     const int32_t *row = g.pl_slot + base + __lane_id();
     // One step ahead: each lane reads its step-j record into registers, the wavefront
-    // syncs, the gathers of step j + 1 are issued, and step j is evaluated while
+    // syncs, the gathers of step j + kSplit are issued, and step j is evaluated while
     // they are in flight.
-    if (steps > 0) gather_dma8(recs, kRec * 8, row[0], buf);
-    int nxt = steps > 1 ? row[64] : 0;
-    for (int j = 0; j < steps; ++j) {
+    if (q < steps) gather_dma8(recs, kRec * 8, row[(int64_t)q << 6], buf);
+    int nxt = q + kSplit < steps ? row[(int64_t)(q + kSplit) << 6] : 0;
+    for (int j = q; j < steps; j += kSplit) {
         wait_vm();
         const double2 b0 = dma8_chunk(buf, 0), b1 = dma8_chunk(buf, 1), b2 = dma8_chunk(buf, 2),
                       b3 = dma8_chunk(buf, 3), b4 = dma8_chunk(buf, 4), b5 = dma8_chunk(buf, 5),
                       b6 = dma8_chunk(buf, 6), b7 = dma8_chunk(buf, 7);
         wave_sync();
-        if (j + 1 < steps) {
+        if (j + kSplit < steps) {
             gather_dma8(recs, kRec * 8, nxt, buf);
-            if (j + 2 < steps) nxt = row[(int64_t)(j + 2) << 6];
+            if (j + 2 * kSplit < steps) nxt = row[(int64_t)(j + 2 * kSplit) << 6];
         }
         if (j < cnt) {
             const double d2 = dist2_exact(xa, ya, za, b0.x, b0.y, b1.x);
@@ -162,7 +166,8 @@ __global__ __launch_bounds__(kBlock) void k_pairs64_list(GridDev g, int64_t n, C
             }
         }
     }
-    if (!act) return;
+    fold_acc64<kSplit, kSplit * 64 * 16, kCorr, kExt>(acc, reinterpret_cast<double *>(lbuf));
+    if (q != 0 || !act) return;
     postpass(k, io_index(g, s), rho_a, acc.L, acc.ax, acc.ay, acc.az, acc.rs, st, out,
              kCorr ? acc.M : nullptr);
     if (kExt) postpass_ext(k, io_index(g, s), acc, st, out);
@@ -213,32 +218,48 @@ __device__ inline void pair32_of(const Consts32 &kf, const Src32 &a, const Src32
                         a.T[4] + b.T[4], a.T[5] + b.T[5], b.m, b.V, acc, a.T, b.T, a.c, b.c);
 }
 
+// the compensated FP32 sums as FP64 values (rs without the particle's own term)
 template <bool kCorr, bool kExt>
-__device__ inline void post32(const Consts &k, int a, double rho_a, double m_a, const Acc32 &acc,
+__device__ inline Acc64 sums_of(const Acc32 &acc) {
+    Acc64 v;
+    v.rs = acc.rs.value();
+#pragma unroll
+    for (int c = 0; c < 9; ++c) v.L[c] = acc.L[c].value();
+    v.ax = acc.ax.value();
+    v.ay = acc.ay.value();
+    v.az = acc.az.value();
+    if constexpr (kCorr) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v.M[c] = acc.M[c].value();
+    }
+    if constexpr (kExt) {
+        v.du = acc.du.value();
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v.xs[c] = acc.xs[c].value();
+    }
+    return v;
+}
+
+template <bool kCorr, bool kExt>
+__device__ inline void post32(const Consts &k, int a, double rho_a, double m_a, const Acc64 &acc,
                               const StateDev &st, const OutDev &out, double *Lout, int64_t n,
                               int64_t s) {
     if constexpr (kExt) {
-        if (out.du) out.du[a] = 0.5 * acc.du.value();
+        if (out.du) out.du[a] = 0.5 * acc.du;
         if (out.dx) {
-            out.dx[a] = st.vx[a] + k.xsph * acc.xs[0].value();
-            out.dy[a] = st.vy[a] + k.xsph * acc.xs[1].value();
-            out.dz[a] = st.vz[a] + k.xsph * acc.xs[2].value();
+            out.dx[a] = st.vx[a] + k.xsph * acc.xs[0];
+            out.dy[a] = st.vy[a] + k.xsph * acc.xs[1];
+            out.dz[a] = st.vz[a] + k.xsph * acc.xs[2];
         }
     }
-    double L[9], M[6];
-#pragma unroll
-    for (int c = 0; c < 9; ++c) L[c] = acc.L[c].value();
-#pragma unroll
-    for (int c = 0; c < 6; ++c) M[c] = kCorr ? acc.M[c].value() : 0.0;
-    const double rs = m_a * k.Wn + acc.rs.value();
-    postpass(k, a, rho_a, L, acc.ax.value(), acc.ay.value(), acc.az.value(), rs, st, out,
-             kCorr ? M : nullptr);
+    const double rs = m_a * k.Wn + acc.rs;
+    postpass(k, a, rho_a, acc.L, acc.ax, acc.ay, acc.az, rs, st, out, kCorr ? acc.M : nullptr);
     if (Lout) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) Lout[i * n + s] = L[i];
+        for (int i = 0; i < 9; ++i) Lout[i * n + s] = acc.L[i];
         if (kCorr) {
 #pragma unroll
-            for (int i = 0; i < 6; ++i) Lout[(9 + i) * n + s] = M[i];
+            for (int i = 0; i < 6; ++i) Lout[(9 + i) * n + s] = acc.M[i];
         }
     }
 }
@@ -259,24 +280,29 @@ __global__ __launch_bounds__(kBlock) void k_pairs32(GridDev g, int64_t n, Consts
         const double d2 = dist2_exact(a.x, a.y, a.z, b.x, b.y, b.z);
         if (d2 < k.h2) pair32_of<kCorr, kExt>(kf, a, b, d2, acc);
     });
-    post32<kCorr, kExt>(k, io_index(g, s), p3.x, p7.x, acc, st, out, Lout, n, s);
+    post32<kCorr, kExt>(k, io_index(g, s), p3.x, p7.x, sums_of<kCorr, kExt>(acc), st, out, Lout, n,
+                        s);
 }
 
 // FP32 pair sums over the frozen pair list (cooperative gathers of the 80-byte records)
+// the FP32 form over the frozen pair list, kSplit wavefronts per block of 64 slots as
+// in the FP64 list kernel (each wavefront's compensated sums folded as FP64 values)
 template <bool kCorr, bool kExt>
-__global__ __launch_bounds__(kBlock) void k_pairs32_list(GridDev g, int64_t n, Consts k,
-                                                         const double *__restrict__ rec,
-                                                         const float *__restrict__ r32,
-                                                         StateDev st, OutDev out,
-                                                         double *__restrict__ Lout) {
-    __shared__ double2 lbuf[kBlock / 64][64 * 5];
-    double2 *buf = lbuf[threadIdx.x >> 6];
-    const int64_t s = xcd_block(gridDim.x) * kBlock + threadIdx.x;
-    const int64_t w0 = s - __lane_id();
-    if (w0 >= n) return;
+__global__ __launch_bounds__(64 * kSplit) void k_pairs32_list(GridDev g, int64_t n, Consts k,
+                                                              const double *__restrict__ rec,
+                                                              const float *__restrict__ r32,
+                                                              StateDev st, OutDev out,
+                                                              double *__restrict__ Lout) {
+    __shared__ double2 lbuf[kSplit][64 * 5];
+    const int q = threadIdx.x >> 6;
+    double2 *buf = lbuf[q];
+    const int64_t w = xcd_block(gridDim.x);
+    const int64_t w0 = w * 64;
+    if (w0 >= n) return;  // whole workgroup past the end
+    const int64_t s = w0 + __lane_id();
     const bool act = s < n;
-    const int64_t base = g.pl_block[w0 >> 6];
-    const int steps = (int)((g.pl_block[(w0 >> 6) + 1] - base) >> 6);
+    const int64_t base = g.pl_block[w];
+    const int steps = (int)((g.pl_block[w + 1] - base) >> 6);
     const int cnt = act ? g.pl_count[s] : 0;
     const Src32 a = load32(r32, act ? s : w0);
     const Consts32 kf = narrow(k);
@@ -284,25 +310,27 @@ __global__ __launch_bounds__(kBlock) void k_pairs32_list(GridDev g, int64_t n, C
     const char *recs = reinterpret_cast<const char *>(r32);
     const int32_t *row = g.pl_slot + base + __lane_id();
     // one step ahead, as in the FP64 kernel
-    if (steps > 0) gather_dma<5>(recs, kRec32Bytes, row[0], buf);
-    int nxt = steps > 1 ? row[64] : 0;
-    for (int j = 0; j < steps; ++j) {
+    if (q < steps) gather_dma<5>(recs, kRec32Bytes, row[(int64_t)q << 6], buf);
+    int nxt = q + kSplit < steps ? row[(int64_t)(q + kSplit) << 6] : 0;
+    for (int j = q; j < steps; j += kSplit) {
         wait_vm();
         const Src32 b = src32(dma_chunk<5>(buf, 0), dma_chunk<5>(buf, 1), dma_chunk<5>(buf, 2),
                               dma_chunk<5>(buf, 3), dma_chunk<5>(buf, 4));
         wave_sync();
-        if (j + 1 < steps) {
+        if (j + kSplit < steps) {
             gather_dma<5>(recs, kRec32Bytes, nxt, buf);
-            if (j + 2 < steps) nxt = row[(int64_t)(j + 2) << 6];
+            if (j + 2 * kSplit < steps) nxt = row[(int64_t)(j + 2 * kSplit) << 6];
         }
         if (j < cnt) {
             const double d2 = dist2_exact(a.x, a.y, a.z, b.x, b.y, b.z);
             if (d2 < k.h2) pair32_of<kCorr, kExt>(kf, a, b, d2, acc);
         }
     }
-    if (!act) return;
+    Acc64 sums = sums_of<kCorr, kExt>(acc);
+    fold_acc64<kSplit, kSplit * 64 * 5 * 2, kCorr, kExt>(sums, reinterpret_cast<double *>(lbuf));
+    if (q != 0 || !act) return;
     const double2 p3 = rec2(rec, s)[3], p7 = rec2(rec, s)[7];
-    post32<kCorr, kExt>(k, io_index(g, s), p3.x, p7.x, acc, st, out, Lout, n, s);
+    post32<kCorr, kExt>(k, io_index(g, s), p3.x, p7.x, sums, st, out, Lout, n, s);
 }
 
 }  // namespace
@@ -409,7 +437,8 @@ int rhs_launch(const sph_grid *grid, const sph_state *state, const sph_params *p
         auto launch = [&](auto corr, auto extra) {
             constexpr bool C = decltype(corr)::value, E = decltype(extra)::value;
             if (g.pl_count)
-                k_pairs64_list<C, E><<<gb, tb, 0, s>>>(g, n, k, rec, st, od, L_out);
+                k_pairs64_list<C, E><<<blocks_for(n, 64), 64 * kSplit, 0, s>>>(g, n, k, rec, st, od,
+                                                                             L_out);
             else
                 k_pairs64<C, E><<<gb, tb, 0, s>>>(g, n, k, rec, st, od, L_out);
         };
@@ -432,7 +461,8 @@ int rhs_launch(const sph_grid *grid, const sph_state *state, const sph_params *p
         auto launch = [&](auto corr, auto extra) {
             constexpr bool C = decltype(corr)::value, E = decltype(extra)::value;
             if (g.pl_count)
-                k_pairs32_list<C, E><<<gb, tb, 0, s>>>(g, n, k, rec, r32, st, od, L_out);
+                k_pairs32_list<C, E><<<blocks_for(n, 64), 64 * kSplit, 0, s>>>(g, n, k, rec, r32, st,
+                                                                             od, L_out);
             else
                 k_pairs32<C, E><<<gb, tb, 0, s>>>(g, n, k, rec, r32, st, od, L_out);
         };

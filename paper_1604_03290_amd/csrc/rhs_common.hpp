@@ -147,6 +147,42 @@ __device__ inline void wave_sync() {
 // vmcnt(0), other counters untouched): the LDS-direct gathers of a step have landed.
 __device__ inline void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
+// The list kernels give one block of 64 slots to a workgroup of P wavefronts: wavefront
+// q evaluates the block's list steps q, q + P, q + 2P, ... for the same 64 targets.  So a
+// launch holds P times fewer slots in flight per XCD for the same number of wavefronts,
+// and the partner records those slots gather stay in that XCD's L2.  fold_waves then
+// adds the P partial sums of each target into wavefront 0 in wavefront order (bit
+// reproducible): wavefronts 1 .. P-1 store their F values per lane in LDS (scratch, Cap
+// doubles, in rounds of Cap / (64 (P - 1)) values), wavefront 0 adds them.  Every thread
+// of the workgroup calls it; it starts with a workgroup barrier, so scratch may alias
+// buffers that the wavefronts read before the call.
+constexpr int kSplit = 4;     // wavefronts per block in the forward list kernels
+constexpr int kSplitAdj = 4;  // and in the adjoint's pair kernel
+
+template <int P, int Cap, int F>
+__device__ inline void fold_waves(double (&v)[F], double *scratch) {
+    static_assert(P >= 2 && Cap >= 64 * (P - 1), "scratch too small");
+    constexpr int G = Cap / (64 * (P - 1));  // values per round
+    const int q = threadIdx.x >> 6, lane = __lane_id();
+#pragma unroll
+    for (int f0 = 0; f0 < F; f0 += G) {
+        __syncthreads();
+        if (q > 0) {
+#pragma unroll
+            for (int f = f0; f < (f0 + G < F ? f0 + G : F); ++f)
+                scratch[((q - 1) * G + (f - f0)) * 64 + lane] = v[f];
+        }
+        __syncthreads();
+        if (q == 0) {
+#pragma unroll
+            for (int r = 1; r < P; ++r)
+#pragma unroll
+                for (int f = f0; f < (f0 + G < F ? f0 + G : F); ++f)
+                    v[f] += scratch[((r - 1) * G + (f - f0)) * 64 + lane];
+        }
+    }
+}
+
 // Coalesced gather of the first N 16-byte chunks of one partner record per lane
 // into the wavefront's LDS buffer (64 N chunks).  Each lane holds its list entry of
 // the step (one coalesced load by the caller); lane shuffles hand the entries to
@@ -537,6 +573,47 @@ struct Acc64 {
     // with the extra terms: energy sum (twice du/dt) and XSPH velocity sum
     double du = 0.0, xs[3] = {0, 0, 0};
 };
+
+// The sums of the P wavefronts of a list kernel's workgroup added into wavefront 0
+// (fold_waves); the correction's and the extra terms' sums only where they are formed.
+template <int P, int Cap, bool kCorr, bool kExt>
+__device__ inline void fold_acc64(Acc64 &a, double *scratch) {
+    constexpr int F = 13 + (kCorr ? 6 : 0) + (kExt ? 4 : 0);
+    double v[F];
+    int i = 0;
+    v[i++] = a.rs;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) v[i++] = a.L[c];
+    v[i++] = a.ax;
+    v[i++] = a.ay;
+    v[i++] = a.az;
+    if constexpr (kCorr) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[i++] = a.M[c];
+    }
+    if constexpr (kExt) {
+        v[i++] = a.du;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[i++] = a.xs[c];
+    }
+    fold_waves<P, Cap>(v, scratch);
+    i = 0;
+    a.rs = v[i++];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) a.L[c] = v[i++];
+    a.ax = v[i++];
+    a.ay = v[i++];
+    a.az = v[i++];
+    if constexpr (kCorr) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) a.M[c] = v[i++];
+    }
+    if constexpr (kExt) {
+        a.du = v[i++];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a.xs[c] = v[i++];
+    }
+}
 
 // f^n for a fractional exponent, out of line so that the pair loop does not carry
 // the registers of pow

@@ -317,6 +317,45 @@ def test_nonuniform_adjoint_matches_directional_derivative():
     assert abs(fd - pred) <= 1e-6 * abs(pred), (fd, pred)
 
 
+def test_nonuniform_adjoint_local_cotangent_matches_oracle():
+    """At 8,388,608 particles, sph_rhs_adjoint against the oracle's reverse-mode product,
+    element by element.  The cotangent is random on the particles within 0.7 h of a
+    centre and zero elsewhere (one centre in each body: the dense sphere, the sphere and
+    the sparse shell).  Every term of the product then involves only particles within
+    2 h of that support (a gradient reaches the partners of the support, and the
+    velocity gradients of the support need their partners), so the oracle's product
+    over the particles within 2.75 h of the centre is the exact value there, and the
+    GPU's gradient must vanish exactly everywhere else."""
+    w = W.config(4)
+    idx = W.subsample(w.n, 512, seed=31)
+    deg = np.diff(native.neighbours(w.pos, w.h, idx)[0])
+    centres = [idx[np.argmax(deg)], idx[np.argmin(np.abs(deg - 60))], idx[np.argmin(deg)]]
+    assert deg.max() > 200 and deg.min() < 30
+    st = gpu_state(w)
+    g = P.sph_build_cells(st.pos, w.h, skin=0.1 * w.dx, cells_per_h=2, pairs=True)
+    rng = np.random.default_rng(32)
+    for c in centres:
+        sup = native.ball(w.pos, w.pos[:, c], 0.7 * w.h)
+        sub = native.ball(w.pos, w.pos[:, c], 2.75 * w.h)
+        fwd = native.rhs(w.pos, w.vel, w.rho, w.S, w.m, w.param_vector(), targets=sup)
+        cot = {"acc": np.zeros((3, w.n)), "drho": np.zeros(w.n), "dS": np.zeros((6, w.n)),
+               "rho_sum": np.zeros(w.n)}
+        for k in cot:  # comparable weight for every output
+            cot[k][..., sup] = rng.normal(size=cot[k][..., sup].shape) / np.abs(fwd[k]).max()
+        got = P.sph_rhs_adjoint(g, st, w.params,
+                                {k: torch.as_tensor(v).cuda().contiguous() for k, v in cot.items()})
+        assert P.workspace_status(got["_ws"]) == 0
+        ref = AD.rhs_vjp(w.take(sub), {k: np.ascontiguousarray(v[..., sub]) for k, v in cot.items()})
+        out = np.ones(w.n, dtype=bool)
+        out[sub] = False
+        for k in ("pos", "vel", "rho", "S"):
+            gk = got[k].cpu().numpy()
+            assert rel(gk[..., sub], ref[k]) < 1e-11, (int(c), k, rel(gk[..., sub], ref[k]))
+            assert not np.any(gk[..., out]), (int(c), k)
+        assert abs(float(got["mu"]) - ref["mu"]) <= 1e-11 * abs(ref["mu"]), int(c)
+        assert abs(float(got["Y0"]) - ref["Y0"]) <= 1e-11 * max(abs(ref["Y0"]), 1e-300), int(c)
+
+
 def test_autograd_function_matches_adjoint_and_oracle():
     # SphRhs: forward = sph_rhs, backward = sph_rhs_adjoint, through torch.autograd
     w = small("cube8_visc")

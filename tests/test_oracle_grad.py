@@ -131,6 +131,35 @@ def test_momentum_objective_closed_form(axis):
     assert abs(g["Y0"]) * vs <= 1e-8 * abs(gk["Y0"])
 
 
+def test_vjp_of_a_local_cotangent_is_local():
+    """A cotangent supported within 0.7 h of a point gives gradients that vanish beyond
+    1.7 h, and the product over the particles within 2.75 h alone equals the whole set's
+    there (every particle it involves has all its partners in that ball): the premise of
+    the full-size adjoint comparison on the GPU."""
+    w = W.config(0)
+    c = 2000
+    sup = native.ball(w.pos, w.pos[:, c], 0.7 * w.h)
+    sub = native.ball(w.pos, w.pos[:, c], 2.75 * w.h)
+    fwd = native.rhs(w.pos, w.vel, w.rho, w.S, w.m, w.param_vector(), targets=sup)
+    rng = np.random.default_rng(1)
+    cot = {"acc": np.zeros((3, w.n)), "drho": np.zeros(w.n), "dS": np.zeros((6, w.n)),
+           "rho_sum": np.zeros(w.n)}
+    for k in cot:
+        cot[k][..., sup] = rng.normal(size=cot[k][..., sup].shape) / np.abs(fwd[k]).max()
+    full = AD.rhs_vjp(w, cot)
+    loc = AD.rhs_vjp(w.take(sub), {k: np.ascontiguousarray(v[..., sub]) for k, v in cot.items()})
+    near = native.ball(w.pos, w.pos[:, c], 1.7 * w.h)
+    far = np.ones(w.n, dtype=bool)
+    far[near] = False
+    assert len(sup) > 5 and len(sub) < w.n // 4
+    for k in ("pos", "vel", "rho", "S"):
+        assert np.array_equal(full[k][..., sub], loc[k]), k
+        assert not np.any(full[k][..., far]), k
+        assert np.any(full[k]), k
+    for k in ("mu", "Y0"):  # sums over the particles, in another order
+        assert abs(full[k] - loc[k]) <= 1e-14 * abs(full[k]), k
+
+
 def test_unlimited_yield_stress_has_zero_gradient():
     w = small(seed=41, n_side=5, Y0=1e30)
     g = AD.leapfrog_grad(w, 3, 0.2 * w.dx / 5000.0, "ke")
