@@ -7,8 +7,9 @@ shell with about 20; h = 2.4 dx).  One step = one pass of the whole hot path ove
   cell build (tiled cell numbering)                          sph_build_cells
   frozen pair list (the interaction list, skin 0)            sph_build_pairs
   partner lists (CSR, user order, rows ascending)            sph_neighbours
-  FP64 right-hand side                                       sph_rhs
-  FP64 adjoint (vector-Jacobian product, random cotangent)   sph_rhs_adjoint
+  FP64 right-hand side (writing its velocity gradient)      sph_rhs
+  FP64 adjoint (vector-Jacobian product, random cotangent,   sph_rhs_adjoint
+  reading that velocity gradient instead of forming it)
 The metric counts the ordered pair interactions (b != a, |x_a - x_b| < h) evaluated
 by the right-hand side and by the adjoint: value = 2 nnz / step time.  Inputs are
 resident on the GPU before timing starts.  Reported beside it: the FP32-compensated
@@ -276,7 +277,7 @@ def single_state_step(args, w, torch, P, L):
     f_app = approaching_fraction(st, row_ptr, col, torch)
     partners = partner_stats(row_ptr, torch)
     del col
-    out = P.api.new_deriv(n)
+    out = P.api.new_deriv(n, vgrad=9)
     cot = {k: torch.randn(out[k].shape, dtype=torch.float64, device="cuda",
                           generator=torch.Generator("cuda").manual_seed(3)) for k in P.api.DERIV_KEYS}
     holder = {}
@@ -285,8 +286,10 @@ def single_state_step(args, w, torch, P, L):
         g = P.sph_build_cells(st.pos, w.h, skin=skin, cells_per_h=CELLS_PER_H, box=box, ws=ws_build)
         P.sph_build_pairs(g, st.pos, capacity=pl_cap, ws=ws_pairs)
         holder["csr"] = P.sph_neighbours(g, st.pos, w.h, col_cap=col_cap, ws=ws_nb)
+        # the forward hands its velocity gradient to the adjoint (as a reverse-mode
+        # caller keeps its forward's intermediates)
         P.sph_rhs(g, st, w.params, "fp64", out=out, ws=ws_rhs)
-        holder["grad"] = P.sph_rhs_adjoint(g, st, w.params, cot, ws=ws_adj)
+        holder["grad"] = P.sph_rhs_adjoint(g, st, w.params, cot, ws=ws_adj, vgrad=out["vgrad"])
         holder["g"] = g
 
     log(f"{w.name}: {nnz} ordered pairs, list of {pl_cap} entries; warm-up")
@@ -332,7 +335,12 @@ def single_state_step(args, w, torch, P, L):
         forms[f"rhs_{form}"] = {"ms": ms, "pairs_per_s": nnz / (ms * 1e-3)}
         outs[form] = o
     ms = median_ms(lambda: P.sph_rhs_adjoint(g, st, w.params, cot, ws=ws_adj), reps, torch)
-    forms["adjoint_fp64"] = {"ms": ms, "pairs_per_s": nnz / (ms * 1e-3)}
+    forms["adjoint_fp64"] = {"ms": ms, "pairs_per_s": nnz / (ms * 1e-3),
+                             "note": "forms the velocity gradient itself"}
+    ms = median_ms(lambda: P.sph_rhs_adjoint(g, st, w.params, cot, ws=ws_adj, vgrad=out["vgrad"]),
+                   reps, torch)
+    forms["adjoint_fp64_vgrad"] = {"ms": ms, "pairs_per_s": nnz / (ms * 1e-3),
+                                   "note": "reads the velocity gradient sph_rhs wrote (the step's form)"}
     forms["fp32comp_speedup_vs_fp64"] = forms["rhs_fp64"]["ms"] / forms["rhs_fp32comp"]["ms"]
     fields = ("acc", "drho", "dS", "rho_sum")
     forms["rhs_fp32comp"]["normwise_error_vs_fp64_gpu"] = {
@@ -358,8 +366,8 @@ def single_state_step(args, w, torch, P, L):
                                  "load_balance_mean_over_max_per_wave": cand / pl_cap},
                    "skin_over_dx": skin / w.dx, "h_over_dx": 2.4, "cells_per_h": CELLS_PER_H,
                    "grid_dims": list(dims), "grid_cells": ncells,
-                   "step": "cell build + pair list + partner CSR + FP64 sph_rhs + FP64 sph_rhs_adjoint "
-                           "(random cotangent) on one state"},
+                   "step": "cell build + pair list + partner CSR + FP64 sph_rhs (writing its velocity "
+                           "gradient) + FP64 sph_rhs_adjoint (random cotangent, reading it) on one state"},
         "roofline": kernel_roofline(kern, nnz, f_app, pl_cap, args.steps, ms_step),
         "forms": forms,
         "copy_calibration_bytes": calib,

@@ -180,7 +180,12 @@ typedef struct {
  * particle's thresholds below eps; dd3 = n_act c_g / R_s with
  * c_g = 0.4 sqrt((K + 4/3 (1 - d) mu) / rho) and R_s = (3 m / (4 pi rho))^(1/3),
  * and 0 once d n_tot >= n_act (the limiter d <= n_act / n_tot, n_tot the
- * particle's flaw count). */
+ * particle's flaw count).  vgrad (NULL, or device [9 n], [15 n] with
+ * params->correction = 1; SPH_FP64 only) receives the velocity gradient that the
+ * pair sums form (section 3.1.6, before the correction), for sph_rhs_adjoint
+ * (sph_deriv_cot.vgrad) to reuse: component i of slot s at vgrad[i n + s], in the
+ * grid's slot order, L row by row (dv^x/dx, dv^x/dy, ..., dv^z/dz), then with the
+ * correction the moment matrix M (xx yy zz xy xz yz). */
 typedef struct {
     double *ax, *ay, *az;
     double *drho;
@@ -190,11 +195,16 @@ typedef struct {
     double *dx, *dy, *dz;
     double *dd3;
     int32_t *n_act;
+    double *vgrad;
 } sph_deriv;
 
 /* Cotangents of the derivatives (inputs of the adjoint), user order.  A NULL
  * pointer means a zero cotangent.  du and dx, dy, dz are the cotangents of the
- * energy rate and of dx/dt (XSPH) of sph_deriv. */
+ * energy rate and of dx/dt (XSPH) of sph_deriv.  vgrad is not a cotangent: NULL, or
+ * the velocity gradient that sph_rhs (SPH_FP64) wrote into sph_deriv.vgrad for the
+ * same grid, state and params, which the adjoint then reads instead of forming it
+ * again (a reverse-mode caller keeps it from its forward call, as it keeps any
+ * intermediate); a vgrad of another state gives wrong gradients, unchecked. */
 typedef struct {
     const double *ax, *ay, *az;
     const double *drho;
@@ -202,6 +212,7 @@ typedef struct {
     const double *rho_sum;
     const double *du;
     const double *dx, *dy, *dz;
+    const double *vgrad;
 } sph_deriv_cot;
 
 /* Writable per-particle fields (no mass): used for gradients with respect to

@@ -77,11 +77,11 @@ _FIELDS = ("x", "y", "z", "vx", "vy", "vz", "rho", "sxx", "syy", "szz", "sxy", "
 
 
 class Deriv(C.Structure):
-    _fields_ = [(k, _pd) for k in _DERIV + ("du", "dx", "dy", "dz", "dd3", "n_act")]
+    _fields_ = [(k, _pd) for k in _DERIV + ("du", "dx", "dy", "dz", "dd3", "n_act", "vgrad")]
 
 
 class DerivCot(C.Structure):
-    _fields_ = [(k, _pd) for k in _DERIV + ("du", "dx", "dy", "dz")]
+    _fields_ = [(k, _pd) for k in _DERIV + ("du", "dx", "dy", "dz", "vgrad")]
 
 
 class Fields(C.Structure):

@@ -265,9 +265,12 @@ def sph_gravity(pos: torch.Tensor, m: torch.Tensor, G: float, theta: float, eps:
     return out
 
 
-def new_deriv(n: int, device="cuda", extra: bool = False, damage: bool = False):
+def new_deriv(n: int, device="cuda", extra: bool = False, damage: bool = False,
+              vgrad: int = 0):
     """Output arrays of sph_rhs; with ``extra`` also du (n) and xv (3, n) = dx/dt, with
-    ``damage`` dd3 (n) = d(d^(1/3))/dt and n_act (n, int32)."""
+    ``damage`` dd3 (n) = d(d^(1/3))/dt and n_act (n, int32), with ``vgrad`` = 9 (15 with
+    the correction tensor) the velocity-gradient handoff for sph_rhs_adjoint (vgrad,
+    (vgrad, n), the grid's slot order)."""
     d = dict(acc=torch.empty(3, n, dtype=F64, device=device),
              drho=torch.empty(n, dtype=F64, device=device),
              dS=torch.empty(6, n, dtype=F64, device=device),
@@ -278,6 +281,8 @@ def new_deriv(n: int, device="cuda", extra: bool = False, damage: bool = False):
     if damage:
         d["dd3"] = torch.empty(n, dtype=F64, device=device)
         d["n_act"] = torch.empty(n, dtype=torch.int32, device=device)
+    if vgrad:
+        d["vgrad"] = torch.empty(vgrad, n, dtype=F64, device=device)
     return d
 
 
@@ -302,7 +307,10 @@ def deriv_struct(d: dict, cls=L.Deriv):
             _dev(dd3)
         if na is not None:
             _dev(na, torch.int32)
-        args += [p(dd3), p(na)]
+        vg = d.get("vgrad")
+        if vg is not None:
+            _dev(vg)
+        args += [p(dd3), p(na), p(vg)]
     return cls(*args)
 
 
@@ -322,13 +330,16 @@ def precision_code(precision) -> int:
 
 
 def sph_rhs(grid: CellGrid, state: ParticleState, params, precision="fp64", out=None,
-            ws: torch.Tensor | None = None, extra: bool = False, damage: bool = False) -> dict:
+            ws: torch.Tensor | None = None, extra: bool = False, damage: bool = False,
+            vgrad: bool = False) -> dict:
     """Right-hand side (C: sph_rhs): dict acc (3, n), drho (n), dS (6, n), rho_sum (n);
     with ``extra`` (or an ``out`` holding them) also du (n) and xv (3, n) = dx/dt, with
-    ``damage`` the damage model's dd3 (n) and n_act (n) (the state's flaw lists needed)."""
+    ``damage`` the damage model's dd3 (n) and n_act (n) (the state's flaw lists needed),
+    with ``vgrad`` (FP64) the velocity gradient that sph_rhs_adjoint can take back."""
     n = state.n
     if out is None:
-        out = new_deriv(n, state.rho.device, extra, damage)
+        nv = (15 if params_struct(params).correction != 0.0 else 9) if vgrad else 0
+        out = new_deriv(n, state.rho.device, extra, damage, nv)
     if ws is None:
         ws = workspace(L.SPH_OP_RHS, n, 0, state.rho.device)
     cs = state.c_state()
@@ -358,18 +369,26 @@ def sph_rhs_noalloc(grid: CellGrid, state: ParticleState, params, precision="fp6
 
 
 def sph_rhs_adjoint(grid: CellGrid, state: ParticleState, params, cot: dict,
-                    ws: torch.Tensor | None = None) -> dict:
+                    ws: torch.Tensor | None = None, vgrad: torch.Tensor | None = None) -> dict:
     """Vector-Jacobian product of sph_rhs (C: sph_rhs_adjoint).  ``cot`` has keys of
-    sph_rhs's outputs (acc, drho, dS, rho_sum, du, xv; missing = zero).  Returns
-    gradients pos, vel, rho, S, mu, Y0, and u with the Tillotson equation."""
+    sph_rhs's outputs (acc, drho, dS, rho_sum, du, xv; missing = zero).  ``vgrad``: the
+    "vgrad" output of an FP64 sph_rhs on the same grid, state and params, reused instead
+    of forming the velocity gradient again.  Returns gradients pos, vel, rho, S, mu, Y0,
+    and u with the Tillotson equation."""
     n = state.n
     dev = state.rho.device
     z3 = lambda k, shape: _dev(cot[k]) if cot.get(k) is not None else None
     acc, drho, dS, rs = (z3("acc", None), z3("drho", None), z3("dS", None), z3("rho_sum", None))
     du, xv = z3("du", None), z3("xv", None)
     p = lambda t, i=None: (t[i].data_ptr() if i is not None else t.data_ptr()) if t is not None else None
+    if vgrad is not None:
+        _dev(vgrad)
+        want = 15 if params_struct(params).correction != 0.0 else 9
+        if tuple(vgrad.shape) != (want, n):
+            raise ValueError(f"vgrad must be ({want}, {n}), got {tuple(vgrad.shape)}")
     dc = L.DerivCot(p(acc, 0), p(acc, 1), p(acc, 2), p(drho), p(dS, 0), p(dS, 1), p(dS, 2),
-                    p(dS, 3), p(dS, 4), p(dS, 5), p(rs), p(du), p(xv, 0), p(xv, 1), p(xv, 2))
+                    p(dS, 3), p(dS, 4), p(dS, 5), p(rs), p(du), p(xv, 0), p(xv, 1), p(xv, 2),
+                    p(vgrad))
     g = dict(pos=torch.empty(3, n, dtype=F64, device=dev), vel=torch.empty(3, n, dtype=F64, device=dev),
              rho=torch.empty(n, dtype=F64, device=dev), S=torch.empty(6, n, dtype=F64, device=dev))
     dparams = torch.empty(2, dtype=F64, device=dev)
@@ -410,10 +429,12 @@ class SphRhs(torch.autograd.Function):
                            rho.detach().contiguous(), S.detach().contiguous(), m.contiguous(),
                            u=None if u is None else u.detach().contiguous(),
                            d=None if d is None else d.detach().contiguous())
-        out = sph_rhs(grid, st, p, "fp64", extra=extra)
+        out = sph_rhs(grid, st, p, "fp64", extra=extra, vgrad=True)
         # the inputs are saved through autograd, so that an in-place change between
-        # forward and backward raises instead of differentiating at a changed state
+        # forward and backward raises instead of differentiating at a changed state;
+        # the velocity gradient is kept for the backward, which then skips forming it
         ctx.save_for_backward(pos, vel, rho, S, m, u, d)
+        ctx.vgrad = out["vgrad"]
         ctx.grid, ctx.params, ctx.extra = grid, p, extra
         ctx.mu_like, ctx.Y0_like = torch.as_tensor(mu), torch.as_tensor(Y0)
         res = (out["acc"], out["drho"], out["dS"], out["rho_sum"])
@@ -426,7 +447,7 @@ class SphRhs(torch.autograd.Function):
         st = ParticleState(c(pos), c(vel), c(rho), c(S), c(m), u=c(u), d=c(d))
         names = ("acc", "drho", "dS", "rho_sum", "du", "xv")
         cot = {k: (v.contiguous() if v is not None else None) for k, v in zip(names, grads)}
-        g = sph_rhs_adjoint(ctx.grid, st, ctx.params, cot)
+        g = sph_rhs_adjoint(ctx.grid, st, ctx.params, cot, vgrad=ctx.vgrad)
         gmu = g["mu"].to(ctx.mu_like.device, ctx.mu_like.dtype).reshape(ctx.mu_like.shape)
         gY0 = g["Y0"].to(ctx.Y0_like.device, ctx.Y0_like.dtype).reshape(ctx.Y0_like.shape)
         return (g["pos"], g["vel"], g["rho"], g["S"], gmu, gY0, None, None, None, None, None,

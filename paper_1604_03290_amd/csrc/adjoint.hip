@@ -809,5 +809,6 @@ extern "C" int sph_rhs_adjoint(const sph_grid *grid, const sph_state *state,
     hipStream_t s = (hipStream_t)stream;
     if ((rc = clear_status(ws, s))) return rc;
     Carve c(ws);
-    return rhs_adjoint_launch(grid, state, params, cot_dev(cot), grad_dev(grad, 0), dparams, 0, c, s);
+    return rhs_adjoint_launch(grid, state, params, cot_dev(cot), grad_dev(grad, 0), dparams, 0, c, s,
+                              cot->vgrad);
 }

@@ -307,6 +307,7 @@ sph_deriv deriv_struct(const Deriv10 &d) {
     o.du = o.dx = o.dy = o.dz = nullptr;
     o.dd3 = nullptr;
     o.n_act = nullptr;
+    o.vgrad = nullptr;  // the leapfrog hands the velocity gradient over itself
     return o;
 }
 

@@ -534,6 +534,8 @@ extern "C" int sph_rhs_noalloc(const sph_grid *grid, const sph_state *state,
         return rc;
     if (precision != SPH_FP64 && precision != SPH_FP32_COMP)
         return fail(SPH_ERR_INVALID_ARG, "unknown precision %d", precision);
+    if (out->vgrad && precision != SPH_FP64)
+        return fail(SPH_ERR_INVALID_ARG, "vgrad is written by the FP64 form only");
     if (grid->n > kNoallocMaxN)
         return fail(SPH_ERR_CAPACITY, "sph_rhs_noalloc serves at most %lld particles (%lld given)",
                     (long long)kNoallocMaxN, (long long)grid->n);
@@ -545,7 +547,7 @@ extern "C" int sph_rhs_noalloc(const sph_grid *grid, const sph_state *state,
     hipStream_t s = (hipStream_t)stream;
     if ((rc = clear_status(ws, s))) return rc;
     Carve c(ws);
-    if ((rc = rhs_launch(grid, state, params, precision, out, c, s, nullptr, false, false, false)))
+    if ((rc = rhs_launch(grid, state, params, precision, out, c, s, out->vgrad, false, false, false)))
         return rc;
     if (status) {
         k_copy_status<<<1, 1, 0, s>>>(reinterpret_cast<const int32_t *>(ws), status);
@@ -565,11 +567,13 @@ extern "C" int sph_rhs(const sph_grid *grid, const sph_state *state, const sph_p
         return rc;
     if (precision != SPH_FP64 && precision != SPH_FP32_COMP)
         return fail(SPH_ERR_INVALID_ARG, "unknown precision %d", precision);
+    if (out->vgrad && precision != SPH_FP64)
+        return fail(SPH_ERR_INVALID_ARG, "vgrad is written by the FP64 form only");
     if (!ws) return fail(SPH_ERR_INVALID_ARG, "workspace is NULL");
     const size_t need = rhs_ws_bytes(grid->n);
     if (ws_bytes < need) return fail(SPH_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
     hipStream_t s = (hipStream_t)stream;
     if ((rc = clear_status(ws, s))) return rc;
     Carve c(ws);
-    return rhs_launch(grid, state, params, precision, out, c, s);
+    return rhs_launch(grid, state, params, precision, out, c, s, out->vgrad);
 }

@@ -317,6 +317,39 @@ def test_nonuniform_adjoint_matches_directional_derivative():
     assert abs(fd - pred) <= 1e-6 * abs(pred), (fd, pred)
 
 
+@pytest.mark.parametrize("corr", [False, True])
+@pytest.mark.parametrize("pairs", [False, True])
+def test_rhs_adjoint_reuses_the_forward_velocity_gradient(corr, pairs):
+    """sph_rhs's vgrad output handed to sph_rhs_adjoint: the same gradients as the
+    adjoint that forms the velocity gradient itself (to rounding: the two kernels sum
+    the same terms), both against the oracle's reverse-mode product."""
+    w = small("cube8_visc")
+    w.params["correction"] = 1.0 if corr else 0.0
+    ref_out = native.rhs_workload(w, want_L=False)
+    rng = np.random.default_rng(27)
+    cot = {k: rng.normal(size=ref_out[k].shape) / np.abs(ref_out[k]).max() for k in ref_out}
+    ref = AD.rhs_vjp(w, cot)
+    st = gpu_state(w)
+    g = P.sph_build_cells(st.pos, w.h, skin=0.05 * w.dx, pairs=pairs)
+    fwd = P.sph_rhs(g, st, w.params, "fp64", vgrad=True)
+    assert fwd["vgrad"].shape == (15 if corr else 9, w.n)
+    plain = P.sph_rhs(g, st, w.params, "fp64")
+    for k in ("acc", "drho", "dS", "rho_sum"):  # writing vgrad changes no output
+        assert torch.equal(fwd[k], plain[k]), k
+    cg = {k: torch.as_tensor(v).cuda().contiguous() for k, v in cot.items()}
+    own = P.sph_rhs_adjoint(g, st, w.params, cg)
+    got = P.sph_rhs_adjoint(g, st, w.params, cg, vgrad=fwd["vgrad"])
+    assert P.workspace_status(got["_ws"]) == 0
+    for k in ("pos", "vel", "rho", "S"):
+        assert rel(got[k].cpu().numpy(), own[k].cpu().numpy()) < 1e-13, k
+        assert rel(got[k].cpu().numpy(), ref[k]) < 1e-11, k
+    for k in ("mu", "Y0"):
+        assert abs(float(got[k]) - ref[k]) <= 1e-11 * abs(ref[k]), k
+    # the FP32-compensated form does not write it
+    with pytest.raises(L.SphError):
+        P.sph_rhs(g, st, w.params, "fp32comp", vgrad=True)
+
+
 def test_nonuniform_adjoint_local_cotangent_matches_oracle():
     """At 8,388,608 particles, sph_rhs_adjoint against the oracle's reverse-mode product,
     element by element.  The cotangent is random on the particles within 0.7 h of a
@@ -369,14 +402,15 @@ def test_autograd_function_matches_adjoint_and_oracle():
     mu = torch.tensor(w.params["mu"], dtype=torch.float64, device="cuda", requires_grad=True)
     Y0 = torch.tensor(w.params["Y0"], dtype=torch.float64, device="cuda", requires_grad=True)
     outs = P.SphRhs.apply(*leaves, mu, Y0, g, w.params, st.m)
-    direct = P.sph_rhs(g, st, w.params, "fp64")
+    direct = P.sph_rhs(g, st, w.params, "fp64", vgrad=True)
     for k, o in zip(("acc", "drho", "dS", "rho_sum"), outs):
         assert torch.equal(o, direct[k]), k
     loss = sum((o * torch.as_tensor(cot[k]).cuda()).sum()
                for k, o in zip(("acc", "drho", "dS", "rho_sum"), outs))
     loss.backward()
     cg = {k: torch.as_tensor(v).cuda().contiguous() for k, v in cot.items()}
-    adj = P.sph_rhs_adjoint(g, st, w.params, cg)
+    # the backward reuses the forward's velocity gradient
+    adj = P.sph_rhs_adjoint(g, st, w.params, cg, vgrad=direct["vgrad"])
     for k, t in zip(("pos", "vel", "rho", "S"), leaves):
         assert torch.equal(t.grad, adj[k]), k
         assert rel(t.grad.cpu().numpy(), ref[k]) < 1e-11, k
