@@ -88,6 +88,8 @@ typedef struct {
     int32_t *slot;         /* [capacity] candidate slots, interleaved by 64 */
     int64_t capacity;
     double *x0;            /* [3 n] slot-ordered positions at build time (x, y, z per slot) */
+    int32_t *partners;     /* [n] or NULL: partners of each slot at build time (distance
+                              below the grid's h), counted by the fill */
 } sph_pairs;
 
 /* Uniform grid of cubic cells ("helping grid", section 3.5.2) produced by
@@ -280,6 +282,11 @@ int sph_build_cells(const double *x, const double *y, const double *z, int64_t n
  * then fill.  Synchronises the stream once to learn the size.
  *   out         host struct filled in; grid->pairs is set to out (keep it alive)
  *   count       device [n]; block_start device [ceil(n/64) + 1]
+ *   partners    device [n] or NULL: receives each slot's partners at build time
+ *               (distance below grid->h, the test sph_neighbours applies), so that
+ *               sph_neighbours called with grid->h at these very positions (checked
+ *               bit for bit) takes its row lengths from here instead of counting, and
+ *               writes the rows whose candidates are all partners without testing them
  *   slot        device [capacity] (may be NULL when capacity is 0)
  *   x0          device [3 n] positions at build time (slot order)
  *   needed      host, receives the number of entries (padding included)
@@ -289,9 +296,9 @@ int sph_build_cells(const double *x, const double *y, const double *z, int64_t n
  * (sph_workspace_bytes(SPH_OP_PAIRS, n, 0)), STALE_GRID (grid older than the
  * positions by more than its skin). */
 int sph_build_pairs(sph_grid *grid, const double *x, const double *y, const double *z,
-                    sph_pairs *out, int32_t *count, int64_t *block_start, int32_t *slot,
-                    int64_t capacity, double *x0, int64_t *needed, void *ws, size_t ws_bytes,
-                    void *stream);
+                    sph_pairs *out, int32_t *count, int32_t *partners, int64_t *block_start,
+                    int32_t *slot, int64_t capacity, double *x0, int64_t *needed, void *ws,
+                    size_t ws_bytes, void *stream);
 
 /* Interaction partner lists (the paper's interactionsList of section 3.5.2)
  * at the current positions: row a of the CSR holds the user indices b of all

@@ -48,7 +48,8 @@ class SphError(RuntimeError):
 
 class Pairs(C.Structure):
     _fields_ = [("n", C.c_int64), ("radius", C.c_double), ("skin", C.c_double), ("count", _vp),
-                ("block_start", _vp), ("slot", _vp), ("capacity", C.c_int64), ("x0", _vp)]
+                ("block_start", _vp), ("slot", _vp), ("capacity", C.c_int64), ("x0", _vp),
+                ("partners", _vp)]
 
 
 class Grid(C.Structure):
@@ -115,8 +116,8 @@ def lib():
         L.sph_build_cells.argtypes = [_pd, _pd, _pd, C.c_int64, P(C.c_double), P(C.c_double),
                                       C.c_double, C.c_double, C.c_int, _pd, _pd, C.c_int64, _pd,
                                       P(Grid), _pd, C.c_size_t, _vp]
-        L.sph_build_pairs.argtypes = [P(Grid), _pd, _pd, _pd, P(Pairs), _pd, _pd, _pd, C.c_int64,
-                                      _pd, P(C.c_int64), _pd, C.c_size_t, _vp]
+        L.sph_build_pairs.argtypes = [P(Grid), _pd, _pd, _pd, P(Pairs), _pd, _pd, _pd, _pd,
+                                      C.c_int64, _pd, P(C.c_int64), _pd, C.c_size_t, _vp]
         L.sph_neighbours.argtypes = [P(Grid), _pd, _pd, _pd, C.c_double, _pd, _pd, C.c_int64,
                                      P(C.c_int64), _pd, C.c_size_t, _vp]
         L.sph_rhs.argtypes = [P(Grid), P(State), P(Params), C.c_int, P(Deriv), _pd, C.c_size_t,

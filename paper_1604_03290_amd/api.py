@@ -122,7 +122,7 @@ class CellGrid:
     def __init__(self, perm, cell_start, cell_of, cstruct: L.Grid):
         self.perm, self.cell_start, self.cell_of, self.c = perm, cell_start, cell_of, cstruct
         self.ws = None
-        self.pairs = None  # (L.Pairs, count, block_start, slot, x0) when attached
+        self.pairs = None  # (L.Pairs, count, block_start, slot, x0, partners) when attached
 
     @property
     def has_pairs(self) -> bool:
@@ -184,6 +184,7 @@ def sph_build_pairs(grid: CellGrid, pos: torch.Tensor, capacity: int | None = No
     dev = pos.device
     nb = (n + 63) // 64
     count = torch.empty(n, dtype=torch.int32, device=dev)
+    partners = torch.empty(n, dtype=torch.int32, device=dev)
     block_start = torch.empty(nb + 1, dtype=torch.int64, device=dev)
     x0 = torch.empty(3 * n, dtype=F64, device=dev)
     if ws is None:
@@ -192,17 +193,18 @@ def sph_build_pairs(grid: CellGrid, pos: torch.Tensor, capacity: int | None = No
     out = L.Pairs()
     if capacity is None:
         rc = L.lib().sph_build_pairs(C.byref(grid.c), _ptr(pos[0]), _ptr(pos[1]), _ptr(pos[2]),
-                                     C.byref(out), _ptr(count), _ptr(block_start), C.c_void_p(0), 0,
+                                     C.byref(out), _ptr(count), _ptr(partners), _ptr(block_start),
+                                     C.c_void_p(0), 0,
                                      _ptr(x0), C.byref(needed), _ptr(ws), ws.numel(), _stream())
         if rc not in (L.SPH_OK, L.SPH_ERR_CAPACITY):
             L.check(rc)
         capacity = int(needed.value)
     slot = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
     L.check(L.lib().sph_build_pairs(C.byref(grid.c), _ptr(pos[0]), _ptr(pos[1]), _ptr(pos[2]),
-                                    C.byref(out), _ptr(count), _ptr(block_start), _ptr(slot),
-                                    capacity, _ptr(x0), C.byref(needed), _ptr(ws), ws.numel(),
-                                    _stream()))
-    grid.pairs = (out, count, block_start, slot, x0)
+                                    C.byref(out), _ptr(count), _ptr(partners), _ptr(block_start),
+                                    _ptr(slot), capacity, _ptr(x0), C.byref(needed), _ptr(ws),
+                                    ws.numel(), _stream()))
+    grid.pairs = (out, count, block_start, slot, x0, partners)
     grid.c.pairs = C.cast(C.pointer(out), C.c_void_p)
     return int(needed.value)
 

@@ -65,7 +65,11 @@ __global__ __launch_bounds__(kBlock) void k_order_cells(const int32_t *__restric
     for (int i = s0; i < s1; ++i) cell_of[i] = (int32_t)c;
 }
 
-__global__ void k_clear_status(int32_t *status) { *status = 0; }
+// the status flag and the header's second word (sph_neighbours' moved flag)
+__global__ void k_clear_status(int32_t *status) {
+    status[0] = 0;
+    status[1] = 0;
+}
 
 }  // namespace
 

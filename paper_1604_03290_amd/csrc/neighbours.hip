@@ -6,7 +6,10 @@
 // with a bitonic network and writes the row with whole-wavefront stores.  From the
 // pair list, one wavefront per group of 64 slots writes the group's rows unsorted
 // (tiles of the list in LDS, contiguous stores per row) and a second pass sorts each
-// row in registers.  Rows longer than kRowMax are sorted afterwards in LDS.
+// row in registers.  Rows longer than kRowMax are sorted afterwards in LDS.  When the
+// list's build counted each slot's partners at this h and no position has changed
+// since (bit for bit), those counts are the row lengths, and a slot whose candidates
+// are all partners has its list written as its row without the test.
 #include <climits>
 
 #include "common.hpp"
@@ -17,26 +20,44 @@ namespace {
 
 constexpr int kSortMax = 1024;  // longest row sorted in LDS by one wavefront
 
+// Gathers the positions into slot order; with a pair list also sets *moved when a
+// position differs, bit for bit, from the list's build-time one.
 __global__ __launch_bounds__(kBlock) void k_nb_gather(GridDev g, const double *__restrict__ x,
                                                       const double *__restrict__ y,
                                                       const double *__restrict__ z, int64_t n,
                                                       double4 *__restrict__ pos,
-                                                      int32_t *__restrict__ status) {
+                                                      int32_t *__restrict__ status,
+                                                      int32_t *__restrict__ moved) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int a = g.perm[s];
     const double px = x[a], py = y[a], pz = z[a];
     if (!within_cell(g, (int)s, px, py, pz)) raise_flag(status, SPH_ERR_STALE_GRID);
     if (!(isfinite(px) && isfinite(py) && isfinite(pz))) raise_flag(status, SPH_ERR_DOMAIN);
+    if (g.pl_x0) {
+        const double *b = g.pl_x0 + 3 * s;
+        if (__double_as_longlong(px) != __double_as_longlong(b[0]) ||
+            __double_as_longlong(py) != __double_as_longlong(b[1]) ||
+            __double_as_longlong(pz) != __double_as_longlong(b[2]))
+            *moved = 1;
+    }
     pos[s] = make_double4(px, py, pz, 0.0);
 }
 
-// partners of every slot (the exact test over its candidates), in user order
+// partners of every slot (the exact test over its candidates), in user order.  known
+// (the list's build-time partner counts, at this h) is taken instead when no position
+// has moved since the list was built (*moved == 0): the same test on the same numbers.
 __global__ __launch_bounds__(kBlock) void k_nb_count(GridDev g, const double4 *__restrict__ pos,
                                                      int64_t n, double h2, double reach,
-                                                     int64_t *__restrict__ count) {
+                                                     int64_t *__restrict__ count,
+                                                     const int32_t *__restrict__ known,
+                                                     const int32_t *__restrict__ moved) {
     const int64_t s = xcd_block(gridDim.x) * kBlock + threadIdx.x;
     if (s >= n) return;
+    if (known && *moved == 0) {
+        count[g.perm[s]] = known[s];
+        return;
+    }
     const double4 pa = pos[s];
     int64_t k = 0;
     for_each_candidate(g, s, pa.x, pa.y, pa.z, reach, [&](int t) {
@@ -180,7 +201,9 @@ constexpr int kTileSteps = 64;
 __global__ __launch_bounds__(kBlock) void k_nb_fill_list(GridDev g, const double4 *__restrict__ pos,
                                                          int64_t n, double h2,
                                                          const int64_t *__restrict__ row_ptr,
-                                                         int32_t *__restrict__ col) {
+                                                         int32_t *__restrict__ col,
+                                                         const int32_t *__restrict__ known,
+                                                         const int32_t *__restrict__ moved) {
     __shared__ int32_t lds[kBlock / 64][kTileSteps][65];
     int32_t(*tile)[65] = lds[threadIdx.x >> 6];
     const int lane = __lane_id();
@@ -195,6 +218,9 @@ __global__ __launch_bounds__(kBlock) void k_nb_fill_list(GridDev g, const double
     const int cnt = act ? g.pl_count[s] : 0;
     const int64_t r0 = act ? row_ptr[g.perm[s]] : 0;
     const int len = act ? (int)(row_ptr[g.perm[s] + 1] - r0) : 0;
+    // every candidate of this slot is a partner (known at build time, positions
+    // unchanged): its row is the list itself, written without the test
+    const bool all = known && *moved == 0 && act && known[s] == cnt;
     int k = 0;
     const int rows = (int)min<int64_t>(64, n - B * 64);
     for (int j0 = 0; j0 < steps; j0 += kTileSteps) {
@@ -205,8 +231,15 @@ __global__ __launch_bounds__(kBlock) void k_nb_fill_list(GridDev g, const double
             const int cr = __shfl(cnt, r);
             if (j0 >= cr) continue;  // wavefront-uniform
             const int64_t sr = B * 64 + r;
-            const double4 pa = pos[sr];
             const bool valid = j0 + lane < cr;
+            if (__shfl(all, r)) {  // wavefront-uniform: lanes 0 .. min(64, cr - j0) - 1 all hit
+                const int64_t rr = __shfl(r0, r);
+                const int kr = __shfl(k, r);
+                if (valid) col[rr + kr + lane] = g.perm[tile[lane][r]];
+                if (lane == r) k += min(64, cr - j0);
+                continue;
+            }
+            const double4 pa = pos[sr];
             bool hit = false;
             int32_t u = 0;
             if (valid) {
@@ -362,9 +395,14 @@ extern "C" int sph_neighbours(const sph_grid *grid, const double *x, const doubl
     GridDev g = grid_dev(grid);
     const double reach = (h + g.delta) * (1.0 + 1e-9);
     if ((rc = clear_status(ws, s))) return rc;
-    k_nb_gather<<<blocks_for(n), kBlock, 0, s>>>(g, x, y, z, n, pos, c.status());
+    // with a pair list whose build counted partners at this h: its counts, and its lists
+    // as rows, where no position has changed since
+    const int32_t *known =
+        g.pl_count && grid->pairs->partners && h == grid->h ? grid->pairs->partners : nullptr;
+    int32_t *moved = c.status() + 1;  // the header's second word, cleared with the flag
+    k_nb_gather<<<blocks_for(n), kBlock, 0, s>>>(g, x, y, z, n, pos, c.status(), moved);
     SPH_LAUNCHED();
-    k_nb_count<<<blocks_for(n), kBlock, 0, s>>>(g, pos, n, h * h, reach, count);
+    k_nb_count<<<blocks_for(n), kBlock, 0, s>>>(g, pos, n, h * h, reach, count, known, moved);
     SPH_LAUNCHED();
     if ((rc = exclusive_scan_i64(count, row_ptr, n, tmp, s))) return rc;
     int64_t nnz = 0;
@@ -380,7 +418,8 @@ extern "C" int sph_neighbours(const sph_grid *grid, const double *x, const doubl
     if (nnz == 0) return SPH_OK;
     if (g.pl_count) {
         k_nb_fill_list<<<blocks_for((n + 63) / 64, kBlock / 64), kBlock, 0, s>>>(g, pos, n, h * h,
-                                                                                row_ptr, col);
+                                                                                row_ptr, col, known,
+                                                                                moved);
         SPH_LAUNCHED();
         k_nb_sort_rows<<<blocks_for(n, kBlock / 64), kBlock, 0, s>>>(row_ptr, n, col);
         SPH_LAUNCHED();

@@ -73,7 +73,8 @@ __global__ __launch_bounds__(kBlock) void k_pl_scan(GridDev g, const double *__r
                                                     int64_t n, double r2, double reach,
                                                     int32_t *__restrict__ count,
                                                     const int64_t *__restrict__ block_start,
-                                                    int32_t *__restrict__ slot) {
+                                                    int32_t *__restrict__ slot, double h2,
+                                                    int32_t *__restrict__ partners) {
     __shared__ double lds[kBlock / 64][3][kWave];
     double(*cand)[kWave] = lds[threadIdx.x >> 6];
     const int lane = __lane_id();
@@ -89,11 +90,12 @@ __global__ __launch_bounds__(kBlock) void k_pl_scan(GridDev g, const double *__r
         base = block_start[B] + lane;
         maxc = (block_start[B + 1] - block_start[B]) / kWave;
     }
-    int c = 0;
-    auto hit = [&](int t) {
+    int c = 0, np = 0;  // candidates and, in the fill, partners (d^2 < h^2) among them
+    auto hit = [&](int t, double d) {
         // the count pass found maxc or fewer with the same test; the guard keeps a
         // write inside the group even so
         if (kFill && c < maxc) slot[base + (int64_t)kWave * c] = t;
+        if (kFill && d < h2) ++np;
         ++c;
     };
     const double bx0 = wave_min(xa), bx1 = wave_max(xa);
@@ -112,7 +114,8 @@ __global__ __launch_bounds__(kBlock) void k_pl_scan(GridDev g, const double *__r
             for_each_row(g, xa, ya, za, reach, [&](int s0, int s1) {
                 for (int t = s0; t < s1; ++t) {
                     if (t == s) continue;
-                    if (dist2_exact(xa, ya, za, x0[3 * t], x0[3 * t + 1], x0[3 * t + 2]) < r2) hit(t);
+                    const double d = dist2_exact(xa, ya, za, x0[3 * t], x0[3 * t + 1], x0[3 * t + 2]);
+                    if (d < r2) hit(t, d);
                 }
             });
     } else {
@@ -140,7 +143,7 @@ __global__ __launch_bounds__(kBlock) void k_pl_scan(GridDev g, const double *__r
                         for (int k = 0; k < m; ++k) {
                             const int tk = t0 + k;
                             const double d = dist2_exact(xa, ya, za, cand[0][k], cand[1][k], cand[2][k]);
-                            if (act && d < r2 && tk != s) hit(tk);
+                            if (act && d < r2 && tk != s) hit(tk, d);
                         }
                         wave_sync();
                     }
@@ -151,6 +154,7 @@ __global__ __launch_bounds__(kBlock) void k_pl_scan(GridDev g, const double *__r
     if (kFill) {
         const int32_t pad = act ? (int32_t)s : (int32_t)(n - 1);
         for (int64_t j = c; j < maxc; ++j) slot[base + kWave * j] = pad;
+        if (partners && act) partners[s] = np;
     } else if (act) {
         count[s] = c;
     }
@@ -182,9 +186,9 @@ size_t pairs_ws_bytes(int64_t n) {
 using namespace sph;
 
 extern "C" int sph_build_pairs(sph_grid *grid, const double *x, const double *y, const double *z,
-                               sph_pairs *out, int32_t *count, int64_t *block_start,
-                               int32_t *slot, int64_t capacity, double *x0, int64_t *needed,
-                               void *ws, size_t ws_bytes, void *stream) {
+                               sph_pairs *out, int32_t *count, int32_t *partners,
+                               int64_t *block_start, int32_t *slot, int64_t capacity, double *x0,
+                               int64_t *needed, void *ws, size_t ws_bytes, void *stream) {
     clear_error();
     int rc = check_grid(grid);
     if (rc) return rc;
@@ -210,8 +214,9 @@ extern "C" int sph_build_pairs(sph_grid *grid, const double *x, const double *y,
     if ((rc = clear_status(ws, s))) return rc;
     k_pl_gather<<<blocks_for(n), kBlock, 0, s>>>(g, x, y, z, n, x0, c.status());
     SPH_LAUNCHED();
+    const double h2 = grid->h * grid->h;  // the partner test of sph_neighbours at grid->h
     k_pl_scan<false><<<blocks_for(nb, kBlock / 64), kBlock, 0, s>>>(g, x0, n, r2, reach, count,
-                                                                      nullptr, nullptr);
+                                                                      nullptr, nullptr, h2, nullptr);
     SPH_LAUNCHED();
     k_pl_sizes<<<blocks_for(nb), kBlock, 0, s>>>(count, n, sizes);
     SPH_LAUNCHED();
@@ -227,7 +232,8 @@ extern "C" int sph_build_pairs(sph_grid *grid, const double *x, const double *y,
         return fail(SPH_ERR_CAPACITY, "pair list needs %lld entries, capacity %lld",
                     (long long)total, (long long)capacity);
     k_pl_scan<true><<<blocks_for(nb, kBlock / 64), kBlock, 0, s>>>(g, x0, n, r2, reach, count,
-                                                                     block_start, slot);
+                                                                     block_start, slot, h2,
+                                                                     partners);
     SPH_LAUNCHED();
     out->n = n;
     out->radius = radius;
@@ -237,6 +243,7 @@ extern "C" int sph_build_pairs(sph_grid *grid, const double *x, const double *y,
     out->slot = slot;
     out->capacity = capacity;
     out->x0 = x0;
+    out->partners = partners;
     grid->pairs = out;
     return SPH_OK;
 }

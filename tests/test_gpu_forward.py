@@ -142,6 +142,37 @@ def test_neighbours_bit_exact(case, cells_per_h, pairs):
     assert np.array_equal(col, col_ref)
 
 
+@pytest.mark.parametrize("case", list(CSR_CASES))
+def test_neighbours_from_the_build_time_partner_counts(case):
+    """Partner sets taken from the list build's own counts (positions unchanged, the
+    grid's h; skin 0, so nearly every row is its list) and, with the same list, the
+    exact test wherever that does not hold: one particle moved by one ulp, a smaller
+    h, and a list built at other positions.  All bit-exact against the brute force."""
+    pos = CSR_CASES[case]()
+    h = 0.3 if case in ("adversarial", "clumps") else (0.15 if case != "lattice10" else 0.24)
+    rp_ref, col_ref = native.neighbours(pos, h)
+    for cph in (1, 2):
+        rp, col, _ = gpu_csr(pos, h, cph, skin=0.0, pairs=True)
+        assert np.array_equal(rp, rp_ref) and np.array_equal(col, col_ref)
+    t = torch.as_tensor(pos, dtype=torch.float64).cuda().contiguous()
+    g = P.sph_build_cells(t, h, skin=0.02 * h, cells_per_h=2, pairs=True)
+    moved = pos.copy()
+    moved[0, 1] = np.nextafter(moved[0, 1], np.inf)
+    tm = torch.as_tensor(moved).cuda().contiguous()
+    rp, col = P.sph_neighbours(g, tm, h)
+    rp_m, col_m = native.neighbours(moved, h)
+    assert np.array_equal(rp.cpu().numpy(), rp_m) and np.array_equal(col.cpu().numpy(), col_m)
+    rp, col = P.sph_neighbours(g, t, 0.9 * h)
+    rp_s, col_s = native.neighbours(pos, 0.9 * h)
+    assert np.array_equal(rp.cpu().numpy(), rp_s) and np.array_equal(col.cpu().numpy(), col_s)
+    rng = np.random.default_rng(8)
+    old = pos + rng.uniform(-0.004, 0.004, pos.shape) * h  # within skin / 2
+    g = P.sph_build_cells(torch.as_tensor(old).cuda().contiguous(), h, skin=0.02 * h,
+                          cells_per_h=2, pairs=True)
+    rp, col = P.sph_neighbours(g, t, h)
+    assert np.array_equal(rp.cpu().numpy(), rp_ref) and np.array_equal(col.cpu().numpy(), col_ref)
+
+
 def test_neighbours_single_particle_and_capacity():
     rp, col, g = gpu_csr(np.zeros((3, 1)) + 0.5, 0.1)
     assert list(rp) == [0, 0] and col.size == 0
