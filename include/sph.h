@@ -341,7 +341,7 @@ int sph_rhs(const sph_grid *grid, const sph_state *state, const sph_params *para
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc).  Same outputs as sph_rhs (same kernels, bit for bit); its scratch is a
  * static device array of the library sized for SPH_NOALLOC_MAX_N particles (about
- * 52 MiB), which every device the library runs on holds until the process ends.  The
+ * 53 MiB), which every device the library runs on holds until the process ends.  The
  * call allocates nothing (no hipMalloc, hipFree or allocating library routine); the
  * first call on a device looks up that device's copy of the array.
  *   status  device int32 or NULL: receives the call's device flag (SPH_OK, or

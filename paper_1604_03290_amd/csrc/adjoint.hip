@@ -188,14 +188,17 @@ __global__ __launch_bounds__(64 * kSplit) void k_adj_L_list(GridDev g, int64_t n
     }
 }
 
-// post stage (see the file header)
+// post stage (see the file header); with inv (user-order state and cotangents, the
+// inverse permutation) thread i takes user particle i, reading those arrays in order
 __global__ __launch_bounds__(kBlock) void k_adj_post(GridDev g, int64_t n, Consts k,
                                                      const double *__restrict__ rec, StateDev st,
-                                                     CotDev cot, AdjRec ad) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                                     CotDev cot, AdjRec ad,
+                                                     const int32_t *__restrict__ inv) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double mu_part = 0.0;
-    if (s < n) {
-        const int a = io_index(g, s);
+    if (i < n) {
+        const int64_t s = inv ? (int64_t)inv[i] : i;
+        const int a = inv ? (int)i : io_index(g, s);
         double L[9], c6[6];
 #pragma unroll
         for (int i = 0; i < 9; ++i) L[i] = ad.L[i][s];
@@ -712,7 +715,7 @@ int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_p
     int rc;
     if (post_ready) {
         if (!L_in || !acc_parts) return fail(SPH_ERR_INVALID_ARG, "post stage not prepared");
-    } else if ((rc = prepass_launch(g, st, n, k, rec, c.status(), s))) {
+    } else if ((rc = prepass_launch(g, st, n, k, rec, c.status(), s, nullptr, ad.inv))) {
         return rc;
     }
     if (L_in) {
@@ -734,7 +737,9 @@ int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_p
         SPH_LAUNCHED();
     }
     if (!post_ready) {
-        k_adj_post<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, cot, ad);
+        // the prepass filled ad.inv when the state is in user order
+        k_adj_post<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, cot, ad,
+                                                    g.io ? ad.inv : nullptr);
         SPH_LAUNCHED();
     }
     {

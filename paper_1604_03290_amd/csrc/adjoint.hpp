@@ -21,6 +21,7 @@ struct AdjRec {
     double *part_mu;   // per-block partial sums (ceil(n / 256))
     double *part_y0;   // per block, or per wavefront for the list kernel (ceil(n / 64))
     double *ext[4];    // cotangents of du and dx/dt (slot order), when given
+    int32_t *inv;      // slot of every user index (the inverse of the grid's perm)
     int add_parts;     // add the block sums to part_* instead of writing them
 };
 
@@ -35,6 +36,7 @@ inline AdjRec carve_adj(Carve &c, int64_t n) {
     r.part_mu = c.take<double>(blocks_for(n));
     r.part_y0 = c.take<double>(blocks_for(n, 64));
     for (int i = 0; i < 4; ++i) r.ext[i] = c.take<double>(n);
+    r.inv = c.take<int32_t>(n);
     r.add_parts = 0;
     return r;
 }

@@ -27,14 +27,25 @@ namespace sph {
 namespace {
 
 // --------------------------------------------------------------- prepass --
-// dd3 / nact (null unless requested): the damage model's rates (section 3.2)
+// the slot of every user index: inv[perm[s]] = s
+__global__ __launch_bounds__(kBlock) void k_invert(const int32_t *__restrict__ perm, int64_t n,
+                                                   int32_t *__restrict__ inv) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) inv[perm[s]] = (int32_t)s;
+}
+
+// dd3 / nact (null unless requested): the damage model's rates (section 3.2).  With
+// inv (user-order state, its inverse permutation) thread i takes user particle i, so
+// the state arrays are read in order and each thread writes its slot's whole 128-byte
+// record; without it (slot-ordered state) thread i takes slot i.
 __global__ __launch_bounds__(kBlock) void k_prepass(GridDev g, StateDev st, int64_t n, Consts k,
                                                     double *__restrict__ rec,
                                                     int32_t *__restrict__ status, double *dd3,
-                                                    int32_t *nact) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const int a = io_index(g, s);
+                                                    int32_t *nact, const int32_t *__restrict__ inv) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t s = inv ? (int64_t)inv[i] : i;
+    const int a = inv ? (int)i : io_index(g, s);
     const double S[6] = {st.sxx[a], st.syy[a], st.szz[a], st.sxy[a], st.sxz[a], st.syz[a]};
     const double d = st.d ? st.d[a] : 0.0, rho = st.rho[a], m = st.m[a];
     const double p = write_rec(g, k, s, st.x[a], st.y[a], st.z[a], st.vx[a], st.vy[a], st.vz[a],
@@ -336,9 +347,15 @@ __global__ __launch_bounds__(64 * kSplit) void k_pairs32_list(GridDev g, int64_t
 }  // namespace
 
 int prepass_launch(const GridDev &g, const StateDev &st, int64_t n, const Consts &k, double *rec,
-                   int32_t *status, hipStream_t s, const OutDev *od) {
+                   int32_t *status, hipStream_t s, const OutDev *od, int32_t *inv) {
+    if (g.io && inv) {
+        k_invert<<<blocks_for(n), kBlock, 0, s>>>(g.io, n, inv);
+        SPH_LAUNCHED();
+    } else {
+        inv = nullptr;
+    }
     k_prepass<<<blocks_for(n), kBlock, 0, s>>>(g, st, n, k, rec, status, od ? od->dd3 : nullptr,
-                                               od ? od->n_act : nullptr);
+                                               od ? od->n_act : nullptr, inv);
     SPH_LAUNCHED();
     return SPH_OK;
 }
@@ -347,6 +364,7 @@ size_t rhs_ws_bytes(int64_t n) {
     Carve c(nullptr);
     c.take<double>((size_t)n * kRec);
     c.take<float>((size_t)n * kRec32);
+    c.take<int32_t>(n);
     return c.used;
 }
 
@@ -424,12 +442,13 @@ int rhs_launch(const sph_grid *grid, const sph_state *state, const sph_params *p
     double *rec = rhs_rec_of(c, n);
     c.take<double>((size_t)n * kRec);
     float *r32 = c.take<float>((size_t)n * kRec32);
+    int32_t *inv = c.take<int32_t>(n);
     StateDev st = state_dev(state);
     OutDev od = out_dev(out);
     int rc;
     if (od.dd3 && rec_ready)
         return fail(SPH_ERR_NOT_IMPLEMENTED, "damage rates need the prepass");
-    if (!rec_ready && (rc = prepass_launch(g, st, n, k, rec, c.status(), s, &od))) return rc;
+    if (!rec_ready && (rc = prepass_launch(g, st, n, k, rec, c.status(), s, &od, inv))) return rc;
     const bool ext = k.eps_s > 0.0 || od.du || od.dx || k.eos != 0;
     if (precision == SPH_FP64) {
         TimedRegion t(timed ? "pairs_fp64" : nullptr, s);
@@ -486,8 +505,9 @@ int rhs_launch(const sph_grid *grid, const sph_state *state, const sph_params *p
 // particles (status word, FP64 operand records, FP32 records), held by every device
 // the library runs on until the process ends.
 constexpr int64_t kNoallocMaxN = SPH_NOALLOC_MAX_N;
-constexpr size_t kNoallocBytes =
-    kAlign + (size_t)kNoallocMaxN * kRec * sizeof(double) + (size_t)kNoallocMaxN * kRec32 * sizeof(float);
+constexpr size_t kNoallocBytes = kAlign + (size_t)kNoallocMaxN * kRec * sizeof(double) +
+                                 (size_t)kNoallocMaxN * kRec32 * sizeof(float) +
+                                 (size_t)kNoallocMaxN * sizeof(int32_t);
 static_assert(kNoallocMaxN % 64 == 0, "record arrays stay 256-byte aligned");
 __device__ __align__(256) unsigned char scratch[kNoallocBytes];
 

@@ -915,8 +915,11 @@ int reduce_params_launch(const double *p0, int64_t m0, const double *p1, int64_t
 
 // rhs.hip
 // od (nullable): outputs whose dd3 / n_act, when set, receive the damage rates
+// inv (nullable): n int32 of scratch; with a user-ordered state the prepass fills it with
+// the inverse permutation and reads the state in user order
 int prepass_launch(const GridDev &g, const StateDev &st, int64_t n, const Consts &k, double *rec,
-                   int32_t *status, hipStream_t s, const OutDev *od = nullptr);
+                   int32_t *status, hipStream_t s, const OutDev *od = nullptr,
+                   int32_t *inv = nullptr);
 int check_state(const sph_grid *grid, const sph_state *st);
 int check_params(const sph_grid *grid, const sph_params *pr);
 int check_deriv(const sph_deriv *o);
