@@ -375,6 +375,33 @@ def single_state_step(args, w, torch, P, L):
     return result, sample
 
 
+def fp32_accuracy_section(w, torch, P, reps=5):
+    """The bullet-into-cube set: FP64 and FP32-compensated right-hand sides on the pair
+    list, and the FP32 form's normwise error per output against the FP64 GPU path and
+    against the oracle on 4,096 sampled targets (the FP64 path's error beside it)."""
+    from oracle import native
+    st = P.ParticleState.from_arrays(w.pos, w.vel, w.rho, w.S, w.m, "cuda")
+    g = P.sph_build_cells(st.pos, w.h, skin=0.0, cells_per_h=CELLS_PER_H, pairs=True)
+    ws = P.workspace(P.api.L.SPH_OP_RHS, w.n)
+    outs, res = {}, {"particles": w.n, "state": w.name}
+    for form in ("fp64", "fp32comp"):
+        o = P.api.new_deriv(w.n)
+        ms = median_ms(lambda: P.sph_rhs(g, st, w.params, form, out=o, ws=ws), reps, torch)
+        outs[form] = o
+        res[f"rhs_{form}_ms"] = ms
+    fields = ("acc", "drho", "dS", "rho_sum")
+    res["fp32comp_normwise_error_vs_fp64_gpu"] = {
+        k: float((outs["fp32comp"][k] - outs["fp64"][k]).abs().max() / outs["fp64"][k].abs().max())
+        for k in fields}
+    idx, csr = oracle_targets(w)
+    ref = native.rhs(w.pos, w.vel, w.rho, w.S, w.m, w.param_vector(), targets=idx, csr=csr, want_L=False)
+    it = torch.as_tensor(idx, device="cuda")
+    for form in ("fp64", "fp32comp"):
+        res[f"{form}_normwise_error_vs_oracle_4096_targets"] = {
+            k: normwise(outs[form][k][..., it].cpu().numpy(), ref[k]) for k in fields}
+    return res
+
+
 def two_spheres_section(args, w, torch, P, L, full_forms=True):
     """The two-sphere collision: cell build, list, CSR, 10-step leapfrog (11 FP64 right-
     hand sides) and its reverse sweep (11 adjoints) for d KE / d (v0, mu, Y0), with the
@@ -543,8 +570,14 @@ def main():
     if sample is not None:
         log("cpu baseline")
         result["cpu_baseline"] = cpu_baseline(w, *sample)
-    if not args.no_two_spheres:
         del w
+        torch.cuda.empty_cache()
+        log("bullet into cube: FP32-compensated accuracy")
+        result["bullet_into_cube_2105344"] = {
+            state: fp32_accuracy_section(W.config(2, state=state), torch, P)
+            for state in ("impact", "random")}
+    if not args.no_two_spheres:
+        w = None
         torch.cuda.empty_cache()
         log("two-sphere collision section")
         result["two_spheres_262144"] = two_spheres_section(args, W.config(1), torch, P, L)

@@ -69,42 +69,67 @@ __global__ __launch_bounds__(kBlock) void k_nb_count(GridDev g, const double4 *_
 
 constexpr int kRowMax = 256;  // longest row sorted in registers (4 per lane)
 
+// The value of lane (lane ^ J): lane-pair moves within a quad by DPP for J = 1, 2 (no
+// LDS round trip), the swizzle unit's XOR mode inside 32 lanes for J = 4, 8, 16, and a
+// backwards permute for J = 32.
+template <int J>
+__device__ inline int32_t xor_lane(int32_t v) {
+    if constexpr (J == 1)
+        return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+    else if constexpr (J == 2)
+        return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+    else if constexpr (J == 4 || J == 8 || J == 16)
+        return __builtin_amdgcn_ds_swizzle(v, 0x1F | (J << 10));  // and 31, or 0, xor J
+    else
+        return __shfl_xor(v, J);
+}
+
 // Bitonic sort, ascending, of the 64 E values v[e] (value i = 64 e + lane) held by
 // one wavefront.
-template <int E>
-__device__ inline void wave_bitonic(int32_t (&v)[E]) {
-    const int lane = __lane_id();
+template <int J, int K, int E>
+__device__ inline void bitonic_lanes(int32_t (&v)[E], int lane) {
 #pragma unroll
-    for (int k = 2; k <= 64 * E; k <<= 1) {
+    for (int e = 0; e < E; ++e) {
+        const int i = 64 * e + lane;
+        const int32_t o = xor_lane<J>(v[e]);
+        const bool up = (i & K) == 0;
+        const bool lower = (lane & J) == 0;  // i < partner
+        // the lower index keeps the min when ascending, the max otherwise
+        const bool take_min = lower == up;
+        v[e] = take_min ? min(v[e], o) : max(v[e], o);
+    }
+}
+
+template <int K, int J, int E>
+__device__ inline void bitonic_stage(int32_t (&v)[E], int lane) {
+    if constexpr (J >= 64) {
+        constexpr int je = J >> 6;
 #pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            if (j >= 64) {
-                const int je = j >> 6;
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    const int f = e ^ je;
-                    if (f > e) {
-                        const bool up = (((64 * e + lane) & k) == 0);
-                        const int32_t a = v[e], b = v[f];
-                        const bool sw = up ? (a > b) : (a < b);
-                        v[e] = sw ? b : a;
-                        v[f] = sw ? a : b;
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    const int i = 64 * e + lane;
-                    const int32_t o = __shfl_xor(v[e], j);
-                    const bool up = (i & k) == 0;
-                    const bool lower = (lane & j) == 0;  // i < partner
-                    // the lower index keeps the min when ascending, the max otherwise
-                    const bool take_min = lower == up;
-                    v[e] = take_min ? min(v[e], o) : max(v[e], o);
-                }
+        for (int e = 0; e < E; ++e) {
+            const int f = e ^ je;
+            if (f > e) {
+                const bool up = (((64 * e + lane) & K) == 0);
+                const int32_t a = v[e], b = v[f];
+                const bool sw = up ? (a > b) : (a < b);
+                v[e] = sw ? b : a;
+                v[f] = sw ? a : b;
             }
         }
+    } else {
+        bitonic_lanes<J, K, E>(v, lane);
     }
+    if constexpr (J > 1) bitonic_stage<K, J / 2, E>(v, lane);
+}
+
+template <int K, int E>
+__device__ inline void bitonic_merges(int32_t (&v)[E], int lane) {
+    bitonic_stage<K, K / 2, E>(v, lane);
+    if constexpr (K < 64 * E) bitonic_merges<2 * K, E>(v, lane);
+}
+
+template <int E>
+__device__ inline void wave_bitonic(int32_t (&v)[E]) {
+    bitonic_merges<2, E>(v, __lane_id());
 }
 
 template <int E>
@@ -198,6 +223,13 @@ __global__ __launch_bounds__(kBlock) void k_nb_rows(GridDev g, const double4 *__
 // store).  The rows are sorted afterwards by k_nb_sort_rows.
 constexpr int kTileSteps = 64;
 
+// lane r's value of a 64-bit quantity, as a scalar (r wavefront-uniform)
+__device__ inline int64_t lane_value64(int64_t v, int r) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, r);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), r);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 __global__ __launch_bounds__(kBlock) void k_nb_fill_list(GridDev g, const double4 *__restrict__ pos,
                                                          int64_t n, double h2,
                                                          const int64_t *__restrict__ row_ptr,
@@ -227,14 +259,15 @@ __global__ __launch_bounds__(kBlock) void k_nb_fill_list(GridDev g, const double
         const int m = min(kTileSteps, steps - j0);
         for (int jj = 0; jj < m; ++jj) tile[jj][lane] = g.pl_slot[base + ((int64_t)(j0 + jj) << 6) + lane];
         wave_sync();
-        for (int r = 0; r < rows; ++r) {
-            const int cr = __shfl(cnt, r);
+        for (int r = 0; r < rows; ++r) {  // row r's values come from lane r (scalar reads)
+            const int cr = __builtin_amdgcn_readlane(cnt, r);
             if (j0 >= cr) continue;  // wavefront-uniform
             const int64_t sr = B * 64 + r;
             const bool valid = j0 + lane < cr;
-            if (__shfl(all, r)) {  // wavefront-uniform: lanes 0 .. min(64, cr - j0) - 1 all hit
-                const int64_t rr = __shfl(r0, r);
-                const int kr = __shfl(k, r);
+            const int kr = __builtin_amdgcn_readlane(k, r);
+            const int64_t rr = lane_value64(r0, r);
+            if (__builtin_amdgcn_readlane((int)all, r)) {
+                // lanes 0 .. min(64, cr - j0) - 1 all hit
                 if (valid) col[rr + kr + lane] = g.perm[tile[lane][r]];
                 if (lane == r) k += min(64, cr - j0);
                 continue;
@@ -249,9 +282,7 @@ __global__ __launch_bounds__(kBlock) void k_nb_fill_list(GridDev g, const double
                 u = g.perm[t];
             }
             const unsigned long long mk = __ballot(hit);
-            const int kr = __shfl(k, r);
-            const int lr = __shfl(len, r);
-            const int64_t rr = __shfl(r0, r);
+            const int lr = __builtin_amdgcn_readlane(len, r);
             if (hit) {
                 const int at = kr + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mk >> 32),
                                                                     __builtin_amdgcn_mbcnt_lo((unsigned)mk, 0));

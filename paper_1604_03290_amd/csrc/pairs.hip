@@ -55,14 +55,14 @@ __device__ inline double wave_max(double v) {
 }
 
 // Count pass (kFill = false) or fill pass, one wavefront per group of 64 slots.
-// Candidates are met in the order of the cell rows (z, then y, increasing), x
-// increasing along a row and slots increasing inside a cell: the order of
-// for_each_row, so each list holds its slot's candidates in the order a cell sweep
-// meets them.  A compact group sweeps the cell region of its bounding box widened
+// A compact group sweeps the cell region of its bounding box widened
 // by the reach once, cooperatively: the 64 lanes load 64 candidate positions with
 // one coalesced load into LDS, then each lane tests all of them against its own
 // slot (broadcast reads).  A group spread over a region of more than kSpread times
-// one slot's cells (sparse parts of a set) sweeps per lane instead.  The fill
+// one slot's cells (sparse parts of a set) sweeps per lane instead (in the order of
+// for_each_row).  The compact sweep meets the cell rows from the middle of the
+// region outwards (z, then y), x increasing along a row and slots increasing inside a
+// cell, and each list holds its slot's candidates in that order.  The fill
 // writes entry j of lane l at block_start[B] + 64 j + l and pads every list to the
 // group's longest with the slot itself (n - 1 for the lanes past n), so every entry
 // of a group is a valid slot and readers of whole groups load without guards.
@@ -120,10 +120,18 @@ __global__ __launch_bounds__(kBlock) void k_pl_scan(GridDev g, const double *__r
             });
     } else {
         const double rr = reach * reach;
-        for (int iz = z0; iz <= z1; ++iz) {
+        // rows from the middle of the region outwards (z, then y): the lanes of the
+        // group then meet their partners at more even rates, so that the rows of the
+        // list they fill together are completed sooner
+        const int zc = (z0 + z1) >> 1, yc = (y0 + y1) >> 1;
+        for (int i = 0; i < 2 * (z1 - z0 + 1); ++i) {
+            const int iz = zc + ((i & 1) ? -((i + 1) >> 1) : (i >> 1));
+            if (iz < z0 || iz > z1) continue;
             const double gz = box_gap(bz0, bz1, g.loz, g.cell, iz, g.nz);
             if (gz * gz >= rr) continue;
-            for (int iy = y0; iy <= y1; ++iy) {
+            for (int j = 0; j < 2 * (y1 - y0 + 1); ++j) {
+                const int iy = yc + ((j & 1) ? -((j + 1) >> 1) : (j >> 1));
+                if (iy < y0 || iy > y1) continue;
                 const double gy = box_gap(by0, by1, g.loy, g.cell, iy, g.ny);
                 const double d2 = gz * gz + gy * gy;
                 if (d2 >= rr) continue;
@@ -139,11 +147,25 @@ __global__ __launch_bounds__(kBlock) void k_pl_scan(GridDev g, const double *__r
                             cand[2][lane] = x0[3 * (int64_t)t + 2];
                         }
                         wave_sync();
-                        const int m = min(kWave, s1 - t0);
-                        for (int k = 0; k < m; ++k) {
-                            const int tk = t0 + k;
-                            const double d = dist2_exact(xa, ya, za, cand[0][k], cand[1][k], cand[2][k]);
-                            if (act && d < r2 && tk != s) hit(tk, d);
+                        const int m = __builtin_amdgcn_readfirstlane(min(kWave, s1 - t0));
+                        // a batch holding none of the group's own slots needs no self test
+                        const bool own = t0 < B * kWave + kWave && t0 + m > B * kWave;
+                        if (!kFill && !own) {
+                            // count pass: branch-free
+#pragma unroll 2
+                            for (int k = 0; k < m; ++k)
+                                c += dist2_exact(xa, ya, za, cand[0][k], cand[1][k], cand[2][k]) < r2;
+                        } else if (!own) {
+                            for (int k = 0; k < m; ++k) {
+                                const double d = dist2_exact(xa, ya, za, cand[0][k], cand[1][k], cand[2][k]);
+                                if (act && d < r2) hit(t0 + k, d);
+                            }
+                        } else {
+                            for (int k = 0; k < m; ++k) {
+                                const int tk = t0 + k;
+                                const double d = dist2_exact(xa, ya, za, cand[0][k], cand[1][k], cand[2][k]);
+                                if (act && d < r2 && tk != s) hit(tk, d);
+                            }
                         }
                         wave_sync();
                     }
