@@ -76,9 +76,12 @@ enum sph_op {
  * section 3.5.2 widened by the grid's skin): for every slot s, the slots whose
  * distance was below h + skin at build time.  Slots are grouped by 64; inside
  * group B the j-th candidate of slot s = 64 B + l is slot[block_start[B] + 64 j
- * + l] for j < count[s]; each group is padded to its longest list with the
- * slot itself (n - 1 for the lanes of the last group past n), so every entry is
- * a valid slot.  All arrays are device arrays owned by the caller. */
+ * + l] for j < count[s]; each group's lists are padded to its longest (the group's
+ * steps: the largest count among its slots) with the slot itself (n - 1 for the
+ * lanes of the last group past n), so every entry of those steps is a valid slot.
+ * The group's room, block_start[B + 1] - block_start[B], is 64 times the largest
+ * upper bound of its slots' counts and may exceed 64 times its steps; entries past
+ * the steps are not written.  All arrays are device arrays owned by the caller. */
 typedef struct {
     int64_t n;             /* slots */
     double radius;         /* h + skin at build time */
@@ -278,8 +281,10 @@ int sph_build_cells(const double *x, const double *y, const double *z, int64_t n
 
 /* Frozen candidate-pair list for the grid's slots at the current positions
  * (the paper's interaction list of section 3.5.2, widened by the grid's skin so
- * it can be reused while particles move): count pass, per-group sizes and scan,
- * then fill.  Synchronises the stream once to learn the size.
+ * it can be reused while particles move): a bound pass (each slot's bound: the
+ * slots of the cells within reach of it, no distance test), per-group room and scan,
+ * then one pass that tests the candidates and writes them.  Synchronises the stream
+ * once to learn the size.
  *   out         host struct filled in; grid->pairs is set to out (keep it alive)
  *   count       device [n]; block_start device [ceil(n/64) + 1]
  *   partners    device [n] or NULL: receives each slot's partners at build time
@@ -289,7 +294,8 @@ int sph_build_cells(const double *x, const double *y, const double *z, int64_t n
  *               writes the rows whose candidates are all partners without testing them
  *   slot        device [capacity] (may be NULL when capacity is 0)
  *   x0          device [3 n] positions at build time (slot order)
- *   needed      host, receives the number of entries (padding included)
+ *   needed      host, receives the number of entries of room the list takes
+ *               (64 times the largest bound of each group, summed)
  * Later calls flag SPH_ERR_STALE_GRID when a particle has moved by more than
  * skin / 2 since this build.  Errors: INVALID_ARG, CAPACITY (needed >
  * capacity; nothing is filled and grid->pairs is unchanged), WORKSPACE

@@ -137,8 +137,8 @@ __global__ __launch_bounds__(64 * kSplit) void k_adj_L_list(GridDev g, int64_t n
     const int64_t s = w0 + __lane_id();
     const bool act = s < n;
     const int64_t base = g.pl_block[w];
-    const int steps = (int)((g.pl_block[w + 1] - base) >> 6);
     const int cnt = act ? g.pl_count[s] : 0;
+    const int steps = list_steps(cnt);
     double2 p0 = make_double2(0, 0), p1 = p0, p2 = p0;
     if (act) {
         const double2 *ra = rec2(rec, s);
@@ -572,8 +572,8 @@ __global__ __launch_bounds__(64 * kSplitAdj) void k_adj_pairs_list(GridDev g, in
     const int64_t s = w0 + __lane_id();
     const bool act = s < n;
     const int64_t base = g.pl_block[w];
-    const int steps = (int)((g.pl_block[w + 1] - base) >> 6);
     const int cnt = act ? g.pl_count[s] : 0;
+    const int steps = list_steps(cnt);
     const AdjOwn o = adj_own(rec, ad, act ? s : w0);
     AdjAcc acc;
     double xo[4] = {0, 0, 0, 0};

@@ -243,11 +243,11 @@ __global__ __launch_bounds__(kBlock) void k_nb_fill_list(GridDev g, const double
     const int64_t B = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     if (B >= nb) return;
     const int64_t base = g.pl_block[B];
-    const int steps = (int)((g.pl_block[B + 1] - base) >> 6);
     const int64_t s = B * 64 + lane;
     const bool act = s < n;
     // this lane's row: candidates, output offset, length; k = partners written so far
     const int cnt = act ? g.pl_count[s] : 0;
+    const int steps = list_steps(cnt);
     const int64_t r0 = act ? row_ptr[g.perm[s]] : 0;
     const int len = act ? (int)(row_ptr[g.perm[s] + 1] - r0) : 0;
     // every candidate of this slot is a partner (known at build time, positions

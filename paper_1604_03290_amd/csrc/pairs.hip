@@ -6,8 +6,11 @@
 //
 // Layout: slots are grouped in blocks of 64 (one wavefront); inside block B the
 // j-th candidate of the block's lane l sits at slot[block_start[B] + 64 j + l],
-// so the j-th loads of a wavefront are contiguous.  Each block is padded to its
-// longest list.
+// so the j-th loads of a wavefront are contiguous.  Each block's lists are padded to
+// its longest, whose length (the largest count of its 64 slots) is the block's number
+// of steps.  A block's room, 64 times the largest bound of its slots (the slots of the
+// cells within reach of each slot, counted without a distance test), is fixed before
+// the one pass that tests and writes the candidates, so no count pass is needed.
 #include "common.hpp"
 #include "rhs_common.hpp"
 
@@ -54,7 +57,21 @@ __device__ inline double wave_max(double v) {
     return v;
 }
 
-// Count pass (kFill = false) or fill pass, one wavefront per group of 64 slots.
+// Upper bound of every slot's candidates: the slots of the cells within reach of its
+// position (each candidate lies in one of them, within delta of its cell's box), self
+// included.
+__global__ __launch_bounds__(kBlock) void k_pl_bound(GridDev g, const double *__restrict__ x0,
+                                                     int64_t n, double reach,
+                                                     int32_t *__restrict__ bound) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    int b = 0;
+    for_each_row(g, x0[3 * s], x0[3 * s + 1], x0[3 * s + 2], reach,
+                 [&](int s0, int s1) { b += s1 - s0; });
+    bound[s] = b;
+}
+
+// Fill pass, one wavefront per group of 64 slots.
 // A compact group sweeps the cell region of its bounding box widened
 // by the reach once, cooperatively: the 64 lanes load 64 candidate positions with
 // one coalesced load into LDS, then each lane tests all of them against its own
@@ -63,13 +80,13 @@ __device__ inline double wave_max(double v) {
 // for_each_row).  The compact sweep meets the cell rows from the middle of the
 // region outwards (z, then y), x increasing along a row and slots increasing inside a
 // cell, and each list holds its slot's candidates in that order.  The fill
-// writes entry j of lane l at block_start[B] + 64 j + l and pads every list to the
+// writes entry j of lane l at block_start[B] + 64 j + l, pads every list to the
 // group's longest with the slot itself (n - 1 for the lanes past n), so every entry
-// of a group is a valid slot and readers of whole groups load without guards.
+// of a group's steps is a valid slot and readers of whole groups load without guards,
+// and writes each slot's count.
 constexpr double kSpread = 8.0;
 
-template <bool kFill>
-__global__ __launch_bounds__(kBlock) void k_pl_scan(GridDev g, const double *__restrict__ x0,
+__global__ __launch_bounds__(kBlock) void k_pl_fill(GridDev g, const double *__restrict__ x0,
                                                     int64_t n, double r2, double reach,
                                                     int32_t *__restrict__ count,
                                                     const int64_t *__restrict__ block_start,
@@ -85,17 +102,14 @@ __global__ __launch_bounds__(kBlock) void k_pl_scan(GridDev g, const double *__r
     const bool act = s < n;
     const int64_t sa = act ? s : B * kWave;  // lanes past n stand on the group's first slot
     const double xa = x0[3 * sa], ya = x0[3 * sa + 1], za = x0[3 * sa + 2];
-    int64_t base = 0, maxc = 0;
-    if (kFill) {
-        base = block_start[B] + lane;
-        maxc = (block_start[B + 1] - block_start[B]) / kWave;
-    }
-    int c = 0, np = 0;  // candidates and, in the fill, partners (d^2 < h^2) among them
+    const int64_t base = block_start[B] + lane;
+    const int64_t room = (block_start[B + 1] - block_start[B]) / kWave;
+    int c = 0, np = 0;  // candidates and partners (d^2 < h^2) among them
     auto hit = [&](int t, double d) {
-        // the count pass found maxc or fewer with the same test; the guard keeps a
-        // write inside the group even so
-        if (kFill && c < maxc) slot[base + (int64_t)kWave * c] = t;
-        if (kFill && d < h2) ++np;
+        // the bound pass gave room for every candidate; the guard keeps a write
+        // inside the group even so
+        if (c < room) slot[base + (int64_t)kWave * c] = t;
+        if (d < h2) ++np;
         ++c;
     };
     const double bx0 = wave_min(xa), bx1 = wave_max(xa);
@@ -150,12 +164,7 @@ __global__ __launch_bounds__(kBlock) void k_pl_scan(GridDev g, const double *__r
                         const int m = __builtin_amdgcn_readfirstlane(min(kWave, s1 - t0));
                         // a batch holding none of the group's own slots needs no self test
                         const bool own = t0 < B * kWave + kWave && t0 + m > B * kWave;
-                        if (!kFill && !own) {
-                            // count pass: branch-free
-#pragma unroll 2
-                            for (int k = 0; k < m; ++k)
-                                c += dist2_exact(xa, ya, za, cand[0][k], cand[1][k], cand[2][k]) < r2;
-                        } else if (!own) {
+                        if (!own) {
                             for (int k = 0; k < m; ++k) {
                                 const double d = dist2_exact(xa, ya, za, cand[0][k], cand[1][k], cand[2][k]);
                                 if (act && d < r2) hit(t0 + k, d);
@@ -173,16 +182,19 @@ __global__ __launch_bounds__(kBlock) void k_pl_scan(GridDev g, const double *__r
             }
         }
     }
-    if (kFill) {
-        const int32_t pad = act ? (int32_t)s : (int32_t)(n - 1);
-        for (int64_t j = c; j < maxc; ++j) slot[base + kWave * j] = pad;
-        if (partners && act) partners[s] = np;
-    } else if (act) {
+    // the group's steps: its longest list (at most its room)
+    int steps = min((int64_t)c, room);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) steps = max(steps, __shfl_xor(steps, o));
+    const int32_t pad = act ? (int32_t)s : (int32_t)(n - 1);
+    for (int64_t j = c; j < steps; ++j) slot[base + kWave * j] = pad;
+    if (act) {
         count[s] = c;
+        if (partners) partners[s] = np;
     }
 }
 
-// sizes[B] = 64 * (longest list of block B)
+// sizes[B] = 64 * (largest bound of block B)
 __global__ __launch_bounds__(kBlock) void k_pl_sizes(const int32_t *__restrict__ count, int64_t n,
                                                      int64_t *__restrict__ sizes) {
     const int64_t B = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -237,8 +249,8 @@ extern "C" int sph_build_pairs(sph_grid *grid, const double *x, const double *y,
     k_pl_gather<<<blocks_for(n), kBlock, 0, s>>>(g, x, y, z, n, x0, c.status());
     SPH_LAUNCHED();
     const double h2 = grid->h * grid->h;  // the partner test of sph_neighbours at grid->h
-    k_pl_scan<false><<<blocks_for(nb, kBlock / 64), kBlock, 0, s>>>(g, x0, n, r2, reach, count,
-                                                                      nullptr, nullptr, h2, nullptr);
+    // bounds into count (the fill overwrites them with the counts)
+    k_pl_bound<<<blocks_for(n), kBlock, 0, s>>>(g, x0, n, reach, count);
     SPH_LAUNCHED();
     k_pl_sizes<<<blocks_for(nb), kBlock, 0, s>>>(count, n, sizes);
     SPH_LAUNCHED();
@@ -253,9 +265,8 @@ extern "C" int sph_build_pairs(sph_grid *grid, const double *x, const double *y,
     if (total > capacity)
         return fail(SPH_ERR_CAPACITY, "pair list needs %lld entries, capacity %lld",
                     (long long)total, (long long)capacity);
-    k_pl_scan<true><<<blocks_for(nb, kBlock / 64), kBlock, 0, s>>>(g, x0, n, r2, reach, count,
-                                                                     block_start, slot, h2,
-                                                                     partners);
+    k_pl_fill<<<blocks_for(nb, kBlock / 64), kBlock, 0, s>>>(g, x0, n, r2, reach, count,
+                                                              block_start, slot, h2, partners);
     SPH_LAUNCHED();
     out->n = n;
     out->radius = radius;

@@ -135,8 +135,8 @@ __global__ __launch_bounds__(64 * kSplit) void k_pairs64_list(GridDev g, int64_t
     const int64_t s = w0 + __lane_id();
     const bool act = s < n;
     const int64_t base = g.pl_block[w];
-    const int steps = (int)((g.pl_block[w + 1] - base) >> 6);
     const int cnt = act ? g.pl_count[s] : 0;
+    const int steps = list_steps(cnt);
     double2 p0 = make_double2(0, 0), p1 = p0, p2 = p0, p3 = p0, p4 = p0, p5 = p0, p6 = p0, p7 = p0;
     if (act) {
         const double2 *ra = rec2(rec, s);
@@ -313,8 +313,8 @@ __global__ __launch_bounds__(64 * kSplit) void k_pairs32_list(GridDev g, int64_t
     const int64_t s = w0 + __lane_id();
     const bool act = s < n;
     const int64_t base = g.pl_block[w];
-    const int steps = (int)((g.pl_block[w + 1] - base) >> 6);
     const int cnt = act ? g.pl_count[s] : 0;
+    const int steps = list_steps(cnt);
     const Src32 a = load32(r32, act ? s : w0);
     const Consts32 kf = narrow(k);
     Acc32 acc;

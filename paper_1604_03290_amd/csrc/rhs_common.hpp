@@ -156,6 +156,14 @@ __device__ inline void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 // doubles, in rounds of Cap / (64 (P - 1)) values), wavefront 0 adds them.  Every thread
 // of the workgroup calls it; it starts with a workgroup barrier, so scratch may alias
 // buffers that the wavefronts read before the call.
+// Steps of a block of the pair list: the longest of its 64 lists (each lane holding
+// its slot's count, 0 past the end).
+__device__ inline int list_steps(int cnt) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) cnt = max(cnt, __shfl_xor(cnt, o));
+    return __builtin_amdgcn_readfirstlane(cnt);
+}
+
 constexpr int kSplit = 4;     // wavefronts per block in the forward list kernels
 constexpr int kSplitAdj = 4;  // and in the adjoint's pair kernel
 
