@@ -255,10 +255,36 @@ __global__ __launch_bounds__(kBlock) void k_nb_fill_list(GridDev g, const double
     const bool all = known && *moved == 0 && act && known[s] == cnt;
     int k = 0;
     const int rows = (int)min<int64_t>(64, n - B * 64);
+    // every row of the group is its list: rows go four at a time (four gathers of user
+    // indices in flight per lane)
+    const bool group_all = __ballot(act && !all) == 0;
     for (int j0 = 0; j0 < steps; j0 += kTileSteps) {
         const int m = min(kTileSteps, steps - j0);
         for (int jj = 0; jj < m; ++jj) tile[jj][lane] = g.pl_slot[base + ((int64_t)(j0 + jj) << 6) + lane];
         wave_sync();
+        if (group_all) {
+            for (int r = 0; r < rows; r += 4) {
+                int cr[4];
+                int32_t u[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    cr[q] = r + q < rows ? __builtin_amdgcn_readlane(cnt, r + q) : 0;
+                    u[q] = j0 + lane < cr[q] ? g.perm[tile[lane][r + q]] : 0;
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (j0 >= cr[q]) continue;  // wavefront-uniform (also past the rows)
+                    const int64_t rr = lane_value64(r0, r + q);
+                    const int kr = __builtin_amdgcn_readlane(k, r + q);
+                    if (j0 + lane < cr[q]) col[rr + kr + lane] = u[q];
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (lane == r + q && j0 < cr[q]) k += min(64, cr[q] - j0);
+            }
+            wave_sync();
+            continue;
+        }
         for (int r = 0; r < rows; ++r) {  // row r's values come from lane r (scalar reads)
             const int cr = __builtin_amdgcn_readlane(cnt, r);
             if (j0 >= cr) continue;  // wavefront-uniform
@@ -324,52 +350,28 @@ __device__ inline void sort_row_inplace(int32_t *__restrict__ row, int len) {
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_nb_sort_rows(const int64_t *__restrict__ row_ptr,
-                                                         int64_t n, int32_t *__restrict__ col) {
-    const int64_t a = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    if (a >= n) return;
-    const int64_t r0 = row_ptr[a];
-    const int len = (int)(row_ptr[a + 1] - r0);
-    if (len <= 1) return;
-    if (len <= 64)
-        sort_row_inplace<1>(col + r0, len);
-    else if (len <= 128)
-        sort_row_inplace<2>(col + r0, len);
-    else if (len <= kRowMax)
-        sort_row_inplace<4>(col + r0, len);
-}
-
-// one wavefront per row longer than min_len: bitonic sort of the row in LDS (rows
-// longer than kSortMax, which no workload here produces, fall back to an
-// insertion sort)
-__global__ __launch_bounds__(kBlock) void k_nb_sort(const int64_t *__restrict__ row_ptr,
-                                                    int64_t n, int32_t *__restrict__ col,
-                                                    int min_len) {
-    __shared__ int32_t lds[kBlock / 64][kSortMax];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int32_t *buf = lds[wave];
-    const int64_t a = (int64_t)blockIdx.x * (kBlock / 64) + wave;
-    if (a >= n) return;
-    const int64_t r0 = row_ptr[a];
-    const int len = (int)(row_ptr[a + 1] - r0);
-    if (len <= 1 || len <= min_len) return;  // shorter rows are sorted already
+// Bitonic sort of one row in LDS by one wavefront (buf: kSortMax values); rows longer
+// than kSortMax, which no workload here produces, fall back to an insertion sort by
+// lane 0.
+__device__ inline void sort_long_row(int32_t *__restrict__ row, int len, int32_t *buf) {
+    const int lane = __lane_id();
     if (len > kSortMax) {
         if (lane == 0) {
-            for (int64_t i = r0 + 1; i < r0 + len; ++i) {
-                const int32_t v = col[i];
+            for (int64_t i = 1; i < len; ++i) {
+                const int32_t v = row[i];
                 int64_t j = i - 1;
-                while (j >= r0 && col[j] > v) {
-                    col[j + 1] = col[j];
+                while (j >= 0 && row[j] > v) {
+                    row[j + 1] = row[j];
                     --j;
                 }
-                col[j + 1] = v;
+                row[j + 1] = v;
             }
         }
         return;
     }
     int n2 = 2;
     while (n2 < len) n2 <<= 1;
-    for (int i = lane; i < n2; i += 64) buf[i] = i < len ? col[r0 + i] : INT_MAX;
+    for (int i = lane; i < n2; i += 64) buf[i] = i < len ? row[i] : INT_MAX;
     wave_sync();
     for (int kk = 2; kk <= n2; kk <<= 1) {
         for (int j = kk >> 1; j > 0; j >>= 1) {
@@ -387,7 +389,40 @@ __global__ __launch_bounds__(kBlock) void k_nb_sort(const int64_t *__restrict__ 
             wave_sync();
         }
     }
-    for (int i = lane; i < len; i += 64) col[r0 + i] = buf[i];
+    for (int i = lane; i < len; i += 64) row[i] = buf[i];
+}
+
+// Every row of the CSR, one wavefront per row: in registers up to kRowMax values, in
+// LDS beyond.
+__global__ __launch_bounds__(kBlock) void k_nb_sort_rows(const int64_t *__restrict__ row_ptr,
+                                                         int64_t n, int32_t *__restrict__ col) {
+    __shared__ int32_t lds[kBlock / 64][kSortMax];
+    const int64_t a = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (a >= n) return;
+    const int64_t r0 = row_ptr[a];
+    const int len = (int)(row_ptr[a + 1] - r0);
+    if (len <= 1) return;
+    if (len <= 64)
+        sort_row_inplace<1>(col + r0, len);
+    else if (len <= 128)
+        sort_row_inplace<2>(col + r0, len);
+    else if (len <= kRowMax)
+        sort_row_inplace<4>(col + r0, len);
+    else
+        sort_long_row(col + r0, len, lds[threadIdx.x >> 6]);
+}
+
+// the rows longer than min_len (which k_nb_rows leaves unsorted), one wavefront per row
+__global__ __launch_bounds__(kBlock) void k_nb_sort(const int64_t *__restrict__ row_ptr,
+                                                    int64_t n, int32_t *__restrict__ col,
+                                                    int min_len) {
+    __shared__ int32_t lds[kBlock / 64][kSortMax];
+    const int64_t a = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (a >= n) return;
+    const int64_t r0 = row_ptr[a];
+    const int len = (int)(row_ptr[a + 1] - r0);
+    if (len <= 1 || len <= min_len) return;  // shorter rows are sorted already
+    sort_long_row(col + r0, len, lds[threadIdx.x >> 6]);
 }
 
 }  // namespace
@@ -457,8 +492,8 @@ extern "C" int sph_neighbours(const sph_grid *grid, const double *x, const doubl
     } else {
         k_nb_rows<<<blocks_for(n, kBlock / 64), kBlock, 0, s>>>(g, pos, n, h * h, reach, row_ptr, col);
         SPH_LAUNCHED();
+        k_nb_sort<<<blocks_for(n, kBlock / 64), kBlock, 0, s>>>(row_ptr, n, col, kRowMax);
+        SPH_LAUNCHED();
     }
-    k_nb_sort<<<blocks_for(n, kBlock / 64), kBlock, 0, s>>>(row_ptr, n, col, kRowMax);
-    SPH_LAUNCHED();
     return SPH_OK;
 }
