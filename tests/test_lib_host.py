@@ -153,3 +153,29 @@ def test_noalloc_rejects_sizes_beyond_its_scratch():
     g, s = _fake_grid(10), _fake_state(10)
     assert lib.sph_rhs_noalloc(C.byref(g), C.byref(s), C.byref(pr), 5, C.byref(d), None, None) == L.SPH_ERR_INVALID_ARG
     assert lib.sph_rhs_noalloc(None, C.byref(s), C.byref(pr), 0, C.byref(d), None, None) == L.SPH_ERR_INVALID_ARG
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes structs have the sizes and field offsets of include/sph.h's
+    (a C program built with gcc prints them)."""
+    import subprocess
+    structs = {"sph_pairs": L.Pairs, "sph_grid": L.Grid, "sph_state": L.State,
+               "sph_params": L.Params, "sph_deriv": L.Deriv, "sph_deriv_cot": L.DerivCot,
+               "sph_fields": L.Fields, "sph_cfields": L.CFields}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "sph.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'    printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'    printf("{name}.{field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    got = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                          text=True).stdout.splitlines())
+    for name, cls in structs.items():
+        assert int(got[f"{name} size"]) == C.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert int(got[f"{name}.{field}"]) == getattr(cls, field).offset, (name, field)
