@@ -222,6 +222,8 @@ __global__ __launch_bounds__(kBlock) void k_nb_rows(GridDev g, const double4 *__
 // partners' user indices to its row in candidate order (ballot prefix, one contiguous
 // store).  The rows are sorted afterwards by k_nb_sort_rows.
 constexpr int kTileSteps = 64;
+// a tile holds one step per lane: lane l tests step j0 + l of each row
+static_assert(kTileSteps == 64, "the fill indexes a tile's steps by lane");
 
 // lane r's value of a 64-bit quantity, as a scalar (r wavefront-uniform)
 __device__ inline int64_t lane_value64(int64_t v, int r) {
