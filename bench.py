@@ -562,12 +562,13 @@ def main():
     log(f"generating workload {args.workload}")
     w = W.config(k)
     if args.workload == "two_spheres":
+        calib = copy_calibration(torch)
         sec = two_spheres_section(args, w, torch, P, L)
         result = {"metric": METRIC, "value": sec["leapfrog_step_pairs_per_s"], "unit": UNIT, "n_gpus": 1,
                   "steps": max(args.steps, 3), "warmup": args.warmup, "ms_per_step": sec["leapfrog_step_ms"],
                   "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
                   "data": "synthetic", "config": {"workload": w.name, "step": sec["leapfrog_step"]},
-                  "two_spheres": sec}
+                  "copy_calibration_bytes": calib, "two_spheres": sec}
         print(json.dumps(result), flush=True)
         return
     res, sample = single_state_step(args, w, torch, P, L)
