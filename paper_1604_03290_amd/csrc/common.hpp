@@ -183,11 +183,11 @@ template <class F>
 __device__ inline void for_each_candidate(const GridDev &g, int64_t s, double xa, double ya,
                                           double za, double reach, F &&f);
 
-// Slot ranges of the cells x0..x1 of the row (iy, iz), in increasing x: runs of
-// consecutive cell numbers (a tile's run of 4 cells, and the next tile's when it
-// follows in the numbering) give one range each.
+// Runs of consecutive cell numbers among the cells x0..x1 (x0 <= x1) of the row
+// (iy, iz), in increasing x: f(c0, c1) for the cells numbered c0 .. c1 - 1 (a tile's
+// run of 4 cells, and the next tile's when it follows in the numbering).
 template <class F>
-__device__ inline void for_each_run(const GridDev &g, int iy, int iz, int x0, int x1, F &&f) {
+__device__ inline void for_each_cell_run(const GridDev &g, int iy, int iz, int x0, int x1, F &&f) {
     int x = x0;
     int cx = cell_number(x, iy, iz, g.nbx, g.nby);  // number of cell x
     int c0 = cx, c1 = cx;                            // the range being merged
@@ -198,11 +198,19 @@ __device__ inline void for_each_run(const GridDev &g, int iy, int iz, int x0, in
         if (x > x1) break;
         cx = cell_number(x, iy, iz, g.nbx, g.nby);
         if (cx != c1 + 1) {
-            f(g.cell_start[c0], g.cell_start[c1 + 1]);
+            f(c0, c1 + 1);
             c0 = cx;
         }
     }
-    f(g.cell_start[c0], g.cell_start[c1 + 1]);
+    f(c0, c1 + 1);
+}
+
+// Slot ranges of the cells x0..x1 of the row (iy, iz), in increasing x, one per run
+// of consecutive cell numbers.
+template <class F>
+__device__ inline void for_each_run(const GridDev &g, int iy, int iz, int x0, int x1, F &&f) {
+    for_each_cell_run(g, iy, iz, x0, x1,
+                      [&](int c0, int c1) { f(g.cell_start[c0], g.cell_start[c1]); });
 }
 
 // Visits the slot ranges [s0, s1) of every cell row whose box comes within

@@ -83,8 +83,16 @@ __global__ __launch_bounds__(kBlock) void k_pl_bound(GridDev g, const double *__
 // writes entry j of lane l at block_start[B] + 64 j + l, pads every list to the
 // group's longest with the slot itself (n - 1 for the lanes past n), so every entry
 // of a group's steps is a valid slot and readers of whole groups load without guards,
-// and writes each slot's count.
+// and writes each slot's count.  The compact sweep works in passes over the rows of
+// its region: each lane takes one row (culled against the group's box as a whole),
+// the rows' runs of consecutive slots are laid out in LDS in row order, and the
+// candidates of all of them are then streamed 64 at a time, so that the loads of a pass
+// do not wait on one another row by row.  Each loaded candidate is culled, one lane per
+// candidate, against the group's bounding box widened by the radius (one farther away
+// is no lane's candidate); the survivors are packed, in order, into an LDS buffer, and
+// the lanes test the buffer 64 candidates at a time.
 constexpr double kSpread = 8.0;
+constexpr int kRunCap = 256;  // runs of one pass (LDS)
 
 __global__ __launch_bounds__(kBlock) void k_pl_fill(GridDev g, const double *__restrict__ x0,
                                                     int64_t n, double r2, double reach,
@@ -92,8 +100,13 @@ __global__ __launch_bounds__(kBlock) void k_pl_fill(GridDev g, const double *__r
                                                     const int64_t *__restrict__ block_start,
                                                     int32_t *__restrict__ slot, double h2,
                                                     int32_t *__restrict__ partners) {
-    __shared__ double lds[kBlock / 64][3][kWave];
-    double(*cand)[kWave] = lds[threadIdx.x >> 6];
+    __shared__ double lds[kBlock / 64][3][2 * kWave];
+    __shared__ int32_t lds_t[kBlock / 64][2 * kWave];
+    __shared__ int32_t lds_r[kBlock / 64][2][kRunCap];
+    double(*cand)[2 * kWave] = lds[threadIdx.x >> 6];
+    int32_t *cand_t = lds_t[threadIdx.x >> 6];
+    int32_t *run_s0 = lds_r[threadIdx.x >> 6][0];   // a run's first slot (first its cell)
+    int32_t *run_pre = lds_r[threadIdx.x >> 6][1];  // candidates before it in the pass
     const int lane = __lane_id();
     const int64_t nb = (n + kWave - 1) / kWave;
     const int64_t B = (int64_t)blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6);
@@ -105,11 +118,13 @@ __global__ __launch_bounds__(kBlock) void k_pl_fill(GridDev g, const double *__r
     const int64_t base = block_start[B] + lane;
     const int64_t room = (block_start[B + 1] - block_start[B]) / kWave;
     int c = 0, np = 0;  // candidates and partners (d^2 < h^2) among them
+    int32_t *const group = slot + block_start[B];  // entry j of lane l at group[64 j + l]
+    const int iroom = (int)min(room, (int64_t)(INT_MAX >> 6));
     auto hit = [&](int t, double d) {
         // the bound pass gave room for every candidate; the guard keeps a write
         // inside the group even so
-        if (c < room) slot[base + (int64_t)kWave * c] = t;
-        if (d < h2) ++np;
+        if (c < iroom) group[(uint32_t)((c << 6) + lane)] = t;
+        np += d < h2;
         ++c;
     };
     const double bx0 = wave_min(xa), bx1 = wave_max(xa);
@@ -134,53 +149,167 @@ __global__ __launch_bounds__(kBlock) void k_pl_fill(GridDev g, const double *__r
             });
     } else {
         const double rr = reach * reach;
+        // the cull keeps every candidate within the radius of a point of the box, with a
+        // margin far above the rounding of either distance
+        const double rb2 = r2 * (1.0 + 1e-6);
+        int pend = 0;  // candidates waiting in the buffer (wavefront-uniform)
+        auto test = [&](int m) {
+            int k = 0;
+            for (; k + 4 <= m; k += 4) {  // four distances, then their hits
+                int t[4];
+                double d[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    t[q] = cand_t[k + q];
+                    d[q] = dist2_exact(xa, ya, za, cand[0][k + q], cand[1][k + q], cand[2][k + q]);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (act && d[q] < r2 && t[q] != (int)s) hit(t[q], d[q]);
+            }
+            for (; k < m; ++k) {
+                const int t = cand_t[k];
+                const double d = dist2_exact(xa, ya, za, cand[0][k], cand[1][k], cand[2][k]);
+                if (act && d < r2 && t != (int)s) hit(t, d);
+            }
+        };
+        // one candidate per lane (t, where valid): loaded, culled, packed behind the
+        // waiting ones; 64 waiting are tested
+        auto push = [&](bool valid, int t) {
+            bool keep = false;
+            double px = 0.0, py = 0.0, pz = 0.0;
+            if (valid) {
+                px = x0[3 * (int64_t)t];
+                py = x0[3 * (int64_t)t + 1];
+                pz = x0[3 * (int64_t)t + 2];
+                const double ex = fmax(fmax(bx0 - px, px - bx1), 0.0);
+                const double ey = fmax(fmax(by0 - py, py - by1), 0.0);
+                const double ez = fmax(fmax(bz0 - pz, pz - bz1), 0.0);
+                keep = ex * ex + ey * ey + ez * ez < rb2;
+            }
+            const unsigned long long mk = __ballot(keep);
+            if (keep) {
+                const int at = pend + (int)__builtin_amdgcn_mbcnt_hi(
+                                          (unsigned)(mk >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mk, 0));
+                cand[0][at] = px;
+                cand[1][at] = py;
+                cand[2][at] = pz;
+                cand_t[at] = t;
+            }
+            pend += __popcll(mk);
+            wave_sync();
+            if (pend >= kWave) {
+                test(kWave);
+                pend -= kWave;
+                wave_sync();
+                if (lane < pend) {  // the rest to the front (reads above kWave only)
+                    cand[0][lane] = cand[0][kWave + lane];
+                    cand[1][lane] = cand[1][kWave + lane];
+                    cand[2][lane] = cand[2][kWave + lane];
+                    cand_t[lane] = cand_t[kWave + lane];
+                }
+                wave_sync();
+            }
+        };
         // rows from the middle of the region outwards (z, then y): the lanes of the
         // group then meet their partners at more even rates, so that the rows of the
-        // list they fill together are completed sooner
-        const int zc = (z0 + z1) >> 1, yc = (y0 + y1) >> 1;
-        for (int i = 0; i < 2 * (z1 - z0 + 1); ++i) {
-            const int iz = zc + ((i & 1) ? -((i + 1) >> 1) : (i >> 1));
-            if (iz < z0 || iz > z1) continue;
-            const double gz = box_gap(bz0, bz1, g.loz, g.cell, iz, g.nz);
-            if (gz * gz >= rr) continue;
-            for (int j = 0; j < 2 * (y1 - y0 + 1); ++j) {
-                const int iy = yc + ((j & 1) ? -((j + 1) >> 1) : (j >> 1));
-                if (iy < y0 || iy > y1) continue;
+        // list they fill together are completed sooner.  Row rank r: z the r / ny-th
+        // and y the r % ny-th of that order.
+        const int nzr = z1 - z0 + 1, nyr = y1 - y0 + 1, nrows = nzr * nyr;
+        auto middle_out = [](int r, int lo, int hi) {  // r-th of c, c - 1, c + 1, c - 2, ...
+            const int c = (lo + hi) >> 1, a = c - lo;
+            return r <= 2 * a ? c + ((r & 1) ? -((r + 1) >> 1) : (r >> 1)) : hi;
+        };
+        for (int rb = 0; rb < nrows;) {
+            // this lane's row of the pass: its cells in x and its number of runs
+            const int r = rb + lane;
+            int iy = 0, iz = 0, xr0 = 0, xr1 = -1, nr = 0;
+            if (r < nrows) {
+                iz = middle_out(r / nyr, z0, z1);
+                iy = middle_out(r % nyr, y0, y1);
+                const double gz = box_gap(bz0, bz1, g.loz, g.cell, iz, g.nz);
                 const double gy = box_gap(by0, by1, g.loy, g.cell, iy, g.ny);
                 const double d2 = gz * gz + gy * gy;
-                if (d2 >= rr) continue;
-                const double w = sqrt(rr - d2) * (1.0 + 1e-9);
-                const int xr0 = cell_index(bx0 - w, g.lox, g.inv_cell, g.nx);
-                const int xr1 = cell_index(bx1 + w, g.lox, g.inv_cell, g.nx);
-                for_each_run(g, iy, iz, xr0, xr1, [&](int s0, int s1) {
-                    for (int t0 = s0; t0 < s1; t0 += kWave) {
-                        const int t = t0 + lane;
-                        if (t < s1) {
-                            cand[0][lane] = x0[3 * (int64_t)t];
-                            cand[1][lane] = x0[3 * (int64_t)t + 1];
-                            cand[2][lane] = x0[3 * (int64_t)t + 2];
-                        }
-                        wave_sync();
-                        const int m = __builtin_amdgcn_readfirstlane(min(kWave, s1 - t0));
-                        // a batch holding none of the group's own slots needs no self test
-                        const bool own = t0 < B * kWave + kWave && t0 + m > B * kWave;
-                        if (!own) {
-                            for (int k = 0; k < m; ++k) {
-                                const double d = dist2_exact(xa, ya, za, cand[0][k], cand[1][k], cand[2][k]);
-                                if (act && d < r2) hit(t0 + k, d);
-                            }
-                        } else {
-                            for (int k = 0; k < m; ++k) {
-                                const int tk = t0 + k;
-                                const double d = dist2_exact(xa, ya, za, cand[0][k], cand[1][k], cand[2][k]);
-                                if (act && d < r2 && tk != s) hit(tk, d);
-                            }
-                        }
-                        wave_sync();
-                    }
+                if (gz * gz < rr && d2 < rr) {
+                    const double w = sqrt(rr - d2) * (1.0 + 1e-9);
+                    xr0 = cell_index(bx0 - w, g.lox, g.inv_cell, g.nx);
+                    xr1 = cell_index(bx1 + w, g.lox, g.inv_cell, g.nx);
+                    for_each_cell_run(g, iy, iz, xr0, xr1, [&](int, int) { ++nr; });
+                }
+            }
+            // runs before this lane's (exclusive scan over the lanes)
+            int off = nr;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int v = __shfl_up(off, o);
+                if (lane >= o) off += v;
+            }
+            off -= nr;
+            // the rows that fit the pass: a prefix of the lanes
+            const int take = __popcll(__ballot(r < nrows && off + nr <= kRunCap));
+            if (take == 0) {
+                // a single row with more runs than a pass holds: its runs one by one
+                const int fy = __builtin_amdgcn_readfirstlane(iy), fz = __builtin_amdgcn_readfirstlane(iz);
+                const int f0 = __builtin_amdgcn_readfirstlane(xr0), f1 = __builtin_amdgcn_readfirstlane(xr1);
+                for_each_run(g, fy, fz, f0, f1, [&](int s0, int s1) {
+                    for (int t0 = s0; t0 < s1; t0 += kWave) push(t0 + lane < s1, t0 + lane);
+                });
+                rb += 1;
+                continue;
+            }
+            const int nrun = __shfl(off + nr, take - 1);
+            if (lane < take && nr > 0) {  // (a culled row has no runs)
+                int j = off;
+                for_each_cell_run(g, iy, iz, xr0, xr1, [&](int c0, int c1) {
+                    run_s0[j] = c0;
+                    run_pre[j] = c1;
+                    ++j;
                 });
             }
+            wave_sync();
+            // the runs' slots: cells to slot ranges, and their lengths scanned
+            int len[kRunCap / kWave], sum = 0;
+#pragma unroll
+            for (int q = 0; q < kRunCap / kWave; ++q) {
+                const int j = kRunCap / kWave * lane + q;
+                len[q] = 0;
+                if (j < nrun) {
+                    const int s0 = g.cell_start[run_s0[j]];
+                    len[q] = g.cell_start[run_pre[j]] - s0;
+                    run_s0[j] = s0;
+                }
+                sum += len[q];
+            }
+            int before = sum;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int v = __shfl_up(before, o);
+                if (lane >= o) before += v;
+            }
+            const int total = __shfl(before, 63);
+            before -= sum;
+#pragma unroll
+            for (int q = 0; q < kRunCap / kWave; ++q) {
+                const int j = kRunCap / kWave * lane + q;
+                if (j < nrun) run_pre[j] = before;
+                before += len[q];
+            }
+            wave_sync();
+            // the pass's candidates in order, 64 at a time (run of candidate f: the last
+            // with run_pre <= f)
+            for (int f0 = 0; f0 < total; f0 += kWave) {
+                const int f = f0 + lane;
+                int lo = 0, hi = nrun;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (run_pre[mid] <= f) lo = mid; else hi = mid;
+                }
+                push(f < total, run_s0[lo] + (f - run_pre[lo]));
+            }
+            wave_sync();
+            rb += take;
         }
+        test(pend);
     }
     // the group's steps: its longest list (at most its room)
     int steps = min((int64_t)c, room);
