@@ -216,12 +216,14 @@ __global__ __launch_bounds__(kBlock) void k_nb_rows(GridDev g, const double4 *__
 }
 
 // Fill over the frozen pair list, one wavefront per group of 64 slots.  The group's
-// list is taken in tiles of 64 steps (each step one coalesced 256-byte load) into LDS;
-// then for each slot of the group in turn the lanes test 64 of its candidates (a
-// column of the tile, conflict-free with the padded row length) and append the
-// partners' user indices to its row in candidate order (ballot prefix, one contiguous
-// store).  The rows are sorted afterwards by k_nb_sort_rows.
+// list is taken in tiles of 64 steps of 16 of its slots (64-byte pieces of the list's
+// rows) into LDS; then for each slot of the tile in turn the lanes test 64 of its
+// candidates (a column of the tile, conflict-free with the padded row length) and
+// append the partners' user indices to its row in candidate order (ballot prefix, one
+// contiguous store).  The rows are sorted afterwards by k_nb_sort_rows.  (A tile of all
+// 64 slots would hold 16.6 KB of LDS per wavefront, two wavefronts per SIMD.)
 constexpr int kTileSteps = 64;
+constexpr int kTileRows = 16;
 // a tile holds one step per lane: lane l tests step j0 + l of each row
 static_assert(kTileSteps == 64, "the fill indexes a tile's steps by lane");
 
@@ -238,8 +240,8 @@ __global__ __launch_bounds__(kBlock) void k_nb_fill_list(GridDev g, const double
                                                          int32_t *__restrict__ col,
                                                          const int32_t *__restrict__ known,
                                                          const int32_t *__restrict__ moved) {
-    __shared__ int32_t lds[kBlock / 64][kTileSteps][65];
-    int32_t(*tile)[65] = lds[threadIdx.x >> 6];
+    __shared__ int32_t lds[kBlock / 64][kTileSteps][kTileRows + 1];
+    int32_t(*tile)[kTileRows + 1] = lds[threadIdx.x >> 6];
     const int lane = __lane_id();
     const int64_t nb = (n + 63) / 64;
     const int64_t B = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
@@ -262,63 +264,70 @@ __global__ __launch_bounds__(kBlock) void k_nb_fill_list(GridDev g, const double
     const bool group_all = __ballot(act && !all) == 0;
     for (int j0 = 0; j0 < steps; j0 += kTileSteps) {
         const int m = min(kTileSteps, steps - j0);
-        for (int jj = 0; jj < m; ++jj) tile[jj][lane] = g.pl_slot[base + ((int64_t)(j0 + jj) << 6) + lane];
-        wave_sync();
-        if (group_all) {
-            for (int r = 0; r < rows; r += 4) {
-                int cr[4];
-                int32_t u[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    cr[q] = r + q < rows ? __builtin_amdgcn_readlane(cnt, r + q) : 0;
-                    u[q] = j0 + lane < cr[q] ? g.perm[tile[lane][r + q]] : 0;
-                }
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (j0 >= cr[q]) continue;  // wavefront-uniform (also past the rows)
-                    const int64_t rr = lane_value64(r0, r + q);
-                    const int kr = __builtin_amdgcn_readlane(k, r + q);
-                    if (j0 + lane < cr[q]) col[rr + kr + lane] = u[q];
-                }
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (lane == r + q && j0 < cr[q]) k += min(64, cr[q] - j0);
+        for (int c0 = 0; c0 < rows; c0 += kTileRows) {
+            const int c1 = min(rows, c0 + kTileRows);
+            // tile[jj][i] = step j0 + jj of slot c0 + i (four steps per load)
+            for (int e = lane; e < m * kTileRows; e += 64) {
+                const int jj = e / kTileRows, i = e % kTileRows;
+                tile[jj][i] = g.pl_slot[base + ((int64_t)(j0 + jj) << 6) + c0 + i];
             }
             wave_sync();
-            continue;
-        }
-        for (int r = 0; r < rows; ++r) {  // row r's values come from lane r (scalar reads)
-            const int cr = __builtin_amdgcn_readlane(cnt, r);
-            if (j0 >= cr) continue;  // wavefront-uniform
-            const int64_t sr = B * 64 + r;
-            const bool valid = j0 + lane < cr;
-            const int kr = __builtin_amdgcn_readlane(k, r);
-            const int64_t rr = lane_value64(r0, r);
-            if (__builtin_amdgcn_readlane((int)all, r)) {
-                // lanes 0 .. min(64, cr - j0) - 1 all hit
-                if (valid) col[rr + kr + lane] = g.perm[tile[lane][r]];
-                if (lane == r) k += min(64, cr - j0);
+            if (group_all) {
+                for (int r = c0; r < c1; r += 4) {
+                    int cr[4];
+                    int32_t u[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        cr[q] = r + q < rows ? __builtin_amdgcn_readlane(cnt, r + q) : 0;
+                        u[q] = j0 + lane < cr[q] ? g.perm[tile[lane][r + q - c0]] : 0;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        if (j0 >= cr[q]) continue;  // wavefront-uniform (also past the rows)
+                        const int64_t rr = lane_value64(r0, r + q);
+                        const int kr = __builtin_amdgcn_readlane(k, r + q);
+                        if (j0 + lane < cr[q]) col[rr + kr + lane] = u[q];
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (lane == r + q && j0 < cr[q]) k += min(64, cr[q] - j0);
+                }
+                wave_sync();
                 continue;
             }
-            const double4 pa = pos[sr];
-            bool hit = false;
-            int32_t u = 0;
-            if (valid) {
-                const int t = tile[lane][r];
-                const double4 pb = pos[t];
-                hit = dist2_exact(pa.x, pa.y, pa.z, pb.x, pb.y, pb.z) < h2;
-                u = g.perm[t];
+            for (int r = c0; r < c1; ++r) {  // row r's values come from lane r (scalar reads)
+                const int cr = __builtin_amdgcn_readlane(cnt, r);
+                if (j0 >= cr) continue;  // wavefront-uniform
+                const int64_t sr = B * 64 + r;
+                const bool valid = j0 + lane < cr;
+                const int kr = __builtin_amdgcn_readlane(k, r);
+                const int64_t rr = lane_value64(r0, r);
+                if (__builtin_amdgcn_readlane((int)all, r)) {
+                    // lanes 0 .. min(64, cr - j0) - 1 all hit
+                    if (valid) col[rr + kr + lane] = g.perm[tile[lane][r - c0]];
+                    if (lane == r) k += min(64, cr - j0);
+                    continue;
+                }
+                const double4 pa = pos[sr];
+                bool hit = false;
+                int32_t u = 0;
+                if (valid) {
+                    const int t = tile[lane][r - c0];
+                    const double4 pb = pos[t];
+                    hit = dist2_exact(pa.x, pa.y, pa.z, pb.x, pb.y, pb.z) < h2;
+                    u = g.perm[t];
+                }
+                const unsigned long long mk = __ballot(hit);
+                const int lr = __builtin_amdgcn_readlane(len, r);
+                if (hit) {
+                    const int at = kr + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mk >> 32),
+                                                                        __builtin_amdgcn_mbcnt_lo((unsigned)mk, 0));
+                    if (at < lr) col[rr + at] = u;  // the count pass found lr with the same test
+                }
+                if (lane == r) k += __popcll(mk);
             }
-            const unsigned long long mk = __ballot(hit);
-            const int lr = __builtin_amdgcn_readlane(len, r);
-            if (hit) {
-                const int at = kr + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mk >> 32),
-                                                                    __builtin_amdgcn_mbcnt_lo((unsigned)mk, 0));
-                if (at < lr) col[rr + at] = u;  // the count pass found lr with the same test
-            }
-            if (lane == r) k += __popcll(mk);
+            wave_sync();
         }
-        wave_sync();
     }
 }
 
