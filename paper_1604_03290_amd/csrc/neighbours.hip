@@ -88,15 +88,18 @@ __device__ inline int32_t xor_lane(int32_t v) {
 // one wavefront.
 template <int J, int K, int E>
 __device__ inline void bitonic_lanes(int32_t (&v)[E], int lane) {
+    const bool lower = (lane & J) == 0;   // value i below its partner
+    const bool lane_up = (lane & K) == 0;  // ascending run (K < 64)
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        const int i = 64 * e + lane;
+        // ascending where bit K of i = 64 e + lane is clear (for K >= 64, bit K of 64 e)
+        const bool up = K < 64 ? lane_up : ((64 * e) & K) == 0;
         const int32_t o = xor_lane<J>(v[e]);
-        const bool up = (i & K) == 0;
-        const bool lower = (lane & J) == 0;  // i < partner
-        // the lower index keeps the min when ascending, the max otherwise
-        const bool take_min = lower == up;
-        v[e] = take_min ? min(v[e], o) : max(v[e], o);
+        // the lower index keeps the min when ascending, the max otherwise: the partner's
+        // value where it is below (min) or not below (max) this one (equal values are
+        // alike, so one compare and one select)
+        const bool take_max = lower != up;
+        v[e] = ((o < v[e]) != take_max) ? o : v[e];
     }
 }
 
