@@ -185,12 +185,13 @@ typedef struct {
  * particle's thresholds below eps; dd3 = n_act c_g / R_s with
  * c_g = 0.4 sqrt((K + 4/3 (1 - d) mu) / rho) and R_s = (3 m / (4 pi rho))^(1/3),
  * and 0 once d n_tot >= n_act (the limiter d <= n_act / n_tot, n_tot the
- * particle's flaw count).  vgrad (NULL, or device [9 n], [15 n] with
+ * particle's flaw count).  vgrad (NULL, or device [n 9], [n 15] with
  * params->correction = 1; SPH_FP64 only) receives the velocity gradient that the
  * pair sums form (section 3.1.6, before the correction), for sph_rhs_adjoint
- * (sph_deriv_cot.vgrad) to reuse: component i of slot s at vgrad[i n + s], in the
- * grid's slot order, L row by row (dv^x/dx, dv^x/dy, ..., dv^z/dz), then with the
- * correction the moment matrix M (xx yy zz xy xz yz). */
+ * (sph_deriv_cot.vgrad) to reuse: one record of m = 9 (15) values per slot, in the
+ * grid's slot order, component i of slot s at vgrad[m s + i]: L row by row
+ * (dv^x/dx, dv^x/dy, ..., dv^z/dz), then with the correction the moment matrix M
+ * (xx yy zz xy xz yz). */
 typedef struct {
     double *ax, *ay, *az;
     double *drho;

@@ -272,7 +272,7 @@ def new_deriv(n: int, device="cuda", extra: bool = False, damage: bool = False,
     """Output arrays of sph_rhs; with ``extra`` also du (n) and xv (3, n) = dx/dt, with
     ``damage`` dd3 (n) = d(d^(1/3))/dt and n_act (n, int32), with ``vgrad`` = 9 (15 with
     the correction tensor) the velocity-gradient handoff for sph_rhs_adjoint (vgrad,
-    (vgrad, n), the grid's slot order)."""
+    (n, vgrad): one row per slot, the grid's slot order)."""
     d = dict(acc=torch.empty(3, n, dtype=F64, device=device),
              drho=torch.empty(n, dtype=F64, device=device),
              dS=torch.empty(6, n, dtype=F64, device=device),
@@ -284,7 +284,7 @@ def new_deriv(n: int, device="cuda", extra: bool = False, damage: bool = False,
         d["dd3"] = torch.empty(n, dtype=F64, device=device)
         d["n_act"] = torch.empty(n, dtype=torch.int32, device=device)
     if vgrad:
-        d["vgrad"] = torch.empty(vgrad, n, dtype=F64, device=device)
+        d["vgrad"] = torch.empty(n, vgrad, dtype=F64, device=device)
     return d
 
 
@@ -386,8 +386,8 @@ def sph_rhs_adjoint(grid: CellGrid, state: ParticleState, params, cot: dict,
     if vgrad is not None:
         _dev(vgrad)
         want = 15 if params_struct(params).correction != 0.0 else 9
-        if tuple(vgrad.shape) != (want, n):
-            raise ValueError(f"vgrad must be ({want}, {n}), got {tuple(vgrad.shape)}")
+        if tuple(vgrad.shape) != (n, want) or not vgrad.is_contiguous():
+            raise ValueError(f"vgrad must be contiguous ({n}, {want}), got {tuple(vgrad.shape)}")
     dc = L.DerivCot(p(acc, 0), p(acc, 1), p(acc, 2), p(drho), p(dS, 0), p(dS, 1), p(dS, 2),
                     p(dS, 3), p(dS, 4), p(dS, 5), p(rs), p(du), p(xv, 0), p(xv, 1), p(xv, 2),
                     p(vgrad))

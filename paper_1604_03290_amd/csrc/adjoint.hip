@@ -113,12 +113,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_L(GridDev g, int64_t n, Consts k
         L[6] = fma(tz, gx, L[6]); L[7] = fma(tz, gy, L[7]); L[8] = fma(tz, gz, L[8]);
         if (kCorr) moment_add(M, V, F, xa - b0.x, ya - b0.y, za - b1.x);
     });
-#pragma unroll
-    for (int i = 0; i < 9; ++i) ad.L[i][s] = L[i];
-    if (kCorr) {
-#pragma unroll
-        for (int i = 0; i < 6; ++i) ad.M[i][s] = M[i];
-    }
+    store_vgrad<kCorr>(ad.L, s, L, M);
 }
 
 // same over the frozen pair list with cooperative gathers of the partners' first
@@ -180,12 +175,7 @@ __global__ __launch_bounds__(64 * kSplit) void k_adj_L_list(GridDev g, int64_t n
     }
     fold_waves<kSplit, kSplit * 64 * 4 * 2>(v, reinterpret_cast<double *>(lbuf));
     if (q != 0 || !act) return;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) ad.L[i][s] = L[i];
-    if (kCorr) {
-#pragma unroll
-        for (int i = 0; i < 6; ++i) ad.M[i][s] = M[i];
-    }
+    store_vgrad<kCorr>(ad.L, s, L, M);
 }
 
 // post stage (see the file header); with inv (user-order state and cotangents, the
@@ -200,15 +190,16 @@ __global__ __launch_bounds__(kBlock) void k_adj_post(GridDev g, int64_t n, Const
         const int64_t s = inv ? (int64_t)inv[i] : i;
         const int a = inv ? (int)i : io_index(g, s);
         double L[9], c6[6];
+        const double *Ls = ad.L + (size_t)s * ad.lw;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) L[i] = ad.L[i][s];
+        for (int i = 0; i < 9; ++i) L[i] = Ls[i];
         const double S[6] = {st.sxx[a], st.syy[a], st.szz[a], st.sxy[a], st.sxz[a], st.syz[a]};
 #pragma unroll
         for (int i = 0; i < 6; ++i) c6[i] = ld(cot.ds[i], a);
         double M[6] = {0, 0, 0, 0, 0, 0};
         if (k.corr) {
 #pragma unroll
-            for (int i = 0; i < 6; ++i) M[i] = ad.M[i][s];
+            for (int i = 0; i < 6; ++i) M[i] = Ls[9 + i];
         }
         mu_part = adj_post_at(k, s, L, k.corr, M, rec[s * kRec + 6], S, c6,
                               ld(cot.drho, a), ld(cot.ax, a), ld(cot.ay, a), ld(cot.az, a),
@@ -437,7 +428,8 @@ __device__ inline double adj_pre(const Consts &k, const AdjRec &ad, const AdjOwn
     const double rc = o.rc;
     const double ir2 = 1.0 / (rc * rc);
     const double keep = st.d ? 1.0 - st.d[a] : 1.0;  // 1 - d
-    double grho = ad.rhob[s] + acc.grho - acc.gV * o.Vc / rc;
+    const double *pb = ad.pb + (size_t)s * kPb;
+    double grho = pb[0] + acc.grho - acc.gV * o.Vc / rc;
 #pragma unroll
     for (int i = 0; i < 6; ++i) grho += acc.gT[i] * (-2.0 * o.Tc[i] / rc);
     const bool cut = kEos != 2 && k.rho_cut > 0.0 && rc / k.rho0 < k.rho_cut;
@@ -469,7 +461,7 @@ __device__ inline double adj_pre(const Consts &k, const AdjRec &ad, const AdjOwn
     double Stb[6], fb = 0.0;
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-        Stb[i] = acc.gT[i] * (ir2 * keep) + ad.Stb[i][s];
+        Stb[i] = acc.gT[i] * (ir2 * keep) + pb[1 + i];
         fb += Stb[i] * S[i];
     }
     double gS[6];
@@ -718,10 +710,9 @@ int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_p
     } else if ((rc = prepass_launch(g, st, n, k, rec, c.status(), s, nullptr, ad.inv))) {
         return rc;
     }
+    ad.lw = vgrad_width(k.corr);
     if (L_in) {
-        for (int i = 0; i < 9; ++i) ad.L[i] = const_cast<double *>(L_in) + (size_t)i * n;
-        if (k.corr)
-            for (int i = 0; i < 6; ++i) ad.M[i] = const_cast<double *>(L_in) + (size_t)(9 + i) * n;
+        ad.L = const_cast<double *>(L_in);
     } else {
         TimedRegion t("adjoint_L", s);
         const dim3 gb(blocks_for(n)), tb(kBlock);

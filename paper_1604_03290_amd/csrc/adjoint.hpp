@@ -11,13 +11,17 @@ namespace sph {
 //   Lbar(9) | abar(3) | rho_sum bar | - - -
 constexpr int kAdj = 16;
 
+// Per-slot records of the post stage's partial cotangents: the density's, then that of
+// f_Y S from the rotation terms (stored components); one 64-byte record per slot.
+constexpr int kPb = 8;
+
 struct AdjRec {
-    double *L[9];      // forward velocity gradient (slot order)
-    double *M[6];      // with the correction: forward moment matrix (xx yy zz xy xz yz)
+    double *L;         // forward velocity gradient and, with the correction, moment matrix
+                       // (slot order, vgrad_width(corr) values per slot)
+    int lw;            // values per slot of L
     double *Mb[6];     // with the correction: its cotangent, symmetrised
     double *arec;      // adjoint records [n][kAdj]
-    double *rhob;      // partial density cotangent from the post stage
-    double *Stb[6];    // partial cotangent of f_Y S from the rotation terms (stored components)
+    double *pb;        // partial cotangents [n][kPb]: rho, then S~ (6)
     double *part_mu;   // per-block partial sums (ceil(n / 256))
     double *part_y0;   // per block, or per wavefront for the list kernel (ceil(n / 64))
     double *ext[4];    // cotangents of du and dx/dt (slot order), when given
@@ -27,12 +31,11 @@ struct AdjRec {
 
 inline AdjRec carve_adj(Carve &c, int64_t n) {
     AdjRec r;
-    for (int i = 0; i < 9; ++i) r.L[i] = c.take<double>(n);
-    for (int i = 0; i < 6; ++i) r.M[i] = c.take<double>(n);
+    r.L = c.take<double>((size_t)n * vgrad_width(true));
+    r.lw = vgrad_width(false);
     for (int i = 0; i < 6; ++i) r.Mb[i] = c.take<double>(n);
     r.arec = c.take<double>((size_t)n * kAdj);
-    r.rhob = c.take<double>(n);
-    for (int i = 0; i < 6; ++i) r.Stb[i] = c.take<double>(n);
+    r.pb = c.take<double>((size_t)n * kPb);
     r.part_mu = c.take<double>(blocks_for(n));
     r.part_y0 = c.take<double>(blocks_for(n, 64));
     for (int i = 0; i < 4; ++i) r.ext[i] = c.take<double>(n);
@@ -142,7 +145,8 @@ __device__ inline double adj_post_at(const Consts &k, int64_t s, const double Lv
 #pragma unroll
         for (int i = 0; i < 9; ++i) Lb[i] = Lu[i] + (i % 4 == 0 ? -rho * rdot : 0.0);
     }
-    ad.rhob[s] = -(Lv[0] + Lv[4] + Lv[8]) * rdot;
+    double *pb = ad.pb + (size_t)s * kPb;
+    pb[0] = -(Lv[0] + Lv[4] + Lv[8]) * rdot;
     double Sb[3][3];  // G R - R G
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -153,12 +157,13 @@ __device__ inline double adj_post_at(const Consts &k, int64_t s, const double Lv
             for (int m = 0; m < 3; ++m) v += G[i][m] * R[m][j] - R[i][m] * G[m][j];
             Sb[i][j] = v;
         }
-    ad.Stb[0][s] = Sb[0][0];
-    ad.Stb[1][s] = Sb[1][1];
-    ad.Stb[2][s] = Sb[2][2];
-    ad.Stb[3][s] = Sb[0][1] + Sb[1][0];
-    ad.Stb[4][s] = Sb[0][2] + Sb[2][0];
-    ad.Stb[5][s] = Sb[1][2] + Sb[2][1];
+    pb[1] = Sb[0][0];
+    pb[2] = Sb[1][1];
+    pb[3] = Sb[2][2];
+    pb[4] = Sb[0][1] + Sb[1][0];
+    pb[5] = Sb[0][2] + Sb[2][0];
+    pb[6] = Sb[1][2] + Sb[2][1];
+    pb[7] = 0.0;
     double2 *o = reinterpret_cast<double2 *>(ad.arec + s * kAdj);
     o[0] = make_double2(Lb[0], Lb[1]);
     o[1] = make_double2(Lb[2], Lb[3]);

@@ -22,7 +22,7 @@
 namespace sph {
 namespace {
 
-constexpr int kArrays = 38;  // x3 v3 rho S6 | a3 drho dS6 | L9 | M6 (slot order; M with the correction)
+constexpr int kArrays = 38;  // x3 v3 rho S6 | a3 drho dS6 | L and M (slot order, vgrad_width values per slot)
 constexpr int kLOffset = 23;
 
 struct Fields13 {
@@ -222,12 +222,13 @@ __global__ __launch_bounds__(kBlock) void k_rev_kick2(Fields13 Uk, Deriv10 Fk, F
         write_rec(g, k, i, x1[i], x1[n + i], x1[2 * n + i], v[0], v[1], v[2], rho, S, mi, rec,
                   status, 0.0, dmg ? dmg[i] : 0.0);
         double L[9];
+        const double *Li = L1 + (size_t)i * vgrad_width(k.corr);
 #pragma unroll
-        for (int c = 0; c < 9; ++c) L[c] = L1[c * n + i];
+        for (int c = 0; c < 9; ++c) L[c] = Li[c];
         double M[6] = {0, 0, 0, 0, 0, 0};
         if (k.corr) {
 #pragma unroll
-            for (int c = 0; c < 6; ++c) M[c] = L1[(9 + c) * n + i];
+            for (int c = 0; c < 6; ++c) M[c] = Li[9 + c];
         }
         const double c6[6] = {cF[4], cF[5], cF[6], cF[7], cF[8], cF[9]};
         mup = adj_post_at(k, i, L, k.corr, M, rho, S, c6, cF[3], cF[0], cF[1], cF[2], 0.0, ad);

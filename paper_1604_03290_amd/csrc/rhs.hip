@@ -107,14 +107,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs64(GridDev g, int64_t n, Consts
     postpass(k, io_index(g, s), rho_a, acc.L, acc.ax, acc.ay, acc.az, acc.rs, st, out,
              kCorr ? acc.M : nullptr);
     if (kExt) postpass_ext(k, io_index(g, s), acc, st, out);
-    if (Lout) {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) Lout[i * n + s] = acc.L[i];
-        if (kCorr) {
-#pragma unroll
-            for (int i = 0; i < 6; ++i) Lout[(9 + i) * n + s] = acc.M[i];
-        }
-    }
+    if (Lout) store_vgrad<kCorr>(Lout, s, acc.L, acc.M);
 }
 
 // FP64 pair sums over the frozen pair list: a workgroup of kSplit wavefronts takes one
@@ -182,14 +175,7 @@ __global__ __launch_bounds__(64 * kSplit) void k_pairs64_list(GridDev g, int64_t
     postpass(k, io_index(g, s), rho_a, acc.L, acc.ax, acc.ay, acc.az, acc.rs, st, out,
              kCorr ? acc.M : nullptr);
     if (kExt) postpass_ext(k, io_index(g, s), acc, st, out);
-    if (Lout) {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) Lout[i * n + s] = acc.L[i];
-        if (kCorr) {
-#pragma unroll
-            for (int i = 0; i < 6; ++i) Lout[(9 + i) * n + s] = acc.M[i];
-        }
-    }
+    if (Lout) store_vgrad<kCorr>(Lout, s, acc.L, acc.M);
 }
 
 // ----------------------------------------- pairs, FP32 + Kahan sums --
@@ -265,14 +251,7 @@ __device__ inline void post32(const Consts &k, int a, double rho_a, double m_a, 
     }
     const double rs = m_a * k.Wn + acc.rs;
     postpass(k, a, rho_a, acc.L, acc.ax, acc.ay, acc.az, rs, st, out, kCorr ? acc.M : nullptr);
-    if (Lout) {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) Lout[i * n + s] = acc.L[i];
-        if (kCorr) {
-#pragma unroll
-            for (int i = 0; i < 6; ++i) Lout[(9 + i) * n + s] = acc.M[i];
-        }
-    }
+    if (Lout) store_vgrad<kCorr>(Lout, s, acc.L, acc.M);
 }
 
 template <bool kCorr, bool kExt>

@@ -897,13 +897,29 @@ struct GradDev {
     double *u;  // gradient of u (Tillotson), else null
 };
 
+// Velocity-gradient handoff (sph_deriv.vgrad) and the adjoint's copy of it: slot s
+// holds vgrad_width(corr) values from L[vgrad_width(corr) * s] on: L row by row, then
+// with the correction the moment matrix (xx yy zz xy xz yz).
+__host__ __device__ constexpr int vgrad_width(bool corr) { return corr ? 15 : 9; }
+
+template <bool kCorr>
+__device__ inline void store_vgrad(double *Lout, int64_t s, const double *L, const double *M) {
+    double *p = Lout + (size_t)s * vgrad_width(kCorr);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) p[i] = L[i];
+    if constexpr (kCorr) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) p[9 + i] = M[i];
+    }
+}
+
 // adjoint.hip
 CotDev cot_dev(const sph_deriv_cot *c);
 GradDev grad_dev(const sph_fields *g, int accumulate);
 int check_grad(const sph_fields *g);
 size_t adjoint_ws_bytes(int64_t n);
 // L_in (nullable): the forward velocity gradient of the same state in slot order
-// (9 arrays of n); when null it is recomputed.  slot_state: the state, cotangent
+// (vgrad_width values per slot); when null it is recomputed.  slot_state: the state, cotangent
 // and gradient arrays are in the grid's slot order instead of user order.
 // acc_parts (nullable): ceil(n / 256) per-block mu accumulators followed by
 // ceil(n / 64) Y0 accumulators (per block, or per wavefront for the list kernel)

@@ -332,7 +332,11 @@ def test_rhs_adjoint_reuses_the_forward_velocity_gradient(corr, pairs):
     st = gpu_state(w)
     g = P.sph_build_cells(st.pos, w.h, skin=0.05 * w.dx, pairs=pairs)
     fwd = P.sph_rhs(g, st, w.params, "fp64", vgrad=True)
-    assert fwd["vgrad"].shape == (15 if corr else 9, w.n)
+    assert fwd["vgrad"].shape == (w.n, 15 if corr else 9)
+    if not corr:  # row s is slot s's L, row by row: the oracle's L of user perm[s]
+        Lu = np.empty((9, w.n))
+        Lu[:, g.perm.cpu().numpy()] = fwd["vgrad"].cpu().numpy().T
+        assert rel(Lu, native.rhs_workload(w)["L"]) < 1e-12
     plain = P.sph_rhs(g, st, w.params, "fp64")
     for k in ("acc", "drho", "dS", "rho_sum"):  # writing vgrad changes no output
         assert torch.equal(fwd[k], plain[k]), k
