@@ -84,55 +84,62 @@ __device__ inline int32_t xor_lane(int32_t v) {
         return __shfl_xor(v, J);
 }
 
-// Bitonic sort, ascending, of the 64 E values v[e] (value i = 64 e + lane) held by
-// one wavefront.
-template <int J, int K, int E>
-__device__ inline void bitonic_lanes(int32_t (&v)[E], int lane) {
-    const bool lower = (lane & J) == 0;   // value i below its partner
-    const bool lane_up = (lane & K) == 0;  // ascending run (K < 64)
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        // ascending where bit K of i = 64 e + lane is clear (for K >= 64, bit K of 64 e)
-        const bool up = K < 64 ? lane_up : ((64 * e) & K) == 0;
-        const int32_t o = xor_lane<J>(v[e]);
-        // the lower index keeps the min when ascending, the max otherwise: the partner's
-        // value where it is below (min) or not below (max) this one (equal values are
-        // alike, so one compare and one select)
-        const bool take_max = lower != up;
-        v[e] = ((o < v[e]) != take_max) ? o : v[e];
-    }
+// Bitonic sort, ascending, of the 64 E values v[e] held by one wavefront, value
+// i = E lane + e (each lane holds E consecutive values): distances below E are
+// exchanges inside a lane, the others between lanes (lane distance J / E).  bit[b] is
+// bit b of the lane number, so a stage's directions are one or two of them.
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x >> 1); }
+
+template <int K, int E>
+__device__ inline bool ascending(const bool (&bit)[6], int e) {
+    // bit K of i = E lane + e: of e for K < E, else bit K / E of the lane (0 past 63)
+    if constexpr (K < E) return (e & K) == 0;
+    else if constexpr (K / E >= 64) return true;
+    else return !bit[ilog2(K / E)];
 }
 
 template <int K, int J, int E>
-__device__ inline void bitonic_stage(int32_t (&v)[E], int lane) {
-    if constexpr (J >= 64) {
-        constexpr int je = J >> 6;
+__device__ inline void bitonic_stage(int32_t (&v)[E], const bool (&bit)[6]) {
+    if constexpr (J < E) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const int f = e ^ je;
+            const int f = e ^ J;
             if (f > e) {
-                const bool up = (((64 * e + lane) & K) == 0);
+                const bool up = ascending<K, E>(bit, e);
                 const int32_t a = v[e], b = v[f];
-                const bool sw = up ? (a > b) : (a < b);
+                const bool sw = (a > b) == up;  // (equal values may swap: alike)
                 v[e] = sw ? b : a;
                 v[f] = sw ? a : b;
             }
         }
     } else {
-        bitonic_lanes<J, K, E>(v, lane);
+        constexpr int JL = J / E;
+        // the lower index keeps the min when ascending, the max otherwise: the partner's
+        // value where it is below (min) or not below (max) this one (equal values are
+        // alike, so one compare and one select); lower: value i below its partner
+        const bool take_max = !bit[ilog2(JL)] != ascending<K, E>(bit, 0);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int32_t o = xor_lane<JL>(v[e]);
+            v[e] = ((o < v[e]) != take_max) ? o : v[e];
+        }
     }
-    if constexpr (J > 1) bitonic_stage<K, J / 2, E>(v, lane);
+    if constexpr (J > 1) bitonic_stage<K, J / 2, E>(v, bit);
 }
 
 template <int K, int E>
-__device__ inline void bitonic_merges(int32_t (&v)[E], int lane) {
-    bitonic_stage<K, K / 2, E>(v, lane);
-    if constexpr (K < 64 * E) bitonic_merges<2 * K, E>(v, lane);
+__device__ inline void bitonic_merges(int32_t (&v)[E], const bool (&bit)[6]) {
+    bitonic_stage<K, K / 2, E>(v, bit);
+    if constexpr (K < 64 * E) bitonic_merges<2 * K, E>(v, bit);
 }
 
 template <int E>
 __device__ inline void wave_bitonic(int32_t (&v)[E]) {
-    bitonic_merges<2, E>(v, __lane_id());
+    const int lane = __lane_id();
+    bool bit[6];
+#pragma unroll
+    for (int b = 0; b < 6; ++b) bit[b] = (lane >> b) & 1;
+    bitonic_merges<2, E>(v, bit);
 }
 
 template <int E>
@@ -141,13 +148,13 @@ __device__ inline void sort_store_row(const int32_t *buf, int len, int32_t *__re
     int32_t v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        const int i = 64 * e + lane;
+        const int i = E * lane + e;
         v[e] = i < len ? buf[i] : INT_MAX;
     }
     wave_bitonic<E>(v);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        const int i = 64 * e + lane;
+        const int i = E * lane + e;
         if (i < len) out[i] = v[e];
     }
 }
@@ -344,22 +351,20 @@ __device__ inline void sort_row_inplace(int32_t *__restrict__ row, int len) {
     int32_t v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        const int i = 64 * e + lane;
+        const int i = E * lane + e;
         v[e] = i < len ? row[i] : INT_MAX;
     }
     // in order already? (value i <= value i + 1 for every i)
     bool ok = true;
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int32_t nxt = __shfl_down(v[e], 1);
-        const int32_t nxt_e = e + 1 < E ? __shfl(v[e + 1 < E ? e + 1 : e], 0) : INT_MAX;
-        ok = ok && v[e] <= (lane == 63 ? nxt_e : nxt);
-    }
+    for (int e = 0; e + 1 < E; ++e) ok = ok && v[e] <= v[e + 1];
+    const int32_t nxt = __shfl_down(v[0], 1);  // the next lane's first
+    ok = ok && (lane == 63 || v[E - 1] <= nxt);
     if (__ballot(!ok) == 0) return;
     wave_bitonic<E>(v);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        const int i = 64 * e + lane;
+        const int i = E * lane + e;
         if (i < len) row[i] = v[e];
     }
 }
