@@ -80,12 +80,12 @@ WORKLOADS = {"two_spheres": 1, "bullet": 2, "nonuniform": 4}
 COUNTERS = {
     "k_adj_pairs_list": {
         "profile": "profiles/hbm_traffic_nonuniform_8388608.md",
-        "fetch_bytes": 17021612970.0, "write_bytes": 3465087936.0, "l2_hit_rate": 0.8382,
-        "sources_sha256": "f674e854a0d81700d9d8a24708ea951f24b357aec6bab6569698f74393b3071d"},
+        "fetch_bytes": 17094169168.6, "write_bytes": 3465127187.2, "l2_hit_rate": 0.8379,
+        "sources_sha256": "76f9598a10c2ecf6f155de216284f4ba8526ee213942a61172776d9e736627f2"},
     "k_pairs64_list": {
         "profile": "profiles/hbm_traffic_nonuniform_8388608.md",
-        "fetch_bytes": 13625132565.0, "write_bytes": 3367414904.0, "l2_hit_rate": 0.7640,
-        "sources_sha256": "10aa0f481cc2973e90389d60823dcd1519d2fe612d0442f30c78e980641c0663"},
+        "fetch_bytes": 13633001176.1, "write_bytes": 3369781208.0, "l2_hit_rate": 0.7726,
+        "sources_sha256": "4cf68aba818b3516e204cf7410596c191b73c959a5d45d0b106c5eb45c4cf917"},
 }
 
 KERNEL_SOURCES = {"k_adj_pairs_list": ("adjoint.hip", "adjoint.hpp", "rhs_common.hpp", "common.hpp"),
