@@ -120,8 +120,19 @@ def clumps(h=0.3, seed=4):
     return np.ascontiguousarray(np.array(pts).T)
 
 
+def lines(h=0.3, spacing=0.25):
+    """Two parallel lines of 64 particles along x, h / 2 apart in y: the list build's
+    groups span many cells in x, so their cell rows hold many runs of slots."""
+    x = np.arange(64) * spacing * h
+    a = np.stack([x, np.zeros(64), np.zeros(64)])
+    b = np.stack([x + 0.5 * spacing * h, np.full(64, 0.5 * h), np.zeros(64)])
+    return np.ascontiguousarray(np.concatenate([a, b], axis=1))
+
+
 CSR_CASES = {
     "clumps": lambda: clumps(),
+    "lines": lambda: lines(),
+    "lines_sparse": lambda: lines(spacing=0.3),
     "cube16": lambda: W.config(0).pos,
     "cube16_shuffled": lambda: W.cube(16, 1 / 16, seed=5, shuffle=True).pos,
     "lattice10": lambda: W.cube(10, 0.1, seed=1, jitter=0.0).pos,
@@ -135,7 +146,7 @@ def test_neighbours_bit_exact(case, cells_per_h, pairs):
     """Partner sets from the cell rows and from the frozen candidate lists, against
     the oracle's brute force."""
     pos = CSR_CASES[case]()
-    h = 0.3 if case in ("adversarial", "clumps") else (0.15 if case != "lattice10" else 0.24)
+    h = 0.3 if case in ("adversarial", "clumps", "lines", "lines_sparse") else (0.15 if case != "lattice10" else 0.24)
     rp_ref, col_ref = native.neighbours(pos, h)
     rp, col, _ = gpu_csr(pos, h, cells_per_h, skin=0.01 * h if pairs else 0.0, pairs=pairs)
     assert np.array_equal(rp, rp_ref)
@@ -149,7 +160,7 @@ def test_neighbours_from_the_build_time_partner_counts(case):
     exact test wherever that does not hold: one particle moved by one ulp, a smaller
     h, and a list built at other positions.  All bit-exact against the brute force."""
     pos = CSR_CASES[case]()
-    h = 0.3 if case in ("adversarial", "clumps") else (0.15 if case != "lattice10" else 0.24)
+    h = 0.3 if case in ("adversarial", "clumps", "lines", "lines_sparse") else (0.15 if case != "lattice10" else 0.24)
     rp_ref, col_ref = native.neighbours(pos, h)
     for cph in (1, 2):
         rp, col, _ = gpu_csr(pos, h, cph, skin=0.0, pairs=True)
