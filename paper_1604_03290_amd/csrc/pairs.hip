@@ -71,26 +71,25 @@ __global__ __launch_bounds__(kBlock) void k_pl_bound(GridDev g, const double *__
     bound[s] = b;
 }
 
-// Fill pass, one wavefront per group of 64 slots.
-// A compact group sweeps the cell region of its bounding box widened
-// by the reach once, cooperatively: the 64 lanes load 64 candidate positions with
-// one coalesced load into LDS, then each lane tests all of them against its own
-// slot (broadcast reads).  A group spread over a region of more than kSpread times
-// one slot's cells (sparse parts of a set) sweeps per lane instead (in the order of
-// for_each_row).  The compact sweep meets the cell rows from the middle of the
-// region outwards (z, then y), x increasing along a row and slots increasing inside a
-// cell, and each list holds its slot's candidates in that order.  The fill
-// writes entry j of lane l at block_start[B] + 64 j + l, pads every list to the
-// group's longest with the slot itself (n - 1 for the lanes past n), so every entry
-// of a group's steps is a valid slot and readers of whole groups load without guards,
-// and writes each slot's count.  The compact sweep works in passes over the rows of
-// its region: each lane takes one row (culled against the group's box as a whole),
-// the rows' runs of consecutive slots are laid out in LDS in row order, and the
-// candidates of all of them are then streamed 64 at a time, so that the loads of a pass
-// do not wait on one another row by row.  Each loaded candidate is culled, one lane per
-// candidate, against the group's bounding box widened by the radius (one farther away
-// is no lane's candidate); the survivors are packed, in order, into an LDS buffer, and
-// the lanes test the buffer 64 candidates at a time.
+// Fill pass, one wavefront per group of 64 slots.  The fill writes entry j of lane l
+// at block_start[B] + 64 j + l, pads every list to the group's longest with the slot
+// itself (n - 1 for the lanes past n), so every entry of a group's steps is a valid
+// slot and readers of whole groups load without guards, and writes each slot's count
+// (and its partners at the grid's h).
+//
+// A compact group sweeps, once and cooperatively, the cell rows of its bounding box
+// widened by the reach, from the middle of the region outwards (z, then y), x
+// increasing along a row and slots increasing inside a cell; each list holds its
+// slot's candidates in that order.  The sweep goes in passes of up to 64 rows: each
+// lane takes one row (culled against the group's box as a whole) and lays the row's
+// runs of consecutive slots out in LDS, in row order; the pass's candidates are then
+// streamed 64 at a time, so that the loads of a pass do not wait on one another row by
+// row.  Each loaded candidate is culled, one lane per candidate, against the group's
+// box widened by the radius (one farther away is no lane's candidate); the survivors
+// are packed in order into an LDS buffer, which the 64 lanes test against their own
+// slots 64 candidates at a time (broadcast reads).  A group spread over a region of
+// more than kSpread times one slot's cells (sparse parts of a set) sweeps per lane
+// instead, in the order of for_each_row.
 constexpr double kSpread = 8.0;
 constexpr int kRunCap = 256;  // runs of one pass (LDS)
 
