@@ -354,6 +354,9 @@ def single_state_step(args, w, torch, P, L):
     forms["adjoint_fp64_vgrad"] = {"ms": ms, "pairs_per_s": nnz / (ms * 1e-3),
                                    "note": "reads the velocity gradient sph_rhs wrote (the step's form)"}
     forms["fp32comp_speedup_vs_fp64"] = forms["rhs_fp64"]["ms"] / forms["rhs_fp32comp"]["ms"]
+    forms["rhs_fp32comp"]["note"] = ("a second precision, not a speedup: without packed FP32 its "
+                                     "vector instructions issue at the FP64 rate, and its 80-byte "
+                                     "records fetch the same cache lines as the FP64 ones")
     fields = ("acc", "drho", "dS", "rho_sum")
     forms["rhs_fp32comp"]["normwise_error_vs_fp64_gpu"] = {
         k: float((outs["fp32comp"][k] - outs["fp64"][k]).abs().max() / outs["fp64"][k].abs().max())
