@@ -635,17 +635,27 @@ __global__ __launch_bounds__(64 * kSplitAdj) void k_adj_pairs_list(GridDev g, in
 }  // namespace
 
 namespace {
+// Sum of p[threadIdx.x + kBlock k] over k in a fixed order: eight running sums (k mod 8)
+// so that eight loads are in flight, added pairwise at the end.
+__device__ inline double strided_sum(const double *__restrict__ p, int64_t m) {
+    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t i = threadIdx.x; i < m; i += 8 * kBlock) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t j = i + (int64_t)u * kBlock;
+            if (j < m) a[u] += p[j];
+        }
+    }
+    return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
 // one block: dparams[i] (+)= sum of part_i in a fixed order (a null part is skipped)
 __global__ __launch_bounds__(kBlock) void k_reduce_params(const double *__restrict__ p0,
                                                           int64_t m0,
                                                           const double *__restrict__ p1,
                                                           int64_t m1, double *dparams,
                                                           int accumulate) {
-    double a = 0.0, b = 0.0;
-    if (p0)
-        for (int64_t i = threadIdx.x; i < m0; i += kBlock) a += p0[i];
-    if (p1)
-        for (int64_t i = threadIdx.x; i < m1; i += kBlock) b += p1[i];
+    double a = p0 ? strided_sum(p0, m0) : 0.0, b = p1 ? strided_sum(p1, m1) : 0.0;
     a = block_sum(a);
     b = block_sum(b);
     if (threadIdx.x == 0) {
