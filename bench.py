@@ -80,11 +80,11 @@ WORKLOADS = {"two_spheres": 1, "bullet": 2, "nonuniform": 4}
 COUNTERS = {
     "k_adj_pairs_list": {
         "profile": "profiles/hbm_traffic_nonuniform_8388608.md",
-        "fetch_bytes": 17094169168.6, "write_bytes": 3465127187.2, "l2_hit_rate": 0.8379,
-        "sources_sha256": "76f9598a10c2ecf6f155de216284f4ba8526ee213942a61172776d9e736627f2"},
+        "fetch_bytes": 17087315363.0, "write_bytes": 3468151104.0, "l2_hit_rate": 0.8379,
+        "sources_sha256": "3994b4b91e92524580cc9b0f18a9ec938c1c4cc78059415727a01f3236408278"},
     "k_pairs64_list": {
         "profile": "profiles/hbm_traffic_nonuniform_8388608.md",
-        "fetch_bytes": 13633001176.1, "write_bytes": 3369781208.0, "l2_hit_rate": 0.7726,
+        "fetch_bytes": 13632555103.7, "write_bytes": 3370111024.0, "l2_hit_rate": 0.7727,
         "sources_sha256": "4cf68aba818b3516e204cf7410596c191b73c959a5d45d0b106c5eb45c4cf917"},
 }
 
