@@ -234,6 +234,7 @@ __global__ __launch_bounds__(kBlock) void k_nb_rows(GridDev g, const double4 *__
 // 64 slots would hold 16.6 KB of LDS per wavefront, two wavefronts per SIMD.)
 constexpr int kTileSteps = 64;
 constexpr int kTileRows = 16;
+constexpr int kRowsInFlight = 8;  // rows whose user indices are gathered together
 // a tile holds one step per lane: lane l tests step j0 + l of each row
 static_assert(kTileSteps == 64, "the fill indexes a tile's steps by lane");
 
@@ -269,7 +270,7 @@ __global__ __launch_bounds__(kBlock) void k_nb_fill_list(GridDev g, const double
     const bool all = known && *moved == 0 && act && known[s] == cnt;
     int k = 0;
     const int rows = (int)min<int64_t>(64, n - B * 64);
-    // every row of the group is its list: rows go four at a time (four gathers of user
+    // every row of the group is its list: rows go kRowsInFlight at a time (as many gathers of user
     // indices in flight per lane)
     const bool group_all = __ballot(act && !all) == 0;
     for (int j0 = 0; j0 < steps; j0 += kTileSteps) {
@@ -283,23 +284,23 @@ __global__ __launch_bounds__(kBlock) void k_nb_fill_list(GridDev g, const double
             }
             wave_sync();
             if (group_all) {
-                for (int r = c0; r < c1; r += 4) {
-                    int cr[4];
-                    int32_t u[4];
+                for (int r = c0; r < c1; r += kRowsInFlight) {
+                    int cr[kRowsInFlight];
+                    int32_t u[kRowsInFlight];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
+                    for (int q = 0; q < kRowsInFlight; ++q) {
                         cr[q] = r + q < rows ? __builtin_amdgcn_readlane(cnt, r + q) : 0;
                         u[q] = j0 + lane < cr[q] ? g.perm[tile[lane][r + q - c0]] : 0;
                     }
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
+                    for (int q = 0; q < kRowsInFlight; ++q) {
                         if (j0 >= cr[q]) continue;  // wavefront-uniform (also past the rows)
                         const int64_t rr = lane_value64(r0, r + q);
                         const int kr = __builtin_amdgcn_readlane(k, r + q);
                         if (j0 + lane < cr[q]) col[rr + kr + lane] = u[q];
                     }
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
+                    for (int q = 0; q < kRowsInFlight; ++q)
                         if (lane == r + q && j0 < cr[q]) k += min(64, cr[q] - j0);
                 }
                 wave_sync();
