@@ -7,9 +7,10 @@ shell with about 20; h = 2.4 dx).  One step = one pass of the whole hot path ove
   cell build (tiled cell numbering)                          sph_build_cells
   frozen pair list (the interaction list, skin 0)            sph_build_pairs
   partner lists (CSR, user order, rows ascending)            sph_neighbours
-  FP64 right-hand side (writing its velocity gradient)      sph_rhs
+  FP64 right-hand side (writing its velocity gradient and   sph_rhs
+  operand records)
   FP64 adjoint (vector-Jacobian product, random cotangent,   sph_rhs_adjoint
-  reading that velocity gradient instead of forming it)
+  reading them instead of forming them again)
 The metric counts the ordered pair interactions (b != a, |x_a - x_b| < h) evaluated
 by the right-hand side and by the adjoint: value = 2 nnz / step time.  Inputs are
 resident on the GPU before timing starts.  Reported beside it: the FP32-compensated
@@ -80,12 +81,12 @@ WORKLOADS = {"two_spheres": 1, "bullet": 2, "nonuniform": 4}
 COUNTERS = {
     "k_adj_pairs_list": {
         "profile": "profiles/hbm_traffic_nonuniform_8388608.md",
-        "fetch_bytes": 17087315363.0, "write_bytes": 3468151104.0, "l2_hit_rate": 0.8379,
-        "sources_sha256": "3994b4b91e92524580cc9b0f18a9ec938c1c4cc78059415727a01f3236408278"},
+        "fetch_bytes": 17094807996.0, "write_bytes": 3465202176.0, "l2_hit_rate": 0.8376,
+        "sources_sha256": "6fdbf3b70b0a9dd90d864db6d96d54e949b44a6c5898310a22431a4a8678c743"},
     "k_pairs64_list": {
         "profile": "profiles/hbm_traffic_nonuniform_8388608.md",
-        "fetch_bytes": 13632555103.7, "write_bytes": 3370111024.0, "l2_hit_rate": 0.7727,
-        "sources_sha256": "4cf68aba818b3516e204cf7410596c191b73c959a5d45d0b106c5eb45c4cf917"},
+        "fetch_bytes": 13632843261.2, "write_bytes": 3370255176.0, "l2_hit_rate": 0.7724,
+        "sources_sha256": "25aa29c4db090ac435c66e9ff0c6db71fc994bbec6143f0ef62c3f7e12718909"},
 }
 
 KERNEL_SOURCES = {"k_adj_pairs_list": ("adjoint.hip", "adjoint.hpp", "rhs_common.hpp", "common.hpp"),
@@ -289,7 +290,7 @@ def single_state_step(args, w, torch, P, L):
     f_app = approaching_fraction(st, row_ptr, col, torch)
     partners = partner_stats(row_ptr, torch)
     del col
-    out = P.api.new_deriv(n, vgrad=9)
+    out = P.api.new_deriv(n, vgrad=9, records=True)
     cot = {k: torch.randn(out[k].shape, dtype=torch.float64, device="cuda",
                           generator=torch.Generator("cuda").manual_seed(3)) for k in P.api.DERIV_KEYS}
     holder = {}
@@ -298,10 +299,11 @@ def single_state_step(args, w, torch, P, L):
         g = P.sph_build_cells(st.pos, w.h, skin=skin, cells_per_h=CELLS_PER_H, box=box, ws=ws_build)
         P.sph_build_pairs(g, st.pos, capacity=pl_cap, ws=ws_pairs)
         holder["csr"] = P.sph_neighbours(g, st.pos, w.h, col_cap=col_cap, ws=ws_nb)
-        # the forward hands its velocity gradient to the adjoint (as a reverse-mode
-        # caller keeps its forward's intermediates)
+        # the forward hands its velocity gradient and operand records to the adjoint (as
+        # a reverse-mode caller keeps its forward's intermediates)
         P.sph_rhs(g, st, w.params, "fp64", out=out, ws=ws_rhs)
-        holder["grad"] = P.sph_rhs_adjoint(g, st, w.params, cot, ws=ws_adj, vgrad=out["vgrad"])
+        holder["grad"] = P.sph_rhs_adjoint(g, st, w.params, cot, ws=ws_adj, vgrad=out["vgrad"],
+                                           rec=out["rec"])
         holder["g"] = g
 
     log(f"{w.name}: {nnz} ordered pairs, list of {padded} entries ({pl_cap} of room); warm-up")
@@ -349,10 +351,11 @@ def single_state_step(args, w, torch, P, L):
     ms = median_ms(lambda: P.sph_rhs_adjoint(g, st, w.params, cot, ws=ws_adj), reps, torch)
     forms["adjoint_fp64"] = {"ms": ms, "pairs_per_s": nnz / (ms * 1e-3),
                              "note": "forms the velocity gradient itself"}
-    ms = median_ms(lambda: P.sph_rhs_adjoint(g, st, w.params, cot, ws=ws_adj, vgrad=out["vgrad"]),
-                   reps, torch)
+    ms = median_ms(lambda: P.sph_rhs_adjoint(g, st, w.params, cot, ws=ws_adj, vgrad=out["vgrad"],
+                                             rec=out["rec"]), reps, torch)
     forms["adjoint_fp64_vgrad"] = {"ms": ms, "pairs_per_s": nnz / (ms * 1e-3),
-                                   "note": "reads the velocity gradient sph_rhs wrote (the step's form)"}
+                                   "note": "reads the velocity gradient and the operand records "
+                                           "sph_rhs wrote (the step's form)"}
     forms["fp32comp_speedup_vs_fp64"] = forms["rhs_fp64"]["ms"] / forms["rhs_fp32comp"]["ms"]
     forms["rhs_fp32comp"]["note"] = ("a second precision, not a speedup: without packed FP32 its "
                                      "vector instructions issue at the FP64 rate, and its 80-byte "
@@ -382,7 +385,8 @@ def single_state_step(args, w, torch, P, L):
                    "skin_over_dx": skin / w.dx, "h_over_dx": 2.4, "cells_per_h": CELLS_PER_H,
                    "grid_dims": list(dims), "grid_cells": ncells,
                    "step": "cell build + pair list + partner CSR + FP64 sph_rhs (writing its velocity "
-                           "gradient) + FP64 sph_rhs_adjoint (random cotangent, reading it) on one state"},
+                           "gradient and operand records) + FP64 sph_rhs_adjoint (random cotangent, "
+                           "reading them) on one state"},
         "roofline": kernel_roofline(kern, nnz, f_app, padded, args.steps, ms_step),
         "forms": forms,
         "copy_calibration_bytes": calib,

@@ -191,7 +191,10 @@ typedef struct {
  * (sph_deriv_cot.vgrad) to reuse: one record of m = 9 (15) values per slot, in the
  * grid's slot order, component i of slot s at vgrad[m s + i]: L row by row
  * (dv^x/dx, dv^x/dy, ..., dv^z/dz), then with the correction the moment matrix M
- * (xx yy zz xy xz yz). */
+ * (xx yy zz xy xz yz).  rec (NULL, or device [n 16] doubles, either precision)
+ * receives the operand records of the prepass (per slot, in the grid's slot order:
+ * the pair operands of each particle, a layout internal to the library), for
+ * sph_rhs_adjoint (sph_deriv_cot.rec) to reuse. */
 typedef struct {
     double *ax, *ay, *az;
     double *drho;
@@ -202,6 +205,7 @@ typedef struct {
     double *dd3;
     int32_t *n_act;
     double *vgrad;
+    double *rec;
 } sph_deriv;
 
 /* Cotangents of the derivatives (inputs of the adjoint), user order.  A NULL
@@ -210,7 +214,10 @@ typedef struct {
  * the velocity gradient that sph_rhs (SPH_FP64) wrote into sph_deriv.vgrad for the
  * same grid, state and params, which the adjoint then reads instead of forming it
  * again (a reverse-mode caller keeps it from its forward call, as it keeps any
- * intermediate); a vgrad of another state gives wrong gradients, unchecked. */
+ * intermediate); a vgrad of another state gives wrong gradients, unchecked.  rec
+ * likewise: NULL, or the records sph_rhs wrote into sph_deriv.rec for the same grid,
+ * state and params; the adjoint then runs no prepass of its own (nor its check that
+ * no particle has left its cell, which the forward call made). */
 typedef struct {
     const double *ax, *ay, *az;
     const double *drho;
@@ -219,6 +226,7 @@ typedef struct {
     const double *du;
     const double *dx, *dy, *dz;
     const double *vgrad;
+    const double *rec;
 } sph_deriv_cot;
 
 /* Writable per-particle fields (no mass): used for gradients with respect to

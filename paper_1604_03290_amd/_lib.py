@@ -78,11 +78,11 @@ _FIELDS = ("x", "y", "z", "vx", "vy", "vz", "rho", "sxx", "syy", "szz", "sxy", "
 
 
 class Deriv(C.Structure):
-    _fields_ = [(k, _pd) for k in _DERIV + ("du", "dx", "dy", "dz", "dd3", "n_act", "vgrad")]
+    _fields_ = [(k, _pd) for k in _DERIV + ("du", "dx", "dy", "dz", "dd3", "n_act", "vgrad", "rec")]
 
 
 class DerivCot(C.Structure):
-    _fields_ = [(k, _pd) for k in _DERIV + ("du", "dx", "dy", "dz", "vgrad")]
+    _fields_ = [(k, _pd) for k in _DERIV + ("du", "dx", "dy", "dz", "vgrad", "rec")]
 
 
 class Fields(C.Structure):

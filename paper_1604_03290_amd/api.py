@@ -16,6 +16,7 @@ import torch
 from . import _lib as L
 
 F64 = torch.float64
+REC_DOUBLES = 16  # operand record of one slot (sph_deriv.rec, sph_deriv_cot.rec)
 PARAM_ORDER = ("h", "rho0", "c", "mu", "Y0", "alpha", "beta", "eps_v", "rho_cut", "correction",
                "eps_s", "n_s", "dmpd", "xsph", "eos", "n_M", "a_T", "b_T", "A_T", "B_T", "E0_T",
                "alpha_T", "beta_T", "E_iv", "E_cv")
@@ -268,11 +269,12 @@ def sph_gravity(pos: torch.Tensor, m: torch.Tensor, G: float, theta: float, eps:
 
 
 def new_deriv(n: int, device="cuda", extra: bool = False, damage: bool = False,
-              vgrad: int = 0):
+              vgrad: int = 0, records: bool = False):
     """Output arrays of sph_rhs; with ``extra`` also du (n) and xv (3, n) = dx/dt, with
     ``damage`` dd3 (n) = d(d^(1/3))/dt and n_act (n, int32), with ``vgrad`` = 9 (15 with
     the correction tensor) the velocity-gradient handoff for sph_rhs_adjoint (vgrad,
-    (n, vgrad): one row per slot, the grid's slot order)."""
+    (n, vgrad): one row per slot, the grid's slot order), with ``records`` the operand
+    records for sph_rhs_adjoint (rec, (n, 16))."""
     d = dict(acc=torch.empty(3, n, dtype=F64, device=device),
              drho=torch.empty(n, dtype=F64, device=device),
              dS=torch.empty(6, n, dtype=F64, device=device),
@@ -285,6 +287,8 @@ def new_deriv(n: int, device="cuda", extra: bool = False, damage: bool = False,
         d["n_act"] = torch.empty(n, dtype=torch.int32, device=device)
     if vgrad:
         d["vgrad"] = torch.empty(n, vgrad, dtype=F64, device=device)
+    if records:
+        d["rec"] = torch.empty(n, REC_DOUBLES, dtype=F64, device=device)
     return d
 
 
@@ -309,10 +313,13 @@ def deriv_struct(d: dict, cls=L.Deriv):
             _dev(dd3)
         if na is not None:
             _dev(na, torch.int32)
-        vg = d.get("vgrad")
-        if vg is not None:
-            _dev(vg)
-        args += [p(dd3), p(na), p(vg)]
+        vg, rec = d.get("vgrad"), d.get("rec")
+        for t in (vg, rec):
+            if t is not None:
+                _dev(t)
+        if rec is not None and (tuple(rec.shape) != (a.shape[1], REC_DOUBLES) or not rec.is_contiguous()):
+            raise ValueError(f"rec must be contiguous ({a.shape[1]}, {REC_DOUBLES})")
+        args += [p(dd3), p(na), p(vg), p(rec)]
     return cls(*args)
 
 
@@ -333,15 +340,16 @@ def precision_code(precision) -> int:
 
 def sph_rhs(grid: CellGrid, state: ParticleState, params, precision="fp64", out=None,
             ws: torch.Tensor | None = None, extra: bool = False, damage: bool = False,
-            vgrad: bool = False) -> dict:
+            vgrad: bool = False, records: bool = False) -> dict:
     """Right-hand side (C: sph_rhs): dict acc (3, n), drho (n), dS (6, n), rho_sum (n);
     with ``extra`` (or an ``out`` holding them) also du (n) and xv (3, n) = dx/dt, with
     ``damage`` the damage model's dd3 (n) and n_act (n) (the state's flaw lists needed),
-    with ``vgrad`` (FP64) the velocity gradient that sph_rhs_adjoint can take back."""
+    with ``vgrad`` (FP64) the velocity gradient and with ``records`` the operand records
+    (rec) that sph_rhs_adjoint can take back."""
     n = state.n
     if out is None:
         nv = (15 if params_struct(params).correction != 0.0 else 9) if vgrad else 0
-        out = new_deriv(n, state.rho.device, extra, damage, nv)
+        out = new_deriv(n, state.rho.device, extra, damage, nv, records)
     if ws is None:
         ws = workspace(L.SPH_OP_RHS, n, 0, state.rho.device)
     cs = state.c_state()
@@ -371,12 +379,14 @@ def sph_rhs_noalloc(grid: CellGrid, state: ParticleState, params, precision="fp6
 
 
 def sph_rhs_adjoint(grid: CellGrid, state: ParticleState, params, cot: dict,
-                    ws: torch.Tensor | None = None, vgrad: torch.Tensor | None = None) -> dict:
+                    ws: torch.Tensor | None = None, vgrad: torch.Tensor | None = None,
+                    rec: torch.Tensor | None = None) -> dict:
     """Vector-Jacobian product of sph_rhs (C: sph_rhs_adjoint).  ``cot`` has keys of
     sph_rhs's outputs (acc, drho, dS, rho_sum, du, xv; missing = zero).  ``vgrad``: the
     "vgrad" output of an FP64 sph_rhs on the same grid, state and params, reused instead
-    of forming the velocity gradient again.  Returns gradients pos, vel, rho, S, mu, Y0,
-    and u with the Tillotson equation."""
+    of forming the velocity gradient again; ``rec`` likewise its "rec" output (the
+    operand records), reused instead of running the prepass again.  Returns gradients
+    pos, vel, rho, S, mu, Y0, and u with the Tillotson equation."""
     n = state.n
     dev = state.rho.device
     z3 = lambda k, shape: _dev(cot[k]) if cot.get(k) is not None else None
@@ -388,9 +398,13 @@ def sph_rhs_adjoint(grid: CellGrid, state: ParticleState, params, cot: dict,
         want = 15 if params_struct(params).correction != 0.0 else 9
         if tuple(vgrad.shape) != (n, want) or not vgrad.is_contiguous():
             raise ValueError(f"vgrad must be contiguous ({n}, {want}), got {tuple(vgrad.shape)}")
+    if rec is not None:
+        _dev(rec)
+        if tuple(rec.shape) != (n, REC_DOUBLES) or not rec.is_contiguous():
+            raise ValueError(f"rec must be contiguous ({n}, {REC_DOUBLES}), got {tuple(rec.shape)}")
     dc = L.DerivCot(p(acc, 0), p(acc, 1), p(acc, 2), p(drho), p(dS, 0), p(dS, 1), p(dS, 2),
                     p(dS, 3), p(dS, 4), p(dS, 5), p(rs), p(du), p(xv, 0), p(xv, 1), p(xv, 2),
-                    p(vgrad))
+                    p(vgrad), p(rec))
     g = dict(pos=torch.empty(3, n, dtype=F64, device=dev), vel=torch.empty(3, n, dtype=F64, device=dev),
              rho=torch.empty(n, dtype=F64, device=dev), S=torch.empty(6, n, dtype=F64, device=dev))
     dparams = torch.empty(2, dtype=F64, device=dev)
@@ -431,12 +445,14 @@ class SphRhs(torch.autograd.Function):
                            rho.detach().contiguous(), S.detach().contiguous(), m.contiguous(),
                            u=None if u is None else u.detach().contiguous(),
                            d=None if d is None else d.detach().contiguous())
-        out = sph_rhs(grid, st, p, "fp64", extra=extra, vgrad=True)
+        out = sph_rhs(grid, st, p, "fp64", extra=extra, vgrad=True, records=True)
         # the inputs are saved through autograd, so that an in-place change between
         # forward and backward raises instead of differentiating at a changed state;
-        # the velocity gradient is kept for the backward, which then skips forming it
+        # the velocity gradient and the operand records are kept for the backward,
+        # which then forms neither again
         ctx.save_for_backward(pos, vel, rho, S, m, u, d)
         ctx.vgrad = out["vgrad"]
+        ctx.rec = out["rec"]
         ctx.grid, ctx.params, ctx.extra = grid, p, extra
         ctx.mu_like, ctx.Y0_like = torch.as_tensor(mu), torch.as_tensor(Y0)
         res = (out["acc"], out["drho"], out["dS"], out["rho_sum"])
@@ -449,7 +465,7 @@ class SphRhs(torch.autograd.Function):
         st = ParticleState(c(pos), c(vel), c(rho), c(S), c(m), u=c(u), d=c(d))
         names = ("acc", "drho", "dS", "rho_sum", "du", "xv")
         cot = {k: (v.contiguous() if v is not None else None) for k, v in zip(names, grads)}
-        g = sph_rhs_adjoint(ctx.grid, st, ctx.params, cot, vgrad=ctx.vgrad)
+        g = sph_rhs_adjoint(ctx.grid, st, ctx.params, cot, vgrad=ctx.vgrad, rec=ctx.rec)
         gmu = g["mu"].to(ctx.mu_like.device, ctx.mu_like.dtype).reshape(ctx.mu_like.shape)
         gY0 = g["Y0"].to(ctx.Y0_like.device, ctx.Y0_like.dtype).reshape(ctx.Y0_like.shape)
         return (g["pos"], g["vel"], g["rho"], g["S"], gmu, gY0, None, None, None, None, None,

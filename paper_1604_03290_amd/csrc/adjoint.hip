@@ -700,7 +700,7 @@ GradDev grad_dev(const sph_fields *g, int accumulate) {
 int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_params *params,
                        const CotDev &cot, const GradDev &grad, double *dparams, int accumulate_params,
                        Carve &c, hipStream_t s, const double *L_in, bool slot_state,
-                       double *acc_parts, bool post_ready) {
+                       double *acc_parts, bool post_ready, const double *rec_in) {
     const int64_t n = grid->n;
     GridDev g = grid_dev(grid);
     if (slot_state) g.io = nullptr;
@@ -717,6 +717,9 @@ int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_p
     int rc;
     if (post_ready) {
         if (!L_in || !acc_parts) return fail(SPH_ERR_INVALID_ARG, "post stage not prepared");
+    } else if (rec_in) {
+        rec = const_cast<double *>(rec_in);  // the forward's records (read only)
+        if ((rc = invert_launch(g, n, ad.inv, s))) return rc;
     } else if ((rc = prepass_launch(g, st, n, k, rec, c.status(), s, nullptr, ad.inv))) {
         return rc;
     }
@@ -738,7 +741,7 @@ int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_p
         SPH_LAUNCHED();
     }
     if (!post_ready) {
-        // the prepass filled ad.inv when the state is in user order
+        // the prepass (or invert_launch) filled ad.inv when the state is in user order
         k_adj_post<<<blocks_for(n), kBlock, 0, s>>>(g, n, k, rec, st, cot, ad,
                                                     g.io ? ad.inv : nullptr);
         SPH_LAUNCHED();
@@ -816,5 +819,5 @@ extern "C" int sph_rhs_adjoint(const sph_grid *grid, const sph_state *state,
     if ((rc = clear_status(ws, s))) return rc;
     Carve c(ws);
     return rhs_adjoint_launch(grid, state, params, cot_dev(cot), grad_dev(grad, 0), dparams, 0, c, s,
-                              cot->vgrad);
+                              cot->vgrad, false, nullptr, false, cot->rec);
 }

@@ -309,6 +309,7 @@ sph_deriv deriv_struct(const Deriv10 &d) {
     o.dd3 = nullptr;
     o.n_act = nullptr;
     o.vgrad = nullptr;  // the leapfrog hands the velocity gradient over itself
+    o.rec = nullptr;    // and keeps its records in its workspace
     return o;
 }
 

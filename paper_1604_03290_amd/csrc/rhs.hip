@@ -325,6 +325,13 @@ __global__ __launch_bounds__(64 * kSplit) void k_pairs32_list(GridDev g, int64_t
 
 }  // namespace
 
+int invert_launch(const GridDev &g, int64_t n, int32_t *inv, hipStream_t s) {
+    if (!g.io) return SPH_OK;
+    k_invert<<<blocks_for(n), kBlock, 0, s>>>(g.io, n, inv);
+    SPH_LAUNCHED();
+    return SPH_OK;
+}
+
 int prepass_launch(const GridDev &g, const StateDev &st, int64_t n, const Consts &k, double *rec,
                    int32_t *status, hipStream_t s, const OutDev *od, int32_t *inv) {
     if (g.io && inv) {
@@ -420,6 +427,7 @@ int rhs_launch(const sph_grid *grid, const sph_state *state, const sph_params *p
     Consts k = make_consts(*params, g.delta);
     double *rec = rhs_rec_of(c, n);
     c.take<double>((size_t)n * kRec);
+    if (out->rec && !rec_ready) rec = out->rec;  // the records go to the caller's buffer
     float *r32 = c.take<float>((size_t)n * kRec32);
     int32_t *inv = c.take<int32_t>(n);
     StateDev st = state_dev(state);

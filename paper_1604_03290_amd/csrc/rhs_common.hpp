@@ -926,18 +926,22 @@ size_t adjoint_ws_bytes(int64_t n);
 // to which the launch adds its sums instead of reducing into dparams.
 // post_ready: the operand records and the post stage's outputs (adj_buffers of
 // this carve) are already written, with the mu block sums added to acc_parts;
-// only the pair stage runs (L_in required).
+// only the pair stage runs (L_in required).  rec_in (nullable): the operand records
+// of the same state that a forward call wrote; the prepass is then not run.
 int rhs_adjoint_launch(const sph_grid *grid, const sph_state *state, const sph_params *params,
                        const CotDev &cot, const GradDev &grad, double *dparams, int accumulate_params,
                        Carve &c, hipStream_t s, const double *L_in = nullptr,
                        bool slot_state = false, double *acc_parts = nullptr,
-                       bool post_ready = false);
+                       bool post_ready = false, const double *rec_in = nullptr);
 // dparams[0] (+)= sum of p0[0..m0), dparams[1] (+)= sum of p1[0..m1) (null parts
 // skipped), fixed summation order
 int reduce_params_launch(const double *p0, int64_t m0, const double *p1, int64_t m1,
                          double *dparams, int accumulate, hipStream_t s);
 
 // rhs.hip
+// inv (n int32) := the inverse permutation (slot of every user index), with a
+// user-ordered state (g.io set); nothing otherwise
+int invert_launch(const GridDev &g, int64_t n, int32_t *inv, hipStream_t s);
 // od (nullable): outputs whose dd3 / n_act, when set, receive the damage rates
 // inv (nullable): n int32 of scratch; with a user-ordered state the prepass fills it with
 // the inverse permutation and reads the state in user order

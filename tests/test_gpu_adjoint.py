@@ -344,6 +344,15 @@ def test_rhs_adjoint_reuses_the_forward_velocity_gradient(corr, pairs):
     own = P.sph_rhs_adjoint(g, st, w.params, cg)
     got = P.sph_rhs_adjoint(g, st, w.params, cg, vgrad=fwd["vgrad"])
     assert P.workspace_status(got["_ws"]) == 0
+    # the forward's operand records handed over as well: the same records, so the same
+    # gradients bit for bit (also with the records alone)
+    fr = P.sph_rhs(g, st, w.params, "fp64", vgrad=True, records=True)
+    assert fr["rec"].shape == (w.n, 16) and torch.equal(fr["vgrad"], fwd["vgrad"])
+    both = P.sph_rhs_adjoint(g, st, w.params, cg, vgrad=fr["vgrad"], rec=fr["rec"])
+    recs = P.sph_rhs_adjoint(g, st, w.params, cg, rec=fr["rec"])
+    for k in ("pos", "vel", "rho", "S", "mu", "Y0"):
+        assert torch.equal(both[k], got[k]), k
+        assert torch.equal(recs[k], own[k]), k
     for k in ("pos", "vel", "rho", "S"):
         assert rel(got[k].cpu().numpy(), own[k].cpu().numpy()) < 1e-13, k
         assert rel(got[k].cpu().numpy(), ref[k]) < 1e-11, k
