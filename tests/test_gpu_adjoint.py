@@ -350,6 +350,9 @@ def test_rhs_adjoint_reuses_the_forward_velocity_gradient(corr, pairs):
     assert fr["rec"].shape == (w.n, 16) and torch.equal(fr["vgrad"], fwd["vgrad"])
     both = P.sph_rhs_adjoint(g, st, w.params, cg, vgrad=fr["vgrad"], rec=fr["rec"])
     recs = P.sph_rhs_adjoint(g, st, w.params, cg, rec=fr["rec"])
+    # the FP32-compensated form writes the same FP64 records
+    f32 = P.sph_rhs(g, st, w.params, "fp32comp", records=True)
+    assert torch.equal(f32["rec"], fr["rec"])
     for k in ("pos", "vel", "rho", "S", "mu", "Y0"):
         assert torch.equal(both[k], got[k]), k
         assert torch.equal(recs[k], own[k]), k
